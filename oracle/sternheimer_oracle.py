@@ -1,0 +1,157 @@
+"""Plain CPU FP64 oracle for the linear Sternheimer solves of the SternheimerGW method.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product (the HIP library and its
+Python binding) may import, call or link this module; only the test suite, the
+smoke check and the benchmark's CPU-baseline leg do.  It shares no code with
+the HIP path.
+
+What it computes (Hartree units; every function cites the passage it follows):
+
+* the plane-wave Hamiltonian at one Bloch vector as a dense matrix
+  (Sec. 2.1, Eq. 1 and the text after it: kinetic part diagonal in
+  reciprocal space, local potential applied on the real-space grid);
+* the driving term of the density response, projected off the occupied
+  manifold (Sec. 2.3, Eq. 8), with the sign reading documented in ``rhs``;
+* the Coulomb-response operator with the occupied projector (Sec. 2.3, Eq. 7)
+  and the Sternheimer equation it enters (Sec. 2.3, Eq. 6);
+* the exact solution of every shifted system, by two direct routes: an LU
+  solve of the shifted operator, and the sum over all unoccupied eigenstates
+  that the Sternheimer approach avoids (Sec. 1 and Sec. 2.2);
+* the relative residual and the condition number used for the error budget.
+
+The Krylov method itself is not reproduced: the iterative solver reaches
+(up to rounding) the exact solution of each shifted system, and that solution
+has the plain definition written out here.
+
+Readings of the paper taken here:
+
+* The energy in the shifted operator is the unperturbed eigenvalue of band v
+  at k (Eq. 6 writes the band energy at k+q; the two coincide at q = 0).
+* The right-hand side carries a minus sign, b = -(1 - P_occ) dV psi_v.
+* The coefficient alpha of the occupied projector is a free parameter; the
+  solution does not depend on it because b is orthogonal to the occupied space.
+* Complex frequencies are z_j = omega_j + i*eta; the operator solved is
+  H - eps_v - z_j + alpha * P_occ.
+* The local potential is defined by its grid samples; its matrix element
+  between plane waves m and m' is the discrete Fourier coefficient at the
+  cyclic difference (m - m') mod N (grid-defined operator, aliasing included).
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.linalg as sla
+
+
+# ---------------------------------------------------------------------------
+# Hamiltonian (Sec. 2.1)
+# ---------------------------------------------------------------------------
+
+def kinetic(miller: np.ndarray, B: np.ndarray, kvec) -> np.ndarray:
+    """Kinetic energy 0.5 |k + G|^2 of each plane wave (Sec. 2.1, Eq. 1)."""
+    kg = np.asarray(miller, float) @ np.asarray(B, float) + np.asarray(kvec, float)
+    return 0.5 * np.einsum("gd,gd->g", kg, kg)
+
+
+def potential_coefficients(v_grid: np.ndarray) -> np.ndarray:
+    """Discrete Fourier coefficients V~[m] = (1/N) sum_j V(r_j) exp(-i G_m . r_j).
+
+    Sec. 2.1: the local potential is applied in real space; for plane waves
+    sampled on the grid this is multiplication by V(r_j), whose plane-wave
+    matrix element is V~ at the cyclic index difference.
+    """
+    return np.fft.fftn(np.asarray(v_grid, float)) / v_grid.size
+
+
+def hamiltonian(miller: np.ndarray, B: np.ndarray, kvec, v_grid: np.ndarray) -> np.ndarray:
+    """Dense plane-wave Hamiltonian H[i, j] = T_i delta_ij + V~[(m_i - m_j) mod N]."""
+    vq = potential_coefficients(v_grid)
+    n0, n1, n2 = v_grid.shape
+    m = np.asarray(miller, np.int64)
+    h = vq[(m[:, None, 0] - m[None, :, 0]) % n0,
+           (m[:, None, 1] - m[None, :, 1]) % n1,
+           (m[:, None, 2] - m[None, :, 2]) % n2]
+    h[np.diag_indices_from(h)] += kinetic(miller, B, kvec)
+    return h
+
+
+def eigh(h: np.ndarray):
+    """All eigenpairs of the Hermitian matrix (LAPACK divide and conquer)."""
+    return sla.eigh(h, driver="evd")
+
+
+# ---------------------------------------------------------------------------
+# right-hand side (Sec. 2.3, Eq. 8)
+# ---------------------------------------------------------------------------
+
+def shifted_source(psi_v: np.ndarray, miller_k: np.ndarray, miller_kq: np.ndarray,
+                   m_p) -> np.ndarray:
+    """Plane-wave coefficients at k+q of exp(i (q + G_p) . r) times psi_v.
+
+    Multiplying the Bloch state at k by the plane wave moves the coefficient of
+    G to G + G_p on the k+q basis: s(G'') = psi_v(G'' - G_p), zero when
+    G'' - G_p lies outside the basis sphere at k.
+    """
+    index_k = {tuple(int(c) for c in m): i for i, m in enumerate(np.asarray(miller_k))}
+    m_p = np.asarray(m_p, np.int64)
+    s = np.zeros(len(miller_kq), complex)
+    for g, m in enumerate(np.asarray(miller_kq, np.int64)):
+        i = index_k.get(tuple(int(c) for c in (m - m_p)))
+        if i is not None:
+            s[g] = psi_v[i]
+    return s
+
+
+def apply_occupied_projector(psi_occ: np.ndarray, x: np.ndarray) -> np.ndarray:
+    """P_occ x = sum_n psi_n <psi_n | x>; ``psi_occ`` rows are the occupied states."""
+    return psi_occ.T @ (psi_occ.conj() @ x)
+
+
+def rhs(psi_v, miller_k, miller_kq, m_p, psi_occ_kq) -> np.ndarray:
+    """b = -(1 - P_occ) dV_p psi_v on the k+q basis (Sec. 2.3, Eq. 8; sign per module docstring)."""
+    s = shifted_source(psi_v, miller_k, miller_kq, m_p)
+    return -(s - apply_occupied_projector(psi_occ_kq, s))
+
+
+# ---------------------------------------------------------------------------
+# shifted operator and its solution (Sec. 2.3, Eqs. 6-7)
+# ---------------------------------------------------------------------------
+
+def coulomb_operator(h_kq: np.ndarray, psi_occ_kq: np.ndarray, eps_v: float, alpha: float):
+    """A0 = H_{k+q} - eps_v + alpha * P_occ (Eq. 7 with the band energy moved into the shift)."""
+    a0 = h_kq - eps_v * np.eye(h_kq.shape[0]) + alpha * (psi_occ_kq.T @ psi_occ_kq.conj())
+    return a0
+
+
+def solve_lu(a0: np.ndarray, b: np.ndarray, z: complex) -> np.ndarray:
+    """x = (A0 - z)^{-1} b by LU with partial pivoting (Eq. 6 solved directly)."""
+    return sla.solve(a0 - z * np.eye(a0.shape[0]), b)
+
+
+def solve_spectral(evals: np.ndarray, evecs: np.ndarray, n_occ: int, eps_v: float,
+                   b: np.ndarray, zs) -> np.ndarray:
+    """x(z) = sum over unoccupied c of u_c <u_c|b> / (eps_c - eps_v - z).
+
+    This is the sum over empty states that the Sternheimer approach replaces
+    (Sec. 1; Sec. 2.2).  ``evecs`` columns are eigenvectors of H_{k+q} in
+    ascending order; the lowest ``n_occ`` are occupied.  Returns [len(zs)][n_pw].
+    """
+    uc = evecs[:, n_occ:]
+    coef = uc.conj().T @ b
+    zs = np.atleast_1d(np.asarray(zs, complex))
+    den = evals[None, n_occ:] - eps_v - zs[:, None]
+    return (coef[None, :] / den) @ uc.T
+
+
+def relative_residual(a0: np.ndarray, x: np.ndarray, b: np.ndarray, z: complex) -> float:
+    """||b - (A0 - z) x|| / ||b||, zero for a zero right-hand side with x = 0."""
+    nb = np.linalg.norm(b)
+    r = b - (a0 @ x - z * x)
+    if nb == 0.0:
+        return float(np.linalg.norm(r))
+    return float(np.linalg.norm(r) / nb)
+
+
+def condition_number(evals: np.ndarray, n_occ: int, eps_v: float, z: complex) -> float:
+    """kappa of (H - eps_v - z) on the unoccupied space, from the exact spectrum."""
+    lam = np.abs(evals[n_occ:] - eps_v - z)
+    return float(lam.max() / lam.min())

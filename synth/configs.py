@@ -1,0 +1,165 @@
+"""The synthetic Sternheimer workloads, seeded and fully determined.
+
+Each workload is a diamond-structure crystal with the Gaussian empirical local
+pseudopotential of ``crystal.gaussian_potential`` (a = 10.26 bohr), the Bloch
+vector k = Gamma, and a set of (band, frequency, perturbation) solves:
+
+=========  ==========================  =====  ======  ====  =====  ===========================  =====  ======
+name       cell                        atoms  E_cut   grid  n_occ  omega (eV) / eta (eV)        perts  tol
+=========  ==========================  =====  ======  ====  =====  ===========================  =====  ======
+si2        fcc primitive               2      8.157   16^3  4      linspace(0,20,8) / 0.1       4, q=0 1e-10
+si16       fcc 2x2x2                   16     11.46   48^3  32     linspace(0,40,64) / 0.05     50     1e-8
+si64       conventional cubic 2x2x2    64     11.46   72^3  128    linspace(0,40,100) / 0.05    20     1e-8
+=========  ==========================  =====  ======  ====  =====  ===========================  =====  ======
+
+``small(...)`` builds reduced cells of the same recipe for tests.  Seeds are
+``1000*config + system``; when the occupied/unoccupied gap at k or k+q is
+below 1e-3 Ha the seed is bumped by one (the bump is recorded in
+``Problem.seed``).
+"""
+from __future__ import annotations
+
+import dataclasses
+import functools
+
+import numpy as np
+
+from . import crystal as cx
+from .ground_state import lowest_states
+
+A_LAT = 10.26
+MIN_GAP_HA = 1e-3
+
+
+@dataclasses.dataclass
+class Problem:
+    name: str
+    A: np.ndarray
+    B: np.ndarray
+    tau: np.ndarray
+    grid: tuple
+    ecut: float
+    kvec: np.ndarray
+    qvec: np.ndarray
+    miller_k: np.ndarray        # [n_pw_k][3] int32, canonical order
+    miller_kq: np.ndarray       # [n_pw_kq][3]
+    v_grid: np.ndarray          # [N0][N1][N2] float64, Ha
+    n_occ: int
+    n_band: int
+    eps_k: np.ndarray           # [n_occ+1] lowest energies at k (Ha)
+    psi_k: np.ndarray           # [n_occ][n_pw_k] occupied states at k
+    eps_kq: np.ndarray          # [n_occ+1] at k+q
+    psi_kq: np.ndarray          # [n_occ][n_pw_kq] occupied states at k+q
+    omega: np.ndarray           # [n_omega] real frequencies (Ha)
+    eta: float                  # imaginary part of every shift (Ha)
+    dv_miller: np.ndarray       # [n_pert][3] int32, perturbation G_p
+    tol: float
+    seed: int
+
+    @property
+    def kqvec(self):
+        return self.kvec + self.qvec
+
+    @property
+    def n_pw_k(self):
+        return int(self.miller_k.shape[0])
+
+    @property
+    def n_pw_kq(self):
+        return int(self.miller_kq.shape[0])
+
+    @property
+    def n_pert(self):
+        return int(self.dv_miller.shape[0])
+
+    @property
+    def n_omega(self):
+        return int(self.omega.shape[0])
+
+    @property
+    def psi_v(self):
+        return self.psi_k[: self.n_band]
+
+    @property
+    def eps_v(self):
+        return self.eps_k[: self.n_band]
+
+    @property
+    def n_solves(self):
+        return self.n_band * self.n_pert * self.n_omega
+
+    def gap(self):
+        return min(self.eps_k[self.n_occ] - self.eps_k[self.n_occ - 1],
+                   self.eps_kq[self.n_occ] - self.eps_kq[self.n_occ - 1])
+
+
+def make_problem(name, A, tau, grid, ecut, n_occ, omega_ev, eta_ev, n_pert, tol, seed,
+                 q_zero=False, n_band=None, noise=0.05, max_bumps=20):
+    B = cx.reciprocal(A)
+    kvec = np.zeros(3)
+    for bump in range(max_bumps):
+        s = seed + bump
+        qvec = np.zeros(3) if q_zero else cx.seeded_q(B, s)
+        v = cx.gaussian_potential(A, tau, grid, noise=noise, seed=s)
+        mk = cx.g_sphere(B, kvec, ecut)
+        mkq = mk if q_zero else cx.g_sphere(B, kvec + qvec, ecut)
+        ek, pk = lowest_states(mk, B, kvec, v, n_occ + 1)
+        if q_zero:
+            ekq, pkq = ek, pk
+        else:
+            ekq, pkq = lowest_states(mkq, B, kvec + qvec, v, n_occ + 1)
+        gap = min(ek[n_occ] - ek[n_occ - 1], ekq[n_occ] - ekq[n_occ - 1])
+        if gap >= MIN_GAP_HA:
+            break
+    else:  # pragma: no cover
+        raise RuntimeError(f"{name}: no seed with a gap >= {MIN_GAP_HA} Ha")
+    pert = cx.perturbations(B, qvec, n_pert)
+    return Problem(
+        name=name, A=A, B=B, tau=tau, grid=tuple(int(g) for g in grid), ecut=float(ecut),
+        kvec=kvec, qvec=qvec, miller_k=mk, miller_kq=mkq, v_grid=v, n_occ=n_occ,
+        n_band=n_occ if n_band is None else n_band,
+        eps_k=ek, psi_k=np.ascontiguousarray(pk[:n_occ]),
+        eps_kq=ekq, psi_kq=np.ascontiguousarray(pkq[:n_occ]),
+        omega=np.asarray(omega_ev, float) / cx.HA_EV, eta=float(eta_ev) / cx.HA_EV,
+        dv_miller=np.ascontiguousarray(pert.astype(np.int32)), tol=float(tol), seed=s)
+
+
+@functools.lru_cache(maxsize=None)
+def si2():
+    """2-atom fcc cell, 307 PW, 16^3 grid, 4 bands x 8 omegas x 4 perts (q = 0)."""
+    A, tau = cx.fcc_primitive(A_LAT)
+    return make_problem("si2", A, tau, (16, 16, 16), 8.157, 4, cx.frequencies_ev(0, 20, 8), 0.1,
+                        4, 1e-10, 1000, q_zero=True)
+
+
+@functools.lru_cache(maxsize=None)
+def si16():
+    """16-atom fcc 2x2x2 supercell, 4015 PW, 48^3, 32 bands x 64 omegas x 50 perts."""
+    A, tau = cx.supercell(*cx.fcc_primitive(A_LAT), (2, 2, 2))
+    return make_problem("si16", A, tau, (48, 48, 48), 11.46, 32, cx.frequencies_ev(0, 40, 64), 0.05,
+                        50, 1e-8, 2000)
+
+
+@functools.lru_cache(maxsize=None)
+def si64():
+    """64-atom conventional 2x2x2 cell, 15967 PW, 72^3, 128 bands x 100 omegas x 20 perts."""
+    A, tau = cx.supercell(*cx.conventional_cubic(A_LAT), (2, 2, 2))
+    return make_problem("si64", A, tau, (72, 72, 72), 11.46, 128, cx.frequencies_ev(0, 40, 100), 0.05,
+                        20, 1e-8, 4000)
+
+
+@functools.lru_cache(maxsize=None)
+def small(cells=(1, 1, 1), grid=None, ecut=11.46, n_occ=None, n_omega=8, n_pert=3,
+          eta_ev=0.1, omega_hi_ev=20.0, q_zero=False, seed=9000, tol=1e-12, n_band=None):
+    """Reduced fcc n0 x n1 x n2 cells of the same recipe (grid 24 n_d unless given)."""
+    A, tau = cx.supercell(*cx.fcc_primitive(A_LAT), cells)
+    if grid is None:
+        grid = tuple(24 * c for c in cells)
+    if n_occ is None:
+        n_occ = 2 * len(tau)
+    return make_problem(f"small{cells}", A, tau, grid, ecut, n_occ,
+                        cx.frequencies_ev(0, omega_hi_ev, n_omega), eta_ev, n_pert, tol, seed,
+                        q_zero=q_zero, n_band=n_band)
+
+
+CONFIGS = {"si2": si2, "si16": si16, "si64": si64}

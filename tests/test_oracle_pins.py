@@ -1,0 +1,293 @@
+"""Pins of the CPU oracle against facts that do not come from the oracle itself.
+
+The paper prints no worked example for the Sternheimer path (its numerical
+results are band gaps of the full GW pipeline and figures that are not part
+of the text), so the oracle is pinned by:
+
+* closed forms: free electrons (V = const), where H is diagonal and every
+  solve has an analytic value that fixes the sign of the right-hand side, the
+  direction of the perturbation's index shift and the kinetic factor 1/2;
+* brute force: the plane-wave Hamiltonian applied through explicit
+  real-space sums with Cartesian G.r phases (no FFT, no Miller index
+  arithmetic), and the shifted source evaluated in real space;
+* an independent high-precision solve (mpmath, 40 digits) on a tiny basis;
+* two independent direct routes (LU vs the sum over unoccupied states);
+* invariants: Hermiticity, P_occ x = 0, residual, alpha-independence,
+  linearity, reciprocity of the resolvent.
+
+Each pin is a ``check_*`` function so that ``test_planted_mistakes`` can plant
+a plausible mistake into the oracle and confirm that some pin catches it.
+"""
+import numpy as np
+import pytest
+
+import oracle.sternheimer_oracle as so
+from synth import crystal as cx
+
+A_LAT = 10.26
+
+
+def _tiny(ecut=2.1, grid=(8, 8, 8), seed=5, kvec=(0.0, 0.0, 0.0)):
+    A, tau = cx.fcc_primitive(A_LAT)
+    B = cx.reciprocal(A)
+    miller = cx.g_sphere(B, np.asarray(kvec), ecut)
+    rng = np.random.default_rng(seed)
+    v = rng.uniform(-1.0, 0.5, size=grid)       # no symmetry at all
+    return A, B, miller, v
+
+
+def _realspace_apply_h(A, B, miller, kvec, v, x):
+    """y = T x + F V F^-1 x with explicit exponentials of Cartesian G.r (no FFT)."""
+    grid = v.shape
+    j = np.stack(np.meshgrid(*[np.arange(n) for n in grid], indexing="ij"), -1).reshape(-1, 3)
+    r = (j / np.array(grid, float)) @ A                       # Cartesian grid points
+    G = miller.astype(float) @ B                              # Cartesian G (no k: periodic part)
+    phase = np.exp(1j * (r @ G.T))                            # [Nr][Npw]
+    psi_r = phase @ x
+    f = v.reshape(-1) * psi_r
+    y_loc = phase.conj().T @ f / v.size
+    kg = G + np.asarray(kvec, float)
+    return 0.5 * (kg * kg).sum(1) * x + y_loc
+
+
+# ---------------------------------------------------------------------------
+# pins
+# ---------------------------------------------------------------------------
+
+def check_kinetic_closed_form():
+    # simple cubic cell of side a: G_(1,0,0) = (2 pi / a, 0, 0)
+    A = A_LAT * np.eye(3)
+    B = cx.reciprocal(A)
+    m = np.array([[1, 0, 0], [0, -2, 0], [1, 1, 1]])
+    k = np.array([0.1, 0.0, -0.2])
+    g = 2 * np.pi / A_LAT
+    expect = 0.5 * np.array([(g + 0.1) ** 2 + 0.04, 0.01 + 4 * g * g + 0.04,
+                             (g + 0.1) ** 2 + g * g + (g - 0.2) ** 2])
+    assert np.allclose(so.kinetic(m, B, k), expect, rtol=1e-14, atol=0)
+
+
+def check_hamiltonian_bruteforce(kvec=(0.03, -0.02, 0.05)):
+    A, B, miller, v = _tiny(kvec=kvec)
+    h = so.hamiltonian(miller, B, kvec, v)
+    rng = np.random.default_rng(1)
+    x = rng.standard_normal(len(miller)) + 1j * rng.standard_normal(len(miller))
+    y_ref = _realspace_apply_h(A, B, miller, kvec, v, x)
+    err = np.linalg.norm(h @ x - y_ref) / np.linalg.norm(y_ref)
+    assert err <= 1e-13, err
+    assert np.abs(h - h.conj().T).max() <= 1e-14 * np.abs(h).max()
+
+
+def check_shifted_source_realspace():
+    """s(G'') is the k+q coefficient of exp(i(q+G_p).r) psi(r), evaluated on an alias-free grid."""
+    A, tau = cx.fcc_primitive(A_LAT)
+    B = cx.reciprocal(A)
+    k = np.array([0.0, 0.0, 0.0])
+    q = np.array([0.05, 0.11, -0.07])
+    mk = cx.g_sphere(B, k, 2.1)
+    mkq = cx.g_sphere(B, k + q, 2.1)
+    rng = np.random.default_rng(3)
+    psi = rng.standard_normal(len(mk)) + 1j * rng.standard_normal(len(mk))
+    m_p = np.array([1, -1, 0])
+    n = 16                                            # > 2*(max|m| + |m_p|) + 1: no aliasing
+    grid = (n, n, n)
+    j = np.stack(np.meshgrid(*[np.arange(g) for g in grid], indexing="ij"), -1).reshape(-1, 3)
+    r = (j / n) @ A
+    u_k = np.exp(1j * (r @ (mk.astype(float) @ B).T)) @ psi          # periodic part at k
+    g_p = m_p.astype(float) @ B
+    prod = np.exp(1j * (r @ g_p)) * u_k                              # periodic part at k+q
+    coef = np.exp(-1j * (r @ (mkq.astype(float) @ B).T)).T @ prod / r.shape[0]
+    inside = np.array([any((mm - m_p == mk).all(1)) for mm in mkq])
+    s = so.shifted_source(psi, mk, mkq, m_p)
+    assert np.allclose(s[inside], coef[inside], rtol=0, atol=1e-12 * np.abs(psi).max())
+    assert np.all(s[~inside] == 0)
+
+
+def check_free_electron_closed_form():
+    """V = V0: H diagonal; Delta psi has one non-zero coefficient, -1 / (0.5|k+q+G_p|^2 - z)."""
+    A, tau = cx.fcc_primitive(A_LAT)
+    B = cx.reciprocal(A)
+    k = np.zeros(3)
+    q = 0.1 * B[0]
+    v0 = -0.7
+    grid = (10, 10, 10)
+    v = np.full(grid, v0)
+    mk = cx.g_sphere(B, k, 2.1)
+    mkq = cx.g_sphere(B, k + q, 2.1)
+    h_k = so.hamiltonian(mk, B, k, v)
+    h_kq = so.hamiltonian(mkq, B, k + q, v)
+    # the lowest state at k and at k+q is G = 0 (first in canonical order)
+    assert (mk[0] == 0).all() and (mkq[0] == 0).all()
+    psi_k = np.zeros((1, len(mk)), complex); psi_k[0, 0] = 1.0
+    psi_kq = np.zeros((1, len(mkq)), complex); psi_kq[0, 0] = 1.0
+    eps_v = h_k[0, 0].real
+    assert abs(eps_v - v0) < 1e-15
+    zs = np.array([0.0 + 0.01j, 0.3 + 0.05j, -0.2 + 0.002j])
+    w, u = np.linalg.eigh(h_kq)
+    for m_p in ([1, 0, 0], [0, -1, 1], [1, 1, 1]):
+        m_p = np.array(m_p)
+        gidx = int(np.nonzero((mkq == m_p).all(1))[0][0])
+        b = so.rhs(psi_k[0], mk, mkq, m_p, psi_kq)
+        e = np.zeros(len(mkq), complex); e[gidx] = -1.0
+        assert np.array_equal(b, e)
+        ekin = 0.5 * np.sum((k + q + m_p @ B) ** 2)
+        for z in zs:
+            expect = np.zeros(len(mkq), complex)
+            expect[gidx] = -1.0 / (ekin - z)
+            for x in (so.solve_lu(so.coulomb_operator(h_kq, psi_kq, eps_v, 1.0), b, z),
+                      so.solve_spectral(w, u, 1, eps_v, b, [z])[0]):
+                assert np.allclose(x, expect, rtol=0, atol=1e-14 / abs(ekin - z))
+    # G_p = 0 drives the occupied state only: zero right-hand side
+    assert np.abs(so.rhs(psi_k[0], mk, mkq, np.zeros(3, int), psi_kq)).max() == 0.0
+
+
+def _small_problem(q=(0.04, -0.03, 0.09), n_occ=4, seed=11, ecut=2.1):
+    A, B, mk, v = _tiny(seed=seed, ecut=ecut)
+    k = np.zeros(3)
+    q = np.asarray(q, float)
+    mkq = cx.g_sphere(B, k + q, ecut)
+    h_k = so.hamiltonian(mk, B, k, v)
+    h_kq = so.hamiltonian(mkq, B, k + q, v)
+    wk, uk = np.linalg.eigh(h_k)
+    wq, uq = np.linalg.eigh(h_kq)
+    return dict(B=B, mk=mk, mkq=mkq, v=v, h_kq=h_kq, wk=wk, uk=uk, wq=wq, uq=uq, n_occ=n_occ,
+                psi_k=uk[:, :n_occ].T.copy(), psi_kq=uq[:, :n_occ].T.copy())
+
+
+def check_mpmath_tiny():
+    mpmath = pytest.importorskip("mpmath")
+    mpmath.mp.dps = 40
+    P = _small_problem()
+    n_occ, psi_kq = P["n_occ"], P["psi_kq"]
+    v, p = 1, np.array([1, 0, -1])
+    b = so.rhs(P["psi_k"][v], P["mk"], P["mkq"], p, psi_kq)
+    eps_v = P["wk"][v]
+    z = 0.25 + 0.004j
+    a0 = so.coulomb_operator(P["h_kq"], psi_kq, eps_v, 1.0)
+    n = a0.shape[0]
+    M = mpmath.matrix(n, n)
+    for i in range(n):
+        for j in range(n):
+            M[i, j] = mpmath.mpc(complex(a0[i, j])) - (z if i == j else 0)
+    rhs_mp = mpmath.matrix([mpmath.mpc(complex(c)) for c in b])
+    x_mp = mpmath.lu_solve(M, rhs_mp)
+    x_hp = np.array([complex(x_mp[i]) for i in range(n)])
+    kappa = so.condition_number(P["wq"], n_occ, eps_v, z)
+    for x in (so.solve_lu(a0, b, z),
+              so.solve_spectral(P["wq"], P["uq"], n_occ, eps_v, b, [z])[0]):
+        err = np.linalg.norm(x - x_hp) / np.linalg.norm(x_hp)
+        assert err <= 1e-14 * kappa + 1e-15, (err, kappa)
+
+
+def check_routes_and_invariants():
+    P = _small_problem()
+    n_occ, psi_kq = P["n_occ"], P["psi_kq"]
+    zs = np.array([0.0 + 0.003j, 0.4 + 0.003j, 1.1 + 0.02j, -0.3 + 0.01j])
+    for v in range(n_occ):
+        eps_v = P["wk"][v]
+        for p in ([1, 0, 0], [0, 1, -1], [-1, -1, -1]):
+            b = so.rhs(P["psi_k"][v], P["mk"], P["mkq"], np.array(p), psi_kq)
+            xs_s = so.solve_spectral(P["wq"], P["uq"], n_occ, eps_v, b, zs)
+            for z, x_s in zip(zs, xs_s):
+                kappa = so.condition_number(P["wq"], n_occ, eps_v, z)
+                a1 = so.coulomb_operator(P["h_kq"], psi_kq, eps_v, 1.0)
+                x_l = so.solve_lu(a1, b, z)
+                nx = np.linalg.norm(x_l)
+                assert np.linalg.norm(x_l - x_s) <= 1e-13 * kappa * nx
+                # P_occ x = 0
+                assert np.linalg.norm(psi_kq.conj() @ x_l) <= 1e-13 * kappa * nx
+                # residual of the direct solve
+                assert so.relative_residual(a1, x_l, b, z) <= 1e-13
+                # independence of the projector coefficient
+                for alpha in (0.5, 5.0):
+                    x_a = so.solve_lu(so.coulomb_operator(P["h_kq"], psi_kq, eps_v, alpha), b, z)
+                    assert np.linalg.norm(x_a - x_l) <= 1e-13 * kappa * nx
+
+
+def check_linearity_and_reciprocity():
+    P = _small_problem()
+    n_occ, psi_kq = P["n_occ"], P["psi_kq"]
+    eps_v = P["wk"][2]
+    a0 = so.coulomb_operator(P["h_kq"], psi_kq, eps_v, 1.0)
+    b1 = so.rhs(P["psi_k"][2], P["mk"], P["mkq"], np.array([1, 0, 0]), psi_kq)
+    b2 = so.rhs(P["psi_k"][3], P["mk"], P["mkq"], np.array([0, 1, 1]), psi_kq)
+    c = 0.3 - 1.7j
+    z = 0.37 + 0.01j
+    x1, x2 = so.solve_lu(a0, b1, z), so.solve_lu(a0, b2, z)
+    x12 = so.solve_lu(a0, b1 + c * b2, z)
+    assert np.linalg.norm(x12 - x1 - c * x2) <= 1e-12 * np.linalg.norm(x12)
+    # (A - conj z)^{-1} is the adjoint of (A - z)^{-1} for Hermitian A
+    lhs = np.vdot(b2, so.solve_lu(a0, b1, np.conj(z)))
+    rhs = np.vdot(so.solve_lu(a0, b2, z), b1)
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+
+
+def check_generator_ground_state():
+    """The generator's occupied states are eigenstates of the oracle's Hamiltonian."""
+    import synth
+    p = synth.si2()
+    h = so.hamiltonian(p.miller_k, p.B, p.kvec, p.v_grid)
+    hn = np.abs(h).max()
+    res = h @ p.psi_k.T - p.psi_k.T * p.eps_k[None, : p.n_occ]
+    assert np.abs(res).max() <= 1e-11 * hn
+    assert np.abs(p.psi_k.conj() @ p.psi_k.T - np.eye(p.n_occ)).max() <= 1e-12
+    w = np.linalg.eigvalsh(h)
+    assert np.allclose(w[: p.n_occ + 1], p.eps_k, rtol=0, atol=1e-11 * hn)
+    assert p.gap() >= 1e-3
+
+
+PINS = [check_kinetic_closed_form, check_hamiltonian_bruteforce, check_shifted_source_realspace,
+        check_free_electron_closed_form, check_mpmath_tiny, check_routes_and_invariants,
+        check_linearity_and_reciprocity]
+
+
+@pytest.mark.parametrize("pin", PINS + [check_generator_ground_state], ids=lambda f: f.__name__)
+def test_pin(pin):
+    pin()
+
+
+def _run_all_pins():
+    failed = []
+    for pin in PINS:
+        try:
+            pin()
+        except AssertionError:
+            failed.append(pin.__name__)
+    return failed
+
+
+_orig_rhs = so.rhs
+_orig_shift = so.shifted_source
+_orig_kin = so.kinetic
+_orig_coef = so.potential_coefficients
+_orig_op = so.coulomb_operator
+_orig_spec = so.solve_spectral
+
+
+def _mut_transposed_potential(miller, B, kvec, v_grid):
+    h = _orig_ham(miller, B, kvec, v_grid)
+    return h.T.copy()
+
+
+_orig_ham = so.hamiltonian
+
+MUTATIONS = {
+    "rhs_sign": ("rhs", lambda *a: -_orig_rhs(*a)),
+    "rhs_no_projection": ("rhs", lambda psi_v, mk, mkq, mp, po: -_orig_shift(psi_v, mk, mkq, mp)),
+    "shift_direction": ("shifted_source", lambda psi, mk, mkq, mp: _orig_shift(psi, mk, mkq, -np.asarray(mp))),
+    "kinetic_no_half": ("kinetic", lambda m, B, k: 2.0 * _orig_kin(m, B, k)),
+    "kinetic_drops_k": ("kinetic", lambda m, B, k: _orig_kin(m, B, 0.0 * np.asarray(k))),
+    "potential_conjugated": ("potential_coefficients", lambda v: np.conj(_orig_coef(v))),
+    "hamiltonian_transposed": ("hamiltonian", _mut_transposed_potential),
+    "operator_shift_sign": ("coulomb_operator", lambda h, po, e, a: _orig_op(h, po, -e, a)),
+    "spectral_off_by_one": ("solve_spectral", lambda w, u, n, e, b, z: _orig_spec(w, u, n + 1, e, b, z)),
+    "spectral_conj_shift": ("solve_spectral", lambda w, u, n, e, b, z: _orig_spec(w, u, n, e, b, np.conj(z))),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MUTATIONS))
+def test_planted_mistakes(name, monkeypatch):
+    """Plant one plausible mistake in the oracle (on the CPU): at least one pin must fail."""
+    attr, fn = MUTATIONS[name]
+    monkeypatch.setattr(so, attr, fn)
+    failed = _run_all_pins()
+    assert failed, f"no pin caught the planted mistake {name}"
