@@ -1,0 +1,783 @@
+// C ABI of libsgw.so: contexts, Hamiltonians, test hooks and the Sternheimer
+// solve driver (host-side scheduling of the device-resident Krylov slots).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "sgw_internal.h"
+#include "solver_state.h"
+
+namespace sgw {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+sgw_status fail(sgw_status code, const std::string &msg) {
+  g_last_error = msg;
+  return code;
+}
+
+const char *kernel_name(int id) {
+  static const char *names[K_COUNT] = {"hx_sticks_inv", "hx_planes", "hx_sticks_fwd", "proj_dot",
+                                       "proj_apply",    "rhs_source", "slot_init",    "lanczos_step",
+                                       "tridiag",       "combine",   "residual",     "permute"};
+  return (id >= 0 && id < K_COUNT) ? names[id] : "?";
+}
+
+static hipEvent_t get_event(sgw_ctx *ctx) {
+  if (!ctx->event_pool.empty()) {
+    hipEvent_t e = ctx->event_pool.back();
+    ctx->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+void timing_begin(sgw_ctx *ctx, int kid, double bytes, double flops, PendingTiming *t) {
+  t->kid = -1;
+  if (!(ctx->profile_mask & (1u << kid))) return;
+  t->kid = kid;
+  t->bytes = bytes;
+  t->flops = flops;
+  t->start = get_event(ctx);
+  t->stop = get_event(ctx);
+  if (!t->start || !t->stop) {
+    t->kid = -1;
+    return;
+  }
+  hipEventRecord(t->start, ctx->stream);
+}
+
+void timing_end(sgw_ctx *ctx, PendingTiming *t) {
+  if (t->kid < 0) return;
+  hipEventRecord(t->stop, ctx->stream);
+  ctx->pending.push_back(*t);
+}
+
+// Must be called after the stream has been synchronised.
+sgw_status timing_collect(sgw_ctx *ctx) {
+  for (auto &p : ctx->pending) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, p.start, p.stop) == hipSuccess) {
+      KernelStat &s = ctx->stats[p.kid];
+      s.launches += 1;
+      s.ms += ms;
+      s.bytes += p.bytes;
+      s.flops += p.flops;
+    }
+    ctx->event_pool.push_back(p.start);
+    ctx->event_pool.push_back(p.stop);
+  }
+  ctx->pending.clear();
+  return SGW_OK;
+}
+
+static sgw_status ensure_pinned(sgw_ctx *ctx, size_t bytes) {
+  if (ctx->pinned_bytes >= bytes) return SGW_OK;
+  if (ctx->pinned) hipHostFree(ctx->pinned);
+  ctx->pinned = nullptr;
+  ctx->pinned_bytes = 0;
+  size_t nb = std::max<size_t>(bytes, 1 << 16);
+  SGW_HIP(hipHostMalloc(&ctx->pinned, nb, hipHostMallocDefault));
+  ctx->pinned_bytes = nb;
+  return SGW_OK;
+}
+
+static sgw_status sync(sgw_ctx *ctx) {
+  SGW_HIP(hipStreamSynchronize(ctx->stream));
+  return timing_collect(ctx);
+}
+
+}  // namespace sgw
+
+using namespace sgw;
+
+// ---------------------------------------------------------------------------
+// misc
+// ---------------------------------------------------------------------------
+extern "C" const char *sgw_last_error(void) { return g_last_error.c_str(); }
+extern "C" const char *sgw_version(void) { return "sgw-mi355x 0.1 (gfx950)"; }
+
+extern "C" sgw_status sgw_ctx_create(int device, void *hip_stream, sgw_ctx **out) {
+  if (!out) return fail(SGW_ERR_INVALID_ARG, "sgw_ctx_create: out is NULL");
+  *out = nullptr;
+  int ndev = 0;
+  SGW_HIP(hipGetDeviceCount(&ndev));
+  if (device < 0 || device >= ndev) return fail(SGW_ERR_INVALID_ARG, "sgw_ctx_create: no such device");
+  SGW_HIP(hipSetDevice(device));
+  sgw_ctx *c = new sgw_ctx();
+  c->device = device;
+  c->stream = (hipStream_t)hip_stream;
+  *out = c;
+  return SGW_OK;
+}
+
+extern "C" sgw_status sgw_ctx_destroy(sgw_ctx *ctx) {
+  if (!ctx) return SGW_OK;
+  hipSetDevice(ctx->device);
+  hipStreamSynchronize(ctx->stream);
+  timing_collect(ctx);
+  for (auto e : ctx->event_pool) hipEventDestroy(e);
+  if (ctx->pinned) hipHostFree(ctx->pinned);
+  delete ctx;
+  return SGW_OK;
+}
+
+extern "C" sgw_status sgw_ctx_set_profiling(sgw_ctx *ctx, const char *kernels) {
+  if (!ctx) return fail(SGW_ERR_INVALID_ARG, "ctx is NULL");
+  if (!kernels || !*kernels) {
+    ctx->profile_mask = 0;
+    return SGW_OK;
+  }
+  if (std::strcmp(kernels, "all") == 0) {
+    ctx->profile_mask = (1u << K_COUNT) - 1;
+    return SGW_OK;
+  }
+  unsigned mask = 0;
+  std::string s(kernels);
+  size_t pos = 0;
+  while (pos <= s.size()) {
+    size_t e = s.find(',', pos);
+    if (e == std::string::npos) e = s.size();
+    const std::string name = s.substr(pos, e - pos);
+    int k = 0;
+    for (; k < K_COUNT; ++k)
+      if (name == kernel_name(k)) break;
+    if (k == K_COUNT) return fail(SGW_ERR_INVALID_ARG, "sgw_ctx_set_profiling: unknown kernel " + name);
+    mask |= 1u << k;
+    pos = e + 1;
+  }
+  ctx->profile_mask = mask;
+  return SGW_OK;
+}
+
+extern "C" sgw_status sgw_ctx_reset_stats(sgw_ctx *ctx) {
+  if (!ctx) return fail(SGW_ERR_INVALID_ARG, "ctx is NULL");
+  for (auto &s : ctx->stats) s = KernelStat();
+  return SGW_OK;
+}
+
+extern "C" sgw_status sgw_kernel_stats(sgw_ctx *ctx, const char *name, int64_t *launches, double *total_ms,
+                                       double *alg_bytes, double *alg_flops) {
+  if (!ctx || !name) return fail(SGW_ERR_INVALID_ARG, "sgw_kernel_stats: NULL argument");
+  for (int k = 0; k < K_COUNT; ++k) {
+    if (std::strcmp(kernel_name(k), name) == 0) {
+      const KernelStat &s = ctx->stats[k];
+      if (launches) *launches = s.launches;
+      if (total_ms) *total_ms = s.ms;
+      if (alg_bytes) *alg_bytes = s.bytes;
+      if (alg_flops) *alg_flops = s.flops;
+      return SGW_OK;
+    }
+  }
+  return fail(SGW_ERR_INVALID_ARG, std::string("sgw_kernel_stats: unknown kernel ") + name);
+}
+
+// ---------------------------------------------------------------------------
+// Hamiltonian
+// ---------------------------------------------------------------------------
+static int imod(int a, int n) {
+  int r = a % n;
+  return r < 0 ? r + n : r;
+}
+
+template <class T>
+static sgw_status upload(sgw_ctx *ctx, T **dst, const std::vector<T> &src) {
+  *dst = nullptr;
+  if (src.empty()) return SGW_OK;
+  SGW_HIP(hipMalloc((void **)dst, sizeof(T) * src.size()));
+  SGW_HIP(hipMemcpyAsync(*dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice, ctx->stream));
+  return SGW_OK;
+}
+
+static void ham_free(sgw_ham *h) {
+  if (!h) return;
+  void *ptrs[] = {h->d_i2u, h->d_u2i, h->d_stick_off, h->d_stick_xy, h->d_pw_stick, h->d_pw_z,
+                  h->d_miller_int, h->d_kin, h->d_vt, h->d_box, h->d_tw};
+  for (void *p : ptrs)
+    if (p) hipFree(p);
+  delete h;
+}
+
+extern "C" sgw_status sgw_ham_create(sgw_ctx *ctx, const sgw_ham_desc *d, sgw_ham **out) {
+  if (!ctx || !d || !out) return fail(SGW_ERR_INVALID_ARG, "sgw_ham_create: NULL argument");
+  *out = nullptr;
+  if (d->n_pw <= 0 || !d->miller) return fail(SGW_ERR_INVALID_ARG, "sgw_ham_create: empty basis");
+  if (!d->v_loc) return fail(SGW_ERR_INVALID_ARG, "sgw_ham_create: v_loc is NULL");
+  for (int a = 0; a < 3; ++a) {
+    if (!hx_grid_supported(d->grid[a]))
+      return fail(SGW_ERR_UNSUPPORTED, "sgw_ham_create: grid size " + std::to_string(d->grid[a]) +
+                                           " not in {16,24,32,48,64,72,96}");
+  }
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b)
+      if (!std::isfinite(d->recip[a][b])) return fail(SGW_ERR_INVALID_ARG, "sgw_ham_create: recip not finite");
+  for (int a = 0; a < 3; ++a)
+    if (!std::isfinite(d->kvec[a])) return fail(SGW_ERR_INVALID_ARG, "sgw_ham_create: kvec not finite");
+  const int npw = d->n_pw;
+  const int *n = d->grid;
+  int mmin[3] = {1 << 30, 1 << 30, 1 << 30}, mmax[3] = {-(1 << 30), -(1 << 30), -(1 << 30)};
+  for (int g = 0; g < npw; ++g)
+    for (int a = 0; a < 3; ++a) {
+      mmin[a] = std::min(mmin[a], d->miller[3 * g + a]);
+      mmax[a] = std::max(mmax[a], d->miller[3 * g + a]);
+    }
+  for (int a = 0; a < 3; ++a) {
+    const int amax = std::max(std::abs(mmin[a]), std::abs(mmax[a]));
+    if (2 * amax + 1 > n[a])
+      return fail(SGW_ERR_INVALID_ARG, "sgw_ham_create: grid too small for the basis along axis " +
+                                           std::to_string(a) + " (need 2*max|m|+1 <= N)");
+  }
+  // lookup box and distinctness
+  int box_dim[3];
+  long box_vol = 1;
+  for (int a = 0; a < 3; ++a) {
+    box_dim[a] = mmax[a] - mmin[a] + 1;
+    box_vol *= box_dim[a];
+  }
+  if (box_vol > (1L << 28)) return fail(SGW_ERR_INVALID_ARG, "sgw_ham_create: Miller range too large");
+  std::vector<int32_t> box(box_vol, -1);
+  for (int g = 0; g < npw; ++g) {
+    const int *m = d->miller + 3 * g;
+    const long idx = ((long)(m[0] - mmin[0]) * box_dim[1] + (m[1] - mmin[1])) * box_dim[2] + (m[2] - mmin[2]);
+    if (box[idx] >= 0) return fail(SGW_ERR_INVALID_ARG, "sgw_ham_create: repeated Miller index");
+    box[idx] = g;
+  }
+  // sticks along axis 2, sorted by (m0, m1); plane waves within a stick by m2
+  std::vector<int> order(npw);
+  std::iota(order.begin(), order.end(), 0);
+  std::sort(order.begin(), order.end(), [&](int a, int b) {
+    const int *ma = d->miller + 3 * a, *mb = d->miller + 3 * b;
+    if (ma[0] != mb[0]) return ma[0] < mb[0];
+    if (ma[1] != mb[1]) return ma[1] < mb[1];
+    return ma[2] < mb[2];
+  });
+  std::vector<int32_t> i2u(npw), u2i(npw), pw_stick(npw), pw_z(npw), miller_int(3 * npw), stick_off, stick_xy;
+  std::vector<double> kin(npw);
+  int ns = 0;
+  for (int gi = 0; gi < npw; ++gi) {
+    const int u = order[gi];
+    const int *m = d->miller + 3 * u;
+    if (gi == 0 || m[0] != d->miller[3 * order[gi - 1]] || m[1] != d->miller[3 * order[gi - 1] + 1]) {
+      stick_off.push_back(gi);
+      stick_xy.push_back((imod(m[0], n[0]) << 16) | imod(m[1], n[1]));
+      ++ns;
+    }
+    i2u[gi] = u;
+    u2i[u] = gi;
+    pw_stick[gi] = ns - 1;
+    pw_z[gi] = imod(m[2], n[2]);
+    for (int a = 0; a < 3; ++a) miller_int[3 * gi + a] = m[a];
+    double kg[3];
+    for (int c = 0; c < 3; ++c)
+      kg[c] = d->kvec[c] + m[0] * d->recip[0][c] + m[1] * d->recip[1][c] + m[2] * d->recip[2][c];
+    kin[gi] = 0.5 * (kg[0] * kg[0] + kg[1] * kg[1] + kg[2] * kg[2]);
+  }
+  stick_off.push_back(npw);
+  // twiddle tables exp(-2 pi i t / N) for the three axes
+  std::vector<double2> tw;
+  int tw_off[3];
+  for (int a = 0; a < 3; ++a) {
+    tw_off[a] = (int)tw.size();
+    for (int t = 0; t < n[a]; ++t) {
+      const long double ang = -2.0L * 3.14159265358979323846264338327950288L * t / n[a];
+      tw.push_back(make_double2((double)cosl(ang), (double)sinl(ang)));
+    }
+  }
+  SGW_HIP(hipSetDevice(ctx->device));
+  sgw_ham *h = new sgw_ham();
+  h->ctx = ctx;
+  h->device = ctx->device;
+  for (int a = 0; a < 3; ++a) {
+    h->n[a] = n[a];
+    h->kvec[a] = d->kvec[a];
+    h->box_lo[a] = mmin[a];
+    h->box_dim[a] = box_dim[a];
+    h->tw_off[a] = tw_off[a];
+    for (int b = 0; b < 3; ++b) h->recip[a][b] = d->recip[a][b];
+  }
+  h->n_pw = npw;
+  h->n_stick = ns;
+  h->m0_lo = mmin[0];
+  h->n_row = mmax[0] - mmin[0] + 1;
+  h->miller.assign(d->miller, d->miller + 3 * npw);
+  sgw_status st = SGW_OK;
+#define SGW_UP(dst, src)                                   \
+  if ((st = upload(ctx, &(dst), (src))) != SGW_OK) {        \
+    hipStreamSynchronize(ctx->stream);                      \
+    ham_free(h);                                            \
+    return st;                                              \
+  }
+  SGW_UP(h->d_i2u, i2u);
+  SGW_UP(h->d_u2i, u2i);
+  SGW_UP(h->d_stick_off, stick_off);
+  SGW_UP(h->d_stick_xy, stick_xy);
+  SGW_UP(h->d_pw_stick, pw_stick);
+  SGW_UP(h->d_pw_z, pw_z);
+  SGW_UP(h->d_miller_int, miller_int);
+  SGW_UP(h->d_kin, kin);
+  SGW_UP(h->d_box, box);
+  SGW_UP(h->d_tw, tw);
+#undef SGW_UP
+  const long ntot = (long)n[0] * n[1] * n[2];
+  hipError_t e = hipMalloc((void **)&h->d_vt, sizeof(double) * ntot);
+  if (e != hipSuccess) {
+    hipStreamSynchronize(ctx->stream);
+    ham_free(h);
+    return fail(SGW_ERR_HIP, std::string("hipMalloc: ") + hipGetErrorString(e));
+  }
+  st = transpose_potential(ctx, d->v_loc, h->d_vt, n);
+  e = hipStreamSynchronize(ctx->stream);
+  if (st != SGW_OK || e != hipSuccess) {
+    ham_free(h);
+    return st != SGW_OK ? st : fail(SGW_ERR_HIP, std::string("sgw_ham_create: ") + hipGetErrorString(e));
+  }
+  *out = h;
+  return SGW_OK;
+}
+
+extern "C" sgw_status sgw_ham_destroy(sgw_ham *h) {
+  if (!h) return SGW_OK;
+  // the context may already be gone: only the device id is used (hipFree waits for the device)
+  hipSetDevice(h->device);
+  ham_free(h);
+  return SGW_OK;
+}
+
+extern "C" int32_t sgw_ham_npw(const sgw_ham *h) { return h ? h->n_pw : -1; }
+
+// ---------------------------------------------------------------------------
+// test hooks
+// ---------------------------------------------------------------------------
+namespace {
+
+// scratch of the test hooks; freed after the hook has synchronised its stream
+struct DevBuf {
+  void *p = nullptr;
+  ~DevBuf() {
+    if (p) hipFree(p);
+  }
+};
+
+sgw_status alloc_async(DevBuf &b, size_t bytes, hipStream_t) {
+  SGW_HIP(hipMalloc(&b.p, std::max<size_t>(bytes, 256)));
+  return SGW_OK;
+}
+
+}  // namespace
+
+extern "C" sgw_status sgw_apply_h(sgw_ctx *ctx, const sgw_ham *h, int n_vec, const sgw_c128 *x, sgw_c128 *y) {
+  if (!ctx || !h) return fail(SGW_ERR_INVALID_ARG, "sgw_apply_h: NULL context or Hamiltonian");
+  if (n_vec < 0) return fail(SGW_ERR_INVALID_ARG, "sgw_apply_h: n_vec < 0");
+  if (n_vec == 0) return SGW_OK;
+  if (!x || !y) return fail(SGW_ERR_INVALID_ARG, "sgw_apply_h: NULL vector");
+  if (x == y) return fail(SGW_ERR_INVALID_ARG, "sgw_apply_h: x and y alias");
+  SGW_HIP(hipSetDevice(ctx->device));
+  const int npw = h->n_pw;
+  const size_t vb = sizeof(double2) * (size_t)npw * n_vec;
+  DevBuf xi, yi, tb;
+  sgw_status st;
+  if ((st = alloc_async(xi, vb, ctx->stream)) != SGW_OK) return st;
+  if ((st = alloc_async(yi, vb, ctx->stream)) != SGW_OK) return st;
+  if ((st = alloc_async(tb, sizeof(double2) * (size_t)n_vec * h->n[2] * h->n_stick, ctx->stream)) != SGW_OK)
+    return st;
+  if ((st = permute(ctx, npw, n_vec, (const double2 *)x, npw, (double2 *)xi.p, npw, h->d_i2u, 0)) != SGW_OK)
+    return st;
+  if ((st = hx_batch(ctx, h, n_vec, contiguous((double2 *)xi.p, npw), (double2 *)yi.p, npw, (double2 *)tb.p)) !=
+      SGW_OK)
+    return st;
+  if ((st = permute(ctx, npw, n_vec, (double2 *)yi.p, npw, (double2 *)y, npw, h->d_i2u, 1)) != SGW_OK) return st;
+  return sync(ctx);
+}
+
+extern "C" sgw_status sgw_apply_projector(sgw_ctx *ctx, const sgw_ham *h, int n_occ, const sgw_c128 *psi,
+                                          int n_vec, const sgw_c128 *x, sgw_c128 *y, double alpha, int mode) {
+  if (!ctx || !h) return fail(SGW_ERR_INVALID_ARG, "sgw_apply_projector: NULL context or Hamiltonian");
+  if (n_vec < 0 || n_occ < 0) return fail(SGW_ERR_INVALID_ARG, "sgw_apply_projector: negative size");
+  if (mode != 0 && mode != 1) return fail(SGW_ERR_INVALID_ARG, "sgw_apply_projector: mode must be 0 or 1");
+  if (n_vec == 0) return SGW_OK;
+  if (!x || !y || (n_occ > 0 && !psi)) return fail(SGW_ERR_INVALID_ARG, "sgw_apply_projector: NULL array");
+  if (x == y) return fail(SGW_ERR_INVALID_ARG, "sgw_apply_projector: x and y alias");
+  SGW_HIP(hipSetDevice(ctx->device));
+  const int npw = h->n_pw;
+  DevBuf cb;
+  sgw_status st;
+  if ((st = alloc_async(cb, sizeof(double2) * (size_t)n_vec * std::max(n_occ, 1), ctx->stream)) != SGW_OK) return st;
+  if ((st = proj_dot(ctx, npw, n_occ, (const double2 *)psi, n_vec, contiguous((const double2 *)x, npw),
+                     (double2 *)cb.p)) != SGW_OK)
+    return st;
+  if ((st = proj_apply(ctx, npw, n_occ, (const double2 *)psi, n_vec, contiguous((const double2 *)x, npw),
+                       (double2 *)cb.p, (double2 *)y, npw, alpha, mode)) != SGW_OK)
+    return st;
+  return sync(ctx);
+}
+
+static sgw_status check_miller_shift(const int32_t *dvm, int n_pert) {
+  for (int p = 0; p < n_pert; ++p)
+    for (int a = 0; a < 3; ++a)
+      if (std::abs(dvm[3 * p + a]) > (1 << 20)) return fail(SGW_ERR_INVALID_ARG, "dv_miller out of range");
+  return SGW_OK;
+}
+
+extern "C" sgw_status sgw_build_rhs(sgw_ctx *ctx, const sgw_ham *h_kq, int n_occ, const sgw_c128 *psi_occ_kq,
+                                    const sgw_ham *h_k, int n_band, const sgw_c128 *psi_v, int n_pert,
+                                    const int32_t *dv_miller, sgw_c128 *b) {
+  if (!ctx || !h_kq || !h_k) return fail(SGW_ERR_INVALID_ARG, "sgw_build_rhs: NULL context or Hamiltonian");
+  if (n_occ < 0 || n_band < 0 || n_pert < 0) return fail(SGW_ERR_INVALID_ARG, "sgw_build_rhs: negative size");
+  const int nvec = n_band * n_pert;
+  if (nvec == 0) return SGW_OK;
+  if (!psi_v || !dv_miller || !b || (n_occ > 0 && !psi_occ_kq))
+    return fail(SGW_ERR_INVALID_ARG, "sgw_build_rhs: NULL array");
+  sgw_status st;
+  if ((st = check_miller_shift(dv_miller, n_pert)) != SGW_OK) return st;
+  SGW_HIP(hipSetDevice(ctx->device));
+  const int npw = h_kq->n_pw;
+  DevBuf pairs, dvm, s, c, psi;
+  if ((st = alloc_async(pairs, sizeof(int32_t) * nvec, ctx->stream)) != SGW_OK) return st;
+  if ((st = alloc_async(dvm, sizeof(int32_t) * 3 * n_pert, ctx->stream)) != SGW_OK) return st;
+  if ((st = alloc_async(s, sizeof(double2) * (size_t)nvec * npw, ctx->stream)) != SGW_OK) return st;
+  if ((st = alloc_async(c, sizeof(double2) * (size_t)nvec * std::max(n_occ, 1), ctx->stream)) != SGW_OK) return st;
+  if ((st = alloc_async(psi, sizeof(double2) * (size_t)std::max(n_occ, 1) * npw, ctx->stream)) != SGW_OK) return st;
+  std::vector<int32_t> hp(nvec);
+  std::iota(hp.begin(), hp.end(), 0);
+  SGW_HIP(hipMemcpyAsync(pairs.p, hp.data(), sizeof(int32_t) * nvec, hipMemcpyHostToDevice, ctx->stream));
+  SGW_HIP(hipMemcpyAsync(dvm.p, dv_miller, sizeof(int32_t) * 3 * n_pert, hipMemcpyHostToDevice, ctx->stream));
+  // internal-order copy of the occupied states
+  if ((st = permute(ctx, npw, n_occ, (const double2 *)psi_occ_kq, npw, (double2 *)psi.p, npw, h_kq->d_i2u, 0)) !=
+      SGW_OK)
+    return st;
+  if ((st = rhs_source(ctx, h_kq, h_k, nvec, (int32_t *)pairs.p, n_pert, (int32_t *)dvm.p,
+                       (const double2 *)psi_v, h_k->n_pw, (double2 *)s.p, npw)) != SGW_OK)
+    return st;
+  if ((st = proj_dot(ctx, npw, n_occ, (double2 *)psi.p, nvec, contiguous((double2 *)s.p, npw), (double2 *)c.p)) !=
+      SGW_OK)
+    return st;
+  // b = -(s - psi^T c): y = s - psi^T c here, negated by the scatter to the caller's order
+  DevBuf bi;
+  if ((st = alloc_async(bi, sizeof(double2) * (size_t)nvec * npw, ctx->stream)) != SGW_OK) return st;
+  if ((st = proj_apply(ctx, npw, n_occ, (double2 *)psi.p, nvec, contiguous((double2 *)s.p, npw), (double2 *)c.p,
+                       (double2 *)bi.p, npw, 1.0, 0)) != SGW_OK)
+    return st;
+  if ((st = permute(ctx, npw, nvec, (double2 *)bi.p, npw, (double2 *)b, npw, h_kq->d_i2u, 1, -1.0)) != SGW_OK)
+    return st;
+  st = sync(ctx);
+  return st;
+}
+
+// ---------------------------------------------------------------------------
+// the solver
+// ---------------------------------------------------------------------------
+extern "C" sgw_status sgw_opts_default(sgw_opts *o) {
+  if (!o) return fail(SGW_ERR_INVALID_ARG, "sgw_opts_default: NULL");
+  std::memset(o, 0, sizeof(*o));
+  o->precision = SGW_FP64;
+  o->max_iter = 600;
+  o->alpha_pv = 1.0;
+  o->tol_safety = 0.1;
+  o->slots = 0;
+  o->finalize_batch = 0;
+  o->steps_per_sync = 8;
+  return SGW_OK;
+}
+
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr double kDefaultBudget = 40.0 * (1ull << 30);
+
+struct Layout {
+  int S = 0, F = 0, kmax = 0, M = 8;
+  size_t psi, omega, epsb, dvm, pair, kcur, status, eps, alpha, beta, rho, res, bvec, basis;
+  size_t l_active, l_fill, l_fillpairs, l_final, Y, C, T, ycoef, cp, X, AX, bad;
+  size_t total = 0;
+};
+
+size_t take(size_t &off, size_t bytes) {
+  off = (off + kAlign - 1) / kAlign * kAlign;
+  size_t r = off;
+  off += std::max<size_t>(bytes, 1);
+  return r;
+}
+
+sgw_opts resolve_opts(const sgw_opts *in) {
+  sgw_opts o;
+  sgw_opts_default(&o);
+  if (in) {
+    o.precision = in->precision;
+    if (in->max_iter > 0) o.max_iter = in->max_iter;
+    if (in->alpha_pv > 0) o.alpha_pv = in->alpha_pv;
+    if (in->tol_safety > 0) o.tol_safety = in->tol_safety;
+    o.slots = in->slots;
+    o.finalize_batch = in->finalize_batch;
+    if (in->steps_per_sync > 0) o.steps_per_sync = in->steps_per_sync;
+  }
+  return o;
+}
+
+Layout make_layout(const sgw_ham *h, int n_occ, int n_band, int n_pert, int n_omega, const sgw_opts &o) {
+  Layout L;
+  const long npw = h->n_pw;
+  const int n_pairs = n_band * n_pert;
+  L.kmax = o.max_iter;
+  L.M = o.steps_per_sync;
+  L.F = o.finalize_batch > 0 ? o.finalize_batch : std::max(1, (4096 + n_omega - 1) / n_omega);
+  L.F = std::max(1, std::min(L.F, std::max(n_pairs, 1)));
+  const double per_slot = (double)(L.kmax + 3) * npw * 16.0 + (double)npw * 16.0 * h->n[2] * 0 +
+                          (double)h->n[2] * h->n_stick * 16.0 + (L.kmax * 2.0 + n_omega * 24.0 + 64.0);
+  int S = o.slots;
+  if (S <= 0) {
+    const double fixed = (double)L.F * n_omega * (2.0 * npw * 16.0 + h->n[2] * h->n_stick * 16.0);
+    S = (int)std::max(1.0, (kDefaultBudget - fixed) / per_slot);
+    S = std::min(S, 4096);
+  }
+  L.S = std::max(1, std::min(S, std::max(n_pairs, 1)));
+  const long nfv = (long)L.F * n_omega;
+  const long tv = std::max<long>(L.S, nfv);
+  size_t off = 0;
+  L.psi = take(off, 16ul * std::max(n_occ, 1) * npw);
+  L.omega = take(off, 8ul * n_omega);
+  L.epsb = take(off, 8ul * std::max(n_band, 1));
+  L.dvm = take(off, 12ul * std::max(n_pert, 1));
+  L.pair = take(off, 4ul * L.S);
+  L.kcur = take(off, 4ul * L.S);
+  L.status = take(off, 4ul * L.S);
+  L.eps = take(off, 8ul * L.S);
+  L.alpha = take(off, 8ul * L.S * L.kmax);
+  L.beta = take(off, 8ul * L.S * (L.kmax + 1));
+  L.rho = take(off, 16ul * L.S * n_omega);
+  L.res = take(off, 8ul * L.S * n_omega);
+  L.bvec = take(off, 16ul * L.S * npw);
+  L.basis = take(off, 16ul * L.S * (L.kmax + 1) * npw);
+  L.l_active = take(off, 4ul * L.S);
+  L.l_fill = take(off, 4ul * L.S);
+  L.l_fillpairs = take(off, 4ul * L.S);
+  L.l_final = take(off, 4ul * L.S);
+  L.Y = take(off, 16ul * L.S * npw);
+  L.C = take(off, 16ul * tv * std::max(n_occ, 1));
+  L.T = take(off, 16ul * tv * h->n[2] * h->n_stick);
+  L.ycoef = take(off, 16ul * L.F * L.kmax * n_omega);
+  L.cp = take(off, 16ul * L.F * L.kmax * n_omega);
+  L.X = take(off, 16ul * nfv * npw);
+  L.AX = take(off, 16ul * nfv * npw);
+  L.bad = take(off, 64);
+  L.total = (off + kAlign - 1) / kAlign * kAlign;
+  return L;
+}
+
+}  // namespace
+
+static sgw_status validate_solve(sgw_ctx *ctx, const sgw_ham *h_kq, int n_occ, const sgw_c128 *psi_occ_kq,
+                                 const sgw_ham *h_k, int n_band, const sgw_c128 *psi_v, const double *eps_v,
+                                 int n_pert, const int32_t *dv_miller, int n_omega, const double *omega, double eta,
+                                 double tol, const sgw_opts &o) {
+  SGW_CHECK(ctx && h_kq && h_k, "sternheimer_solve: NULL context or Hamiltonian");
+  SGW_CHECK(h_kq->ctx == ctx && h_k->ctx == ctx, "sternheimer_solve: Hamiltonian of another context");
+  SGW_CHECK(n_occ >= 0 && n_band >= 0 && n_pert >= 0 && n_omega >= 0, "sternheimer_solve: negative size");
+  if (n_occ > kMaxOcc)
+    return fail(SGW_ERR_UNSUPPORTED, "sternheimer_solve: n_occ above " + std::to_string(kMaxOcc));
+  SGW_CHECK(n_occ < h_kq->n_pw, "sternheimer_solve: n_occ must be below the basis size");
+  SGW_CHECK(o.precision == SGW_FP64, "sternheimer_solve: unknown precision mode");
+  SGW_CHECK(o.max_iter >= 1 && o.max_iter <= 100000, "sternheimer_solve: max_iter out of range");
+  SGW_CHECK(std::isfinite(eta) && eta != 0.0, "sternheimer_solve: eta must be finite and non-zero");
+  SGW_CHECK(std::isfinite(tol) && tol > 0.0, "sternheimer_solve: tol must be positive");
+  SGW_CHECK(std::isfinite(o.alpha_pv) && o.alpha_pv > 0.0, "sternheimer_solve: alpha_pv must be positive");
+  if ((long)n_band * n_pert * n_omega == 0) return SGW_OK;
+  SGW_CHECK(psi_v && eps_v && dv_miller && omega, "sternheimer_solve: NULL input array");
+  SGW_CHECK(n_occ == 0 || psi_occ_kq, "sternheimer_solve: psi_occ_kq is NULL");
+  for (int j = 0; j < n_omega; ++j) SGW_CHECK(std::isfinite(omega[j]), "sternheimer_solve: omega not finite");
+  for (int v = 0; v < n_band; ++v) SGW_CHECK(std::isfinite(eps_v[v]), "sternheimer_solve: eps_v not finite");
+  if (lanczos_ept(h_kq->n_pw) > 32) return fail(SGW_ERR_UNSUPPORTED, "sternheimer_solve: basis above 16384");
+  return check_miller_shift(dv_miller, n_pert);
+}
+
+extern "C" sgw_status sternheimer_workspace_size(sgw_ctx *ctx, const sgw_ham *h_kq, int n_occ, int n_band,
+                                                 int n_pert, int n_omega, const sgw_opts *opts, size_t *bytes) {
+  if (!ctx || !h_kq || !bytes) return fail(SGW_ERR_INVALID_ARG, "sternheimer_workspace_size: NULL argument");
+  if (n_occ < 0 || n_band < 0 || n_pert < 0 || n_omega < 0)
+    return fail(SGW_ERR_INVALID_ARG, "sternheimer_workspace_size: negative size");
+  const sgw_opts o = resolve_opts(opts);
+  *bytes = make_layout(h_kq, n_occ, n_band, n_pert, std::max(n_omega, 1), o).total;
+  return SGW_OK;
+}
+
+extern "C" sgw_status sternheimer_solve(sgw_ctx *ctx, const sgw_ham *h_kq, int n_occ, const sgw_c128 *psi_occ_kq,
+                                        const sgw_ham *h_k, int n_band, const sgw_c128 *psi_v, const double *eps_v,
+                                        int n_pert, const int32_t *dv_miller, int n_omega, const double *omega,
+                                        double eta, double tol, const sgw_opts *opts, void *workspace,
+                                        size_t workspace_bytes, sgw_c128 *dpsi, sgw_solve_info *info) {
+  const sgw_opts o = resolve_opts(opts);
+  sgw_status st = validate_solve(ctx, h_kq, n_occ, psi_occ_kq, h_k, n_band, psi_v, eps_v, n_pert, dv_miller,
+                                 n_omega, omega, eta, tol, o);
+  if (st != SGW_OK) return st;
+  const int n_pairs = n_band * n_pert;
+  if ((long)n_pairs * n_omega == 0) return SGW_OK;
+  SGW_CHECK(dpsi && info, "sternheimer_solve: NULL output array");
+  const Layout L = make_layout(h_kq, n_occ, n_band, n_pert, n_omega, o);
+  if (!workspace || workspace_bytes < L.total)
+    return fail(SGW_ERR_WORKSPACE, "sternheimer_solve: workspace needs " + std::to_string(L.total) + " bytes");
+  if (((uintptr_t)workspace) % kAlign != 0)
+    return fail(SGW_ERR_WORKSPACE, "sternheimer_solve: workspace must be 256-byte aligned");
+  SGW_HIP(hipSetDevice(ctx->device));
+  char *W = (char *)workspace;
+  const int npw = h_kq->n_pw;
+  const int S = L.S, F = L.F;
+
+  SolverState Sx;
+  Sx.npw = npw;
+  Sx.n_occ = n_occ;
+  Sx.n_omega = n_omega;
+  Sx.n_pert = n_pert;
+  Sx.kmax = L.kmax;
+  Sx.slot_stride = (long)(L.kmax + 1) * npw;
+  Sx.psi = (double2 *)(W + L.psi);
+  Sx.basis = (double2 *)(W + L.basis);
+  Sx.bvec = (double2 *)(W + L.bvec);
+  Sx.alpha_t = (double *)(W + L.alpha);
+  Sx.beta = (double *)(W + L.beta);
+  Sx.rho = (double2 *)(W + L.rho);
+  Sx.res = (double *)(W + L.res);
+  Sx.pair = (int32_t *)(W + L.pair);
+  Sx.kcur = (int32_t *)(W + L.kcur);
+  Sx.status = (int32_t *)(W + L.status);
+  Sx.eps = (double *)(W + L.eps);
+  Sx.eps_band = (double *)(W + L.epsb);
+  Sx.omega = (double *)(W + L.omega);
+  Sx.eta = eta;
+  Sx.alpha = o.alpha_pv;
+  Sx.tol_int = tol * o.tol_safety;
+  int32_t *d_active = (int32_t *)(W + L.l_active);
+  int32_t *d_fill = (int32_t *)(W + L.l_fill);
+  int32_t *d_fillpairs = (int32_t *)(W + L.l_fillpairs);
+  int32_t *d_final = (int32_t *)(W + L.l_final);
+  int32_t *d_dvm = (int32_t *)(W + L.dvm);
+  double2 *Y = (double2 *)(W + L.Y);
+  double2 *C = (double2 *)(W + L.C);
+  double2 *T = (double2 *)(W + L.T);
+  double2 *ycoef = (double2 *)(W + L.ycoef);
+  double2 *cp = (double2 *)(W + L.cp);
+  double2 *X = (double2 *)(W + L.X);
+  double2 *AX = (double2 *)(W + L.AX);
+  int *d_bad = (int *)(W + L.bad);
+
+  // pinned staging: status[S] | active[S] | fill[S] | fillpairs[S] | final[S] | bad
+  if ((st = ensure_pinned(ctx, sizeof(int32_t) * (5ul * S + 16))) != SGW_OK) return st;
+  int32_t *p_status = (int32_t *)ctx->pinned;
+  int32_t *p_active = p_status + S;
+  int32_t *p_fill = p_active + S;
+  int32_t *p_fillpairs = p_fill + S;
+  int32_t *p_final = p_fillpairs + S;
+  int32_t *p_bad = p_final + S;
+
+  // parameters
+  SGW_HIP(hipMemcpyAsync((void *)Sx.omega, omega, sizeof(double) * n_omega, hipMemcpyHostToDevice, ctx->stream));
+  SGW_HIP(hipMemcpyAsync((void *)Sx.eps_band, eps_v, sizeof(double) * n_band, hipMemcpyHostToDevice, ctx->stream));
+  SGW_HIP(hipMemcpyAsync(d_dvm, dv_miller, sizeof(int32_t) * 3 * n_pert, hipMemcpyHostToDevice, ctx->stream));
+  SGW_HIP(hipMemsetAsync(d_bad, 0, sizeof(int), ctx->stream));
+  if ((st = permute(ctx, npw, n_occ, (const double2 *)psi_occ_kq, npw, (double2 *)Sx.psi, npw, h_kq->d_i2u, 0)) !=
+      SGW_OK)
+    return st;
+
+  // work queue: the highest bands (slowest to converge) first
+  std::vector<int> queue(n_pairs);
+  std::iota(queue.begin(), queue.end(), 0);
+  std::stable_sort(queue.begin(), queue.end(), [&](int a, int b) { return eps_v[a / n_pert] > eps_v[b / n_pert]; });
+  size_t next = 0;
+  std::vector<int> slot_pair(S, -1), free_slots, active, done;
+  for (int s = S - 1; s >= 0; --s) free_slots.push_back(s);
+  const VecSrc cur{Sx.basis, npw, d_active, Sx.kcur, Sx.slot_stride};
+  const VecSrc xsrc = contiguous(X, npw);
+  size_t finalized = 0;
+  double ksum = 0;
+  long kcount = 0;
+  std::vector<int32_t> kc_host(S);
+
+  auto finalize = [&](std::vector<int> &list) -> sgw_status {
+    for (size_t off = 0; off < list.size(); off += F) {
+      const int nf = (int)std::min<size_t>(F, list.size() - off);
+      double kavg = 0;
+      for (int f = 0; f < nf; ++f) kavg += kc_host[list[off + f]];
+      kavg /= nf;
+      std::memcpy(p_final, list.data() + off, sizeof(int32_t) * nf);
+      SGW_HIP(hipMemcpyAsync(d_final, p_final, sizeof(int32_t) * nf, hipMemcpyHostToDevice, ctx->stream));
+      sgw_status s2;
+      if ((s2 = tridiag(ctx, Sx, d_final, nf, ycoef, cp)) != SGW_OK) return s2;
+      if ((s2 = combine(ctx, Sx, d_final, nf, ycoef, X, kavg)) != SGW_OK) return s2;
+      const int nv = nf * n_omega;
+      if ((s2 = proj_dot(ctx, npw, n_occ, Sx.psi, nv, xsrc, C)) != SGW_OK) return s2;
+      if ((s2 = hx_batch(ctx, h_kq, nv, xsrc, AX, npw, T)) != SGW_OK) return s2;
+      if ((s2 = residual(ctx, Sx, d_final, nf, X, AX, C, h_kq->d_i2u, (double2 *)dpsi, info, tol, d_bad)) != SGW_OK)
+        return s2;
+      // the pinned final list is reused by the next chunk: wait for the upload
+      if ((s2 = sync(ctx)) != SGW_OK) return s2;
+    }
+    for (int s : list) {
+      slot_pair[s] = -1;
+      free_slots.push_back(s);
+    }
+    finalized += list.size();
+    list.clear();
+    return SGW_OK;
+  };
+
+  while (finalized < (size_t)n_pairs) {
+    // refill free slots
+    int nfill = 0;
+    while (!free_slots.empty() && next < queue.size()) {
+      const int s = free_slots.back();
+      free_slots.pop_back();
+      slot_pair[s] = queue[next++];
+      p_fill[nfill] = s;
+      p_fillpairs[nfill] = slot_pair[s];
+      ++nfill;
+    }
+    if (nfill > 0) {
+      SGW_HIP(hipMemcpyAsync(d_fill, p_fill, sizeof(int32_t) * nfill, hipMemcpyHostToDevice, ctx->stream));
+      SGW_HIP(hipMemcpyAsync(d_fillpairs, p_fillpairs, sizeof(int32_t) * nfill, hipMemcpyHostToDevice, ctx->stream));
+      if ((st = rhs_source(ctx, h_kq, h_k, nfill, d_fillpairs, n_pert, d_dvm, (const double2 *)psi_v, h_k->n_pw, Y,
+                           npw)) != SGW_OK)
+        return st;
+      if ((st = proj_dot(ctx, npw, n_occ, Sx.psi, nfill, contiguous(Y, npw), C)) != SGW_OK) return st;
+      if ((st = slot_init(ctx, Sx, nfill, Y, C, d_fill, d_fillpairs)) != SGW_OK) return st;
+      for (int i = 0; i < nfill; ++i) active.push_back(p_fill[i]);
+    }
+    if (!active.empty()) {
+      std::memcpy(p_active, active.data(), sizeof(int32_t) * active.size());
+      const int na = (int)active.size();
+      SGW_HIP(hipMemcpyAsync(d_active, p_active, sizeof(int32_t) * na, hipMemcpyHostToDevice, ctx->stream));
+      for (int step = 0; step < L.M; ++step) {
+        if ((st = proj_dot(ctx, npw, n_occ, Sx.psi, na, cur, C)) != SGW_OK) return st;
+        if ((st = hx_batch(ctx, h_kq, na, cur, Y, npw, T)) != SGW_OK) return st;
+        if ((st = lanczos_step(ctx, Sx, na, d_active, Y, C)) != SGW_OK) return st;
+      }
+    }
+    // poll
+    SGW_HIP(hipMemcpyAsync(p_status, Sx.status, sizeof(int32_t) * S, hipMemcpyDeviceToHost, ctx->stream));
+    SGW_HIP(hipMemcpyAsync(kc_host.data(), Sx.kcur, sizeof(int32_t) * S, hipMemcpyDeviceToHost, ctx->stream));
+    if ((st = sync(ctx)) != SGW_OK) return st;
+    std::vector<int> still;
+    for (int s : active) {
+      if (p_status[s] == SLOT_RUNNING) still.push_back(s);
+      else {
+        done.push_back(s);
+        ksum += kc_host[s];
+        ++kcount;
+      }
+    }
+    active.swap(still);
+    const bool refill_waiting = next < queue.size();
+    if (!done.empty() && (active.empty() || (int)done.size() >= F || (refill_waiting && (int)done.size() * 4 >= F))) {
+      if ((st = finalize(done)) != SGW_OK) return st;
+    }
+  }
+  SGW_HIP(hipMemcpyAsync(p_bad, d_bad, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+  if ((st = sync(ctx)) != SGW_OK) return st;
+  return *p_bad > 0 ? SGW_NOT_CONVERGED : SGW_OK;
+}

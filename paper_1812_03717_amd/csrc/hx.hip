@@ -1,0 +1,247 @@
+// H.x in plane waves (Sec. 2.1): kinetic diagonal plus the local potential
+// applied on the real-space grid through a pruned 3D FFT, batched over vectors.
+//
+// The plane-wave sphere occupies, along grid axis 2, a set of "sticks" (one per
+// (m0, m1) column).  The transform runs in three kernels:
+//   sticks_inv : per stick, scatter the coefficients into a length-N2 column and
+//                inverse-FFT along axis 2; write T[vec][i2][stick]
+//   planes     : per (vec, i2) plane, place the stick values, inverse-FFT along
+//                axis 1 (only the rows that hold sticks) and axis 0, multiply by
+//                V(r), forward-FFT along axis 0 and axis 1, gather the sticks
+//   sticks_fwd : per stick, forward-FFT along axis 2, gather the sphere, scale by
+//                1/N, add the kinetic term
+// Only the stick data (N2 * n_stick values per vector) travels through HBM; a
+// full plane lives in LDS.
+#include "fft_lds.h"
+#include "sgw_internal.h"
+
+namespace sgw {
+namespace {
+
+struct StrideBase {
+  int ld;
+  __device__ __forceinline__ int operator()(int t) const { return t * ld; }
+};
+struct UnitBase {
+  __device__ __forceinline__ int operator()(int t) const { return t; }
+};
+// rows of a plane that hold sticks: row t -> i0 = (m0_lo + t) mod N0
+struct RowBase {
+  int m0_lo, n0, ld;
+  __device__ __forceinline__ int operator()(int t) const {
+    int i0 = m0_lo + t;
+    i0 += (i0 < 0) ? n0 : 0;
+    return i0 * ld;
+  }
+};
+
+template <int N2> constexpr int sticks_per_block() { return N2 <= 32 ? 64 : 32; }
+constexpr int kStickThreads = 256;
+
+template <int N2>
+__global__ __launch_bounds__(kStickThreads) void k_sticks_inv(VecSrc x, double2 *__restrict__ T, int n_stick,
+                                                              const int32_t *__restrict__ stick_off,
+                                                              const int32_t *__restrict__ pw_stick,
+                                                              const int32_t *__restrict__ pw_z,
+                                                              const double2 *__restrict__ twg, int groups) {
+  constexpr int SG = sticks_per_block<N2>();
+  constexpr int LDC = N2 + 1;
+  __shared__ double2 col[SG * LDC];
+  __shared__ double2 tw[N2];
+  const int tid = threadIdx.x;
+  const int vec = blockIdx.x / groups;
+  const int s0 = (blockIdx.x - vec * groups) * SG;
+  const int ns = min(SG, n_stick - s0);
+  const double2 *xv = x.ptr(vec);
+  for (int i = tid; i < SG * LDC; i += kStickThreads) col[i] = make_double2(0.0, 0.0);
+  for (int i = tid; i < N2; i += kStickThreads) tw[i] = twg[i];
+  __syncthreads();
+  const int g0 = stick_off[s0], g1 = stick_off[s0 + ns];
+  for (int g = g0 + tid; g < g1; g += kStickThreads) col[(pw_stick[g] - s0) * LDC + pw_z[g]] = xv[g];
+  __syncthreads();
+  lds_fft<N2, +1, SG, kStickThreads, false>(col, ns, StrideBase{LDC}, 1, tw, tid);
+  double2 *Tv = T + (long)vec * N2 * n_stick + s0;
+  for (int i = tid; i < ns * N2; i += kStickThreads) {
+    const int z = i / ns, s = i - z * ns;
+    Tv[(long)z * n_stick + s] = col[s * LDC + z];
+  }
+}
+
+template <int N2>
+__global__ __launch_bounds__(kStickThreads) void k_sticks_fwd(const double2 *__restrict__ T, int n_stick,
+                                                              const int32_t *__restrict__ stick_off,
+                                                              const int32_t *__restrict__ pw_stick,
+                                                              const int32_t *__restrict__ pw_z,
+                                                              const double2 *__restrict__ twg, int groups,
+                                                              VecSrc x, const double *__restrict__ kin,
+                                                              double2 *__restrict__ y, long ldy, double scale) {
+  constexpr int SG = sticks_per_block<N2>();
+  constexpr int LDC = N2 + 1;
+  __shared__ double2 col[SG * LDC];
+  __shared__ double2 tw[N2];
+  const int tid = threadIdx.x;
+  const int vec = blockIdx.x / groups;
+  const int s0 = (blockIdx.x - vec * groups) * SG;
+  const int ns = min(SG, n_stick - s0);
+  for (int i = tid; i < N2; i += kStickThreads) tw[i] = twg[i];
+  const double2 *Tv = T + (long)vec * N2 * n_stick + s0;
+  for (int i = tid; i < ns * N2; i += kStickThreads) {
+    const int z = i / ns, s = i - z * ns;
+    col[s * LDC + z] = Tv[(long)z * n_stick + s];
+  }
+  __syncthreads();
+  lds_fft<N2, -1, SG, kStickThreads, false>(col, ns, StrideBase{LDC}, 1, tw, tid);
+  const double2 *xv = x.ptr(vec);
+  double2 *yv = y + (long)vec * ldy;
+  const int g0 = stick_off[s0], g1 = stick_off[s0 + ns];
+  for (int g = g0 + tid; g < g1; g += kStickThreads) {
+    const double2 c = col[(pw_stick[g] - s0) * LDC + pw_z[g]];
+    const double2 xg = xv[g];
+    const double t = kin[g];
+    yv[g] = make_double2(fma(c.x, scale, t * xg.x), fma(c.y, scale, t * xg.y));
+  }
+}
+
+template <int N0, int N1> constexpr int plane_threads() { return N0 * N1 <= 48 * 48 ? 256 : 512; }
+
+template <int N0, int N1>
+__global__ __launch_bounds__((plane_threads<N0, N1>())) void k_planes(double2 *__restrict__ T, int n2, int n_stick,
+                                                                   const int32_t *__restrict__ stick_xy,
+                                                                   int m0_lo, int n_row,
+                                                                   const double *__restrict__ vt,
+                                                                   const double2 *__restrict__ tw0g,
+                                                                   const double2 *__restrict__ tw1g) {
+  constexpr int NT = plane_threads<N0, N1>();
+  constexpr int LD = N1 + 1;
+  __shared__ double2 plane[N0 * LD];
+  __shared__ double2 tw0[N0];
+  __shared__ double2 tw1[N1];
+  const int tid = threadIdx.x;
+  const int vec = blockIdx.x / n2;
+  const int z = blockIdx.x - vec * n2;
+  double2 *Tz = T + ((long)vec * n2 + z) * n_stick;
+  for (int i = tid; i < N0 * LD; i += NT) plane[i] = make_double2(0.0, 0.0);
+  for (int i = tid; i < N0; i += NT) tw0[i] = tw0g[i];
+  for (int i = tid; i < N1; i += NT) tw1[i] = tw1g[i];
+  __syncthreads();
+  for (int s = tid; s < n_stick; s += NT) {
+    const int xy = stick_xy[s];
+    plane[(xy >> 16) * LD + (xy & 0xffff)] = Tz[s];
+  }
+  __syncthreads();
+  lds_fft<N1, +1, N0, NT, false>(plane, n_row, RowBase{m0_lo, N0, LD}, 1, tw1, tid);
+  lds_fft<N0, +1, N1, NT, true>(plane, N1, UnitBase{}, LD, tw0, tid);
+  const double *vz = vt + (long)z * N0 * N1;
+  for (int i = tid; i < N0 * N1; i += NT) {
+    const int i0 = i / N1, i1 = i - i0 * N1;
+    plane[i0 * LD + i1] = c_scale(plane[i0 * LD + i1], vz[i]);
+  }
+  __syncthreads();
+  lds_fft<N0, -1, N1, NT, true>(plane, N1, UnitBase{}, LD, tw0, tid);
+  lds_fft<N1, -1, N0, NT, false>(plane, n_row, RowBase{m0_lo, N0, LD}, 1, tw1, tid);
+  for (int s = tid; s < n_stick; s += NT) {
+    const int xy = stick_xy[s];
+    Tz[s] = plane[(xy >> 16) * LD + (xy & 0xffff)];
+  }
+}
+
+template <int N2>
+sgw_status launch_sticks(sgw_ctx *ctx, const sgw_ham *h, int n_vec, VecSrc x, double2 *y, long ldy,
+                         double2 *tbuf, bool inverse) {
+  constexpr int SG = sticks_per_block<N2>();
+  const int groups = (h->n_stick + SG - 1) / SG;
+  const long blocks = (long)groups * n_vec;
+  const double2 *tw = h->d_tw + h->tw_off[2];
+  const double n2 = N2, nst = h->n_stick, npw = h->n_pw;
+  PendingTiming tm;
+  if (inverse) {
+    timing_begin(ctx, K_STICKS_INV, n_vec * (npw * 16.0 + n2 * nst * 16.0), 0.0, &tm);
+    hipLaunchKernelGGL(k_sticks_inv<N2>, dim3(blocks), dim3(kStickThreads), 0, ctx->stream, x, tbuf,
+                       h->n_stick, h->d_stick_off, h->d_pw_stick, h->d_pw_z, tw, groups);
+    timing_end(ctx, &tm);
+  } else {
+    const double scale = 1.0 / ((double)h->n[0] * h->n[1] * h->n[2]);
+    timing_begin(ctx, K_STICKS_FWD, n_vec * (npw * 32.0 + n2 * nst * 16.0), 0.0, &tm);
+    hipLaunchKernelGGL(k_sticks_fwd<N2>, dim3(blocks), dim3(kStickThreads), 0, ctx->stream, tbuf, h->n_stick,
+                       h->d_stick_off, h->d_pw_stick, h->d_pw_z, tw, groups, x, h->d_kin, y, ldy, scale);
+    timing_end(ctx, &tm);
+  }
+  SGW_HIP(hipGetLastError());
+  return SGW_OK;
+}
+
+template <int N0, int N1>
+sgw_status launch_planes(sgw_ctx *ctx, const sgw_ham *h, int n_vec, double2 *tbuf) {
+  const long blocks = (long)n_vec * h->n[2];
+  PendingTiming tm;
+  // algorithmic bytes: stick values in and out; the potential is read once per launch
+  const double bytes = (double)n_vec * h->n[2] * h->n_stick * 32.0 + (double)N0 * N1 * h->n[2] * 8.0;
+  timing_begin(ctx, K_PLANES, bytes, 0.0, &tm);
+  hipLaunchKernelGGL((k_planes<N0, N1>), dim3(blocks), dim3(plane_threads<N0, N1>()), 0, ctx->stream, tbuf,
+                     h->n[2], h->n_stick, h->d_stick_xy, h->m0_lo, h->n_row, h->d_vt, h->d_tw + h->tw_off[0],
+                     h->d_tw + h->tw_off[1]);
+  timing_end(ctx, &tm);
+  SGW_HIP(hipGetLastError());
+  return SGW_OK;
+}
+
+#define SGW_GRID_LIST(X) X(16) X(24) X(32) X(48) X(64) X(72) X(96)
+
+sgw_status dispatch_sticks(sgw_ctx *ctx, const sgw_ham *h, int n_vec, VecSrc x, double2 *y, long ldy,
+                           double2 *tbuf, bool inverse) {
+  switch (h->n[2]) {
+#define SGW_CASE(N) \
+  case N:           \
+    return launch_sticks<N>(ctx, h, n_vec, x, y, ldy, tbuf, inverse);
+    SGW_GRID_LIST(SGW_CASE)
+#undef SGW_CASE
+  }
+  return fail(SGW_ERR_UNSUPPORTED, "grid size along axis 2 not supported");
+}
+
+template <int N0>
+sgw_status dispatch_planes_n1(sgw_ctx *ctx, const sgw_ham *h, int n_vec, double2 *tbuf) {
+  switch (h->n[1]) {
+#define SGW_CASE(N) \
+  case N:           \
+    return launch_planes<N0, N>(ctx, h, n_vec, tbuf);
+    SGW_GRID_LIST(SGW_CASE)
+#undef SGW_CASE
+  }
+  return fail(SGW_ERR_UNSUPPORTED, "grid size along axis 1 not supported");
+}
+
+sgw_status dispatch_planes(sgw_ctx *ctx, const sgw_ham *h, int n_vec, double2 *tbuf) {
+  switch (h->n[0]) {
+#define SGW_CASE(N) \
+  case N:           \
+    return dispatch_planes_n1<N>(ctx, h, n_vec, tbuf);
+    SGW_GRID_LIST(SGW_CASE)
+#undef SGW_CASE
+  }
+  return fail(SGW_ERR_UNSUPPORTED, "grid size along axis 0 not supported");
+}
+
+}  // namespace
+
+bool hx_grid_supported(int n) {
+  switch (n) {
+#define SGW_CASE(N) \
+  case N:           \
+    return true;
+    SGW_GRID_LIST(SGW_CASE)
+#undef SGW_CASE
+  }
+  return false;
+}
+
+sgw_status hx_batch(sgw_ctx *ctx, const sgw_ham *h, int n_vec, VecSrc x, double2 *y, long ldy, double2 *tbuf) {
+  if (n_vec <= 0) return SGW_OK;
+  sgw_status st = dispatch_sticks(ctx, h, n_vec, x, nullptr, 0, tbuf, true);
+  if (st != SGW_OK) return st;
+  st = dispatch_planes(ctx, h, n_vec, tbuf);
+  if (st != SGW_OK) return st;
+  return dispatch_sticks(ctx, h, n_vec, x, y, ldy, tbuf, false);
+}
+
+}  // namespace sgw

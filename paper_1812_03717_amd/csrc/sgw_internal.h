@@ -1,0 +1,146 @@
+// Internal declarations shared by the translation units of libsgw.so.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/sgw.h"
+
+namespace sgw {
+
+// ---------------------------------------------------------------------------
+// error reporting
+// ---------------------------------------------------------------------------
+void set_error(const std::string &msg);
+sgw_status fail(sgw_status code, const std::string &msg);
+
+#define SGW_HIP(call)                                                                   \
+  do {                                                                                  \
+    hipError_t e_ = (call);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return ::sgw::fail(SGW_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+#define SGW_CHECK(cond, msg)                                               \
+  do {                                                                     \
+    if (!(cond)) return ::sgw::fail(SGW_ERR_INVALID_ARG, (msg));           \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// kernel identifiers for timing statistics
+// ---------------------------------------------------------------------------
+enum KernelId {
+  K_STICKS_INV = 0,
+  K_PLANES,
+  K_STICKS_FWD,
+  K_PROJ_DOT,
+  K_PROJ_APPLY,
+  K_RHS,
+  K_INIT,
+  K_LANCZOS,
+  K_TRIDIAG,
+  K_COMBINE,
+  K_RESIDUAL,
+  K_PERMUTE,
+  K_COUNT
+};
+const char *kernel_name(int id);
+
+struct KernelStat {
+  int64_t launches = 0;
+  double ms = 0, bytes = 0, flops = 0;
+};
+
+struct PendingTiming {
+  int kid;
+  hipEvent_t start, stop;
+  double bytes, flops;
+};
+
+}  // namespace sgw
+
+struct sgw_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  unsigned profile_mask = 0;        // bit k: time launches of kernel k
+  sgw::KernelStat stats[sgw::K_COUNT];
+  std::vector<sgw::PendingTiming> pending;
+  std::vector<hipEvent_t> event_pool;
+  // pinned host staging (status polls, small uploads)
+  void *pinned = nullptr;
+  size_t pinned_bytes = 0;
+};
+
+// Device-resident index maps of one Hamiltonian.  "internal" order is
+// stick-major: plane waves grouped by (m0, m1) column along axis 2.
+struct sgw_ham {
+  sgw_ctx *ctx = nullptr;           // creating context (not used after it is destroyed)
+  int device = 0;
+  int n[3] = {0, 0, 0};
+  int n_pw = 0;
+  int n_stick = 0;
+  int m0_lo = 0, n_row = 0;         // rows (axis 0) holding sticks: m0 in [m0_lo, m0_lo + n_row)
+  double kvec[3];
+  double recip[3][3];
+  std::vector<int32_t> miller;      // host copy, caller order
+  int box_lo[3], box_dim[3];        // Miller lookup box (caller indices)
+  // device arrays
+  int32_t *d_i2u = nullptr;         // [n_pw] internal -> caller index
+  int32_t *d_u2i = nullptr;         // [n_pw] caller -> internal index
+  int32_t *d_stick_off = nullptr;   // [n_stick + 1]
+  int32_t *d_stick_xy = nullptr;    // [n_stick] i0 * N1 + i1
+  int32_t *d_pw_stick = nullptr;    // [n_pw] internal -> stick
+  int32_t *d_pw_z = nullptr;        // [n_pw] internal -> i2
+  int32_t *d_miller_int = nullptr;  // [n_pw][3] internal order
+  double *d_kin = nullptr;          // [n_pw] internal order, 0.5|k+G|^2
+  double *d_vt = nullptr;           // [N2][N0][N1] potential, plane-major
+  int32_t *d_box = nullptr;         // [box volume] -> caller index or -1
+  double2 *d_tw = nullptr;          // twiddles: 3 tables of N_d entries exp(-2 pi i t / N_d)
+  int tw_off[3];
+};
+
+namespace sgw {
+
+// Describes where vector a of a batch lives: base + a*ld, or, with a slot list,
+// base + list[a]*slot_stride + kidx[list[a]]*ld.
+struct VecSrc {
+  const double2 *base;
+  long ld;
+  const int32_t *list;
+  const int32_t *kidx;
+  long slot_stride;
+  __host__ __device__ inline const double2 *ptr(int a) const {
+    if (!list) return base + (long)a * ld;
+    int s = list[a];
+    return base + (long)s * slot_stride + (long)kidx[s] * ld;
+  }
+};
+
+inline VecSrc contiguous(const double2 *p, long ld) { return VecSrc{p, ld, nullptr, nullptr, 0}; }
+
+// Timing helpers (no-ops when profiling is off).
+void timing_begin(sgw_ctx *ctx, int kid, double bytes, double flops, PendingTiming *out);
+void timing_end(sgw_ctx *ctx, PendingTiming *t);
+sgw_status timing_collect(sgw_ctx *ctx);
+
+// H.x over a batch (internal order): y = T.x + F V F^-1 x.  `tbuf` holds
+// n_vec * N2 * n_stick complex entries.
+sgw_status hx_batch(sgw_ctx *ctx, const sgw_ham *h, int n_vec, VecSrc x, double2 *y, long ldy,
+                    double2 *tbuf);
+bool hx_grid_supported(int n);
+
+// Projector pieces (internal order).
+// c[a][i] = sum_g conj(psi[i][g]) x_a[g]
+sgw_status proj_dot(sgw_ctx *ctx, int n_pw, int n_occ, const double2 *psi, int n_vec, VecSrc x,
+                    double2 *c);
+// mode 0: y_a = x_a - psi^T c_a ; mode 1: y_a += alpha psi^T c_a
+sgw_status proj_apply(sgw_ctx *ctx, int n_pw, int n_occ, const double2 *psi, int n_vec, VecSrc x,
+                      const double2 *c, double2 *y, long ldy, double alpha, int mode);
+// out[a][g] = in[a][perm[g]] (gather) or out[a][perm[g]] = in[a][g] (scatter)
+sgw_status permute(sgw_ctx *ctx, int n_pw, int n_vec, const double2 *in, long ldin, double2 *out,
+                   long ldout, const int32_t *perm, int scatter, double scale = 1.0);
+
+}  // namespace sgw

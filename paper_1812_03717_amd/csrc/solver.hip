@@ -1,0 +1,626 @@
+// Kernels of the multishift Sternheimer solver (Sec. 2.2-2.3).
+//
+// One (band v, perturbation p) pair owns a "slot": its right-hand side b, its
+// Lanczos basis v_0..v_K of the seed operator A0 = H - eps_v + alpha P_occ,
+// the tridiagonal coefficients, and per-shift recurrence state.  Every shift
+// z_j = omega_j + i eta shares the basis: the FOM solution of the shifted
+// system is x_j = V_K (T_K - z_j)^-1 ||b|| e_0, and its residual norm is
+// ||b|| prod_i beta_{i+1} / |rho_i(z_j)|, where rho_i are the pivots of the
+// LU factorisation of T_K - z_j.  The basis is kept in HBM, so no per-shift
+// vector is updated during the iteration; x_j is formed once at the end.
+#include "fft_lds.h"
+#include "sgw_internal.h"
+#include "solver_state.h"
+
+namespace sgw {
+namespace {
+
+// deterministic block sum: wave butterfly (shuffle-xor) then a fixed-order
+// sum over waves.  Every thread returns the total.
+template <int NT>
+__device__ __forceinline__ double block_sum(double v, double *sh) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) sh[wid] = v;
+  __syncthreads();
+  double r = 0.0;
+#pragma unroll
+  for (int w = 0; w < NT / 64; ++w) r += sh[w];
+  __syncthreads();
+  return r;
+}
+
+// M simultaneous block sums; results in out[0..M) for every thread
+template <int NT, int M>
+__device__ __forceinline__ void block_sum_n(double *v, double *sh, double *out) {
+#pragma unroll
+  for (int m = 0; m < M; ++m) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v[m] += __shfl_xor(v[m], off, 64);
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) {
+#pragma unroll
+    for (int m = 0; m < M; ++m) sh[wid * M + m] = v[m];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int m = 0; m < M; ++m) {
+    double r = 0.0;
+#pragma unroll
+    for (int w = 0; w < NT / 64; ++w) r += sh[w * M + m];
+    out[m] = r;
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// permutation between the caller's order and the internal order
+// ---------------------------------------------------------------------------
+__global__ void k_permute(int npw, int n_vec, const double2 *__restrict__ in, long ldin, double2 *__restrict__ out,
+                          long ldout, const int32_t *__restrict__ perm, int scatter, double scale, int tiles) {
+  const int a = blockIdx.x / tiles;
+  const int g = (blockIdx.x - a * tiles) * blockDim.x + threadIdx.x;
+  if (g >= npw) return;
+  if (scatter) out[(long)a * ldout + perm[g]] = c_scale(in[(long)a * ldin + g], scale);
+  else out[(long)a * ldout + g] = c_scale(in[(long)a * ldin + perm[g]], scale);
+}
+
+// ---------------------------------------------------------------------------
+// c[a][i] = sum_g conj(psi[i][g]) x_a[g]   (occupied-state overlaps, Eqs. 7-8)
+// ---------------------------------------------------------------------------
+constexpr int kDotThreads = 256;
+constexpr int kDotOcc = 8;
+
+__global__ __launch_bounds__(kDotThreads) void k_proj_dot(int npw, int n_occ, const double2 *__restrict__ psi,
+                                                          VecSrc x, double2 *__restrict__ c, int oblocks) {
+  __shared__ double sh[(kDotThreads / 64) * 2 * kDotOcc];
+  const int a = blockIdx.x / oblocks;
+  const int i0 = (blockIdx.x - a * oblocks) * kDotOcc;
+  const int no = min(kDotOcc, n_occ - i0);
+  const double2 *xv = x.ptr(a);
+  double acc[2 * kDotOcc];
+#pragma unroll
+  for (int o = 0; o < 2 * kDotOcc; ++o) acc[o] = 0.0;
+  for (int g = threadIdx.x; g < npw; g += kDotThreads) {
+    const double2 xg = xv[g];
+#pragma unroll
+    for (int o = 0; o < kDotOcc; ++o) {
+      if (o < no) {
+        const double2 p = psi[(long)(i0 + o) * npw + g];
+        acc[2 * o] = fma(p.x, xg.x, fma(p.y, xg.y, acc[2 * o]));
+        acc[2 * o + 1] = fma(p.x, xg.y, fma(-p.y, xg.x, acc[2 * o + 1]));
+      }
+    }
+  }
+  double tot[2 * kDotOcc];
+  block_sum_n<kDotThreads, 2 * kDotOcc>(acc, sh, tot);
+  if (threadIdx.x < no) {
+    const int o = threadIdx.x;
+    c[(long)a * n_occ + i0 + o] = make_double2(tot[2 * o], tot[2 * o + 1]);
+  }
+}
+
+// mode 0: y = x - psi^T c ; mode 1: y += alpha psi^T c
+__global__ void k_proj_apply(int npw, int n_occ, const double2 *__restrict__ psi, VecSrc x,
+                             const double2 *__restrict__ c, double2 *__restrict__ y, long ldy, double alpha,
+                             int mode, int tiles) {
+  extern __shared__ double2 cs[];
+  const int a = blockIdx.x / tiles;
+  const int g = (blockIdx.x - a * tiles) * blockDim.x + threadIdx.x;
+  for (int i = threadIdx.x; i < n_occ; i += blockDim.x) cs[i] = c[(long)a * n_occ + i];
+  __syncthreads();
+  if (g >= npw) return;
+  double2 s = make_double2(0.0, 0.0);
+  for (int i = 0; i < n_occ; ++i) s = c_add(s, c_mul(psi[(long)i * npw + g], cs[i]));
+  double2 *yp = y + (long)a * ldy + g;
+  if (mode == 0) *yp = c_sub(x.ptr(a)[g], s);
+  else *yp = c_add(*yp, c_scale(s, alpha));
+}
+
+// ---------------------------------------------------------------------------
+// right-hand side source (Eq. 8): s(G'') = psi_v(G'' - G_p), zero outside the k sphere
+// ---------------------------------------------------------------------------
+__global__ void k_rhs_source(int npw, const int32_t *__restrict__ miller_int, const int32_t *__restrict__ box,
+                             int3 box_lo, int3 box_dim, const int32_t *__restrict__ pairs, int n_pert,
+                             const int32_t *__restrict__ dvm, const double2 *__restrict__ psi_v, long ld_psi,
+                             double2 *__restrict__ s, long lds, int tiles) {
+  const int a = blockIdx.x / tiles;
+  const int g = (blockIdx.x - a * tiles) * blockDim.x + threadIdx.x;
+  if (g >= npw) return;
+  const int pair = pairs[a];
+  const int v = pair / n_pert, p = pair - v * n_pert;
+  const int m0 = miller_int[3 * g] - dvm[3 * p] - box_lo.x;
+  const int m1 = miller_int[3 * g + 1] - dvm[3 * p + 1] - box_lo.y;
+  const int m2 = miller_int[3 * g + 2] - dvm[3 * p + 2] - box_lo.z;
+  double2 val = make_double2(0.0, 0.0);
+  if (m0 >= 0 && m0 < box_dim.x && m1 >= 0 && m1 < box_dim.y && m2 >= 0 && m2 < box_dim.z) {
+    const int idx = box[(m0 * box_dim.y + m1) * box_dim.z + m2];
+    if (idx >= 0) val = psi_v[(long)v * ld_psi + idx];
+  }
+  s[(long)a * lds + g] = val;
+}
+
+// ---------------------------------------------------------------------------
+// slot initialisation: b = -(s - psi^T c), v_0 = b / ||b||
+// ---------------------------------------------------------------------------
+constexpr int kRowThreads = 256;
+
+__global__ __launch_bounds__(kRowThreads) void k_init(SolverState S, const double2 *__restrict__ src,
+                                                      const double2 *__restrict__ c,
+                                                      const int32_t *__restrict__ fill_slots,
+                                                      const int32_t *__restrict__ fill_pairs) {
+  __shared__ double sh[kRowThreads / 64];
+  extern __shared__ double2 cs[];
+  const int a = blockIdx.x;
+  const int slot = fill_slots[a], pair = fill_pairs[a];
+  for (int i = threadIdx.x; i < S.n_occ; i += kRowThreads) cs[i] = c[(long)a * S.n_occ + i];
+  __syncthreads();
+  const double2 *sv = src + (long)a * S.npw;
+  double2 *bv = S.bvec + (long)slot * S.npw;
+  double acc = 0.0, accs = 0.0;
+  for (int g = threadIdx.x; g < S.npw; g += kRowThreads) {
+    double2 pc = make_double2(0.0, 0.0);
+    for (int i = 0; i < S.n_occ; ++i) pc = c_add(pc, c_mul(S.psi[(long)i * S.npw + g], cs[i]));
+    const double2 sg = sv[g];
+    const double2 b = c_sub(pc, sg);
+    bv[g] = b;
+    acc += b.x * b.x + b.y * b.y;
+    accs += sg.x * sg.x + sg.y * sg.y;
+  }
+  double nb = sqrt(block_sum<kRowThreads>(acc, sh));
+  const double ns = sqrt(block_sum<kRowThreads>(accs, sh));
+  // a source inside the occupied space leaves only cancellation noise: the
+  // right-hand side is zero to working precision
+  const bool zero = !(nb > kZeroRhsRel * ns);
+  if (zero && isfinite(nb)) nb = 0.0;
+  double2 *v0 = S.basis + (long)slot * S.slot_stride;
+  const double inv = nb > 0.0 ? 1.0 / nb : 0.0;
+  for (int g = threadIdx.x; g < S.npw; g += kRowThreads) {
+    if (nb == 0.0) bv[g] = make_double2(0.0, 0.0);
+    v0[g] = c_scale(bv[g], inv);
+  }
+  for (int j = threadIdx.x; j < S.n_omega; j += kRowThreads) {
+    S.res[(long)slot * S.n_omega + j] = 1.0;
+    S.rho[(long)slot * S.n_omega + j] = make_double2(1.0, 0.0);
+  }
+  if (threadIdx.x == 0) {
+    const int v = pair / S.n_pert;
+    S.pair[slot] = pair;
+    S.kcur[slot] = 0;
+    S.eps[slot] = S.eps_band[v];
+    S.beta[(long)slot * (S.kmax + 1)] = nb;
+    int st = SLOT_RUNNING;
+    if (!isfinite(nb)) st = SLOT_NONFINITE;
+    else if (nb == 0.0) st = SLOT_ZERO_RHS;
+    S.status[slot] = st;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// one Lanczos step of the seed operator plus the shift recurrences
+//   w = A0 v_k - beta_k v_{k-1};  a_k = <v_k, w>;  w -= a_k v_k;  beta_{k+1} = ||w||
+//   A0 v_k = (H v_k) - eps_v v_k + alpha psi^T (psi^* v_k)
+// ---------------------------------------------------------------------------
+constexpr int kLzThreads = 512;
+
+template <int EPT>
+__global__ __launch_bounds__(kLzThreads) void k_lanczos(SolverState S, const int32_t *__restrict__ list,
+                                                        const double2 *__restrict__ Y,
+                                                        const double2 *__restrict__ C) {
+  __shared__ double sh[kLzThreads / 64];
+  __shared__ double2 cs[kMaxOcc];
+  __shared__ int all_conv;
+  const int a = blockIdx.x;
+  const int slot = list[a];
+  if (S.status[slot] != SLOT_RUNNING) return;
+  const int k = S.kcur[slot];
+  const int npw = S.npw;
+  const double2 *v = S.basis + (long)slot * S.slot_stride + (long)k * npw;
+  const double2 *vp = v - npw;
+  double2 *vn = const_cast<double2 *>(v) + npw;
+  const double2 *y = Y + (long)a * npw;
+  const double eps = S.eps[slot];
+  const double bk = k > 0 ? S.beta[(long)slot * (S.kmax + 1) + k] : 0.0;
+  for (int i = threadIdx.x; i < S.n_occ; i += kLzThreads) cs[i] = C[(long)a * S.n_occ + i];
+  if (threadIdx.x == 0) all_conv = 1;
+  __syncthreads();
+  double2 w[EPT];
+  double acc = 0.0;
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    const int g = threadIdx.x + e * kLzThreads;
+    if (g < npw) {
+      const double2 vg = v[g];
+      double2 pc = make_double2(0.0, 0.0);
+      for (int i = 0; i < S.n_occ; ++i) pc = c_add(pc, c_mul(S.psi[(long)i * npw + g], cs[i]));
+      double2 t = y[g];
+      t.x = fma(-eps, vg.x, fma(S.alpha, pc.x, t.x));
+      t.y = fma(-eps, vg.y, fma(S.alpha, pc.y, t.y));
+      if (k > 0) {
+        const double2 pg = vp[g];
+        t.x = fma(-bk, pg.x, t.x);
+        t.y = fma(-bk, pg.y, t.y);
+      }
+      w[e] = t;
+      acc = fma(vg.x, t.x, fma(vg.y, t.y, acc));
+    }
+  }
+  const double ak = block_sum<kLzThreads>(acc, sh);
+  double acc2 = 0.0;
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    const int g = threadIdx.x + e * kLzThreads;
+    if (g < npw) {
+      const double2 vg = v[g];
+      w[e].x = fma(-ak, vg.x, w[e].x);
+      w[e].y = fma(-ak, vg.y, w[e].y);
+      acc2 = fma(w[e].x, w[e].x, fma(w[e].y, w[e].y, acc2));
+    }
+  }
+  const double bn = sqrt(block_sum<kLzThreads>(acc2, sh));
+  const double inv = bn > 0.0 ? 1.0 / bn : 0.0;
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    const int g = threadIdx.x + e * kLzThreads;
+    if (g < npw) vn[g] = c_scale(w[e], inv);
+  }
+  // shift recurrences: rho_k(z) = a_k - z - beta_k^2 / rho_{k-1}(z); res *= beta_{k+1} / |rho_k|
+  for (int j = threadIdx.x; j < S.n_omega; j += kLzThreads) {
+    const long idx = (long)slot * S.n_omega + j;
+    double2 rho = make_double2(ak - S.omega[j], -S.eta);
+    if (k > 0) {
+      const double2 rp = S.rho[idx];
+      const double d = bk * bk / (rp.x * rp.x + rp.y * rp.y);
+      rho.x -= d * rp.x;
+      rho.y += d * rp.y;
+    }
+    S.rho[idx] = rho;
+    const double r = S.res[idx] * bn / sqrt(rho.x * rho.x + rho.y * rho.y);
+    S.res[idx] = r;
+    if (!(r <= S.tol_int)) all_conv = 0;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    S.alpha_t[(long)slot * S.kmax + k] = ak;
+    S.beta[(long)slot * (S.kmax + 1) + k + 1] = bn;
+    S.kcur[slot] = k + 1;
+    int st = SLOT_RUNNING;
+    if (!isfinite(ak) || !isfinite(bn)) st = SLOT_NONFINITE;
+    else if (bn <= 1e-14 * (fabs(ak) + bk)) st = SLOT_BREAKDOWN;
+    else if (all_conv) st = SLOT_CONVERGED;
+    else if (k + 1 >= S.kmax) st = SLOT_MAXITER;
+    S.status[slot] = st;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// FOM coefficients per shift: (T_K - z_j) y = ||b|| e_0 (Thomas algorithm; the
+// matrix is complex symmetric with a definite imaginary part, so elimination
+// without pivoting is stable)
+// ---------------------------------------------------------------------------
+__global__ void k_tridiag(SolverState S, const int32_t *__restrict__ flist, int nf, double2 *__restrict__ ycoef,
+                          double2 *__restrict__ cp) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nf * S.n_omega) return;
+  const int f = t / S.n_omega, j = t - f * S.n_omega;
+  const int slot = flist[f];
+  const int K = S.kcur[slot];
+  const int nw = S.n_omega;
+  const long base = (long)f * S.kmax * nw + j;
+  const double *al = S.alpha_t + (long)slot * S.kmax;
+  const double *be = S.beta + (long)slot * (S.kmax + 1);
+  const double zr = S.omega[j], zi = S.eta;
+  double2 dprev = make_double2(0.0, 0.0), cprev = make_double2(0.0, 0.0);
+  for (int i = 0; i < K; ++i) {
+    // den = (a_i - z) - beta_i * cp_{i-1}
+    double2 den = make_double2(al[i] - zr, -zi);
+    double2 rhs = make_double2(i == 0 ? be[0] : 0.0, 0.0);
+    if (i > 0) {
+      den.x -= be[i] * cprev.x;
+      den.y -= be[i] * cprev.y;
+      rhs.x -= be[i] * dprev.x;
+      rhs.y -= be[i] * dprev.y;
+    }
+    const double dn = 1.0 / (den.x * den.x + den.y * den.y);
+    const double2 iden = make_double2(den.x * dn, -den.y * dn);
+    const double off = (i + 1 < K) ? be[i + 1] : 0.0;
+    cprev = c_scale(iden, off);
+    dprev = c_mul(rhs, iden);
+    cp[base + (long)i * nw] = cprev;
+    ycoef[base + (long)i * nw] = dprev;
+  }
+  double2 ynext = make_double2(0.0, 0.0);
+  for (int i = K - 1; i >= 0; --i) {
+    const double2 d = ycoef[base + (long)i * nw];
+    const double2 c = cp[base + (long)i * nw];
+    const double2 yi = c_sub(d, c_mul(c, ynext));
+    ycoef[base + (long)i * nw] = yi;
+    ynext = yi;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// x_j = sum_k ycoef[k][j] v_k  for every shift j of a slot
+// ---------------------------------------------------------------------------
+constexpr int kCmbThreads = 256;
+constexpr int kCmbJ = 16;
+constexpr int kCmbK = 32;
+
+__global__ __launch_bounds__(kCmbThreads) void k_combine(SolverState S, const int32_t *__restrict__ flist,
+                                                         const double2 *__restrict__ ycoef,
+                                                         double2 *__restrict__ X, int gtiles, int jchunks) {
+  __shared__ double2 yt[kCmbK][kCmbJ];
+  int b = blockIdx.x;
+  const int jc = b % jchunks; b /= jchunks;
+  const int gt = b % gtiles;
+  const int f = b / gtiles;
+  const int slot = flist[f];
+  const int K = S.kcur[slot];
+  const int nw = S.n_omega;
+  const int j0 = jc * kCmbJ;
+  const int g = gt * kCmbThreads + threadIdx.x;
+  const double2 *V = S.basis + (long)slot * S.slot_stride;
+  double2 acc[kCmbJ];
+#pragma unroll
+  for (int q = 0; q < kCmbJ; ++q) acc[q] = make_double2(0.0, 0.0);
+  for (int k0 = 0; k0 < K; k0 += kCmbK) {
+    for (int i = threadIdx.x; i < kCmbK * kCmbJ; i += kCmbThreads) {
+      const int kk = i / kCmbJ, q = i - kk * kCmbJ;
+      const int k = k0 + kk, j = j0 + q;
+      yt[kk][q] = (k < K && j < nw) ? ycoef[((long)f * S.kmax + k) * nw + j] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    if (g < S.npw) {
+      const int kend = min(kCmbK, K - k0);
+      for (int kk = 0; kk < kend; ++kk) {
+        const double2 vk = V[(long)(k0 + kk) * S.npw + g];
+#pragma unroll
+        for (int q = 0; q < kCmbJ; ++q) {
+          const double2 yc = yt[kk][q];
+          acc[q].x = fma(yc.x, vk.x, fma(-yc.y, vk.y, acc[q].x));
+          acc[q].y = fma(yc.x, vk.y, fma(yc.y, vk.x, acc[q].y));
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (g < S.npw) {
+#pragma unroll
+    for (int q = 0; q < kCmbJ; ++q) {
+      const int j = j0 + q;
+      if (j < nw) X[((long)f * nw + j) * S.npw + g] = acc[q];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// true FP64 residual r = b - (A0 - z_j) x_j with A0 x_j applied afresh; writes
+// dpsi (caller order) and the per-solve info
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kRowThreads) void k_residual(SolverState S, const int32_t *__restrict__ flist,
+                                                          const double2 *__restrict__ X,
+                                                          const double2 *__restrict__ AX,
+                                                          const double2 *__restrict__ C,
+                                                          const int32_t *__restrict__ i2u,
+                                                          double2 *__restrict__ dpsi,
+                                                          sgw_solve_info *__restrict__ info, double tol,
+                                                          int *__restrict__ n_bad) {
+  __shared__ double sh[(kRowThreads / 64) * 3];
+  __shared__ double2 cs[kMaxOcc];
+  const int fj = blockIdx.x;
+  const int f = fj / S.n_omega, j = fj - f * S.n_omega;
+  const int slot = flist[f];
+  const int pair = S.pair[slot];
+  const int npw = S.npw;
+  const double2 *x = X + (long)fj * npw;
+  const double2 *ax = AX + (long)fj * npw;
+  const double2 *b = S.bvec + (long)slot * npw;
+  for (int i = threadIdx.x; i < S.n_occ; i += kRowThreads) cs[i] = C[(long)fj * S.n_occ + i];
+  __syncthreads();
+  const double eps = S.eps[slot];
+  const double zr = S.omega[j], zi = S.eta;
+  double2 *out = dpsi + ((long)pair * S.n_omega + j) * npw;
+  double acc[3] = {0.0, 0.0, 0.0};
+  for (int g = threadIdx.x; g < npw; g += kRowThreads) {
+    double2 pc = make_double2(0.0, 0.0);
+    for (int i = 0; i < S.n_occ; ++i) pc = c_add(pc, c_mul(S.psi[(long)i * npw + g], cs[i]));
+    const double2 xg = x[g];
+    const double2 ag = ax[g];
+    // (A0 - z) x = Hx + alpha P x - (eps + z) x
+    const double er = eps + zr;
+    double2 ox;
+    ox.x = ag.x + S.alpha * pc.x - (er * xg.x - zi * xg.y);
+    ox.y = ag.y + S.alpha * pc.y - (er * xg.y + zi * xg.x);
+    const double2 r = c_sub(b[g], ox);
+    acc[0] = fma(r.x, r.x, fma(r.y, r.y, acc[0]));
+    acc[1] = fma(xg.x, xg.x, fma(xg.y, xg.y, acc[1]));
+    out[i2u[g]] = xg;
+  }
+  double cc = 0.0;
+  for (int i = threadIdx.x; i < S.n_occ; i += kRowThreads) cc += cs[i].x * cs[i].x + cs[i].y * cs[i].y;
+  acc[2] = cc;
+  double tot[3];
+  block_sum_n<kRowThreads, 3>(acc, sh, tot);
+  if (threadIdx.x == 0) {
+    const double nb = S.beta[(long)slot * (S.kmax + 1)];
+    const double rn = sqrt(tot[0]);
+    const double relres = nb > 0.0 ? rn / nb : rn;
+    const int st = S.status[slot];
+    int flags = 0;
+    if (st == SLOT_MAXITER) flags |= SGW_FLAG_MAXITER;
+    if (st == SLOT_BREAKDOWN) flags |= SGW_FLAG_BREAKDOWN;
+    if (st == SLOT_NONFINITE || !isfinite(relres)) flags |= SGW_FLAG_NONFINITE;
+    if (st == SLOT_ZERO_RHS) flags |= SGW_FLAG_ZERO_RHS;
+    if (relres <= tol && !(flags & SGW_FLAG_NONFINITE)) flags |= SGW_FLAG_CONVERGED;
+    else atomicAdd(n_bad, 1);
+    sgw_solve_info inf;
+    inf.iters = S.kcur[slot];
+    inf.flags = flags;
+    inf.relres = relres;
+    inf.occ_leak = tot[1] > 0.0 ? sqrt(tot[2] / tot[1]) : 0.0;
+    info[(long)pair * S.n_omega + j] = inf;
+  }
+}
+
+__global__ void k_transpose_potential(const double *__restrict__ v, double *__restrict__ vt, int n0, int n1,
+                                      int n2) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long n = (long)n0 * n1 * n2;
+  if (i >= n) return;
+  // i indexes vt[i2][i0][i1]
+  const int i1 = i % n1;
+  const int i0 = (i / n1) % n0;
+  const int i2 = i / ((long)n0 * n1);
+  vt[i] = v[((long)i0 * n1 + i1) * n2 + i2];
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+sgw_status permute(sgw_ctx *ctx, int npw, int n_vec, const double2 *in, long ldin, double2 *out, long ldout,
+                   const int32_t *perm, int scatter, double scale) {
+  if (n_vec <= 0) return SGW_OK;
+  const int tiles = (npw + 255) / 256;
+  PendingTiming tm;
+  timing_begin(ctx, K_PERMUTE, n_vec * (npw * 36.0), 0.0, &tm);
+  hipLaunchKernelGGL(k_permute, dim3((long)tiles * n_vec), dim3(256), 0, ctx->stream, npw, n_vec, in, ldin, out,
+                     ldout, perm, scatter, scale, tiles);
+  timing_end(ctx, &tm);
+  SGW_HIP(hipGetLastError());
+  return SGW_OK;
+}
+
+sgw_status proj_dot(sgw_ctx *ctx, int npw, int n_occ, const double2 *psi, int n_vec, VecSrc x, double2 *c) {
+  if (n_vec <= 0 || n_occ <= 0) return SGW_OK;
+  const int ob = (n_occ + kDotOcc - 1) / kDotOcc;
+  PendingTiming tm;
+  timing_begin(ctx, K_PROJ_DOT, n_vec * (npw * 16.0) + (double)n_occ * npw * 16.0, 8.0 * n_vec * npw * n_occ,
+               &tm);
+  hipLaunchKernelGGL(k_proj_dot, dim3((long)ob * n_vec), dim3(kDotThreads), 0, ctx->stream, npw, n_occ, psi, x, c,
+                     ob);
+  timing_end(ctx, &tm);
+  SGW_HIP(hipGetLastError());
+  return SGW_OK;
+}
+
+sgw_status proj_apply(sgw_ctx *ctx, int npw, int n_occ, const double2 *psi, int n_vec, VecSrc x, const double2 *c,
+                      double2 *y, long ldy, double alpha, int mode) {
+  if (n_vec <= 0) return SGW_OK;
+  const int tiles = (npw + 255) / 256;
+  PendingTiming tm;
+  timing_begin(ctx, K_PROJ_APPLY, n_vec * (npw * 32.0), 8.0 * n_vec * npw * n_occ, &tm);
+  hipLaunchKernelGGL(k_proj_apply, dim3((long)tiles * n_vec), dim3(256), sizeof(double2) * (n_occ > 0 ? n_occ : 1),
+                     ctx->stream, npw, n_occ, psi, x, c, y, ldy, alpha, mode, tiles);
+  timing_end(ctx, &tm);
+  SGW_HIP(hipGetLastError());
+  return SGW_OK;
+}
+
+sgw_status rhs_source(sgw_ctx *ctx, const sgw_ham *h_kq, const sgw_ham *h_k, int n_vec, const int32_t *pairs,
+                      int n_pert, const int32_t *dvm, const double2 *psi_v, long ld_psi, double2 *s, long lds) {
+  if (n_vec <= 0) return SGW_OK;
+  const int npw = h_kq->n_pw;
+  const int tiles = (npw + 255) / 256;
+  PendingTiming tm;
+  timing_begin(ctx, K_RHS, n_vec * (npw * 32.0), 0.0, &tm);
+  hipLaunchKernelGGL(k_rhs_source, dim3((long)tiles * n_vec), dim3(256), 0, ctx->stream, npw, h_kq->d_miller_int,
+                     h_k->d_box, make_int3(h_k->box_lo[0], h_k->box_lo[1], h_k->box_lo[2]),
+                     make_int3(h_k->box_dim[0], h_k->box_dim[1], h_k->box_dim[2]), pairs, n_pert, dvm, psi_v,
+                     ld_psi, s, lds, tiles);
+  timing_end(ctx, &tm);
+  SGW_HIP(hipGetLastError());
+  return SGW_OK;
+}
+
+sgw_status slot_init(sgw_ctx *ctx, const SolverState &S, int n_fill, const double2 *src, const double2 *c,
+                     const int32_t *fill_slots, const int32_t *fill_pairs) {
+  if (n_fill <= 0) return SGW_OK;
+  PendingTiming tm;
+  timing_begin(ctx, K_INIT, n_fill * (S.npw * 48.0), 8.0 * n_fill * S.npw * S.n_occ, &tm);
+  hipLaunchKernelGGL(k_init, dim3(n_fill), dim3(kRowThreads), sizeof(double2) * (S.n_occ > 0 ? S.n_occ : 1),
+                     ctx->stream, S, src, c, fill_slots, fill_pairs);
+  timing_end(ctx, &tm);
+  SGW_HIP(hipGetLastError());
+  return SGW_OK;
+}
+
+int lanczos_ept(int npw) {
+  int e = 1;
+  while (e * kLzThreads < npw) e *= 2;
+  return e;
+}
+
+sgw_status lanczos_step(sgw_ctx *ctx, const SolverState &S, int n_active, const int32_t *list, const double2 *Y,
+                        const double2 *C) {
+  if (n_active <= 0) return SGW_OK;
+  PendingTiming tm;
+  timing_begin(ctx, K_LANCZOS, n_active * (S.npw * 16.0 * 5), 8.0 * n_active * S.npw * S.n_occ, &tm);
+  const int ept = lanczos_ept(S.npw);
+  switch (ept) {
+#define SGW_LZ(E)                                                                                      \
+  case E:                                                                                              \
+    hipLaunchKernelGGL(k_lanczos<E>, dim3(n_active), dim3(kLzThreads), 0, ctx->stream, S, list, Y, C); \
+    break;
+    SGW_LZ(1) SGW_LZ(2) SGW_LZ(4) SGW_LZ(8) SGW_LZ(16) SGW_LZ(32)
+#undef SGW_LZ
+    default:
+      return fail(SGW_ERR_UNSUPPORTED, "too many plane waves for the Lanczos kernel");
+  }
+  timing_end(ctx, &tm);
+  SGW_HIP(hipGetLastError());
+  return SGW_OK;
+}
+
+sgw_status tridiag(sgw_ctx *ctx, const SolverState &S, const int32_t *flist, int nf, double2 *ycoef, double2 *cp) {
+  if (nf <= 0) return SGW_OK;
+  const int n = nf * S.n_omega;
+  PendingTiming tm;
+  timing_begin(ctx, K_TRIDIAG, 0.0, 0.0, &tm);
+  hipLaunchKernelGGL(k_tridiag, dim3((n + 63) / 64), dim3(64), 0, ctx->stream, S, flist, nf, ycoef, cp);
+  timing_end(ctx, &tm);
+  SGW_HIP(hipGetLastError());
+  return SGW_OK;
+}
+
+sgw_status combine(sgw_ctx *ctx, const SolverState &S, const int32_t *flist, int nf, const double2 *ycoef,
+                   double2 *X, double est_kavg) {
+  if (nf <= 0) return SGW_OK;
+  const int gtiles = (S.npw + kCmbThreads - 1) / kCmbThreads;
+  const int jchunks = (S.n_omega + kCmbJ - 1) / kCmbJ;
+  PendingTiming tm;
+  const double bytes = nf * (est_kavg * S.npw * 16.0 + (double)S.n_omega * S.npw * 16.0);
+  timing_begin(ctx, K_COMBINE, bytes, 8.0 * nf * est_kavg * S.npw * S.n_omega, &tm);
+  hipLaunchKernelGGL(k_combine, dim3((long)nf * gtiles * jchunks), dim3(kCmbThreads), 0, ctx->stream, S, flist,
+                     ycoef, X, gtiles, jchunks);
+  timing_end(ctx, &tm);
+  SGW_HIP(hipGetLastError());
+  return SGW_OK;
+}
+
+sgw_status residual(sgw_ctx *ctx, const SolverState &S, const int32_t *flist, int nf, const double2 *X,
+                    const double2 *AX, const double2 *C, const int32_t *i2u, double2 *dpsi, sgw_solve_info *info,
+                    double tol, int *n_bad) {
+  if (nf <= 0) return SGW_OK;
+  PendingTiming tm;
+  timing_begin(ctx, K_RESIDUAL, (double)nf * S.n_omega * S.npw * 16.0 * 4, 8.0 * nf * S.n_omega * S.npw * S.n_occ,
+               &tm);
+  hipLaunchKernelGGL(k_residual, dim3((long)nf * S.n_omega), dim3(kRowThreads), 0, ctx->stream, S, flist, X, AX, C,
+                     i2u, dpsi, info, tol, n_bad);
+  timing_end(ctx, &tm);
+  SGW_HIP(hipGetLastError());
+  return SGW_OK;
+}
+
+sgw_status transpose_potential(sgw_ctx *ctx, const double *v, double *vt, const int n[3]) {
+  const long tot = (long)n[0] * n[1] * n[2];
+  hipLaunchKernelGGL(k_transpose_potential, dim3((tot + 255) / 256), dim3(256), 0, ctx->stream, v, vt, n[0], n[1],
+                     n[2]);
+  SGW_HIP(hipGetLastError());
+  return SGW_OK;
+}
+
+}  // namespace sgw

@@ -1,0 +1,62 @@
+// Device-side state of the slot-based multishift solver (passed by value to kernels).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "sgw_internal.h"
+
+namespace sgw {
+
+constexpr int kMaxOcc = 256;  // occupied states held in LDS by the per-vector kernels
+// ||(1 - P_occ) s|| below this fraction of ||s|| counts as a zero right-hand side
+constexpr double kZeroRhsRel = 1e-13;
+
+enum SlotStatus {
+  SLOT_FREE = -1,
+  SLOT_RUNNING = 0,
+  SLOT_CONVERGED = 1,
+  SLOT_MAXITER = 2,
+  SLOT_BREAKDOWN = 3,
+  SLOT_NONFINITE = 4,
+  SLOT_ZERO_RHS = 5
+};
+
+struct SolverState {
+  int npw, n_occ, n_omega, n_pert, kmax;
+  long slot_stride;          // (kmax + 1) * npw
+  const double2 *psi;        // [n_occ][npw] occupied states, internal order
+  double2 *basis;            // [slots][kmax + 1][npw]
+  double2 *bvec;             // [slots][npw] right-hand sides
+  double *alpha_t;           // [slots][kmax] Lanczos diagonal
+  double *beta;              // [slots][kmax + 1]; beta[0] = ||b||
+  double2 *rho;              // [slots][n_omega] last LU pivot per shift
+  double *res;               // [slots][n_omega] estimated relative residual
+  int32_t *pair;             // [slots] pair index v * n_pert + p
+  int32_t *kcur;             // [slots] completed steps
+  int32_t *status;           // [slots] SlotStatus
+  double *eps;               // [slots] band energy of the slot's pair
+  const double *eps_band;    // [n_band]
+  const double *omega;       // [n_omega]
+  double eta;
+  double alpha;              // coefficient of P_occ
+  double tol_int;            // stop when every estimated residual is below this
+};
+
+sgw_status rhs_source(sgw_ctx *ctx, const sgw_ham *h_kq, const sgw_ham *h_k, int n_vec, const int32_t *pairs,
+                      int n_pert, const int32_t *dvm, const double2 *psi_v, long ld_psi, double2 *s, long lds);
+sgw_status slot_init(sgw_ctx *ctx, const SolverState &S, int n_fill, const double2 *src, const double2 *c,
+                     const int32_t *fill_slots, const int32_t *fill_pairs);
+sgw_status lanczos_step(sgw_ctx *ctx, const SolverState &S, int n_active, const int32_t *list, const double2 *Y,
+                        const double2 *C);
+sgw_status tridiag(sgw_ctx *ctx, const SolverState &S, const int32_t *flist, int nf, double2 *ycoef, double2 *cp);
+sgw_status combine(sgw_ctx *ctx, const SolverState &S, const int32_t *flist, int nf, const double2 *ycoef,
+                   double2 *X, double est_kavg);
+sgw_status residual(sgw_ctx *ctx, const SolverState &S, const int32_t *flist, int nf, const double2 *X,
+                    const double2 *AX, const double2 *C, const int32_t *i2u, double2 *dpsi, sgw_solve_info *info,
+                    double tol, int *n_bad);
+sgw_status transpose_potential(sgw_ctx *ctx, const double *v, double *vt, const int n[3]);
+int lanczos_ept(int npw);
+
+}  // namespace sgw

@@ -1,0 +1,284 @@
+"""Thin ctypes binding of libsgw.so (argument marshalling only).
+
+Every function keeps the name of the C entry point it wraps.  Device arrays
+are torch tensors on the context's device (complex128 for plane-wave vectors,
+float64 for the potential); all GPU work runs in the library's HIP kernels.
+There is no fallback: if the library is missing or no GPU is present, the
+calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsgw.so")
+
+SGW_OK, SGW_NOT_CONVERGED = 0, 1
+SGW_ERR_INVALID_ARG, SGW_ERR_HIP, SGW_ERR_WORKSPACE, SGW_ERR_UNSUPPORTED = -1, -2, -3, -4
+FLAG_CONVERGED, FLAG_MAXITER, FLAG_BREAKDOWN, FLAG_NONFINITE, FLAG_ZERO_RHS = 1, 2, 4, 8, 16
+
+INFO_DTYPE = np.dtype([("iters", "<i4"), ("flags", "<i4"), ("relres", "<f8"), ("occ_leak", "<f8")])
+
+EXPORTED = [
+    "sgw_last_error", "sgw_version", "sgw_ctx_create", "sgw_ctx_destroy", "sgw_ctx_set_profiling",
+    "sgw_ctx_reset_stats", "sgw_kernel_stats", "sgw_ham_create", "sgw_ham_destroy", "sgw_ham_npw",
+    "sgw_apply_h", "sgw_apply_projector", "sgw_build_rhs", "sgw_opts_default",
+    "sternheimer_workspace_size", "sternheimer_solve",
+]
+
+
+class SgwError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"sgw error {code}: {msg}")
+        self.code = code
+
+
+class sgw_ham_desc(C.Structure):
+    _fields_ = [("grid", C.c_int32 * 3), ("recip", (C.c_double * 3) * 3), ("kvec", C.c_double * 3),
+                ("n_pw", C.c_int32), ("miller", C.POINTER(C.c_int32)), ("v_loc", C.c_void_p)]
+
+
+class sgw_opts(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("max_iter", C.c_int32), ("alpha_pv", C.c_double),
+                ("tol_safety", C.c_double), ("slots", C.c_int32), ("finalize_batch", C.c_int32),
+                ("steps_per_sync", C.c_int32), ("reserved", C.c_int32)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libsgw.so once; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise FileNotFoundError(f"{path} not built: run `python -m paper_1812_03717_amd.build`")
+    lib = C.CDLL(path)
+    vp, i32, dbl, sz = C.c_void_p, C.c_int32, C.c_double, C.c_size_t
+    lib.sgw_last_error.restype = C.c_char_p
+    lib.sgw_version.restype = C.c_char_p
+    sig = {
+        "sgw_ctx_create": [C.c_int, vp, C.POINTER(vp)],
+        "sgw_ctx_destroy": [vp],
+        "sgw_ctx_set_profiling": [vp, C.c_char_p],
+        "sgw_ctx_reset_stats": [vp],
+        "sgw_kernel_stats": [vp, C.c_char_p, C.POINTER(C.c_int64), C.POINTER(dbl), C.POINTER(dbl), C.POINTER(dbl)],
+        "sgw_ham_create": [vp, C.POINTER(sgw_ham_desc), C.POINTER(vp)],
+        "sgw_ham_destroy": [vp],
+        "sgw_apply_h": [vp, vp, C.c_int, vp, vp],
+        "sgw_apply_projector": [vp, vp, C.c_int, vp, C.c_int, vp, vp, dbl, C.c_int],
+        "sgw_build_rhs": [vp, vp, C.c_int, vp, vp, C.c_int, vp, C.c_int, C.POINTER(i32), vp],
+        "sgw_opts_default": [C.POINTER(sgw_opts)],
+        "sternheimer_workspace_size": [vp, vp, C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(sgw_opts),
+                                       C.POINTER(sz)],
+        "sternheimer_solve": [vp, vp, C.c_int, vp, vp, C.c_int, vp, C.POINTER(dbl), C.c_int, C.POINTER(i32),
+                              C.c_int, C.POINTER(dbl), dbl, dbl, C.POINTER(sgw_opts), vp, sz, vp, vp],
+    }
+    for name, args in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = C.c_int
+    lib.sgw_ham_npw.argtypes = [vp]
+    lib.sgw_ham_npw.restype = C.c_int32
+    _lib = lib
+    return lib
+
+
+def _check(code):
+    if code < 0:
+        raise SgwError(code, load_library().sgw_last_error().decode())
+    return code
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else C.c_void_p(0)
+
+
+def _require(t, dtype, device, shape=None, name="array"):
+    import torch
+    if not isinstance(t, torch.Tensor) or t.dtype != dtype or t.device != device or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous {dtype} tensor on {device}")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+
+
+# ---------------------------------------------------------------------------
+# context
+# ---------------------------------------------------------------------------
+
+class sgw_ctx_create:
+    """Context on ``device`` enqueuing on ``stream`` (default: torch's current stream)."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        lib = load_library()
+        self.device = torch.device("cuda", device)
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        self.stream = stream
+        h = C.c_void_p()
+        _check(lib.sgw_ctx_create(device, C.c_void_p(stream.cuda_stream), C.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load_library().sgw_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_profiling(self, kernels):
+        """kernels: comma-separated kernel names, "all", or None."""
+        _check(load_library().sgw_ctx_set_profiling(self.handle, kernels.encode() if kernels else None))
+
+    def reset_stats(self):
+        _check(load_library().sgw_ctx_reset_stats(self.handle))
+
+    def kernel_stats(self, name: str):
+        n, ms, b, f = C.c_int64(), C.c_double(), C.c_double(), C.c_double()
+        _check(load_library().sgw_kernel_stats(self.handle, name.encode(), C.byref(n), C.byref(ms), C.byref(b),
+                                               C.byref(f)))
+        return {"launches": n.value, "ms": ms.value, "bytes": b.value, "flops": f.value}
+
+
+class sgw_ham_create:
+    """Hamiltonian at one Bloch vector: grid, reciprocal rows, k, Miller list (host), V(r) (device float64)."""
+
+    def __init__(self, ctx: sgw_ctx_create, grid, recip, kvec, miller, v_loc):
+        lib = load_library()
+        _require(v_loc, __import__("torch").float64, ctx.device, tuple(grid), "v_loc")
+        self.ctx = ctx
+        self.miller = np.ascontiguousarray(np.asarray(miller, np.int32))
+        d = sgw_ham_desc()
+        for a in range(3):
+            d.grid[a] = int(grid[a])
+            d.kvec[a] = float(kvec[a])
+            for b in range(3):
+                d.recip[a][b] = float(recip[a][b])
+        d.n_pw = int(self.miller.shape[0])
+        d.miller = self.miller.ctypes.data_as(C.POINTER(C.c_int32))
+        d.v_loc = C.c_void_p(v_loc.data_ptr())
+        h = C.c_void_p()
+        _check(lib.sgw_ham_create(ctx.handle, C.byref(d), C.byref(h)))
+        self.handle = h
+        self.n_pw = d.n_pw
+        self.grid = tuple(int(g) for g in grid)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load_library().sgw_ham_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------------------
+# calls
+# ---------------------------------------------------------------------------
+
+def sgw_apply_h(ctx, ham, x):
+    import torch
+    _require(x, torch.complex128, ctx.device, (x.shape[0], ham.n_pw), "x")
+    y = torch.empty_like(x)
+    _check(load_library().sgw_apply_h(ctx.handle, ham.handle, int(x.shape[0]), _ptr(x), _ptr(y)))
+    return y
+
+
+def sgw_apply_projector(ctx, ham, psi, x, alpha=1.0, mode=0, y=None):
+    import torch
+    _require(x, torch.complex128, ctx.device, (x.shape[0], ham.n_pw), "x")
+    _require(psi, torch.complex128, ctx.device, (psi.shape[0], ham.n_pw), "psi")
+    if y is None:
+        y = torch.zeros_like(x)
+    _check(load_library().sgw_apply_projector(ctx.handle, ham.handle, int(psi.shape[0]), _ptr(psi),
+                                              int(x.shape[0]), _ptr(x), _ptr(y), float(alpha), int(mode)))
+    return y
+
+
+def sgw_build_rhs(ctx, h_kq, psi_occ_kq, h_k, psi_v, dv_miller):
+    import torch
+    _require(psi_v, torch.complex128, ctx.device, (psi_v.shape[0], h_k.n_pw), "psi_v")
+    _require(psi_occ_kq, torch.complex128, ctx.device, (psi_occ_kq.shape[0], h_kq.n_pw), "psi_occ_kq")
+    dvm = np.ascontiguousarray(np.asarray(dv_miller, np.int32).reshape(-1, 3))
+    n_band, n_pert = int(psi_v.shape[0]), int(dvm.shape[0])
+    b = torch.empty((n_band, n_pert, h_kq.n_pw), dtype=torch.complex128, device=ctx.device)
+    _check(load_library().sgw_build_rhs(ctx.handle, h_kq.handle, int(psi_occ_kq.shape[0]), _ptr(psi_occ_kq),
+                                        h_k.handle, n_band, _ptr(psi_v), n_pert,
+                                        dvm.ctypes.data_as(C.POINTER(C.c_int32)), _ptr(b)))
+    return b
+
+
+def sgw_opts_default(**overrides):
+    o = sgw_opts()
+    _check(load_library().sgw_opts_default(C.byref(o)))
+    for k, v in overrides.items():
+        setattr(o, k, v)
+    return o
+
+
+def sternheimer_workspace_size(ctx, h_kq, n_occ, n_band, n_pert, n_omega, opts=None):
+    o = opts if opts is not None else sgw_opts_default()
+    n = C.c_size_t()
+    _check(load_library().sternheimer_workspace_size(ctx.handle, h_kq.handle, n_occ, n_band, n_pert, n_omega,
+                                                     C.byref(o), C.byref(n)))
+    return int(n.value)
+
+
+class Workspace:
+    """Caller-owned device workspace (a torch uint8 tensor), reused across calls."""
+
+    def __init__(self, ctx):
+        self.ctx = ctx
+        self.buf = None
+
+    def get(self, nbytes):
+        import torch
+        if self.buf is None or self.buf.numel() < nbytes:
+            self.buf = None
+            self.buf = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.ctx.device)
+        return self.buf
+
+
+def sternheimer_solve(ctx, h_kq, psi_occ_kq, h_k, psi_v, eps_v, dv_miller, omega, eta, tol, opts=None,
+                      workspace=None, dpsi=None, info=None):
+    """Returns (status, dpsi [n_band][n_pert][n_omega][n_pw_kq] complex128 tensor, info device uint8 tensor)."""
+    import torch
+    _require(psi_v, torch.complex128, ctx.device, (psi_v.shape[0], h_k.n_pw), "psi_v")
+    _require(psi_occ_kq, torch.complex128, ctx.device, (psi_occ_kq.shape[0], h_kq.n_pw), "psi_occ_kq")
+    eps = np.ascontiguousarray(np.asarray(eps_v, np.float64))
+    om = np.ascontiguousarray(np.asarray(omega, np.float64))
+    dvm = np.ascontiguousarray(np.asarray(dv_miller, np.int32).reshape(-1, 3))
+    n_band, n_pert, n_omega, n_occ = int(psi_v.shape[0]), int(dvm.shape[0]), int(om.shape[0]), int(psi_occ_kq.shape[0])
+    if eps.shape != (n_band,):
+        raise ValueError("eps_v must have one energy per band")
+    o = opts if opts is not None else sgw_opts_default()
+    nbytes = sternheimer_workspace_size(ctx, h_kq, n_occ, n_band, n_pert, n_omega, o)
+    ws = (workspace or Workspace(ctx)).get(nbytes)
+    if dpsi is None:
+        dpsi = torch.empty((n_band, n_pert, n_omega, h_kq.n_pw), dtype=torch.complex128, device=ctx.device)
+    if info is None:
+        info = torch.empty(n_band * n_pert * n_omega * INFO_DTYPE.itemsize, dtype=torch.uint8, device=ctx.device)
+    st = _check(load_library().sternheimer_solve(
+        ctx.handle, h_kq.handle, n_occ, _ptr(psi_occ_kq), h_k.handle, n_band, _ptr(psi_v),
+        eps.ctypes.data_as(C.POINTER(C.c_double)), n_pert, dvm.ctypes.data_as(C.POINTER(C.c_int32)), n_omega,
+        om.ctypes.data_as(C.POINTER(C.c_double)), float(eta), float(tol), C.byref(o), _ptr(ws),
+        C.c_size_t(ws.numel()), _ptr(dpsi), _ptr(info)))
+    return st, dpsi, info
+
+
+def info_to_numpy(info, shape=None):
+    """Device info bytes -> structured numpy array (fields iters, flags, relres, occ_leak)."""
+    a = info.cpu().numpy().view(INFO_DTYPE)
+    return a.reshape(shape) if shape is not None else a

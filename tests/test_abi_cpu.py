@@ -1,0 +1,47 @@
+"""Host-only checks of the C ABI: the library loads and exports every declared symbol,
+and host-side argument validation answers without a GPU."""
+import ctypes as C
+import os
+import re
+
+from paper_1812_03717_amd import sgw
+from tests.libutil import ensure_library
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "sgw.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b((?:sgw|sternheimer)_\w+)\s*\(", src)))
+
+
+def test_header_declares_the_binding_names():
+    decl = declared_functions()
+    assert set(decl) == set(sgw.EXPORTED), (set(decl) ^ set(sgw.EXPORTED))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ensure_library()
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_host_side_calls():
+    lib = ensure_library()
+    assert b"gfx950" in lib.sgw_version()
+    o = sgw.sgw_opts()
+    assert lib.sgw_opts_default(C.byref(o)) == 0
+    assert o.max_iter == 600 and o.alpha_pv == 1.0 and o.precision == 0
+    # NULL arguments are rejected with a message, never a crash
+    assert lib.sgw_opts_default(None) == sgw.SGW_ERR_INVALID_ARG
+    assert b"NULL" in lib.sgw_last_error()
+    n = C.c_size_t()
+    assert lib.sternheimer_workspace_size(None, None, 1, 1, 1, 1, None, C.byref(n)) == sgw.SGW_ERR_INVALID_ARG
+    assert lib.sgw_ctx_create(0, None, None) == sgw.SGW_ERR_INVALID_ARG
+    assert lib.sgw_ham_create(None, None, None) == sgw.SGW_ERR_INVALID_ARG
+    assert lib.sgw_apply_h(None, None, 1, None, None) == sgw.SGW_ERR_INVALID_ARG
+    assert lib.sgw_kernel_stats(None, b"hx_planes", None, None, None, None) == sgw.SGW_ERR_INVALID_ARG
+    st = lib.sternheimer_solve(None, None, 0, None, None, 0, None, None, 0, None, 0, None, 0.1, 1e-8, None, None,
+                               0, None, None)
+    assert st == sgw.SGW_ERR_INVALID_ARG

@@ -1,0 +1,161 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Bars: H.x, projector and right-hand side to 1e-12 relative (complex128,
+rounding-order differences only); solved Delta psi to 1e-8 relative per solve
+when the solver tolerance is set from the condition number (tol_eff =
+1e-8 / (2 kappa)), and to kappa * relres for solves at the workload tolerance.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import oracle.sternheimer_oracle as so
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from tests.libutil import ensure_library
+    ensure_library()
+    from paper_1812_03717_amd import sgw
+    c = sgw.sgw_ctx_create(0)
+    yield c
+    torch.cuda.synchronize()
+
+
+def _dev(ctx, p):
+    from paper_1812_03717_amd.workload import DeviceProblem
+    return DeviceProblem(ctx, p)
+
+
+PROBLEMS = {
+    "si2": lambda: synth.si2(),
+    "fcc1_q": lambda: synth.small((1, 1, 1), n_omega=6, n_pert=5, seed=9100),
+    "fcc112_q": lambda: synth.small((1, 1, 2), n_omega=5, n_pert=3, seed=9200, ecut=6.0),
+}
+
+
+@pytest.mark.parametrize("name", sorted(PROBLEMS))
+def test_apply_h_matches_dense(ctx, name):
+    from paper_1812_03717_amd import sgw
+    p = PROBLEMS[name]()
+    d = _dev(ctx, p)
+    rng = np.random.default_rng(0)
+    for ham, miller, k in ((d.h_k, p.miller_k, p.kvec), (d.h_kq, p.miller_kq, p.kvec + p.qvec)):
+        n = miller.shape[0]
+        x = rng.standard_normal((7, n)) + 1j * rng.standard_normal((7, n))
+        y = sgw.sgw_apply_h(ctx, ham, torch.from_numpy(x).to(ctx.device)).cpu().numpy()
+        h = so.hamiltonian(miller, p.B, k, p.v_grid)
+        yr = x @ h.T
+        err = np.abs(y - yr).max() / np.abs(yr).max()
+        print(name, n, "apply_h rel err", err, flush=True)
+        assert err <= 1e-12
+
+
+def test_apply_projector(ctx):
+    from paper_1812_03717_amd import sgw
+    p = PROBLEMS["fcc1_q"]()
+    d = _dev(ctx, p)
+    rng = np.random.default_rng(1)
+    n = p.n_pw_kq
+    x = rng.standard_normal((5, n)) + 1j * rng.standard_normal((5, n))
+    xt = torch.from_numpy(x).to(ctx.device)
+    y0 = sgw.sgw_apply_projector(ctx, d.h_kq, d.psi_occ_kq, xt, mode=0).cpu().numpy()
+    ref0 = np.array([xi - so.apply_occupied_projector(p.psi_kq, xi) for xi in x])
+    assert np.abs(y0 - ref0).max() <= 1e-12 * np.abs(ref0).max()
+    base = rng.standard_normal((5, n)) + 1j * rng.standard_normal((5, n))
+    y1 = sgw.sgw_apply_projector(ctx, d.h_kq, d.psi_occ_kq, xt, alpha=2.5, mode=1,
+                                 y=torch.from_numpy(base.copy()).to(ctx.device)).cpu().numpy()
+    ref1 = base + 2.5 * np.array([so.apply_occupied_projector(p.psi_kq, xi) for xi in x])
+    assert np.abs(y1 - ref1).max() <= 1e-12 * np.abs(ref1).max()
+
+
+@pytest.mark.parametrize("name", sorted(PROBLEMS))
+def test_build_rhs(ctx, name):
+    from paper_1812_03717_amd import sgw
+    p = PROBLEMS[name]()
+    d = _dev(ctx, p)
+    b = sgw.sgw_build_rhs(ctx, d.h_kq, d.psi_occ_kq, d.h_k, d.psi_v, p.dv_miller).cpu().numpy()
+    for v in range(p.n_band):
+        for q in range(p.n_pert):
+            ref = so.rhs(p.psi_k[v], p.miller_k, p.miller_kq, p.dv_miller[q], p.psi_kq)
+            assert np.abs(b[v, q] - ref).max() <= 1e-13 * max(1.0, np.abs(ref).max()), (v, q)
+
+
+def _oracle_solutions(p, pairs):
+    setup = oracle.spectral_setup(p.miller_kq, p.B, p.kvec + p.qvec, p.v_grid)
+    xs, bs = oracle.solve_pairs(setup, p.n_occ, p.psi_k, p.eps_k, p.miller_k, p.miller_kq, p.dv_miller, p.psi_kq,
+                                p.omega, p.eta, pairs)
+    return setup, xs, bs
+
+
+def _kappa(setup, p, v):
+    _, w, _ = setup
+    return np.array([so.condition_number(w, p.n_occ, p.eps_k[v], om + 1j * p.eta) for om in p.omega])
+
+
+@pytest.mark.parametrize("name", sorted(PROBLEMS))
+def test_solve_matches_oracle(ctx, name):
+    from paper_1812_03717_amd import sgw
+    p = PROBLEMS[name]()
+    d = _dev(ctx, p)
+    pairs = [(v, q) for v in range(p.n_band) for q in range(p.n_pert)]
+    setup, xs, bs = _oracle_solutions(p, pairs)
+    kap = max(_kappa(setup, p, v).max() for v in range(p.n_band))
+    tol = min(p.tol, 1e-8 / (2.0 * kap))
+    st, dpsi, info = d.solve(tol=tol)
+    dpsi = dpsi.cpu().numpy()
+    inf = sgw.info_to_numpy(info, (p.n_band, p.n_pert, p.n_omega))
+    print(name, "kappa", kap, "tol", tol, "iters", inf["iters"].min(), inf["iters"].max(), flush=True)
+    assert st == sgw.SGW_OK, sgw.load_library().sgw_last_error()
+    assert np.all(inf["flags"] & sgw.FLAG_CONVERGED)
+    assert inf["relres"].max() <= tol
+    worst = 0.0
+    for i, (v, q) in enumerate(pairs):
+        for j in range(p.n_omega):
+            ref = xs[i, j]
+            err = np.linalg.norm(dpsi[v, q, j] - ref) / np.linalg.norm(ref)
+            worst = max(worst, err)
+            assert err <= 1e-8, (v, q, j, err)
+    print(name, "max rel err vs oracle", worst, "max occ leak", inf["occ_leak"].max(), flush=True)
+    assert inf["occ_leak"].max() <= 1e-10
+
+
+def test_solve_edge_cases(ctx):
+    """Zero right-hand side (G_p = 0 at q = 0), a single frequency, negative eta, max_iter = 1."""
+    from paper_1812_03717_amd import sgw
+    p = synth.si2()
+    d = _dev(ctx, p)
+    # G_p = 0 at q = 0 drives only occupied states: b = 0, dpsi = 0, relres 0, ZERO_RHS flag
+    st, dpsi, info = sgw.sternheimer_solve(ctx, d.h_kq, d.psi_occ_kq, d.h_k, d.psi_v, d.eps_v,
+                                           np.zeros((1, 3), np.int32), p.omega[:3], p.eta, 1e-10)
+    inf = sgw.info_to_numpy(info)
+    assert st == sgw.SGW_OK
+    assert np.all(inf["flags"] & sgw.FLAG_ZERO_RHS) and np.all(inf["relres"] == 0)
+    assert torch.count_nonzero(dpsi).item() == 0
+    # max_iter = 1: every solve flagged, best iterate returned, status NOT_CONVERGED
+    st, dpsi, info = d.solve(tol=1e-10, opts=sgw.sgw_opts_default(max_iter=1))
+    inf = sgw.info_to_numpy(info)
+    assert st == sgw.SGW_NOT_CONVERGED
+    assert np.all(inf["flags"] & sgw.FLAG_MAXITER) and np.all(inf["iters"] == 1)
+    # negative eta: the advanced branch, checked against the oracle's LU route
+    v, q = 3, 1
+    b = so.rhs(p.psi_k[v], p.miller_k, p.miller_kq, p.dv_miller[q], p.psi_kq)
+    h = so.hamiltonian(p.miller_kq, p.B, p.kvec, p.v_grid)
+    a0 = so.coulomb_operator(h, p.psi_kq, p.eps_k[v], 1.0)
+    st, dpsi, info = sgw.sternheimer_solve(ctx, d.h_kq, d.psi_occ_kq, d.h_k, d.psi_v[v:v + 1].contiguous(),
+                                           d.eps_v[v:v + 1], p.dv_miller[q:q + 1], p.omega[2:3], -p.eta, 1e-12)
+    x = dpsi.cpu().numpy()[0, 0, 0]
+    ref = so.solve_lu(a0, b, p.omega[2] - 1j * p.eta)
+    assert np.linalg.norm(x - ref) <= 1e-8 * np.linalg.norm(ref)
+    # invalid arguments are rejected before any GPU work
+    with pytest.raises(sgw.SgwError):
+        sgw.sternheimer_solve(ctx, d.h_kq, d.psi_occ_kq, d.h_k, d.psi_v, d.eps_v, p.dv_miller, p.omega, 0.0, 1e-8)
+    with pytest.raises(sgw.SgwError):
+        sgw.sternheimer_solve(ctx, d.h_kq, d.psi_occ_kq, d.h_k, d.psi_v, d.eps_v, p.dv_miller, p.omega, p.eta, -1.0)
