@@ -36,7 +36,7 @@ WORKLOADS = {
            "eta 0.1 eV, tol 1e-10",
 }
 
-KERNELS = ["hx_sticks_inv", "hx_planes", "hx_sticks_fwd", "proj_dot", "lanczos_step", "slot_init", "rhs_source",
+KERNELS = ["hx_sticks_inv", "hx_planes", "hx_sticks_fwd", "proj_dot", "proj_apply", "lanczos_step", "slot_init", "rhs_source",
            "tridiag", "combine", "residual", "permute"]
 
 
@@ -98,7 +98,19 @@ def main():
     ap.add_argument("--slots", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-pairs", type=int, default=8)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run 5 device-to-device copies of MIB MiB (HBM counter calibration) and exit")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        n = args.copy_calibration << 20
+        a = torch.empty(n, dtype=torch.uint8, device="cuda").fill_(1)
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_each_way": n, "copies": 5}))
+        return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
               "(the (band, perturbation) pairs would be sharded across GPUs; see DESIGN.md)", file=sys.stderr)

@@ -104,7 +104,7 @@ sgw_status sgw_kernel_stats(sgw_ctx *ctx, const char *name, int64_t *launches, d
  * the local potential on the FFT grid.
  */
 typedef struct {
-  int32_t grid[3];          /* N0, N1, N2; each in {16, 24, 32, 48, 64, 72, 96} */
+  int32_t grid[3];          /* N0, N1, N2; each in {16, 24, 32, 48, 64, 72} */
   double recip[3][3];       /* rows b_i of the reciprocal lattice, bohr^-1 */
   double kvec[3];           /* Cartesian Bloch vector, bohr^-1 */
   int32_t n_pw;             /* number of plane waves */

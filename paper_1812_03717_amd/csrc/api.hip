@@ -200,7 +200,7 @@ static sgw_status upload(sgw_ctx *ctx, T **dst, const std::vector<T> &src) {
 
 static void ham_free(sgw_ham *h) {
   if (!h) return;
-  void *ptrs[] = {h->d_i2u, h->d_u2i, h->d_stick_off, h->d_stick_xy, h->d_pw_stick, h->d_pw_z,
+  void *ptrs[] = {h->d_i2u, h->d_u2i, h->d_stick_off, h->d_stick_at, h->d_pw_stick, h->d_pw_z,
                   h->d_miller_int, h->d_kin, h->d_vt, h->d_box, h->d_tw};
   for (void *p : ptrs)
     if (p) hipFree(p);
@@ -215,7 +215,7 @@ extern "C" sgw_status sgw_ham_create(sgw_ctx *ctx, const sgw_ham_desc *d, sgw_ha
   for (int a = 0; a < 3; ++a) {
     if (!hx_grid_supported(d->grid[a]))
       return fail(SGW_ERR_UNSUPPORTED, "sgw_ham_create: grid size " + std::to_string(d->grid[a]) +
-                                           " not in {16,24,32,48,64,72,96}");
+                                           " not in {16,24,32,48,64,72}");
   }
   for (int a = 0; a < 3; ++a)
     for (int b = 0; b < 3; ++b)
@@ -260,7 +260,8 @@ extern "C" sgw_status sgw_ham_create(sgw_ctx *ctx, const sgw_ham_desc *d, sgw_ha
     if (ma[1] != mb[1]) return ma[1] < mb[1];
     return ma[2] < mb[2];
   });
-  std::vector<int32_t> i2u(npw), u2i(npw), pw_stick(npw), pw_z(npw), miller_int(3 * npw), stick_off, stick_xy;
+  std::vector<int32_t> i2u(npw), u2i(npw), pw_stick(npw), pw_z(npw), miller_int(3 * npw), stick_off;
+  std::vector<int32_t> stick_at((size_t)n[0] * n[1], -1);
   std::vector<double> kin(npw);
   int ns = 0;
   for (int gi = 0; gi < npw; ++gi) {
@@ -268,7 +269,7 @@ extern "C" sgw_status sgw_ham_create(sgw_ctx *ctx, const sgw_ham_desc *d, sgw_ha
     const int *m = d->miller + 3 * u;
     if (gi == 0 || m[0] != d->miller[3 * order[gi - 1]] || m[1] != d->miller[3 * order[gi - 1] + 1]) {
       stick_off.push_back(gi);
-      stick_xy.push_back((imod(m[0], n[0]) << 16) | imod(m[1], n[1]));
+      stick_at[(size_t)imod(m[0], n[0]) * n[1] + imod(m[1], n[1])] = ns;
       ++ns;
     }
     i2u[gi] = u;
@@ -319,7 +320,7 @@ extern "C" sgw_status sgw_ham_create(sgw_ctx *ctx, const sgw_ham_desc *d, sgw_ha
   SGW_UP(h->d_i2u, i2u);
   SGW_UP(h->d_u2i, u2i);
   SGW_UP(h->d_stick_off, stick_off);
-  SGW_UP(h->d_stick_xy, stick_xy);
+  SGW_UP(h->d_stick_at, stick_at);
   SGW_UP(h->d_pw_stick, pw_stick);
   SGW_UP(h->d_pw_z, pw_z);
   SGW_UP(h->d_miller_int, miller_int);
@@ -410,12 +411,14 @@ extern "C" sgw_status sgw_apply_projector(sgw_ctx *ctx, const sgw_ham *h, int n_
   const int npw = h->n_pw;
   DevBuf cb;
   sgw_status st;
-  if ((st = alloc_async(cb, sizeof(double2) * (size_t)n_vec * std::max(n_occ, 1), ctx->stream)) != SGW_OK) return st;
+  if ((st = alloc_async(cb, sizeof(double2) * kProjChunks * (size_t)n_vec * std::max(n_occ, 1), ctx->stream)) !=
+      SGW_OK)
+    return st;
   if ((st = proj_dot(ctx, npw, n_occ, (const double2 *)psi, n_vec, contiguous((const double2 *)x, npw),
-                     (double2 *)cb.p)) != SGW_OK)
+                     (double2 *)cb.p, n_vec)) != SGW_OK)
     return st;
   if ((st = proj_apply(ctx, npw, n_occ, (const double2 *)psi, n_vec, contiguous((const double2 *)x, npw),
-                       (double2 *)cb.p, (double2 *)y, npw, alpha, mode)) != SGW_OK)
+                       (double2 *)cb.p, n_vec, (double2 *)y, npw, alpha, mode)) != SGW_OK)
     return st;
   return sync(ctx);
 }
@@ -444,7 +447,9 @@ extern "C" sgw_status sgw_build_rhs(sgw_ctx *ctx, const sgw_ham *h_kq, int n_occ
   if ((st = alloc_async(pairs, sizeof(int32_t) * nvec, ctx->stream)) != SGW_OK) return st;
   if ((st = alloc_async(dvm, sizeof(int32_t) * 3 * n_pert, ctx->stream)) != SGW_OK) return st;
   if ((st = alloc_async(s, sizeof(double2) * (size_t)nvec * npw, ctx->stream)) != SGW_OK) return st;
-  if ((st = alloc_async(c, sizeof(double2) * (size_t)nvec * std::max(n_occ, 1), ctx->stream)) != SGW_OK) return st;
+  if ((st = alloc_async(c, sizeof(double2) * kProjChunks * (size_t)nvec * std::max(n_occ, 1), ctx->stream)) !=
+      SGW_OK)
+    return st;
   if ((st = alloc_async(psi, sizeof(double2) * (size_t)std::max(n_occ, 1) * npw, ctx->stream)) != SGW_OK) return st;
   std::vector<int32_t> hp(nvec);
   std::iota(hp.begin(), hp.end(), 0);
@@ -457,14 +462,14 @@ extern "C" sgw_status sgw_build_rhs(sgw_ctx *ctx, const sgw_ham *h_kq, int n_occ
   if ((st = rhs_source(ctx, h_kq, h_k, nvec, (int32_t *)pairs.p, n_pert, (int32_t *)dvm.p,
                        (const double2 *)psi_v, h_k->n_pw, (double2 *)s.p, npw)) != SGW_OK)
     return st;
-  if ((st = proj_dot(ctx, npw, n_occ, (double2 *)psi.p, nvec, contiguous((double2 *)s.p, npw), (double2 *)c.p)) !=
-      SGW_OK)
+  if ((st = proj_dot(ctx, npw, n_occ, (double2 *)psi.p, nvec, contiguous((double2 *)s.p, npw), (double2 *)c.p,
+                     nvec)) != SGW_OK)
     return st;
   // b = -(s - psi^T c): y = s - psi^T c here, negated by the scatter to the caller's order
   DevBuf bi;
   if ((st = alloc_async(bi, sizeof(double2) * (size_t)nvec * npw, ctx->stream)) != SGW_OK) return st;
   if ((st = proj_apply(ctx, npw, n_occ, (double2 *)psi.p, nvec, contiguous((double2 *)s.p, npw), (double2 *)c.p,
-                       (double2 *)bi.p, npw, 1.0, 0)) != SGW_OK)
+                       nvec, (double2 *)bi.p, npw, 1.0, 0)) != SGW_OK)
     return st;
   if ((st = permute(ctx, npw, nvec, (double2 *)bi.p, npw, (double2 *)b, npw, h_kq->d_i2u, 1, -1.0)) != SGW_OK)
     return st;
@@ -496,7 +501,8 @@ constexpr double kDefaultBudget = 40.0 * (1ull << 30);
 struct Layout {
   int S = 0, F = 0, kmax = 0, M = 8;
   size_t psi, omega, epsb, dvm, pair, kcur, status, eps, alpha, beta, rho, res, bvec, basis;
-  size_t l_active, l_fill, l_fillpairs, l_final, Y, C, T, ycoef, cp, X, AX, bad;
+  size_t l_active, l_fill, l_fillpairs, l_final, Y, Y2, C, T, ycoef, cp, X, AX, bad;
+  long c_rows = 0;
   size_t total = 0;
 };
 
@@ -561,7 +567,9 @@ Layout make_layout(const sgw_ham *h, int n_occ, int n_band, int n_pert, int n_om
   L.l_fillpairs = take(off, 4ul * L.S);
   L.l_final = take(off, 4ul * L.S);
   L.Y = take(off, 16ul * L.S * npw);
-  L.C = take(off, 16ul * tv * std::max(n_occ, 1));
+  L.Y2 = take(off, 16ul * L.S * npw);
+  L.c_rows = tv;
+  L.C = take(off, 16ul * kProjChunks * tv * std::max(n_occ, 1));
   L.T = take(off, 16ul * tv * h->n[2] * h->n_stick);
   L.ycoef = take(off, 16ul * L.F * L.kmax * n_omega);
   L.cp = take(off, 16ul * L.F * L.kmax * n_omega);
@@ -659,7 +667,9 @@ extern "C" sgw_status sternheimer_solve(sgw_ctx *ctx, const sgw_ham *h_kq, int n
   int32_t *d_final = (int32_t *)(W + L.l_final);
   int32_t *d_dvm = (int32_t *)(W + L.dvm);
   double2 *Y = (double2 *)(W + L.Y);
-  double2 *C = (double2 *)(W + L.C);
+  double2 *C = (double2 *)(W + L.C);   // overlap partials [kProjChunks][c_rows][n_occ]
+  double2 *Y2 = (double2 *)(W + L.Y2);
+  const long crow = L.c_rows;
   double2 *T = (double2 *)(W + L.T);
   double2 *ycoef = (double2 *)(W + L.ycoef);
   double2 *cp = (double2 *)(W + L.cp);
@@ -711,9 +721,11 @@ extern "C" sgw_status sternheimer_solve(sgw_ctx *ctx, const sgw_ham *h_kq, int n
       if ((s2 = tridiag(ctx, Sx, d_final, nf, ycoef, cp)) != SGW_OK) return s2;
       if ((s2 = combine(ctx, Sx, d_final, nf, ycoef, X, kavg)) != SGW_OK) return s2;
       const int nv = nf * n_omega;
-      if ((s2 = proj_dot(ctx, npw, n_occ, Sx.psi, nv, xsrc, C)) != SGW_OK) return s2;
+      if ((s2 = proj_dot(ctx, npw, n_occ, Sx.psi, nv, xsrc, C, crow)) != SGW_OK) return s2;
       if ((s2 = hx_batch(ctx, h_kq, nv, xsrc, AX, npw, T)) != SGW_OK) return s2;
-      if ((s2 = residual(ctx, Sx, d_final, nf, X, AX, C, h_kq->d_i2u, (double2 *)dpsi, info, tol, d_bad)) != SGW_OK)
+      if ((s2 = proj_apply(ctx, npw, n_occ, Sx.psi, nv, xsrc, C, crow, AX, npw, o.alpha_pv, 1)) != SGW_OK) return s2;
+      if ((s2 = residual(ctx, Sx, d_final, nf, X, AX, C, crow, h_kq->d_i2u, (double2 *)dpsi, info, tol, d_bad)) !=
+          SGW_OK)
         return s2;
       // the pinned final list is reused by the next chunk: wait for the upload
       if ((s2 = sync(ctx)) != SGW_OK) return s2;
@@ -744,8 +756,10 @@ extern "C" sgw_status sternheimer_solve(sgw_ctx *ctx, const sgw_ham *h_kq, int n
       if ((st = rhs_source(ctx, h_kq, h_k, nfill, d_fillpairs, n_pert, d_dvm, (const double2 *)psi_v, h_k->n_pw, Y,
                            npw)) != SGW_OK)
         return st;
-      if ((st = proj_dot(ctx, npw, n_occ, Sx.psi, nfill, contiguous(Y, npw), C)) != SGW_OK) return st;
-      if ((st = slot_init(ctx, Sx, nfill, Y, C, d_fill, d_fillpairs)) != SGW_OK) return st;
+      if ((st = proj_dot(ctx, npw, n_occ, Sx.psi, nfill, contiguous(Y, npw), C, crow)) != SGW_OK) return st;
+      if ((st = proj_apply(ctx, npw, n_occ, Sx.psi, nfill, contiguous(Y, npw), C, crow, Y2, npw, 1.0, 0)) != SGW_OK)
+        return st;
+      if ((st = slot_init(ctx, Sx, nfill, Y, Y2, d_fill, d_fillpairs)) != SGW_OK) return st;
       for (int i = 0; i < nfill; ++i) active.push_back(p_fill[i]);
     }
     if (!active.empty()) {
@@ -753,9 +767,10 @@ extern "C" sgw_status sternheimer_solve(sgw_ctx *ctx, const sgw_ham *h_kq, int n
       const int na = (int)active.size();
       SGW_HIP(hipMemcpyAsync(d_active, p_active, sizeof(int32_t) * na, hipMemcpyHostToDevice, ctx->stream));
       for (int step = 0; step < L.M; ++step) {
-        if ((st = proj_dot(ctx, npw, n_occ, Sx.psi, na, cur, C)) != SGW_OK) return st;
+        if ((st = proj_dot(ctx, npw, n_occ, Sx.psi, na, cur, C, crow)) != SGW_OK) return st;
         if ((st = hx_batch(ctx, h_kq, na, cur, Y, npw, T)) != SGW_OK) return st;
-        if ((st = lanczos_step(ctx, Sx, na, d_active, Y, C)) != SGW_OK) return st;
+        if ((st = proj_apply(ctx, npw, n_occ, Sx.psi, na, cur, C, crow, Y, npw, o.alpha_pv, 1)) != SGW_OK) return st;
+        if ((st = lanczos_step(ctx, Sx, na, d_active, Y)) != SGW_OK) return st;
       }
     }
     // poll

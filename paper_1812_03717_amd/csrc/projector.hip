@@ -1,0 +1,210 @@
+// Occupied-manifold projector on the FP64 matrix cores (Sec. 2.3, Eqs. 7-8).
+//
+//   overlaps:  C[a][i] = sum_g conj(psi[i][g]) x_a[g]      (n_occ x n_vec, K = n_pw)
+//   apply:     y_a[g]  = x_a[g] - sum_i psi[i][g] C[a][i]   (mode 0: 1 - P_occ)
+//              y_a[g] += alpha sum_i psi[i][g] C[a][i]     (mode 1: + alpha P_occ)
+//
+// Both are complex GEMMs done as four real 16x16x4 FP64 MFMAs per step
+// (re*re, im*im, re*im, im*re).  One wavefront owns a 16 x 16 output tile:
+// in the overlap kernel rows are occupied states and columns are vectors, in
+// the apply kernel rows are plane waves and columns are vectors.  The overlap
+// reduction over plane waves is split into chunks (one wave per chunk and
+// vector tile); consumers add the chunk partials in a fixed order, so the
+// result is deterministic.
+//
+// MFMA operand layout (v_mfma_f64_16x16x4f64, wave64): lane l supplies
+// A[l % 16][l / 16] and B[l / 16][l % 16]; it receives D[l / 16 + 4 r][l % 16]
+// in accumulator element r.
+#include "fft_lds.h"
+#include "sgw_internal.h"
+
+namespace sgw {
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ d4 mfma(double a, double b, d4 c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+
+constexpr int kOccTilesMax = 8;  // occupied tiles (of 16) held in accumulators per pass
+
+// grid: vtiles x n_chunks x occ passes, block: one wavefront
+template <int NOT>
+__global__ __launch_bounds__(64) void k_proj_dot(int npw, int n_occ, const double2 *__restrict__ psi, VecSrc x,
+                                                 int n_vec, int kc, int n_chunks, double2 *__restrict__ cp,
+                                                 long rows, int vtiles) {
+  const int lane = threadIdx.x;
+  const int col = lane & 15, kq = lane >> 4;
+  int b = blockIdx.x;
+  const int vt = b % vtiles;
+  b /= vtiles;
+  const int chunk = b % n_chunks;
+  const int pass = b / n_chunks;
+  const int occ0 = pass * NOT * 16;
+  const int a = vt * 16 + col;
+  const bool va = a < n_vec;
+  const double2 *xv = va ? x.ptr(a) : nullptr;
+  const int g0 = chunk * kc, g1 = min(npw, g0 + kc);
+  d4 re[NOT], im[NOT];
+#pragma unroll
+  for (int t = 0; t < NOT; ++t) {
+    re[t] = d4{0.0, 0.0, 0.0, 0.0};
+    im[t] = d4{0.0, 0.0, 0.0, 0.0};
+  }
+  const double2 *prow[NOT];
+  bool vrow[NOT];
+#pragma unroll
+  for (int t = 0; t < NOT; ++t) {
+    const int i = occ0 + t * 16 + col;
+    vrow[t] = i < n_occ;
+    prow[t] = psi + (long)(vrow[t] ? i : 0) * npw;
+  }
+  // software pipeline: operands of step g are loaded one step ahead
+  auto load = [&](int g, double2 &xo, double2 (&po)[NOT]) {
+    const int gg = g + kq;
+    const bool in = gg < g1;
+    xo = (va && in) ? xv[gg] : make_double2(0.0, 0.0);
+#pragma unroll
+    for (int t = 0; t < NOT; ++t) po[t] = (vrow[t] && in) ? prow[t][gg] : make_double2(0.0, 0.0);
+  };
+  double2 xc, pc[NOT];
+  load(g0, xc, pc);
+  for (int g = g0; g < g1; g += 4) {
+    double2 xn, pn[NOT];
+    load(g + 4, xn, pn);
+#pragma unroll
+    for (int t = 0; t < NOT; ++t) {
+      re[t] = mfma(pc[t].x, xc.x, re[t]);
+      im[t] = mfma(pc[t].x, xc.y, im[t]);
+      re[t] = mfma(pc[t].y, xc.y, re[t]);
+      im[t] = mfma(-pc[t].y, xc.x, im[t]);
+    }
+    xc = xn;
+#pragma unroll
+    for (int t = 0; t < NOT; ++t) pc[t] = pn[t];
+  }
+  if (!va) return;
+  double2 *out = cp + ((long)chunk * rows + a) * n_occ;
+#pragma unroll
+  for (int t = 0; t < NOT; ++t) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = occ0 + t * 16 + kq + 4 * r;
+      if (i < n_occ) out[i] = make_double2(re[t][r], im[t][r]);
+    }
+  }
+}
+
+constexpr int kApplyWaves = 4;
+constexpr int kApplyG = 256;  // plane waves per block (each wave: kApplyG / kApplyWaves / 16 tiles)
+
+// grid: vtiles x gtiles, block: kApplyWaves wavefronts; dynamic LDS: 16 * n_occ complex
+__global__ __launch_bounds__(64 * kApplyWaves) void k_proj_apply(int npw, int n_occ, const double2 *__restrict__ psi,
+                                                                VecSrc x, int n_vec, const double2 *__restrict__ cp,
+                                                                int n_chunks, long rows, double2 *__restrict__ y,
+                                                                long ldy, double alpha, int mode, int vtiles) {
+  extern __shared__ double2 cs[];  // [16][n_occ]: C of the tile's vectors, chunk partials summed
+  const int vt = blockIdx.x % vtiles;
+  const int gt = blockIdx.x / vtiles;
+  const int a0 = vt * 16;
+  for (int e = threadIdx.x; e < 16 * n_occ; e += 64 * kApplyWaves) {
+    const int v = e / n_occ, i = e - v * n_occ;
+    double2 s = make_double2(0.0, 0.0);
+    if (a0 + v < n_vec)
+      for (int c = 0; c < n_chunks; ++c) s = c_add(s, cp[((long)c * rows + a0 + v) * n_occ + i]);
+    cs[e] = s;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int col = lane & 15, kq = lane >> 4;
+  const int a = a0 + col;
+  const bool va = a < n_vec;
+  for (int sub = wave; sub < kApplyG / 16; sub += kApplyWaves) {
+    const int gb = gt * kApplyG + sub * 16;
+    if (gb >= npw) break;
+    d4 re = {0.0, 0.0, 0.0, 0.0}, im = {0.0, 0.0, 0.0, 0.0};
+    const int ga = gb + col;  // A operand row (plane wave) of this lane
+    for (int i0 = 0; i0 < n_occ; i0 += 4) {
+      const int i = i0 + kq;
+      const double2 p = (i < n_occ && ga < npw) ? psi[(long)i * npw + ga] : make_double2(0.0, 0.0);
+      const double2 c = (i < n_occ) ? cs[col * n_occ + i] : make_double2(0.0, 0.0);
+      re = mfma(p.x, c.x, re);
+      im = mfma(p.x, c.y, im);
+      re = mfma(-p.y, c.y, re);
+      im = mfma(p.y, c.x, im);
+    }
+    if (!va) continue;
+    const double2 *xa = mode == 0 ? x.ptr(a) : nullptr;
+    double2 *ya = y + (long)a * ldy;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int g = gb + kq + 4 * r;
+      if (g < npw) {
+        if (mode == 0) {
+          const double2 xg = xa[g];
+          ya[g] = make_double2(xg.x - re[r], xg.y - im[r]);
+        } else {
+          const double2 yg = ya[g];
+          ya[g] = make_double2(fma(alpha, re[r], yg.x), fma(alpha, im[r], yg.y));
+        }
+      }
+    }
+  }
+}
+
+}  // namespace
+
+int proj_chunks(int npw, int *kc) {
+  int n = (npw + 255) / 256;
+  n = n < 1 ? 1 : (n > kProjChunks ? kProjChunks : n);
+  int k = (npw + n - 1) / n;
+  k = (k + 3) / 4 * 4;
+  *kc = k;
+  return (npw + k - 1) / k;
+}
+
+sgw_status proj_dot(sgw_ctx *ctx, int npw, int n_occ, const double2 *psi, int n_vec, VecSrc x, double2 *cp,
+                    long rows) {
+  if (n_vec <= 0 || n_occ <= 0) return SGW_OK;
+  int kc;
+  const int nch = proj_chunks(npw, &kc);
+  const int vtiles = (n_vec + 15) / 16;
+  const int otiles = (n_occ + 15) / 16;
+  int not_ = 1;
+  while (not_ < otiles && not_ < kOccTilesMax) not_ *= 2;
+  const int passes = (otiles + not_ - 1) / not_;
+  PendingTiming tm;
+  timing_begin(ctx, K_PROJ_DOT, n_vec * (npw * 16.0) + (double)n_occ * npw * 16.0, 8.0 * n_vec * npw * n_occ, &tm);
+  const dim3 grid((long)vtiles * nch * passes), block(64);
+  switch (not_) {
+    case 1: hipLaunchKernelGGL(k_proj_dot<1>, grid, block, 0, ctx->stream, npw, n_occ, psi, x, n_vec, kc, nch, cp, rows, vtiles); break;
+    case 2: hipLaunchKernelGGL(k_proj_dot<2>, grid, block, 0, ctx->stream, npw, n_occ, psi, x, n_vec, kc, nch, cp, rows, vtiles); break;
+    case 4: hipLaunchKernelGGL(k_proj_dot<4>, grid, block, 0, ctx->stream, npw, n_occ, psi, x, n_vec, kc, nch, cp, rows, vtiles); break;
+    default: hipLaunchKernelGGL(k_proj_dot<8>, grid, block, 0, ctx->stream, npw, n_occ, psi, x, n_vec, kc, nch, cp, rows, vtiles); break;
+  }
+  timing_end(ctx, &tm);
+  SGW_HIP(hipGetLastError());
+  return SGW_OK;
+}
+
+sgw_status proj_apply(sgw_ctx *ctx, int npw, int n_occ, const double2 *psi, int n_vec, VecSrc x, const double2 *cp,
+                      long rows, double2 *y, long ldy, double alpha, int mode) {
+  if (n_vec <= 0) return SGW_OK;
+  if (n_occ <= 0) {
+    if (mode == 1) return SGW_OK;
+    // y = x: nothing to subtract
+    return permute_copy(ctx, npw, n_vec, x, y, ldy);
+  }
+  int kc;
+  const int nch = proj_chunks(npw, &kc);
+  const int vtiles = (n_vec + 15) / 16;
+  const int gtiles = (npw + kApplyG - 1) / kApplyG;
+  PendingTiming tm;
+  timing_begin(ctx, K_PROJ_APPLY, n_vec * (npw * 32.0) + (double)n_occ * npw * 16.0, 8.0 * n_vec * npw * n_occ, &tm);
+  hipLaunchKernelGGL(k_proj_apply, dim3((long)vtiles * gtiles), dim3(64 * kApplyWaves), sizeof(double2) * 16 * n_occ,
+                     ctx->stream, npw, n_occ, psi, x, n_vec, cp, nch, rows, y, ldy, alpha, mode, vtiles);
+  timing_end(ctx, &tm);
+  SGW_HIP(hipGetLastError());
+  return SGW_OK;
+}
+
+}  // namespace sgw

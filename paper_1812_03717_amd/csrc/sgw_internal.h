@@ -91,7 +91,7 @@ struct sgw_ham {
   int32_t *d_i2u = nullptr;         // [n_pw] internal -> caller index
   int32_t *d_u2i = nullptr;         // [n_pw] caller -> internal index
   int32_t *d_stick_off = nullptr;   // [n_stick + 1]
-  int32_t *d_stick_xy = nullptr;    // [n_stick] i0 * N1 + i1
+  int32_t *d_stick_at = nullptr;    // [N0 * N1] stick index at (i0, i1), or -1
   int32_t *d_pw_stick = nullptr;    // [n_pw] internal -> stick
   int32_t *d_pw_z = nullptr;        // [n_pw] internal -> i2
   int32_t *d_miller_int = nullptr;  // [n_pw][3] internal order
@@ -132,13 +132,21 @@ sgw_status hx_batch(sgw_ctx *ctx, const sgw_ham *h, int n_vec, VecSrc x, double2
                     double2 *tbuf);
 bool hx_grid_supported(int n);
 
-// Projector pieces (internal order).
-// c[a][i] = sum_g conj(psi[i][g]) x_a[g]
+// Projector pieces (internal order, FP64 MFMA).  The overlaps are produced as
+// partial sums over plane-wave chunks: cp[chunk][a][i] for chunk < n_chunks,
+// a < n_vec (leading dimension `rows` >= n_vec), i < n_occ.
+constexpr int kProjChunks = 16;
+// number of chunks for n_pw plane waves; *kc receives the chunk length
+int proj_chunks(int n_pw, int *kc);
+// cp[chunk][a][i] = sum_{g in chunk} conj(psi[i][g]) x_a[g]
 sgw_status proj_dot(sgw_ctx *ctx, int n_pw, int n_occ, const double2 *psi, int n_vec, VecSrc x,
-                    double2 *c);
-// mode 0: y_a = x_a - psi^T c_a ; mode 1: y_a += alpha psi^T c_a
+                    double2 *cp, long rows);
+// with c = sum over chunks of cp:  mode 0: y_a = x_a - psi^T c_a ; mode 1: y_a += alpha psi^T c_a
+// (mode 0 may run in place, y_a == x_a)
 sgw_status proj_apply(sgw_ctx *ctx, int n_pw, int n_occ, const double2 *psi, int n_vec, VecSrc x,
-                      const double2 *c, double2 *y, long ldy, double alpha, int mode);
+                      const double2 *cp, long rows, double2 *y, long ldy, double alpha, int mode);
+// y_a = x_a
+sgw_status permute_copy(sgw_ctx *ctx, int n_pw, int n_vec, VecSrc x, double2 *y, long ldy);
 // out[a][g] = in[a][perm[g]] (gather) or out[a][perm[g]] = in[a][g] (scatter)
 sgw_status permute(sgw_ctx *ctx, int n_pw, int n_vec, const double2 *in, long ldin, double2 *out,
                    long ldout, const int32_t *perm, int scatter, double scale = 1.0);

@@ -67,56 +67,11 @@ __global__ void k_permute(int npw, int n_vec, const double2 *__restrict__ in, lo
   else out[(long)a * ldout + g] = c_scale(in[(long)a * ldin + perm[g]], scale);
 }
 
-// ---------------------------------------------------------------------------
-// c[a][i] = sum_g conj(psi[i][g]) x_a[g]   (occupied-state overlaps, Eqs. 7-8)
-// ---------------------------------------------------------------------------
-constexpr int kDotThreads = 256;
-constexpr int kDotOcc = 8;
-
-__global__ __launch_bounds__(kDotThreads) void k_proj_dot(int npw, int n_occ, const double2 *__restrict__ psi,
-                                                          VecSrc x, double2 *__restrict__ c, int oblocks) {
-  __shared__ double sh[(kDotThreads / 64) * 2 * kDotOcc];
-  const int a = blockIdx.x / oblocks;
-  const int i0 = (blockIdx.x - a * oblocks) * kDotOcc;
-  const int no = min(kDotOcc, n_occ - i0);
-  const double2 *xv = x.ptr(a);
-  double acc[2 * kDotOcc];
-#pragma unroll
-  for (int o = 0; o < 2 * kDotOcc; ++o) acc[o] = 0.0;
-  for (int g = threadIdx.x; g < npw; g += kDotThreads) {
-    const double2 xg = xv[g];
-#pragma unroll
-    for (int o = 0; o < kDotOcc; ++o) {
-      if (o < no) {
-        const double2 p = psi[(long)(i0 + o) * npw + g];
-        acc[2 * o] = fma(p.x, xg.x, fma(p.y, xg.y, acc[2 * o]));
-        acc[2 * o + 1] = fma(p.x, xg.y, fma(-p.y, xg.x, acc[2 * o + 1]));
-      }
-    }
-  }
-  double tot[2 * kDotOcc];
-  block_sum_n<kDotThreads, 2 * kDotOcc>(acc, sh, tot);
-  if (threadIdx.x < no) {
-    const int o = threadIdx.x;
-    c[(long)a * n_occ + i0 + o] = make_double2(tot[2 * o], tot[2 * o + 1]);
-  }
-}
-
-// mode 0: y = x - psi^T c ; mode 1: y += alpha psi^T c
-__global__ void k_proj_apply(int npw, int n_occ, const double2 *__restrict__ psi, VecSrc x,
-                             const double2 *__restrict__ c, double2 *__restrict__ y, long ldy, double alpha,
-                             int mode, int tiles) {
-  extern __shared__ double2 cs[];
+// y_a = x_a
+__global__ void k_copy(int npw, VecSrc x, double2 *__restrict__ y, long ldy, int tiles) {
   const int a = blockIdx.x / tiles;
   const int g = (blockIdx.x - a * tiles) * blockDim.x + threadIdx.x;
-  for (int i = threadIdx.x; i < n_occ; i += blockDim.x) cs[i] = c[(long)a * n_occ + i];
-  __syncthreads();
-  if (g >= npw) return;
-  double2 s = make_double2(0.0, 0.0);
-  for (int i = 0; i < n_occ; ++i) s = c_add(s, c_mul(psi[(long)i * npw + g], cs[i]));
-  double2 *yp = y + (long)a * ldy + g;
-  if (mode == 0) *yp = c_sub(x.ptr(a)[g], s);
-  else *yp = c_add(*yp, c_scale(s, alpha));
+  if (g < npw) y[(long)a * ldy + g] = x.ptr(a)[g];
 }
 
 // ---------------------------------------------------------------------------
@@ -143,28 +98,25 @@ __global__ void k_rhs_source(int npw, const int32_t *__restrict__ miller_int, co
 }
 
 // ---------------------------------------------------------------------------
-// slot initialisation: b = -(s - psi^T c), v_0 = b / ||b||
+// slot initialisation: b = -(1 - P_occ) s, v_0 = b / ||b||
 // ---------------------------------------------------------------------------
 constexpr int kRowThreads = 256;
 
 __global__ __launch_bounds__(kRowThreads) void k_init(SolverState S, const double2 *__restrict__ src,
-                                                      const double2 *__restrict__ c,
+                                                      const double2 *__restrict__ proj,
                                                       const int32_t *__restrict__ fill_slots,
                                                       const int32_t *__restrict__ fill_pairs) {
   __shared__ double sh[kRowThreads / 64];
-  extern __shared__ double2 cs[];
   const int a = blockIdx.x;
   const int slot = fill_slots[a], pair = fill_pairs[a];
-  for (int i = threadIdx.x; i < S.n_occ; i += kRowThreads) cs[i] = c[(long)a * S.n_occ + i];
-  __syncthreads();
-  const double2 *sv = src + (long)a * S.npw;
+  const double2 *sv = src + (long)a * S.npw;   // s
+  const double2 *pv = proj + (long)a * S.npw;  // (1 - P_occ) s
   double2 *bv = S.bvec + (long)slot * S.npw;
   double acc = 0.0, accs = 0.0;
   for (int g = threadIdx.x; g < S.npw; g += kRowThreads) {
-    double2 pc = make_double2(0.0, 0.0);
-    for (int i = 0; i < S.n_occ; ++i) pc = c_add(pc, c_mul(S.psi[(long)i * S.npw + g], cs[i]));
     const double2 sg = sv[g];
-    const double2 b = c_sub(pc, sg);
+    const double2 pg = pv[g];
+    const double2 b = make_double2(-pg.x, -pg.y);
     bv[g] = b;
     acc += b.x * b.x + b.y * b.y;
     accs += sg.x * sg.x + sg.y * sg.y;
@@ -201,16 +153,15 @@ __global__ __launch_bounds__(kRowThreads) void k_init(SolverState S, const doubl
 // ---------------------------------------------------------------------------
 // one Lanczos step of the seed operator plus the shift recurrences
 //   w = A0 v_k - beta_k v_{k-1};  a_k = <v_k, w>;  w -= a_k v_k;  beta_{k+1} = ||w||
-//   A0 v_k = (H v_k) - eps_v v_k + alpha psi^T (psi^* v_k)
+//   A0 v_k = Y - eps_v v_k, where Y = H v_k + alpha P_occ v_k has been formed
+//   by the H.x and projector kernels
 // ---------------------------------------------------------------------------
 constexpr int kLzThreads = 512;
 
 template <int EPT>
 __global__ __launch_bounds__(kLzThreads) void k_lanczos(SolverState S, const int32_t *__restrict__ list,
-                                                        const double2 *__restrict__ Y,
-                                                        const double2 *__restrict__ C) {
+                                                        const double2 *__restrict__ Y) {
   __shared__ double sh[kLzThreads / 64];
-  __shared__ double2 cs[kMaxOcc];
   __shared__ int all_conv;
   const int a = blockIdx.x;
   const int slot = list[a];
@@ -223,7 +174,6 @@ __global__ __launch_bounds__(kLzThreads) void k_lanczos(SolverState S, const int
   const double2 *y = Y + (long)a * npw;
   const double eps = S.eps[slot];
   const double bk = k > 0 ? S.beta[(long)slot * (S.kmax + 1) + k] : 0.0;
-  for (int i = threadIdx.x; i < S.n_occ; i += kLzThreads) cs[i] = C[(long)a * S.n_occ + i];
   if (threadIdx.x == 0) all_conv = 1;
   __syncthreads();
   double2 w[EPT];
@@ -233,11 +183,9 @@ __global__ __launch_bounds__(kLzThreads) void k_lanczos(SolverState S, const int
     const int g = threadIdx.x + e * kLzThreads;
     if (g < npw) {
       const double2 vg = v[g];
-      double2 pc = make_double2(0.0, 0.0);
-      for (int i = 0; i < S.n_occ; ++i) pc = c_add(pc, c_mul(S.psi[(long)i * npw + g], cs[i]));
       double2 t = y[g];
-      t.x = fma(-eps, vg.x, fma(S.alpha, pc.x, t.x));
-      t.y = fma(-eps, vg.y, fma(S.alpha, pc.y, t.y));
+      t.x = fma(-eps, vg.x, t.x);
+      t.y = fma(-eps, vg.y, t.y);
       if (k > 0) {
         const double2 pg = vp[g];
         t.x = fma(-bk, pg.x, t.x);
@@ -402,44 +350,44 @@ __global__ __launch_bounds__(kCmbThreads) void k_combine(SolverState S, const in
 __global__ __launch_bounds__(kRowThreads) void k_residual(SolverState S, const int32_t *__restrict__ flist,
                                                           const double2 *__restrict__ X,
                                                           const double2 *__restrict__ AX,
-                                                          const double2 *__restrict__ C,
-                                                          const int32_t *__restrict__ i2u,
+                                                          const double2 *__restrict__ cp, int n_chunks,
+                                                          long rows, const int32_t *__restrict__ i2u,
                                                           double2 *__restrict__ dpsi,
                                                           sgw_solve_info *__restrict__ info, double tol,
                                                           int *__restrict__ n_bad) {
   __shared__ double sh[(kRowThreads / 64) * 3];
-  __shared__ double2 cs[kMaxOcc];
   const int fj = blockIdx.x;
   const int f = fj / S.n_omega, j = fj - f * S.n_omega;
   const int slot = flist[f];
   const int pair = S.pair[slot];
   const int npw = S.npw;
   const double2 *x = X + (long)fj * npw;
-  const double2 *ax = AX + (long)fj * npw;
+  const double2 *ax = AX + (long)fj * npw;  // H x + alpha P_occ x
   const double2 *b = S.bvec + (long)slot * npw;
-  for (int i = threadIdx.x; i < S.n_occ; i += kRowThreads) cs[i] = C[(long)fj * S.n_occ + i];
-  __syncthreads();
   const double eps = S.eps[slot];
   const double zr = S.omega[j], zi = S.eta;
   double2 *out = dpsi + ((long)pair * S.n_omega + j) * npw;
   double acc[3] = {0.0, 0.0, 0.0};
   for (int g = threadIdx.x; g < npw; g += kRowThreads) {
-    double2 pc = make_double2(0.0, 0.0);
-    for (int i = 0; i < S.n_occ; ++i) pc = c_add(pc, c_mul(S.psi[(long)i * npw + g], cs[i]));
     const double2 xg = x[g];
     const double2 ag = ax[g];
-    // (A0 - z) x = Hx + alpha P x - (eps + z) x
+    // (A0 - z) x = (H + alpha P_occ) x - (eps + z) x
     const double er = eps + zr;
     double2 ox;
-    ox.x = ag.x + S.alpha * pc.x - (er * xg.x - zi * xg.y);
-    ox.y = ag.y + S.alpha * pc.y - (er * xg.y + zi * xg.x);
+    ox.x = ag.x - (er * xg.x - zi * xg.y);
+    ox.y = ag.y - (er * xg.y + zi * xg.x);
     const double2 r = c_sub(b[g], ox);
     acc[0] = fma(r.x, r.x, fma(r.y, r.y, acc[0]));
     acc[1] = fma(xg.x, xg.x, fma(xg.y, xg.y, acc[1]));
     out[i2u[g]] = xg;
   }
+  // ||psi^* x||^2 from the chunk partials of the overlaps
   double cc = 0.0;
-  for (int i = threadIdx.x; i < S.n_occ; i += kRowThreads) cc += cs[i].x * cs[i].x + cs[i].y * cs[i].y;
+  for (int i = threadIdx.x; i < S.n_occ; i += kRowThreads) {
+    double2 c = make_double2(0.0, 0.0);
+    for (int ch = 0; ch < n_chunks; ++ch) c = c_add(c, cp[((long)ch * rows + fj) * S.n_occ + i]);
+    cc += c.x * c.x + c.y * c.y;
+  }
   acc[2] = cc;
   double tot[3];
   block_sum_n<kRowThreads, 3>(acc, sh, tot);
@@ -494,28 +442,10 @@ sgw_status permute(sgw_ctx *ctx, int npw, int n_vec, const double2 *in, long ldi
   return SGW_OK;
 }
 
-sgw_status proj_dot(sgw_ctx *ctx, int npw, int n_occ, const double2 *psi, int n_vec, VecSrc x, double2 *c) {
-  if (n_vec <= 0 || n_occ <= 0) return SGW_OK;
-  const int ob = (n_occ + kDotOcc - 1) / kDotOcc;
-  PendingTiming tm;
-  timing_begin(ctx, K_PROJ_DOT, n_vec * (npw * 16.0) + (double)n_occ * npw * 16.0, 8.0 * n_vec * npw * n_occ,
-               &tm);
-  hipLaunchKernelGGL(k_proj_dot, dim3((long)ob * n_vec), dim3(kDotThreads), 0, ctx->stream, npw, n_occ, psi, x, c,
-                     ob);
-  timing_end(ctx, &tm);
-  SGW_HIP(hipGetLastError());
-  return SGW_OK;
-}
-
-sgw_status proj_apply(sgw_ctx *ctx, int npw, int n_occ, const double2 *psi, int n_vec, VecSrc x, const double2 *c,
-                      double2 *y, long ldy, double alpha, int mode) {
+sgw_status permute_copy(sgw_ctx *ctx, int npw, int n_vec, VecSrc x, double2 *y, long ldy) {
   if (n_vec <= 0) return SGW_OK;
   const int tiles = (npw + 255) / 256;
-  PendingTiming tm;
-  timing_begin(ctx, K_PROJ_APPLY, n_vec * (npw * 32.0), 8.0 * n_vec * npw * n_occ, &tm);
-  hipLaunchKernelGGL(k_proj_apply, dim3((long)tiles * n_vec), dim3(256), sizeof(double2) * (n_occ > 0 ? n_occ : 1),
-                     ctx->stream, npw, n_occ, psi, x, c, y, ldy, alpha, mode, tiles);
-  timing_end(ctx, &tm);
+  hipLaunchKernelGGL(k_copy, dim3((long)tiles * n_vec), dim3(256), 0, ctx->stream, npw, x, y, ldy, tiles);
   SGW_HIP(hipGetLastError());
   return SGW_OK;
 }
@@ -536,13 +466,12 @@ sgw_status rhs_source(sgw_ctx *ctx, const sgw_ham *h_kq, const sgw_ham *h_k, int
   return SGW_OK;
 }
 
-sgw_status slot_init(sgw_ctx *ctx, const SolverState &S, int n_fill, const double2 *src, const double2 *c,
+sgw_status slot_init(sgw_ctx *ctx, const SolverState &S, int n_fill, const double2 *src, const double2 *proj,
                      const int32_t *fill_slots, const int32_t *fill_pairs) {
   if (n_fill <= 0) return SGW_OK;
   PendingTiming tm;
-  timing_begin(ctx, K_INIT, n_fill * (S.npw * 48.0), 8.0 * n_fill * S.npw * S.n_occ, &tm);
-  hipLaunchKernelGGL(k_init, dim3(n_fill), dim3(kRowThreads), sizeof(double2) * (S.n_occ > 0 ? S.n_occ : 1),
-                     ctx->stream, S, src, c, fill_slots, fill_pairs);
+  timing_begin(ctx, K_INIT, n_fill * (S.npw * 64.0), 0.0, &tm);
+  hipLaunchKernelGGL(k_init, dim3(n_fill), dim3(kRowThreads), 0, ctx->stream, S, src, proj, fill_slots, fill_pairs);
   timing_end(ctx, &tm);
   SGW_HIP(hipGetLastError());
   return SGW_OK;
@@ -554,16 +483,15 @@ int lanczos_ept(int npw) {
   return e;
 }
 
-sgw_status lanczos_step(sgw_ctx *ctx, const SolverState &S, int n_active, const int32_t *list, const double2 *Y,
-                        const double2 *C) {
+sgw_status lanczos_step(sgw_ctx *ctx, const SolverState &S, int n_active, const int32_t *list, const double2 *Y) {
   if (n_active <= 0) return SGW_OK;
   PendingTiming tm;
-  timing_begin(ctx, K_LANCZOS, n_active * (S.npw * 16.0 * 5), 8.0 * n_active * S.npw * S.n_occ, &tm);
+  timing_begin(ctx, K_LANCZOS, n_active * (S.npw * 16.0 * 4), 0.0, &tm);
   const int ept = lanczos_ept(S.npw);
   switch (ept) {
 #define SGW_LZ(E)                                                                                      \
   case E:                                                                                              \
-    hipLaunchKernelGGL(k_lanczos<E>, dim3(n_active), dim3(kLzThreads), 0, ctx->stream, S, list, Y, C); \
+    hipLaunchKernelGGL(k_lanczos<E>, dim3(n_active), dim3(kLzThreads), 0, ctx->stream, S, list, Y);    \
     break;
     SGW_LZ(1) SGW_LZ(2) SGW_LZ(4) SGW_LZ(8) SGW_LZ(16) SGW_LZ(32)
 #undef SGW_LZ
@@ -602,14 +530,15 @@ sgw_status combine(sgw_ctx *ctx, const SolverState &S, const int32_t *flist, int
 }
 
 sgw_status residual(sgw_ctx *ctx, const SolverState &S, const int32_t *flist, int nf, const double2 *X,
-                    const double2 *AX, const double2 *C, const int32_t *i2u, double2 *dpsi, sgw_solve_info *info,
-                    double tol, int *n_bad) {
+                    const double2 *AX, const double2 *cp, long rows, const int32_t *i2u, double2 *dpsi,
+                    sgw_solve_info *info, double tol, int *n_bad) {
   if (nf <= 0) return SGW_OK;
+  int kc;
+  const int nch = proj_chunks(S.npw, &kc);
   PendingTiming tm;
-  timing_begin(ctx, K_RESIDUAL, (double)nf * S.n_omega * S.npw * 16.0 * 4, 8.0 * nf * S.n_omega * S.npw * S.n_occ,
-               &tm);
-  hipLaunchKernelGGL(k_residual, dim3((long)nf * S.n_omega), dim3(kRowThreads), 0, ctx->stream, S, flist, X, AX, C,
-                     i2u, dpsi, info, tol, n_bad);
+  timing_begin(ctx, K_RESIDUAL, (double)nf * S.n_omega * S.npw * 16.0 * 4, 0.0, &tm);
+  hipLaunchKernelGGL(k_residual, dim3((long)nf * S.n_omega), dim3(kRowThreads), 0, ctx->stream, S, flist, X, AX, cp,
+                     nch, rows, i2u, dpsi, info, tol, n_bad);
   timing_end(ctx, &tm);
   SGW_HIP(hipGetLastError());
   return SGW_OK;

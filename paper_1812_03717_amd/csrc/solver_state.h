@@ -46,16 +46,18 @@ struct SolverState {
 
 sgw_status rhs_source(sgw_ctx *ctx, const sgw_ham *h_kq, const sgw_ham *h_k, int n_vec, const int32_t *pairs,
                       int n_pert, const int32_t *dvm, const double2 *psi_v, long ld_psi, double2 *s, long lds);
-sgw_status slot_init(sgw_ctx *ctx, const SolverState &S, int n_fill, const double2 *src, const double2 *c,
+// b = -proj (proj = (1 - P_occ) src), ||src|| for the zero test, v_0 = b / ||b||
+sgw_status slot_init(sgw_ctx *ctx, const SolverState &S, int n_fill, const double2 *src, const double2 *proj,
                      const int32_t *fill_slots, const int32_t *fill_pairs);
-sgw_status lanczos_step(sgw_ctx *ctx, const SolverState &S, int n_active, const int32_t *list, const double2 *Y,
-                        const double2 *C);
+// Y[a] must hold (H + alpha P_occ) v_k of slot list[a]
+sgw_status lanczos_step(sgw_ctx *ctx, const SolverState &S, int n_active, const int32_t *list, const double2 *Y);
 sgw_status tridiag(sgw_ctx *ctx, const SolverState &S, const int32_t *flist, int nf, double2 *ycoef, double2 *cp);
 sgw_status combine(sgw_ctx *ctx, const SolverState &S, const int32_t *flist, int nf, const double2 *ycoef,
                    double2 *X, double est_kavg);
+// AX must hold (H + alpha P_occ) X; cp the overlap partials of X (leading dimension rows)
 sgw_status residual(sgw_ctx *ctx, const SolverState &S, const int32_t *flist, int nf, const double2 *X,
-                    const double2 *AX, const double2 *C, const int32_t *i2u, double2 *dpsi, sgw_solve_info *info,
-                    double tol, int *n_bad);
+                    const double2 *AX, const double2 *cp, long rows, const int32_t *i2u, double2 *dpsi,
+                    sgw_solve_info *info, double tol, int *n_bad);
 sgw_status transpose_potential(sgw_ctx *ctx, const double *v, double *vt, const int n[3]);
 int lanczos_ept(int npw);
 
