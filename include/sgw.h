@@ -156,7 +156,8 @@ typedef struct {
   int32_t precision;        /* SGW_FP64 (only mode of this build) */
   int32_t max_iter;         /* Krylov dimension limit per (v,p); <= 0 -> 600 */
   double alpha_pv;          /* coefficient of P_occ in the operator, Ha; <= 0 -> 1.0 */
-  double tol_safety;        /* the recurrence stops at tol*tol_safety; <= 0 -> 0.1 */
+  double tol_safety;        /* the recurrence stops when every shift's estimated residual
+                               is below tol*tol_safety; <= 0 -> 0.5 */
   int32_t slots;            /* (v,p) pairs iterated concurrently; <= 0 -> automatic */
   int32_t finalize_batch;   /* pairs per finalisation batch; <= 0 -> automatic */
   int32_t steps_per_sync;   /* Krylov steps between host polls; <= 0 -> 8 */

@@ -200,7 +200,7 @@ static sgw_status upload(sgw_ctx *ctx, T **dst, const std::vector<T> &src) {
 
 static void ham_free(sgw_ham *h) {
   if (!h) return;
-  void *ptrs[] = {h->d_i2u, h->d_u2i, h->d_stick_off, h->d_stick_at, h->d_pw_stick, h->d_pw_z,
+  void *ptrs[] = {h->d_i2u, h->d_u2i, h->d_stick_off, h->d_rows, h->d_pw_stick, h->d_pw_z,
                   h->d_miller_int, h->d_kin, h->d_vt, h->d_box, h->d_tw};
   for (void *p : ptrs)
     if (p) hipFree(p);
@@ -261,7 +261,9 @@ extern "C" sgw_status sgw_ham_create(sgw_ctx *ctx, const sgw_ham_desc *d, sgw_ha
     return ma[2] < mb[2];
   });
   std::vector<int32_t> i2u(npw), u2i(npw), pw_stick(npw), pw_z(npw), miller_int(3 * npw), stick_off;
-  std::vector<int32_t> stick_at((size_t)n[0] * n[1], -1);
+  // per row m0 = mmin[0] + t: first stick and the m1 range (one contiguous run)
+  std::vector<int4> rows(mmax[0] - mmin[0] + 1, make_int4(0, 1, 0, 0));
+  std::vector<char> row_seen(rows.size(), 0);
   std::vector<double> kin(npw);
   int ns = 0;
   for (int gi = 0; gi < npw; ++gi) {
@@ -269,7 +271,16 @@ extern "C" sgw_status sgw_ham_create(sgw_ctx *ctx, const sgw_ham_desc *d, sgw_ha
     const int *m = d->miller + 3 * u;
     if (gi == 0 || m[0] != d->miller[3 * order[gi - 1]] || m[1] != d->miller[3 * order[gi - 1] + 1]) {
       stick_off.push_back(gi);
-      stick_at[(size_t)imod(m[0], n[0]) * n[1] + imod(m[1], n[1])] = ns;
+      int4 &r = rows[m[0] - mmin[0]];
+      if (!row_seen[m[0] - mmin[0]]) {
+        row_seen[m[0] - mmin[0]] = 1;
+        r = make_int4(ns, m[1], m[1], 0);
+      } else if (m[1] != r.z + 1) {
+        return fail(SGW_ERR_UNSUPPORTED, "sgw_ham_create: the sticks of row m0 = " + std::to_string(m[0]) +
+                                             " do not form one contiguous m1 range (basis not sphere-like)");
+      } else {
+        r.z = m[1];
+      }
       ++ns;
     }
     i2u[gi] = u;
@@ -320,7 +331,7 @@ extern "C" sgw_status sgw_ham_create(sgw_ctx *ctx, const sgw_ham_desc *d, sgw_ha
   SGW_UP(h->d_i2u, i2u);
   SGW_UP(h->d_u2i, u2i);
   SGW_UP(h->d_stick_off, stick_off);
-  SGW_UP(h->d_stick_at, stick_at);
+  SGW_UP(h->d_rows, rows);
   SGW_UP(h->d_pw_stick, pw_stick);
   SGW_UP(h->d_pw_z, pw_z);
   SGW_UP(h->d_miller_int, miller_int);
@@ -486,7 +497,7 @@ extern "C" sgw_status sgw_opts_default(sgw_opts *o) {
   o->precision = SGW_FP64;
   o->max_iter = 600;
   o->alpha_pv = 1.0;
-  o->tol_safety = 0.1;
+  o->tol_safety = 0.5;
   o->slots = 0;
   o->finalize_batch = 0;
   o->steps_per_sync = 8;

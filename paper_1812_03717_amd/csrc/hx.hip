@@ -14,6 +14,7 @@
 // full plane lives in LDS.
 #include "fft_lds.h"
 #include "fft_reg.h"
+#include "planes.h"
 #include "sgw_internal.h"
 
 namespace sgw {
@@ -103,171 +104,6 @@ __global__ __launch_bounds__(kStickThreads) void k_sticks_fwd(const double2 *__r
   }
 }
 
-template <int N0, int N1> constexpr int plane_threads() { return N0 * N1 <= 48 * 48 ? 256 : 512; }
-
-// One (vector, i2) plane: 2D inverse FFT of the stick values, multiplication by
-// V(r), 2D forward FFT, back to the stick values.  Every 1D transform is split
-// N = A * B into two register stages (fft_reg.h) with one LDS exchange; along
-// axis 0 the inverse's second stage, the potential and the forward's first
-// stage run on the same registers.  Rows (fixed i0) that hold no stick are
-// zero before the axis-0 transform and not needed after it, so they are never
-// stored.  LD = N1 + 1 keeps row-strided and column-strided accesses free of
-// LDS bank conflicts.
-template <int N0, int N1>
-__global__ __launch_bounds__((plane_threads<N0, N1>())) void k_planes(double2 *__restrict__ T, int n2,
-                                                                   int n_stick,
-                                                                   const int32_t *__restrict__ stick_at,
-                                                                   int m0_lo, int n_row,
-                                                                   const double *__restrict__ vt,
-                                                                   const double2 *__restrict__ tw0g,
-                                                                   const double2 *__restrict__ tw1g) {
-  constexpr int NT = plane_threads<N0, N1>();
-  constexpr int LD = N1 + 1;
-  constexpr int A0 = Split<N0>::a, B0 = Split<N0>::b;
-  constexpr int A1 = Split<N1>::a, B1 = Split<N1>::b;
-  constexpr int MT = (N1 * B0 + NT - 1) / NT;  // column tasks held per thread
-  __shared__ double2 plane[N0 * LD];
-  __shared__ double2 tw0[N0];
-  __shared__ double2 tw1[N1];
-  const int tid = threadIdx.x;
-  const int vec = blockIdx.x / n2;
-  const int z = blockIdx.x - vec * n2;
-  double2 *Tz = T + ((long)vec * n2 + z) * n_stick;
-  for (int i = tid; i < N0; i += NT) tw0[i] = tw0g[i];
-  for (int i = tid; i < N1; i += NT) tw1[i] = tw1g[i];
-  __syncthreads();
-  auto row_i0 = [&](int t) {
-    int i0 = m0_lo + t;
-    return i0 < 0 ? i0 + N0 : i0;
-  };
-  auto has_sticks = [&](int i0) {
-    int t = i0 - m0_lo;
-    t = t < 0 ? t + N0 : (t >= N0 ? t - N0 : t);
-    return t < n_row;
-  };
-
-  // ---- axis 1, inverse, rows holding sticks (thread-consecutive rows) ----
-  for (int task = tid; task < n_row * B1; task += NT) {
-    const int t = task % n_row, b = task / n_row;
-    const int i0 = row_i0(t);
-    double2 v[A1];
-#pragma unroll
-    for (int a = 0; a < A1; ++a) {
-      const int s = stick_at[i0 * N1 + B1 * a + b];
-      v[a] = s >= 0 ? Tz[s] : make_double2(0.0, 0.0);
-    }
-    RegDft<A1, +1>::run(v);
-#pragma unroll
-    for (int ka = 0; ka < A1; ++ka) plane[i0 * LD + b * A1 + ka] = (b * ka) ? twiddle<+1>(v[ka], tw1, b * ka) : v[ka];
-  }
-  __syncthreads();
-  for (int task = tid; task < n_row * A1; task += NT) {
-    const int t = task % n_row, ka = task / n_row;
-    const int i0 = row_i0(t);
-    double2 v[B1];
-#pragma unroll
-    for (int b = 0; b < B1; ++b) v[b] = plane[i0 * LD + b * A1 + ka];
-    RegDft<B1, +1>::run(v);
-#pragma unroll
-    for (int kb = 0; kb < B1; ++kb) plane[i0 * LD + ka + A1 * kb] = v[kb];
-  }
-  __syncthreads();
-
-  // ---- axis 0, inverse stage 1 (thread-consecutive columns) ----
-  double2 h[MT][A0];
-#pragma unroll
-  for (int m = 0; m < MT; ++m) {
-    const int task = tid + m * NT;
-    if (task < N1 * B0) {
-      const int i1 = task % N1, b = task / N1;
-#pragma unroll
-      for (int a = 0; a < A0; ++a) {
-        const int i0 = B0 * a + b;
-        h[m][a] = has_sticks(i0) ? plane[i0 * LD + i1] : make_double2(0.0, 0.0);
-      }
-    }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int m = 0; m < MT; ++m) {
-    const int task = tid + m * NT;
-    if (task < N1 * B0) {
-      const int i1 = task % N1, b = task / N1;
-      RegDft<A0, +1>::run(h[m]);
-#pragma unroll
-      for (int ka = 0; ka < A0; ++ka)
-        plane[(b * A0 + ka) * LD + i1] = (b * ka) ? twiddle<+1>(h[m][ka], tw0, b * ka) : h[m][ka];
-    }
-  }
-  __syncthreads();
-  // ---- axis 0: inverse stage 2, times V(r), forward stage 1 ----
-  const double *vz = vt + (long)z * N0 * N1;
-  for (int task = tid; task < N1 * A0; task += NT) {
-    const int i1 = task % N1, ka = task / N1;
-    double2 v[B0];
-#pragma unroll
-    for (int b = 0; b < B0; ++b) v[b] = plane[(b * A0 + ka) * LD + i1];
-    RegDft<B0, +1>::run(v);
-#pragma unroll
-    for (int kb = 0; kb < B0; ++kb) v[kb] = c_scale(v[kb], vz[(ka + A0 * kb) * N1 + i1]);
-    RegDft<B0, -1>::run(v);
-#pragma unroll
-    for (int e = 0; e < B0; ++e) plane[(e * A0 + ka) * LD + i1] = (ka * e) ? twiddle<-1>(v[e], tw0, ka * e) : v[e];
-  }
-  __syncthreads();
-  // ---- axis 0, forward stage 2; only rows holding sticks are kept ----
-#pragma unroll
-  for (int m = 0; m < MT; ++m) {
-    const int task = tid + m * NT;
-    if (task < N1 * B0) {
-      const int i1 = task % N1, e = task / N1;
-#pragma unroll
-      for (int c = 0; c < A0; ++c) h[m][c] = plane[(e * A0 + c) * LD + i1];
-    }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int m = 0; m < MT; ++m) {
-    const int task = tid + m * NT;
-    if (task < N1 * B0) {
-      const int i1 = task % N1, e = task / N1;
-      RegDft<A0, -1>::run(h[m]);
-#pragma unroll
-      for (int f = 0; f < A0; ++f) {
-        const int i0 = e + B0 * f;
-        if (has_sticks(i0)) plane[i0 * LD + i1] = h[m][f];
-      }
-    }
-  }
-  __syncthreads();
-
-  // ---- axis 1, forward, rows holding sticks; gather the sticks ----
-  for (int task = tid; task < n_row * A1; task += NT) {
-    const int t = task % n_row, c = task / n_row;
-    const int i0 = row_i0(t);
-    double2 v[B1];
-#pragma unroll
-    for (int d = 0; d < B1; ++d) v[d] = plane[i0 * LD + c + A1 * d];
-    RegDft<B1, -1>::run(v);
-#pragma unroll
-    for (int e = 0; e < B1; ++e) plane[i0 * LD + e * A1 + c] = (c * e) ? twiddle<-1>(v[e], tw1, c * e) : v[e];
-  }
-  __syncthreads();
-  for (int task = tid; task < n_row * B1; task += NT) {
-    const int t = task % n_row, e = task / n_row;
-    const int i0 = row_i0(t);
-    double2 v[A1];
-#pragma unroll
-    for (int c = 0; c < A1; ++c) v[c] = plane[i0 * LD + e * A1 + c];
-    RegDft<A1, -1>::run(v);
-#pragma unroll
-    for (int f = 0; f < A1; ++f) {
-      const int s = stick_at[i0 * N1 + e + B1 * f];
-      if (s >= 0) Tz[s] = v[f];
-    }
-  }
-}
-
 template <int N2>
 sgw_status launch_sticks(sgw_ctx *ctx, const sgw_ham *h, int n_vec, VecSrc x, double2 *y, long ldy,
                          double2 *tbuf, bool inverse) {
@@ -301,7 +137,7 @@ sgw_status launch_planes(sgw_ctx *ctx, const sgw_ham *h, int n_vec, double2 *tbu
   const double bytes = (double)n_vec * h->n[2] * h->n_stick * 32.0 + (double)N0 * N1 * h->n[2] * 8.0;
   timing_begin(ctx, K_PLANES, bytes, 0.0, &tm);
   hipLaunchKernelGGL((k_planes<N0, N1>), dim3(blocks), dim3(plane_threads<N0, N1>()), 0, ctx->stream, tbuf,
-                     h->n[2], h->n_stick, h->d_stick_at, h->m0_lo, h->n_row, h->d_vt, h->d_tw + h->tw_off[0],
+                     h->n[2], h->n_stick, h->d_rows, h->m0_lo, h->n_row, h->d_vt, h->d_tw + h->tw_off[0],
                      h->d_tw + h->tw_off[1]);
   timing_end(ctx, &tm);
   SGW_HIP(hipGetLastError());

@@ -8,9 +8,10 @@
 // (re*re, im*im, re*im, im*re).  One wavefront owns a 16 x 16 output tile:
 // in the overlap kernel rows are occupied states and columns are vectors, in
 // the apply kernel rows are plane waves and columns are vectors.  The overlap
-// reduction over plane waves is split into chunks (one wave per chunk and
-// vector tile); consumers add the chunk partials in a fixed order, so the
-// result is deterministic.
+// reduction over plane waves is split into chunks (one workgroup per chunk and
+// vector tile, its four waves splitting the chunk again and reducing through
+// LDS); consumers add the chunk partials in a fixed order, so the result is
+// deterministic.
 //
 // MFMA operand layout (v_mfma_f64_16x16x4f64, wave64): lane l supplies
 // A[l % 16][l / 16] and B[l / 16][l % 16]; it receives D[l / 16 + 4 r][l % 16]
@@ -26,13 +27,16 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ d4 mfma(double a, double b, d4 c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
 
 constexpr int kOccTilesMax = 8;  // occupied tiles (of 16) held in accumulators per pass
+constexpr int kDotWaves = 4;
+constexpr int kDotDepth = 4;     // K-steps of operands kept in flight per wave
 
-// grid: vtiles x n_chunks x occ passes, block: one wavefront
+// grid: vtiles x n_chunks x occ passes, block: kDotWaves wavefronts
 template <int NOT>
-__global__ __launch_bounds__(64) void k_proj_dot(int npw, int n_occ, const double2 *__restrict__ psi, VecSrc x,
-                                                 int n_vec, int kc, int n_chunks, double2 *__restrict__ cp,
-                                                 long rows, int vtiles) {
-  const int lane = threadIdx.x;
+__global__ __launch_bounds__(64 * kDotWaves) void k_proj_dot(int npw, int n_occ, const double2 *__restrict__ psi,
+                                                             VecSrc x, int n_vec, int kc, int n_chunks,
+                                                             double2 *__restrict__ cp, long rows, int vtiles) {
+  __shared__ d4 red[kDotWaves - 1][2][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int col = lane & 15, kq = lane >> 4;
   int b = blockIdx.x;
   const int vt = b % vtiles;
@@ -43,7 +47,12 @@ __global__ __launch_bounds__(64) void k_proj_dot(int npw, int n_occ, const doubl
   const int a = vt * 16 + col;
   const bool va = a < n_vec;
   const double2 *xv = va ? x.ptr(a) : nullptr;
-  const int g0 = chunk * kc, g1 = min(npw, g0 + kc);
+  // this wave's share of the chunk, in steps of 4 plane waves
+  const int c0 = chunk * kc, c1 = min(npw, c0 + kc);
+  const int nsteps = (c1 - c0 + 3) / 4;
+  const int sper = (nsteps + kDotWaves - 1) / kDotWaves;
+  const int g0 = c0 + 4 * min(nsteps, wave * sper);
+  const int g1 = min(c1, c0 + 4 * min(nsteps, (wave + 1) * sper));
   d4 re[NOT], im[NOT];
 #pragma unroll
   for (int t = 0; t < NOT; ++t) {
@@ -58,44 +67,62 @@ __global__ __launch_bounds__(64) void k_proj_dot(int npw, int n_occ, const doubl
     vrow[t] = i < n_occ;
     prow[t] = psi + (long)(vrow[t] ? i : 0) * npw;
   }
-  // software pipeline: operands of step g are loaded one step ahead
-  auto load = [&](int g, double2 &xo, double2 (&po)[NOT]) {
+  // ring of kDotDepth steps of operands
+  double2 xr[kDotDepth], pr[kDotDepth][NOT];
+  auto load = [&](int g, int slot) {
     const int gg = g + kq;
     const bool in = gg < g1;
-    xo = (va && in) ? xv[gg] : make_double2(0.0, 0.0);
+    xr[slot] = (va && in) ? xv[gg] : make_double2(0.0, 0.0);
 #pragma unroll
-    for (int t = 0; t < NOT; ++t) po[t] = (vrow[t] && in) ? prow[t][gg] : make_double2(0.0, 0.0);
+    for (int t = 0; t < NOT; ++t) pr[slot][t] = (vrow[t] && in) ? prow[t][gg] : make_double2(0.0, 0.0);
   };
-  double2 xc, pc[NOT];
-  load(g0, xc, pc);
-  for (int g = g0; g < g1; g += 4) {
-    double2 xn, pn[NOT];
-    load(g + 4, xn, pn);
 #pragma unroll
-    for (int t = 0; t < NOT; ++t) {
-      re[t] = mfma(pc[t].x, xc.x, re[t]);
-      im[t] = mfma(pc[t].x, xc.y, im[t]);
-      re[t] = mfma(pc[t].y, xc.y, re[t]);
-      im[t] = mfma(-pc[t].y, xc.x, im[t]);
+  for (int d = 0; d < kDotDepth; ++d) load(g0 + 4 * d, d);
+  for (int g = g0; g < g1; g += 4 * kDotDepth) {
+#pragma unroll
+    for (int d = 0; d < kDotDepth; ++d) {
+      const double2 xc = xr[d];
+#pragma unroll
+      for (int t = 0; t < NOT; ++t) {
+        const double2 pc = pr[d][t];
+        re[t] = mfma(pc.x, xc.x, re[t]);
+        im[t] = mfma(pc.x, xc.y, im[t]);
+        re[t] = mfma(pc.y, xc.y, re[t]);
+        im[t] = mfma(-pc.y, xc.x, im[t]);
+      }
+      load(g + 4 * (d + kDotDepth), d);
     }
-    xc = xn;
-#pragma unroll
-    for (int t = 0; t < NOT; ++t) pc[t] = pn[t];
   }
-  if (!va) return;
-  double2 *out = cp + ((long)chunk * rows + a) * n_occ;
+  // reduce the waves' partial tiles through LDS, one occupied tile at a time
+  double2 *out = cp + ((long)chunk * rows + (va ? a : 0)) * n_occ;
 #pragma unroll
   for (int t = 0; t < NOT; ++t) {
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int i = occ0 + t * 16 + kq + 4 * r;
-      if (i < n_occ) out[i] = make_double2(re[t][r], im[t][r]);
+    if (wave > 0) {
+      red[wave - 1][0][lane] = re[t];
+      red[wave - 1][1][lane] = im[t];
     }
+    __syncthreads();
+    if (wave == 0) {
+#pragma unroll
+      for (int w = 0; w < kDotWaves - 1; ++w) {
+        re[t] += red[w][0][lane];
+        im[t] += red[w][1][lane];
+      }
+      if (va) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = occ0 + t * 16 + kq + 4 * r;
+          if (i < n_occ) out[i] = make_double2(re[t][r], im[t][r]);
+        }
+      }
+    }
+    __syncthreads();
   }
 }
 
 constexpr int kApplyWaves = 4;
-constexpr int kApplyG = 256;  // plane waves per block (each wave: kApplyG / kApplyWaves / 16 tiles)
+constexpr int kApplyG = 256;   // plane waves per block (each wave: kApplyG / kApplyWaves / 16 tiles)
+constexpr int kApplyBatch = 8; // occupied K-steps whose operands are loaded before their MFMAs
 
 // grid: vtiles x gtiles, block: kApplyWaves wavefronts; dynamic LDS: 16 * n_occ complex
 __global__ __launch_bounds__(64 * kApplyWaves) void k_proj_apply(int npw, int n_occ, const double2 *__restrict__ psi,
@@ -108,9 +135,14 @@ __global__ __launch_bounds__(64 * kApplyWaves) void k_proj_apply(int npw, int n_
   const int a0 = vt * 16;
   for (int e = threadIdx.x; e < 16 * n_occ; e += 64 * kApplyWaves) {
     const int v = e / n_occ, i = e - v * n_occ;
+    double2 part[kProjChunks];
+    const bool ok = a0 + v < n_vec;
+#pragma unroll
+    for (int c = 0; c < kProjChunks; ++c)
+      part[c] = (ok && c < n_chunks) ? cp[((long)c * rows + a0 + v) * n_occ + i] : make_double2(0.0, 0.0);
     double2 s = make_double2(0.0, 0.0);
-    if (a0 + v < n_vec)
-      for (int c = 0; c < n_chunks; ++c) s = c_add(s, cp[((long)c * rows + a0 + v) * n_occ + i]);
+#pragma unroll
+    for (int c = 0; c < kProjChunks; ++c) s = c_add(s, part[c]);
     cs[e] = s;
   }
   __syncthreads();
@@ -118,23 +150,31 @@ __global__ __launch_bounds__(64 * kApplyWaves) void k_proj_apply(int npw, int n_
   const int col = lane & 15, kq = lane >> 4;
   const int a = a0 + col;
   const bool va = a < n_vec;
+  const double2 *xa = (va && mode == 0) ? x.ptr(a) : nullptr;
+  double2 *ya = y + (long)(va ? a : 0) * ldy;
   for (int sub = wave; sub < kApplyG / 16; sub += kApplyWaves) {
     const int gb = gt * kApplyG + sub * 16;
     if (gb >= npw) break;
     d4 re = {0.0, 0.0, 0.0, 0.0}, im = {0.0, 0.0, 0.0, 0.0};
     const int ga = gb + col;  // A operand row (plane wave) of this lane
-    for (int i0 = 0; i0 < n_occ; i0 += 4) {
-      const int i = i0 + kq;
-      const double2 p = (i < n_occ && ga < npw) ? psi[(long)i * npw + ga] : make_double2(0.0, 0.0);
-      const double2 c = (i < n_occ) ? cs[col * n_occ + i] : make_double2(0.0, 0.0);
-      re = mfma(p.x, c.x, re);
-      im = mfma(p.x, c.y, im);
-      re = mfma(-p.y, c.y, re);
-      im = mfma(p.y, c.x, im);
+    const bool gin = ga < npw;
+    for (int i0 = 0; i0 < n_occ; i0 += 4 * kApplyBatch) {
+      double2 p[kApplyBatch], c[kApplyBatch];
+#pragma unroll
+      for (int s = 0; s < kApplyBatch; ++s) {
+        const int i = i0 + 4 * s + kq;
+        p[s] = (i < n_occ && gin) ? psi[(long)i * npw + ga] : make_double2(0.0, 0.0);
+        c[s] = (i < n_occ) ? cs[col * n_occ + i] : make_double2(0.0, 0.0);
+      }
+#pragma unroll
+      for (int s = 0; s < kApplyBatch; ++s) {
+        re = mfma(p[s].x, c[s].x, re);
+        im = mfma(p[s].x, c[s].y, im);
+        re = mfma(-p[s].y, c[s].y, re);
+        im = mfma(p[s].y, c[s].x, im);
+      }
     }
     if (!va) continue;
-    const double2 *xa = mode == 0 ? x.ptr(a) : nullptr;
-    double2 *ya = y + (long)a * ldy;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int g = gb + kq + 4 * r;
@@ -174,13 +214,17 @@ sgw_status proj_dot(sgw_ctx *ctx, int npw, int n_occ, const double2 *psi, int n_
   const int passes = (otiles + not_ - 1) / not_;
   PendingTiming tm;
   timing_begin(ctx, K_PROJ_DOT, n_vec * (npw * 16.0) + (double)n_occ * npw * 16.0, 8.0 * n_vec * npw * n_occ, &tm);
-  const dim3 grid((long)vtiles * nch * passes), block(64);
+  const dim3 grid((long)vtiles * nch * passes), block(64 * kDotWaves);
+#define SGW_DOT(NOT)                                                                                           \
+  hipLaunchKernelGGL(k_proj_dot<NOT>, grid, block, 0, ctx->stream, npw, n_occ, psi, x, n_vec, kc, nch, cp, rows, \
+                     vtiles)
   switch (not_) {
-    case 1: hipLaunchKernelGGL(k_proj_dot<1>, grid, block, 0, ctx->stream, npw, n_occ, psi, x, n_vec, kc, nch, cp, rows, vtiles); break;
-    case 2: hipLaunchKernelGGL(k_proj_dot<2>, grid, block, 0, ctx->stream, npw, n_occ, psi, x, n_vec, kc, nch, cp, rows, vtiles); break;
-    case 4: hipLaunchKernelGGL(k_proj_dot<4>, grid, block, 0, ctx->stream, npw, n_occ, psi, x, n_vec, kc, nch, cp, rows, vtiles); break;
-    default: hipLaunchKernelGGL(k_proj_dot<8>, grid, block, 0, ctx->stream, npw, n_occ, psi, x, n_vec, kc, nch, cp, rows, vtiles); break;
+    case 1: SGW_DOT(1); break;
+    case 2: SGW_DOT(2); break;
+    case 4: SGW_DOT(4); break;
+    default: SGW_DOT(8); break;
   }
+#undef SGW_DOT
   timing_end(ctx, &tm);
   SGW_HIP(hipGetLastError());
   return SGW_OK;
