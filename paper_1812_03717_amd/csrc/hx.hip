@@ -135,7 +135,11 @@ sgw_status launch_planes(sgw_ctx *ctx, const sgw_ham *h, int n_vec, double2 *tbu
   PendingTiming tm;
   // algorithmic bytes: stick values in and out; the potential is read once per launch
   const double bytes = (double)n_vec * h->n[2] * h->n_stick * 32.0 + (double)N0 * N1 * h->n[2] * 8.0;
-  timing_begin(ctx, K_PLANES, bytes, 0.0, &tm);
+  // algorithmic flops: 5 N log2 N per complex N-point transform (n_row rows and N1 columns, inverse
+  // and forward) plus 2 per potential multiply, per plane
+  const double per_plane = 2.0 * (h->n_row * 5.0 * N1 * std::log2((double)N1) + N1 * 5.0 * N0 * std::log2((double)N0)) +
+                           2.0 * N0 * N1;
+  timing_begin(ctx, K_PLANES, bytes, per_plane * h->n[2] * n_vec, &tm);
   hipLaunchKernelGGL((k_planes<N0, N1>), dim3(blocks), dim3(plane_threads<N0, N1>()), 0, ctx->stream, tbuf,
                      h->n[2], h->n_stick, h->d_rows, h->m0_lo, h->n_row, h->d_vt, h->d_tw + h->tw_off[0],
                      h->d_tw + h->tw_off[1]);

@@ -1,0 +1,120 @@
+"""Summaries of rocprofv3 results (rocpd SQLite databases) for the library's kernels.
+
+    python -m paper_1812_03717_amd.profiling top DB
+    python -m paper_1812_03717_amd.profiling pmc DB
+    python -m paper_1812_03717_amd.profiling traffic --kernel k_planes --fetch DB --write DB \
+        --copy-fetch DB --copy-write DB --copy-bytes N [--out FILE.json]
+
+``traffic`` scales the per-dispatch FETCH_SIZE and WRITE_SIZE averages (KiB) of
+one kernel by what the same counters read for a plain device copy of known
+size, and records a hash of the kernel's sources so that a later change of the
+kernel marks the numbers stale (``source_hash``).
+"""
+from __future__ import annotations
+
+import argparse
+import collections
+import hashlib
+import json
+import os
+import re
+import sqlite3
+
+CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
+
+# sources that define each timed kernel
+KERNEL_SOURCES = {
+    "hx_planes": ["planes.h", "fft_reg.h", "fft_lds.h", "hx.hip"],
+    "hx_sticks_inv": ["hx.hip", "fft_lds.h"],
+    "hx_sticks_fwd": ["hx.hip", "fft_lds.h"],
+    "proj_dot": ["projector.hip"],
+    "proj_apply": ["projector.hip"],
+}
+
+
+def source_hash(kernel: str) -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES.get(kernel, []):
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(f.encode() + b"\0" + fh.read())
+    return h.hexdigest()[:16]
+
+
+def short_name(n: str) -> str:
+    m = re.search(r"(k_\w+)(<[^>]*>)?", n)
+    return (m.group(1) + (m.group(2) or "")) if m else n[:60]
+
+
+def top(db: str):
+    c = sqlite3.connect(db)
+    rows = c.execute("select name, total_calls, total_duration, average, percentage from top_kernels "
+                     "order by total_duration desc").fetchall()
+    return [(short_name(n), calls, tot, avg, pct) for n, calls, tot, avg, pct in rows]
+
+
+def pmc(db: str):
+    """{(kernel, counter): (dispatches, average value)}"""
+    c = sqlite3.connect(db)
+    agg = collections.defaultdict(lambda: [0, 0.0])
+    for name, cn, val in c.execute("select kernel_name, counter_name, value from counters_collection"):
+        k = (short_name(name), cn)
+        agg[k][0] += 1
+        agg[k][1] += val
+    return {k: (n, s / n) for k, (n, s) in agg.items()}
+
+
+def _avg(db, kernel_prefix, counter):
+    for (k, cn), (n, avg) in pmc(db).items():
+        if cn == counter and k.startswith(kernel_prefix):
+            return n, avg
+    raise KeyError(f"{kernel_prefix}/{counter} not in {db}")
+
+
+def traffic(kernel_prefix, fetch_db, write_db, copy_fetch_db, copy_write_db, copy_bytes):
+    nf, fetch_kib = _avg(fetch_db, kernel_prefix, "FETCH_SIZE")
+    nw, write_kib = _avg(write_db, kernel_prefix, "WRITE_SIZE")
+    _, cf = _avg(copy_fetch_db, "__amd_rocclr_copyBuffer", "FETCH_SIZE")
+    _, cw = _avg(copy_write_db, "__amd_rocclr_copyBuffer", "WRITE_SIZE")
+    f_scale = copy_bytes / (cf * 1024.0)
+    w_scale = copy_bytes / (cw * 1024.0)
+    return {"fetch_bytes_per_dispatch": fetch_kib * 1024.0 * f_scale,
+            "write_bytes_per_dispatch": write_kib * 1024.0 * w_scale,
+            "fetch_scale": f_scale, "write_scale": w_scale, "dispatches": [nf, nw]}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    t = sub.add_parser("top")
+    t.add_argument("db")
+    p = sub.add_parser("pmc")
+    p.add_argument("db")
+    r = sub.add_parser("traffic")
+    r.add_argument("--kernel", required=True, help="kernel symbol prefix, e.g. k_planes")
+    r.add_argument("--name", required=True, help="library kernel name, e.g. hx_planes")
+    for k in ("fetch", "write", "copy-fetch", "copy-write"):
+        r.add_argument(f"--{k}", required=True)
+    r.add_argument("--copy-bytes", type=float, required=True)
+    r.add_argument("--out")
+    a = ap.parse_args()
+    if a.cmd == "top":
+        # rocpd reports durations in microseconds
+        print(f"{'kernel':40s} {'calls':>7s} {'total_ms':>10s} {'avg_us':>9s} {'pct':>6s}")
+        for n, calls, tot, avg, pct in top(a.db):
+            print(f"{n:40s} {calls:7d} {tot / 1e3:10.2f} {avg:9.2f} {pct:6.2f}")
+    elif a.cmd == "pmc":
+        for (k, cn), (n, avg) in sorted(pmc(a.db).items()):
+            print(f"{k:40s} {cn:12s} dispatches {n:6d} avg {avg:14.1f} KiB")
+    else:
+        res = traffic(a.kernel, a.fetch, a.write, a.copy_fetch, a.copy_write, a.copy_bytes)
+        res["kernel"] = a.name
+        res["source_hash"] = source_hash(a.name)
+        print(json.dumps(res, indent=1))
+        if a.out:
+            with open(a.out, "w") as fh:
+                json.dump(res, fh, indent=1)
+                fh.write("\n")
+
+
+if __name__ == "__main__":
+    main()

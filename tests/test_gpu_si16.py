@@ -1,0 +1,86 @@
+"""Full-size parity on the si16 workload, in the launch configuration bench.py times.
+
+Every one of the 102,400 solves (32 bands x 50 perturbations x 64 frequencies,
+tol 1e-8) must report a true FP64 relative residual <= tol and a negligible
+occupied component.  A seeded sample of solves is checked against the oracle's
+direct LU solve with the rigorous error budget of a Hermitian operator with a
+complex shift: ||x - x*|| <= ||r|| / eta, since every singular value of
+H - eps - z is at least |Im z| = eta.  A second, smaller launch at tol 1e-12
+checks sampled solves to 1e-8 relative error.
+"""
+import numpy as np
+import pytest
+
+import oracle.sternheimer_oracle as so
+import synth
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def setup():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from tests.libutil import ensure_library
+    ensure_library()
+    from paper_1812_03717_amd import sgw
+    from paper_1812_03717_amd.workload import DeviceProblem
+    p = synth.si16()
+    ctx = sgw.sgw_ctx_create(0)
+    dev = DeviceProblem(ctx, p)
+    print(f"si16: {p.n_pw_kq} PW, {p.n_solves} solves", flush=True)
+    h = so.hamiltonian(p.miller_kq, p.B, p.kvec + p.qvec, p.v_grid)
+    return p, ctx, dev, h
+
+
+def _lu_reference(p, h, v, q, om, eta):
+    b = so.rhs(p.psi_k[v], p.miller_k, p.miller_kq, p.dv_miller[q], p.psi_kq)
+    a0 = so.coulomb_operator(h, p.psi_kq, p.eps_k[v], 1.0)
+    return b, so.solve_lu(a0, b, om + 1j * eta)
+
+
+def test_si16_full_workload(setup):
+    from paper_1812_03717_amd import sgw
+    p, ctx, dev, h = setup
+    st, dpsi, info = dev.solve()           # default options, as bench.py runs it
+    torch.cuda.synchronize()
+    inf = sgw.info_to_numpy(info, (p.n_band, p.n_pert, p.n_omega))
+    print(f"status {st}; iters {inf['iters'].min()}..{inf['iters'].max()}; max relres {inf['relres'].max():.3e}; "
+          f"max occ leak {inf['occ_leak'].max():.3e}", flush=True)
+    assert st == sgw.SGW_OK
+    assert np.all(inf["flags"] & sgw.FLAG_CONVERGED)
+    assert inf["relres"].max() <= p.tol
+    assert inf["occ_leak"].max() <= 1e-9
+    rng = np.random.default_rng(16)
+    for _ in range(4):
+        v, q, j = int(rng.integers(p.n_band)), int(rng.integers(p.n_pert)), int(rng.integers(p.n_omega))
+        b, ref = _lu_reference(p, h, v, q, p.omega[j], p.eta)
+        x = dpsi[v, q, j].cpu().numpy()
+        err = np.linalg.norm(x - ref)
+        bound = inf["relres"][v, q, j] * np.linalg.norm(b) / p.eta
+        print(f"  (v={v}, p={q}, j={j}): |x - x*| = {err:.3e}, budget {bound:.3e}, "
+              f"rel err {err / np.linalg.norm(ref):.3e}", flush=True)
+        assert err <= 1.01 * bound + 1e-12 * np.linalg.norm(ref)
+
+
+def test_si16_tight_sample(setup):
+    """Top and bottom bands, two perturbations, every frequency, at tol 1e-12: 1e-8 relative error."""
+    from paper_1812_03717_amd import sgw
+    p, ctx, dev, h = setup
+    bands, perts = [0, p.n_band - 1], [0, 7]
+    st, dpsi, info = dev.solve(tol=1e-12, bands=bands, perts=perts,
+                               opts=sgw.sgw_opts_default(max_iter=1500))
+    torch.cuda.synchronize()
+    inf = sgw.info_to_numpy(info, (len(bands), len(perts), p.n_omega))
+    print(f"tight: status {st}; iters {inf['iters'].min()}..{inf['iters'].max()}; "
+          f"max relres {inf['relres'].max():.3e}", flush=True)
+    got = dpsi.cpu().numpy()
+    for bi, v in enumerate(bands):
+        for pi, q in enumerate(perts):
+            for j in (0, p.n_omega - 1):
+                b, ref = _lu_reference(p, h, v, q, p.omega[j], p.eta)
+                err = np.linalg.norm(got[bi, pi, j] - ref) / np.linalg.norm(ref)
+                print(f"  (v={v}, p={q}, j={j}): rel err {err:.3e}, relres {inf['relres'][bi, pi, j]:.2e}",
+                      flush=True)
+                assert err <= 1e-8
