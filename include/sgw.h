@@ -59,14 +59,30 @@ enum {
   SGW_FLAG_MAXITER = 2,       /* Krylov space reached max_iter before the estimate met tol */
   SGW_FLAG_BREAKDOWN = 4,     /* invariant Krylov subspace found (solution exact in it) */
   SGW_FLAG_NONFINITE = 8,     /* NaN or Inf met in the recurrence or the result */
-  SGW_FLAG_ZERO_RHS = 16      /* right-hand side zero to working precision, i.e.
+  SGW_FLAG_ZERO_RHS = 16,     /* right-hand side zero to working precision, i.e.
                                  ||(1 - P_occ) s|| <= 1e-13 ||s||: dpsi = 0, relres = 0 */
+  SGW_FLAG_PER_SHIFT = 32     /* finished by the per-shift solver: iters counts its
+                                 BiCGStab iterations (two operator applications each) */
 };
 
 enum { SGW_FP64 = 0 };        /* precision modes */
 
+/* solver (sgw_opts.solver) */
+enum {
+  SGW_SOLVER_MULTISHIFT = 0,  /* all shifts of one (v,p) share one Krylov space (Sec. 2.2) */
+  SGW_SOLVER_PER_SHIFT = 1,   /* every (v,p,z) its own preconditioned BiCGStab solve */
+  SGW_SOLVER_TAIL = 2         /* multishift up to Krylov dimension tail_iter, then the shifts
+                                 still above tol continue per shift, warm-started from the
+                                 multishift iterate */
+};
+/* diagonal preconditioner of the per-shift solves (sgw_opts.precond) */
+enum { SGW_PC_NONE = 0, SGW_PC_TETER = 1, SGW_PC_LEARNED = 2 };
+/* initial guess of the per-shift solves (sgw_opts.guess); TAIL always warm-starts */
+enum { SGW_GUESS_ZERO = 0, SGW_GUESS_LEARNED = 1 };
+
 typedef struct sgw_ctx sgw_ctx;
 typedef struct sgw_ham sgw_ham;
+typedef struct sgw_mlp sgw_mlp;
 
 /* Last error message of the calling thread ("" if none). Never NULL. */
 const char *sgw_last_error(void);
@@ -161,6 +177,20 @@ typedef struct {
   int32_t slots;            /* (v,p) pairs iterated concurrently; <= 0 -> automatic */
   int32_t finalize_batch;   /* pairs per finalisation batch; <= 0 -> automatic */
   int32_t steps_per_sync;   /* Krylov steps between host polls; <= 0 -> 8 */
+  int32_t solver;           /* SGW_SOLVER_* (default MULTISHIFT) */
+  int32_t precond;          /* SGW_PC_* for per-shift solves (default NONE); a preconditioner or
+                               a non-zero initial guess breaks the shared Krylov space, so the
+                               multishift solver accepts only NONE / ZERO */
+  int32_t guess;            /* SGW_GUESS_* for per-shift solves (default ZERO) */
+  int32_t tail_iter;        /* TAIL: multishift Krylov dimension cap; <= 0 -> 160 */
+  int32_t ps_max_iter;      /* per-shift BiCGStab iteration limit; <= 0 -> 2000 */
+  int32_t ps_slots;         /* per-shift systems iterated concurrently; <= 0 -> automatic */
+  const sgw_mlp *mlp;       /* model for PC_LEARNED / GUESS_LEARNED (same device), else NULL */
+  sgw_c128 *hist_r;         /* optional device out [n_band][n_pert][n_omega][n_pw_kq]: per-shift
+                               residual r_k after hist_iter iterations (caller's order); left
+                               untouched for solves that finished earlier */
+  sgw_c128 *hist_x;         /* optional device out, same shape: the iterate x_k with r_k */
+  int32_t hist_iter;        /* iteration of the snapshot (> 0 with hist_r, hist_x) */
   int32_t reserved;
 } sgw_opts;
 
@@ -168,7 +198,8 @@ typedef struct {
 sgw_status sgw_opts_default(sgw_opts *opts);
 
 typedef struct {
-  int32_t iters;            /* Krylov dimension used (matrix-vector products of the seed) */
+  int32_t iters;            /* Krylov dimension at which this shift's residual estimate met the
+                               stopping threshold (the pair's full dimension if it never did) */
   int32_t flags;            /* SGW_FLAG_* */
   double relres;            /* true FP64 ||b - A_z x|| / ||b||, A_z applied afresh to x */
   double occ_leak;          /* ||Psi^H x|| / ||x|| (0 for x = 0) */
@@ -208,6 +239,69 @@ sgw_status sternheimer_solve(sgw_ctx *ctx, const sgw_ham *h_kq, int n_occ, const
                              int n_pert, const int32_t *dv_miller, int n_omega, const double *omega,
                              double eta, double tol, const sgw_opts *opts, void *workspace,
                              size_t workspace_bytes, sgw_c128 *dpsi, sgw_solve_info *info);
+
+/*
+ * Learned diagonal preconditioner and initial guess for the per-shift solves
+ * (not part of the paper; its solves replace the sum over empty states, Sec. 2.3,
+ * and any preconditioner leaves their solution unchanged).  A 3-layer perceptron,
+ * 5 -> 64 -> 64 -> 4 with tanh, evaluated per plane wave G of a system with band
+ * energy eps and shift z = omega + i*eta (Ha), on the features
+ *     f = (T/10, eps/10, omega, 100*eta, (T - eps - omega)/10),  T = 0.5|k+G|^2.
+ * With outputs o and s = 1/(T + 1): preconditioner m_G = s (o0 + i o1), guess
+ * x0_G = s (o2 + i o3) b_G.
+ *
+ * Parameters: FP32, sgw_mlp_num_params() of them, in this order (row-major):
+ *     W1[64][5], b1[64], W2[64][64], b2[64], W3[4][64], b3[4].
+ * Inference inside the solver uses a BF16 rounding of the weights with FP32
+ * arithmetic; sgw_mlp_forward / _grad / _train_step use the FP32 weights.
+ *
+ * Training rows: feat [n_rows][5] and target [n_rows][8] = (u_m, w_m, u_g, w_g) as
+ * complex (re, im) pairs; the loss is the mean over rows of
+ *     |m u_m - w_m|^2 + |g u_g - w_g|^2,   m = s (o0 + i o1), g = s (o2 + i o3).
+ * feat, target, out, grad_out and loss_out are device arrays (FP32).
+ */
+int32_t sgw_mlp_num_params(void);
+/* init_w: host [num_params] or NULL for a seeded Glorot-uniform start with m = g = s. */
+sgw_status sgw_mlp_create(sgw_ctx *ctx, const float *init_w, uint64_t seed, sgw_mlp **out);
+sgw_status sgw_mlp_destroy(sgw_mlp *mlp);
+/* host copies of the FP32 master weights */
+sgw_status sgw_mlp_get_weights(const sgw_mlp *mlp, float *w);
+sgw_status sgw_mlp_set_weights(sgw_mlp *mlp, const float *w);
+/* out [n_rows][4]: the raw outputs o */
+sgw_status sgw_mlp_forward(sgw_ctx *ctx, const sgw_mlp *mlp, int n_rows, const float *feat, float *out);
+/* grad_out [num_params]: d loss / d w; loss_out [1] (may be NULL).  Deterministic. */
+sgw_status sgw_mlp_grad(sgw_ctx *ctx, const sgw_mlp *mlp, int n_rows, const float *feat, const float *target,
+                        float *grad_out, float *loss_out);
+/* One Adam step (beta 0.9 / 0.999, eps 1e-8) with learning rate lr on the loss of these rows.
+   loss_out: host [1] (may be NULL), the loss before the step. */
+sgw_status sgw_mlp_train_step(sgw_ctx *ctx, sgw_mlp *mlp, int n_rows, const float *feat, const float *target,
+                              float lr, float *loss_out);
+/*
+ * Column statistics of the operator A0 = H + alpha P_occ (the shifted operator of
+ * Sec. 2.3, Eq. 6, without -eps_v - z): for every plane wave G (caller's order)
+ *     diag[G] = (A0)_GG,   off2[G] = sum_{G' != G} |(A0)_G'G|^2.
+ * Computed by applying A0 to unit vectors in batches.  psi: device [n_occ][n_pw];
+ * diag, off2: device [n_pw].  Allocates a temporary device buffer.
+ */
+sgw_status sgw_operator_columns(sgw_ctx *ctx, const sgw_ham *ham, int n_occ, const sgw_c128 *psi, double alpha,
+                                double *diag, double *off2);
+/*
+ * Training rows from residual histories (device [n_vec][n_pw], caller's order):
+ * r are residuals of per-shift solves (snapshots, sternheimer_solve hist_r), b the
+ * right-hand sides; eps, omega: host [n_vec] band energies and frequencies (Ha).
+ * With D_G = diag[G] - eps - (omega + i eta) and c_G = off2[G], each sampled plane
+ * wave u = stride*t (t < P = ceil(n_pw/stride)) of vector a gives rows 2(aP+t)
+ * and 2(aP+t)+1:
+ *     (u_m, w_m, u_g, w_g) = (D r, r, D b, b) / norms   and   (sqrt(c) r, 0, sqrt(c) b, 0) / norms
+ * (norms: ||r|| for the first pair, ||b|| for the second, over the sampled plane
+ * waves).  Summed over a vector's rows the loss is the diagonal approximate-
+ * inverse objective  sum_G |r_G|^2 (|1 - D_G m_G|^2 + c_G |m_G|^2) / ||r||^2:
+ * the residual left after one step x += m (.) r, with the off-diagonal part of A
+ * counted by its column norm.  feat: device [2 n_vec P][5], target [2 n_vec P][8].
+ */
+sgw_status sgw_mlp_rows(sgw_ctx *ctx, const sgw_ham *ham, const double *diag, const double *off2, int n_vec,
+                        const double *eps, const double *omega, double eta, const sgw_c128 *r, const sgw_c128 *b,
+                        int stride, float *feat, float *target);
 
 #ifdef __cplusplus
 }

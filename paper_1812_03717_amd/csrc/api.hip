@@ -10,6 +10,7 @@
 #include <string>
 #include <vector>
 
+#include "pershift.h"
 #include "sgw_internal.h"
 #include "solver_state.h"
 
@@ -80,7 +81,7 @@ sgw_status timing_collect(sgw_ctx *ctx) {
   return SGW_OK;
 }
 
-static sgw_status ensure_pinned(sgw_ctx *ctx, size_t bytes) {
+sgw_status ensure_pinned(sgw_ctx *ctx, size_t bytes) {
   if (ctx->pinned_bytes >= bytes) return SGW_OK;
   if (ctx->pinned) hipHostFree(ctx->pinned);
   ctx->pinned = nullptr;
@@ -91,7 +92,7 @@ static sgw_status ensure_pinned(sgw_ctx *ctx, size_t bytes) {
   return SGW_OK;
 }
 
-static sgw_status sync(sgw_ctx *ctx) {
+sgw_status sync(sgw_ctx *ctx) {
   SGW_HIP(hipStreamSynchronize(ctx->stream));
   return timing_collect(ctx);
 }
@@ -501,6 +502,16 @@ extern "C" sgw_status sgw_opts_default(sgw_opts *o) {
   o->slots = 0;
   o->finalize_batch = 0;
   o->steps_per_sync = 8;
+  o->solver = SGW_SOLVER_MULTISHIFT;
+  o->precond = SGW_PC_NONE;
+  o->guess = SGW_GUESS_ZERO;
+  o->tail_iter = 160;
+  o->ps_max_iter = 2000;
+  o->ps_slots = 0;
+  o->mlp = nullptr;
+  o->hist_r = nullptr;
+  o->hist_x = nullptr;
+  o->hist_iter = 0;
   return SGW_OK;
 }
 
@@ -511,7 +522,7 @@ constexpr double kDefaultBudget = 40.0 * (1ull << 30);
 
 struct Layout {
   int S = 0, F = 0, kmax = 0, M = 8;
-  size_t psi, omega, epsb, dvm, pair, kcur, status, eps, alpha, beta, rho, res, bvec, basis;
+  size_t psi, omega, epsb, dvm, pair, kcur, status, eps, alpha, beta, rho, res, conv, bvec, basis;
   size_t l_active, l_fill, l_fillpairs, l_final, Y, Y2, C, T, ycoef, cp, X, AX, bad;
   long c_rows = 0;
   size_t total = 0;
@@ -535,6 +546,16 @@ sgw_opts resolve_opts(const sgw_opts *in) {
     o.slots = in->slots;
     o.finalize_batch = in->finalize_batch;
     if (in->steps_per_sync > 0) o.steps_per_sync = in->steps_per_sync;
+    o.solver = in->solver;
+    o.precond = in->precond;
+    o.guess = in->guess;
+    if (in->tail_iter > 0) o.tail_iter = in->tail_iter;
+    if (in->ps_max_iter > 0) o.ps_max_iter = in->ps_max_iter;
+    o.ps_slots = in->ps_slots;
+    o.mlp = in->mlp;
+    o.hist_r = in->hist_r;
+    o.hist_x = in->hist_x;
+    o.hist_iter = in->hist_iter;
   }
   return o;
 }
@@ -571,6 +592,7 @@ Layout make_layout(const sgw_ham *h, int n_occ, int n_band, int n_pert, int n_om
   L.beta = take(off, 8ul * L.S * (L.kmax + 1));
   L.rho = take(off, 16ul * L.S * n_omega);
   L.res = take(off, 8ul * L.S * n_omega);
+  L.conv = take(off, 4ul * L.S * n_omega);
   L.bvec = take(off, 16ul * L.S * npw);
   L.basis = take(off, 16ul * L.S * (L.kmax + 1) * npw);
   L.l_active = take(off, 4ul * L.S);
@@ -608,6 +630,19 @@ static sgw_status validate_solve(sgw_ctx *ctx, const sgw_ham *h_kq, int n_occ, c
   SGW_CHECK(std::isfinite(eta) && eta != 0.0, "sternheimer_solve: eta must be finite and non-zero");
   SGW_CHECK(std::isfinite(tol) && tol > 0.0, "sternheimer_solve: tol must be positive");
   SGW_CHECK(std::isfinite(o.alpha_pv) && o.alpha_pv > 0.0, "sternheimer_solve: alpha_pv must be positive");
+  SGW_CHECK(o.solver >= SGW_SOLVER_MULTISHIFT && o.solver <= SGW_SOLVER_TAIL, "sternheimer_solve: unknown solver");
+  SGW_CHECK(o.precond >= SGW_PC_NONE && o.precond <= SGW_PC_LEARNED, "sternheimer_solve: unknown preconditioner");
+  SGW_CHECK(o.guess == SGW_GUESS_ZERO || o.guess == SGW_GUESS_LEARNED, "sternheimer_solve: unknown initial guess");
+  SGW_CHECK(o.solver != SGW_SOLVER_MULTISHIFT || (o.precond == SGW_PC_NONE && o.guess == SGW_GUESS_ZERO),
+            "sternheimer_solve: a preconditioner or initial guess breaks the shared Krylov space; "
+            "use the per-shift or tail solver");
+  SGW_CHECK(o.ps_max_iter >= 1 && o.ps_max_iter <= 100000, "sternheimer_solve: ps_max_iter out of range");
+  if (o.precond == SGW_PC_LEARNED || (o.guess == SGW_GUESS_LEARNED && o.solver == SGW_SOLVER_PER_SHIFT)) {
+    SGW_CHECK(o.mlp != nullptr, "sternheimer_solve: the learned preconditioner or guess needs opts.mlp");
+    SGW_CHECK(o.mlp->device == ctx->device, "sternheimer_solve: opts.mlp lives on another device");
+  }
+  SGW_CHECK(o.hist_iter >= 0, "sternheimer_solve: hist_iter < 0");
+  SGW_CHECK(o.hist_iter == 0 || (o.hist_r && o.hist_x), "sternheimer_solve: hist_iter > 0 needs hist_r and hist_x");
   if ((long)n_band * n_pert * n_omega == 0) return SGW_OK;
   SGW_CHECK(psi_v && eps_v && dv_miller && omega, "sternheimer_solve: NULL input array");
   SGW_CHECK(n_occ == 0 || psi_occ_kq, "sternheimer_solve: psi_occ_kq is NULL");
@@ -617,34 +652,49 @@ static sgw_status validate_solve(sgw_ctx *ctx, const sgw_ham *h_kq, int n_occ, c
   return check_miller_shift(dv_miller, n_pert);
 }
 
+// options of the multishift phase of a TAIL solve
+static sgw_opts tail_phase_opts(const sgw_opts &o) {
+  sgw_opts m = o;
+  m.max_iter = std::min(o.max_iter, o.tail_iter);
+  return m;
+}
+
+static size_t solve_workspace_bytes(const sgw_ham *h_kq, int n_occ, int n_band, int n_pert, int n_omega,
+                                    const sgw_opts &o) {
+  const long n_sys = (long)n_band * n_pert * n_omega;
+  const int n_sys_i = (int)std::min<long>(n_sys, 1L << 30);
+  switch (o.solver) {
+    case SGW_SOLVER_PER_SHIFT:
+      return ps_workspace_bytes(h_kq, n_occ, n_band, n_pert, n_omega, o, n_sys_i);
+    case SGW_SOLVER_TAIL:
+      return std::max(make_layout(h_kq, n_occ, n_band, n_pert, n_omega, tail_phase_opts(o)).total,
+                      ps_workspace_bytes(h_kq, n_occ, n_band, n_pert, n_omega, o, n_sys_i));
+    default:
+      return make_layout(h_kq, n_occ, n_band, n_pert, n_omega, o).total;
+  }
+}
+
 extern "C" sgw_status sternheimer_workspace_size(sgw_ctx *ctx, const sgw_ham *h_kq, int n_occ, int n_band,
                                                  int n_pert, int n_omega, const sgw_opts *opts, size_t *bytes) {
   if (!ctx || !h_kq || !bytes) return fail(SGW_ERR_INVALID_ARG, "sternheimer_workspace_size: NULL argument");
   if (n_occ < 0 || n_band < 0 || n_pert < 0 || n_omega < 0)
     return fail(SGW_ERR_INVALID_ARG, "sternheimer_workspace_size: negative size");
   const sgw_opts o = resolve_opts(opts);
-  *bytes = make_layout(h_kq, n_occ, n_band, n_pert, std::max(n_omega, 1), o).total;
+  if (o.solver < SGW_SOLVER_MULTISHIFT || o.solver > SGW_SOLVER_TAIL)
+    return fail(SGW_ERR_INVALID_ARG, "sternheimer_workspace_size: unknown solver");
+  *bytes = solve_workspace_bytes(h_kq, n_occ, n_band, n_pert, std::max(n_omega, 1), o);
   return SGW_OK;
 }
 
-extern "C" sgw_status sternheimer_solve(sgw_ctx *ctx, const sgw_ham *h_kq, int n_occ, const sgw_c128 *psi_occ_kq,
-                                        const sgw_ham *h_k, int n_band, const sgw_c128 *psi_v, const double *eps_v,
-                                        int n_pert, const int32_t *dv_miller, int n_omega, const double *omega,
-                                        double eta, double tol, const sgw_opts *opts, void *workspace,
-                                        size_t workspace_bytes, sgw_c128 *dpsi, sgw_solve_info *info) {
-  const sgw_opts o = resolve_opts(opts);
-  sgw_status st = validate_solve(ctx, h_kq, n_occ, psi_occ_kq, h_k, n_band, psi_v, eps_v, n_pert, dv_miller,
-                                 n_omega, omega, eta, tol, o);
-  if (st != SGW_OK) return st;
+// The multishift solve proper (arguments validated, workspace checked).
+static sgw_status multishift_solve(sgw_ctx *ctx, const sgw_ham *h_kq, int n_occ, const sgw_c128 *psi_occ_kq,
+                                   const sgw_ham *h_k, int n_band, const sgw_c128 *psi_v, const double *eps_v,
+                                   int n_pert, const int32_t *dv_miller, int n_omega, const double *omega,
+                                   double eta, double tol, const sgw_opts &o, void *workspace, sgw_c128 *dpsi,
+                                   sgw_solve_info *info) {
+  sgw_status st;
   const int n_pairs = n_band * n_pert;
-  if ((long)n_pairs * n_omega == 0) return SGW_OK;
-  SGW_CHECK(dpsi && info, "sternheimer_solve: NULL output array");
   const Layout L = make_layout(h_kq, n_occ, n_band, n_pert, n_omega, o);
-  if (!workspace || workspace_bytes < L.total)
-    return fail(SGW_ERR_WORKSPACE, "sternheimer_solve: workspace needs " + std::to_string(L.total) + " bytes");
-  if (((uintptr_t)workspace) % kAlign != 0)
-    return fail(SGW_ERR_WORKSPACE, "sternheimer_solve: workspace must be 256-byte aligned");
-  SGW_HIP(hipSetDevice(ctx->device));
   char *W = (char *)workspace;
   const int npw = h_kq->n_pw;
   const int S = L.S, F = L.F;
@@ -663,6 +713,7 @@ extern "C" sgw_status sternheimer_solve(sgw_ctx *ctx, const sgw_ham *h_kq, int n
   Sx.beta = (double *)(W + L.beta);
   Sx.rho = (double2 *)(W + L.rho);
   Sx.res = (double *)(W + L.res);
+  Sx.conv = (int32_t *)(W + L.conv);
   Sx.pair = (int32_t *)(W + L.pair);
   Sx.kcur = (int32_t *)(W + L.kcur);
   Sx.status = (int32_t *)(W + L.status);
@@ -806,4 +857,51 @@ extern "C" sgw_status sternheimer_solve(sgw_ctx *ctx, const sgw_ham *h_kq, int n
   SGW_HIP(hipMemcpyAsync(p_bad, d_bad, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
   if ((st = sync(ctx)) != SGW_OK) return st;
   return *p_bad > 0 ? SGW_NOT_CONVERGED : SGW_OK;
+}
+
+extern "C" sgw_status sternheimer_solve(sgw_ctx *ctx, const sgw_ham *h_kq, int n_occ, const sgw_c128 *psi_occ_kq,
+                                        const sgw_ham *h_k, int n_band, const sgw_c128 *psi_v, const double *eps_v,
+                                        int n_pert, const int32_t *dv_miller, int n_omega, const double *omega,
+                                        double eta, double tol, const sgw_opts *opts, void *workspace,
+                                        size_t workspace_bytes, sgw_c128 *dpsi, sgw_solve_info *info) {
+  const sgw_opts o = resolve_opts(opts);
+  sgw_status st = validate_solve(ctx, h_kq, n_occ, psi_occ_kq, h_k, n_band, psi_v, eps_v, n_pert, dv_miller,
+                                 n_omega, omega, eta, tol, o);
+  if (st != SGW_OK) return st;
+  const long n_sys = (long)n_band * n_pert * n_omega;
+  if (n_sys == 0) return SGW_OK;
+  SGW_CHECK(dpsi && info, "sternheimer_solve: NULL output array");
+  SGW_CHECK(n_sys < (1L << 31), "sternheimer_solve: more than 2^31 solves in one call");
+  const size_t need = solve_workspace_bytes(h_kq, n_occ, n_band, n_pert, n_omega, o);
+  if (!workspace || workspace_bytes < need)
+    return fail(SGW_ERR_WORKSPACE, "sternheimer_solve: workspace needs " + std::to_string(need) + " bytes");
+  if (((uintptr_t)workspace) % kAlign != 0)
+    return fail(SGW_ERR_WORKSPACE, "sternheimer_solve: workspace must be 256-byte aligned");
+  SGW_HIP(hipSetDevice(ctx->device));
+  PsProblem P{h_kq, h_k, n_occ, (const double2 *)psi_occ_kq, n_band, (const double2 *)psi_v, eps_v, n_pert,
+              dv_miller, n_omega, omega, eta, tol};
+  if (o.solver == SGW_SOLVER_PER_SHIFT) {
+    int n_bad = 0;
+    if ((st = ps_solve(ctx, P, o, {}, false, workspace, workspace_bytes, (double2 *)dpsi, info, &n_bad)) != SGW_OK)
+      return st;
+    return n_bad > 0 ? SGW_NOT_CONVERGED : SGW_OK;
+  }
+  if (o.solver == SGW_SOLVER_MULTISHIFT)
+    return multishift_solve(ctx, h_kq, n_occ, psi_occ_kq, h_k, n_band, psi_v, eps_v, n_pert, dv_miller, n_omega,
+                            omega, eta, tol, o, workspace, dpsi, info);
+  // TAIL: multishift up to tail_iter, then the shifts above tol per shift from their multishift iterate
+  st = multishift_solve(ctx, h_kq, n_occ, psi_occ_kq, h_k, n_band, psi_v, eps_v, n_pert, dv_miller, n_omega, omega,
+                        eta, tol, tail_phase_opts(o), workspace, dpsi, info);
+  if (st != SGW_OK && st != SGW_NOT_CONVERGED) return st;
+  if (st == SGW_OK) return SGW_OK;
+  std::vector<sgw_solve_info> hinfo(n_sys);
+  SGW_HIP(hipMemcpyAsync(hinfo.data(), info, sizeof(sgw_solve_info) * n_sys, hipMemcpyDeviceToHost, ctx->stream));
+  if ((st = sync(ctx)) != SGW_OK) return st;
+  std::vector<int32_t> tail;
+  for (long y = 0; y < n_sys; ++y)
+    if (!(hinfo[y].flags & SGW_FLAG_CONVERGED)) tail.push_back((int32_t)y);
+  int n_bad = 0;
+  if ((st = ps_solve(ctx, P, o, tail, true, workspace, workspace_bytes, (double2 *)dpsi, info, &n_bad)) != SGW_OK)
+    return st;
+  return n_bad > 0 ? SGW_NOT_CONVERGED : SGW_OK;
 }

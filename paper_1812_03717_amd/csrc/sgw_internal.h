@@ -105,7 +105,7 @@ struct sgw_ham {
 namespace sgw {
 
 // Describes where vector a of a batch lives: base + a*ld, or, with a slot list,
-// base + list[a]*slot_stride + kidx[list[a]]*ld.
+// base + list[a]*slot_stride (+ kidx[list[a]]*ld when kidx is given).
 struct VecSrc {
   const double2 *base;
   long ld;
@@ -115,9 +115,11 @@ struct VecSrc {
   __host__ __device__ inline const double2 *ptr(int a) const {
     if (!list) return base + (long)a * ld;
     int s = list[a];
-    return base + (long)s * slot_stride + (long)kidx[s] * ld;
+    return base + (long)s * slot_stride + (kidx ? (long)kidx[s] * ld : 0L);
   }
 };
+
+inline VecSrc listed(const double2 *p, long ld, const int32_t *list) { return VecSrc{p, ld, list, nullptr, ld}; }
 
 inline VecSrc contiguous(const double2 *p, long ld) { return VecSrc{p, ld, nullptr, nullptr, 0}; }
 
@@ -125,6 +127,10 @@ inline VecSrc contiguous(const double2 *p, long ld) { return VecSrc{p, ld, nullp
 void timing_begin(sgw_ctx *ctx, int kid, double bytes, double flops, PendingTiming *out);
 void timing_end(sgw_ctx *ctx, PendingTiming *t);
 sgw_status timing_collect(sgw_ctx *ctx);
+// pinned host staging of at least `bytes` in ctx->pinned
+sgw_status ensure_pinned(sgw_ctx *ctx, size_t bytes);
+// waits for the context's stream, then collects kernel timings
+sgw_status sync(sgw_ctx *ctx);
 
 // H.x over a batch (internal order): y = T.x + F V F^-1 x.  `tbuf` holds
 // n_vec * N2 * n_stick complex entries.

@@ -135,6 +135,7 @@ __global__ __launch_bounds__(kRowThreads) void k_init(SolverState S, const doubl
   }
   for (int j = threadIdx.x; j < S.n_omega; j += kRowThreads) {
     S.res[(long)slot * S.n_omega + j] = 1.0;
+    S.conv[(long)slot * S.n_omega + j] = -1;
     S.rho[(long)slot * S.n_omega + j] = make_double2(1.0, 0.0);
   }
   if (threadIdx.x == 0) {
@@ -228,6 +229,7 @@ __global__ __launch_bounds__(kLzThreads) void k_lanczos(SolverState S, const int
     const double r = S.res[idx] * bn / sqrt(rho.x * rho.x + rho.y * rho.y);
     S.res[idx] = r;
     if (!(r <= S.tol_int)) all_conv = 0;
+    else if (S.conv[idx] < 0) S.conv[idx] = k + 1;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -404,7 +406,8 @@ __global__ __launch_bounds__(kRowThreads) void k_residual(SolverState S, const i
     if (relres <= tol && !(flags & SGW_FLAG_NONFINITE)) flags |= SGW_FLAG_CONVERGED;
     else atomicAdd(n_bad, 1);
     sgw_solve_info inf;
-    inf.iters = S.kcur[slot];
+    const int cj = S.conv[(long)slot * S.n_omega + j];
+    inf.iters = cj >= 0 ? cj : S.kcur[slot];
     inf.flags = flags;
     inf.relres = relres;
     inf.occ_leak = tot[1] > 0.0 ? sqrt(tot[2] / tot[1]) : 0.0;

@@ -33,6 +33,7 @@ struct SolverState {
   double *beta;              // [slots][kmax + 1]; beta[0] = ||b||
   double2 *rho;              // [slots][n_omega] last LU pivot per shift
   double *res;               // [slots][n_omega] estimated relative residual
+  int32_t *conv;             // [slots][n_omega] Krylov dimension at which the estimate met tol_int, or -1
   int32_t *pair;             // [slots] pair index v * n_pert + p
   int32_t *kcur;             // [slots] completed steps
   int32_t *status;           // [slots] SlotStatus

@@ -19,6 +19,10 @@ LIB_PATH = os.path.join(_HERE, "libsgw.so")
 SGW_OK, SGW_NOT_CONVERGED = 0, 1
 SGW_ERR_INVALID_ARG, SGW_ERR_HIP, SGW_ERR_WORKSPACE, SGW_ERR_UNSUPPORTED = -1, -2, -3, -4
 FLAG_CONVERGED, FLAG_MAXITER, FLAG_BREAKDOWN, FLAG_NONFINITE, FLAG_ZERO_RHS = 1, 2, 4, 8, 16
+FLAG_PER_SHIFT = 32
+SOLVER_MULTISHIFT, SOLVER_PER_SHIFT, SOLVER_TAIL = 0, 1, 2
+PC_NONE, PC_TETER, PC_LEARNED = 0, 1, 2
+GUESS_ZERO, GUESS_LEARNED = 0, 1
 
 INFO_DTYPE = np.dtype([("iters", "<i4"), ("flags", "<i4"), ("relres", "<f8"), ("occ_leak", "<f8")])
 
@@ -26,7 +30,9 @@ EXPORTED = [
     "sgw_last_error", "sgw_version", "sgw_ctx_create", "sgw_ctx_destroy", "sgw_ctx_set_profiling",
     "sgw_ctx_reset_stats", "sgw_kernel_stats", "sgw_ham_create", "sgw_ham_destroy", "sgw_ham_npw",
     "sgw_apply_h", "sgw_apply_projector", "sgw_build_rhs", "sgw_opts_default",
-    "sternheimer_workspace_size", "sternheimer_solve",
+    "sternheimer_workspace_size", "sternheimer_solve", "sgw_mlp_num_params", "sgw_mlp_create",
+    "sgw_mlp_destroy", "sgw_mlp_get_weights", "sgw_mlp_set_weights", "sgw_mlp_forward", "sgw_mlp_grad",
+    "sgw_mlp_train_step", "sgw_operator_columns", "sgw_mlp_rows",
 ]
 
 
@@ -44,7 +50,10 @@ class sgw_ham_desc(C.Structure):
 class sgw_opts(C.Structure):
     _fields_ = [("precision", C.c_int32), ("max_iter", C.c_int32), ("alpha_pv", C.c_double),
                 ("tol_safety", C.c_double), ("slots", C.c_int32), ("finalize_batch", C.c_int32),
-                ("steps_per_sync", C.c_int32), ("reserved", C.c_int32)]
+                ("steps_per_sync", C.c_int32), ("solver", C.c_int32), ("precond", C.c_int32),
+                ("guess", C.c_int32), ("tail_iter", C.c_int32), ("ps_max_iter", C.c_int32),
+                ("ps_slots", C.c_int32), ("mlp", C.c_void_p), ("hist_r", C.c_void_p), ("hist_x", C.c_void_p),
+                ("hist_iter", C.c_int32), ("reserved", C.c_int32)]
 
 
 _lib = None
@@ -77,6 +86,15 @@ def load_library(path: str = LIB_PATH):
                                        C.POINTER(sz)],
         "sternheimer_solve": [vp, vp, C.c_int, vp, vp, C.c_int, vp, C.POINTER(dbl), C.c_int, C.POINTER(i32),
                               C.c_int, C.POINTER(dbl), dbl, dbl, C.POINTER(sgw_opts), vp, sz, vp, vp],
+        "sgw_mlp_create": [vp, C.POINTER(C.c_float), C.c_uint64, C.POINTER(vp)],
+        "sgw_mlp_destroy": [vp],
+        "sgw_mlp_get_weights": [vp, C.POINTER(C.c_float)],
+        "sgw_mlp_set_weights": [vp, C.POINTER(C.c_float)],
+        "sgw_mlp_forward": [vp, vp, C.c_int, vp, vp],
+        "sgw_mlp_grad": [vp, vp, C.c_int, vp, vp, vp, vp],
+        "sgw_mlp_train_step": [vp, vp, C.c_int, vp, vp, C.c_float, C.POINTER(C.c_float)],
+        "sgw_operator_columns": [vp, vp, C.c_int, vp, dbl, vp, vp],
+        "sgw_mlp_rows": [vp, vp, vp, vp, C.c_int, C.POINTER(dbl), C.POINTER(dbl), dbl, vp, vp, C.c_int, vp, vp],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -84,6 +102,8 @@ def load_library(path: str = LIB_PATH):
         f.restype = C.c_int
     lib.sgw_ham_npw.argtypes = [vp]
     lib.sgw_ham_npw.restype = C.c_int32
+    lib.sgw_mlp_num_params.argtypes = []
+    lib.sgw_mlp_num_params.restype = C.c_int32
     _lib = lib
     return lib
 
@@ -221,9 +241,14 @@ def sgw_build_rhs(ctx, h_kq, psi_occ_kq, h_k, psi_v, dv_miller):
 
 
 def sgw_opts_default(**overrides):
+    """Default options with overrides; mlp takes an sgw_mlp_create, hist_r / hist_x device tensors."""
     o = sgw_opts()
     _check(load_library().sgw_opts_default(C.byref(o)))
     for k, v in overrides.items():
+        if k == "mlp" and v is not None and hasattr(v, "handle"):
+            v = v.handle.value
+        elif k in ("hist_r", "hist_x") and v is not None and hasattr(v, "data_ptr"):
+            v = v.data_ptr()
         setattr(o, k, v)
     return o
 
@@ -282,3 +307,113 @@ def info_to_numpy(info, shape=None):
     """Device info bytes -> structured numpy array (fields iters, flags, relres, occ_leak)."""
     a = info.cpu().numpy().view(INFO_DTYPE)
     return a.reshape(shape) if shape is not None else a
+
+
+# ---------------------------------------------------------------------------
+# learned preconditioner / initial guess
+# ---------------------------------------------------------------------------
+
+def sgw_mlp_num_params():
+    return int(load_library().sgw_mlp_num_params())
+
+
+class sgw_mlp_create:
+    """The 5-64-64-4 model; init_w: host float32 [num_params] or None (seeded start)."""
+
+    def __init__(self, ctx: sgw_ctx_create, init_w=None, seed: int = 0):
+        lib = load_library()
+        self.ctx = ctx
+        h = C.c_void_p()
+        w = None
+        if init_w is not None:
+            w = np.ascontiguousarray(np.asarray(init_w, np.float32))
+            if w.shape != (sgw_mlp_num_params(),):
+                raise ValueError("init_w has the wrong size")
+        _check(lib.sgw_mlp_create(ctx.handle, w.ctypes.data_as(C.POINTER(C.c_float)) if w is not None else None,
+                                  C.c_uint64(seed), C.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load_library().sgw_mlp_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def get_weights(self):
+        w = np.empty(sgw_mlp_num_params(), np.float32)
+        _check(load_library().sgw_mlp_get_weights(self.handle, w.ctypes.data_as(C.POINTER(C.c_float))))
+        return w
+
+    def set_weights(self, w):
+        w = np.ascontiguousarray(np.asarray(w, np.float32))
+        if w.shape != (sgw_mlp_num_params(),):
+            raise ValueError("weights have the wrong size")
+        _check(load_library().sgw_mlp_set_weights(self.handle, w.ctypes.data_as(C.POINTER(C.c_float))))
+
+
+def sgw_mlp_forward(ctx, mlp, feat):
+    import torch
+    _require(feat, torch.float32, ctx.device, (feat.shape[0], 5), "feat")
+    out = torch.empty((feat.shape[0], 4), dtype=torch.float32, device=ctx.device)
+    _check(load_library().sgw_mlp_forward(ctx.handle, mlp.handle, int(feat.shape[0]), _ptr(feat), _ptr(out)))
+    return out
+
+
+def sgw_mlp_grad(ctx, mlp, feat, target):
+    """Returns (grad [num_params] device float32, loss [1] device float32)."""
+    import torch
+    n = int(feat.shape[0])
+    _require(feat, torch.float32, ctx.device, (n, 5), "feat")
+    _require(target, torch.float32, ctx.device, (n, 8), "target")
+    g = torch.empty(sgw_mlp_num_params(), dtype=torch.float32, device=ctx.device)
+    loss = torch.empty(1, dtype=torch.float32, device=ctx.device)
+    _check(load_library().sgw_mlp_grad(ctx.handle, mlp.handle, n, _ptr(feat), _ptr(target), _ptr(g), _ptr(loss)))
+    return g, loss
+
+
+def sgw_mlp_train_step(ctx, mlp, feat, target, lr):
+    """One Adam step; returns the loss before the step."""
+    import torch
+    n = int(feat.shape[0])
+    _require(feat, torch.float32, ctx.device, (n, 5), "feat")
+    _require(target, torch.float32, ctx.device, (n, 8), "target")
+    loss = C.c_float()
+    _check(load_library().sgw_mlp_train_step(ctx.handle, mlp.handle, n, _ptr(feat), _ptr(target), C.c_float(lr),
+                                             C.byref(loss)))
+    return float(loss.value)
+
+
+def sgw_operator_columns(ctx, ham, psi, alpha=1.0):
+    """(diag, off2): device float64 [n_pw] column statistics of H + alpha P_occ (caller's order)."""
+    import torch
+    _require(psi, torch.complex128, ctx.device, (psi.shape[0], ham.n_pw), "psi")
+    diag = torch.empty(ham.n_pw, dtype=torch.float64, device=ctx.device)
+    off2 = torch.empty_like(diag)
+    _check(load_library().sgw_operator_columns(ctx.handle, ham.handle, int(psi.shape[0]), _ptr(psi), float(alpha),
+                                               _ptr(diag), _ptr(off2)))
+    return diag, off2
+
+
+def sgw_mlp_rows(ctx, ham, diag, off2, eps, omega, eta, r, b, stride=1):
+    """Training rows (feat [2 n_vec P][5], target [2 n_vec P][8]) from residuals r and right-hand sides b."""
+    import torch
+    n_vec = int(r.shape[0])
+    _require(r, torch.complex128, ctx.device, (n_vec, ham.n_pw), "r")
+    _require(b, torch.complex128, ctx.device, (n_vec, ham.n_pw), "b")
+    _require(diag, torch.float64, ctx.device, (ham.n_pw,), "diag")
+    _require(off2, torch.float64, ctx.device, (ham.n_pw,), "off2")
+    e = np.ascontiguousarray(np.asarray(eps, np.float64).reshape(n_vec))
+    om = np.ascontiguousarray(np.asarray(omega, np.float64).reshape(n_vec))
+    per = (ham.n_pw + stride - 1) // stride
+    feat = torch.empty((2 * n_vec * per, 5), dtype=torch.float32, device=ctx.device)
+    tgt = torch.empty((2 * n_vec * per, 8), dtype=torch.float32, device=ctx.device)
+    _check(load_library().sgw_mlp_rows(ctx.handle, ham.handle, _ptr(diag), _ptr(off2), n_vec,
+                                       e.ctypes.data_as(C.POINTER(C.c_double)),
+                                       om.ctypes.data_as(C.POINTER(C.c_double)), float(eta), _ptr(r), _ptr(b),
+                                       int(stride), _ptr(feat), _ptr(tgt)))
+    return feat, tgt

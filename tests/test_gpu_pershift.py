@@ -1,0 +1,252 @@
+"""GPU: per-shift solves (none / Teter / learned), the multishift-then-per-shift
+tail, and the learned model's kernels, through the C ABI, against the oracle.
+
+A diagonal preconditioner and an initial guess change the iteration, not the
+solution, so every mode is held to the same parity bar as the multishift
+solver: 1e-8 relative per solve at tol_eff = 1e-8 / (2 kappa).  The model
+kernels (FP32) are held to the FP64 reference of oracle.mlp_oracle: outputs
+and loss to 1e-5, gradients to 1e-4 relative.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import oracle.mlp_oracle as mo
+import oracle.sternheimer_oracle as so
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from tests.libutil import ensure_library
+    ensure_library()
+    from paper_1812_03717_amd import sgw
+    c = sgw.sgw_ctx_create(0)
+    yield c
+    torch.cuda.synchronize()
+
+
+def _problem():
+    return synth.small((1, 1, 1), n_omega=6, n_pert=5, seed=9100)
+
+
+@pytest.fixture(scope="module")
+def case(ctx):
+    from paper_1812_03717_amd.workload import DeviceProblem
+    p = _problem()
+    d = DeviceProblem(ctx, p)
+    pairs = [(v, q) for v in range(p.n_band) for q in range(p.n_pert)]
+    setup = oracle.spectral_setup(p.miller_kq, p.B, p.kvec + p.qvec, p.v_grid)
+    xs, _ = oracle.solve_pairs(setup, p.n_occ, p.psi_k, p.eps_k, p.miller_k, p.miller_kq, p.dv_miller, p.psi_kq,
+                               p.omega, p.eta, pairs)
+    _, w, _ = setup
+    kap = max(so.condition_number(w, p.n_occ, p.eps_k[v], om + 1j * p.eta) for v in range(p.n_band)
+              for om in p.omega)
+    tol = min(p.tol, 1e-8 / (2.0 * kap))
+    return p, d, pairs, xs, tol
+
+
+def _check_parity(p, pairs, xs, dpsi, inf, tol):
+    from paper_1812_03717_amd import sgw
+    assert np.all(inf["flags"] & sgw.FLAG_CONVERGED), inf["flags"]
+    assert inf["relres"].max() <= tol
+    assert inf["occ_leak"].max() <= 1e-10
+    worst = 0.0
+    for i, (v, q) in enumerate(pairs):
+        for j in range(p.n_omega):
+            ref = xs[i, j]
+            err = np.linalg.norm(dpsi[v, q, j] - ref) / np.linalg.norm(ref)
+            worst = max(worst, err)
+            assert err <= 1e-8, (v, q, j, err)
+    return worst
+
+
+@pytest.mark.parametrize("pc", ["none", "teter"])
+def test_per_shift_matches_oracle(ctx, case, pc):
+    from paper_1812_03717_amd import sgw
+    p, d, pairs, xs, tol = case
+    opts = sgw.sgw_opts_default(solver=sgw.SOLVER_PER_SHIFT,
+                                precond={"none": sgw.PC_NONE, "teter": sgw.PC_TETER}[pc], ps_slots=37,
+                                steps_per_sync=3)
+    st, dpsi, info = d.solve(tol=tol, opts=opts)
+    inf = sgw.info_to_numpy(info, (p.n_band, p.n_pert, p.n_omega))
+    assert st == sgw.SGW_OK, sgw.load_library().sgw_last_error()
+    assert np.all(inf["flags"] & sgw.FLAG_PER_SHIFT)
+    worst = _check_parity(p, pairs, xs, dpsi.cpu().numpy(), inf, tol)
+    print(pc, "per-shift iters mean", inf["iters"].mean(), "max", inf["iters"].max(), "err", worst, flush=True)
+
+
+def test_tail_matches_oracle(ctx, case):
+    """Multishift capped below the slowest shifts; the rest continue per shift from that iterate."""
+    from paper_1812_03717_amd import sgw
+    p, d, pairs, xs, tol = case
+    st, _, info = d.solve(tol=tol)
+    full = sgw.info_to_numpy(info, (p.n_band, p.n_pert, p.n_omega))
+    cap = int(np.median(full["iters"]))
+    opts = sgw.sgw_opts_default(solver=sgw.SOLVER_TAIL, tail_iter=cap, precond=sgw.PC_TETER)
+    st, dpsi, info = d.solve(tol=tol, opts=opts)
+    inf = sgw.info_to_numpy(info, (p.n_band, p.n_pert, p.n_omega))
+    assert st == sgw.SGW_OK, sgw.load_library().sgw_last_error()
+    tail = (inf["flags"] & sgw.FLAG_PER_SHIFT) != 0
+    print("tail cap", cap, "tail solves", tail.sum(), "of", tail.size, "tail iters mean", inf["iters"][tail].mean(),
+          flush=True)
+    assert 0 < tail.sum() < tail.size
+    _check_parity(p, pairs, xs, dpsi.cpu().numpy(), inf, tol)
+
+
+def test_learned_solve_matches_oracle(ctx, case):
+    """Untrained model (m = g = 1/(T+1)) as preconditioner and initial guess: same solutions."""
+    from paper_1812_03717_amd import sgw
+    p, d, pairs, xs, tol = case
+    mlp = sgw.sgw_mlp_create(ctx, seed=5)
+    opts = sgw.sgw_opts_default(solver=sgw.SOLVER_PER_SHIFT, precond=sgw.PC_LEARNED, guess=sgw.GUESS_LEARNED,
+                                mlp=mlp)
+    st, dpsi, info = d.solve(tol=tol, opts=opts)
+    inf = sgw.info_to_numpy(info, (p.n_band, p.n_pert, p.n_omega))
+    assert st == sgw.SGW_OK, sgw.load_library().sgw_last_error()
+    _check_parity(p, pairs, xs, dpsi.cpu().numpy(), inf, tol)
+    mlp.close()
+
+
+def test_per_shift_edge_cases(ctx):
+    """Zero right-hand side, iteration limit, hist snapshot shape, rejected combinations."""
+    from paper_1812_03717_amd import sgw
+    p = synth.si2()
+    from paper_1812_03717_amd.workload import DeviceProblem
+    d = DeviceProblem(ctx, p)
+    opts = sgw.sgw_opts_default(solver=sgw.SOLVER_PER_SHIFT, precond=sgw.PC_TETER)
+    st, dpsi, info = sgw.sternheimer_solve(ctx, d.h_kq, d.psi_occ_kq, d.h_k, d.psi_v, d.eps_v,
+                                           np.zeros((1, 3), np.int32), p.omega[:3], p.eta, 1e-10, opts=opts)
+    inf = sgw.info_to_numpy(info)
+    assert st == sgw.SGW_OK
+    assert np.all(inf["flags"] & sgw.FLAG_ZERO_RHS) and np.all(inf["relres"] == 0)
+    assert torch.count_nonzero(dpsi).item() == 0
+    st, dpsi, info = d.solve(tol=1e-12, opts=sgw.sgw_opts_default(solver=sgw.SOLVER_PER_SHIFT, ps_max_iter=2))
+    inf = sgw.info_to_numpy(info)
+    assert st == sgw.SGW_NOT_CONVERGED
+    assert np.all(inf["flags"] & sgw.FLAG_MAXITER) and np.all(inf["iters"] == 2)
+    assert np.all(np.isfinite(inf["relres"]))
+    # snapshot at iteration 3: r_3 = b - A x_3 for every solve still running at 3
+    nb, npt, nw, npw = p.n_band, p.n_pert, p.n_omega, d.h_kq.n_pw
+    hr = torch.zeros((nb, npt, nw, npw), dtype=torch.complex128, device=ctx.device)
+    hx = torch.zeros_like(hr)
+    st, dpsi, info = d.solve(tol=1e-10, opts=sgw.sgw_opts_default(solver=sgw.SOLVER_PER_SHIFT, hist_r=hr, hist_x=hx,
+                                                                  hist_iter=3))
+    assert st == sgw.SGW_OK
+    inf = sgw.info_to_numpy(info, (nb, npt, nw))
+    h = so.hamiltonian(p.miller_kq, p.B, p.kvec, p.v_grid)
+    hr, hx = hr.cpu().numpy(), hx.cpu().numpy()
+    checked = 0
+    for v, q, j in [(3, 1, 0), (2, 0, 5), (0, 3, 7)]:
+        if inf["iters"][v, q, j] <= 3:
+            continue
+        b = so.rhs(p.psi_k[v], p.miller_k, p.miller_kq, p.dv_miller[q], p.psi_kq)
+        a = so.coulomb_operator(h, p.psi_kq, p.eps_k[v], 1.0) - (p.omega[j] + 1j * p.eta) * np.eye(npw)
+        r = b - a @ hx[v, q, j]
+        assert np.linalg.norm(r - hr[v, q, j]) <= 1e-9 * np.linalg.norm(b)
+        checked += 1
+    assert checked > 0
+    # a preconditioner with the multishift solver breaks the shared Krylov space: rejected
+    with pytest.raises(sgw.SgwError):
+        d.solve(tol=1e-8, opts=sgw.sgw_opts_default(precond=sgw.PC_TETER))
+    with pytest.raises(sgw.SgwError):
+        d.solve(tol=1e-8, opts=sgw.sgw_opts_default(solver=sgw.SOLVER_PER_SHIFT, precond=sgw.PC_LEARNED))
+
+
+def test_operator_columns_and_rows(ctx, case):
+    """Column statistics of H + alpha P and the training rows built from them, against the oracle."""
+    from paper_1812_03717_amd import sgw
+    p, d, _, _, _ = case
+    k = p.kvec + p.qvec
+    diag, off2 = sgw.sgw_operator_columns(ctx, d.h_kq, d.psi_occ_kq, 1.0)
+    h = so.hamiltonian(p.miller_kq, p.B, k, p.v_grid)
+    dr, o2r = mo.operator_columns(so.coulomb_operator(h, p.psi_kq, 0.0, 1.0))
+    diag, off2 = diag.cpu().numpy(), off2.cpu().numpy()
+    assert np.abs(diag - dr).max() <= 1e-12 * np.abs(dr).max()
+    assert np.abs(off2 - o2r).max() <= 1e-11 * np.abs(o2r).max()
+    rng = np.random.default_rng(21)
+    n_vec, npw = 3, p.n_pw_kq
+    r = rng.standard_normal((n_vec, npw)) + 1j * rng.standard_normal((n_vec, npw))
+    b = rng.standard_normal((n_vec, npw)) + 1j * rng.standard_normal((n_vec, npw))
+    eps = p.eps_k[:n_vec]
+    om = p.omega[[0, 2, 4]]
+    for stride in (1, 3):
+        f, t = sgw.sgw_mlp_rows(ctx, d.h_kq, torch.from_numpy(dr).to(ctx.device), torch.from_numpy(o2r).to(ctx.device),
+                                eps, om, p.eta, torch.from_numpy(r).to(ctx.device), torch.from_numpy(b).to(ctx.device),
+                                stride=stride)
+        fr, tr = mo.rows(so.kinetic(p.miller_kq, p.B, k), dr, o2r, eps, om, p.eta, r, b, stride=stride)
+        assert f.shape == fr.shape and t.shape == tr.shape
+        assert np.abs(f.cpu().numpy() - fr).max() <= 1e-6 * np.abs(fr).max()
+        assert np.abs(t.cpu().numpy() - tr).max() <= 1e-6 * np.abs(tr).max()
+
+
+def _rows(seed, n):
+    rng = np.random.default_rng(seed)
+    t = rng.uniform(0.0, 11.0, n)
+    feat = mo.features(t, rng.uniform(-1.0, 0.4, n), rng.uniform(0.0, 1.5, n), 0.0018).astype(np.float32)
+    target = rng.standard_normal((n, 8)).astype(np.float32)
+    return feat, target
+
+
+@pytest.mark.parametrize("n_rows", [1, 63, 1000, 4097])
+def test_mlp_forward_grad_vs_oracle(ctx, n_rows):
+    from paper_1812_03717_amd import sgw
+    rng = np.random.default_rng(n_rows)
+    w = (0.3 * rng.standard_normal(mo.N_PARAMS)).astype(np.float32)
+    mlp = sgw.sgw_mlp_create(ctx, init_w=w)
+    assert np.array_equal(mlp.get_weights(), w)
+    feat, target = _rows(n_rows + 1, n_rows)
+    ft = torch.from_numpy(feat).to(ctx.device)
+    tt = torch.from_numpy(target).to(ctx.device)
+    out = sgw.sgw_mlp_forward(ctx, mlp, ft).cpu().numpy()
+    ref, _ = mo.forward(w.astype(np.float64), feat.astype(np.float64))
+    assert np.abs(out - ref).max() <= 1e-5 * max(1.0, np.abs(ref).max())
+    g, loss = sgw.sgw_mlp_grad(ctx, mlp, ft, tt)
+    g = g.cpu().numpy().astype(np.float64)
+    gr = mo.grad(w.astype(np.float64), feat.astype(np.float64), target.astype(np.float64))
+    lr_ = mo.loss(w.astype(np.float64), feat.astype(np.float64), target.astype(np.float64))
+    rel = np.linalg.norm(g - gr) / np.linalg.norm(gr)
+    print("rows", n_rows, "grad rel err", rel, "loss", loss.item(), lr_, flush=True)
+    assert rel <= 1e-4
+    assert abs(loss.item() - lr_) <= 1e-5 * lr_
+    # deterministic: the same call gives the same bits
+    g2, _ = sgw.sgw_mlp_grad(ctx, mlp, ft, tt)
+    assert np.array_equal(g2.cpu().numpy().astype(np.float64), g)
+    mlp.close()
+
+
+def test_mlp_adam_step_and_training(ctx):
+    """First Adam step moves each weight by -lr * sign(g); 300 steps cut the loss of a learnable target."""
+    from paper_1812_03717_amd import sgw
+    rng = np.random.default_rng(11)
+    w0 = (0.2 * rng.standard_normal(mo.N_PARAMS)).astype(np.float32)
+    mlp = sgw.sgw_mlp_create(ctx, init_w=w0)
+    feat, _ = _rows(12, 3000)
+    # learnable target: w_m = u_m / (T - eps - omega + 1 - i eta'), w_g = u_g / (T + 2)
+    t = feat[:, 0].astype(np.float64) * 10.0
+    e = feat[:, 1] * 10.0
+    om = feat[:, 2]
+    u = rng.standard_normal((3000, 2)) + 1j * rng.standard_normal((3000, 2))
+    wm = u[:, 0] / (np.abs(t - e - om) + 1.0 - 0.3j)
+    wg = u[:, 1] / (t + 2.0)
+    target = np.stack([u[:, 0].real, u[:, 0].imag, wm.real, wm.imag, u[:, 1].real, u[:, 1].imag, wg.real, wg.imag],
+                      axis=1).astype(np.float32)
+    ft = torch.from_numpy(feat).to(ctx.device)
+    tt = torch.from_numpy(target).to(ctx.device)
+    lr = 1e-3
+    gr = mo.grad(w0.astype(np.float64), feat.astype(np.float64), target.astype(np.float64))
+    loss0 = sgw.sgw_mlp_train_step(ctx, mlp, ft, tt, lr)
+    w1 = mlp.get_weights().astype(np.float64)
+    big = np.abs(gr) > 1e-3 * np.abs(gr).max()
+    step = (w1 - w0)[big]
+    assert np.allclose(step, -lr * np.sign(gr[big]), rtol=1e-3, atol=2e-7)
+    losses = [loss0] + [sgw.sgw_mlp_train_step(ctx, mlp, ft, tt, lr) for _ in range(300)]
+    print("loss", losses[0], "->", losses[-1], flush=True)
+    assert losses[-1] < 0.2 * losses[0]
+    mlp.close()
