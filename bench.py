@@ -34,6 +34,9 @@ WORKLOADS = {
             "eta 0.05 eV, tol 1e-8",
     "si2": "si2: diamond fcc primitive (2 atoms), 307 PW, 16^3 grid, 4 bands x 4 perts x 8 omega in [0,20] eV, "
            "eta 0.1 eV, tol 1e-10",
+    "batch200": "batch200: 200 independent diamond fcc n0 x n1 x n2 cells (n_d in 1..3, 2-54 atoms), grid 24 n_d "
+                "per axis, Ecut 4 Ha (100-2800 PW), all ~2*atoms occupied bands, 16-128 omega in [0,40] eV, "
+                "4-16 perts at an own seeded q, eta 0.05 eV, tol 1e-8",
 }
 
 KERNELS = ["hx_sticks_inv", "hx_planes", "hx_sticks_fwd", "proj_dot", "proj_apply", "lanczos_step", "slot_init", "rhs_source",
@@ -108,6 +111,87 @@ def cpu_baseline(problem, n_pairs_sample, log):
                       f"all {n_total_pairs * p.n_omega} solves / (setup + per-pair time x {n_total_pairs})"}
 
 
+def bench_batch(args, log):
+    """Batches of uneven systems: sternheimer_solve_batch over all of them (one step) after autotuning
+    each system class; the same systems solved one after another with default options give the
+    sequential reference."""
+    import torch
+    import synth
+    from paper_1812_03717_amd import sgw
+    from paper_1812_03717_amd.workload import DeviceProblem
+
+    t0 = time.perf_counter()
+    problems = synth.batch(200, workers=min(16, os.cpu_count() or 1))
+    n_solves = sum(p.n_solves for p in problems)
+    log(f"generated 200 systems, {n_solves} solves ({time.perf_counter() - t0:.1f} s)")
+    ctx = sgw.sgw_ctx_create(0)
+    devs = [DeviceProblem(ctx, p) for p in problems]
+    ws = sgw.Workspace(ctx)
+    batch = sgw.Batch(ctx)
+    # the largest cells (72^3, ~110 bands, dense spectrum in the frequency window) need up to ~4000
+    # Krylov steps for their upper bands; the slot count is fitted to the workspace
+    opts = lambda: sgw.sgw_opts_default(max_iter=args.batch_max_iter)
+    for d in devs:
+        p = d.problem
+        batch.add(d.h_kq, d.psi_occ_kq, d.h_k, d.psi_v, d.eps_v, p.dv_miller, p.omega, p.eta, p.tol, opts=opts())
+    t = time.perf_counter()
+    tune_ms = sum(batch.autotune(i) for i in range(len(devs)))
+    log(f"autotune: {tune_ms / 1e3:.2f} s (wall {time.perf_counter() - t:.2f} s); steps_per_sync/graph chosen: "
+        f"{sorted({(it['problem'].opts.steps_per_sync, it['problem'].opts.graph) for it in batch.items})}")
+    workers = args.batch_workers
+
+    def ok_count(items):
+        n = 0
+        for it in items:
+            inf = sgw.info_to_numpy(it["info"])
+            n += int(np.count_nonzero((inf["flags"] & sgw.FLAG_CONVERGED) != 0))
+        return n
+
+    # sequential reference: one system at a time, default options, the library's own stream
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    seq_ok = 0
+    for d, it in zip(devs, batch.items):
+        st, _, info = d.solve(workspace=ws, opts=opts())
+        inf = sgw.info_to_numpy(info)
+        seq_ok += int(np.count_nonzero((inf["flags"] & sgw.FLAG_CONVERGED) != 0))
+    torch.cuda.synchronize()
+    seq_s = time.perf_counter() - t
+    log(f"sequential: {seq_s:.3f} s, converged {seq_ok}/{n_solves}")
+    for w in range(max(args.warmup, 1)):
+        t = time.perf_counter()
+        st = batch.solve(n_workers=workers, workspace=ws)
+        torch.cuda.synchronize()
+        log(f"warmup {w}: status {st}, {time.perf_counter() - t:.3f} s")
+    ctx.reset_stats()
+    ctx.set_profiling("hx_planes")
+    n_ok = 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        batch.solve(n_workers=workers, workspace=ws)
+        n_ok += ok_count(batch.items)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ctx.set_profiling(None)
+    ks = ctx.kernel_stats("hx_planes")
+    value = n_ok / elapsed
+    log(f"batch: {elapsed / args.steps:.3f} s per step, converged {n_ok}/{n_solves * args.steps}")
+    out = {
+        "metric": "Sternheimer solves/s (band x omega x pert) at true FP64 rel. residual <= tol",
+        "value": round(value, 1), "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(1e3 * elapsed / args.steps, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "speedup_vs_sequential": round(value / (seq_ok / seq_s), 3), "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": WORKLOADS["batch200"], "solves_per_step": n_solves, "workers": workers,
+                   "autotune_s": round(tune_ms / 1e3, 3), "sequential_solves_per_s": round(seq_ok / seq_s, 1),
+                   "max_iter": args.batch_max_iter,
+                   "method": "plain FP64 multishift Lanczos-FOM, batched over worker streams, autotuned"},
+        "roofline": roofline("hx_planes", ks, "batch200"),
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -116,6 +200,8 @@ def main():
     ap.add_argument("--workload", default="si16", choices=sorted(WORKLOADS))
     ap.add_argument("--slots", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batch-workers", type=int, default=4)
+    ap.add_argument("--batch-max-iter", type=int, default=4000)
     ap.add_argument("--cpu-sample-pairs", type=int, default=160)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 5 device-to-device copies of MIB MiB (HBM counter calibration) and exit")
@@ -147,6 +233,8 @@ def main():
         log("no GPU available")
         sys.exit(1)
     sgw.load_library()
+    if args.workload == "batch200":
+        return bench_batch(args, log)
     t0 = time.perf_counter()
     problem = getattr(synth, args.workload)()
     log(f"generated {args.workload}: {problem.n_pw_kq} PW, grid {problem.grid}, {problem.n_solves} solves "

@@ -191,7 +191,10 @@ typedef struct {
                                untouched for solves that finished earlier */
   sgw_c128 *hist_x;         /* optional device out, same shape: the iterate x_k with r_k */
   int32_t hist_iter;        /* iteration of the snapshot (> 0 with hist_r, hist_x) */
-  int32_t reserved;
+  int32_t graph;            /* 1: the multishift solver captures the Krylov steps between two
+                               polls in a HIP graph and replays it (re-captured when the number
+                               of active slots changes; ignored while kernel timing is on and
+                               on the legacy default stream, which cannot be captured) */
 } sgw_opts;
 
 /* Fills *opts with the defaults. */
@@ -239,6 +242,61 @@ sgw_status sternheimer_solve(sgw_ctx *ctx, const sgw_ham *h_kq, int n_occ, const
                              int n_pert, const int32_t *dv_miller, int n_omega, const double *omega,
                              double eta, double tol, const sgw_opts *opts, void *workspace,
                              size_t workspace_bytes, sgw_c128 *dpsi, sgw_solve_info *info);
+
+/*
+ * Batches of independent systems (each a Sternheimer problem of Sec. 2.3,
+ * Eqs. 6-8, with its own Hamiltonians, bands, perturbations and frequencies).
+ * The arguments of one sternheimer_solve call, plus per-system options and outputs.
+ */
+typedef struct {
+  const sgw_ham *h_kq;
+  const sgw_ham *h_k;
+  int32_t n_occ, n_band, n_pert, n_omega;
+  const sgw_c128 *psi_occ_kq;   /* device [n_occ][n_pw_kq] */
+  const sgw_c128 *psi_v;        /* device [n_band][n_pw_k] */
+  const double *eps_v;          /* host [n_band] */
+  const int32_t *dv_miller;     /* host [n_pert][3] */
+  const double *omega;          /* host [n_omega] */
+  double eta, tol;
+  sgw_opts opts;                /* per-system options (for example from sgw_autotune) */
+  sgw_c128 *dpsi;               /* device out [n_band][n_pert][n_omega][n_pw_kq] */
+  sgw_solve_info *info;         /* device out [n_band][n_pert][n_omega] */
+  int32_t status;               /* out: this system's sgw_status */
+  int32_t worker;               /* out: worker stream that solved it */
+  double ms;                    /* out: wall time of its solve on that worker */
+} sgw_problem;
+
+/*
+ * Workspace for sternheimer_solve_batch with n_workers workers: n_workers equal
+ * parts, each large enough for every system with its slot count fitted to a
+ * per-worker share of the default memory budget.
+ */
+sgw_status sternheimer_batch_workspace_size(sgw_ctx *ctx, int n_sys, const sgw_problem *problems, int n_workers,
+                                            size_t *bytes);
+/*
+ * Solves every system of the batch.  n_workers (1..16) worker streams of the
+ * context's device, each driven by its own host thread, take systems from one
+ * queue in order of decreasing predicted cost and solve them exactly as
+ * sternheimer_solve would (results are identical), each in its own part of the
+ * workspace; a multishift system's slot count is lowered to fit that part.
+ * Small systems thereby share the GPU.  The workers start after the work already
+ * enqueued on the context's stream; the call returns when all systems are done.
+ * Returns the first error (problems[i].status tells which), else SGW_NOT_CONVERGED
+ * if any system did not converge, else SGW_OK.  Kernel timing statistics of the
+ * workers are added to the context's.
+ */
+sgw_status sternheimer_solve_batch(sgw_ctx *ctx, int n_sys, sgw_problem *problems, int n_workers, void *workspace,
+                                   size_t workspace_bytes);
+/*
+ * Autotuner for the multishift solver: times the candidate settings of
+ * steps_per_sync (4, 8, 16) and graph (0, 1) on a sample of the problem (its two
+ * highest bands, up to eight perturbations, all frequencies; allocates the sample's
+ * buffers) and writes problem->opts with the fastest of them to *best.  Results
+ * are cached in the context per class (the grid, and n_pw, n_occ and n_omega each
+ * to within a factor sqrt(2)); a cached class
+ * returns at once with *tune_ms = 0.  tune_ms (may be NULL): wall time spent.
+ */
+sgw_status sgw_autotune(sgw_ctx *ctx, const sgw_problem *problem, sgw_opts *best, double *tune_ms);
 
 /*
  * Learned diagonal preconditioner and initial guess for the per-shift solves

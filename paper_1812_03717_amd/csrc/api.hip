@@ -3,11 +3,15 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <numeric>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "pershift.h"
@@ -512,6 +516,7 @@ extern "C" sgw_status sgw_opts_default(sgw_opts *o) {
   o->hist_r = nullptr;
   o->hist_x = nullptr;
   o->hist_iter = 0;
+  o->graph = 0;
   return SGW_OK;
 }
 
@@ -556,6 +561,7 @@ sgw_opts resolve_opts(const sgw_opts *in) {
     o.hist_r = in->hist_r;
     o.hist_x = in->hist_x;
     o.hist_iter = in->hist_iter;
+    o.graph = in->graph;
   }
   return o;
 }
@@ -651,6 +657,40 @@ static sgw_status validate_solve(sgw_ctx *ctx, const sgw_ham *h_kq, int n_occ, c
   if (lanczos_ept(h_kq->n_pw) > 32) return fail(SGW_ERR_UNSUPPORTED, "sternheimer_solve: basis above 16384");
   return check_miller_shift(dv_miller, n_pert);
 }
+
+// A captured sequence of launches on one stream, replayed with hipGraphLaunch.
+struct StepGraph {
+  hipGraphExec_t exec = nullptr;
+  int na = -1;
+  StepGraph() = default;
+  StepGraph(const StepGraph &) = delete;
+  StepGraph &operator=(const StepGraph &) = delete;
+  ~StepGraph() {
+    if (exec) hipGraphExecDestroy(exec);
+  }
+  template <class F>
+  sgw_status capture(hipStream_t stream, F &&launches) {
+    if (exec) hipGraphExecDestroy(exec);
+    exec = nullptr;
+    na = -1;
+    SGW_HIP(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+    const sgw_status st = launches();
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(stream, &g);
+    if (st != SGW_OK) {
+      if (g) hipGraphDestroy(g);
+      return st;
+    }
+    if (e != hipSuccess) return fail(SGW_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    const hipError_t e2 = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (e2 != hipSuccess) {
+      exec = nullptr;
+      return fail(SGW_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e2));
+    }
+    return SGW_OK;
+  }
+};
 
 // options of the multishift phase of a TAIL solve
 static sgw_opts tail_phase_opts(const sgw_opts &o) {
@@ -766,6 +806,7 @@ static sgw_status multishift_solve(sgw_ctx *ctx, const sgw_ham *h_kq, int n_occ,
   for (int s = S - 1; s >= 0; --s) free_slots.push_back(s);
   const VecSrc cur{Sx.basis, npw, d_active, Sx.kcur, Sx.slot_stride};
   const VecSrc xsrc = contiguous(X, npw);
+  StepGraph graph;
   size_t finalized = 0;
   double ksum = 0;
   long kcount = 0;
@@ -828,11 +869,27 @@ static sgw_status multishift_solve(sgw_ctx *ctx, const sgw_ham *h_kq, int n_occ,
       std::memcpy(p_active, active.data(), sizeof(int32_t) * active.size());
       const int na = (int)active.size();
       SGW_HIP(hipMemcpyAsync(d_active, p_active, sizeof(int32_t) * na, hipMemcpyHostToDevice, ctx->stream));
-      for (int step = 0; step < L.M; ++step) {
-        if ((st = proj_dot(ctx, npw, n_occ, Sx.psi, na, cur, C, crow)) != SGW_OK) return st;
-        if ((st = hx_batch(ctx, h_kq, na, cur, Y, npw, T)) != SGW_OK) return st;
-        if ((st = proj_apply(ctx, npw, n_occ, Sx.psi, na, cur, C, crow, Y, npw, o.alpha_pv, 1)) != SGW_OK) return st;
-        if ((st = lanczos_step(ctx, Sx, na, d_active, Y)) != SGW_OK) return st;
+      auto steps = [&]() -> sgw_status {
+        sgw_status s2;
+        for (int step = 0; step < L.M; ++step) {
+          if ((s2 = proj_dot(ctx, npw, n_occ, Sx.psi, na, cur, C, crow)) != SGW_OK) return s2;
+          if ((s2 = hx_batch(ctx, h_kq, na, cur, Y, npw, T)) != SGW_OK) return s2;
+          if ((s2 = proj_apply(ctx, npw, n_occ, Sx.psi, na, cur, C, crow, Y, npw, o.alpha_pv, 1)) != SGW_OK) return s2;
+          if ((s2 = lanczos_step(ctx, Sx, na, d_active, Y)) != SGW_OK) return s2;
+        }
+        return SGW_OK;
+      };
+      // The launches read the active list from device memory, so a captured
+      // sequence depends only on the number of active slots.  The legacy
+      // default stream cannot be captured: launches stay eager there.
+      if (o.graph && ctx->profile_mask == 0 && ctx->stream != nullptr) {
+        if (graph.na != na) {
+          if ((st = graph.capture(ctx->stream, steps)) != SGW_OK) return st;
+          graph.na = na;
+        }
+        SGW_HIP(hipGraphLaunch(graph.exec, ctx->stream));
+      } else if ((st = steps()) != SGW_OK) {
+        return st;
       }
     }
     // poll
@@ -859,49 +916,342 @@ static sgw_status multishift_solve(sgw_ctx *ctx, const sgw_ham *h_kq, int n_occ,
   return *p_bad > 0 ? SGW_NOT_CONVERGED : SGW_OK;
 }
 
-extern "C" sgw_status sternheimer_solve(sgw_ctx *ctx, const sgw_ham *h_kq, int n_occ, const sgw_c128 *psi_occ_kq,
-                                        const sgw_ham *h_k, int n_band, const sgw_c128 *psi_v, const double *eps_v,
-                                        int n_pert, const int32_t *dv_miller, int n_omega, const double *omega,
-                                        double eta, double tol, const sgw_opts *opts, void *workspace,
-                                        size_t workspace_bytes, sgw_c128 *dpsi, sgw_solve_info *info) {
-  const sgw_opts o = resolve_opts(opts);
-  sgw_status st = validate_solve(ctx, h_kq, n_occ, psi_occ_kq, h_k, n_band, psi_v, eps_v, n_pert, dv_miller,
-                                 n_omega, omega, eta, tol, o);
+// Validation of one problem with resolved options (no GPU work).
+static sgw_status check_problem(sgw_ctx *ctx, const sgw_problem &p, const sgw_opts &o) {
+  sgw_status st = validate_solve(ctx, p.h_kq, p.n_occ, p.psi_occ_kq, p.h_k, p.n_band, p.psi_v, p.eps_v, p.n_pert,
+                                 p.dv_miller, p.n_omega, p.omega, p.eta, p.tol, o);
   if (st != SGW_OK) return st;
-  const long n_sys = (long)n_band * n_pert * n_omega;
+  const long n_sys = (long)p.n_band * p.n_pert * p.n_omega;
   if (n_sys == 0) return SGW_OK;
-  SGW_CHECK(dpsi && info, "sternheimer_solve: NULL output array");
+  SGW_CHECK(p.dpsi && p.info, "sternheimer_solve: NULL output array");
   SGW_CHECK(n_sys < (1L << 31), "sternheimer_solve: more than 2^31 solves in one call");
-  const size_t need = solve_workspace_bytes(h_kq, n_occ, n_band, n_pert, n_omega, o);
+  return SGW_OK;
+}
+
+static size_t problem_workspace_bytes(const sgw_problem &p, const sgw_opts &o) {
+  return solve_workspace_bytes(p.h_kq, p.n_occ, p.n_band, p.n_pert, std::max(p.n_omega, 1), o);
+}
+
+// The solve of a validated problem on ctx's stream, dispatched on the solver.
+static sgw_status run_solve(sgw_ctx *ctx, const sgw_problem &p, const sgw_opts &o, void *workspace,
+                            size_t workspace_bytes) {
+  const long n_sys = (long)p.n_band * p.n_pert * p.n_omega;
+  if (n_sys == 0) return SGW_OK;
+  const size_t need = problem_workspace_bytes(p, o);
   if (!workspace || workspace_bytes < need)
     return fail(SGW_ERR_WORKSPACE, "sternheimer_solve: workspace needs " + std::to_string(need) + " bytes");
   if (((uintptr_t)workspace) % kAlign != 0)
     return fail(SGW_ERR_WORKSPACE, "sternheimer_solve: workspace must be 256-byte aligned");
   SGW_HIP(hipSetDevice(ctx->device));
-  PsProblem P{h_kq, h_k, n_occ, (const double2 *)psi_occ_kq, n_band, (const double2 *)psi_v, eps_v, n_pert,
-              dv_miller, n_omega, omega, eta, tol};
+  sgw_status st;
+  PsProblem P{p.h_kq, p.h_k, p.n_occ, (const double2 *)p.psi_occ_kq, p.n_band, (const double2 *)p.psi_v, p.eps_v,
+              p.n_pert, p.dv_miller, p.n_omega, p.omega, p.eta, p.tol};
   if (o.solver == SGW_SOLVER_PER_SHIFT) {
     int n_bad = 0;
-    if ((st = ps_solve(ctx, P, o, {}, false, workspace, workspace_bytes, (double2 *)dpsi, info, &n_bad)) != SGW_OK)
+    if ((st = ps_solve(ctx, P, o, {}, false, workspace, workspace_bytes, (double2 *)p.dpsi, p.info, &n_bad)) !=
+        SGW_OK)
       return st;
     return n_bad > 0 ? SGW_NOT_CONVERGED : SGW_OK;
   }
   if (o.solver == SGW_SOLVER_MULTISHIFT)
-    return multishift_solve(ctx, h_kq, n_occ, psi_occ_kq, h_k, n_band, psi_v, eps_v, n_pert, dv_miller, n_omega,
-                            omega, eta, tol, o, workspace, dpsi, info);
+    return multishift_solve(ctx, p.h_kq, p.n_occ, p.psi_occ_kq, p.h_k, p.n_band, p.psi_v, p.eps_v, p.n_pert,
+                            p.dv_miller, p.n_omega, p.omega, p.eta, p.tol, o, workspace, p.dpsi, p.info);
   // TAIL: multishift up to tail_iter, then the shifts above tol per shift from their multishift iterate
-  st = multishift_solve(ctx, h_kq, n_occ, psi_occ_kq, h_k, n_band, psi_v, eps_v, n_pert, dv_miller, n_omega, omega,
-                        eta, tol, tail_phase_opts(o), workspace, dpsi, info);
+  st = multishift_solve(ctx, p.h_kq, p.n_occ, p.psi_occ_kq, p.h_k, p.n_band, p.psi_v, p.eps_v, p.n_pert,
+                        p.dv_miller, p.n_omega, p.omega, p.eta, p.tol, tail_phase_opts(o), workspace, p.dpsi, p.info);
   if (st != SGW_OK && st != SGW_NOT_CONVERGED) return st;
   if (st == SGW_OK) return SGW_OK;
   std::vector<sgw_solve_info> hinfo(n_sys);
-  SGW_HIP(hipMemcpyAsync(hinfo.data(), info, sizeof(sgw_solve_info) * n_sys, hipMemcpyDeviceToHost, ctx->stream));
+  SGW_HIP(hipMemcpyAsync(hinfo.data(), p.info, sizeof(sgw_solve_info) * n_sys, hipMemcpyDeviceToHost, ctx->stream));
   if ((st = sync(ctx)) != SGW_OK) return st;
   std::vector<int32_t> tail;
   for (long y = 0; y < n_sys; ++y)
     if (!(hinfo[y].flags & SGW_FLAG_CONVERGED)) tail.push_back((int32_t)y);
   int n_bad = 0;
-  if ((st = ps_solve(ctx, P, o, tail, true, workspace, workspace_bytes, (double2 *)dpsi, info, &n_bad)) != SGW_OK)
+  if ((st = ps_solve(ctx, P, o, tail, true, workspace, workspace_bytes, (double2 *)p.dpsi, p.info, &n_bad)) !=
+      SGW_OK)
     return st;
   return n_bad > 0 ? SGW_NOT_CONVERGED : SGW_OK;
+}
+
+extern "C" sgw_status sternheimer_solve(sgw_ctx *ctx, const sgw_ham *h_kq, int n_occ, const sgw_c128 *psi_occ_kq,
+                                        const sgw_ham *h_k, int n_band, const sgw_c128 *psi_v, const double *eps_v,
+                                        int n_pert, const int32_t *dv_miller, int n_omega, const double *omega,
+                                        double eta, double tol, const sgw_opts *opts, void *workspace,
+                                        size_t workspace_bytes, sgw_c128 *dpsi, sgw_solve_info *info) {
+  sgw_problem p;
+  std::memset(&p, 0, sizeof(p));
+  p.h_kq = h_kq;
+  p.h_k = h_k;
+  p.n_occ = n_occ;
+  p.n_band = n_band;
+  p.n_pert = n_pert;
+  p.n_omega = n_omega;
+  p.psi_occ_kq = psi_occ_kq;
+  p.psi_v = psi_v;
+  p.eps_v = eps_v;
+  p.dv_miller = dv_miller;
+  p.omega = omega;
+  p.eta = eta;
+  p.tol = tol;
+  p.dpsi = dpsi;
+  p.info = info;
+  const sgw_opts o = resolve_opts(opts);
+  const sgw_status st = check_problem(ctx, p, o);
+  if (st != SGW_OK) return st;
+  return run_solve(ctx, p, o, workspace, workspace_bytes);
+}
+
+// ---------------------------------------------------------------------------
+// batches of systems and the autotuner
+// ---------------------------------------------------------------------------
+namespace {
+
+// Multishift options whose workspace fits `budget` bytes: the slot count (and the
+// finalisation batch) are lowered from the requested or automatic values.
+sgw_opts fit_to_budget(const sgw_problem &p, sgw_opts o, size_t budget) {
+  if (o.solver != SGW_SOLVER_MULTISHIFT) return o;
+  const int n_omega = std::max(p.n_omega, 1);
+  Layout L = make_layout(p.h_kq, p.n_occ, p.n_band, p.n_pert, n_omega, o);
+  o.slots = L.S;
+  o.finalize_batch = L.F;
+  while (L.total > budget && (o.slots > 1 || o.finalize_batch > 1)) {
+    if (o.slots > 1) o.slots = std::max(1, o.slots * 3 / 4);
+    if (o.finalize_batch > 1 && (o.slots == 1 || (long)o.finalize_batch * n_omega > o.slots))
+      o.finalize_batch = std::max(1, o.finalize_batch * 3 / 4);
+    L = make_layout(p.h_kq, p.n_occ, p.n_band, p.n_pert, n_omega, o);
+  }
+  return o;
+}
+
+double predicted_cost(const sgw_problem &p) {
+  const double npw = p.h_kq->n_pw;
+  const double grid = (double)p.h_kq->n[0] * p.h_kq->n[1] * p.h_kq->n[2];
+  const double pairs = (double)p.n_band * p.n_pert;
+  // Krylov steps (~100 per pair, each an FFT H.x and the projector) plus the residual of every shift
+  return pairs * (100.0 + p.n_omega) * (grid * std::log2(std::max(grid, 2.0)) / 8.0 + npw * (p.n_occ + 8));
+}
+
+}  // namespace
+
+extern "C" sgw_status sternheimer_batch_workspace_size(sgw_ctx *ctx, int n_sys, const sgw_problem *problems,
+                                                       int n_workers, size_t *bytes) {
+  if (!ctx || !bytes || (n_sys > 0 && !problems))
+    return fail(SGW_ERR_INVALID_ARG, "sternheimer_batch_workspace_size: NULL argument");
+  if (n_sys < 0 || n_workers < 1 || n_workers > kMaxWorkers)
+    return fail(SGW_ERR_INVALID_ARG, "sternheimer_batch_workspace_size: bad n_sys or n_workers");
+  const size_t budget = (size_t)(kDefaultBudget / n_workers) / kAlign * kAlign;
+  size_t part = 0;
+  for (int i = 0; i < n_sys; ++i) {
+    if (!problems[i].h_kq) return fail(SGW_ERR_INVALID_ARG, "sternheimer_batch_workspace_size: NULL Hamiltonian");
+    const sgw_opts o = fit_to_budget(problems[i], resolve_opts(&problems[i].opts), budget);
+    part = std::max(part, problem_workspace_bytes(problems[i], o));
+  }
+  part = (part + kAlign - 1) / kAlign * kAlign;
+  *bytes = part * n_workers;
+  return SGW_OK;
+}
+
+extern "C" sgw_status sternheimer_solve_batch(sgw_ctx *ctx, int n_sys, sgw_problem *problems, int n_workers,
+                                              void *workspace, size_t workspace_bytes) {
+  SGW_CHECK(ctx, "sternheimer_solve_batch: NULL context");
+  SGW_CHECK(n_sys >= 0 && (n_sys == 0 || problems), "sternheimer_solve_batch: bad problem array");
+  SGW_CHECK(n_workers >= 1 && n_workers <= kMaxWorkers, "sternheimer_solve_batch: n_workers out of range");
+  if (n_sys == 0) return SGW_OK;
+  SGW_CHECK(workspace && ((uintptr_t)workspace) % kAlign == 0, "sternheimer_solve_batch: workspace missing or unaligned");
+  const size_t part = workspace_bytes / n_workers / kAlign * kAlign;
+  std::vector<sgw_opts> opts(n_sys);
+  for (int i = 0; i < n_sys; ++i) {
+    sgw_problem &p = problems[i];
+    p.status = SGW_OK;
+    p.worker = -1;
+    p.ms = 0.0;
+    const sgw_opts o = resolve_opts(&p.opts);
+    sgw_status st = check_problem(ctx, p, o);
+    if (st != SGW_OK) {
+      p.status = st;
+      return fail(st, "problem " + std::to_string(i) + ": " + sgw_last_error());
+    }
+    opts[i] = fit_to_budget(p, o, part);
+    if (problem_workspace_bytes(p, opts[i]) > part) {
+      p.status = SGW_ERR_WORKSPACE;
+      return fail(SGW_ERR_WORKSPACE, "sternheimer_solve_batch: problem " + std::to_string(i) +
+                                         " does not fit the per-worker workspace of " + std::to_string(part) +
+                                         " bytes");
+    }
+  }
+  // longest predicted first over the workers
+  std::vector<int> order(n_sys);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int b) { return predicted_cost(problems[a]) > predicted_cost(problems[b]); });
+  SGW_HIP(hipSetDevice(ctx->device));
+  // the workers' streams wait for the work already queued on the caller's stream
+  hipEvent_t ready = nullptr;
+  SGW_HIP(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
+  SGW_HIP(hipEventRecord(ready, ctx->stream));
+  struct Worker {
+    hipStream_t stream = nullptr;
+    sgw_ctx *ctx = nullptr;
+  };
+  std::vector<Worker> workers(n_workers);
+  sgw_status st = SGW_OK;
+  for (int w = 0; w < n_workers && st == SGW_OK; ++w) {
+    if (hipStreamCreateWithFlags(&workers[w].stream, hipStreamNonBlocking) != hipSuccess) {
+      st = fail(SGW_ERR_HIP, "sternheimer_solve_batch: hipStreamCreate failed");
+      break;
+    }
+    if ((st = sgw_ctx_create(ctx->device, workers[w].stream, &workers[w].ctx)) != SGW_OK) break;
+    workers[w].ctx->profile_mask = ctx->profile_mask;
+    if (hipStreamWaitEvent(workers[w].stream, ready, 0) != hipSuccess)
+      st = fail(SGW_ERR_HIP, "sternheimer_solve_batch: hipStreamWaitEvent failed");
+  }
+  std::atomic<int> next{0};
+  std::atomic<bool> abort_flag{false};
+  std::mutex mu;
+  std::string first_error;
+  sgw_status first_status = SGW_OK;
+  auto work = [&](int w) {
+    if (hipSetDevice(ctx->device) != hipSuccess) {
+      abort_flag = true;
+      return;
+    }
+    char *base = (char *)workspace + (size_t)w * part;
+    while (!abort_flag) {
+      const int k = next++;
+      if (k >= n_sys) break;
+      const int i = order[k];
+      const auto t0 = std::chrono::steady_clock::now();
+      const sgw_status s = run_solve(workers[w].ctx, problems[i], opts[i], base, part);
+      const auto t1 = std::chrono::steady_clock::now();
+      problems[i].status = s;
+      problems[i].worker = w;
+      problems[i].ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+      if (s < 0) {
+        std::lock_guard<std::mutex> lock(mu);
+        if (first_status == SGW_OK) {
+          first_status = s;
+          first_error = "problem " + std::to_string(i) + ": " + sgw_last_error();
+        }
+        abort_flag = true;
+      }
+    }
+  };
+  if (st == SGW_OK) {
+    std::vector<std::thread> threads;
+    for (int w = 1; w < n_workers; ++w) threads.emplace_back(work, w);
+    work(0);
+    for (auto &t : threads) t.join();
+  }
+  for (auto &w : workers) {
+    if (w.ctx) {
+      hipStreamSynchronize(w.stream);
+      timing_collect(w.ctx);
+      for (int k = 0; k < K_COUNT; ++k) {
+        ctx->stats[k].launches += w.ctx->stats[k].launches;
+        ctx->stats[k].ms += w.ctx->stats[k].ms;
+        ctx->stats[k].bytes += w.ctx->stats[k].bytes;
+        ctx->stats[k].flops += w.ctx->stats[k].flops;
+      }
+      sgw_ctx_destroy(w.ctx);
+    }
+    if (w.stream) hipStreamDestroy(w.stream);
+  }
+  hipEventDestroy(ready);
+  if (st != SGW_OK) return st;
+  if (first_status != SGW_OK) return fail(first_status, first_error);
+  for (int i = 0; i < n_sys; ++i)
+    if (problems[i].status == SGW_NOT_CONVERGED) return SGW_NOT_CONVERGED;
+  return SGW_OK;
+}
+
+extern "C" sgw_status sgw_autotune(sgw_ctx *ctx, const sgw_problem *problem, sgw_opts *best, double *tune_ms) {
+  SGW_CHECK(ctx && problem && best, "sgw_autotune: NULL argument");
+  const auto t_start = std::chrono::steady_clock::now();
+  const sgw_problem &p = *problem;
+  const sgw_opts base = resolve_opts(&p.opts);
+  sgw_status st = validate_solve(ctx, p.h_kq, p.n_occ, p.psi_occ_kq, p.h_k, p.n_band, p.psi_v, p.eps_v, p.n_pert,
+                                 p.dv_miller, p.n_omega, p.omega, p.eta, p.tol, base);
+  if (st != SGW_OK) return st;
+  SGW_CHECK(base.solver == SGW_SOLVER_MULTISHIFT, "sgw_autotune: tunes the multishift solver only");
+  // system class: grid, and n_pw, n_occ, n_omega to within a factor sqrt(2)
+  auto bucket = [](int n) { return std::to_string((int)std::lround(2.0 * std::log2(std::max(n, 1)))); };
+  const std::string key = std::to_string(p.h_kq->n[0]) + "x" + std::to_string(p.h_kq->n[1]) + "x" +
+                          std::to_string(p.h_kq->n[2]) + "/" + bucket(p.h_kq->n_pw) + "/" + bucket(p.n_occ) + "/" +
+                          bucket(p.n_omega);
+  auto hit = ctx->tuned.find(key);
+  if (hit != ctx->tuned.end()) {
+    *best = base;
+    best->steps_per_sync = hit->second.steps_per_sync;
+    best->graph = hit->second.graph;
+    if (tune_ms) *tune_ms = 0.0;
+    return SGW_OK;
+  }
+  *best = base;
+  if ((long)p.n_band * p.n_pert * p.n_omega == 0) {
+    if (tune_ms) *tune_ms = 0.0;
+    return SGW_OK;
+  }
+  SGW_HIP(hipSetDevice(ctx->device));
+  // sample: the two highest bands (the slowest pairs) and up to eight perturbations
+  sgw_problem s = p;
+  const int nb = std::min(p.n_band, 2), np = std::min(p.n_pert, 8);
+  s.n_band = nb;
+  s.psi_v = p.psi_v + (size_t)(p.n_band - nb) * p.h_k->n_pw;
+  s.eps_v = p.eps_v + (p.n_band - nb);
+  s.n_pert = np;
+  const size_t n_sys = (size_t)nb * np * p.n_omega;
+  const size_t ws_b = problem_workspace_bytes(s, base);
+  void *buf = nullptr;
+  const size_t out_b = (sizeof(sgw_c128) * n_sys * p.h_kq->n_pw + kAlign - 1) / kAlign * kAlign;
+  const size_t info_b = (sizeof(sgw_solve_info) * n_sys + kAlign - 1) / kAlign * kAlign;
+  SGW_HIP(hipMalloc(&buf, out_b + info_b + ws_b));
+  s.dpsi = (sgw_c128 *)buf;
+  s.info = (sgw_solve_info *)((char *)buf + out_b);
+  void *ws = (char *)buf + out_b + info_b;
+  // candidates run on a stream of their own, as the workers of a batch do (capturable, untimed)
+  hipStream_t tstream = nullptr;
+  sgw_ctx *tctx = nullptr;
+  hipEvent_t ready = nullptr;
+  if (hipStreamCreateWithFlags(&tstream, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&ready, hipEventDisableTiming) != hipSuccess ||
+      hipEventRecord(ready, ctx->stream) != hipSuccess || hipStreamWaitEvent(tstream, ready, 0) != hipSuccess) {
+    st = fail(SGW_ERR_HIP, "sgw_autotune: stream setup failed");
+  } else {
+    st = sgw_ctx_create(ctx->device, tstream, &tctx);
+  }
+  double best_ms = 1e300;
+  sgw_opts winner = base;
+  const int steps[] = {4, 8, 16};
+  for (int warm = 1, c = 0; c < 6 && st >= 0; ++c) {
+    sgw_opts o = base;
+    o.steps_per_sync = steps[c % 3];
+    o.graph = c / 3;
+    if (warm) {  // first launch of every kernel: not timed
+      st = run_solve(tctx, s, o, ws, ws_b);
+      warm = 0;
+      if (st < 0) break;
+    }
+    const auto t0 = std::chrono::steady_clock::now();
+    st = run_solve(tctx, s, o, ws, ws_b);
+    const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (st >= 0 && ms < best_ms) {
+      best_ms = ms;
+      winner = o;
+    }
+  }
+  const std::string err = st < 0 ? std::string(sgw_last_error()) : std::string();
+  if (tstream) hipStreamSynchronize(tstream);
+  if (tctx) sgw_ctx_destroy(tctx);
+  if (tstream) hipStreamDestroy(tstream);
+  if (ready) hipEventDestroy(ready);
+  hipFree(buf);
+  if (st < 0) return fail(st, err);
+  *best = base;
+  best->steps_per_sync = winner.steps_per_sync;
+  best->graph = winner.graph;
+  ctx->tuned[key] = *best;
+  if (tune_ms)
+    *tune_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+  return SGW_OK;
 }

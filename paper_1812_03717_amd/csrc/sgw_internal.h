@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -72,6 +73,8 @@ struct sgw_ctx {
   // pinned host staging (status polls, small uploads)
   void *pinned = nullptr;
   size_t pinned_bytes = 0;
+  // autotuned options per system class (grid / n_pw / n_occ / n_omega)
+  std::map<std::string, sgw_opts> tuned;
 };
 
 // Device-resident index maps of one Hamiltonian.  "internal" order is
@@ -142,6 +145,8 @@ bool hx_grid_supported(int n);
 // partial sums over plane-wave chunks: cp[chunk][a][i] for chunk < n_chunks,
 // a < n_vec (leading dimension `rows` >= n_vec), i < n_occ.
 constexpr int kProjChunks = 16;
+// worker streams of a batch solve
+constexpr int kMaxWorkers = 16;
 // number of chunks for n_pw plane waves; *kc receives the chunk length
 int proj_chunks(int n_pw, int *kc);
 // cp[chunk][a][i] = sum_{g in chunk} conj(psi[i][g]) x_a[g]

@@ -32,7 +32,8 @@ EXPORTED = [
     "sgw_apply_h", "sgw_apply_projector", "sgw_build_rhs", "sgw_opts_default",
     "sternheimer_workspace_size", "sternheimer_solve", "sgw_mlp_num_params", "sgw_mlp_create",
     "sgw_mlp_destroy", "sgw_mlp_get_weights", "sgw_mlp_set_weights", "sgw_mlp_forward", "sgw_mlp_grad",
-    "sgw_mlp_train_step", "sgw_operator_columns", "sgw_mlp_rows",
+    "sgw_mlp_train_step", "sgw_operator_columns", "sgw_mlp_rows", "sternheimer_batch_workspace_size",
+    "sternheimer_solve_batch", "sgw_autotune",
 ]
 
 
@@ -53,7 +54,16 @@ class sgw_opts(C.Structure):
                 ("steps_per_sync", C.c_int32), ("solver", C.c_int32), ("precond", C.c_int32),
                 ("guess", C.c_int32), ("tail_iter", C.c_int32), ("ps_max_iter", C.c_int32),
                 ("ps_slots", C.c_int32), ("mlp", C.c_void_p), ("hist_r", C.c_void_p), ("hist_x", C.c_void_p),
-                ("hist_iter", C.c_int32), ("reserved", C.c_int32)]
+                ("hist_iter", C.c_int32), ("graph", C.c_int32)]
+
+
+class sgw_problem(C.Structure):
+    _fields_ = [("h_kq", C.c_void_p), ("h_k", C.c_void_p), ("n_occ", C.c_int32), ("n_band", C.c_int32),
+                ("n_pert", C.c_int32), ("n_omega", C.c_int32), ("psi_occ_kq", C.c_void_p), ("psi_v", C.c_void_p),
+                ("eps_v", C.POINTER(C.c_double)), ("dv_miller", C.POINTER(C.c_int32)),
+                ("omega", C.POINTER(C.c_double)), ("eta", C.c_double), ("tol", C.c_double), ("opts", sgw_opts),
+                ("dpsi", C.c_void_p), ("info", C.c_void_p), ("status", C.c_int32), ("worker", C.c_int32),
+                ("ms", C.c_double)]
 
 
 _lib = None
@@ -94,6 +104,9 @@ def load_library(path: str = LIB_PATH):
         "sgw_mlp_grad": [vp, vp, C.c_int, vp, vp, vp, vp],
         "sgw_mlp_train_step": [vp, vp, C.c_int, vp, vp, C.c_float, C.POINTER(C.c_float)],
         "sgw_operator_columns": [vp, vp, C.c_int, vp, dbl, vp, vp],
+        "sternheimer_batch_workspace_size": [vp, C.c_int, C.POINTER(sgw_problem), C.c_int, C.POINTER(sz)],
+        "sternheimer_solve_batch": [vp, C.c_int, C.POINTER(sgw_problem), C.c_int, vp, sz],
+        "sgw_autotune": [vp, C.POINTER(sgw_problem), C.POINTER(sgw_opts), C.POINTER(dbl)],
         "sgw_mlp_rows": [vp, vp, vp, vp, C.c_int, C.POINTER(dbl), C.POINTER(dbl), dbl, vp, vp, C.c_int, vp, vp],
     }
     for name, args in sig.items():
@@ -301,6 +314,72 @@ def sternheimer_solve(ctx, h_kq, psi_occ_kq, h_k, psi_v, eps_v, dv_miller, omega
         om.ctypes.data_as(C.POINTER(C.c_double)), float(eta), float(tol), C.byref(o), _ptr(ws),
         C.c_size_t(ws.numel()), _ptr(dpsi), _ptr(info)))
     return st, dpsi, info
+
+
+class Batch:
+    """A batch of systems for sternheimer_solve_batch: add() marshals one problem (keeping its host
+    arrays and output tensors alive); solve() runs them all."""
+
+    def __init__(self, ctx):
+        self.ctx = ctx
+        self.items = []
+
+    def add(self, h_kq, psi_occ_kq, h_k, psi_v, eps_v, dv_miller, omega, eta, tol, opts=None):
+        import torch
+        _require(psi_v, torch.complex128, self.ctx.device, (psi_v.shape[0], h_k.n_pw), "psi_v")
+        _require(psi_occ_kq, torch.complex128, self.ctx.device, (psi_occ_kq.shape[0], h_kq.n_pw), "psi_occ_kq")
+        eps = np.ascontiguousarray(np.asarray(eps_v, np.float64))
+        om = np.ascontiguousarray(np.asarray(omega, np.float64))
+        dvm = np.ascontiguousarray(np.asarray(dv_miller, np.int32).reshape(-1, 3))
+        n_band, n_pert, n_omega = int(psi_v.shape[0]), int(dvm.shape[0]), int(om.shape[0])
+        dpsi = torch.empty((n_band, n_pert, n_omega, h_kq.n_pw), dtype=torch.complex128, device=self.ctx.device)
+        info = torch.empty(n_band * n_pert * n_omega * INFO_DTYPE.itemsize, dtype=torch.uint8, device=self.ctx.device)
+        p = sgw_problem()
+        p.h_kq, p.h_k = h_kq.handle.value, h_k.handle.value
+        p.n_occ, p.n_band, p.n_pert, p.n_omega = int(psi_occ_kq.shape[0]), n_band, n_pert, n_omega
+        p.psi_occ_kq, p.psi_v = psi_occ_kq.data_ptr(), psi_v.data_ptr()
+        p.eps_v = eps.ctypes.data_as(C.POINTER(C.c_double))
+        p.dv_miller = dvm.ctypes.data_as(C.POINTER(C.c_int32))
+        p.omega = om.ctypes.data_as(C.POINTER(C.c_double))
+        p.eta, p.tol = float(eta), float(tol)
+        p.opts = opts if opts is not None else sgw_opts_default()
+        p.dpsi, p.info = dpsi.data_ptr(), info.data_ptr()
+        self.items.append(dict(problem=p, keep=(eps, om, dvm, psi_v, psi_occ_kq, h_kq, h_k), dpsi=dpsi, info=info,
+                               shape=(n_band, n_pert, n_omega)))
+        return len(self.items) - 1
+
+    def _array(self):
+        arr = (sgw_problem * len(self.items))()
+        for i, it in enumerate(self.items):
+            arr[i] = it["problem"]
+        return arr
+
+    def autotune(self, index):
+        """sgw_autotune on one problem; stores the tuned options in it and returns the time spent (ms)."""
+        best = sgw_opts()
+        ms = C.c_double()
+        p = self.items[index]["problem"]
+        _check(load_library().sgw_autotune(self.ctx.handle, C.byref(p), C.byref(best), C.byref(ms)))
+        p.opts = best
+        return ms.value
+
+    def workspace_size(self, n_workers):
+        arr = self._array()
+        n = C.c_size_t()
+        _check(load_library().sternheimer_batch_workspace_size(self.ctx.handle, len(self.items), arr, n_workers,
+                                                              C.byref(n)))
+        return int(n.value)
+
+    def solve(self, n_workers=4, workspace=None):
+        """Returns the batch status; per-system status / worker / ms are stored in self.items."""
+        arr = self._array()
+        nbytes = self.workspace_size(n_workers)
+        ws = (workspace or Workspace(self.ctx)).get(nbytes)
+        st = _check(load_library().sternheimer_solve_batch(self.ctx.handle, len(self.items), arr, n_workers,
+                                                          _ptr(ws), C.c_size_t(ws.numel())))
+        for i, it in enumerate(self.items):
+            it["status"], it["worker"], it["ms"] = arr[i].status, arr[i].worker, arr[i].ms
+        return st
 
 
 def info_to_numpy(info, shape=None):

@@ -94,22 +94,28 @@ class Problem:
 
 
 def make_problem(name, A, tau, grid, ecut, n_occ, omega_ev, eta_ev, n_pert, tol, seed,
-                 q_zero=False, n_band=None, noise=0.05, max_bumps=20):
+                 q_zero=False, n_band=None, noise=0.05, max_bumps=20, occ_window=0):
+    """occ_window > 0: when the states n_occ - 1 and n_occ are (near-)degenerate, take the band count
+    within n_occ +- occ_window closest to n_occ that has a gap >= MIN_GAP_HA at k and k+q."""
     B = cx.reciprocal(A)
     kvec = np.zeros(3)
+    target = n_occ
     for bump in range(max_bumps):
         s = seed + bump
         qvec = np.zeros(3) if q_zero else cx.seeded_q(B, s)
         v = cx.gaussian_potential(A, tau, grid, noise=noise, seed=s)
         mk = cx.g_sphere(B, kvec, ecut)
         mkq = mk if q_zero else cx.g_sphere(B, kvec + qvec, ecut)
-        ek, pk = lowest_states(mk, B, kvec, v, n_occ + 1)
+        n_states = target + occ_window + 1
+        ek, pk = lowest_states(mk, B, kvec, v, n_states)
         if q_zero:
             ekq, pkq = ek, pk
         else:
-            ekq, pkq = lowest_states(mkq, B, kvec + qvec, v, n_occ + 1)
-        gap = min(ek[n_occ] - ek[n_occ - 1], ekq[n_occ] - ekq[n_occ - 1])
-        if gap >= MIN_GAP_HA:
+            ekq, pkq = lowest_states(mkq, B, kvec + qvec, v, n_states)
+        cands = sorted(range(max(1, target - occ_window), target + occ_window + 1), key=lambda n: (abs(n - target), n))
+        ok = [n for n in cands if min(ek[n] - ek[n - 1], ekq[n] - ekq[n - 1]) >= MIN_GAP_HA]
+        if ok:
+            n_occ = ok[0]
             break
     else:  # pragma: no cover
         raise RuntimeError(f"{name}: no seed with a gap >= {MIN_GAP_HA} Ha")
@@ -163,3 +169,33 @@ def small(cells=(1, 1, 1), grid=None, ecut=11.46, n_occ=None, n_omega=8, n_pert=
 
 
 CONFIGS = {"si2": si2, "si16": si16, "si64": si64}
+
+
+def _batch_system(args):
+    i, seed0, ecut, cells_max, n_omega_range, n_pert_range, tol, threads = args
+    from threadpoolctl import threadpool_limits
+    rng = np.random.default_rng([seed0 + i, 1])
+    cells = tuple(int(c) for c in rng.integers(1, cells_max + 1, 3))
+    n_omega = int(rng.integers(n_omega_range[0], n_omega_range[1] + 1))
+    n_pert = int(rng.integers(n_pert_range[0], n_pert_range[1] + 1))
+    A, tau = cx.supercell(*cx.fcc_primitive(A_LAT), cells)
+    with threadpool_limits(threads):
+        return make_problem(f"batch{i}{cells}", A, tau, tuple(24 * c for c in cells), ecut, 2 * len(tau),
+                            cx.frequencies_ev(0, 40, n_omega), 0.05, n_pert, tol, seed0 + i, occ_window=6)
+
+
+def batch(n_sys=200, seed0=3000, ecut=4.0, cells_max=3, n_omega_range=(16, 128), n_pert_range=(4, 16), tol=1e-8,
+          workers=8):
+    """Independent systems of uneven size: fcc n0 x n1 x n2 cells (n_d uniform in 1..cells_max, 2-54
+    atoms), grid 24 n_d per axis, all 2*atoms occupied bands, n_omega and n_pert uniform in their
+    ranges, frequencies linspace(0, 40 eV), eta 0.05 eV, one seeded q each; system i has seed seed0 + i.
+    Where states 2*atoms - 1 and 2*atoms are degenerate the nearest band count (within +-6) with a gap
+    is occupied instead.
+    Generated in `workers` processes (dense eigensolver per system)."""
+    args = [(i, seed0, ecut, cells_max, n_omega_range, n_pert_range, tol, 2) for i in range(n_sys)]
+    if workers <= 1:
+        return [_batch_system(a) for a in args]
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    with cf.ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn")) as ex:
+        return list(ex.map(_batch_system, args))

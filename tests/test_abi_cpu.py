@@ -45,3 +45,32 @@ def test_host_side_calls():
     st = lib.sternheimer_solve(None, None, 0, None, None, 0, None, None, 0, None, 0, None, 0.1, 1e-8, None, None,
                                0, None, None)
     assert st == sgw.SGW_ERR_INVALID_ARG
+
+
+def _c_layout(tmp_path, struct, fields):
+    """sizeof and offsetof of a header struct, from the C compiler."""
+    import subprocess
+    src = tmp_path / "layout.c"
+    lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{ROOT}/include/sgw.h"', 'int main(void) {',
+             f'  printf("%zu\\n", sizeof({struct}));']
+    lines += [f'  printf("%zu\\n", offsetof({struct}, {f}));' for f in fields]
+    lines += ['  return 0;', '}']
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()
+    return int(out[0]), [int(x) for x in out[1:]]
+
+
+def test_struct_layouts_match_the_binding(tmp_path):
+    """The ctypes mirrors of the header's structs have the C compiler's sizes and field offsets."""
+    import ctypes as C
+    for cls, struct in ((sgw.sgw_opts, "sgw_opts"), (sgw.sgw_problem, "sgw_problem"),
+                        (sgw.sgw_ham_desc, "sgw_ham_desc")):
+        names = [f[0] for f in cls._fields_]
+        size, offs = _c_layout(tmp_path, struct, names)
+        assert C.sizeof(cls) == size, struct
+        assert [getattr(cls, n).offset for n in names] == offs, struct
+    size, offs = _c_layout(tmp_path, "sgw_solve_info", list(sgw.INFO_DTYPE.names))
+    assert sgw.INFO_DTYPE.itemsize == size
+    assert [sgw.INFO_DTYPE.fields[n][1] for n in sgw.INFO_DTYPE.names] == offs

@@ -1,0 +1,128 @@
+"""GPU: batches of uneven systems (sternheimer_solve_batch), graph-captured Krylov
+steps and the autotuner, through the C ABI.
+
+Each system's solve does not depend on what else runs (slots, FFT batches and
+projector partial sums are per vector), so a batch must reproduce the
+one-system solves bit for bit, with or without graph replay and for any
+steps_per_sync.  Two systems are also checked against the oracle's LU solves.
+"""
+import numpy as np
+import pytest
+
+import oracle.sternheimer_oracle as so
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from tests.libutil import ensure_library
+    ensure_library()
+    from paper_1812_03717_amd import sgw
+    c = sgw.sgw_ctx_create(0)
+    yield c
+    torch.cuda.synchronize()
+
+
+@pytest.fixture(scope="module")
+def systems(ctx):
+    from paper_1812_03717_amd.workload import DeviceProblem
+    ps = synth.batch(7, seed0=3500, cells_max=2, n_omega_range=(4, 12), n_pert_range=(2, 4), tol=1e-10, workers=4)
+    return ps, [DeviceProblem(ctx, p) for p in ps]
+
+
+def _batch(ctx, devs, opts=None):
+    from paper_1812_03717_amd import sgw
+    b = sgw.Batch(ctx)
+    for d in devs:
+        p = d.problem
+        b.add(d.h_kq, d.psi_occ_kq, d.h_k, d.psi_v, d.eps_v, p.dv_miller, p.omega, p.eta, p.tol,
+              opts=opts() if opts else None)
+    return b
+
+
+@pytest.fixture(scope="module")
+def singles(ctx, systems):
+    from paper_1812_03717_amd import sgw
+    _, devs = systems
+    out = []
+    for d in devs:
+        st, dpsi, info = d.solve()
+        assert st == sgw.SGW_OK, sgw.load_library().sgw_last_error()
+        out.append((dpsi.cpu().numpy(), info.cpu().numpy()))
+    return out
+
+
+@pytest.mark.parametrize("variant", ["streams3", "graph", "graph_m3_streams2", "one_worker"])
+def test_batch_matches_single_solves(ctx, systems, singles, variant):
+    from paper_1812_03717_amd import sgw
+    ps, devs = systems
+    opts = {"streams3": None, "graph": lambda: sgw.sgw_opts_default(graph=1),
+            "graph_m3_streams2": lambda: sgw.sgw_opts_default(graph=1, steps_per_sync=3),
+            "one_worker": None}[variant]
+    workers = {"streams3": 3, "graph": 3, "graph_m3_streams2": 2, "one_worker": 1}[variant]
+    b = _batch(ctx, devs, opts)
+    st = b.solve(n_workers=workers)
+    assert st == sgw.SGW_OK, sgw.load_library().sgw_last_error()
+    used = set()
+    for it, (dpsi, info), p in zip(b.items, singles, ps):
+        assert it["status"] == sgw.SGW_OK
+        used.add(it["worker"])
+        assert np.array_equal(it["dpsi"].cpu().numpy(), dpsi), p.name
+        assert np.array_equal(it["info"].cpu().numpy(), info), p.name
+    assert used <= set(range(workers))
+    print(variant, "workers", sorted(used), "ms", [round(it["ms"], 2) for it in b.items], flush=True)
+
+
+def test_batch_against_oracle(ctx, systems):
+    """The two smallest systems of a batch, solved at tol 1e-12, against LU solves of the oracle."""
+    from paper_1812_03717_amd import sgw
+    ps, devs = systems
+    idx = sorted(range(len(ps)), key=lambda i: ps[i].miller_kq.shape[0])[:2]
+    b = sgw.Batch(ctx)
+    for i in idx:
+        d, p = devs[i], ps[i]
+        b.add(d.h_kq, d.psi_occ_kq, d.h_k, d.psi_v, d.eps_v, p.dv_miller, p.omega, p.eta, 1e-12)
+    assert b.solve(n_workers=2) == sgw.SGW_OK
+    for it, i in zip(b.items, idx):
+        p = ps[i]
+        x = it["dpsi"].cpu().numpy()
+        h = so.hamiltonian(p.miller_kq, p.B, p.kvec + p.qvec, p.v_grid)
+        for v in (0, p.n_band - 1):
+            a0 = so.coulomb_operator(h, p.psi_kq, p.eps_k[v], 1.0)
+            for q in range(len(p.dv_miller)):
+                rhs = so.rhs(p.psi_k[v], p.miller_k, p.miller_kq, p.dv_miller[q], p.psi_kq)
+                for j in (0, len(p.omega) - 1):
+                    ref = so.solve_lu(a0, rhs, p.omega[j] + 1j * p.eta)
+                    err = np.linalg.norm(x[v, q, j] - ref) / np.linalg.norm(ref)
+                    assert err <= 1e-8, (p.name, v, q, j, err)
+
+
+def test_autotune(ctx, systems, singles):
+    from paper_1812_03717_amd import sgw
+    ps, devs = systems
+    b = _batch(ctx, devs)
+    ms = b.autotune(0)
+    o = b.items[0]["problem"].opts
+    print("autotune", ps[0].name, "ms", ms, "steps_per_sync", o.steps_per_sync, "graph", o.graph, flush=True)
+    assert ms > 0 and o.steps_per_sync in (4, 8, 16) and o.graph in (0, 1)
+    assert b.autotune(0) == 0.0  # cached for this system class
+    assert b.solve(n_workers=2) == sgw.SGW_OK
+    assert np.array_equal(b.items[0]["dpsi"].cpu().numpy(), singles[0][0])
+
+
+def test_batch_rejects_bad_input(ctx, systems):
+    from paper_1812_03717_amd import sgw
+    _, devs = systems
+    b = _batch(ctx, devs[:2])
+    b.items[1]["problem"].eta = 0.0
+    with pytest.raises(sgw.SgwError) as e:
+        b.solve(n_workers=2)
+    assert "problem 1" in str(e.value)
+    with pytest.raises(sgw.SgwError):
+        _batch(ctx, devs[:1]).solve(n_workers=0)
