@@ -65,7 +65,17 @@ enum {
                                  BiCGStab iterations (two operator applications each) */
 };
 
-enum { SGW_FP64 = 0 };        /* precision modes */
+/* precision modes */
+enum {
+  SGW_FP64 = 0,               /* complex128 throughout */
+  SGW_MIXED = 1               /* a (v,p) pair's Krylov steps apply the potential term of H.x in
+                                 complex64 (FP32 transforms and V) once the estimated residuals of
+                                 all its shifts are below mixed_switch * tol (matvec errors made late enter
+                                 the solutions weighted by the shrinking step coefficients); the
+                                 projector, recurrences, basis and residuals stay FP64, and every
+                                 shift whose true FP64 residual is still above tol is then refined
+                                 by FP64 per-shift solves from its multishift iterate */
+};
 
 /* solver (sgw_opts.solver) */
 enum {
@@ -143,8 +153,11 @@ int32_t sgw_ham_npw(const sgw_ham *ham);
  * y = H x for n_vec vectors (Sec. 2.1): y_G = 0.5|k+G|^2 x_G + [F V F^-1 x]_G
  * with F^-1 x (r_j) = sum_G x_G exp(i G.r_j) and F f (G) = (1/N) sum_j f_j exp(-i G.r_j).
  * x, y: device [n_vec][n_pw] in the caller's order; may not alias.
+ * precision SGW_FP64, or SGW_MIXED: the potential term in FP32 (x rounded to
+ * complex64, FP32 transforms and V(r)), the kinetic term and y in FP64.
  */
-sgw_status sgw_apply_h(sgw_ctx *ctx, const sgw_ham *ham, int n_vec, const sgw_c128 *x, sgw_c128 *y);
+sgw_status sgw_apply_h(sgw_ctx *ctx, const sgw_ham *ham, int n_vec, const sgw_c128 *x, sgw_c128 *y,
+                       int precision);
 
 /*
  * Occupied-manifold projector (Sec. 2.3, Eqs. 7-8), applied to n_vec vectors:
@@ -169,7 +182,7 @@ sgw_status sgw_build_rhs(sgw_ctx *ctx, const sgw_ham *h_kq, int n_occ, const sgw
                          const int32_t *dv_miller, sgw_c128 *b);
 
 typedef struct {
-  int32_t precision;        /* SGW_FP64 (only mode of this build) */
+  int32_t precision;        /* SGW_FP64 or SGW_MIXED (not with the per-shift solver) */
   int32_t max_iter;         /* Krylov dimension limit per (v,p); <= 0 -> 600 */
   double alpha_pv;          /* coefficient of P_occ in the operator, Ha; <= 0 -> 1.0 */
   double tol_safety;        /* the recurrence stops when every shift's estimated residual
@@ -178,9 +191,10 @@ typedef struct {
   int32_t finalize_batch;   /* pairs per finalisation batch; <= 0 -> automatic */
   int32_t steps_per_sync;   /* Krylov steps between host polls; <= 0 -> 8 */
   int32_t solver;           /* SGW_SOLVER_* (default MULTISHIFT) */
-  int32_t precond;          /* SGW_PC_* for per-shift solves (default NONE); a preconditioner or
-                               a non-zero initial guess breaks the shared Krylov space, so the
-                               multishift solver accepts only NONE / ZERO */
+  int32_t precond;          /* SGW_PC_* for per-shift solves (default NONE): the per-shift solver
+                               and the per-shift phases of TAIL and MIXED; a preconditioner or a
+                               non-zero initial guess breaks the shared Krylov space, so a plain
+                               FP64 multishift solve accepts only NONE / ZERO */
   int32_t guess;            /* SGW_GUESS_* for per-shift solves (default ZERO) */
   int32_t tail_iter;        /* TAIL: multishift Krylov dimension cap; <= 0 -> 160 */
   int32_t ps_max_iter;      /* per-shift BiCGStab iteration limit; <= 0 -> 2000 */
@@ -191,6 +205,8 @@ typedef struct {
                                untouched for solves that finished earlier */
   sgw_c128 *hist_x;         /* optional device out, same shape: the iterate x_k with r_k */
   int32_t hist_iter;        /* iteration of the snapshot (> 0 with hist_r, hist_x) */
+  double mixed_switch;      /* SGW_MIXED: a pair's steps use FP32 potential matvecs once all its
+                               shifts' estimated residuals are below mixed_switch * tol; <= 0 -> 1e4 */
   int32_t graph;            /* 1: the multishift solver captures the Krylov steps between two
                                polls in a HIP graph and replays it (re-captured when the number
                                of active slots changes; ignored while kernel timing is on and

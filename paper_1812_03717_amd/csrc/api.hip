@@ -206,7 +206,7 @@ static sgw_status upload(sgw_ctx *ctx, T **dst, const std::vector<T> &src) {
 static void ham_free(sgw_ham *h) {
   if (!h) return;
   void *ptrs[] = {h->d_i2u, h->d_u2i, h->d_stick_off, h->d_rows, h->d_pw_stick, h->d_pw_z,
-                  h->d_miller_int, h->d_kin, h->d_vt, h->d_box, h->d_tw};
+                  h->d_miller_int, h->d_kin, h->d_vt, h->d_box, h->d_tw, h->d_vt32, h->d_tw32};
   for (void *p : ptrs)
     if (p) hipFree(p);
   delete h;
@@ -301,12 +301,14 @@ extern "C" sgw_status sgw_ham_create(sgw_ctx *ctx, const sgw_ham_desc *d, sgw_ha
   stick_off.push_back(npw);
   // twiddle tables exp(-2 pi i t / N) for the three axes
   std::vector<double2> tw;
+  std::vector<float2> tw32;
   int tw_off[3];
   for (int a = 0; a < 3; ++a) {
     tw_off[a] = (int)tw.size();
     for (int t = 0; t < n[a]; ++t) {
       const long double ang = -2.0L * 3.14159265358979323846264338327950288L * t / n[a];
       tw.push_back(make_double2((double)cosl(ang), (double)sinl(ang)));
+      tw32.push_back(make_float2((float)cosl(ang), (float)sinl(ang)));
     }
   }
   SGW_HIP(hipSetDevice(ctx->device));
@@ -343,15 +345,17 @@ extern "C" sgw_status sgw_ham_create(sgw_ctx *ctx, const sgw_ham_desc *d, sgw_ha
   SGW_UP(h->d_kin, kin);
   SGW_UP(h->d_box, box);
   SGW_UP(h->d_tw, tw);
+  SGW_UP(h->d_tw32, tw32);
 #undef SGW_UP
   const long ntot = (long)n[0] * n[1] * n[2];
   hipError_t e = hipMalloc((void **)&h->d_vt, sizeof(double) * ntot);
+  if (e == hipSuccess) e = hipMalloc((void **)&h->d_vt32, sizeof(float) * ntot);
   if (e != hipSuccess) {
     hipStreamSynchronize(ctx->stream);
     ham_free(h);
     return fail(SGW_ERR_HIP, std::string("hipMalloc: ") + hipGetErrorString(e));
   }
-  st = transpose_potential(ctx, d->v_loc, h->d_vt, n);
+  st = transpose_potential(ctx, d->v_loc, h->d_vt, h->d_vt32, n);
   e = hipStreamSynchronize(ctx->stream);
   if (st != SGW_OK || e != hipSuccess) {
     ham_free(h);
@@ -391,9 +395,12 @@ sgw_status alloc_async(DevBuf &b, size_t bytes, hipStream_t) {
 
 }  // namespace
 
-extern "C" sgw_status sgw_apply_h(sgw_ctx *ctx, const sgw_ham *h, int n_vec, const sgw_c128 *x, sgw_c128 *y) {
+extern "C" sgw_status sgw_apply_h(sgw_ctx *ctx, const sgw_ham *h, int n_vec, const sgw_c128 *x, sgw_c128 *y,
+                                  int precision) {
   if (!ctx || !h) return fail(SGW_ERR_INVALID_ARG, "sgw_apply_h: NULL context or Hamiltonian");
   if (n_vec < 0) return fail(SGW_ERR_INVALID_ARG, "sgw_apply_h: n_vec < 0");
+  if (precision != SGW_FP64 && precision != SGW_MIXED)
+    return fail(SGW_ERR_INVALID_ARG, "sgw_apply_h: unknown precision mode");
   if (n_vec == 0) return SGW_OK;
   if (!x || !y) return fail(SGW_ERR_INVALID_ARG, "sgw_apply_h: NULL vector");
   if (x == y) return fail(SGW_ERR_INVALID_ARG, "sgw_apply_h: x and y alias");
@@ -408,8 +415,8 @@ extern "C" sgw_status sgw_apply_h(sgw_ctx *ctx, const sgw_ham *h, int n_vec, con
     return st;
   if ((st = permute(ctx, npw, n_vec, (const double2 *)x, npw, (double2 *)xi.p, npw, h->d_i2u, 0)) != SGW_OK)
     return st;
-  if ((st = hx_batch(ctx, h, n_vec, contiguous((double2 *)xi.p, npw), (double2 *)yi.p, npw, (double2 *)tb.p)) !=
-      SGW_OK)
+  if ((st = hx_batch(ctx, h, n_vec, contiguous((double2 *)xi.p, npw), (double2 *)yi.p, npw, tb.p,
+                     precision == SGW_MIXED)) != SGW_OK)
     return st;
   if ((st = permute(ctx, npw, n_vec, (double2 *)yi.p, npw, (double2 *)y, npw, h->d_i2u, 1)) != SGW_OK) return st;
   return sync(ctx);
@@ -516,6 +523,7 @@ extern "C" sgw_status sgw_opts_default(sgw_opts *o) {
   o->hist_r = nullptr;
   o->hist_x = nullptr;
   o->hist_iter = 0;
+  o->mixed_switch = kMixedSwitch;
   o->graph = 0;
   return SGW_OK;
 }
@@ -527,7 +535,7 @@ constexpr double kDefaultBudget = 40.0 * (1ull << 30);
 
 struct Layout {
   int S = 0, F = 0, kmax = 0, M = 8;
-  size_t psi, omega, epsb, dvm, pair, kcur, status, eps, alpha, beta, rho, res, conv, bvec, basis;
+  size_t psi, omega, epsb, dvm, pair, kcur, status, eps, alpha, beta, rho, res, maxres, conv, bvec, basis;
   size_t l_active, l_fill, l_fillpairs, l_final, Y, Y2, C, T, ycoef, cp, X, AX, bad;
   long c_rows = 0;
   size_t total = 0;
@@ -562,6 +570,7 @@ sgw_opts resolve_opts(const sgw_opts *in) {
     o.hist_x = in->hist_x;
     o.hist_iter = in->hist_iter;
     o.graph = in->graph;
+    if (in->mixed_switch > 0) o.mixed_switch = in->mixed_switch;
   }
   return o;
 }
@@ -598,6 +607,7 @@ Layout make_layout(const sgw_ham *h, int n_occ, int n_band, int n_pert, int n_om
   L.beta = take(off, 8ul * L.S * (L.kmax + 1));
   L.rho = take(off, 16ul * L.S * n_omega);
   L.res = take(off, 8ul * L.S * n_omega);
+  L.maxres = take(off, 8ul * L.S);
   L.conv = take(off, 4ul * L.S * n_omega);
   L.bvec = take(off, 16ul * L.S * npw);
   L.basis = take(off, 16ul * L.S * (L.kmax + 1) * npw);
@@ -631,7 +641,9 @@ static sgw_status validate_solve(sgw_ctx *ctx, const sgw_ham *h_kq, int n_occ, c
   if (n_occ > kMaxOcc)
     return fail(SGW_ERR_UNSUPPORTED, "sternheimer_solve: n_occ above " + std::to_string(kMaxOcc));
   SGW_CHECK(n_occ < h_kq->n_pw, "sternheimer_solve: n_occ must be below the basis size");
-  SGW_CHECK(o.precision == SGW_FP64, "sternheimer_solve: unknown precision mode");
+  SGW_CHECK(o.precision == SGW_FP64 || o.precision == SGW_MIXED, "sternheimer_solve: unknown precision mode");
+  SGW_CHECK(o.precision == SGW_FP64 || o.solver != SGW_SOLVER_PER_SHIFT,
+            "sternheimer_solve: the per-shift solver runs in FP64 only");
   SGW_CHECK(o.max_iter >= 1 && o.max_iter <= 100000, "sternheimer_solve: max_iter out of range");
   SGW_CHECK(std::isfinite(eta) && eta != 0.0, "sternheimer_solve: eta must be finite and non-zero");
   SGW_CHECK(std::isfinite(tol) && tol > 0.0, "sternheimer_solve: tol must be positive");
@@ -639,7 +651,10 @@ static sgw_status validate_solve(sgw_ctx *ctx, const sgw_ham *h_kq, int n_occ, c
   SGW_CHECK(o.solver >= SGW_SOLVER_MULTISHIFT && o.solver <= SGW_SOLVER_TAIL, "sternheimer_solve: unknown solver");
   SGW_CHECK(o.precond >= SGW_PC_NONE && o.precond <= SGW_PC_LEARNED, "sternheimer_solve: unknown preconditioner");
   SGW_CHECK(o.guess == SGW_GUESS_ZERO || o.guess == SGW_GUESS_LEARNED, "sternheimer_solve: unknown initial guess");
-  SGW_CHECK(o.solver != SGW_SOLVER_MULTISHIFT || (o.precond == SGW_PC_NONE && o.guess == SGW_GUESS_ZERO),
+  // preconditioners and guesses act in per-shift solves only: the per-shift solver, and the per-shift
+  // phases of TAIL and MIXED (the multishift phase itself never uses them)
+  SGW_CHECK(o.solver != SGW_SOLVER_MULTISHIFT || o.precision == SGW_MIXED ||
+                (o.precond == SGW_PC_NONE && o.guess == SGW_GUESS_ZERO),
             "sternheimer_solve: a preconditioner or initial guess breaks the shared Krylov space; "
             "use the per-shift or tail solver");
   SGW_CHECK(o.ps_max_iter >= 1 && o.ps_max_iter <= 100000, "sternheimer_solve: ps_max_iter out of range");
@@ -661,7 +676,7 @@ static sgw_status validate_solve(sgw_ctx *ctx, const sgw_ham *h_kq, int n_occ, c
 // A captured sequence of launches on one stream, replayed with hipGraphLaunch.
 struct StepGraph {
   hipGraphExec_t exec = nullptr;
-  int na = -1;
+  int na = -1, n64 = -1;
   StepGraph() = default;
   StepGraph(const StepGraph &) = delete;
   StepGraph &operator=(const StepGraph &) = delete;
@@ -673,6 +688,7 @@ struct StepGraph {
     if (exec) hipGraphExecDestroy(exec);
     exec = nullptr;
     na = -1;
+    n64 = -1;
     SGW_HIP(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
     const sgw_status st = launches();
     hipGraph_t g = nullptr;
@@ -710,6 +726,9 @@ static size_t solve_workspace_bytes(const sgw_ham *h_kq, int n_occ, int n_band, 
       return std::max(make_layout(h_kq, n_occ, n_band, n_pert, n_omega, tail_phase_opts(o)).total,
                       ps_workspace_bytes(h_kq, n_occ, n_band, n_pert, n_omega, o, n_sys_i));
     default:
+      if (o.precision == SGW_MIXED)  // FP64 per-shift refinement after the mixed multishift phase
+        return std::max(make_layout(h_kq, n_occ, n_band, n_pert, n_omega, o).total,
+                        ps_workspace_bytes(h_kq, n_occ, n_band, n_pert, n_omega, o, n_sys_i));
       return make_layout(h_kq, n_occ, n_band, n_pert, n_omega, o).total;
   }
 }
@@ -753,6 +772,7 @@ static sgw_status multishift_solve(sgw_ctx *ctx, const sgw_ham *h_kq, int n_occ,
   Sx.beta = (double *)(W + L.beta);
   Sx.rho = (double2 *)(W + L.rho);
   Sx.res = (double *)(W + L.res);
+  Sx.maxres = (double *)(W + L.maxres);
   Sx.conv = (int32_t *)(W + L.conv);
   Sx.pair = (int32_t *)(W + L.pair);
   Sx.kcur = (int32_t *)(W + L.kcur);
@@ -762,6 +782,12 @@ static sgw_status multishift_solve(sgw_ctx *ctx, const sgw_ham *h_kq, int n_occ,
   Sx.omega = (double *)(W + L.omega);
   Sx.eta = eta;
   Sx.alpha = o.alpha_pv;
+  // Mixed precision: a matvec error at step k enters the shifted solutions weighted by their step-k
+  // coefficients, which shrink with the residual (inexact Krylov theory); so a slot switches to
+  // FP32 potential matvecs (~3e-8 relative error) once all its shifts' estimates are below
+  // kMixedSwitch * tol, and the true FP64 residual decides afterwards.
+  const bool mixed = o.precision == SGW_MIXED;
+  const double switch_res = o.mixed_switch * tol;
   Sx.tol_int = tol * o.tol_safety;
   int32_t *d_active = (int32_t *)(W + L.l_active);
   int32_t *d_fill = (int32_t *)(W + L.l_fill);
@@ -779,14 +805,16 @@ static sgw_status multishift_solve(sgw_ctx *ctx, const sgw_ham *h_kq, int n_occ,
   double2 *AX = (double2 *)(W + L.AX);
   int *d_bad = (int *)(W + L.bad);
 
-  // pinned staging: status[S] | active[S] | fill[S] | fillpairs[S] | final[S] | bad
-  if ((st = ensure_pinned(ctx, sizeof(int32_t) * (5ul * S + 16))) != SGW_OK) return st;
+  // pinned staging: status[S] | active[S] | fill[S] | fillpairs[S] | final[S] | bad[16] | maxres[S]
+  if ((st = ensure_pinned(ctx, sizeof(int32_t) * (5ul * S + 16) + sizeof(double) * (S + 1))) != SGW_OK) return st;
   int32_t *p_status = (int32_t *)ctx->pinned;
   int32_t *p_active = p_status + S;
   int32_t *p_fill = p_active + S;
   int32_t *p_fillpairs = p_fill + S;
   int32_t *p_final = p_fillpairs + S;
   int32_t *p_bad = p_final + S;
+  double *p_maxres = (double *)(((uintptr_t)(p_bad + 16) + 7) & ~(uintptr_t)7);
+  std::vector<char> slot_fp32(S, 0);
 
   // parameters
   SGW_HIP(hipMemcpyAsync((void *)Sx.omega, omega, sizeof(double) * n_omega, hipMemcpyHostToDevice, ctx->stream));
@@ -863,29 +891,41 @@ static sgw_status multishift_solve(sgw_ctx *ctx, const sgw_ham *h_kq, int n_occ,
       if ((st = proj_apply(ctx, npw, n_occ, Sx.psi, nfill, contiguous(Y, npw), C, crow, Y2, npw, 1.0, 0)) != SGW_OK)
         return st;
       if ((st = slot_init(ctx, Sx, nfill, Y, Y2, d_fill, d_fillpairs)) != SGW_OK) return st;
-      for (int i = 0; i < nfill; ++i) active.push_back(p_fill[i]);
+      for (int i = 0; i < nfill; ++i) {
+        active.push_back(p_fill[i]);
+        slot_fp32[p_fill[i]] = 0;
+      }
     }
     if (!active.empty()) {
-      std::memcpy(p_active, active.data(), sizeof(int32_t) * active.size());
+      // FP64 slots first, then the slots whose matvecs run with the FP32 potential
+      int n64 = 0;
+      for (int s : active)
+        if (!slot_fp32[s]) p_active[n64++] = s;
+      int k32 = n64;
+      for (int s : active)
+        if (slot_fp32[s]) p_active[k32++] = s;
       const int na = (int)active.size();
       SGW_HIP(hipMemcpyAsync(d_active, p_active, sizeof(int32_t) * na, hipMemcpyHostToDevice, ctx->stream));
+      const VecSrc cur32{Sx.basis, npw, d_active + n64, Sx.kcur, Sx.slot_stride};
       auto steps = [&]() -> sgw_status {
         sgw_status s2;
         for (int step = 0; step < L.M; ++step) {
           if ((s2 = proj_dot(ctx, npw, n_occ, Sx.psi, na, cur, C, crow)) != SGW_OK) return s2;
-          if ((s2 = hx_batch(ctx, h_kq, na, cur, Y, npw, T)) != SGW_OK) return s2;
+          if ((s2 = hx_batch(ctx, h_kq, n64, cur, Y, npw, T)) != SGW_OK) return s2;
+          if ((s2 = hx_batch(ctx, h_kq, na - n64, cur32, Y + (long)n64 * npw, npw, T, true)) != SGW_OK) return s2;
           if ((s2 = proj_apply(ctx, npw, n_occ, Sx.psi, na, cur, C, crow, Y, npw, o.alpha_pv, 1)) != SGW_OK) return s2;
           if ((s2 = lanczos_step(ctx, Sx, na, d_active, Y)) != SGW_OK) return s2;
         }
         return SGW_OK;
       };
       // The launches read the active list from device memory, so a captured
-      // sequence depends only on the number of active slots.  The legacy
-      // default stream cannot be captured: launches stay eager there.
+      // sequence depends only on the number of active slots (and of FP64 ones).
+      // The legacy default stream cannot be captured: launches stay eager there.
       if (o.graph && ctx->profile_mask == 0 && ctx->stream != nullptr) {
-        if (graph.na != na) {
+        if (graph.na != na || graph.n64 != n64) {
           if ((st = graph.capture(ctx->stream, steps)) != SGW_OK) return st;
           graph.na = na;
+          graph.n64 = n64;
         }
         SGW_HIP(hipGraphLaunch(graph.exec, ctx->stream));
       } else if ((st = steps()) != SGW_OK) {
@@ -895,7 +935,11 @@ static sgw_status multishift_solve(sgw_ctx *ctx, const sgw_ham *h_kq, int n_occ,
     // poll
     SGW_HIP(hipMemcpyAsync(p_status, Sx.status, sizeof(int32_t) * S, hipMemcpyDeviceToHost, ctx->stream));
     SGW_HIP(hipMemcpyAsync(kc_host.data(), Sx.kcur, sizeof(int32_t) * S, hipMemcpyDeviceToHost, ctx->stream));
+    if (mixed)
+      SGW_HIP(hipMemcpyAsync(p_maxres, Sx.maxres, sizeof(double) * S, hipMemcpyDeviceToHost, ctx->stream));
     if ((st = sync(ctx)) != SGW_OK) return st;
+    if (mixed)
+      for (int s : active) slot_fp32[s] = slot_fp32[s] || p_maxres[s] <= switch_res;
     std::vector<int> still;
     for (int s : active) {
       if (p_status[s] == SLOT_RUNNING) still.push_back(s);
@@ -953,12 +997,14 @@ static sgw_status run_solve(sgw_ctx *ctx, const sgw_problem &p, const sgw_opts &
       return st;
     return n_bad > 0 ? SGW_NOT_CONVERGED : SGW_OK;
   }
-  if (o.solver == SGW_SOLVER_MULTISHIFT)
+  if (o.solver == SGW_SOLVER_MULTISHIFT && o.precision == SGW_FP64)
     return multishift_solve(ctx, p.h_kq, p.n_occ, p.psi_occ_kq, p.h_k, p.n_band, p.psi_v, p.eps_v, p.n_pert,
                             p.dv_miller, p.n_omega, p.omega, p.eta, p.tol, o, workspace, p.dpsi, p.info);
-  // TAIL: multishift up to tail_iter, then the shifts above tol per shift from their multishift iterate
+  // TAIL: multishift up to tail_iter; MIXED: multishift with FP32 potential matvecs.  Then the shifts
+  // whose true FP64 residual is above tol continue per shift in FP64 from their multishift iterate.
+  const sgw_opts o1 = o.solver == SGW_SOLVER_TAIL ? tail_phase_opts(o) : o;
   st = multishift_solve(ctx, p.h_kq, p.n_occ, p.psi_occ_kq, p.h_k, p.n_band, p.psi_v, p.eps_v, p.n_pert,
-                        p.dv_miller, p.n_omega, p.omega, p.eta, p.tol, tail_phase_opts(o), workspace, p.dpsi, p.info);
+                        p.dv_miller, p.n_omega, p.omega, p.eta, p.tol, o1, workspace, p.dpsi, p.info);
   if (st != SGW_OK && st != SGW_NOT_CONVERGED) return st;
   if (st == SGW_OK) return SGW_OK;
   std::vector<sgw_solve_info> hinfo(n_sys);

@@ -27,10 +27,18 @@ template <> struct Split<64> { static constexpr int a = 8, b = 8; };
 template <> struct Split<72> { static constexpr int a = 8, b = 9; };
 
 template <int N, int SIGN> struct RegDft;
-template <int SIGN> struct RegDft<2, SIGN> { __device__ __forceinline__ static void run(double2 *v) { Dft<2, SIGN>::run(v); } };
-template <int SIGN> struct RegDft<3, SIGN> { __device__ __forceinline__ static void run(double2 *v) { Dft<3, SIGN>::run(v); } };
-template <int SIGN> struct RegDft<4, SIGN> { __device__ __forceinline__ static void run(double2 *v) { Dft<4, SIGN>::run(v); } };
-template <int SIGN> struct RegDft<8, SIGN> { __device__ __forceinline__ static void run(double2 *v) { Dft<8, SIGN>::run(v); } };
+template <int SIGN> struct RegDft<2, SIGN> {
+  template <class C2> __device__ __forceinline__ static void run(C2 *v) { Dft<2, SIGN>::run(v); }
+};
+template <int SIGN> struct RegDft<3, SIGN> {
+  template <class C2> __device__ __forceinline__ static void run(C2 *v) { Dft<3, SIGN>::run(v); }
+};
+template <int SIGN> struct RegDft<4, SIGN> {
+  template <class C2> __device__ __forceinline__ static void run(C2 *v) { Dft<4, SIGN>::run(v); }
+};
+template <int SIGN> struct RegDft<8, SIGN> {
+  template <class C2> __device__ __forceinline__ static void run(C2 *v) { Dft<8, SIGN>::run(v); }
+};
 
 constexpr int inv_mod(int a, int m) {
   for (int x = 1; x < m; ++x)
@@ -39,15 +47,15 @@ constexpr int inv_mod(int a, int m) {
 }
 
 // prime-factor DFT of length P*Q, gcd(P, Q) = 1
-template <int P, int Q, int SIGN>
-__device__ __forceinline__ void pfa_dft(double2 *v) {
+template <int P, int Q, int SIGN, class C2>
+__device__ __forceinline__ void pfa_dft(C2 *v) {
   constexpr int N = P * Q;
   constexpr int U = inv_mod(Q % P, P);
   constexpr int V = inv_mod(P % Q, Q);
-  double2 y[P][Q];
+  C2 y[P][Q];
 #pragma unroll
   for (int n2 = 0; n2 < Q; ++n2) {
-    double2 t[P];
+    C2 t[P];
 #pragma unroll
     for (int n1 = 0; n1 < P; ++n1) t[n1] = v[(Q * n1 + P * n2) % N];
     RegDft<P, SIGN>::run(t);
@@ -56,7 +64,7 @@ __device__ __forceinline__ void pfa_dft(double2 *v) {
   }
 #pragma unroll
   for (int k1 = 0; k1 < P; ++k1) {
-    double2 t[Q];
+    C2 t[Q];
 #pragma unroll
     for (int n2 = 0; n2 < Q; ++n2) t[n2] = y[k1][n2];
     RegDft<Q, SIGN>::run(t);
@@ -65,27 +73,34 @@ __device__ __forceinline__ void pfa_dft(double2 *v) {
   }
 }
 
-template <int SIGN> struct RegDft<6, SIGN> { __device__ __forceinline__ static void run(double2 *v) { pfa_dft<2, 3, SIGN>(v); } };
-template <int SIGN> struct RegDft<12, SIGN> { __device__ __forceinline__ static void run(double2 *v) { pfa_dft<4, 3, SIGN>(v); } };
+template <int SIGN> struct RegDft<6, SIGN> {
+  template <class C2> __device__ __forceinline__ static void run(C2 *v) { pfa_dft<2, 3, SIGN>(v); }
+};
+template <int SIGN> struct RegDft<12, SIGN> {
+  template <class C2> __device__ __forceinline__ static void run(C2 *v) { pfa_dft<4, 3, SIGN>(v); }
+};
 
 // exp(2 pi i m / 9) for m = 1, 2, 4
-__device__ __forceinline__ double2 root9(int m) {
-  return m == 1 ? make_double2(0.7660444431189780352024, 0.6427876096865393263226)
-       : m == 2 ? make_double2(0.1736481776669303488517, 0.9848077530122080593667)
-                : make_double2(-0.9396926207859083840541, 0.3420201433256687330441);
+template <class C2>
+__device__ __forceinline__ C2 root9(int m) {
+  using R = typename CT<C2>::R;
+  return m == 1 ? CT<C2>::make(R(0.7660444431189780352024), R(0.6427876096865393263226))
+       : m == 2 ? CT<C2>::make(R(0.1736481776669303488517), R(0.9848077530122080593667))
+                : CT<C2>::make(R(-0.9396926207859083840541), R(0.3420201433256687330441));
 }
 
 template <int SIGN> struct RegDft<9, SIGN> {
-  __device__ __forceinline__ static void run(double2 *v) {
-    double2 y[3][3];
+  template <class C2>
+  __device__ __forceinline__ static void run(C2 *v) {
+    C2 y[3][3];
 #pragma unroll
     for (int b = 0; b < 3; ++b) {
-      double2 t[3] = {v[b], v[3 + b], v[6 + b]};
+      C2 t[3] = {v[b], v[3 + b], v[6 + b]};
       Dft<3, SIGN>::run(t);
 #pragma unroll
       for (int ka = 0; ka < 3; ++ka) {
         if (b * ka != 0) {
-          double2 w = root9(b * ka);
+          C2 w = root9<C2>(b * ka);
           if (SIGN < 0) w.y = -w.y;
           t[ka] = c_mul(t[ka], w);
         }
@@ -94,7 +109,7 @@ template <int SIGN> struct RegDft<9, SIGN> {
     }
 #pragma unroll
     for (int ka = 0; ka < 3; ++ka) {
-      double2 t[3] = {y[0][ka], y[1][ka], y[2][ka]};
+      C2 t[3] = {y[0][ka], y[1][ka], y[2][ka]};
       Dft<3, SIGN>::run(t);
 #pragma unroll
       for (int kb = 0; kb < 3; ++kb) v[ka + 3 * kb] = t[kb];
@@ -103,9 +118,9 @@ template <int SIGN> struct RegDft<9, SIGN> {
 };
 
 // multiply v by w_N^(SIGN * m) read from a table tw[t] = exp(-2 pi i t / N)
-template <int SIGN>
-__device__ __forceinline__ double2 twiddle(double2 v, const double2 *tw, int m) {
-  double2 w = tw[m];
+template <int SIGN, class C2>
+__device__ __forceinline__ C2 twiddle(C2 v, const C2 *tw, int m) {
+  C2 w = tw[m];
   if (SIGN > 0) w.y = -w.y;
   return c_mul(v, w);
 }

@@ -40,53 +40,60 @@ struct RowBase {
 template <int N2> constexpr int sticks_per_block() { return N2 <= 32 ? 64 : 32; }
 constexpr int kStickThreads = 256;
 
-template <int N2>
-__global__ __launch_bounds__(kStickThreads) void k_sticks_inv(VecSrc x, double2 *__restrict__ T, int n_stick,
+template <class C2>
+__device__ __forceinline__ C2 to_c(double2 v) {
+  using R = typename CT<C2>::R;
+  return CT<C2>::make((R)v.x, (R)v.y);
+}
+
+template <class C2, int N2>
+__global__ __launch_bounds__(kStickThreads) void k_sticks_inv(VecSrc x, C2 *__restrict__ T, int n_stick,
                                                               const int32_t *__restrict__ stick_off,
                                                               const int32_t *__restrict__ pw_stick,
                                                               const int32_t *__restrict__ pw_z,
-                                                              const double2 *__restrict__ twg, int groups) {
+                                                              const C2 *__restrict__ twg, int groups) {
+  using R = typename CT<C2>::R;
   constexpr int SG = sticks_per_block<N2>();
   constexpr int LDC = N2 + 1;
-  __shared__ double2 col[SG * LDC];
-  __shared__ double2 tw[N2];
+  __shared__ C2 col[SG * LDC];
+  __shared__ C2 tw[N2];
   const int tid = threadIdx.x;
   const int vec = blockIdx.x / groups;
   const int s0 = (blockIdx.x - vec * groups) * SG;
   const int ns = min(SG, n_stick - s0);
   const double2 *xv = x.ptr(vec);
-  for (int i = tid; i < SG * LDC; i += kStickThreads) col[i] = make_double2(0.0, 0.0);
+  for (int i = tid; i < SG * LDC; i += kStickThreads) col[i] = CT<C2>::make(R(0), R(0));
   for (int i = tid; i < N2; i += kStickThreads) tw[i] = twg[i];
   __syncthreads();
   const int g0 = stick_off[s0], g1 = stick_off[s0 + ns];
-  for (int g = g0 + tid; g < g1; g += kStickThreads) col[(pw_stick[g] - s0) * LDC + pw_z[g]] = xv[g];
+  for (int g = g0 + tid; g < g1; g += kStickThreads) col[(pw_stick[g] - s0) * LDC + pw_z[g]] = to_c<C2>(xv[g]);
   __syncthreads();
   lds_fft<N2, +1, SG, kStickThreads, false>(col, ns, StrideBase{LDC}, 1, tw, tid);
-  double2 *Tv = T + (long)vec * N2 * n_stick + s0;
+  C2 *Tv = T + (long)vec * N2 * n_stick + s0;
   for (int i = tid; i < ns * N2; i += kStickThreads) {
     const int z = i / ns, s = i - z * ns;
     Tv[(long)z * n_stick + s] = col[s * LDC + z];
   }
 }
 
-template <int N2>
-__global__ __launch_bounds__(kStickThreads) void k_sticks_fwd(const double2 *__restrict__ T, int n_stick,
+template <class C2, int N2>
+__global__ __launch_bounds__(kStickThreads) void k_sticks_fwd(const C2 *__restrict__ T, int n_stick,
                                                               const int32_t *__restrict__ stick_off,
                                                               const int32_t *__restrict__ pw_stick,
                                                               const int32_t *__restrict__ pw_z,
-                                                              const double2 *__restrict__ twg, int groups,
+                                                              const C2 *__restrict__ twg, int groups,
                                                               VecSrc x, const double *__restrict__ kin,
                                                               double2 *__restrict__ y, long ldy, double scale) {
   constexpr int SG = sticks_per_block<N2>();
   constexpr int LDC = N2 + 1;
-  __shared__ double2 col[SG * LDC];
-  __shared__ double2 tw[N2];
+  __shared__ C2 col[SG * LDC];
+  __shared__ C2 tw[N2];
   const int tid = threadIdx.x;
   const int vec = blockIdx.x / groups;
   const int s0 = (blockIdx.x - vec * groups) * SG;
   const int ns = min(SG, n_stick - s0);
   for (int i = tid; i < N2; i += kStickThreads) tw[i] = twg[i];
-  const double2 *Tv = T + (long)vec * N2 * n_stick + s0;
+  const C2 *Tv = T + (long)vec * N2 * n_stick + s0;
   for (int i = tid; i < ns * N2; i += kStickThreads) {
     const int z = i / ns, s = i - z * ns;
     col[s * LDC + z] = Tv[(long)z * n_stick + s];
@@ -97,52 +104,61 @@ __global__ __launch_bounds__(kStickThreads) void k_sticks_fwd(const double2 *__r
   double2 *yv = y + (long)vec * ldy;
   const int g0 = stick_off[s0], g1 = stick_off[s0 + ns];
   for (int g = g0 + tid; g < g1; g += kStickThreads) {
-    const double2 c = col[(pw_stick[g] - s0) * LDC + pw_z[g]];
+    const C2 c = col[(pw_stick[g] - s0) * LDC + pw_z[g]];
     const double2 xg = xv[g];
     const double t = kin[g];
-    yv[g] = make_double2(fma(c.x, scale, t * xg.x), fma(c.y, scale, t * xg.y));
+    yv[g] = make_double2(fma((double)c.x, scale, t * xg.x), fma((double)c.y, scale, t * xg.y));
   }
 }
 
-template <int N2>
-sgw_status launch_sticks(sgw_ctx *ctx, const sgw_ham *h, int n_vec, VecSrc x, double2 *y, long ldy,
-                         double2 *tbuf, bool inverse) {
+template <class C2> const C2 *twiddles(const sgw_ham *h, int axis);
+template <> const double2 *twiddles<double2>(const sgw_ham *h, int axis) { return h->d_tw + h->tw_off[axis]; }
+template <> const float2 *twiddles<float2>(const sgw_ham *h, int axis) { return h->d_tw32 + h->tw_off[axis]; }
+template <class C2> const typename CT<C2>::R *potential(const sgw_ham *h);
+template <> const double *potential<double2>(const sgw_ham *h) { return h->d_vt; }
+template <> const float *potential<float2>(const sgw_ham *h) { return h->d_vt32; }
+
+template <class C2, int N2>
+sgw_status launch_sticks(sgw_ctx *ctx, const sgw_ham *h, int n_vec, VecSrc x, double2 *y, long ldy, C2 *tbuf,
+                         bool inverse) {
   constexpr int SG = sticks_per_block<N2>();
   const int groups = (h->n_stick + SG - 1) / SG;
   const long blocks = (long)groups * n_vec;
-  const double2 *tw = h->d_tw + h->tw_off[2];
-  const double n2 = N2, nst = h->n_stick, npw = h->n_pw;
+  const C2 *tw = twiddles<C2>(h, 2);
+  const double n2 = N2, nst = h->n_stick, npw = h->n_pw, cb = sizeof(C2);
   PendingTiming tm;
   if (inverse) {
-    timing_begin(ctx, K_STICKS_INV, n_vec * (npw * 16.0 + n2 * nst * 16.0), 0.0, &tm);
-    hipLaunchKernelGGL(k_sticks_inv<N2>, dim3(blocks), dim3(kStickThreads), 0, ctx->stream, x, tbuf,
+    timing_begin(ctx, K_STICKS_INV, n_vec * (npw * 16.0 + n2 * nst * cb), 0.0, &tm);
+    hipLaunchKernelGGL((k_sticks_inv<C2, N2>), dim3(blocks), dim3(kStickThreads), 0, ctx->stream, x, tbuf,
                        h->n_stick, h->d_stick_off, h->d_pw_stick, h->d_pw_z, tw, groups);
     timing_end(ctx, &tm);
   } else {
     const double scale = 1.0 / ((double)h->n[0] * h->n[1] * h->n[2]);
-    timing_begin(ctx, K_STICKS_FWD, n_vec * (npw * 32.0 + n2 * nst * 16.0), 0.0, &tm);
-    hipLaunchKernelGGL(k_sticks_fwd<N2>, dim3(blocks), dim3(kStickThreads), 0, ctx->stream, tbuf, h->n_stick,
-                       h->d_stick_off, h->d_pw_stick, h->d_pw_z, tw, groups, x, h->d_kin, y, ldy, scale);
+    timing_begin(ctx, K_STICKS_FWD, n_vec * (npw * 32.0 + n2 * nst * cb), 0.0, &tm);
+    hipLaunchKernelGGL((k_sticks_fwd<C2, N2>), dim3(blocks), dim3(kStickThreads), 0, ctx->stream, tbuf,
+                       h->n_stick, h->d_stick_off, h->d_pw_stick, h->d_pw_z, tw, groups, x, h->d_kin, y, ldy,
+                       scale);
     timing_end(ctx, &tm);
   }
   SGW_HIP(hipGetLastError());
   return SGW_OK;
 }
 
-template <int N0, int N1>
-sgw_status launch_planes(sgw_ctx *ctx, const sgw_ham *h, int n_vec, double2 *tbuf) {
+template <class C2, int N0, int N1>
+sgw_status launch_planes(sgw_ctx *ctx, const sgw_ham *h, int n_vec, C2 *tbuf) {
   const long blocks = (long)n_vec * h->n[2];
   PendingTiming tm;
   // algorithmic bytes: stick values in and out; the potential is read once per launch
-  const double bytes = (double)n_vec * h->n[2] * h->n_stick * 32.0 + (double)N0 * N1 * h->n[2] * 8.0;
+  const double bytes = (double)n_vec * h->n[2] * h->n_stick * 2.0 * sizeof(C2) +
+                       (double)N0 * N1 * h->n[2] * sizeof(typename CT<C2>::R);
   // algorithmic flops: 5 N log2 N per complex N-point transform (n_row rows and N1 columns, inverse
   // and forward) plus 2 per potential multiply, per plane
   const double per_plane = 2.0 * (h->n_row * 5.0 * N1 * std::log2((double)N1) + N1 * 5.0 * N0 * std::log2((double)N0)) +
                            2.0 * N0 * N1;
   timing_begin(ctx, K_PLANES, bytes, per_plane * h->n[2] * n_vec, &tm);
-  hipLaunchKernelGGL((k_planes<N0, N1>), dim3(blocks), dim3(plane_threads<N0, N1>()), 0, ctx->stream, tbuf,
-                     h->n[2], h->n_stick, h->d_rows, h->m0_lo, h->n_row, h->d_vt, h->d_tw + h->tw_off[0],
-                     h->d_tw + h->tw_off[1]);
+  hipLaunchKernelGGL((k_planes<C2, N0, N1>), dim3(blocks), dim3(plane_threads<N0, N1>()), 0, ctx->stream, tbuf,
+                     h->n[2], h->n_stick, h->d_rows, h->m0_lo, h->n_row, potential<C2>(h), twiddles<C2>(h, 0),
+                     twiddles<C2>(h, 1));
   timing_end(ctx, &tm);
   SGW_HIP(hipGetLastError());
   return SGW_OK;
@@ -150,35 +166,37 @@ sgw_status launch_planes(sgw_ctx *ctx, const sgw_ham *h, int n_vec, double2 *tbu
 
 #define SGW_GRID_LIST(X) X(16) X(24) X(32) X(48) X(64) X(72)
 
-sgw_status dispatch_sticks(sgw_ctx *ctx, const sgw_ham *h, int n_vec, VecSrc x, double2 *y, long ldy,
-                           double2 *tbuf, bool inverse) {
+template <class C2>
+sgw_status dispatch_sticks(sgw_ctx *ctx, const sgw_ham *h, int n_vec, VecSrc x, double2 *y, long ldy, C2 *tbuf,
+                           bool inverse) {
   switch (h->n[2]) {
 #define SGW_CASE(N) \
   case N:           \
-    return launch_sticks<N>(ctx, h, n_vec, x, y, ldy, tbuf, inverse);
+    return launch_sticks<C2, N>(ctx, h, n_vec, x, y, ldy, tbuf, inverse);
     SGW_GRID_LIST(SGW_CASE)
 #undef SGW_CASE
   }
   return fail(SGW_ERR_UNSUPPORTED, "grid size along axis 2 not supported");
 }
 
-template <int N0>
-sgw_status dispatch_planes_n1(sgw_ctx *ctx, const sgw_ham *h, int n_vec, double2 *tbuf) {
+template <class C2, int N0>
+sgw_status dispatch_planes_n1(sgw_ctx *ctx, const sgw_ham *h, int n_vec, C2 *tbuf) {
   switch (h->n[1]) {
 #define SGW_CASE(N) \
   case N:           \
-    return launch_planes<N0, N>(ctx, h, n_vec, tbuf);
+    return launch_planes<C2, N0, N>(ctx, h, n_vec, tbuf);
     SGW_GRID_LIST(SGW_CASE)
 #undef SGW_CASE
   }
   return fail(SGW_ERR_UNSUPPORTED, "grid size along axis 1 not supported");
 }
 
-sgw_status dispatch_planes(sgw_ctx *ctx, const sgw_ham *h, int n_vec, double2 *tbuf) {
+template <class C2>
+sgw_status dispatch_planes(sgw_ctx *ctx, const sgw_ham *h, int n_vec, C2 *tbuf) {
   switch (h->n[0]) {
 #define SGW_CASE(N) \
   case N:           \
-    return dispatch_planes_n1<N>(ctx, h, n_vec, tbuf);
+    return dispatch_planes_n1<C2, N>(ctx, h, n_vec, tbuf);
     SGW_GRID_LIST(SGW_CASE)
 #undef SGW_CASE
   }
@@ -198,13 +216,20 @@ bool hx_grid_supported(int n) {
   return false;
 }
 
-sgw_status hx_batch(sgw_ctx *ctx, const sgw_ham *h, int n_vec, VecSrc x, double2 *y, long ldy, double2 *tbuf) {
+template <class C2>
+sgw_status hx_run(sgw_ctx *ctx, const sgw_ham *h, int n_vec, VecSrc x, double2 *y, long ldy, C2 *tbuf) {
+  sgw_status st = dispatch_sticks<C2>(ctx, h, n_vec, x, nullptr, 0, tbuf, true);
+  if (st != SGW_OK) return st;
+  st = dispatch_planes<C2>(ctx, h, n_vec, tbuf);
+  if (st != SGW_OK) return st;
+  return dispatch_sticks<C2>(ctx, h, n_vec, x, y, ldy, tbuf, false);
+}
+
+sgw_status hx_batch(sgw_ctx *ctx, const sgw_ham *h, int n_vec, VecSrc x, double2 *y, long ldy, void *tbuf,
+                    bool fp32) {
   if (n_vec <= 0) return SGW_OK;
-  sgw_status st = dispatch_sticks(ctx, h, n_vec, x, nullptr, 0, tbuf, true);
-  if (st != SGW_OK) return st;
-  st = dispatch_planes(ctx, h, n_vec, tbuf);
-  if (st != SGW_OK) return st;
-  return dispatch_sticks(ctx, h, n_vec, x, y, ldy, tbuf, false);
+  if (fp32) return hx_run<float2>(ctx, h, n_vec, x, y, ldy, (float2 *)tbuf);
+  return hx_run<double2>(ctx, h, n_vec, x, y, ldy, (double2 *)tbuf);
 }
 
 }  // namespace sgw

@@ -25,30 +25,32 @@ namespace sgw {
 
 template <int N0, int N1> constexpr int plane_threads() { return N0 * N1 <= 48 * 48 ? 256 : 512; }
 
-template <int N0, int N1>
-__global__ __launch_bounds__((plane_threads<N0, N1>())) void k_planes(double2 *__restrict__ T, int n2, int n_stick,
+template <class C2, int N0, int N1>
+__global__ __launch_bounds__((plane_threads<N0, N1>())) void k_planes(C2 *__restrict__ T, int n2, int n_stick,
                                                                    const int4 *__restrict__ rows, int m0_lo,
-                                                                   int n_row, const double *__restrict__ vt,
-                                                                   const double2 *__restrict__ tw0g,
-                                                                   const double2 *__restrict__ tw1g) {
+                                                                   int n_row,
+                                                                   const typename CT<C2>::R *__restrict__ vt,
+                                                                   const C2 *__restrict__ tw0g,
+                                                                   const C2 *__restrict__ tw1g) {
+  using R = typename CT<C2>::R;
   constexpr int NT = plane_threads<N0, N1>();
   constexpr int LD = N1 + 1;
   constexpr int A0 = Split<N0>::a, B0 = Split<N0>::b;
   constexpr int A1 = Split<N1>::a, B1 = Split<N1>::b;
   constexpr int MTC = (N1 * B0 + NT - 1) / NT;  // axis-0 stage-1/3 tasks per thread
   constexpr int MTB = (N1 * A0 + NT - 1) / NT;  // axis-0 stage-2 tasks per thread
-  __shared__ double2 plane[N0 * LD];
-  __shared__ double2 tw0[N0];
-  __shared__ double2 tw1[N1];
+  __shared__ C2 plane[N0 * LD];
+  __shared__ C2 tw0[N0];
+  __shared__ C2 tw1[N1];
   __shared__ int4 rinfo[N0];
   const int tid = threadIdx.x;
   const int vec = blockIdx.x / n2;
   const int z = blockIdx.x - vec * n2;
-  double2 *Tz = T + ((long)vec * n2 + z) * n_stick;
-  const double *vz = vt + (long)z * N0 * N1;
+  C2 *Tz = T + ((long)vec * n2 + z) * n_stick;
+  const R *vz = vt + (long)z * N0 * N1;
 
   // prefetch this thread's potential values for the axis-0 middle stage
-  double vpre[MTB][B0];
+  R vpre[MTB][B0];
 #pragma unroll
   for (int m = 0; m < MTB; ++m) {
     const int task = tid + m * NT;
@@ -66,7 +68,7 @@ __global__ __launch_bounds__((plane_threads<N0, N1>())) void k_planes(double2 *_
     const int t = n_row + e / N1, i1 = e % N1;
     int i0 = m0_lo + t;
     i0 += i0 < 0 ? N0 : (i0 >= N0 ? -N0 : 0);
-    plane[i0 * LD + i1] = make_double2(0.0, 0.0);
+    plane[i0 * LD + i1] = CT<C2>::make(R(0), R(0));
   }
   __syncthreads();
   auto row_i0 = [&](int t) {
@@ -84,14 +86,14 @@ __global__ __launch_bounds__((plane_threads<N0, N1>())) void k_planes(double2 *_
     const int b = task / n_row, t = task - b * n_row;
     const int i0 = row_i0(t);
     const int4 ri = rinfo[t];
-    double2 v[A1];
+    C2 v[A1];
 #pragma unroll
     for (int a = 0; a < A1; ++a) {
       const int s = stick(ri, B1 * a + b);
-      v[a] = s >= 0 ? Tz[s] : make_double2(0.0, 0.0);
+      v[a] = s >= 0 ? Tz[s] : CT<C2>::make(R(0), R(0));
     }
     RegDft<A1, +1>::run(v);
-    double2 *row = plane + i0 * LD + b * A1;
+    C2 *row = plane + i0 * LD + b * A1;
     row[0] = v[0];
 #pragma unroll
     for (int ka = 1; ka < A1; ++ka) row[ka] = twiddle<+1>(v[ka], tw1, b * ka);
@@ -99,8 +101,8 @@ __global__ __launch_bounds__((plane_threads<N0, N1>())) void k_planes(double2 *_
   __syncthreads();
   for (int task = tid; task < n_row * A1; task += NT) {
     const int ka = task / n_row, t = task - ka * n_row;
-    double2 *row = plane + row_i0(t) * LD;
-    double2 v[B1];
+    C2 *row = plane + row_i0(t) * LD;
+    C2 v[B1];
 #pragma unroll
     for (int b = 0; b < B1; ++b) v[b] = row[b * A1 + ka];
     RegDft<B1, +1>::run(v);
@@ -110,7 +112,7 @@ __global__ __launch_bounds__((plane_threads<N0, N1>())) void k_planes(double2 *_
   __syncthreads();
 
   // ---- axis 0, inverse stage 1 (thread-consecutive columns) ----
-  double2 h[MTC][A0];
+  C2 h[MTC][A0];
 #pragma unroll
   for (int m = 0; m < MTC; ++m) {
     const int task = tid + m * NT;
@@ -139,7 +141,7 @@ __global__ __launch_bounds__((plane_threads<N0, N1>())) void k_planes(double2 *_
     const int task = tid + m * NT;
     if (task < N1 * A0) {
       const int i1 = task % N1, ka = task / N1;
-      double2 v[B0];
+      C2 v[B0];
 #pragma unroll
       for (int b = 0; b < B0; ++b) v[b] = plane[(b * A0 + ka) * LD + i1];
       RegDft<B0, +1>::run(v);
@@ -178,8 +180,8 @@ __global__ __launch_bounds__((plane_threads<N0, N1>())) void k_planes(double2 *_
   // ---- axis 1, forward, rows holding sticks; gather the sticks ----
   for (int task = tid; task < n_row * A1; task += NT) {
     const int c = task / n_row, t = task - c * n_row;
-    double2 *row = plane + row_i0(t) * LD;
-    double2 v[B1];
+    C2 *row = plane + row_i0(t) * LD;
+    C2 v[B1];
 #pragma unroll
     for (int d = 0; d < B1; ++d) v[d] = row[c + A1 * d];
     RegDft<B1, -1>::run(v);
@@ -190,9 +192,9 @@ __global__ __launch_bounds__((plane_threads<N0, N1>())) void k_planes(double2 *_
   __syncthreads();
   for (int task = tid; task < n_row * B1; task += NT) {
     const int e = task / n_row, t = task - e * n_row;
-    const double2 *row = plane + row_i0(t) * LD;
+    const C2 *row = plane + row_i0(t) * LD;
     const int4 ri = rinfo[t];
-    double2 v[A1];
+    C2 v[A1];
 #pragma unroll
     for (int c = 0; c < A1; ++c) v[c] = row[e * A1 + c];
     RegDft<A1, -1>::run(v);

@@ -100,8 +100,10 @@ struct sgw_ham {
   int32_t *d_miller_int = nullptr;  // [n_pw][3] internal order
   double *d_kin = nullptr;          // [n_pw] internal order, 0.5|k+G|^2
   double *d_vt = nullptr;           // [N2][N0][N1] potential, plane-major
+  float *d_vt32 = nullptr;          // the same in FP32
   int32_t *d_box = nullptr;         // [box volume] -> caller index or -1
   double2 *d_tw = nullptr;          // twiddles: 3 tables of N_d entries exp(-2 pi i t / N_d)
+  float2 *d_tw32 = nullptr;         // the same in FP32
   int tw_off[3];
 };
 
@@ -136,9 +138,11 @@ sgw_status ensure_pinned(sgw_ctx *ctx, size_t bytes);
 sgw_status sync(sgw_ctx *ctx);
 
 // H.x over a batch (internal order): y = T.x + F V F^-1 x.  `tbuf` holds
-// n_vec * N2 * n_stick complex entries.
-sgw_status hx_batch(sgw_ctx *ctx, const sgw_ham *h, int n_vec, VecSrc x, double2 *y, long ldy,
-                    double2 *tbuf);
+// n_vec * N2 * n_stick complex entries (complex128, or complex64 when fp32).
+// fp32: the potential term F V F^-1 x runs in FP32 (x rounded to FP32, FP32
+// transforms and potential); the kinetic term and y stay FP64.
+sgw_status hx_batch(sgw_ctx *ctx, const sgw_ham *h, int n_vec, VecSrc x, double2 *y, long ldy, void *tbuf,
+                    bool fp32 = false);
 bool hx_grid_supported(int n);
 
 // Projector pieces (internal order, FP64 MFMA).  The overlaps are produced as

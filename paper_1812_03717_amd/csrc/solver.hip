@@ -31,6 +31,20 @@ __device__ __forceinline__ double block_sum(double v, double *sh) {
   return r;
 }
 
+template <int NT>
+__device__ __forceinline__ double block_max(double v, double *sh) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double r = sh[0];
+#pragma unroll
+  for (int w = 1; w < NT / 64; ++w) r = fmax(r, sh[w]);
+  __syncthreads();
+  return r;
+}
+
 // M simultaneous block sums; results in out[0..M) for every thread
 template <int NT, int M>
 __device__ __forceinline__ void block_sum_n(double *v, double *sh, double *out) {
@@ -142,6 +156,7 @@ __global__ __launch_bounds__(kRowThreads) void k_init(SolverState S, const doubl
     const int v = pair / S.n_pert;
     S.pair[slot] = pair;
     S.kcur[slot] = 0;
+    S.maxres[slot] = 1.0;
     S.eps[slot] = S.eps_band[v];
     S.beta[(long)slot * (S.kmax + 1)] = nb;
     int st = SLOT_RUNNING;
@@ -216,6 +231,7 @@ __global__ __launch_bounds__(kLzThreads) void k_lanczos(SolverState S, const int
     if (g < npw) vn[g] = c_scale(w[e], inv);
   }
   // shift recurrences: rho_k(z) = a_k - z - beta_k^2 / rho_{k-1}(z); res *= beta_{k+1} / |rho_k|
+  double rmax = 0.0;
   for (int j = threadIdx.x; j < S.n_omega; j += kLzThreads) {
     const long idx = (long)slot * S.n_omega + j;
     double2 rho = make_double2(ak - S.omega[j], -S.eta);
@@ -228,11 +244,13 @@ __global__ __launch_bounds__(kLzThreads) void k_lanczos(SolverState S, const int
     S.rho[idx] = rho;
     const double r = S.res[idx] * bn / sqrt(rho.x * rho.x + rho.y * rho.y);
     S.res[idx] = r;
+    rmax = fmax(rmax, isfinite(r) ? r : 1e300);
     if (!(r <= S.tol_int)) all_conv = 0;
     else if (S.conv[idx] < 0) S.conv[idx] = k + 1;
   }
-  __syncthreads();
+  const double slot_max = block_max<kLzThreads>(rmax, sh);
   if (threadIdx.x == 0) {
+    S.maxres[slot] = slot_max;
     S.alpha_t[(long)slot * S.kmax + k] = ak;
     S.beta[(long)slot * (S.kmax + 1) + k + 1] = bn;
     S.kcur[slot] = k + 1;
@@ -415,8 +433,8 @@ __global__ __launch_bounds__(kRowThreads) void k_residual(SolverState S, const i
   }
 }
 
-__global__ void k_transpose_potential(const double *__restrict__ v, double *__restrict__ vt, int n0, int n1,
-                                      int n2) {
+__global__ void k_transpose_potential(const double *__restrict__ v, double *__restrict__ vt,
+                                      float *__restrict__ vt32, int n0, int n1, int n2) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   const long n = (long)n0 * n1 * n2;
   if (i >= n) return;
@@ -424,7 +442,9 @@ __global__ void k_transpose_potential(const double *__restrict__ v, double *__re
   const int i1 = i % n1;
   const int i0 = (i / n1) % n0;
   const int i2 = i / ((long)n0 * n1);
-  vt[i] = v[((long)i0 * n1 + i1) * n2 + i2];
+  const double x = v[((long)i0 * n1 + i1) * n2 + i2];
+  vt[i] = x;
+  vt32[i] = (float)x;
 }
 
 }  // namespace
@@ -547,10 +567,10 @@ sgw_status residual(sgw_ctx *ctx, const SolverState &S, const int32_t *flist, in
   return SGW_OK;
 }
 
-sgw_status transpose_potential(sgw_ctx *ctx, const double *v, double *vt, const int n[3]) {
+sgw_status transpose_potential(sgw_ctx *ctx, const double *v, double *vt, float *vt32, const int n[3]) {
   const long tot = (long)n[0] * n[1] * n[2];
-  hipLaunchKernelGGL(k_transpose_potential, dim3((tot + 255) / 256), dim3(256), 0, ctx->stream, v, vt, n[0], n[1],
-                     n[2]);
+  hipLaunchKernelGGL(k_transpose_potential, dim3((tot + 255) / 256), dim3(256), 0, ctx->stream, v, vt, vt32, n[0],
+                     n[1], n[2]);
   SGW_HIP(hipGetLastError());
   return SGW_OK;
 }

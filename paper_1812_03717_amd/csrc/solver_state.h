@@ -11,6 +11,9 @@ namespace sgw {
 
 constexpr int kMaxOcc = 256;  // occupied states held in LDS by the per-vector kernels
 // ||(1 - P_occ) s|| below this fraction of ||s|| counts as a zero right-hand side
+// mixed precision: default of sgw_opts.mixed_switch (a slot's Krylov steps apply the potential in
+// FP32 once the largest estimated relative residual of its shifts is below mixed_switch * tol)
+constexpr double kMixedSwitch = 1e4;
 constexpr double kZeroRhsRel = 1e-13;
 
 enum SlotStatus {
@@ -33,6 +36,7 @@ struct SolverState {
   double *beta;              // [slots][kmax + 1]; beta[0] = ||b||
   double2 *rho;              // [slots][n_omega] last LU pivot per shift
   double *res;               // [slots][n_omega] estimated relative residual
+  double *maxres;            // [slots] largest estimated relative residual over the shifts
   int32_t *conv;             // [slots][n_omega] Krylov dimension at which the estimate met tol_int, or -1
   int32_t *pair;             // [slots] pair index v * n_pert + p
   int32_t *kcur;             // [slots] completed steps
@@ -59,7 +63,8 @@ sgw_status combine(sgw_ctx *ctx, const SolverState &S, const int32_t *flist, int
 sgw_status residual(sgw_ctx *ctx, const SolverState &S, const int32_t *flist, int nf, const double2 *X,
                     const double2 *AX, const double2 *cp, long rows, const int32_t *i2u, double2 *dpsi,
                     sgw_solve_info *info, double tol, int *n_bad);
-sgw_status transpose_potential(sgw_ctx *ctx, const double *v, double *vt, const int n[3]);
+// plane-major copies of the potential, FP64 and FP32
+sgw_status transpose_potential(sgw_ctx *ctx, const double *v, double *vt, float *vt32, const int n[3]);
 int lanczos_ept(int npw);
 
 }  // namespace sgw

@@ -21,6 +21,7 @@ SGW_ERR_INVALID_ARG, SGW_ERR_HIP, SGW_ERR_WORKSPACE, SGW_ERR_UNSUPPORTED = -1, -
 FLAG_CONVERGED, FLAG_MAXITER, FLAG_BREAKDOWN, FLAG_NONFINITE, FLAG_ZERO_RHS = 1, 2, 4, 8, 16
 FLAG_PER_SHIFT = 32
 SOLVER_MULTISHIFT, SOLVER_PER_SHIFT, SOLVER_TAIL = 0, 1, 2
+FP64, MIXED = 0, 1
 PC_NONE, PC_TETER, PC_LEARNED = 0, 1, 2
 GUESS_ZERO, GUESS_LEARNED = 0, 1
 
@@ -54,7 +55,7 @@ class sgw_opts(C.Structure):
                 ("steps_per_sync", C.c_int32), ("solver", C.c_int32), ("precond", C.c_int32),
                 ("guess", C.c_int32), ("tail_iter", C.c_int32), ("ps_max_iter", C.c_int32),
                 ("ps_slots", C.c_int32), ("mlp", C.c_void_p), ("hist_r", C.c_void_p), ("hist_x", C.c_void_p),
-                ("hist_iter", C.c_int32), ("graph", C.c_int32)]
+                ("hist_iter", C.c_int32), ("mixed_switch", C.c_double), ("graph", C.c_int32)]
 
 
 class sgw_problem(C.Structure):
@@ -88,7 +89,7 @@ def load_library(path: str = LIB_PATH):
         "sgw_kernel_stats": [vp, C.c_char_p, C.POINTER(C.c_int64), C.POINTER(dbl), C.POINTER(dbl), C.POINTER(dbl)],
         "sgw_ham_create": [vp, C.POINTER(sgw_ham_desc), C.POINTER(vp)],
         "sgw_ham_destroy": [vp],
-        "sgw_apply_h": [vp, vp, C.c_int, vp, vp],
+        "sgw_apply_h": [vp, vp, C.c_int, vp, vp, C.c_int],
         "sgw_apply_projector": [vp, vp, C.c_int, vp, C.c_int, vp, vp, dbl, C.c_int],
         "sgw_build_rhs": [vp, vp, C.c_int, vp, vp, C.c_int, vp, C.c_int, C.POINTER(i32), vp],
         "sgw_opts_default": [C.POINTER(sgw_opts)],
@@ -221,11 +222,11 @@ class sgw_ham_create:
 # calls
 # ---------------------------------------------------------------------------
 
-def sgw_apply_h(ctx, ham, x):
+def sgw_apply_h(ctx, ham, x, precision=0):
     import torch
     _require(x, torch.complex128, ctx.device, (x.shape[0], ham.n_pw), "x")
     y = torch.empty_like(x)
-    _check(load_library().sgw_apply_h(ctx.handle, ham.handle, int(x.shape[0]), _ptr(x), _ptr(y)))
+    _check(load_library().sgw_apply_h(ctx.handle, ham.handle, int(x.shape[0]), _ptr(x), _ptr(y), int(precision)))
     return y
 
 

@@ -40,7 +40,7 @@ def test_host_side_calls():
     assert lib.sternheimer_workspace_size(None, None, 1, 1, 1, 1, None, C.byref(n)) == sgw.SGW_ERR_INVALID_ARG
     assert lib.sgw_ctx_create(0, None, None) == sgw.SGW_ERR_INVALID_ARG
     assert lib.sgw_ham_create(None, None, None) == sgw.SGW_ERR_INVALID_ARG
-    assert lib.sgw_apply_h(None, None, 1, None, None) == sgw.SGW_ERR_INVALID_ARG
+    assert lib.sgw_apply_h(None, None, 1, None, None, 0) == sgw.SGW_ERR_INVALID_ARG
     assert lib.sgw_kernel_stats(None, b"hx_planes", None, None, None, None) == sgw.SGW_ERR_INVALID_ARG
     st = lib.sternheimer_solve(None, None, 0, None, None, 0, None, None, 0, None, 0, None, 0.1, 1e-8, None, None,
                                0, None, None)

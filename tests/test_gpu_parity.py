@@ -58,6 +58,29 @@ def test_apply_h_matches_dense(ctx, name):
         assert err <= 1e-12
 
 
+@pytest.mark.parametrize("name", sorted(PROBLEMS))
+def test_apply_h_mixed_precision(ctx, name):
+    """FP32 potential term: error bound from the FP32 unit roundoff u = 6e-8 grown over the
+    ~2 log2(N) radix stages of the inverse and forward 3D transforms (~2*3*3 = 18 passes here), on
+    the potential part only: |y32 - y| <= 18 u max|V| ||x||_inf * (small constant) -> 2e-5 max|y|."""
+    from paper_1812_03717_amd import sgw
+    p = PROBLEMS[name]()
+    d = _dev(ctx, p)
+    rng = np.random.default_rng(3)
+    n = p.miller_kq.shape[0]
+    x = rng.standard_normal((5, n)) + 1j * rng.standard_normal((5, n))
+    xt = torch.from_numpy(x).to(ctx.device)
+    y64 = sgw.sgw_apply_h(ctx, d.h_kq, xt, precision=sgw.FP64).cpu().numpy()
+    y32 = sgw.sgw_apply_h(ctx, d.h_kq, xt, precision=sgw.MIXED).cpu().numpy()
+    h = so.hamiltonian(p.miller_kq, p.B, p.kvec + p.qvec, p.v_grid)
+    yr = x @ h.T
+    e64 = np.abs(y64 - yr).max() / np.abs(yr).max()
+    e32 = np.abs(y32 - yr).max() / np.abs(yr).max()
+    print(name, "apply_h rel err fp64", e64, "mixed", e32, flush=True)
+    assert e64 <= 1e-12
+    assert 1e-10 < e32 <= 2e-5
+
+
 def test_apply_projector(ctx):
     from paper_1812_03717_amd import sgw
     p = PROBLEMS["fcc1_q"]()

@@ -100,6 +100,23 @@ def test_tail_matches_oracle(ctx, case):
     _check_parity(p, pairs, xs, dpsi.cpu().numpy(), inf, tol)
 
 
+def test_mixed_precision_solve_matches_oracle(ctx, case):
+    """FP32-potential multishift phase, then FP64 per-shift refinement: every solve meets the FP64
+    true residual, so the oracle bar is unchanged."""
+    from paper_1812_03717_amd import sgw
+    p, d, pairs, xs, tol = case
+    opts = sgw.sgw_opts_default(precision=sgw.MIXED, precond=sgw.PC_TETER)
+    st, dpsi, info = d.solve(tol=tol, opts=opts)
+    inf = sgw.info_to_numpy(info, (p.n_band, p.n_pert, p.n_omega))
+    assert st == sgw.SGW_OK, sgw.load_library().sgw_last_error()
+    refined = (inf["flags"] & sgw.FLAG_PER_SHIFT) != 0
+    print("mixed: refined", refined.sum(), "of", refined.size, "refinement iters mean",
+          inf["iters"][refined].mean() if refined.any() else 0, flush=True)
+    _check_parity(p, pairs, xs, dpsi.cpu().numpy(), inf, tol)
+    with pytest.raises(sgw.SgwError):
+        d.solve(tol=tol, opts=sgw.sgw_opts_default(precision=sgw.MIXED, solver=sgw.SOLVER_PER_SHIFT))
+
+
 def test_learned_solve_matches_oracle(ctx, case):
     """Untrained model (m = g = 1/(T+1)) as preconditioner and initial guess: same solutions."""
     from paper_1812_03717_amd import sgw
