@@ -24,7 +24,6 @@
 namespace sgw {
 
 template <int N0, int N1> constexpr int plane_threads() { return N0 * N1 <= 48 * 48 ? 256 : 512; }
-
 template <class C2, int N0, int N1>
 __global__ __launch_bounds__((plane_threads<N0, N1>())) void k_planes(C2 *__restrict__ T, int n2, int n_stick,
                                                                    const int4 *__restrict__ rows, int m0_lo,

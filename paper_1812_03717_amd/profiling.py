@@ -41,8 +41,20 @@ def source_hash(kernel: str) -> str:
 
 
 def short_name(n: str) -> str:
-    m = re.search(r"(k_\w+)(<[^>]*>)?", n)
-    return (m.group(1) + (m.group(2) or "")) if m else n[:60]
+    """Kernel symbol with its template arguments, e.g. k_planes<double2, 48, 48>."""
+    n = n.replace("HIP_vector_type<double, 2u>", "double2").replace("HIP_vector_type<float, 2u>", "float2")
+    m = re.search(r"k_\w+", n)
+    if not m:
+        return n[:60]
+    out, i = m.group(0), m.end()
+    if i < len(n) and n[i] == "<":
+        depth = 0
+        for j in range(i, len(n)):
+            depth += (n[j] == "<") - (n[j] == ">")
+            if depth == 0:
+                out += n[i:j + 1]
+                break
+    return out
 
 
 def top(db: str):
