@@ -40,14 +40,18 @@ def _lu_reference(p, h, v, q, om, eta):
     return b, so.solve_lu(a0, b, om + 1j * eta)
 
 
-def test_si16_full_workload(setup):
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_si16_full_workload(setup, precision):
+    """Both precisions bench.py times: plain FP64, and FP32 potential matvecs late in each pair."""
     from paper_1812_03717_amd import sgw
     p, ctx, dev, h = setup
-    st, dpsi, info = dev.solve()           # default options, as bench.py runs it
+    opts = sgw.sgw_opts_default(precision=sgw.MIXED if precision == "mixed" else sgw.FP64)
+    st, dpsi, info = dev.solve(opts=opts)
     torch.cuda.synchronize()
     inf = sgw.info_to_numpy(info, (p.n_band, p.n_pert, p.n_omega))
-    print(f"status {st}; iters {inf['iters'].min()}..{inf['iters'].max()}; max relres {inf['relres'].max():.3e}; "
-          f"max occ leak {inf['occ_leak'].max():.3e}", flush=True)
+    print(f"{precision}: status {st}; iters {inf['iters'].min()}..{inf['iters'].max()}; "
+          f"max relres {inf['relres'].max():.3e}; max occ leak {inf['occ_leak'].max():.3e}; "
+          f"refined per shift {int(np.count_nonzero(inf['flags'] & sgw.FLAG_PER_SHIFT))}", flush=True)
     assert st == sgw.SGW_OK
     assert np.all(inf["flags"] & sgw.FLAG_CONVERGED)
     assert inf["relres"].max() <= p.tol
