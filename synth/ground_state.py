@@ -28,6 +28,40 @@ def _potential_matrix(miller: np.ndarray, v_grid: np.ndarray) -> np.ndarray:
     return vq[d0, d1, d2]
 
 
+# above this many plane waves the dense eigensolver runs on the GPU when one is present
+GPU_EIGH_MIN_PW = 8000
+
+
+def _lowest_states_gpu(miller, B, kvec, v_grid, n_states):
+    """The same Hamiltonian and eigenpairs with torch.linalg.eigh on the GPU (rocSOLVER): for the
+    64-atom cell the CPU eigensolver takes over a quarter of an hour.  Input generation only."""
+    import torch
+    dev = torch.device("cuda")
+    grid = v_grid.shape
+    vq = torch.from_numpy(np.fft.fftn(v_grid) / v_grid.size).to(dev)
+    m = torch.from_numpy(miller.astype(np.int64)).to(dev)
+    n = m.shape[0]
+    h = torch.empty((n, n), dtype=torch.complex128, device=dev)
+    for r0 in range(0, n, 2048):  # rows in blocks to bound the index tensors
+        mr = m[r0:r0 + 2048]
+        d = [(mr[:, None, a] - m[None, :, a]) % grid[a] for a in range(3)]
+        h[r0:r0 + 2048] = vq[d[0], d[1], d[2]]
+    h.diagonal().add_(torch.from_numpy(kinetic_energies(miller, B, kvec)).to(dev))
+    h = 0.5 * (h + h.conj().T)
+    import sys
+    import time
+    t0 = time.time()
+    print(f"[synth] dense eigh of {n} plane waves on the GPU", file=sys.stderr, flush=True)
+    w, u = torch.linalg.eigh(h)
+    torch.cuda.synchronize()
+    print(f"[synth] eigh done in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
+    w = w[:n_states].cpu().numpy()
+    u = u[:, :n_states].T.contiguous().cpu().numpy()
+    del h
+    torch.cuda.empty_cache()
+    return w, u
+
+
 def lowest_states(miller: np.ndarray, B: np.ndarray, kvec, v_grid: np.ndarray, n_states: int):
     """Lowest ``n_states`` eigenpairs of the plane-wave Hamiltonian.
 
@@ -35,13 +69,24 @@ def lowest_states(miller: np.ndarray, B: np.ndarray, kvec, v_grid: np.ndarray, n
     coefficient rows in the order of ``miller``).  Each state's phase is fixed so
     that its largest-magnitude coefficient (first one on ties) is real positive.
     """
-    h = _potential_matrix(miller, v_grid)
-    h[np.diag_indices_from(h)] += kinetic_energies(miller, B, kvec)
-    h = 0.5 * (h + h.conj().T)
-    n_states = min(n_states, h.shape[0])
-    w, u = sla.eigh(h, subset_by_index=[0, n_states - 1], driver="evr")
-    u = u.T.copy()
+    n_states = min(n_states, miller.shape[0])
+    if miller.shape[0] >= GPU_EIGH_MIN_PW and _gpu_present():
+        w, u = _lowest_states_gpu(miller, B, kvec, v_grid, n_states)
+    else:
+        h = _potential_matrix(miller, v_grid)
+        h[np.diag_indices_from(h)] += kinetic_energies(miller, B, kvec)
+        h = 0.5 * (h + h.conj().T)
+        w, u = sla.eigh(h, subset_by_index=[0, n_states - 1], driver="evr")
+        u = u.T.copy()
     piv = np.argmax(np.abs(u), axis=1)
     ph = u[np.arange(u.shape[0]), piv]
     u *= (np.abs(ph) / ph)[:, None]
     return w, np.ascontiguousarray(u)
+
+
+def _gpu_present() -> bool:
+    try:
+        import torch
+        return torch.cuda.is_available()
+    except ImportError:  # pragma: no cover
+        return False
