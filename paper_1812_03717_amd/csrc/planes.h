@@ -6,8 +6,8 @@
 // with one LDS exchange in between; along axis 0 the inverse's second stage,
 // the potential and the forward's first stage run on the same registers, so a
 // column makes three LDS round trips for inverse + V + forward.  Rows (fixed
-// i0) outside the sticks' m0 range are zero on input; they are zero-filled
-// once so that the axis-0 stages read and write unconditionally.
+// i0) outside the sticks' m0 range are zero on input and not needed on output:
+// the axis-0 stages skip their LDS reads (using 0) and their final writes.
 //
 // Stick lookup: within a row the sticks are one contiguous run of m1 values
 // (the basis is a sphere, so its (m0, m1) projection is convex); rows[t] =
@@ -23,7 +23,14 @@
 
 namespace sgw {
 
-template <int N0, int N1> constexpr int plane_threads() { return N0 * N1 <= 48 * 48 ? 256 : 512; }
+// Threads per plane workgroup.  Planes up to 48 x 48 fit four workgroups of 256 per CU.  Larger
+// planes fill most of the LDS with one workgroup per CU, so it takes one thread per axis-0 column
+// task (whole wavefronts): more waves to hide LDS latency and one task's registers per thread.
+template <int N0, int N1> constexpr int plane_threads() {
+  constexpr int tasks = N1 * (Split<N0>::a > Split<N0>::b ? Split<N0>::a : Split<N0>::b);
+  constexpr int nt = (tasks + 63) / 64 * 64;
+  return N0 * N1 <= 48 * 48 ? 256 : (nt > 1024 ? 1024 : nt);
+}
 template <class C2, int N0, int N1>
 __global__ __launch_bounds__((plane_threads<N0, N1>())) void k_planes(C2 *__restrict__ T, int n2, int n_stick,
                                                                    const int4 *__restrict__ rows, int m0_lo,
@@ -48,28 +55,32 @@ __global__ __launch_bounds__((plane_threads<N0, N1>())) void k_planes(C2 *__rest
   C2 *Tz = T + ((long)vec * n2 + z) * n_stick;
   const R *vz = vt + (long)z * N0 * N1;
 
-  // prefetch this thread's potential values for the axis-0 middle stage
-  R vpre[MTB][B0];
+  // Planes up to 48 x 48 prefetch this thread's potential values for the axis-0 middle stage (the
+  // registers do not lower their occupancy, which the LDS sets); larger planes load them there.
+  constexpr bool kPrefetchV = N0 * N1 <= 48 * 48;
+  R vpre[kPrefetchV ? MTB : 1][B0];
+  if constexpr (kPrefetchV) {
 #pragma unroll
-  for (int m = 0; m < MTB; ++m) {
-    const int task = tid + m * NT;
-    if (task < N1 * A0) {
-      const int i1 = task % N1, ka = task / N1;
+    for (int m = 0; m < MTB; ++m) {
+      const int task = tid + m * NT;
+      if (task < N1 * A0) {
+        const int i1 = task % N1, ka = task / N1;
 #pragma unroll
-      for (int kb = 0; kb < B0; ++kb) vpre[m][kb] = vz[(ka + A0 * kb) * N1 + i1];
+        for (int kb = 0; kb < B0; ++kb) vpre[m][kb] = vz[(ka + A0 * kb) * N1 + i1];
+      }
     }
   }
   for (int i = tid; i < N0; i += NT) tw0[i] = tw0g[i];
   for (int i = tid; i < N1; i += NT) tw1[i] = tw1g[i];
   for (int i = tid; i < n_row; i += NT) rinfo[i] = rows[i];
-  // rows outside the stick range are zero
-  for (int e = tid; e < (N0 - n_row) * N1; e += NT) {
-    const int t = n_row + e / N1, i1 = e % N1;
-    int i0 = m0_lo + t;
-    i0 += i0 < 0 ? N0 : (i0 >= N0 ? -N0 : 0);
-    plane[i0 * LD + i1] = CT<C2>::make(R(0), R(0));
-  }
   __syncthreads();
+  // Rows outside the stick range are zero after the axis-1 inverse and unused by the axis-1
+  // forward: the axis-0 stages neither read them (they use 0) nor write them back.
+  auto stick_row = [&](int i0) {
+    int t = i0 - m0_lo;
+    t += t < 0 ? N0 : (t >= N0 ? -N0 : 0);
+    return t < n_row;
+  };
   auto row_i0 = [&](int t) {
     const int i0 = m0_lo + t;
     return i0 < 0 ? i0 + N0 : i0;
@@ -118,7 +129,8 @@ __global__ __launch_bounds__((plane_threads<N0, N1>())) void k_planes(C2 *__rest
     if (task < N1 * B0) {
       const int i1 = task % N1, b = task / N1;
 #pragma unroll
-      for (int a = 0; a < A0; ++a) h[m][a] = plane[(B0 * a + b) * LD + i1];
+      for (int a = 0; a < A0; ++a)
+        h[m][a] = stick_row(B0 * a + b) ? plane[(B0 * a + b) * LD + i1] : CT<C2>::make(R(0), R(0));
     }
   }
   __syncthreads();
@@ -143,9 +155,12 @@ __global__ __launch_bounds__((plane_threads<N0, N1>())) void k_planes(C2 *__rest
       C2 v[B0];
 #pragma unroll
       for (int b = 0; b < B0; ++b) v[b] = plane[(b * A0 + ka) * LD + i1];
+      R vr[B0];
+#pragma unroll
+      for (int kb = 0; kb < B0; ++kb) vr[kb] = kPrefetchV ? vpre[kPrefetchV ? m : 0][kb] : vz[(ka + A0 * kb) * N1 + i1];
       RegDft<B0, +1>::run(v);
 #pragma unroll
-      for (int kb = 0; kb < B0; ++kb) v[kb] = c_scale(v[kb], vpre[m][kb]);
+      for (int kb = 0; kb < B0; ++kb) v[kb] = c_scale(v[kb], vr[kb]);
       RegDft<B0, -1>::run(v);
       plane[ka * LD + i1] = v[0];
 #pragma unroll
@@ -171,7 +186,8 @@ __global__ __launch_bounds__((plane_threads<N0, N1>())) void k_planes(C2 *__rest
       const int i1 = task % N1, e = task / N1;
       RegDft<A0, -1>::run(h[m]);
 #pragma unroll
-      for (int f = 0; f < A0; ++f) plane[(e + B0 * f) * LD + i1] = h[m][f];
+      for (int f = 0; f < A0; ++f)
+        if (stick_row(e + B0 * f)) plane[(e + B0 * f) * LD + i1] = h[m][f];
     }
   }
   __syncthreads();
