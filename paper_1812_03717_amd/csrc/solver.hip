@@ -315,15 +315,25 @@ __global__ void k_tridiag(SolverState S, const int32_t *__restrict__ flist, int 
 constexpr int kCmbThreads = 256;
 constexpr int kCmbJ = 16;
 constexpr int kCmbK = 32;
+// workgroups are dealt round-robin to the GPU's 8 XCDs (each with its own L2)
+constexpr int kXcds = 8;
 
+// One workgroup per (slot, tile of 256 plane waves, chunk of 16 shifts).  The chunks of a tile read
+// the same basis vectors; workgroup ids are arranged so that they run on one XCD (ids spaced by
+// kXcds, dispatched close together) and share that XCD's L2 copy of the tile.
 __global__ __launch_bounds__(kCmbThreads) void k_combine(SolverState S, const int32_t *__restrict__ flist,
                                                          const double2 *__restrict__ ycoef,
-                                                         double2 *__restrict__ X, int gtiles, int jchunks) {
+                                                         double2 *__restrict__ X, int gtiles, int jchunks,
+                                                         int ntiles) {
   __shared__ double2 yt[kCmbK][kCmbJ];
   int b = blockIdx.x;
-  const int jc = b % jchunks; b /= jchunks;
-  const int gt = b % gtiles;
-  const int f = b / gtiles;
+  const int xcd = b % kXcds;
+  b /= kXcds;
+  const int jc = b % jchunks;
+  const int tile = (b / jchunks) * kXcds + xcd;
+  if (tile >= ntiles) return;
+  const int gt = tile % gtiles;
+  const int f = tile / gtiles;
   const int slot = flist[f];
   const int K = S.kcur[slot];
   const int nw = S.n_omega;
@@ -545,8 +555,10 @@ sgw_status combine(sgw_ctx *ctx, const SolverState &S, const int32_t *flist, int
   PendingTiming tm;
   const double bytes = nf * (est_kavg * S.npw * 16.0 + (double)S.n_omega * S.npw * 16.0);
   timing_begin(ctx, K_COMBINE, bytes, 8.0 * nf * est_kavg * S.npw * S.n_omega, &tm);
-  hipLaunchKernelGGL(k_combine, dim3((long)nf * gtiles * jchunks), dim3(kCmbThreads), 0, ctx->stream, S, flist,
-                     ycoef, X, gtiles, jchunks);
+  const int ntiles = nf * gtiles;
+  const long groups = (long)(ntiles + kXcds - 1) / kXcds * kXcds * jchunks;
+  hipLaunchKernelGGL(k_combine, dim3(groups), dim3(kCmbThreads), 0, ctx->stream, S, flist, ycoef, X, gtiles,
+                     jchunks, ntiles);
   timing_end(ctx, &tm);
   SGW_HIP(hipGetLastError());
   return SGW_OK;
