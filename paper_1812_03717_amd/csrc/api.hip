@@ -205,7 +205,7 @@ static sgw_status upload(sgw_ctx *ctx, T **dst, const std::vector<T> &src) {
 
 static void ham_free(sgw_ham *h) {
   if (!h) return;
-  void *ptrs[] = {h->d_i2u, h->d_u2i, h->d_stick_off, h->d_rows, h->d_pw_stick, h->d_pw_z,
+  void *ptrs[] = {h->d_i2u, h->d_u2i, h->d_stick_off, h->d_rows, h->d_stick_ij, h->d_pw_stick, h->d_pw_z,
                   h->d_miller_int, h->d_kin, h->d_vt, h->d_box, h->d_tw, h->d_vt32, h->d_tw32};
   for (void *p : ptrs)
     if (p) hipFree(p);
@@ -265,7 +265,7 @@ extern "C" sgw_status sgw_ham_create(sgw_ctx *ctx, const sgw_ham_desc *d, sgw_ha
     if (ma[1] != mb[1]) return ma[1] < mb[1];
     return ma[2] < mb[2];
   });
-  std::vector<int32_t> i2u(npw), u2i(npw), pw_stick(npw), pw_z(npw), miller_int(3 * npw), stick_off;
+  std::vector<int32_t> i2u(npw), u2i(npw), pw_stick(npw), pw_z(npw), miller_int(3 * npw), stick_off, stick_ij;
   // per row m0 = mmin[0] + t: first stick and the m1 range (one contiguous run)
   std::vector<int4> rows(mmax[0] - mmin[0] + 1, make_int4(0, 1, 0, 0));
   std::vector<char> row_seen(rows.size(), 0);
@@ -276,6 +276,7 @@ extern "C" sgw_status sgw_ham_create(sgw_ctx *ctx, const sgw_ham_desc *d, sgw_ha
     const int *m = d->miller + 3 * u;
     if (gi == 0 || m[0] != d->miller[3 * order[gi - 1]] || m[1] != d->miller[3 * order[gi - 1] + 1]) {
       stick_off.push_back(gi);
+      stick_ij.push_back((imod(m[0], n[0]) << 16) | imod(m[1], n[1]));
       int4 &r = rows[m[0] - mmin[0]];
       if (!row_seen[m[0] - mmin[0]]) {
         row_seen[m[0] - mmin[0]] = 1;
@@ -339,6 +340,7 @@ extern "C" sgw_status sgw_ham_create(sgw_ctx *ctx, const sgw_ham_desc *d, sgw_ha
   SGW_UP(h->d_u2i, u2i);
   SGW_UP(h->d_stick_off, stick_off);
   SGW_UP(h->d_rows, rows);
+  SGW_UP(h->d_stick_ij, stick_ij);
   SGW_UP(h->d_pw_stick, pw_stick);
   SGW_UP(h->d_pw_z, pw_z);
   SGW_UP(h->d_miller_int, miller_int);

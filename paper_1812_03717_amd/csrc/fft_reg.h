@@ -15,6 +15,7 @@
 #pragma once
 
 #include "fft_lds.h"
+#include "twiddle_const.h"
 
 namespace sgw {
 
@@ -123,6 +124,25 @@ __device__ __forceinline__ C2 twiddle(C2 v, const C2 *tw, int m) {
   C2 w = tw[m];
   if (SIGN > 0) w.y = -w.y;
   return c_mul(v, w);
+}
+
+
+
+// v * exp(SIGN 2 pi i m / N) with m known at compile time after unrolling
+template <int N, int SIGN, class C2>
+__device__ __forceinline__ C2 twiddle_c(C2 v, int m) {
+  using R = typename CT<C2>::R;
+  m %= N;
+  const int q = (4 * m) / N, r = m - q * (N / 4);
+  if (r == 0) {  // a power of i: exact
+    const int e = (SIGN > 0 ? q : 4 - q) % 4;
+    return e == 0 ? v : e == 1 ? CT<C2>::make(-v.y, v.x) : e == 2 ? CT<C2>::make(-v.x, -v.y) : CT<C2>::make(v.y, -v.x);
+  }
+  const double c = ctw::kQuarterCos<N>.v[r], s = ctw::kQuarterCos<N>.v[N / 4 - r];
+  // exp(i 2 pi m / N) = i^q (c + i s)
+  const double wr = q == 0 ? c : q == 1 ? -s : q == 2 ? -c : s;
+  const double wi = q == 0 ? s : q == 1 ? c : q == 2 ? -s : -c;
+  return c_mul(v, CT<C2>::make(R(wr), R(SIGN > 0 ? wi : -wi)));
 }
 
 }  // namespace sgw

@@ -156,9 +156,23 @@ sgw_status launch_planes(sgw_ctx *ctx, const sgw_ham *h, int n_vec, C2 *tbuf) {
   const double per_plane = 2.0 * (h->n_row * 5.0 * N1 * std::log2((double)N1) + N1 * 5.0 * N0 * std::log2((double)N0)) +
                            2.0 * N0 * N1;
   timing_begin(ctx, K_PLANES, bytes, per_plane * h->n[2] * n_vec, &tm);
-  hipLaunchKernelGGL((k_planes<C2, N0, N1>), dim3(blocks), dim3(plane_threads<N0, N1>()), 0, ctx->stream, tbuf,
-                     h->n[2], h->n_stick, h->d_rows, h->m0_lo, h->n_row, potential<C2>(h), twiddles<C2>(h, 0),
-                     twiddles<C2>(h, 1));
+  bool launched = false;
+  if constexpr (line_planes_fit<C2, N0, N1>()) {
+    // whole lines in registers when the stick rows fit the N0 / 2 LDS slots (a sphere-like basis on
+    // a grid that also holds the potential always does)
+    if (2 * h->n_row <= N0) {
+      constexpr int P = line_plane_count<C2, N1>();
+      const long n_planes = (long)n_vec * h->n[2];
+      hipLaunchKernelGGL((k_planes_line<C2, N0, N1, P>), dim3((n_planes + P - 1) / P),
+                         dim3(line_plane_threads<P, N1>()), 0, ctx->stream, tbuf, n_planes, h->n[2], h->n_stick,
+                         h->d_rows, h->d_stick_ij, h->m0_lo, h->n_row, potential<C2>(h));
+      launched = true;
+    }
+  }
+  if (!launched)
+    hipLaunchKernelGGL((k_planes<C2, N0, N1>), dim3(blocks), dim3(plane_threads<N0, N1>()), 0, ctx->stream, tbuf,
+                       h->n[2], h->n_stick, h->d_rows, h->m0_lo, h->n_row, potential<C2>(h), twiddles<C2>(h, 0),
+                       twiddles<C2>(h, 1));
   timing_end(ctx, &tm);
   SGW_HIP(hipGetLastError());
   return SGW_OK;

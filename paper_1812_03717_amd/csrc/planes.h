@@ -221,4 +221,179 @@ __global__ __launch_bounds__((plane_threads<N0, N1>())) void k_planes(C2 *__rest
   }
 }
 
+// Whole-line variant for planes whose rows and columns fit one thread's registers: a thread holds
+// a complete row (axis-1 passes) or column (axis-0 pass) and runs both stages of the split in
+// registers (the exchange between them is register renaming).  The arithmetic is that of
+// k_planes value for value.  Only the stick rows live in LDS: they are at most N0 / 2 cyclically
+// consecutive rows of the plane, so row i0 is kept in slot i0 mod (N0 / 2), which no two of them
+// share, and every column access has a compile-time offset.  The potential is loaded one group of
+// the inverse's second stage ahead and applied as that stage's outputs appear.  Sticks go back to
+// HBM one per thread (coalesced) through a per-stick (i0, i1) table.  P planes per workgroup.
+// c ? a : b on values, component by component (a conditional between two objects would select
+// their addresses and keep both in memory)
+template <class C2> __device__ __forceinline__ C2 csel(bool c, C2 a, C2 b) {
+  return CT<C2>::make(c ? a.x : b.x, c ? a.y : b.y);
+}
+
+template <int N, int SIGN, class C2, class Post>
+__device__ __forceinline__ void reg_dft_line(C2 *x, Post &post) {
+  constexpr int A = Split<N>::a, B = Split<N>::b;
+  C2 y[A][B];
+#pragma unroll
+  for (int b = 0; b < B; ++b) {
+    C2 t[A];
+#pragma unroll
+    for (int a = 0; a < A; ++a) t[a] = x[B * a + b];
+    RegDft<A, SIGN>::run(t);
+#pragma unroll
+    for (int ka = 0; ka < A; ++ka) y[ka][b] = twiddle_c<N, SIGN>(t[ka], b * ka);
+  }
+#pragma unroll
+  for (int ka = 0; ka < A; ++ka) {
+    post.prefetch(ka + 1);
+    RegDft<B, SIGN>::run(y[ka]);
+#pragma unroll
+    for (int kb = 0; kb < B; ++kb) x[ka + A * kb] = post.apply(ka, kb, y[ka][kb]);
+  }
+}
+
+struct NoPost {
+  __device__ __forceinline__ void prefetch(int) {}
+  template <class C2> __device__ __forceinline__ C2 apply(int, int, C2 v) { return v; }
+};
+
+// x[ka + A kb] *= V(r) at that i0, for one column; V of group ka + 1 is loaded while group ka is
+// transformed
+template <class C2, int N0, int N1>
+struct PotentialPost {
+  using R = typename CT<C2>::R;
+  static constexpr int A = Split<N0>::a, B = Split<N0>::b;
+  const R *vz;  // V at (i0 = 0, this column), stride N1 along i0
+  R cur[B], nxt[B];
+  __device__ __forceinline__ explicit PotentialPost(const R *v) : vz(v) {
+#pragma unroll
+    for (int kb = 0; kb < B; ++kb) cur[kb] = vz[(A * kb) * N1];
+  }
+  __device__ __forceinline__ void prefetch(int ka) {
+    if (ka < A) {
+#pragma unroll
+      for (int kb = 0; kb < B; ++kb) nxt[kb] = vz[(ka + A * kb) * N1];
+    }
+  }
+  template <class T> __device__ __forceinline__ T apply(int ka, int kb, T v) {
+    const T r = c_scale(v, cur[kb]);
+    if (kb == B - 1) {
+#pragma unroll
+      for (int k = 0; k < B; ++k) cur[k] = nxt[k];
+    }
+    return r;
+  }
+};
+
+// The line kernel holds max(N0, N1) values per thread: FP64 up to 48 (192 of 256 VGPRs at 48),
+// FP32 likewise.  Planes per workgroup: about 96 (FP64) or 192 (FP32) column threads, which measured
+// best at 48 x 48 (LDS and registers then allow 8 resp. 12 waves per CU).
+template <class C2, int N0, int N1> constexpr bool line_planes_fit() {
+  return N0 % 4 == 0 && N1 % 4 == 0 && N0 <= 48 && N1 <= 48;
+}
+template <class C2, int N1> constexpr int line_plane_count() {
+  return (sizeof(C2) == 16 ? 96 : 192) / N1 > 0 ? (sizeof(C2) == 16 ? 96 : 192) / N1 : 1;
+}
+template <int P, int N1> constexpr int line_plane_threads() { return (P * N1 + 63) / 64 * 64; }
+template <class C2, int N0, int N1> constexpr int line_waves_per_eu() {
+  constexpr int n = N0 > N1 ? N0 : N1;
+  return sizeof(C2) == 16 ? (n <= 16 ? 4 : n <= 24 ? 3 : 2) : (n <= 24 ? 4 : 3);
+}
+
+template <class C2, int N0, int N1, int P>
+__global__ __launch_bounds__((line_plane_threads<P, N1>())) __attribute__((amdgpu_waves_per_eu(line_waves_per_eu<C2, N0, N1>())))
+void k_planes_line(C2 *__restrict__ T, long n_planes, int n2, int n_stick, const int4 *__restrict__ rows,
+                   const int *__restrict__ stick_ij, int m0_lo, int n_row, const typename CT<C2>::R *__restrict__ vt) {
+  using R = typename CT<C2>::R;
+  constexpr int NT = line_plane_threads<P, N1>();
+  constexpr int LD = N1 + 1;
+  constexpr int H0 = N0 / 2;
+  __shared__ C2 buf[P][H0][LD];
+  const long q0 = (long)blockIdx.x * P;
+  const int tid = threadIdx.x;
+  const C2 zero = CT<C2>::make(R(0), R(0));
+  auto row_slot = [&](int t) {
+    const int i0 = m0_lo + t;
+    return (i0 < 0 ? i0 + N0 : i0) % H0;
+  };
+  auto stick_row = [&](int i0) {
+    int t = i0 - m0_lo;
+    t += t < 0 ? N0 : (t >= N0 ? -N0 : 0);
+    return t < n_row;
+  };
+  NoPost none;
+
+  // ---- axis 1, inverse: one stick row per thread ----
+  for (int task = tid; task < P * n_row; task += NT) {
+    const int p = task / n_row, t = task - p * n_row;
+    if (q0 + p >= n_planes) continue;
+    const int4 ri = rows[t];
+    const C2 *run = T + (q0 + p) * n_stick + (ri.x - ri.y);  // run[m1]: the row's stick at m1
+    C2 x[N1];
+#pragma unroll
+    for (int i1 = 0; i1 < N1; ++i1) {
+      // the row's sticks are one run of m1 values; outside it the row is zero
+      const int m1 = i1 <= (N1 - 1) / 2 ? i1 : i1 - N1;
+      x[i1] = zero;
+      if (m1 >= ri.y && m1 <= ri.z) x[i1] = run[m1];
+    }
+    reg_dft_line<N1, +1>(x, none);
+    C2 *row = buf[p][row_slot(t)];
+#pragma unroll
+    for (int i1 = 0; i1 < N1; ++i1) row[i1] = x[i1];
+  }
+  __syncthreads();
+  // ---- axis 0: inverse, times V(r), forward; one column per thread ----
+  for (int task = tid; task < P * N1; task += NT) {
+    const int p = task / N1, i1 = task - p * N1;
+    const long q = q0 + p;
+    if (q >= n_planes) continue;
+    const int z = (int)(q % n2);
+    C2 x[N0];
+#pragma unroll
+    for (int j = 0; j < H0; ++j) {
+      // slot j holds row j or row j + N0/2, whichever is a stick row (at most one is)
+      const C2 v = buf[p][j][i1];
+      x[j] = csel(stick_row(j), v, zero);
+      x[j + H0] = csel(stick_row(j + H0), v, zero);
+    }
+    PotentialPost<C2, N0, N1> vpost(vt + (long)z * N0 * N1 + i1);
+    reg_dft_line<N0, +1>(x, vpost);
+    reg_dft_line<N0, -1>(x, none);
+#pragma unroll
+    for (int j = 0; j < H0; ++j) buf[p][j][i1] = csel(stick_row(j), x[j], x[j + H0]);
+  }
+  __syncthreads();
+
+  // ---- axis 1, forward: one stick row per thread, back into its slot ----
+  for (int task = tid; task < P * n_row; task += NT) {
+    const int p = task / n_row, t = task - p * n_row;
+    if (q0 + p >= n_planes) continue;
+    C2 *row = buf[p][row_slot(t)];
+    C2 x[N1];
+#pragma unroll
+    for (int i1 = 0; i1 < N1; ++i1) x[i1] = row[i1];
+    reg_dft_line<N1, -1>(x, none);
+#pragma unroll
+    for (int i1 = 0; i1 < N1; ++i1) row[i1] = x[i1];
+  }
+  __syncthreads();
+
+  // ---- gather the sticks, one per thread ----
+#pragma unroll
+  for (int p = 0; p < P; ++p) {
+    if (q0 + p >= n_planes) break;
+    C2 *Tz = T + (q0 + p) * n_stick;
+    for (int s = tid; s < n_stick; s += NT) {
+      const int ij = stick_ij[s];
+      Tz[s] = buf[p][(ij >> 16) % H0][ij & 0xffff];
+    }
+  }
+}
+
 }  // namespace sgw

@@ -95,6 +95,7 @@ struct sgw_ham {
   int32_t *d_u2i = nullptr;         // [n_pw] caller -> internal index
   int32_t *d_stick_off = nullptr;   // [n_stick + 1]
   int4 *d_rows = nullptr;           // [n_row] {first stick, m1_lo, m1_hi, 0} of row m0 = m0_lo + t
+  int32_t *d_stick_ij = nullptr;    // [n_stick] (i0 << 16) | i1: the stick's grid column
   int32_t *d_pw_stick = nullptr;    // [n_pw] internal -> stick
   int32_t *d_pw_z = nullptr;        // [n_pw] internal -> i2
   int32_t *d_miller_int = nullptr;  // [n_pw][3] internal order

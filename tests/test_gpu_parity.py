@@ -40,6 +40,8 @@ PROBLEMS = {
     "fcc112_q": lambda: synth.small((1, 1, 2), n_omega=5, n_pert=3, seed=9200, ecut=6.0),
     # a 72^3 grid: planes above 48 x 48 (one axis-0 column task per thread)
     "fcc1_g72": lambda: synth.small((1, 1, 1), grid=(72, 72, 72), n_omega=4, n_pert=2, seed=9300),
+    # 48 x 48 planes (whole-line plane kernel), 24-point sticks
+    "fcc221_g48": lambda: synth.small((2, 2, 1), n_omega=4, n_pert=2, seed=9400, ecut=6.0),
 }
 
 
