@@ -328,6 +328,8 @@ extern "C" sgw_status sgw_ham_create(sgw_ctx *ctx, const sgw_ham_desc *d, sgw_ha
   h->n_stick = ns;
   h->m0_lo = mmin[0];
   h->n_row = mmax[0] - mmin[0] + 1;
+  h->m1_lo = mmin[1];
+  h->m1_hi = mmax[1];
   h->miller.assign(d->miller, d->miller + 3 * npw);
   sgw_status st = SGW_OK;
 #define SGW_UP(dst, src)                                   \

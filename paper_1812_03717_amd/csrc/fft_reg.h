@@ -145,4 +145,48 @@ __device__ __forceinline__ C2 twiddle_c(C2 v, int m) {
   return c_mul(v, CT<C2>::make(R(wr), R(SIGN > 0 ? wi : -wi)));
 }
 
+
+// DFT of length A (4 or 8) whose inputs vanish for a in [A/4, 3A/4): only v[0..A/4) and
+// v[3A/4..A) are read.  Same operations as RegDft<A> on those inputs, without the zero terms
+// (lines whose support is the central half of a grid: |m| < N/4, as a sphere that the grid can hold
+// twice over has).
+template <int A, int SIGN> struct HalfDft;
+template <int SIGN> struct HalfDft<4, SIGN> {
+  template <class C2> __device__ __forceinline__ static void run(C2 *v) {
+    // inputs v0, v3:  X = (v0 + v3, v0 - s i v3, v0 - v3, v0 + s i v3), s = SIGN
+    const C2 a = v[0], d = c_mul_si<SIGN>(v[3]);
+    const C2 b = v[3];
+    v[0] = c_add(a, b);
+    v[1] = c_sub(a, d);
+    v[2] = c_sub(a, b);
+    v[3] = c_add(a, d);
+  }
+};
+template <int SIGN> struct HalfDft<8, SIGN> {
+  template <class C2> __device__ __forceinline__ static void run(C2 *v) {
+    using R = typename CT<C2>::R;
+    constexpr R c = R(0.70710678118654752440);  // cos(pi/4)
+    constexpr R sg = R(SIGN);
+    C2 e[4], o[4];
+    e[0] = v[0];
+    e[3] = v[6];
+    o[0] = v[1];
+    o[3] = v[7];
+    HalfDft<4, SIGN>::run(e);
+    HalfDft<4, SIGN>::run(o);
+    // w^k o[k], w = exp(SIGN i pi / 4), as in Dft<8>
+    const C2 o1 = CT<C2>::make(c * (o[1].x - sg * o[1].y), c * (o[1].y + sg * o[1].x));
+    const C2 o2 = c_mul_si<SIGN>(o[2]);
+    const C2 o3 = CT<C2>::make(c * (-o[3].x - sg * o[3].y), c * (-o[3].y + sg * o[3].x));
+    v[0] = c_add(e[0], o[0]);
+    v[4] = c_sub(e[0], o[0]);
+    v[1] = c_add(e[1], o1);
+    v[5] = c_sub(e[1], o1);
+    v[2] = c_add(e[2], o2);
+    v[6] = c_sub(e[2], o2);
+    v[3] = c_add(e[3], o3);
+    v[7] = c_sub(e[3], o3);
+  }
+};
+
 }  // namespace sgw

@@ -158,9 +158,9 @@ sgw_status launch_planes(sgw_ctx *ctx, const sgw_ham *h, int n_vec, C2 *tbuf) {
   timing_begin(ctx, K_PLANES, bytes, per_plane * h->n[2] * n_vec, &tm);
   bool launched = false;
   if constexpr (line_planes_fit<C2, N0, N1>()) {
-    // whole lines in registers when the stick rows fit the N0 / 2 LDS slots (a sphere-like basis on
-    // a grid that also holds the potential always does)
-    if (2 * h->n_row <= N0) {
+    // whole lines in registers when every stick lies in the central half of the plane (a sphere
+    // that the grid holds twice over does)
+    if (line_window_ok(h->n, h->m0_lo, h->n_row, h->m1_lo, h->m1_hi)) {
       constexpr int P = line_plane_count<C2, N1>();
       const long n_planes = (long)n_vec * h->n[2];
       hipLaunchKernelGGL((k_planes_line<C2, N0, N1, P>), dim3((n_planes + P - 1) / P),

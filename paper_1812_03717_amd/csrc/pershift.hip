@@ -327,7 +327,7 @@ __global__ __launch_bounds__(kPsThreads) void k_ps_k3(PsState S, const int32_t *
 // true FP64 residual with Y = (H + alpha P_occ) x, dpsi and info
 __global__ __launch_bounds__(kPsThreads) void k_ps_final(PsState S, const int32_t *__restrict__ list,
                                                         const double2 *__restrict__ Y,
-                                                        const double2 *__restrict__ cp, int n_chunks, long rows,
+                                                        const double2 *__restrict__ cp,
                                                         double2 *__restrict__ dpsi,
                                                         sgw_solve_info *__restrict__ info, int *__restrict__ n_bad,
                                                         int extra_flags) {
@@ -347,8 +347,7 @@ __global__ __launch_bounds__(kPsThreads) void k_ps_final(PsState S, const int32_
   }
   double cc = 0.0;
   for (int o = threadIdx.x; o < S.n_occ; o += kPsThreads) {
-    double2 c = make_double2(0.0, 0.0);
-    for (int ch = 0; ch < n_chunks; ++ch) c = c_add(c, cp[((long)ch * rows + a) * S.n_occ + o]);
+    const double2 c = cp[(long)a * S.n_occ + o];
     cc += c.x * c.x + c.y * c.y;
   }
   acc[2] = cc;
@@ -419,9 +418,7 @@ sgw_status ps_k3(sgw_ctx *ctx, const PsState &S, int n, const int32_t *list, con
 sgw_status ps_final(sgw_ctx *ctx, const PsState &S, int n, const int32_t *list, const double2 *Y,
                     const double2 *cp, long rows, double2 *dpsi, sgw_solve_info *info, int *n_bad,
                     int extra_flags) {
-  int kc;
-  const int nch = proj_chunks(S.npw, &kc);
-  SGW_PS_LAUNCH(k_ps_final, n, S, list, Y, cp, nch, rows, dpsi, info, n_bad, extra_flags);
+  SGW_PS_LAUNCH(k_ps_final, n, S, list, Y, cp, dpsi, info, n_bad, extra_flags);
 }
 
 }  // namespace sgw

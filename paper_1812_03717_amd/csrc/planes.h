@@ -223,28 +223,35 @@ __global__ __launch_bounds__((plane_threads<N0, N1>())) void k_planes(C2 *__rest
 
 // Whole-line variant for planes whose rows and columns fit one thread's registers: a thread holds
 // a complete row (axis-1 passes) or column (axis-0 pass) and runs both stages of the split in
-// registers (the exchange between them is register renaming).  The arithmetic is that of
-// k_planes value for value.  Only the stick rows live in LDS: they are at most N0 / 2 cyclically
-// consecutive rows of the plane, so row i0 is kept in slot i0 mod (N0 / 2), which no two of them
-// share, and every column access has a compile-time offset.  The potential is loaded one group of
-// the inverse's second stage ahead and applied as that stage's outputs appear.  Sticks go back to
-// HBM one per thread (coalesced) through a per-stick (i0, i1) table.  P planes per workgroup.
-// c ? a : b on values, component by component (a conditional between two objects would select
-// their addresses and keep both in memory)
-template <class C2> __device__ __forceinline__ C2 csel(bool c, C2 a, C2 b) {
-  return CT<C2>::make(c ? a.x : b.x, c ? a.y : b.y);
-}
-
-template <int N, int SIGN, class C2, class Post>
+// registers (the exchange between them is register renaming).  Its arithmetic is that of k_planes
+// value for value, without the terms that are zero by construction.
+//
+// Window: the kernel requires every stick to satisfy -N0/4 <= m0 < N0/4 and -N1/4 <= m1 < N1/4
+// (a sphere that the grid holds twice over, as it must for the density, does).  Then along either
+// axis a line's inverse input and its needed forward output live on the window i < N/4 or
+// i >= 3N/4: the inverse's first stage is a HalfDft and the forward computes only window outputs.
+// Window row i0 is kept in LDS slot i0 (i0 < N0/4) or i0 - N0/2 (i0 >= 3N0/4), every column access
+// has a compile-time offset, and window rows without sticks are zero-filled once.  Only the window
+// rows pass through LDS, once after the axis-1 inverse and once before the axis-1 forward; sticks go
+// back to HBM one per thread (coalesced) through a per-stick (i0, i1) table.  The potential is
+// loaded one group of the inverse's second stage ahead.  P planes per workgroup.
+template <int N, int SIGN, bool IN_HALF, class C2, class Post>
 __device__ __forceinline__ void reg_dft_line(C2 *x, Post &post) {
   constexpr int A = Split<N>::a, B = Split<N>::b;
   C2 y[A][B];
 #pragma unroll
   for (int b = 0; b < B; ++b) {
     C2 t[A];
+    if constexpr (IN_HALF) {
 #pragma unroll
-    for (int a = 0; a < A; ++a) t[a] = x[B * a + b];
-    RegDft<A, SIGN>::run(t);
+      for (int a = 0; a < A; ++a)
+        if (4 * a < A || 4 * a >= 3 * A) t[a] = x[B * a + b];
+      HalfDft<A, SIGN>::run(t);
+    } else {
+#pragma unroll
+      for (int a = 0; a < A; ++a) t[a] = x[B * a + b];
+      RegDft<A, SIGN>::run(t);
+    }
 #pragma unroll
     for (int ka = 0; ka < A; ++ka) y[ka][b] = twiddle_c<N, SIGN>(t[ka], b * ka);
   }
@@ -290,11 +297,12 @@ struct PotentialPost {
   }
 };
 
-// The line kernel holds max(N0, N1) values per thread: FP64 up to 48 (192 of 256 VGPRs at 48),
-// FP32 likewise.  Planes per workgroup: about 96 (FP64) or 192 (FP32) column threads, which measured
-// best at 48 x 48 (LDS and registers then allow 8 resp. 12 waves per CU).
+// The line kernel holds max(N0, N1) values per thread: up to 48 (FP64: 192 of 256 VGPRs at 48).
+// Planes per workgroup: about 96 (FP64) or 192 (FP32) column threads, which measured best at
+// 48 x 48 (LDS and registers then allow 8 resp. 12 waves per CU).
 template <class C2, int N0, int N1> constexpr bool line_planes_fit() {
-  return N0 % 4 == 0 && N1 % 4 == 0 && N0 <= 48 && N1 <= 48;
+  return N0 % 4 == 0 && N1 % 4 == 0 && N0 <= 48 && N1 <= 48 && Split<N0>::a % 4 == 0 &&
+         Split<N1>::a % 4 == 0;
 }
 template <class C2, int N1> constexpr int line_plane_count() {
   return (sizeof(C2) == 16 ? 96 : 192) / N1 > 0 ? (sizeof(C2) == 16 ? 96 : 192) / N1 : 1;
@@ -304,6 +312,10 @@ template <class C2, int N0, int N1> constexpr int line_waves_per_eu() {
   constexpr int n = N0 > N1 ? N0 : N1;
   return sizeof(C2) == 16 ? (n <= 16 ? 4 : n <= 24 ? 3 : 2) : (n <= 24 ? 4 : 3);
 }
+// true when every stick lies in the window the line kernel requires
+inline bool line_window_ok(const int n[3], int m0_lo, int n_row, int m1_lo, int m1_hi) {
+  return m0_lo >= -n[0] / 4 && m0_lo + n_row - 1 < n[0] / 4 && m1_lo >= -n[1] / 4 && m1_hi < n[1] / 4;
+}
 
 template <class C2, int N0, int N1, int P>
 __global__ __launch_bounds__((line_plane_threads<P, N1>())) __attribute__((amdgpu_waves_per_eu(line_waves_per_eu<C2, N0, N1>())))
@@ -312,23 +324,26 @@ void k_planes_line(C2 *__restrict__ T, long n_planes, int n2, int n_stick, const
   using R = typename CT<C2>::R;
   constexpr int NT = line_plane_threads<P, N1>();
   constexpr int LD = N1 + 1;
-  constexpr int H0 = N0 / 2;
+  constexpr int H0 = N0 / 2, Q0 = N0 / 4, Q1 = N1 / 4;
   __shared__ C2 buf[P][H0][LD];
   const long q0 = (long)blockIdx.x * P;
   const int tid = threadIdx.x;
   const C2 zero = CT<C2>::make(R(0), R(0));
-  auto row_slot = [&](int t) {
-    const int i0 = m0_lo + t;
-    return (i0 < 0 ? i0 + N0 : i0) % H0;
-  };
-  auto stick_row = [&](int i0) {
-    int t = i0 - m0_lo;
-    t += t < 0 ? N0 : (t >= N0 ? -N0 : 0);
-    return t < n_row;
-  };
-  NoPost none;
+  // window row m0 (-N0/4 <= m0 < N0/4) -> LDS slot
+  auto slot_of = [](int m0) { return m0 >= 0 ? m0 : m0 + H0; };
+  auto in_window1 = [](int i1) { return i1 < Q1 || i1 >= 3 * Q1; };
+
+  // window rows without sticks read as zero in the axis-0 pass
+  const int n_below = m0_lo + Q0, n_empty = H0 - n_row;
+  for (int e = tid; e < P * n_empty * LD; e += NT) {
+    const int p = e / (n_empty * LD), r = e - p * (n_empty * LD);
+    const int k = r / LD, c = r - k * LD;
+    const int m0 = k < n_below ? -Q0 + k : m0_lo + n_row + (k - n_below);
+    buf[p][slot_of(m0)][c] = zero;
+  }
 
   // ---- axis 1, inverse: one stick row per thread ----
+  NoPost none;
   for (int task = tid; task < P * n_row; task += NT) {
     const int p = task / n_row, t = task - p * n_row;
     if (q0 + p >= n_planes) continue;
@@ -337,17 +352,19 @@ void k_planes_line(C2 *__restrict__ T, long n_planes, int n2, int n_stick, const
     C2 x[N1];
 #pragma unroll
     for (int i1 = 0; i1 < N1; ++i1) {
+      if (!in_window1(i1)) continue;
       // the row's sticks are one run of m1 values; outside it the row is zero
-      const int m1 = i1 <= (N1 - 1) / 2 ? i1 : i1 - N1;
+      const int m1 = i1 < Q1 ? i1 : i1 - N1;
       x[i1] = zero;
       if (m1 >= ri.y && m1 <= ri.z) x[i1] = run[m1];
     }
-    reg_dft_line<N1, +1>(x, none);
-    C2 *row = buf[p][row_slot(t)];
+    reg_dft_line<N1, +1, true>(x, none);
+    C2 *row = buf[p][slot_of(m0_lo + t)];
 #pragma unroll
     for (int i1 = 0; i1 < N1; ++i1) row[i1] = x[i1];
   }
   __syncthreads();
+
   // ---- axis 0: inverse, times V(r), forward; one column per thread ----
   for (int task = tid; task < P * N1; task += NT) {
     const int p = task / N1, i1 = task - p * N1;
@@ -356,31 +373,33 @@ void k_planes_line(C2 *__restrict__ T, long n_planes, int n2, int n_stick, const
     const int z = (int)(q % n2);
     C2 x[N0];
 #pragma unroll
-    for (int j = 0; j < H0; ++j) {
-      // slot j holds row j or row j + N0/2, whichever is a stick row (at most one is)
-      const C2 v = buf[p][j][i1];
-      x[j] = csel(stick_row(j), v, zero);
-      x[j + H0] = csel(stick_row(j + H0), v, zero);
+    for (int j = 0; j < Q0; ++j) {
+      x[j] = buf[p][j][i1];                   // rows i0 = j
+      x[N0 - Q0 + j] = buf[p][Q0 + j][i1];    // rows i0 = 3 N0 / 4 + j
     }
     PotentialPost<C2, N0, N1> vpost(vt + (long)z * N0 * N1 + i1);
-    reg_dft_line<N0, +1>(x, vpost);
-    reg_dft_line<N0, -1>(x, none);
+    reg_dft_line<N0, +1, true>(x, vpost);
+    reg_dft_line<N0, -1, false>(x, none);
 #pragma unroll
-    for (int j = 0; j < H0; ++j) buf[p][j][i1] = csel(stick_row(j), x[j], x[j + H0]);
+    for (int j = 0; j < Q0; ++j) {
+      buf[p][j][i1] = x[j];
+      buf[p][Q0 + j][i1] = x[N0 - Q0 + j];
+    }
   }
   __syncthreads();
 
-  // ---- axis 1, forward: one stick row per thread, back into its slot ----
+  // ---- axis 1, forward: one stick row per thread, window columns back into its slot ----
   for (int task = tid; task < P * n_row; task += NT) {
     const int p = task / n_row, t = task - p * n_row;
     if (q0 + p >= n_planes) continue;
-    C2 *row = buf[p][row_slot(t)];
+    C2 *row = buf[p][slot_of(m0_lo + t)];
     C2 x[N1];
 #pragma unroll
     for (int i1 = 0; i1 < N1; ++i1) x[i1] = row[i1];
-    reg_dft_line<N1, -1>(x, none);
+    reg_dft_line<N1, -1, false>(x, none);
 #pragma unroll
-    for (int i1 = 0; i1 < N1; ++i1) row[i1] = x[i1];
+    for (int i1 = 0; i1 < N1; ++i1)
+      if (in_window1(i1)) row[i1] = x[i1];
   }
   __syncthreads();
 
@@ -391,7 +410,8 @@ void k_planes_line(C2 *__restrict__ T, long n_planes, int n2, int n_stick, const
     C2 *Tz = T + (q0 + p) * n_stick;
     for (int s = tid; s < n_stick; s += NT) {
       const int ij = stick_ij[s];
-      Tz[s] = buf[p][(ij >> 16) % H0][ij & 0xffff];
+      const int i0 = ij >> 16;
+      Tz[s] = buf[p][i0 < Q0 ? i0 : i0 - H0][ij & 0xffff];
     }
   }
 }

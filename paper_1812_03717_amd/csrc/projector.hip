@@ -10,8 +10,8 @@
 // the apply kernel rows are plane waves and columns are vectors.  The overlap
 // reduction over plane waves is split into chunks (one workgroup per chunk and
 // vector tile, its four waves splitting the chunk again and reducing through
-// LDS); consumers add the chunk partials in a fixed order, so the result is
-// deterministic.
+// LDS); a second pass adds the chunk partials in a fixed order into chunk 0,
+// so the result is deterministic and consumers read one complete overlap.
 //
 // MFMA operand layout (v_mfma_f64_16x16x4f64, wave64): lane l supplies
 // A[l % 16][l / 16] and B[l / 16][l % 16]; it receives D[l / 16 + 4 r][l % 16]
@@ -120,6 +120,22 @@ __global__ __launch_bounds__(64 * kDotWaves) void k_proj_dot(int npw, int n_occ,
   }
 }
 
+// cp[0][a][i] = sum over chunks c of cp[c][a][i], in chunk order
+__global__ __launch_bounds__(256) void k_proj_reduce(double2 *__restrict__ cp, long rows, int n_vec, int n_occ,
+                                                   int n_chunks) {
+  const long e = (long)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (long)n_vec * n_occ) return;
+  const int a = (int)(e / n_occ), i = (int)(e - (long)a * n_occ);
+  double2 part[kProjChunks];
+#pragma unroll
+  for (int c = 0; c < kProjChunks; ++c)
+    part[c] = c < n_chunks ? cp[((long)c * rows + a) * n_occ + i] : make_double2(0.0, 0.0);
+  double2 s = make_double2(0.0, 0.0);
+#pragma unroll
+  for (int c = 0; c < kProjChunks; ++c) s = c_add(s, part[c]);
+  cp[(long)a * n_occ + i] = s;
+}
+
 constexpr int kApplyWaves = 4;
 constexpr int kApplyG = 256;   // plane waves per block (each wave: kApplyG / kApplyWaves / 16 tiles)
 constexpr int kApplyBatch = 8; // occupied K-steps whose operands are loaded before their MFMAs
@@ -127,23 +143,15 @@ constexpr int kApplyBatch = 8; // occupied K-steps whose operands are loaded bef
 // grid: vtiles x gtiles, block: kApplyWaves wavefronts; dynamic LDS: 16 * n_occ complex
 __global__ __launch_bounds__(64 * kApplyWaves) void k_proj_apply(int npw, int n_occ, const double2 *__restrict__ psi,
                                                                 VecSrc x, int n_vec, const double2 *__restrict__ cp,
-                                                                int n_chunks, long rows, double2 *__restrict__ y,
-                                                                long ldy, double alpha, int mode, int vtiles) {
-  extern __shared__ double2 cs[];  // [16][n_occ]: C of the tile's vectors, chunk partials summed
+                                                                double2 *__restrict__ y, long ldy, double alpha,
+                                                                int mode, int vtiles) {
+  extern __shared__ double2 cs[];  // [16][n_occ]: C of the tile's vectors
   const int vt = blockIdx.x % vtiles;
   const int gt = blockIdx.x / vtiles;
   const int a0 = vt * 16;
   for (int e = threadIdx.x; e < 16 * n_occ; e += 64 * kApplyWaves) {
-    const int v = e / n_occ, i = e - v * n_occ;
-    double2 part[kProjChunks];
-    const bool ok = a0 + v < n_vec;
-#pragma unroll
-    for (int c = 0; c < kProjChunks; ++c)
-      part[c] = (ok && c < n_chunks) ? cp[((long)c * rows + a0 + v) * n_occ + i] : make_double2(0.0, 0.0);
-    double2 s = make_double2(0.0, 0.0);
-#pragma unroll
-    for (int c = 0; c < kProjChunks; ++c) s = c_add(s, part[c]);
-    cs[e] = s;
+    const int v = e / n_occ;
+    cs[e] = a0 + v < n_vec ? cp[(long)a0 * n_occ + e] : make_double2(0.0, 0.0);
   }
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -152,9 +160,18 @@ __global__ __launch_bounds__(64 * kApplyWaves) void k_proj_apply(int npw, int n_
   const bool va = a < n_vec;
   const double2 *xa = (va && mode == 0) ? x.ptr(a) : nullptr;
   double2 *ya = y + (long)(va ? a : 0) * ldy;
+  const double2 *src = mode == 0 ? xa : ya;  // the values this lane updates
   for (int sub = wave; sub < kApplyG / 16; sub += kApplyWaves) {
     const int gb = gt * kApplyG + sub * 16;
     if (gb >= npw) break;
+    // loaded before the products, so that their latency overlaps the MFMAs
+    double2 old[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int g = gb + kq + 4 * r;
+      old[r] = make_double2(0.0, 0.0);
+      if (va && g < npw) old[r] = src[g];
+    }
     d4 re = {0.0, 0.0, 0.0, 0.0}, im = {0.0, 0.0, 0.0, 0.0};
     const int ga = gb + col;  // A operand row (plane wave) of this lane
     const bool gin = ga < npw;
@@ -178,15 +195,9 @@ __global__ __launch_bounds__(64 * kApplyWaves) void k_proj_apply(int npw, int n_
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int g = gb + kq + 4 * r;
-      if (g < npw) {
-        if (mode == 0) {
-          const double2 xg = xa[g];
-          ya[g] = make_double2(xg.x - re[r], xg.y - im[r]);
-        } else {
-          const double2 yg = ya[g];
-          ya[g] = make_double2(fma(alpha, re[r], yg.x), fma(alpha, im[r], yg.y));
-        }
-      }
+      if (g < npw)
+        ya[g] = mode == 0 ? make_double2(old[r].x - re[r], old[r].y - im[r])
+                          : make_double2(fma(alpha, re[r], old[r].x), fma(alpha, im[r], old[r].y));
     }
   }
 }
@@ -225,6 +236,10 @@ sgw_status proj_dot(sgw_ctx *ctx, int npw, int n_occ, const double2 *psi, int n_
     default: SGW_DOT(8); break;
   }
 #undef SGW_DOT
+  if (nch > 1) {
+    const long ne = (long)n_vec * n_occ;
+    hipLaunchKernelGGL(k_proj_reduce, dim3((ne + 255) / 256), dim3(256), 0, ctx->stream, cp, rows, n_vec, n_occ, nch);
+  }
   timing_end(ctx, &tm);
   SGW_HIP(hipGetLastError());
   return SGW_OK;
@@ -238,14 +253,12 @@ sgw_status proj_apply(sgw_ctx *ctx, int npw, int n_occ, const double2 *psi, int 
     // y = x: nothing to subtract
     return permute_copy(ctx, npw, n_vec, x, y, ldy);
   }
-  int kc;
-  const int nch = proj_chunks(npw, &kc);
   const int vtiles = (n_vec + 15) / 16;
   const int gtiles = (npw + kApplyG - 1) / kApplyG;
   PendingTiming tm;
   timing_begin(ctx, K_PROJ_APPLY, n_vec * (npw * 32.0) + (double)n_occ * npw * 16.0, 8.0 * n_vec * npw * n_occ, &tm);
   hipLaunchKernelGGL(k_proj_apply, dim3((long)vtiles * gtiles), dim3(64 * kApplyWaves), sizeof(double2) * 16 * n_occ,
-                     ctx->stream, npw, n_occ, psi, x, n_vec, cp, nch, rows, y, ldy, alpha, mode, vtiles);
+                     ctx->stream, npw, n_occ, psi, x, n_vec, cp, y, ldy, alpha, mode, vtiles);
   timing_end(ctx, &tm);
   SGW_HIP(hipGetLastError());
   return SGW_OK;

@@ -86,6 +86,7 @@ struct sgw_ham {
   int n_pw = 0;
   int n_stick = 0;
   int m0_lo = 0, n_row = 0;         // rows (axis 0) holding sticks: m0 in [m0_lo, m0_lo + n_row)
+  int m1_lo = 0, m1_hi = -1;        // m1 range of all sticks
   double kvec[3];
   double recip[3][3];
   std::vector<int32_t> miller;      // host copy, caller order
@@ -154,10 +155,11 @@ constexpr int kProjChunks = 16;
 constexpr int kMaxWorkers = 16;
 // number of chunks for n_pw plane waves; *kc receives the chunk length
 int proj_chunks(int n_pw, int *kc);
-// cp[chunk][a][i] = sum_{g in chunk} conj(psi[i][g]) x_a[g]
+// cp[chunk][a][i] = sum_{g in chunk} conj(psi[i][g]) x_a[g], then cp[0][a][i] = the sum over all
+// chunks (in chunk order): on return chunk 0 holds the complete overlaps
 sgw_status proj_dot(sgw_ctx *ctx, int n_pw, int n_occ, const double2 *psi, int n_vec, VecSrc x,
                     double2 *cp, long rows);
-// with c = sum over chunks of cp:  mode 0: y_a = x_a - psi^T c_a ; mode 1: y_a += alpha psi^T c_a
+// with c = cp[0]:  mode 0: y_a = x_a - psi^T c_a ; mode 1: y_a += alpha psi^T c_a
 // (mode 0 may run in place, y_a == x_a)
 sgw_status proj_apply(sgw_ctx *ctx, int n_pw, int n_occ, const double2 *psi, int n_vec, VecSrc x,
                       const double2 *cp, long rows, double2 *y, long ldy, double alpha, int mode);

@@ -380,8 +380,8 @@ __global__ __launch_bounds__(kCmbThreads) void k_combine(SolverState S, const in
 __global__ __launch_bounds__(kRowThreads) void k_residual(SolverState S, const int32_t *__restrict__ flist,
                                                           const double2 *__restrict__ X,
                                                           const double2 *__restrict__ AX,
-                                                          const double2 *__restrict__ cp, int n_chunks,
-                                                          long rows, const int32_t *__restrict__ i2u,
+                                                          const double2 *__restrict__ cp,
+                                                          const int32_t *__restrict__ i2u,
                                                           double2 *__restrict__ dpsi,
                                                           sgw_solve_info *__restrict__ info, double tol,
                                                           int *__restrict__ n_bad) {
@@ -411,11 +411,10 @@ __global__ __launch_bounds__(kRowThreads) void k_residual(SolverState S, const i
     acc[1] = fma(xg.x, xg.x, fma(xg.y, xg.y, acc[1]));
     out[i2u[g]] = xg;
   }
-  // ||psi^* x||^2 from the chunk partials of the overlaps
+  // ||psi^* x||^2 from the overlaps
   double cc = 0.0;
   for (int i = threadIdx.x; i < S.n_occ; i += kRowThreads) {
-    double2 c = make_double2(0.0, 0.0);
-    for (int ch = 0; ch < n_chunks; ++ch) c = c_add(c, cp[((long)ch * rows + fj) * S.n_occ + i]);
+    const double2 c = cp[(long)fj * S.n_occ + i];
     cc += c.x * c.x + c.y * c.y;
   }
   acc[2] = cc;
@@ -568,12 +567,10 @@ sgw_status residual(sgw_ctx *ctx, const SolverState &S, const int32_t *flist, in
                     const double2 *AX, const double2 *cp, long rows, const int32_t *i2u, double2 *dpsi,
                     sgw_solve_info *info, double tol, int *n_bad) {
   if (nf <= 0) return SGW_OK;
-  int kc;
-  const int nch = proj_chunks(S.npw, &kc);
   PendingTiming tm;
   timing_begin(ctx, K_RESIDUAL, (double)nf * S.n_omega * S.npw * 16.0 * 4, 0.0, &tm);
   hipLaunchKernelGGL(k_residual, dim3((long)nf * S.n_omega), dim3(kRowThreads), 0, ctx->stream, S, flist, X, AX, cp,
-                     nch, rows, i2u, dpsi, info, tol, n_bad);
+                     i2u, dpsi, info, tol, n_bad);
   timing_end(ctx, &tm);
   SGW_HIP(hipGetLastError());
   return SGW_OK;
