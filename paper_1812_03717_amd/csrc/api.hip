@@ -330,6 +330,8 @@ extern "C" sgw_status sgw_ham_create(sgw_ctx *ctx, const sgw_ham_desc *d, sgw_ha
   h->n_row = mmax[0] - mmin[0] + 1;
   h->m1_lo = mmin[1];
   h->m1_hi = mmax[1];
+  h->m2_lo = mmin[2];
+  h->m2_hi = mmax[2];
   h->miller.assign(d->miller, d->miller + 3 * npw);
   sgw_status st = SGW_OK;
 #define SGW_UP(dst, src)                                   \

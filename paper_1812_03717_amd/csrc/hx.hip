@@ -111,6 +111,121 @@ __global__ __launch_bounds__(kStickThreads) void k_sticks_fwd(const C2 *__restri
   }
 }
 
+// Whole-line stick kernels: a workgroup takes 64 consecutive sticks of one vector, one thread per
+// stick transforms it in registers (planes.h: reg_dft_line).  They require the window
+// -N2/4 <= m2 < N2/4 of the plane kernel's, so the inverse's first stage reads only the window
+// and the forward computes only window outputs.  The window values pass through LDS
+// ([window row][stick]; window row w holds m2 = w for w < N2/4, m2 = w - N2/2 otherwise) between
+// the coalesced plane-wave accesses and the per-stick transforms; the T accesses of consecutive
+// threads are consecutive.
+constexpr int kStickLineSticks = 64;
+template <class C2, int N2>
+__global__ __launch_bounds__(kStickLineSticks) __attribute__((amdgpu_waves_per_eu(line_waves_per_eu<C2, N2, N2>())))
+void k_sticks_inv_line(VecSrc x, C2 *__restrict__ T, int n_stick, int groups, const int32_t *__restrict__ stick_off,
+                       const int32_t *__restrict__ pw_stick, const int32_t *__restrict__ pw_z) {
+  using R = typename CT<C2>::R;
+  constexpr int Q = N2 / 4;
+  constexpr int SG = kStickLineSticks;
+  __shared__ C2 win[2 * Q][SG];
+  const int vec = blockIdx.x / groups;
+  const int s0 = (blockIdx.x - vec * groups) * SG;
+  const int ns = min(SG, n_stick - s0);
+  const int tid = threadIdx.x;
+  const C2 zero = CT<C2>::make(R(0), R(0));
+#pragma unroll
+  for (int w = 0; w < 2 * Q; ++w) win[w][tid] = zero;
+  __syncthreads();
+  const double2 *xv = x.ptr(vec);
+  const int g0 = stick_off[s0], g1 = stick_off[s0 + ns];
+  for (int g = g0 + tid; g < g1; g += SG) {
+    const int z = pw_z[g];
+    win[z < Q ? z : z - 2 * Q][pw_stick[g] - s0] = to_c<C2>(xv[g]);
+  }
+  __syncthreads();
+  if (tid >= ns) return;
+  C2 v[N2];
+#pragma unroll
+  for (int w = 0; w < Q; ++w) {
+    v[w] = win[w][tid];
+    v[N2 - Q + w] = win[Q + w][tid];
+  }
+  NoPost none;
+  reg_dft_line<N2, +1, true>(v, none);
+  C2 *Tv = T + (long)vec * N2 * n_stick + s0 + tid;
+#pragma unroll
+  for (int z = 0; z < N2; ++z) Tv[(long)z * n_stick] = v[z];
+}
+
+// inverse with direct loads: one thread per (vector, stick) reads its run of plane waves itself
+// (one base pointer, compile-time offsets), 256 threads per workgroup and no LDS; measured faster
+// than the LDS-staged kernel in FP64 (more waves resident), slower in FP32
+template <class C2, int N2>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(line_waves_per_eu<C2, N2, N2>())))
+void k_sticks_inv_direct(VecSrc x, C2 *__restrict__ T, int n_stick, long n_items,
+                         const int32_t *__restrict__ stick_off, const int32_t *__restrict__ pw_z) {
+  using R = typename CT<C2>::R;
+  constexpr int Q = N2 / 4;
+  const long item = (long)blockIdx.x * 256 + threadIdx.x;
+  if (item >= n_items) return;
+  const int vec = (int)(item / n_stick), s = (int)(item - (long)vec * n_stick);
+  const int g0 = stick_off[s], g1 = stick_off[s + 1];
+  const int z0 = pw_z[g0];
+  const int m2lo = z0 <= (N2 - 1) / 2 ? z0 : z0 - N2, m2hi = m2lo + (g1 - g0) - 1;
+  const double2 *run = x.ptr(vec) + (g0 - m2lo);  // run[m2]: the coefficient at m2
+  const C2 zero = CT<C2>::make(R(0), R(0));
+  C2 v[N2];
+#pragma unroll
+  for (int i2 = 0; i2 < N2; ++i2) {
+    if (i2 >= Q && i2 < 3 * Q) continue;
+    const int m2 = i2 < Q ? i2 : i2 - N2;
+    v[i2] = zero;
+    if (m2 >= m2lo && m2 <= m2hi) v[i2] = to_c<C2>(run[m2]);
+  }
+  NoPost none;
+  reg_dft_line<N2, +1, true>(v, none);
+  C2 *Tv = T + (long)vec * N2 * n_stick + s;
+#pragma unroll
+  for (int z = 0; z < N2; ++z) Tv[(long)z * n_stick] = v[z];
+}
+
+template <class C2, int N2>
+__global__ __launch_bounds__(kStickLineSticks) __attribute__((amdgpu_waves_per_eu(line_waves_per_eu<C2, N2, N2>())))
+void k_sticks_fwd_line(const C2 *__restrict__ T, int n_stick, int groups, const int32_t *__restrict__ stick_off,
+                       const int32_t *__restrict__ pw_stick, const int32_t *__restrict__ pw_z, VecSrc x,
+                       const double *__restrict__ kin, double2 *__restrict__ y, long ldy, double scale) {
+  constexpr int Q = N2 / 4;
+  constexpr int SG = kStickLineSticks;
+  __shared__ C2 win[2 * Q][SG];  // window row w: m2 = w (w < Q) or w - 2Q
+  const int vec = blockIdx.x / groups;
+  const int s0 = (blockIdx.x - vec * groups) * SG;
+  const int ns = min(SG, n_stick - s0);
+  const int tid = threadIdx.x;
+  if (tid < ns) {
+    const C2 *Tv = T + (long)vec * N2 * n_stick + s0 + tid;
+    C2 v[N2];
+#pragma unroll
+    for (int z = 0; z < N2; ++z) v[z] = Tv[(long)z * n_stick];
+    NoPost none;
+    reg_dft_line<N2, -1, false>(v, none);
+#pragma unroll
+    for (int w = 0; w < Q; ++w) {
+      win[w][tid] = v[w];
+      win[Q + w][tid] = v[N2 - Q + w];
+    }
+  }
+  __syncthreads();
+  const double2 *xv = x.ptr(vec);
+  double2 *yv = y + (long)vec * ldy;
+  const int g0 = stick_off[s0], g1 = stick_off[s0 + ns];
+  for (int g = g0 + tid; g < g1; g += SG) {
+    const int z = pw_z[g];
+    const C2 c = win[z < Q ? z : z - 2 * Q][pw_stick[g] - s0];
+    const double2 xg = xv[g];
+    const double t = kin[g];
+    yv[g] = make_double2(fma((double)c.x, scale, t * xg.x), fma((double)c.y, scale, t * xg.y));
+  }
+}
+
 template <class C2> const C2 *twiddles(const sgw_ham *h, int axis);
 template <> const double2 *twiddles<double2>(const sgw_ham *h, int axis) { return h->d_tw + h->tw_off[axis]; }
 template <> const float2 *twiddles<float2>(const sgw_ham *h, int axis) { return h->d_tw32 + h->tw_off[axis]; }
@@ -127,6 +242,31 @@ sgw_status launch_sticks(sgw_ctx *ctx, const sgw_ham *h, int n_vec, VecSrc x, do
   const C2 *tw = twiddles<C2>(h, 2);
   const double n2 = N2, nst = h->n_stick, npw = h->n_pw, cb = sizeof(C2);
   PendingTiming tm;
+  if constexpr (line_planes_fit<C2, N2, N2>()) {
+    if (h->m2_lo >= -N2 / 4 && h->m2_hi < N2 / 4) {
+      const int lg = (h->n_stick + kStickLineSticks - 1) / kStickLineSticks;
+      if (inverse) {
+        timing_begin(ctx, K_STICKS_INV, n_vec * (npw * 16.0 + n2 * nst * cb), 0.0, &tm);
+        if (sizeof(C2) == 16) {
+          const long items = (long)n_vec * h->n_stick;
+          hipLaunchKernelGGL((k_sticks_inv_direct<C2, N2>), dim3((items + 255) / 256), dim3(256), 0, ctx->stream, x,
+                             tbuf, h->n_stick, items, h->d_stick_off, h->d_pw_z);
+        } else {
+          hipLaunchKernelGGL((k_sticks_inv_line<C2, N2>), dim3((long)lg * n_vec), dim3(kStickLineSticks), 0,
+                             ctx->stream, x, tbuf, h->n_stick, lg, h->d_stick_off, h->d_pw_stick, h->d_pw_z);
+        }
+      } else {
+        const double scale = 1.0 / ((double)h->n[0] * h->n[1] * h->n[2]);
+        timing_begin(ctx, K_STICKS_FWD, n_vec * (npw * 32.0 + n2 * nst * cb), 0.0, &tm);
+        hipLaunchKernelGGL((k_sticks_fwd_line<C2, N2>), dim3((long)lg * n_vec), dim3(kStickLineSticks), 0, ctx->stream,
+                           tbuf, h->n_stick, lg, h->d_stick_off, h->d_pw_stick, h->d_pw_z, x, h->d_kin, y, ldy,
+                           scale);
+      }
+      timing_end(ctx, &tm);
+      SGW_HIP(hipGetLastError());
+      return SGW_OK;
+    }
+  }
   if (inverse) {
     timing_begin(ctx, K_STICKS_INV, n_vec * (npw * 16.0 + n2 * nst * cb), 0.0, &tm);
     hipLaunchKernelGGL((k_sticks_inv<C2, N2>), dim3(blocks), dim3(kStickThreads), 0, ctx->stream, x, tbuf,

@@ -235,9 +235,14 @@ __global__ __launch_bounds__((plane_threads<N0, N1>())) void k_planes(C2 *__rest
 // rows pass through LDS, once after the axis-1 inverse and once before the axis-1 forward; sticks go
 // back to HBM one per thread (coalesced) through a per-stick (i0, i1) table.  The potential is
 // loaded one group of the inverse's second stage ahead.  P planes per workgroup.
+// split N = A * B of a whole line (A = 4 or 8 for the half-input first stage)
+template <int N> struct LineSplit {
+  static constexpr int a = Split<N>::a, b = Split<N>::b;
+};
+
 template <int N, int SIGN, bool IN_HALF, class C2, class Post>
 __device__ __forceinline__ void reg_dft_line(C2 *x, Post &post) {
-  constexpr int A = Split<N>::a, B = Split<N>::b;
+  constexpr int A = LineSplit<N>::a, B = LineSplit<N>::b;
   C2 y[A][B];
 #pragma unroll
   for (int b = 0; b < B; ++b) {
@@ -274,7 +279,7 @@ struct NoPost {
 template <class C2, int N0, int N1>
 struct PotentialPost {
   using R = typename CT<C2>::R;
-  static constexpr int A = Split<N0>::a, B = Split<N0>::b;
+  static constexpr int A = LineSplit<N0>::a, B = LineSplit<N0>::b;
   const R *vz;  // V at (i0 = 0, this column), stride N1 along i0
   R cur[B], nxt[B];
   __device__ __forceinline__ explicit PotentialPost(const R *v) : vz(v) {
@@ -301,8 +306,8 @@ struct PotentialPost {
 // Planes per workgroup: about 96 (FP64) or 192 (FP32) column threads, which measured best at
 // 48 x 48 (LDS and registers then allow 8 resp. 12 waves per CU).
 template <class C2, int N0, int N1> constexpr bool line_planes_fit() {
-  return N0 % 4 == 0 && N1 % 4 == 0 && N0 <= 48 && N1 <= 48 && Split<N0>::a % 4 == 0 &&
-         Split<N1>::a % 4 == 0;
+  return N0 % 4 == 0 && N1 % 4 == 0 && N0 <= 48 && N1 <= 48 && LineSplit<N0>::a % 4 == 0 &&
+         LineSplit<N1>::a % 4 == 0;
 }
 template <class C2, int N1> constexpr int line_plane_count() {
   return (sizeof(C2) == 16 ? 96 : 192) / N1 > 0 ? (sizeof(C2) == 16 ? 96 : 192) / N1 : 1;

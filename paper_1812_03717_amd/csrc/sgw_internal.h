@@ -87,6 +87,7 @@ struct sgw_ham {
   int n_stick = 0;
   int m0_lo = 0, n_row = 0;         // rows (axis 0) holding sticks: m0 in [m0_lo, m0_lo + n_row)
   int m1_lo = 0, m1_hi = -1;        // m1 range of all sticks
+  int m2_lo = 0, m2_hi = -1;        // m2 range of all plane waves
   double kvec[3];
   double recip[3][3];
   std::vector<int32_t> miller;      // host copy, caller order
