@@ -39,6 +39,7 @@ struct RowBase {
 
 template <int N2> constexpr int sticks_per_block() { return N2 <= 32 ? 64 : 32; }
 constexpr int kStickThreads = 256;
+constexpr int kStickBatch = 4;
 
 template <class C2>
 __device__ __forceinline__ C2 to_c(double2 v) {
@@ -66,7 +67,21 @@ __global__ __launch_bounds__(kStickThreads) void k_sticks_inv(VecSrc x, C2 *__re
   for (int i = tid; i < N2; i += kStickThreads) tw[i] = twg[i];
   __syncthreads();
   const int g0 = stick_off[s0], g1 = stick_off[s0 + ns];
-  for (int g = g0 + tid; g < g1; g += kStickThreads) col[(pw_stick[g] - s0) * LDC + pw_z[g]] = to_c<C2>(xv[g]);
+  // kStickBatch plane waves per thread at a time: their loads are all issued before any is used
+  for (int gb = g0 + tid; gb < g1; gb += kStickBatch * kStickThreads) {
+    int pos[kStickBatch];
+    double2 xg[kStickBatch];
+#pragma unroll
+    for (int u = 0; u < kStickBatch; ++u) {
+      const int g = gb + u * kStickThreads;
+      const bool ok = g < g1;
+      pos[u] = ok ? (pw_stick[g] - s0) * LDC + pw_z[g] : 0;
+      xg[u] = ok ? xv[g] : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int u = 0; u < kStickBatch; ++u)
+      if (gb + u * kStickThreads < g1) col[pos[u]] = to_c<C2>(xg[u]);
+  }
   __syncthreads();
   lds_fft<N2, +1, SG, kStickThreads, false>(col, ns, StrideBase{LDC}, 1, tw, tid);
   C2 *Tv = T + (long)vec * N2 * n_stick + s0;
@@ -103,11 +118,26 @@ __global__ __launch_bounds__(kStickThreads) void k_sticks_fwd(const C2 *__restri
   const double2 *xv = x.ptr(vec);
   double2 *yv = y + (long)vec * ldy;
   const int g0 = stick_off[s0], g1 = stick_off[s0 + ns];
-  for (int g = g0 + tid; g < g1; g += kStickThreads) {
-    const C2 c = col[(pw_stick[g] - s0) * LDC + pw_z[g]];
-    const double2 xg = xv[g];
-    const double t = kin[g];
-    yv[g] = make_double2(fma((double)c.x, scale, t * xg.x), fma((double)c.y, scale, t * xg.y));
+  for (int gb = g0 + tid; gb < g1; gb += kStickBatch * kStickThreads) {
+    int pos[kStickBatch];
+    double2 xg[kStickBatch];
+    double t[kStickBatch];
+#pragma unroll
+    for (int u = 0; u < kStickBatch; ++u) {
+      const int g = gb + u * kStickThreads;
+      const bool ok = g < g1;
+      pos[u] = ok ? (pw_stick[g] - s0) * LDC + pw_z[g] : 0;
+      xg[u] = ok ? xv[g] : make_double2(0.0, 0.0);
+      t[u] = ok ? kin[g] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kStickBatch; ++u) {
+      const int g = gb + u * kStickThreads;
+      if (g < g1) {
+        const C2 c = col[pos[u]];
+        yv[g] = make_double2(fma((double)c.x, scale, t[u] * xg[u].x), fma((double)c.y, scale, t[u] * xg[u].y));
+      }
+    }
   }
 }
 
@@ -119,6 +149,7 @@ __global__ __launch_bounds__(kStickThreads) void k_sticks_fwd(const C2 *__restri
 // the coalesced plane-wave accesses and the per-stick transforms; the T accesses of consecutive
 // threads are consecutive.
 constexpr int kStickLineSticks = 64;
+constexpr int kGatherBatch = 8;
 template <class C2, int N2>
 __global__ __launch_bounds__(kStickLineSticks) __attribute__((amdgpu_waves_per_eu(line_waves_per_eu<C2, N2, N2>())))
 void k_sticks_inv_line(VecSrc x, C2 *__restrict__ T, int n_stick, int groups, const int32_t *__restrict__ stick_off,
@@ -137,9 +168,20 @@ void k_sticks_inv_line(VecSrc x, C2 *__restrict__ T, int n_stick, int groups, co
   __syncthreads();
   const double2 *xv = x.ptr(vec);
   const int g0 = stick_off[s0], g1 = stick_off[s0 + ns];
-  for (int g = g0 + tid; g < g1; g += SG) {
-    const int z = pw_z[g];
-    win[z < Q ? z : z - 2 * Q][pw_stick[g] - s0] = to_c<C2>(xv[g]);
+  for (int gb = g0 + tid; gb < g1; gb += kGatherBatch * SG) {
+    int z[kGatherBatch], st[kGatherBatch];
+    double2 xg[kGatherBatch];
+#pragma unroll
+    for (int u = 0; u < kGatherBatch; ++u) {
+      const int g = gb + u * SG;
+      const bool ok = g < g1;
+      z[u] = ok ? pw_z[g] : 0;
+      st[u] = ok ? pw_stick[g] : s0;
+      xg[u] = ok ? xv[g] : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int u = 0; u < kGatherBatch; ++u)
+      if (gb + u * SG < g1) win[z[u] < Q ? z[u] : z[u] - 2 * Q][st[u] - s0] = to_c<C2>(xg[u]);
   }
   __syncthreads();
   if (tid >= ns) return;
@@ -217,12 +259,28 @@ void k_sticks_fwd_line(const C2 *__restrict__ T, int n_stick, int groups, const 
   const double2 *xv = x.ptr(vec);
   double2 *yv = y + (long)vec * ldy;
   const int g0 = stick_off[s0], g1 = stick_off[s0 + ns];
-  for (int g = g0 + tid; g < g1; g += SG) {
-    const int z = pw_z[g];
-    const C2 c = win[z < Q ? z : z - 2 * Q][pw_stick[g] - s0];
-    const double2 xg = xv[g];
-    const double t = kin[g];
-    yv[g] = make_double2(fma((double)c.x, scale, t * xg.x), fma((double)c.y, scale, t * xg.y));
+  // kGatherBatch plane waves per thread at a time: their loads are all issued before any is used
+  for (int gb = g0 + tid; gb < g1; gb += kGatherBatch * SG) {
+    int z[kGatherBatch], st[kGatherBatch];
+    double2 xg[kGatherBatch];
+    double t[kGatherBatch];
+#pragma unroll
+    for (int u = 0; u < kGatherBatch; ++u) {
+      const int g = gb + u * SG;
+      const bool ok = g < g1;
+      z[u] = ok ? pw_z[g] : 0;
+      st[u] = ok ? pw_stick[g] : s0;
+      xg[u] = ok ? xv[g] : make_double2(0.0, 0.0);
+      t[u] = ok ? kin[g] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kGatherBatch; ++u) {
+      const int g = gb + u * SG;
+      if (g < g1) {
+        const C2 c = win[z[u] < Q ? z[u] : z[u] - 2 * Q][st[u] - s0];
+        yv[g] = make_double2(fma((double)c.x, scale, t[u] * xg[u].x), fma((double)c.y, scale, t[u] * xg[u].y));
+      }
+    }
   }
 }
 
