@@ -315,6 +315,7 @@ __global__ void k_tridiag(SolverState S, const int32_t *__restrict__ flist, int 
 constexpr int kCmbThreads = 256;
 constexpr int kCmbJ = 16;
 constexpr int kCmbK = 32;
+constexpr int kCmbU = 8;  // basis values loaded ahead (divides kCmbK)
 // workgroups are dealt round-robin to the GPU's 8 XCDs (each with its own L2)
 constexpr int kXcds = 8;
 
@@ -352,13 +353,21 @@ __global__ __launch_bounds__(kCmbThreads) void k_combine(SolverState S, const in
     __syncthreads();
     if (g < S.npw) {
       const int kend = min(kCmbK, K - k0);
-      for (int kk = 0; kk < kend; ++kk) {
-        const double2 vk = V[(long)(k0 + kk) * S.npw + g];
+      // kCmbU basis values are loaded before any is used; past kend they are 0 (and so are their
+      // coefficients in yt), which leaves acc unchanged
+      for (int kb = 0; kb < kend; kb += kCmbU) {
+        double2 vk[kCmbU];
 #pragma unroll
-        for (int q = 0; q < kCmbJ; ++q) {
-          const double2 yc = yt[kk][q];
-          acc[q].x = fma(yc.x, vk.x, fma(-yc.y, vk.y, acc[q].x));
-          acc[q].y = fma(yc.x, vk.y, fma(yc.y, vk.x, acc[q].y));
+        for (int u = 0; u < kCmbU; ++u)
+          vk[u] = kb + u < kend ? V[(long)(k0 + kb + u) * S.npw + g] : make_double2(0.0, 0.0);
+#pragma unroll
+        for (int u = 0; u < kCmbU; ++u) {
+#pragma unroll
+          for (int q = 0; q < kCmbJ; ++q) {
+            const double2 yc = yt[kb + u][q];
+            acc[q].x = fma(yc.x, vk[u].x, fma(-yc.y, vk[u].y, acc[q].x));
+            acc[q].y = fma(yc.x, vk[u].y, fma(yc.y, vk[u].x, acc[q].y));
+          }
         }
       }
     }
