@@ -861,7 +861,7 @@ static sgw_status multishift_solve(sgw_ctx *ctx, const sgw_ham *h_kq, int n_occ,
       if ((s2 = proj_dot(ctx, npw, n_occ, Sx.psi, nv, xsrc, C, crow)) != SGW_OK) return s2;
       if ((s2 = hx_batch(ctx, h_kq, nv, xsrc, AX, npw, T)) != SGW_OK) return s2;
       if ((s2 = proj_apply(ctx, npw, n_occ, Sx.psi, nv, xsrc, C, crow, AX, npw, o.alpha_pv, 1)) != SGW_OK) return s2;
-      if ((s2 = residual(ctx, Sx, d_final, nf, X, AX, C, crow, h_kq->d_i2u, (double2 *)dpsi, info, tol, d_bad)) !=
+      if ((s2 = residual(ctx, Sx, d_final, nf, X, AX, C, crow, h_kq->d_u2i, (double2 *)dpsi, info, tol, d_bad)) !=
           SGW_OK)
         return s2;
       // the pinned final list is reused by the next chunk: wait for the upload

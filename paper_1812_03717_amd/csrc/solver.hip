@@ -268,6 +268,8 @@ __global__ __launch_bounds__(kLzThreads) void k_lanczos(SolverState S, const int
 // matrix is complex symmetric with a definite imaginary part, so elimination
 // without pivoting is stable)
 // ---------------------------------------------------------------------------
+constexpr int kTriBatch = 8;
+
 __global__ void k_tridiag(SolverState S, const int32_t *__restrict__ flist, int nf, double2 *__restrict__ ycoef,
                           double2 *__restrict__ cp) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -281,31 +283,55 @@ __global__ void k_tridiag(SolverState S, const int32_t *__restrict__ flist, int 
   const double *be = S.beta + (long)slot * (S.kmax + 1);
   const double zr = S.omega[j], zi = S.eta;
   double2 dprev = make_double2(0.0, 0.0), cprev = make_double2(0.0, 0.0);
-  for (int i = 0; i < K; ++i) {
-    // den = (a_i - z) - beta_i * cp_{i-1}
-    double2 den = make_double2(al[i] - zr, -zi);
-    double2 rhs = make_double2(i == 0 ? be[0] : 0.0, 0.0);
-    if (i > 0) {
-      den.x -= be[i] * cprev.x;
-      den.y -= be[i] * cprev.y;
-      rhs.x -= be[i] * dprev.x;
-      rhs.y -= be[i] * dprev.y;
+  // the recurrence's inputs (alpha, beta) and, going back, its stored pivots are loaded kTriBatch
+  // steps at a time, ahead of the dependent arithmetic
+  for (int i0 = 0; i0 < K; i0 += kTriBatch) {
+    double a_[kTriBatch], b_[kTriBatch], bn_[kTriBatch];
+#pragma unroll
+    for (int u = 0; u < kTriBatch; ++u) {
+      const int i = i0 + u;
+      a_[u] = i < K ? al[i] : 0.0;
+      b_[u] = i < K ? be[i] : 0.0;
+      bn_[u] = i + 1 < K ? be[i + 1] : 0.0;
     }
-    const double dn = 1.0 / (den.x * den.x + den.y * den.y);
-    const double2 iden = make_double2(den.x * dn, -den.y * dn);
-    const double off = (i + 1 < K) ? be[i + 1] : 0.0;
-    cprev = c_scale(iden, off);
-    dprev = c_mul(rhs, iden);
-    cp[base + (long)i * nw] = cprev;
-    ycoef[base + (long)i * nw] = dprev;
+#pragma unroll
+    for (int u = 0; u < kTriBatch; ++u) {
+      const int i = i0 + u;
+      if (i >= K) break;
+      // den = (a_i - z) - beta_i * cp_{i-1}
+      double2 den = make_double2(a_[u] - zr, -zi);
+      double2 rhs = make_double2(i == 0 ? b_[u] : 0.0, 0.0);
+      if (i > 0) {
+        den.x -= b_[u] * cprev.x;
+        den.y -= b_[u] * cprev.y;
+        rhs.x -= b_[u] * dprev.x;
+        rhs.y -= b_[u] * dprev.y;
+      }
+      const double dn = 1.0 / (den.x * den.x + den.y * den.y);
+      const double2 iden = make_double2(den.x * dn, -den.y * dn);
+      cprev = c_scale(iden, bn_[u]);
+      dprev = c_mul(rhs, iden);
+      cp[base + (long)i * nw] = cprev;
+      ycoef[base + (long)i * nw] = dprev;
+    }
   }
   double2 ynext = make_double2(0.0, 0.0);
-  for (int i = K - 1; i >= 0; --i) {
-    const double2 d = ycoef[base + (long)i * nw];
-    const double2 c = cp[base + (long)i * nw];
-    const double2 yi = c_sub(d, c_mul(c, ynext));
-    ycoef[base + (long)i * nw] = yi;
-    ynext = yi;
+  for (int i1 = K - 1; i1 >= 0; i1 -= kTriBatch) {
+    double2 d_[kTriBatch], c_[kTriBatch];
+#pragma unroll
+    for (int u = 0; u < kTriBatch; ++u) {
+      const int i = i1 - u;
+      d_[u] = i >= 0 ? ycoef[base + (long)i * nw] : make_double2(0.0, 0.0);
+      c_[u] = i >= 0 ? cp[base + (long)i * nw] : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int u = 0; u < kTriBatch; ++u) {
+      const int i = i1 - u;
+      if (i < 0) break;
+      const double2 yi = c_sub(d_[u], c_mul(c_[u], ynext));
+      ycoef[base + (long)i * nw] = yi;
+      ynext = yi;
+    }
   }
 }
 
@@ -382,6 +408,8 @@ __global__ __launch_bounds__(kCmbThreads) void k_combine(SolverState S, const in
   }
 }
 
+constexpr int kResBatch = 4;
+
 // ---------------------------------------------------------------------------
 // true FP64 residual r = b - (A0 - z_j) x_j with A0 x_j applied afresh; writes
 // dpsi (caller order) and the per-solve info
@@ -390,7 +418,7 @@ __global__ __launch_bounds__(kRowThreads) void k_residual(SolverState S, const i
                                                           const double2 *__restrict__ X,
                                                           const double2 *__restrict__ AX,
                                                           const double2 *__restrict__ cp,
-                                                          const int32_t *__restrict__ i2u,
+                                                          const int32_t *__restrict__ u2i,
                                                           double2 *__restrict__ dpsi,
                                                           sgw_solve_info *__restrict__ info, double tol,
                                                           int *__restrict__ n_bad) {
@@ -407,18 +435,40 @@ __global__ __launch_bounds__(kRowThreads) void k_residual(SolverState S, const i
   const double zr = S.omega[j], zi = S.eta;
   double2 *out = dpsi + ((long)pair * S.n_omega + j) * npw;
   double acc[3] = {0.0, 0.0, 0.0};
-  for (int g = threadIdx.x; g < npw; g += kRowThreads) {
-    const double2 xg = x[g];
-    const double2 ag = ax[g];
-    // (A0 - z) x = (H + alpha P_occ) x - (eps + z) x
-    const double er = eps + zr;
-    double2 ox;
-    ox.x = ag.x - (er * xg.x - zi * xg.y);
-    ox.y = ag.y - (er * xg.y + zi * xg.x);
-    const double2 r = c_sub(b[g], ox);
-    acc[0] = fma(r.x, r.x, fma(r.y, r.y, acc[0]));
-    acc[1] = fma(xg.x, xg.x, fma(xg.y, xg.y, acc[1]));
-    out[i2u[g]] = xg;
+  const double er = eps + zr;
+  // kResBatch plane waves per thread at a time, their loads issued before any is used
+  for (int gb = threadIdx.x; gb < npw; gb += kResBatch * kRowThreads) {
+    double2 xg[kResBatch], ag[kResBatch], bg[kResBatch];
+#pragma unroll
+    for (int u = 0; u < kResBatch; ++u) {
+      const int g = gb + u * kRowThreads;
+      const bool ok = g < npw;
+      xg[u] = ok ? x[g] : make_double2(0.0, 0.0);
+      ag[u] = ok ? ax[g] : make_double2(0.0, 0.0);
+      bg[u] = ok ? b[g] : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int u = 0; u < kResBatch; ++u) {
+      // (A0 - z) x = (H + alpha P_occ) x - (eps + z) x   (all zero past npw)
+      double2 ox;
+      ox.x = ag[u].x - (er * xg[u].x - zi * xg[u].y);
+      ox.y = ag[u].y - (er * xg[u].y + zi * xg[u].x);
+      const double2 r = c_sub(bg[u], ox);
+      acc[0] = fma(r.x, r.x, fma(r.y, r.y, acc[0]));
+      acc[1] = fma(xg[u].x, xg[u].x, fma(xg[u].y, xg[u].y, acc[1]));
+    }
+  }
+  // the solution in the caller's order: coalesced writes, gathered reads (x was just written)
+  for (int ub = threadIdx.x; ub < npw; ub += kResBatch * kRowThreads) {
+    double2 xv[kResBatch];
+#pragma unroll
+    for (int u = 0; u < kResBatch; ++u) {
+      const int c = ub + u * kRowThreads;
+      xv[u] = c < npw ? x[u2i[c]] : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int u = 0; u < kResBatch; ++u)
+      if (ub + u * kRowThreads < npw) out[ub + u * kRowThreads] = xv[u];
   }
   // ||psi^* x||^2 from the overlaps
   double cc = 0.0;
@@ -573,13 +623,13 @@ sgw_status combine(sgw_ctx *ctx, const SolverState &S, const int32_t *flist, int
 }
 
 sgw_status residual(sgw_ctx *ctx, const SolverState &S, const int32_t *flist, int nf, const double2 *X,
-                    const double2 *AX, const double2 *cp, long rows, const int32_t *i2u, double2 *dpsi,
+                    const double2 *AX, const double2 *cp, long rows, const int32_t *u2i, double2 *dpsi,
                     sgw_solve_info *info, double tol, int *n_bad) {
   if (nf <= 0) return SGW_OK;
   PendingTiming tm;
   timing_begin(ctx, K_RESIDUAL, (double)nf * S.n_omega * S.npw * 16.0 * 4, 0.0, &tm);
   hipLaunchKernelGGL(k_residual, dim3((long)nf * S.n_omega), dim3(kRowThreads), 0, ctx->stream, S, flist, X, AX, cp,
-                     i2u, dpsi, info, tol, n_bad);
+                     u2i, dpsi, info, tol, n_bad);
   timing_end(ctx, &tm);
   SGW_HIP(hipGetLastError());
   return SGW_OK;

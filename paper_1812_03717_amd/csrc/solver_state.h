@@ -59,9 +59,10 @@ sgw_status lanczos_step(sgw_ctx *ctx, const SolverState &S, int n_active, const 
 sgw_status tridiag(sgw_ctx *ctx, const SolverState &S, const int32_t *flist, int nf, double2 *ycoef, double2 *cp);
 sgw_status combine(sgw_ctx *ctx, const SolverState &S, const int32_t *flist, int nf, const double2 *ycoef,
                    double2 *X, double est_kavg);
-// AX must hold (H + alpha P_occ) X; cp the overlap partials of X (leading dimension rows)
+// AX must hold (H + alpha P_occ) X; cp[0] the overlaps of X (as proj_dot leaves them); u2i maps
+// caller to internal plane-wave indices (dpsi is written in the caller's order)
 sgw_status residual(sgw_ctx *ctx, const SolverState &S, const int32_t *flist, int nf, const double2 *X,
-                    const double2 *AX, const double2 *cp, long rows, const int32_t *i2u, double2 *dpsi,
+                    const double2 *AX, const double2 *cp, long rows, const int32_t *u2i, double2 *dpsi,
                     sgw_solve_info *info, double tol, int *n_bad);
 // plane-major copies of the potential, FP64 and FP32
 sgw_status transpose_potential(sgw_ctx *ctx, const double *v, double *vt, float *vt32, const int n[3]);
