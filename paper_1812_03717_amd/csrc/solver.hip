@@ -172,9 +172,11 @@ __global__ __launch_bounds__(kRowThreads) void k_init(SolverState S, const doubl
 //   A0 v_k = Y - eps_v v_k, where Y = H v_k + alpha P_occ v_k has been formed
 //   by the H.x and projector kernels
 // ---------------------------------------------------------------------------
-constexpr int kLzThreads = 512;
+// threads per vector: 256 up to 4096 plane waves (one round of workgroups for ~1000 vectors on
+// 256 CUs at 16 values per thread), 512 above; values per thread EPT up to 32
+constexpr int kLzSmall = 256, kLzLarge = 512;
 
-template <int EPT>
+template <int EPT, int kLzThreads>
 __global__ __launch_bounds__(kLzThreads) void k_lanczos(SolverState S, const int32_t *__restrict__ list,
                                                         const double2 *__restrict__ Y) {
   __shared__ double sh[kLzThreads / 64];
@@ -568,9 +570,12 @@ sgw_status slot_init(sgw_ctx *ctx, const SolverState &S, int n_fill, const doubl
   return SGW_OK;
 }
 
+static int lanczos_threads(int npw) { return npw <= 16 * kLzSmall ? kLzSmall : kLzLarge; }
+
 int lanczos_ept(int npw) {
+  const int nt = lanczos_threads(npw);
   int e = 1;
-  while (e * kLzThreads < npw) e *= 2;
+  while (e * nt < npw) e *= 2;
   return e;
 }
 
@@ -579,10 +584,16 @@ sgw_status lanczos_step(sgw_ctx *ctx, const SolverState &S, int n_active, const 
   PendingTiming tm;
   timing_begin(ctx, K_LANCZOS, n_active * (S.npw * 16.0 * 4), 0.0, &tm);
   const int ept = lanczos_ept(S.npw);
+  const bool small = lanczos_threads(S.npw) == kLzSmall;
   switch (ept) {
-#define SGW_LZ(E)                                                                                      \
-  case E:                                                                                              \
-    hipLaunchKernelGGL(k_lanczos<E>, dim3(n_active), dim3(kLzThreads), 0, ctx->stream, S, list, Y);    \
+#define SGW_LZ(E)                                                                                          \
+  case E:                                                                                                  \
+    if (small)                                                                                             \
+      hipLaunchKernelGGL((k_lanczos<E, kLzSmall>), dim3(n_active), dim3(kLzSmall), 0, ctx->stream, S, list, \
+                         Y);                                                                               \
+    else                                                                                                   \
+      hipLaunchKernelGGL((k_lanczos<E, kLzLarge>), dim3(n_active), dim3(kLzLarge), 0, ctx->stream, S, list, \
+                         Y);                                                                               \
     break;
     SGW_LZ(1) SGW_LZ(2) SGW_LZ(4) SGW_LZ(8) SGW_LZ(16) SGW_LZ(32)
 #undef SGW_LZ
