@@ -138,7 +138,7 @@ __global__ __launch_bounds__(256) void k_proj_reduce(double2 *__restrict__ cp, l
 
 constexpr int kApplyWaves = 4;
 constexpr int kApplyG = 256;   // plane waves per block (each wave: kApplyG / kApplyWaves / 16 tiles)
-constexpr int kApplyBatch = 8; // occupied K-steps whose operands are loaded before their MFMAs
+constexpr int kApplyBatch = 4; // occupied K-steps whose operands are loaded before their MFMAs
 
 // grid: vtiles x gtiles, block: kApplyWaves wavefronts; dynamic LDS: 16 * n_occ complex
 __global__ __launch_bounds__(64 * kApplyWaves) void k_proj_apply(int npw, int n_occ, const double2 *__restrict__ psi,
