@@ -26,7 +26,7 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ d4 mfma(double a, double b, d4 c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
 
-constexpr int kOccTilesMax = 8;  // occupied tiles (of 16) held in accumulators per pass
+constexpr int kOccTilesMax = 4;  // occupied tiles (of 16) held in accumulators per pass
 constexpr int kDotWaves = 4;
 constexpr int kDotDepth = 4;     // K-steps of operands kept in flight per wave
 
