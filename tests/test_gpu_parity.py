@@ -34,13 +34,18 @@ def _dev(ctx, p):
     return DeviceProblem(ctx, p)
 
 
+# Which H.x kernels each case runs (the whole-line kernels need every stick in the central half
+# of the grid, |m| < N/4, and lines of at most 48 points):
 PROBLEMS = {
+    # 16^3 grid with |m| up to 4: outside the window, the LDS plane and stick kernels
     "si2": lambda: synth.si2(),
+    # 24^3: whole-line plane and stick kernels
     "fcc1_q": lambda: synth.small((1, 1, 1), n_omega=6, n_pert=5, seed=9100),
+    # 24 x 24 planes, 48-point sticks: whole-line kernels
     "fcc112_q": lambda: synth.small((1, 1, 2), n_omega=5, n_pert=3, seed=9200, ecut=6.0),
-    # a 72^3 grid: planes above 48 x 48 (one axis-0 column task per thread)
+    # 72^3: planes above 48 x 48 (LDS plane kernel, one axis-0 column task per thread), LDS sticks
     "fcc1_g72": lambda: synth.small((1, 1, 1), grid=(72, 72, 72), n_omega=4, n_pert=2, seed=9300),
-    # 48 x 48 planes (whole-line plane kernel), 24-point sticks
+    # 48 x 48 planes, 24-point sticks: whole-line kernels
     "fcc221_g48": lambda: synth.small((2, 2, 1), n_omega=4, n_pert=2, seed=9400, ecut=6.0),
 }
 
