@@ -4,11 +4,18 @@
     python -m paper_1812_03717_amd.profiling pmc DB
     python -m paper_1812_03717_amd.profiling traffic --kernel k_planes --fetch DB --write DB \
         --copy-fetch DB --copy-write DB --copy-bytes N [--out FILE.json]
+    python -m paper_1812_03717_amd.profiling mfma --pmc DB --trace DB --kernel k_proj_dot [--kernel ...]
 
 ``traffic`` scales the per-dispatch FETCH_SIZE and WRITE_SIZE averages (KiB) of
 one kernel by what the same counters read for a plain device copy of known
 size, and records a hash of the kernel's sources so that a later change of the
 kernel marks the numbers stale (``source_hash``).
+
+``mfma`` reports, per kernel, the FP64 matrix flops per dispatch
+(SQ_INSTS_VALU_MFMA_MOPS_F64 counts units of 512 flops), the achieved rate over
+the traced average duration, and the fraction of SIMD cycles the matrix units
+were busy (SQ_VALU_MFMA_BUSY_CYCLES, summed over the SIMDs, against the traced
+duration on all 1024 SIMDs at the 2.4 GHz peak clock).
 """
 from __future__ import annotations
 
@@ -94,6 +101,26 @@ def traffic(kernel_prefix, fetch_db, write_db, copy_fetch_db, copy_write_db, cop
             "fetch_scale": f_scale, "write_scale": w_scale, "dispatches": [nf, nw]}
 
 
+N_SIMD = 256 * 4      # MI355X: 256 compute units of 4 SIMDs
+CLOCK_HZ = 2.4e9      # peak engine clock
+FP64_MFMA_PEAK = 78.6e12
+
+
+def mfma(pmc_db, trace_db, kernel_prefix):
+    """{dispatches, avg_us, flops, tflops, frac_peak, busy_frac} of one kernel."""
+    durs = [(calls, avg) for n, calls, tot, avg, pct in top(trace_db) if n.startswith(kernel_prefix)]
+    if not durs:
+        raise KeyError(f"{kernel_prefix} not in {trace_db}")
+    calls = sum(c for c, _ in durs)
+    avg_us = sum(c * a for c, a in durs) / calls
+    n, mops = _avg(pmc_db, kernel_prefix, "SQ_INSTS_VALU_MFMA_MOPS_F64")
+    _, busy = _avg(pmc_db, kernel_prefix, "SQ_VALU_MFMA_BUSY_CYCLES")
+    flops = mops * 512.0
+    return {"dispatches": n, "avg_us": avg_us, "flops": flops, "tflops": flops / (avg_us * 1e-6) / 1e12,
+            "frac_peak": flops / (avg_us * 1e-6) / FP64_MFMA_PEAK,
+            "busy_frac": busy / (avg_us * 1e-6 * CLOCK_HZ * N_SIMD)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -108,6 +135,10 @@ def main():
         r.add_argument(f"--{k}", required=True)
     r.add_argument("--copy-bytes", type=float, required=True)
     r.add_argument("--out")
+    m = sub.add_parser("mfma")
+    m.add_argument("--pmc", required=True)
+    m.add_argument("--trace", required=True)
+    m.add_argument("--kernel", action="append", required=True)
     a = ap.parse_args()
     if a.cmd == "top":
         # rocpd reports durations in microseconds
@@ -116,7 +147,15 @@ def main():
             print(f"{n:40s} {calls:7d} {tot / 1e3:10.2f} {avg:9.2f} {pct:6.2f}")
     elif a.cmd == "pmc":
         for (k, cn), (n, avg) in sorted(pmc(a.db).items()):
-            print(f"{k:40s} {cn:12s} dispatches {n:6d} avg {avg:14.1f} KiB")
+            unit = " KiB" if cn in ("FETCH_SIZE", "WRITE_SIZE") else ""
+            print(f"{k:40s} {cn:12s} dispatches {n:6d} avg {avg:14.1f}{unit}")
+    elif a.cmd == "mfma":
+        print(f"{'kernel':24s} {'dispatches':>10s} {'avg_us':>8s} {'GFLOP/disp':>10s} {'TFLOP/s':>8s} "
+              f"{'of_peak':>7s} {'mfma_busy':>9s}")
+        for k in a.kernel:
+            r = mfma(a.pmc, a.trace, k)
+            print(f"{k:24s} {r['dispatches']:10d} {r['avg_us']:8.2f} {r['flops'] / 1e9:10.3f} {r['tflops']:8.2f} "
+                  f"{r['frac_peak']:7.3f} {r['busy_frac']:9.3f}")
     else:
         res = traffic(a.kernel, a.fetch, a.write, a.copy_fetch, a.copy_write, a.copy_bytes)
         res["kernel"] = a.name
