@@ -537,7 +537,8 @@ extern "C" sgw_status sgw_opts_default(sgw_opts *o) {
 namespace {
 
 constexpr size_t kAlign = 256;
-constexpr double kDefaultBudget = 40.0 * (1ull << 30);
+// workspace budget that sizes the automatic slot count: a third of one MI355X's 288 GB of HBM
+constexpr double kDefaultBudget = 96.0 * (1ull << 30);
 
 struct Layout {
   int S = 0, F = 0, kmax = 0, M = 8;
