@@ -74,6 +74,20 @@ def hamiltonian(miller: np.ndarray, B: np.ndarray, kvec, v_grid: np.ndarray) -> 
     return h
 
 
+def hamiltonian_rows(miller: np.ndarray, B: np.ndarray, kvec, v_grid: np.ndarray, rows) -> np.ndarray:
+    """Rows `rows` of the dense plane-wave Hamiltonian, by the same definition as `hamiltonian`:
+    H[i, j] = T_i delta_ij + V~[(m_i - m_j) mod N] (for bases too large to hold H whole)."""
+    vq = potential_coefficients(v_grid)
+    n0, n1, n2 = v_grid.shape
+    m = np.asarray(miller, np.int64)
+    r = np.asarray(rows, np.int64)
+    h = vq[(m[r, None, 0] - m[None, :, 0]) % n0,
+           (m[r, None, 1] - m[None, :, 1]) % n1,
+           (m[r, None, 2] - m[None, :, 2]) % n2]
+    h[np.arange(len(r)), r] += kinetic(miller, B, kvec)[r]
+    return h
+
+
 def eigh(h: np.ndarray):
     """All eigenpairs of the Hermitian matrix (LAPACK divide and conquer)."""
     return sla.eigh(h, driver="evd")

@@ -367,6 +367,15 @@ sgw_status launch_planes(sgw_ctx *ctx, const sgw_ham *h, int n_vec, C2 *tbuf) {
       launched = true;
     }
   }
+  if constexpr (pair_planes_fit<C2, N0, N1>()) {
+    // lines too long for one thread: two threads per line, split by real-space parity
+    if (line_window_ok(h->n, h->m0_lo, h->n_row, h->m1_lo, h->m1_hi)) {
+      hipLaunchKernelGGL((k_planes_pair<N0, N1>), dim3(blocks), dim3(pair_plane_threads<N0, N1>()), 0, ctx->stream,
+                         (double2 *)tbuf, h->n[2], h->n_stick, h->d_rows, h->d_stick_ij, h->m0_lo, h->n_row,
+                         h->d_vt);
+      launched = true;
+    }
+  }
   if (!launched)
     hipLaunchKernelGGL((k_planes<C2, N0, N1>), dim3(blocks), dim3(plane_threads<N0, N1>()), 0, ctx->stream, tbuf,
                        h->n[2], h->n_stick, h->d_rows, h->m0_lo, h->n_row, potential<C2>(h), twiddles<C2>(h, 0),

@@ -421,4 +421,157 @@ void k_planes_line(C2 *__restrict__ T, long n_planes, int n2, int n_stick, const
   }
 }
 
+// Pair-of-threads variant for FP64 planes whose lines do not fit one thread's registers (64 and 72
+// points), under the same central-half window.  With window input X[k] (k < N/4 or k >= 3N/4, i.e.
+// one k for each residue j = k mod N/2), the inverse line splits by the parity r of the real-space
+// index n = 2m + r into two half-length transforms:
+//   x[2m + r] = sum_j X[k_j] w_N^(r k_j) w_{N/2}^(m j),        k_j = j (j < N/4), j + N/2 (else)
+// and the forward's window outputs are the sum of the two parities' half-length transforms:
+//   X'[k_j] = sum_r w_N^(-r k_j) sum_m x'[2m + r] w_{N/2}^(-m j).
+// So a row or column is handled by two threads (r = 0, 1), each holding N/2 values; the parity-1
+// thread twiddles its inputs and outputs, and the two forward halves are added through LDS (parity 1
+// writes, parity 0 adds its own).  The arithmetic is that of the full-length transforms
+// reassociated, not the same operations: results agree with the other plane kernels to rounding.
+template <int N, int SIGN, class C2>
+__device__ __forceinline__ void half_line_dft(C2 *x) {
+  if constexpr (N == 36) {
+    pfa_dft<4, 9, SIGN>(x);
+  } else if constexpr (N == 24) {
+    pfa_dft<8, 3, SIGN>(x);
+  } else if constexpr (N == 8 || N == 12) {
+    RegDft<N, SIGN>::run(x);
+  } else {
+    NoPost none;
+    reg_dft_line<N, SIGN, false>(x, none);
+  }
+}
+template <class C2, int N0, int N1> constexpr bool pair_planes_fit() {
+  return sizeof(C2) == 16 && !line_planes_fit<C2, N0, N1>() && N0 % 4 == 0 && N1 % 4 == 0 && N0 <= 72 && N1 <= 72;
+}
+// threads: one per (parity, column) and at least one per (parity, window row)
+template <int N0, int N1> constexpr int pair_plane_threads() {
+  return ((2 * N1 > N0 ? 2 * N1 : N0) + 63) / 64 * 64;
+}
+
+template <int N0, int N1>
+__global__ __launch_bounds__((pair_plane_threads<N0, N1>())) __attribute__((amdgpu_waves_per_eu(2)))
+void k_planes_pair(double2 *__restrict__ T, int n2, int n_stick, const int4 *__restrict__ rows,
+                   const int *__restrict__ stick_ij, int m0_lo, int n_row, const double *__restrict__ vt) {
+  constexpr int NT = pair_plane_threads<N0, N1>();
+  constexpr int LD = N1 + 1;
+  constexpr int H0 = N0 / 2, Q0 = N0 / 4, H1 = N1 / 2, Q1 = N1 / 4;
+  __shared__ double2 buf[H0][LD];
+  const long q = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int z = (int)(q % n2);
+  double2 *Tq = T + q * n_stick;
+  const double *vz = vt + (long)z * N0 * N1;
+  const double2 zero = make_double2(0.0, 0.0);
+  auto slot_of = [](int m0) { return m0 >= 0 ? m0 : m0 + H0; };
+
+  // window rows without sticks read as zero in the axis-0 pass
+  const int n_below = m0_lo + Q0, n_empty = H0 - n_row;
+  for (int e = tid; e < n_empty * LD; e += NT) {
+    const int k = e / LD, c = e - k * LD;
+    const int m0 = k < n_below ? -Q0 + k : m0_lo + n_row + (k - n_below);
+    buf[slot_of(m0)][c] = zero;
+  }
+
+  // ---- axis 1, inverse: (parity, stick row) per thread; parity r writes the columns 2m + r ----
+  const bool row_act = tid < 2 * n_row;
+  const int rr = tid >= n_row;
+  const int t = tid - rr * n_row;
+  const int srow = slot_of(m0_lo + t);
+  if (row_act) {
+    const int4 ri = rows[t];
+    const double2 *run = Tq + (ri.x - ri.y);  // run[m1]: the row's stick at m1
+    double2 x[H1];
+#pragma unroll
+    for (int j = 0; j < H1; ++j) {
+      const int m1 = j < Q1 ? j : j - H1;
+      x[j] = zero;
+      if (m1 >= ri.y && m1 <= ri.z) x[j] = run[m1];
+    }
+    if (rr) {
+#pragma unroll
+      for (int j = 0; j < H1; ++j) x[j] = twiddle_c<N1, +1>(x[j], j < Q1 ? j : j + H1);
+    }
+    half_line_dft<H1, +1>(x);
+#pragma unroll
+    for (int m = 0; m < H1; ++m) buf[srow][2 * m + rr] = x[m];
+  }
+  __syncthreads();
+
+  // ---- axis 0: inverse, times V(r), forward; (parity, column) per thread ----
+  {
+    const bool act = tid < 2 * N1;
+    const int r = tid >= N1;
+    const int i1 = tid - r * N1;
+    double2 x[H0];
+    if (act) {
+#pragma unroll
+      for (int j = 0; j < H0; ++j) x[j] = buf[j][i1];  // slot j holds window row k_j
+      if (r) {
+#pragma unroll
+        for (int j = 0; j < H0; ++j) x[j] = twiddle_c<N0, +1>(x[j], j < Q0 ? j : j + H0);
+      }
+      half_line_dft<H0, +1>(x);
+      const double *vc = vz + r * N1 + i1;  // V at i0 = 2m + r
+#pragma unroll
+      for (int m = 0; m < H0; ++m) x[m] = c_scale(x[m], vc[2 * m * N1]);
+      half_line_dft<H0, -1>(x);
+      if (r) {
+#pragma unroll
+        for (int j = 0; j < H0; ++j) x[j] = twiddle_c<N0, -1>(x[j], j < Q0 ? j : j + H0);
+      }
+    }
+    __syncthreads();
+    if (act && r) {
+#pragma unroll
+      for (int j = 0; j < H0; ++j) buf[j][i1] = x[j];
+    }
+    __syncthreads();
+    if (act && !r) {
+#pragma unroll
+      for (int j = 0; j < H0; ++j) buf[j][i1] = c_add(x[j], buf[j][i1]);
+    }
+    __syncthreads();
+  }
+
+  // ---- axis 1, forward: (parity, stick row) per thread; window column k_j <- sum of parities ----
+  {
+    double2 x[H1];
+    if (row_act) {
+#pragma unroll
+      for (int m = 0; m < H1; ++m) x[m] = buf[srow][2 * m + rr];
+      half_line_dft<H1, -1>(x);
+      if (rr) {
+#pragma unroll
+        for (int j = 0; j < H1; ++j) x[j] = twiddle_c<N1, -1>(x[j], j < Q1 ? j : j + H1);
+      }
+    }
+    __syncthreads();
+    if (row_act && rr) {
+#pragma unroll
+      for (int j = 0; j < H1; ++j) buf[srow][j < Q1 ? j : j + H1] = x[j];
+    }
+    __syncthreads();
+    if (row_act && !rr) {
+#pragma unroll
+      for (int j = 0; j < H1; ++j) {
+        const int c = j < Q1 ? j : j + H1;
+        buf[srow][c] = c_add(x[j], buf[srow][c]);
+      }
+    }
+    __syncthreads();
+  }
+
+  // ---- gather the sticks, one per thread ----
+  for (int s = tid; s < n_stick; s += NT) {
+    const int ij = stick_ij[s];
+    const int i0 = ij >> 16;
+    Tq[s] = buf[i0 < Q0 ? i0 : i0 - H0][ij & 0xffff];
+  }
+}
+
 }  // namespace sgw

@@ -43,8 +43,14 @@ PROBLEMS = {
     "fcc1_q": lambda: synth.small((1, 1, 1), n_omega=6, n_pert=5, seed=9100),
     # 24 x 24 planes, 48-point sticks: whole-line kernels
     "fcc112_q": lambda: synth.small((1, 1, 2), n_omega=5, n_pert=3, seed=9200, ecut=6.0),
-    # 72^3: planes above 48 x 48 (LDS plane kernel, one axis-0 column task per thread), LDS sticks
+    # 72^3: two-thread plane kernel (FP64; the FP32 potential path keeps the LDS plane kernel), LDS sticks
     "fcc1_g72": lambda: synth.small((1, 1, 1), grid=(72, 72, 72), n_omega=4, n_pert=2, seed=9300),
+    # 72 x 24 planes (72-point columns, 24-point rows), 48-point sticks: two-thread plane kernel
+    "fcc312_g72": lambda: synth.small((3, 1, 2), n_omega=4, n_pert=2, seed=9500, ecut=6.0),
+    # 24 x 72 planes (72-point rows), 24-point sticks: two-thread plane kernel
+    "fcc131_g72": lambda: synth.small((1, 3, 1), n_omega=4, n_pert=2, seed=9600, ecut=6.0),
+    # 64^3: two-thread plane kernel on 32-point half lines, LDS sticks
+    "fcc1_g64": lambda: synth.small((1, 1, 1), grid=(64, 64, 64), n_omega=4, n_pert=2, seed=9700),
     # 48 x 48 planes, 24-point sticks: whole-line kernels
     "fcc221_g48": lambda: synth.small((2, 2, 1), n_omega=4, n_pert=2, seed=9400, ecut=6.0),
 }
@@ -65,6 +71,32 @@ def test_apply_h_matches_dense(ctx, name):
         err = np.abs(y - yr).max() / np.abs(yr).max()
         print(name, n, "apply_h rel err", err, flush=True)
         assert err <= 1e-12
+
+
+def test_apply_h_si64_shape_sampled(ctx):
+    """72^3 grid at the si64 size (64-atom cubic cell, ~16,000 plane waves, sticks filling most of the
+    central-half window): 48 sampled rows of H, from the oracle's definition, against the FP64 H.x of
+    64 vectors."""
+    from paper_1812_03717_amd import sgw
+    from synth import configs
+    from synth import crystal as cx
+    A, tau = cx.supercell(*cx.conventional_cubic(configs.A_LAT), (2, 2, 2))
+    B = cx.reciprocal(A)
+    q = cx.seeded_q(B, 5)
+    grid = (72, 72, 72)
+    v = cx.gaussian_potential(A, tau, grid, noise=0.05, seed=5)
+    miller = cx.g_sphere(B, q, 11.46)
+    vt = torch.from_numpy(np.ascontiguousarray(v, np.float64)).to(ctx.device)
+    ham = sgw.sgw_ham_create(ctx, grid, B, q, miller, vt)
+    n = miller.shape[0]
+    rng = np.random.default_rng(72)
+    x = rng.standard_normal((64, n)) + 1j * rng.standard_normal((64, n))
+    y = sgw.sgw_apply_h(ctx, ham, torch.from_numpy(x).to(ctx.device)).cpu().numpy()
+    rows = rng.choice(n, 48, replace=False)
+    ref = x @ so.hamiltonian_rows(miller, B, q, v, rows).T
+    err = np.abs(y[:, rows] - ref).max() / np.abs(ref).max()
+    print("si64 shape", n, "PW, m range", miller.min(0), miller.max(0), "sampled rel err", err, flush=True)
+    assert err <= 1e-12
 
 
 @pytest.mark.parametrize("name", sorted(PROBLEMS))

@@ -75,6 +75,11 @@ def check_hamiltonian_bruteforce(kvec=(0.03, -0.02, 0.05)):
     err = np.linalg.norm(h @ x - y_ref) / np.linalg.norm(y_ref)
     assert err <= 1e-13, err
     assert np.abs(h - h.conj().T).max() <= 1e-14 * np.abs(h).max()
+    # the row-restricted form (sampled outputs at bases too large for H) against the same sums
+    rows = np.array([0, 3, len(miller) // 2, len(miller) - 1])
+    hr = so.hamiltonian_rows(miller, B, kvec, v, rows)
+    err_r = np.abs(hr @ x - y_ref[rows]).max() / np.abs(y_ref).max()
+    assert err_r <= 1e-13, err_r
 
 
 def check_shifted_source_realspace():
@@ -269,6 +274,12 @@ def _mut_transposed_potential(miller, B, kvec, v_grid):
 
 
 _orig_ham = so.hamiltonian
+_orig_rows = so.hamiltonian_rows
+
+
+def _mut_rows_index_swap(miller, B, kvec, v_grid, rows):
+    # V~ at m_j - m_i instead of m_i - m_j
+    return _orig_ham(miller, B, kvec, v_grid).T[np.asarray(rows)].copy()
 
 MUTATIONS = {
     "rhs_sign": ("rhs", lambda *a: -_orig_rhs(*a)),
@@ -278,6 +289,7 @@ MUTATIONS = {
     "kinetic_drops_k": ("kinetic", lambda m, B, k: _orig_kin(m, B, 0.0 * np.asarray(k))),
     "potential_conjugated": ("potential_coefficients", lambda v: np.conj(_orig_coef(v))),
     "hamiltonian_transposed": ("hamiltonian", _mut_transposed_potential),
+    "hamiltonian_rows_index_swap": ("hamiltonian_rows", _mut_rows_index_swap),
     "operator_shift_sign": ("coulomb_operator", lambda h, po, e, a: _orig_op(h, po, -e, a)),
     "spectral_off_by_one": ("solve_spectral", lambda w, u, n, e, b, z: _orig_spec(w, u, n + 1, e, b, z)),
     "spectral_conj_shift": ("solve_spectral", lambda w, u, n, e, b, z: _orig_spec(w, u, n, e, b, np.conj(z))),
