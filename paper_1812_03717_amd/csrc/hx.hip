@@ -230,6 +230,43 @@ void k_sticks_inv_direct(VecSrc x, C2 *__restrict__ T, int n_stick, long n_items
   for (int z = 0; z < N2; ++z) Tv[(long)z * n_stick] = v[z];
 }
 
+// y[g] = scale * (window value of plane wave g) + kin[g] x[g] for the plane waves of sticks
+// [s0, s0 + ns), read from win[window row][stick - s0] (window row w: m2 = w for w < Q, w - 2Q
+// otherwise); NT threads, kGatherBatch plane waves per thread at a time, all loads issued before use
+// (the gather of k_sticks_fwd_line, for other thread counts)
+template <class C2, int Q, int SG, int NT>
+__device__ __forceinline__ void fwd_window_gather(const C2 (*win)[SG], int s0, int ns,
+                                                  const int32_t *__restrict__ stick_off,
+                                                  const int32_t *__restrict__ pw_stick,
+                                                  const int32_t *__restrict__ pw_z,
+                                                  const double2 *__restrict__ xv, const double *__restrict__ kin,
+                                                  double2 *__restrict__ yv, double scale) {
+  const int tid = threadIdx.x;
+  const int g0 = stick_off[s0], g1 = stick_off[s0 + ns];
+  for (int gb = g0 + tid; gb < g1; gb += kGatherBatch * NT) {
+    int z[kGatherBatch], st[kGatherBatch];
+    double2 xg[kGatherBatch];
+    double t[kGatherBatch];
+#pragma unroll
+    for (int u = 0; u < kGatherBatch; ++u) {
+      const int g = gb + u * NT;
+      const bool ok = g < g1;
+      z[u] = ok ? pw_z[g] : 0;
+      st[u] = ok ? pw_stick[g] : s0;
+      xg[u] = ok ? xv[g] : make_double2(0.0, 0.0);
+      t[u] = ok ? kin[g] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kGatherBatch; ++u) {
+      const int g = gb + u * NT;
+      if (g < g1) {
+        const C2 c = win[z[u] < Q ? z[u] : z[u] - 2 * Q][st[u] - s0];
+        yv[g] = make_double2(fma((double)c.x, scale, t[u] * xg[u].x), fma((double)c.y, scale, t[u] * xg[u].y));
+      }
+    }
+  }
+}
+
 template <class C2, int N2>
 __global__ __launch_bounds__(kStickLineSticks) __attribute__((amdgpu_waves_per_eu(line_waves_per_eu<C2, N2, N2>())))
 void k_sticks_fwd_line(const C2 *__restrict__ T, int n_stick, int groups, const int32_t *__restrict__ stick_off,
@@ -284,6 +321,95 @@ void k_sticks_fwd_line(const C2 *__restrict__ T, int n_stick, int groups, const 
   }
 }
 
+// Stick kernels for FP64 lines too long for one thread (64 and 72 points), under the same window:
+// two threads per stick split the transform by the parity r of i2 (planes.h: k_planes_pair).  The
+// inverse writes T at i2 = 2m + r; the forward's two halves meet in the LDS window (parity 1 writes,
+// parity 0 adds) before the coalesced gather.
+// Inverse: a workgroup gathers the plane waves of 64 sticks into the LDS window once (coalesced;
+// measured a third faster than each thread of a pair loading its stick's run itself), then each
+// (parity, stick) thread transforms its column of the window.
+template <int N2>
+__global__ __launch_bounds__(2 * kStickLineSticks) __attribute__((amdgpu_waves_per_eu(2)))
+void k_sticks_inv_pair(VecSrc x, double2 *__restrict__ T, int n_stick, int groups, const int32_t *__restrict__ stick_off,
+                       const int32_t *__restrict__ pw_stick, const int32_t *__restrict__ pw_z) {
+  constexpr int Q = N2 / 4, H = N2 / 2;
+  constexpr int SG = kStickLineSticks, NT = 2 * SG;
+  __shared__ double2 win[2 * Q][SG];  // window row w: m2 = w (w < Q) or w - 2Q
+  const int vec = blockIdx.x / groups;
+  const int s0 = (blockIdx.x - vec * groups) * SG;
+  const int ns = min(SG, n_stick - s0);
+  const int tid = threadIdx.x;
+  for (int e = tid; e < 2 * Q * SG; e += NT) win[e / SG][e % SG] = make_double2(0.0, 0.0);
+  __syncthreads();
+  const double2 *xv = x.ptr(vec);
+  const int g0 = stick_off[s0], g1 = stick_off[s0 + ns];
+  for (int gb = g0 + tid; gb < g1; gb += kGatherBatch * NT) {
+    int z[kGatherBatch], st[kGatherBatch];
+    double2 xg[kGatherBatch];
+#pragma unroll
+    for (int u = 0; u < kGatherBatch; ++u) {
+      const int g = gb + u * NT;
+      const bool ok = g < g1;
+      z[u] = ok ? pw_z[g] : 0;
+      st[u] = ok ? pw_stick[g] : s0;
+      xg[u] = ok ? xv[g] : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int u = 0; u < kGatherBatch; ++u)
+      if (gb + u * NT < g1) win[z[u] < Q ? z[u] : z[u] - 2 * Q][st[u] - s0] = xg[u];
+  }
+  __syncthreads();
+  const int r = tid / SG, t = tid - r * SG;  // parity per wavefront
+  if (t >= ns) return;
+  double2 v[H];
+#pragma unroll
+  for (int j = 0; j < H; ++j) v[j] = win[j][t];
+  if (r) {
+#pragma unroll
+    for (int j = 0; j < H; ++j) v[j] = twiddle_c<N2, +1>(v[j], j < Q ? j : j + H);
+  }
+  half_line_dft<H, +1>(v);
+  double2 *Tv = T + ((long)vec * N2 + r) * n_stick + s0 + t;
+#pragma unroll
+  for (int m = 0; m < H; ++m) Tv[(long)(2 * m) * n_stick] = v[m];
+}
+
+template <int N2>
+__global__ __launch_bounds__(2 * kStickLineSticks) __attribute__((amdgpu_waves_per_eu(2)))
+void k_sticks_fwd_pair(const double2 *__restrict__ T, int n_stick, int groups, const int32_t *__restrict__ stick_off,
+                       const int32_t *__restrict__ pw_stick, const int32_t *__restrict__ pw_z, VecSrc x,
+                       const double *__restrict__ kin, double2 *__restrict__ y, long ldy, double scale) {
+  constexpr int Q = N2 / 4, H = N2 / 2;
+  constexpr int SG = kStickLineSticks;
+  __shared__ double2 win[2 * Q][SG];  // window row w: m2 = w (w < Q) or w - 2Q
+  const int vec = blockIdx.x / groups;
+  const int s0 = (blockIdx.x - vec * groups) * SG;
+  const int ns = min(SG, n_stick - s0);
+  const int tid = threadIdx.x;
+  const int r = tid / SG, t = tid - r * SG;  // parity per wavefront
+  double2 v[H];
+  if (t < ns) {
+    const double2 *Tv = T + ((long)vec * N2 + r) * n_stick + s0 + t;
+#pragma unroll
+    for (int m = 0; m < H; ++m) v[m] = Tv[(long)(2 * m) * n_stick];
+    half_line_dft<H, -1>(v);
+    if (r) {
+#pragma unroll
+      for (int j = 0; j < H; ++j) v[j] = twiddle_c<N2, -1>(v[j], j < Q ? j : j + H);
+#pragma unroll
+      for (int j = 0; j < H; ++j) win[j][t] = v[j];
+    }
+  }
+  __syncthreads();
+  if (t < ns && !r) {
+#pragma unroll
+    for (int j = 0; j < H; ++j) win[j][t] = c_add(v[j], win[j][t]);
+  }
+  __syncthreads();
+  fwd_window_gather<double2, Q, SG, 2 * SG>(win, s0, ns, stick_off, pw_stick, pw_z, x.ptr(vec), kin,
+                                            y + (long)vec * ldy, scale);
+}
+
 template <class C2> const C2 *twiddles(const sgw_ham *h, int axis);
 template <> const double2 *twiddles<double2>(const sgw_ham *h, int axis) { return h->d_tw + h->tw_off[axis]; }
 template <> const float2 *twiddles<float2>(const sgw_ham *h, int axis) { return h->d_tw32 + h->tw_off[axis]; }
@@ -319,6 +445,26 @@ sgw_status launch_sticks(sgw_ctx *ctx, const sgw_ham *h, int n_vec, VecSrc x, do
         hipLaunchKernelGGL((k_sticks_fwd_line<C2, N2>), dim3((long)lg * n_vec), dim3(kStickLineSticks), 0, ctx->stream,
                            tbuf, h->n_stick, lg, h->d_stick_off, h->d_pw_stick, h->d_pw_z, x, h->d_kin, y, ldy,
                            scale);
+      }
+      timing_end(ctx, &tm);
+      SGW_HIP(hipGetLastError());
+      return SGW_OK;
+    }
+  }
+  if constexpr (pair_planes_fit<C2, N2, N2>()) {
+    if (h->m2_lo >= -N2 / 4 && h->m2_hi < N2 / 4) {
+      const int lg = (h->n_stick + kStickLineSticks - 1) / kStickLineSticks;
+      if (inverse) {
+        timing_begin(ctx, K_STICKS_INV, n_vec * (npw * 16.0 + n2 * nst * cb), 0.0, &tm);
+        hipLaunchKernelGGL((k_sticks_inv_pair<N2>), dim3((long)lg * n_vec), dim3(2 * kStickLineSticks), 0,
+                           ctx->stream, x, (double2 *)tbuf, h->n_stick, lg, h->d_stick_off, h->d_pw_stick,
+                           h->d_pw_z);
+      } else {
+        const double scale = 1.0 / ((double)h->n[0] * h->n[1] * h->n[2]);
+        timing_begin(ctx, K_STICKS_FWD, n_vec * (npw * 32.0 + n2 * nst * cb), 0.0, &tm);
+        hipLaunchKernelGGL((k_sticks_fwd_pair<N2>), dim3((long)lg * n_vec), dim3(2 * kStickLineSticks), 0,
+                           ctx->stream, (const double2 *)tbuf, h->n_stick, lg, h->d_stick_off, h->d_pw_stick,
+                           h->d_pw_z, x, h->d_kin, y, ldy, scale);
       }
       timing_end(ctx, &tm);
       SGW_HIP(hipGetLastError());
