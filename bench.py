@@ -17,6 +17,8 @@ events on the library's stream during the plain FP64 steps) and the CPU oracle
 timed on a bounded sample of the same workload.
 
     python bench.py --workload batch200     # 200 uneven systems, sternheimer_solve_batch
+    python bench.py --workload si64 --precision fp64 --max-iter 3500 --no-cpu-baseline
+                                            # 64-atom cell, 72^3 grid, 256,000 solves
 """
 from __future__ import annotations
 
@@ -39,6 +41,8 @@ WORKLOADS = {
             "eta 0.05 eV, tol 1e-8",
     "si2": "si2: diamond fcc primitive (2 atoms), 307 PW, 16^3 grid, 4 bands x 4 perts x 8 omega in [0,20] eV, "
            "eta 0.1 eV, tol 1e-10",
+    "si64": "si64: diamond conventional 2x2x2 (64 atoms), 16013 PW, 72^3 grid, 128 bands x 20 perts x 100 omega in "
+            "[0,40] eV, eta 0.05 eV, tol 1e-8",
     "batch200": "batch200: 200 independent diamond fcc n0 x n1 x n2 cells (n_d in 1..3, 2-54 atoms), grid 24 n_d "
                 "per axis, Ecut 4 Ha (100-2800 PW), all ~2*atoms occupied bands, 16-128 omega in [0,40] eV, "
                 "4-16 perts at an own seeded q, eta 0.05 eV, tol 1e-8",
@@ -204,6 +208,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="si16", choices=sorted(WORKLOADS))
     ap.add_argument("--slots", type=int, default=0)
+    ap.add_argument("--max-iter", type=int, default=0,
+                    help="Krylov steps per pair before a solve is flagged (0: the library default; si64 needs ~3500)")
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="mixed",
                     help="the timed method; mixed: FP32 potential matvecs once a pair's residuals are small, "
                          "FP64 refinement.  A plain FP64 leg is always timed beside it.")
@@ -255,6 +261,8 @@ def main():
     kw = dict(precision=prec)
     if args.slots:
         kw["slots"] = args.slots
+    if args.max_iter:
+        kw["max_iter"] = args.max_iter
     if args.mixed_switch:
         kw["mixed_switch"] = args.mixed_switch
     opts = sgw.sgw_opts_default(**kw)
@@ -306,7 +314,7 @@ def main():
     else:
         elapsed, n_ok, inf = timed(opts, None)
         report(f"timed ({args.precision})", elapsed, n_ok, inf)
-        plain = sgw.sgw_opts_default(slots=args.slots) if args.slots else sgw.sgw_opts_default()
+        plain = sgw.sgw_opts_default(**{k: v for k, v in kw.items() if k in ("slots", "max_iter")})
         p_el, p_ok, p_inf = timed(plain, dominant)
         report("timed (plain fp64)", p_el, p_ok, p_inf)
     ks = ctx.kernel_stats(dominant)

@@ -32,8 +32,8 @@ CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
 # sources that define each timed kernel
 KERNEL_SOURCES = {
     "hx_planes": ["planes.h", "fft_reg.h", "fft_lds.h", "twiddle_const.h", "hx.hip"],
-    "hx_sticks_inv": ["hx.hip", "fft_lds.h"],
-    "hx_sticks_fwd": ["hx.hip", "fft_lds.h"],
+    "hx_sticks_inv": ["hx.hip", "planes.h", "fft_reg.h", "fft_lds.h", "twiddle_const.h"],
+    "hx_sticks_fwd": ["hx.hip", "planes.h", "fft_reg.h", "fft_lds.h", "twiddle_const.h"],
     "proj_dot": ["projector.hip"],
     "proj_apply": ["projector.hip"],
 }

@@ -12,6 +12,9 @@ Fourier coefficients of the sampled potential V(r_j).
 """
 from __future__ import annotations
 
+import hashlib
+import os
+
 import numpy as np
 import scipy.linalg as sla
 
@@ -62,14 +65,33 @@ def _lowest_states_gpu(miller, B, kvec, v_grid, n_states):
     return w, u
 
 
+def _cache_path(miller, B, kvec, v_grid, n_states):
+    """File of a cached eigensystem under $SYNTH_EIGH_CACHE (unset: no cache), keyed by the inputs."""
+    root = os.environ.get("SYNTH_EIGH_CACHE")
+    if not root:
+        return None
+    h = hashlib.sha256()
+    for a in (np.asarray(miller, np.int64), np.asarray(B, float), np.asarray(kvec, float), np.asarray(v_grid, float)):
+        h.update(np.ascontiguousarray(a).tobytes())
+    h.update(str(n_states).encode())
+    return os.path.join(root, f"eigh_{h.hexdigest()[:24]}.npz")
+
+
 def lowest_states(miller: np.ndarray, B: np.ndarray, kvec, v_grid: np.ndarray, n_states: int):
     """Lowest ``n_states`` eigenpairs of the plane-wave Hamiltonian.
 
     Returns (energies [n_states] in Ha ascending, states [n_states][n_pw] complex128,
     coefficient rows in the order of ``miller``).  Each state's phase is fixed so
     that its largest-magnitude coefficient (first one on ties) is real positive.
+    With $SYNTH_EIGH_CACHE set, the result is stored there and later calls with the same
+    inputs load it instead of diagonalising again (e.g. profiler runs that should not
+    trace the eigensolver).
     """
     n_states = min(n_states, miller.shape[0])
+    path = _cache_path(miller, B, kvec, v_grid, n_states)
+    if path and os.path.exists(path):
+        with np.load(path) as d:
+            return d["w"], d["u"]
     if miller.shape[0] >= GPU_EIGH_MIN_PW and _gpu_present():
         w, u = _lowest_states_gpu(miller, B, kvec, v_grid, n_states)
     else:
@@ -81,7 +103,11 @@ def lowest_states(miller: np.ndarray, B: np.ndarray, kvec, v_grid: np.ndarray, n
     piv = np.argmax(np.abs(u), axis=1)
     ph = u[np.arange(u.shape[0]), piv]
     u *= (np.abs(ph) / ph)[:, None]
-    return w, np.ascontiguousarray(u)
+    u = np.ascontiguousarray(u)
+    if path:
+        os.makedirs(os.path.dirname(path), exist_ok=True)
+        np.savez(path, w=w, u=u)
+    return w, u
 
 
 def _gpu_present() -> bool:
