@@ -5,6 +5,7 @@
     python -m paper_1812_03717_amd.profiling traffic --kernel k_planes --fetch DB --write DB \
         --copy-fetch DB --copy-write DB --copy-bytes N [--out FILE.json]
     python -m paper_1812_03717_amd.profiling mfma --pmc DB --trace DB --kernel k_proj_dot [--kernel ...]
+    python -m paper_1812_03717_amd.profiling valu --pmc DB --trace DB --kernel k_planes_line [--alg-flops F]
 
 ``traffic`` scales the per-dispatch FETCH_SIZE and WRITE_SIZE averages (KiB) of
 one kernel by what the same counters read for a plain device copy of known
@@ -121,6 +122,33 @@ def mfma(pmc_db, trace_db, kernel_prefix):
             "busy_frac": busy / (avg_us * 1e-6 * CLOCK_HZ * N_SIMD)}
 
 
+VALU_COUNTERS = ("SQ_INSTS_VALU", "SQ_INSTS_VALU_ADD_F64", "SQ_INSTS_VALU_MUL_F64", "SQ_INSTS_VALU_FMA_F64",
+                 "SQ_INSTS_LDS", "SQ_INSTS_SALU", "SQ_WAVES")
+
+
+def valu(pmc_db, trace_db, kernel_prefix):
+    """Per-dispatch instruction counts of one kernel (per wavefront instruction issued) and the share
+    of the SIMDs' cycles its VALU instructions occupy: a wave64 VALU instruction takes 4 cycles of
+    a 16-lane SIMD, against the traced duration on all 1024 SIMDs at the 2.4 GHz peak clock."""
+    durs = [(calls, avg) for n, calls, tot, avg, pct in top(trace_db) if n.startswith(kernel_prefix)]
+    if not durs:
+        raise KeyError(f"{kernel_prefix} not in {trace_db}")
+    calls = sum(c for c, _ in durs)
+    avg_us = sum(c * a for c, a in durs) / calls
+    r = {"avg_us": avg_us}
+    for c in VALU_COUNTERS:
+        r[c] = _avg(pmc_db, kernel_prefix, c)[1]
+    f64 = r["SQ_INSTS_VALU_ADD_F64"] + r["SQ_INSTS_VALU_MUL_F64"] + r["SQ_INSTS_VALU_FMA_F64"]
+    cyc = avg_us * 1e-6 * CLOCK_HZ * N_SIMD
+    r["fp64_share"] = f64 / r["SQ_INSTS_VALU"]
+    r["valu_busy"] = 4.0 * r["SQ_INSTS_VALU"] / cyc
+    r["fp64_busy"] = 4.0 * f64 / cyc
+    # flops the FP64 instructions would do with all 64 lanes active (FMA = 2)
+    r["fp64_flops_full_lanes"] = 64.0 * (r["SQ_INSTS_VALU_ADD_F64"] + r["SQ_INSTS_VALU_MUL_F64"] +
+                                         2.0 * r["SQ_INSTS_VALU_FMA_F64"])
+    return r
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -139,6 +167,11 @@ def main():
     m.add_argument("--pmc", required=True)
     m.add_argument("--trace", required=True)
     m.add_argument("--kernel", action="append", required=True)
+    v = sub.add_parser("valu")
+    v.add_argument("--pmc", required=True)
+    v.add_argument("--trace", required=True)
+    v.add_argument("--kernel", required=True)
+    v.add_argument("--alg-flops", type=float, default=0.0, help="algorithmic flops per dispatch, if known")
     a = ap.parse_args()
     if a.cmd == "top":
         # rocpd reports durations in microseconds
@@ -156,6 +189,16 @@ def main():
             r = mfma(a.pmc, a.trace, k)
             print(f"{k:24s} {r['dispatches']:10d} {r['avg_us']:8.2f} {r['flops'] / 1e9:10.3f} {r['tflops']:8.2f} "
                   f"{r['frac_peak']:7.3f} {r['busy_frac']:9.3f}")
+    elif a.cmd == "valu":
+        r = valu(a.pmc, a.trace, a.kernel)
+        print(f"{a.kernel}: {r['avg_us']:.2f} us per dispatch, {r['SQ_WAVES']:.0f} waves")
+        for c in VALU_COUNTERS[:-1]:
+            print(f"  {c:24s} {r[c]:16.0f}")
+        print(f"  FP64 share of VALU instructions   {r['fp64_share']:.3f}")
+        print(f"  VALU issue / SIMD cycles          {r['valu_busy']:.3f}   (FP64 alone {r['fp64_busy']:.3f})")
+        print(f"  FP64 flops at full lanes          {r['fp64_flops_full_lanes'] / 1e9:.3f} GFLOP per dispatch")
+        if a.alg_flops:
+            print(f"  algorithmic / full-lane FP64 flops {a.alg_flops / r['fp64_flops_full_lanes']:.3f}")
     else:
         res = traffic(a.kernel, a.fetch, a.write, a.copy_fetch, a.copy_write, a.copy_bytes)
         res["kernel"] = a.name
