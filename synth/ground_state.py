@@ -106,7 +106,9 @@ def lowest_states(miller: np.ndarray, B: np.ndarray, kvec, v_grid: np.ndarray, n
     u = np.ascontiguousarray(u)
     if path:
         os.makedirs(os.path.dirname(path), exist_ok=True)
-        np.savez(path, w=w, u=u)
+        tmp = f"{path}.{os.getpid()}.tmp.npz"
+        np.savez(tmp, w=w, u=u)
+        os.replace(tmp, path)  # readers see a whole file or none
     return w, u
 
 
