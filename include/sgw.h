@@ -89,6 +89,20 @@ enum {
 enum { SGW_PC_NONE = 0, SGW_PC_TETER = 1, SGW_PC_LEARNED = 2 };
 /* initial guess of the per-shift solves (sgw_opts.guess); TAIL always warm-starts */
 enum { SGW_GUESS_ZERO = 0, SGW_GUESS_LEARNED = 1 };
+/*
+ * Kernel of the plane pass of the FP64 H.x (sgw_opts.fft_planes, sgw_ctx_set_fft_planes): the
+ * 2D inverse FFT of a plane, the potential and the 2D forward FFT (Sec. 2.1).
+ *   SGW_FFT_AUTO  the built-in choice: LINE where it applies, else PAIR, else LDS
+ *   SGW_FFT_LINE  one thread per row or column, the whole line in registers: lines of at most 48
+ *                 points whose sticks lie in the central half of the plane (|m| < N/4)
+ *   SGW_FFT_PAIR  two threads per line, split by real-space parity: lines of at most 72 points in
+ *                 the central half
+ *   SGW_FFT_LDS   the whole plane in LDS, radix stages exchanged through it: every grid
+ * A kernel that does not apply to a grid falls back to the built-in choice; the FP32 potential
+ * path of SGW_MIXED always takes the built-in choice (PAIR has no FP32 form).  All give H.x to
+ * rounding.
+ */
+enum { SGW_FFT_AUTO = 0, SGW_FFT_LINE = 1, SGW_FFT_PAIR = 2, SGW_FFT_LDS = 3 };
 
 typedef struct sgw_ctx sgw_ctx;
 typedef struct sgw_ham sgw_ham;
@@ -115,6 +129,16 @@ sgw_status sgw_ctx_destroy(sgw_ctx *ctx);
  * launches were charged with.  Unknown names: SGW_ERR_INVALID_ARG.
  */
 sgw_status sgw_ctx_set_profiling(sgw_ctx *ctx, const char *kernels);
+/*
+ * Plane-pass kernel of this context's H.x (SGW_FFT_*): used by sgw_apply_h and by solves whose
+ * sgw_opts.fft_planes is SGW_FFT_AUTO.  Default SGW_FFT_AUTO.  Other values: SGW_ERR_INVALID_ARG.
+ */
+sgw_status sgw_ctx_set_fft_planes(sgw_ctx *ctx, int fft_planes);
+/*
+ * The plane-pass kernel (SGW_FFT_LINE, SGW_FFT_PAIR or SGW_FFT_LDS) that H.x of `ham` runs under the
+ * context's setting, for `precision` SGW_FP64 or SGW_MIXED (the FP32 potential path); *out.
+ */
+sgw_status sgw_plane_kernel(sgw_ctx *ctx, const sgw_ham *ham, int precision, int32_t *out);
 /* Clears all accumulated kernel statistics. */
 sgw_status sgw_ctx_reset_stats(sgw_ctx *ctx);
 /*
@@ -212,6 +236,8 @@ typedef struct {
                                polls in a HIP graph and replays it (re-captured when the number
                                of active slots changes; ignored while kernel timing is on and
                                on the legacy default stream, which cannot be captured) */
+  int32_t fft_planes;       /* plane-pass kernel of the FP64 H.x (SGW_FFT_*); SGW_FFT_AUTO: the
+                               context's setting (sgw_ctx_set_fft_planes) */
 } sgw_opts;
 
 /* Fills *opts with the defaults. */

@@ -136,6 +136,22 @@ extern "C" sgw_status sgw_ctx_destroy(sgw_ctx *ctx) {
   return SGW_OK;
 }
 
+extern "C" sgw_status sgw_ctx_set_fft_planes(sgw_ctx *ctx, int fft_planes) {
+  if (!ctx) return fail(SGW_ERR_INVALID_ARG, "ctx is NULL");
+  if (fft_planes < SGW_FFT_AUTO || fft_planes > SGW_FFT_LDS)
+    return fail(SGW_ERR_INVALID_ARG, "sgw_ctx_set_fft_planes: unknown plane kernel");
+  ctx->fft_planes = fft_planes;
+  return SGW_OK;
+}
+
+extern "C" sgw_status sgw_plane_kernel(sgw_ctx *ctx, const sgw_ham *ham, int precision, int32_t *out) {
+  if (!ctx || !ham || !out) return fail(SGW_ERR_INVALID_ARG, "sgw_plane_kernel: NULL argument");
+  if (precision != SGW_FP64 && precision != SGW_MIXED)
+    return fail(SGW_ERR_INVALID_ARG, "sgw_plane_kernel: unknown precision mode");
+  *out = hx_plane_kernel(ctx, ham, precision == SGW_MIXED);
+  return SGW_OK;
+}
+
 extern "C" sgw_status sgw_ctx_set_profiling(sgw_ctx *ctx, const char *kernels) {
   if (!ctx) return fail(SGW_ERR_INVALID_ARG, "ctx is NULL");
   if (!kernels || !*kernels) {
@@ -531,6 +547,7 @@ extern "C" sgw_status sgw_opts_default(sgw_opts *o) {
   o->hist_iter = 0;
   o->mixed_switch = kMixedSwitch;
   o->graph = 0;
+  o->fft_planes = SGW_FFT_AUTO;
   return SGW_OK;
 }
 
@@ -577,6 +594,7 @@ sgw_opts resolve_opts(const sgw_opts *in) {
     o.hist_x = in->hist_x;
     o.hist_iter = in->hist_iter;
     o.graph = in->graph;
+    o.fft_planes = in->fft_planes;
     if (in->mixed_switch > 0) o.mixed_switch = in->mixed_switch;
   }
   return o;
@@ -658,6 +676,7 @@ static sgw_status validate_solve(sgw_ctx *ctx, const sgw_ham *h_kq, int n_occ, c
   SGW_CHECK(o.solver >= SGW_SOLVER_MULTISHIFT && o.solver <= SGW_SOLVER_TAIL, "sternheimer_solve: unknown solver");
   SGW_CHECK(o.precond >= SGW_PC_NONE && o.precond <= SGW_PC_LEARNED, "sternheimer_solve: unknown preconditioner");
   SGW_CHECK(o.guess == SGW_GUESS_ZERO || o.guess == SGW_GUESS_LEARNED, "sternheimer_solve: unknown initial guess");
+  SGW_CHECK(o.fft_planes >= SGW_FFT_AUTO && o.fft_planes <= SGW_FFT_LDS, "sternheimer_solve: unknown plane kernel");
   // preconditioners and guesses act in per-shift solves only: the per-shift solver, and the per-shift
   // phases of TAIL and MIXED (the multishift phase itself never uses them)
   SGW_CHECK(o.solver != SGW_SOLVER_MULTISHIFT || o.precision == SGW_MIXED ||
@@ -994,6 +1013,7 @@ static sgw_status run_solve(sgw_ctx *ctx, const sgw_problem &p, const sgw_opts &
   if (((uintptr_t)workspace) % kAlign != 0)
     return fail(SGW_ERR_WORKSPACE, "sternheimer_solve: workspace must be 256-byte aligned");
   SGW_HIP(hipSetDevice(ctx->device));
+  FftScope fft(ctx, o.fft_planes);
   sgw_status st;
   PsProblem P{p.h_kq, p.h_k, p.n_occ, (const double2 *)p.psi_occ_kq, p.n_band, (const double2 *)p.psi_v, p.eps_v,
               p.n_pert, p.dv_miller, p.n_omega, p.omega, p.eta, p.tol};
@@ -1155,6 +1175,7 @@ extern "C" sgw_status sternheimer_solve_batch(sgw_ctx *ctx, int n_sys, sgw_probl
       break;
     }
     if ((st = sgw_ctx_create(ctx->device, workers[w].stream, &workers[w].ctx)) != SGW_OK) break;
+    workers[w].ctx->fft_planes = ctx->fft_planes;
     workers[w].ctx->profile_mask = ctx->profile_mask;
     if (hipStreamWaitEvent(workers[w].stream, ready, 0) != hipSuccess)
       st = fail(SGW_ERR_HIP, "sternheimer_solve_batch: hipStreamWaitEvent failed");
@@ -1237,6 +1258,7 @@ extern "C" sgw_status sgw_autotune(sgw_ctx *ctx, const sgw_problem *problem, sgw
     *best = base;
     best->steps_per_sync = hit->second.steps_per_sync;
     best->graph = hit->second.graph;
+    if (base.fft_planes == SGW_FFT_AUTO) best->fft_planes = hit->second.fft_planes;
     if (tune_ms) *tune_ms = 0.0;
     return SGW_OK;
   }
@@ -1272,12 +1294,56 @@ extern "C" sgw_status sgw_autotune(sgw_ctx *ctx, const sgw_problem *problem, sgw
     st = fail(SGW_ERR_HIP, "sgw_autotune: stream setup failed");
   } else {
     st = sgw_ctx_create(ctx->device, tstream, &tctx);
+    if (st == SGW_OK) tctx->fft_planes = ctx->fft_planes;
+  }
+  // plane-pass kernel of the FP64 H.x: every kernel that applies to this grid, timed on a batch of
+  // vectors the size of a typical step (the slots of up to 512 pairs), zeros as input
+  int fft_best = base.fft_planes;
+  if (st >= 0 && base.fft_planes == SGW_FFT_AUTO) {
+    const sgw_ham *h = p.h_kq;
+    const int nv = (int)std::min<long>(512, std::max<long>(1, (long)p.n_band * p.n_pert));
+    const size_t vb = sizeof(double2) * (size_t)nv * h->n_pw;
+    const size_t tb = sizeof(double2) * (size_t)nv * h->n[2] * h->n_stick;
+    void *hb = nullptr;
+    if (hipMalloc(&hb, 2 * vb + tb) != hipSuccess) {
+      st = fail(SGW_ERR_HIP, "sgw_autotune: H.x buffers");
+    } else if (hipMemsetAsync(hb, 0, 2 * vb, tstream) != hipSuccess) {
+      st = fail(SGW_ERR_HIP, "sgw_autotune: H.x buffers");
+    } else {
+      double fft_ms = 1e300;
+      const double2 *x = (const double2 *)hb;
+      double2 *y = (double2 *)((char *)hb + vb);
+      void *t = (char *)hb + 2 * vb;
+      for (int v = SGW_FFT_LINE; v <= SGW_FFT_LDS && st >= 0; ++v) {
+        FftScope fs(tctx, v);
+        if (hx_plane_kernel(tctx, h, false) != v) continue;  // does not apply here
+        double ms = 0;
+        for (int rep = 0; rep < 4 && st >= 0; ++rep) {  // the first run is not timed
+          const auto t0 = std::chrono::steady_clock::now();
+          st = hx_batch(tctx, h, nv, contiguous(x, h->n_pw), y, h->n_pw, t);
+          if (st >= 0 && hipStreamSynchronize(tstream) != hipSuccess)
+            st = fail(SGW_ERR_HIP, "sgw_autotune: H.x timing");
+          if (rep > 0)
+            ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        }
+        if (st >= 0 && ms < fft_ms) {
+          fft_ms = ms;
+          fft_best = v;
+        }
+      }
+    }
+    if (hb) {
+      hipStreamSynchronize(tstream);
+      hipFree(hb);
+    }
   }
   double best_ms = 1e300;
   sgw_opts winner = base;
+  winner.fft_planes = fft_best;
   const int steps[] = {4, 8, 16};
   for (int warm = 1, c = 0; c < 6 && st >= 0; ++c) {
     sgw_opts o = base;
+    o.fft_planes = fft_best;
     o.steps_per_sync = steps[c % 3];
     o.graph = c / 3;
     if (warm) {  // first launch of every kernel: not timed
@@ -1303,6 +1369,7 @@ extern "C" sgw_status sgw_autotune(sgw_ctx *ctx, const sgw_problem *problem, sgw
   *best = base;
   best->steps_per_sync = winner.steps_per_sync;
   best->graph = winner.graph;
+  best->fft_planes = winner.fft_planes;
   ctx->tuned[key] = *best;
   if (tune_ms)
     *tune_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();

@@ -451,7 +451,7 @@ sgw_status launch_sticks(sgw_ctx *ctx, const sgw_ham *h, int n_vec, VecSrc x, do
       return SGW_OK;
     }
   }
-  if constexpr (pair_planes_fit<C2, N2, N2>()) {
+  if constexpr (pair_planes_fit<C2, N2, N2>() && !line_planes_fit<C2, N2, N2>()) {
     if (h->m2_lo >= -N2 / 4 && h->m2_hi < N2 / 4) {
       const int lg = (h->n_stick + kStickLineSticks - 1) / kStickLineSticks;
       if (inverse) {
@@ -488,6 +488,21 @@ sgw_status launch_sticks(sgw_ctx *ctx, const sgw_ham *h, int n_vec, VecSrc x, do
   return SGW_OK;
 }
 
+// The plane kernel of H.x for this grid and precision: the one the context asks for if it applies,
+// else whole lines in registers, else two threads per line (FP64), else the whole plane in LDS.
+// Lines in registers need every stick in the central half of the plane (a sphere that the grid
+// holds twice over has them there).
+template <class C2, int N0, int N1>
+int plane_kernel(const sgw_ctx *ctx, const sgw_ham *h) {
+  const bool win = line_window_ok(h->n, h->m0_lo, h->n_row, h->m1_lo, h->m1_hi);
+  const bool line = win && line_planes_fit<C2, N0, N1>(), pair = win && pair_planes_fit<C2, N0, N1>();
+  const int want = ctx->fft_active ? ctx->fft_active : ctx->fft_planes;
+  if (want == SGW_FFT_LINE && line) return SGW_FFT_LINE;
+  if (want == SGW_FFT_PAIR && pair) return SGW_FFT_PAIR;
+  if (want == SGW_FFT_LDS) return SGW_FFT_LDS;
+  return line ? SGW_FFT_LINE : pair ? SGW_FFT_PAIR : SGW_FFT_LDS;
+}
+
 template <class C2, int N0, int N1>
 sgw_status launch_planes(sgw_ctx *ctx, const sgw_ham *h, int n_vec, C2 *tbuf) {
   const long blocks = (long)n_vec * h->n[2];
@@ -500,29 +515,23 @@ sgw_status launch_planes(sgw_ctx *ctx, const sgw_ham *h, int n_vec, C2 *tbuf) {
   const double per_plane = 2.0 * (h->n_row * 5.0 * N1 * std::log2((double)N1) + N1 * 5.0 * N0 * std::log2((double)N0)) +
                            2.0 * N0 * N1;
   timing_begin(ctx, K_PLANES, bytes, per_plane * h->n[2] * n_vec, &tm);
-  bool launched = false;
+  const int use = plane_kernel<C2, N0, N1>(ctx, h);
   if constexpr (line_planes_fit<C2, N0, N1>()) {
-    // whole lines in registers when every stick lies in the central half of the plane (a sphere
-    // that the grid holds twice over does)
-    if (line_window_ok(h->n, h->m0_lo, h->n_row, h->m1_lo, h->m1_hi)) {
+    if (use == SGW_FFT_LINE) {
       constexpr int P = line_plane_count<C2, N1>();
       const long n_planes = (long)n_vec * h->n[2];
       hipLaunchKernelGGL((k_planes_line<C2, N0, N1, P>), dim3((n_planes + P - 1) / P),
                          dim3(line_plane_threads<P, N1>()), 0, ctx->stream, tbuf, n_planes, h->n[2], h->n_stick,
                          h->d_rows, h->d_stick_ij, h->m0_lo, h->n_row, potential<C2>(h));
-      launched = true;
     }
   }
   if constexpr (pair_planes_fit<C2, N0, N1>()) {
-    // lines too long for one thread: two threads per line, split by real-space parity
-    if (line_window_ok(h->n, h->m0_lo, h->n_row, h->m1_lo, h->m1_hi)) {
+    if (use == SGW_FFT_PAIR)
       hipLaunchKernelGGL((k_planes_pair<N0, N1>), dim3(blocks), dim3(pair_plane_threads<N0, N1>()), 0, ctx->stream,
                          (double2 *)tbuf, h->n[2], h->n_stick, h->d_rows, h->d_stick_ij, h->m0_lo, h->n_row,
                          h->d_vt);
-      launched = true;
-    }
   }
-  if (!launched)
+  if (use == SGW_FFT_LDS)
     hipLaunchKernelGGL((k_planes<C2, N0, N1>), dim3(blocks), dim3(plane_threads<N0, N1>()), 0, ctx->stream, tbuf,
                        h->n[2], h->n_stick, h->d_rows, h->m0_lo, h->n_row, potential<C2>(h), twiddles<C2>(h, 0),
                        twiddles<C2>(h, 1));
@@ -571,6 +580,29 @@ sgw_status dispatch_planes(sgw_ctx *ctx, const sgw_ham *h, int n_vec, C2 *tbuf) 
 }
 
 }  // namespace
+
+template <class C2, int N0>
+int plane_kernel_n1(const sgw_ctx *ctx, const sgw_ham *h) {
+  switch (h->n[1]) {
+#define SGW_CASE(N) \
+  case N:           \
+    return plane_kernel<C2, N0, N>(ctx, h);
+    SGW_GRID_LIST(SGW_CASE)
+#undef SGW_CASE
+  }
+  return SGW_FFT_LDS;
+}
+
+int hx_plane_kernel(const sgw_ctx *ctx, const sgw_ham *h, bool fp32) {
+  switch (h->n[0]) {
+#define SGW_CASE(N) \
+  case N:           \
+    return fp32 ? plane_kernel_n1<float2, N>(ctx, h) : plane_kernel_n1<double2, N>(ctx, h);
+    SGW_GRID_LIST(SGW_CASE)
+#undef SGW_CASE
+  }
+  return SGW_FFT_LDS;
+}
 
 bool hx_grid_supported(int n) {
   switch (n) {

@@ -421,8 +421,8 @@ void k_planes_line(C2 *__restrict__ T, long n_planes, int n2, int n_stick, const
   }
 }
 
-// Pair-of-threads variant for FP64 planes whose lines do not fit one thread's registers (64 and 72
-// points), under the same central-half window.  With window input X[k] (k < N/4 or k >= 3N/4, i.e.
+// Pair-of-threads variant for FP64 planes, built for lines that do not fit one thread's registers
+// (64 and 72 points) and usable at every size, under the same central-half window.  With window input X[k] (k < N/4 or k >= 3N/4, i.e.
 // one k for each residue j = k mod N/2), the inverse line splits by the parity r of the real-space
 // index n = 2m + r into two half-length transforms:
 //   x[2m + r] = sum_j X[k_j] w_N^(r k_j) w_{N/2}^(m j),        k_j = j (j < N/4), j + N/2 (else)
@@ -446,7 +446,7 @@ __device__ __forceinline__ void half_line_dft(C2 *x) {
   }
 }
 template <class C2, int N0, int N1> constexpr bool pair_planes_fit() {
-  return sizeof(C2) == 16 && !line_planes_fit<C2, N0, N1>() && N0 % 4 == 0 && N1 % 4 == 0 && N0 <= 72 && N1 <= 72;
+  return sizeof(C2) == 16 && N0 % 4 == 0 && N1 % 4 == 0 && N0 <= 72 && N1 <= 72;
 }
 // threads: one per (parity, column) and at least one per (parity, window row)
 template <int N0, int N1> constexpr int pair_plane_threads() {

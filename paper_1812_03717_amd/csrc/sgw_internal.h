@@ -67,6 +67,8 @@ struct sgw_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
   unsigned profile_mask = 0;        // bit k: time launches of kernel k
+  int fft_planes = 0;               // plane-pass kernel of H.x (SGW_FFT_*), the context's setting
+  int fft_active = 0;               // the same for the solve in progress (0: fft_planes)
   sgw::KernelStat stats[sgw::K_COUNT];
   std::vector<sgw::PendingTiming> pending;
   std::vector<hipEvent_t> event_pool;
@@ -147,6 +149,17 @@ sgw_status sync(sgw_ctx *ctx);
 sgw_status hx_batch(sgw_ctx *ctx, const sgw_ham *h, int n_vec, VecSrc x, double2 *y, long ldy, void *tbuf,
                     bool fp32 = false);
 bool hx_grid_supported(int n);
+// the plane-pass kernel (SGW_FFT_LINE / PAIR / LDS) that H.x of `h` uses under ctx's setting
+int hx_plane_kernel(const sgw_ctx *ctx, const sgw_ham *h, bool fp32);
+// the solve in progress uses plane kernel `v` (0: the context's setting) while the scope lives
+struct FftScope {
+  sgw_ctx *ctx;
+  int saved;
+  FftScope(sgw_ctx *c, int v) : ctx(c), saved(c->fft_active) { c->fft_active = v; }
+  ~FftScope() { ctx->fft_active = saved; }
+  FftScope(const FftScope &) = delete;
+  FftScope &operator=(const FftScope &) = delete;
+};
 
 // Projector pieces (internal order, FP64 MFMA).  The overlaps are produced as
 // partial sums over plane-wave chunks: cp[chunk][a][i] for chunk < n_chunks,

@@ -24,11 +24,13 @@ SOLVER_MULTISHIFT, SOLVER_PER_SHIFT, SOLVER_TAIL = 0, 1, 2
 FP64, MIXED = 0, 1
 PC_NONE, PC_TETER, PC_LEARNED = 0, 1, 2
 GUESS_ZERO, GUESS_LEARNED = 0, 1
+FFT_AUTO, FFT_LINE, FFT_PAIR, FFT_LDS = 0, 1, 2, 3
 
 INFO_DTYPE = np.dtype([("iters", "<i4"), ("flags", "<i4"), ("relres", "<f8"), ("occ_leak", "<f8")])
 
 EXPORTED = [
     "sgw_last_error", "sgw_version", "sgw_ctx_create", "sgw_ctx_destroy", "sgw_ctx_set_profiling",
+    "sgw_ctx_set_fft_planes", "sgw_plane_kernel",
     "sgw_ctx_reset_stats", "sgw_kernel_stats", "sgw_ham_create", "sgw_ham_destroy", "sgw_ham_npw",
     "sgw_apply_h", "sgw_apply_projector", "sgw_build_rhs", "sgw_opts_default",
     "sternheimer_workspace_size", "sternheimer_solve", "sgw_mlp_num_params", "sgw_mlp_create",
@@ -55,7 +57,8 @@ class sgw_opts(C.Structure):
                 ("steps_per_sync", C.c_int32), ("solver", C.c_int32), ("precond", C.c_int32),
                 ("guess", C.c_int32), ("tail_iter", C.c_int32), ("ps_max_iter", C.c_int32),
                 ("ps_slots", C.c_int32), ("mlp", C.c_void_p), ("hist_r", C.c_void_p), ("hist_x", C.c_void_p),
-                ("hist_iter", C.c_int32), ("mixed_switch", C.c_double), ("graph", C.c_int32)]
+                ("hist_iter", C.c_int32), ("mixed_switch", C.c_double), ("graph", C.c_int32),
+                ("fft_planes", C.c_int32)]
 
 
 class sgw_problem(C.Structure):
@@ -85,6 +88,8 @@ def load_library(path: str = LIB_PATH):
         "sgw_ctx_create": [C.c_int, vp, C.POINTER(vp)],
         "sgw_ctx_destroy": [vp],
         "sgw_ctx_set_profiling": [vp, C.c_char_p],
+        "sgw_ctx_set_fft_planes": [vp, C.c_int],
+        "sgw_plane_kernel": [vp, vp, C.c_int, C.POINTER(i32)],
         "sgw_ctx_reset_stats": [vp],
         "sgw_kernel_stats": [vp, C.c_char_p, C.POINTER(C.c_int64), C.POINTER(dbl), C.POINTER(dbl), C.POINTER(dbl)],
         "sgw_ham_create": [vp, C.POINTER(sgw_ham_desc), C.POINTER(vp)],
@@ -172,6 +177,17 @@ class sgw_ctx_create:
     def set_profiling(self, kernels):
         """kernels: comma-separated kernel names, "all", or None."""
         _check(load_library().sgw_ctx_set_profiling(self.handle, kernels.encode() if kernels else None))
+
+    def set_fft_planes(self, kernel):
+        """Plane-pass kernel of H.x: FFT_AUTO, FFT_LINE, FFT_PAIR or FFT_LDS."""
+        _check(load_library().sgw_ctx_set_fft_planes(self.handle, int(kernel)))
+
+    def plane_kernel(self, ham, precision=0):
+        """The plane-pass kernel H.x of `ham` runs under this context's setting (FFT_LINE/PAIR/LDS)."""
+        out = C.c_int32()
+        _check(load_library().sgw_plane_kernel(self.handle, ham.handle if hasattr(ham, "handle") else ham,
+                                               int(precision), C.byref(out)))
+        return out.value
 
     def reset_stats(self):
         _check(load_library().sgw_ctx_reset_stats(self.handle))

@@ -109,11 +109,18 @@ def test_autotune(ctx, systems, singles):
     b = _batch(ctx, devs)
     ms = b.autotune(0)
     o = b.items[0]["problem"].opts
-    print("autotune", ps[0].name, "ms", ms, "steps_per_sync", o.steps_per_sync, "graph", o.graph, flush=True)
+    print("autotune", ps[0].name, "ms", ms, "steps_per_sync", o.steps_per_sync, "graph", o.graph,
+          "plane kernel", o.fft_planes, flush=True)
     assert ms > 0 and o.steps_per_sync in (4, 8, 16) and o.graph in (0, 1)
+    assert o.fft_planes in (sgw.FFT_LINE, sgw.FFT_PAIR, sgw.FFT_LDS)
     assert b.autotune(0) == 0.0  # cached for this system class
     assert b.solve(n_workers=2) == sgw.SGW_OK
-    assert np.array_equal(b.items[0]["dpsi"].cpu().numpy(), singles[0][0])
+    # the batch reproduces the one-system solve under the same (tuned) options bit for bit
+    st, dpsi, info = devs[0].solve(opts=o)
+    assert st == sgw.SGW_OK
+    assert np.array_equal(b.items[0]["dpsi"].cpu().numpy(), dpsi.cpu().numpy())
+    if o.fft_planes == sgw.FFT_LINE:  # the built-in choice at these grids: also equal to the untuned solve
+        assert np.array_equal(b.items[0]["dpsi"].cpu().numpy(), singles[0][0])
 
 
 def test_batch_rejects_bad_input(ctx, systems):

@@ -73,6 +73,65 @@ def test_apply_h_matches_dense(ctx, name):
         assert err <= 1e-12
 
 
+@pytest.mark.parametrize("name", ["si2", "fcc1_q", "fcc1_g64", "fcc1_g72", "fcc312_g72", "fcc131_g72"])
+def test_apply_h_each_plane_kernel(ctx, name):
+    """Every plane-pass kernel that applies to the grid, forced through sgw_ctx_set_fft_planes, gives
+    H.x to rounding; the whole-plane LDS kernel applies everywhere, the two-thread kernel wherever the
+    sticks lie in the central half of the plane (all these grids but si2's), the whole-line kernel
+    there up to 48 points."""
+    from paper_1812_03717_amd import sgw
+    p = PROBLEMS[name]()
+    d = _dev(ctx, p)
+    rng = np.random.default_rng(5)
+    n = p.miller_kq.shape[0]
+    x = rng.standard_normal((6, n)) + 1j * rng.standard_normal((6, n))
+    yr = x @ so.hamiltonian(p.miller_kq, p.B, p.kvec + p.qvec, p.v_grid).T
+    ran = []
+    try:
+        for v in (sgw.FFT_LINE, sgw.FFT_PAIR, sgw.FFT_LDS):
+            ctx.set_fft_planes(v)
+            k = ctx.plane_kernel(d.h_kq)
+            y = sgw.sgw_apply_h(ctx, d.h_kq, torch.from_numpy(x).to(ctx.device)).cpu().numpy()
+            err = np.abs(y - yr).max() / np.abs(yr).max()
+            print(name, "asked", v, "ran", k, "rel err", err, flush=True)
+            assert err <= 1e-12
+            ran.append(k)
+    finally:
+        ctx.set_fft_planes(sgw.FFT_AUTO)
+    assert ran[2] == sgw.FFT_LDS
+    assert ran[1] == (sgw.FFT_LDS if name == "si2" else sgw.FFT_PAIR)
+    line_fits = name != "si2" and max(p.v_grid.shape[:2]) <= 48
+    assert ran[0] == (sgw.FFT_LINE if line_fits else sgw.FFT_PAIR if name != "si2" else sgw.FFT_LDS)
+
+
+@pytest.mark.parametrize("kernel", ["pair", "lds"])
+def test_solve_each_plane_kernel(ctx, kernel):
+    """The solver with its plane kernel forced through sgw_opts.fft_planes (24^3, where the built-in
+    choice is the whole-line kernel), against the oracle at the bar of test_solve_matches_oracle."""
+    from paper_1812_03717_amd import sgw
+    p = PROBLEMS["fcc1_q"]()
+    d = _dev(ctx, p)
+    v = {"pair": sgw.FFT_PAIR, "lds": sgw.FFT_LDS}[kernel]
+    opts = sgw.sgw_opts_default(fft_planes=v)
+    assert ctx.plane_kernel(d.h_kq) == sgw.FFT_LINE
+    pairs = [(b, q) for b in range(p.n_band) for q in range(p.n_pert)]
+    setup, xs, bs = _oracle_solutions(p, pairs)
+    kap = max(_kappa(setup, p, b).max() for b in range(p.n_band))
+    tol = min(p.tol, 1e-8 / (2.0 * kap))
+    st, dpsi, info = d.solve(tol=tol, opts=opts)
+    assert st == sgw.SGW_OK, sgw.load_library().sgw_last_error()
+    dpsi = dpsi.cpu().numpy()
+    worst = 0.0
+    for i, (b, q) in enumerate(pairs):
+        for j in range(p.n_omega):
+            err = np.linalg.norm(dpsi[b, q, j] - xs[i, j]) / np.linalg.norm(xs[i, j])
+            worst = max(worst, err)
+    print(kernel, "max rel err vs oracle", worst, flush=True)
+    assert worst <= 1e-8
+    with pytest.raises(sgw.SgwError):
+        d.solve(tol=tol, opts=sgw.sgw_opts_default(fft_planes=7))
+
+
 def test_apply_h_si64_shape_sampled(ctx):
     """72^3 grid at the si64 size (64-atom cubic cell, ~16,000 plane waves, sticks filling most of the
     central-half window): 48 sampled rows of H, from the oracle's definition, against the FP64 H.x of
