@@ -234,8 +234,8 @@ def main():
         print(json.dumps({"copy_calibration_bytes_each_way": n, "copies": 5}))
         return
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(the (band, perturbation) pairs would be sharded across GPUs; see DESIGN.md)", file=sys.stderr)
+        print(f"bench.py: the library runs on one GPU; --gpus {args.gpus} is not supported "
+              "(across GPUs each would take a slice of the (band, perturbation) pair queue)", file=sys.stderr)
         sys.exit(2)
 
     def log(msg):

@@ -50,7 +50,7 @@ typedef enum {
   SGW_ERR_INVALID_ARG = -1,
   SGW_ERR_HIP = -2,           /* a HIP runtime call failed */
   SGW_ERR_WORKSPACE = -3,     /* workspace missing or too small */
-  SGW_ERR_UNSUPPORTED = -4    /* valid request this build does not implement (e.g. grid size) */
+  SGW_ERR_UNSUPPORTED = -4    /* valid request the library does not implement (e.g. grid size) */
 } sgw_status;
 
 /* per-solve flags (sgw_solve_info.flags, bitwise) */

@@ -2,7 +2,7 @@
 library's kernels from residual histories of per-shift solves on small cells,
 then used as the preconditioner of per-shift solves on held-out cells (other
 seeds and sizes), against the Teter diagonal (the fallback) on the same
-systems.  Every solve is judged by its true FP64 residual."""
+systems.  Every solve is decided by its true FP64 residual."""
 import numpy as np
 import pytest
 
