@@ -22,6 +22,7 @@ from __future__ import annotations
 
 import argparse
 import collections
+import functools
 import hashlib
 import json
 import os
@@ -72,8 +73,9 @@ def top(db: str):
     return [(short_name(n), calls, tot, avg, pct) for n, calls, tot, avg, pct in rows]
 
 
+@functools.lru_cache(maxsize=None)
 def pmc(db: str):
-    """{(kernel, counter): (dispatches, average value)}"""
+    """{(kernel, counter): (dispatches, average value)} (read once per database)"""
     c = sqlite3.connect(db)
     agg = collections.defaultdict(lambda: [0, 0.0])
     for name, cn, val in c.execute("select kernel_name, counter_name, value from counters_collection"):
