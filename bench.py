@@ -52,7 +52,7 @@ KERNELS = ["hx_sticks_inv", "hx_planes", "hx_sticks_fwd", "proj_dot", "proj_appl
            "tridiag", "combine", "residual", "permute"]
 
 
-def roofline(kernel, ks, workload):
+def roofline(kernel, ks, workload, default_launch=True):
     """Roofline entry of the dominant kernel from the library's event timing.
 
     The library charges every launch with its algorithmic bytes (HBM data the
@@ -61,7 +61,8 @@ def roofline(kernel, ks, workload):
     is bound by FP64 arithmetic, so its entry is "alu" against the FP64 vector
     peak; HBM figures are given beside it.  ``traffic`` comes from the committed
     rocprofv3 FETCH_SIZE/WRITE_SIZE summary, only while the kernel's sources
-    still hash to the value recorded with those counters.
+    still hash to the value recorded with those counters and the launches have
+    the size they had there (``default_launch``: no --slots override).
     """
     from paper_1812_03717_amd import profiling
     n = max(ks["launches"], 1)
@@ -71,7 +72,7 @@ def roofline(kernel, ks, workload):
     gbs = bytes_per_launch / avg_s / 1e9
     traffic = None
     tfile = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.json")
-    if os.path.exists(tfile):
+    if default_launch and os.path.exists(tfile):
         with open(tfile) as fh:
             t = json.load(fh)
         if t.get("source_hash") == profiling.source_hash(kernel):
@@ -329,7 +330,7 @@ def main():
         p_el, p_ok, p_inf = timed(plain, dominant)
         report("timed (plain fp64)", p_el, p_ok, p_inf)
     ks = ctx.kernel_stats(dominant)
-    roof = roofline(dominant, ks, args.workload)
+    roof = roofline(dominant, ks, args.workload, default_launch=not args.slots)
     roof["leg"] = "plain FP64 timed steps"
     value = n_ok / elapsed
     plain_value = p_ok / p_el
