@@ -238,6 +238,11 @@ typedef struct {
                                on the legacy default stream, which cannot be captured) */
   int32_t fft_planes;       /* plane-pass kernel of the FP64 H.x (SGW_FFT_*); SGW_FFT_AUTO: the
                                context's setting (sgw_ctx_set_fft_planes) */
+  int32_t basis_blocks;     /* Krylov bases of the multishift slots.  0: each slot holds max_iter + 1
+                               vectors.  > 0: the slots draw their vectors from a pool of this many
+                               blocks of 32 (at least (max_iter + 1) / 32 rounded up) as they grow; a
+                               pair that cannot grow waits, and when no running pair can grow the
+                               least advanced one is restarted later.  Results do not change. */
 } sgw_opts;
 
 /* Fills *opts with the defaults. */

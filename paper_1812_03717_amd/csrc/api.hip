@@ -7,6 +7,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <deque>
 #include <map>
 #include <mutex>
 #include <numeric>
@@ -548,20 +549,26 @@ extern "C" sgw_status sgw_opts_default(sgw_opts *o) {
   o->mixed_switch = kMixedSwitch;
   o->graph = 0;
   o->fft_planes = SGW_FFT_AUTO;
+  o->basis_blocks = 0;
   return SGW_OK;
 }
 
 namespace {
 
 constexpr size_t kAlign = 256;
+// pooled Krylov basis: 32 vectors per block
+constexpr int kBasisBlockShift = 5;
 // workspace budget that sizes the automatic slot count: a third of one MI355X's 288 GB of HBM
 constexpr double kDefaultBudget = 96.0 * (1ull << 30);
 
 struct Layout {
   int S = 0, F = 0, kmax = 0, M = 8;
   size_t psi, omega, epsb, dvm, pair, kcur, status, eps, alpha, beta, rho, res, maxres, conv, bvec, basis;
-  size_t l_active, l_fill, l_fillpairs, l_final, Y, Y2, C, T, ycoef, cp, X, AX, bad;
+  size_t l_active, l_fill, l_fillpairs, l_final, Y, Y2, C, T, ycoef, cp, X, AX, bad, btab = 0;
   long c_rows = 0;
+  // pooled Krylov basis: blocks of 2^bshift vectors, nbmax per slot at most, nblk in the pool
+  bool pooled = false;
+  int bshift = 0, nbmax = 0, nblk = 0;
   size_t total = 0;
 };
 
@@ -595,6 +602,7 @@ sgw_opts resolve_opts(const sgw_opts *in) {
     o.hist_iter = in->hist_iter;
     o.graph = in->graph;
     o.fft_planes = in->fft_planes;
+    o.basis_blocks = in->basis_blocks;
     if (in->mixed_switch > 0) o.mixed_switch = in->mixed_switch;
   }
   return o;
@@ -616,6 +624,14 @@ Layout make_layout(const sgw_ham *h, int n_occ, int n_band, int n_pert, int n_om
     S = (int)std::max(1.0, (kDefaultBudget - fixed) / per_slot);
     S = std::min(S, 4096);
   }
+  // Pooled basis (the caller sizes the pool with basis_blocks): the slots draw their Krylov vectors
+  // from a pool in blocks of 2^bshift as they grow, instead of each holding max_iter + 1
+  L.bshift = kBasisBlockShift;
+  L.nbmax = (L.kmax + 1 + (1 << L.bshift) - 1) >> L.bshift;
+  if (o.basis_blocks > 0) {
+    L.pooled = true;
+    L.nblk = o.basis_blocks;
+  }
   L.S = std::max(1, std::min(S, std::max(n_pairs, 1)));
   const long nfv = (long)L.F * n_omega;
   const long tv = std::max<long>(L.S, nfv);
@@ -635,7 +651,12 @@ Layout make_layout(const sgw_ham *h, int n_occ, int n_band, int n_pert, int n_om
   L.maxres = take(off, 8ul * L.S);
   L.conv = take(off, 4ul * L.S * n_omega);
   L.bvec = take(off, 16ul * L.S * npw);
-  L.basis = take(off, 16ul * L.S * (L.kmax + 1) * npw);
+  if (L.pooled) {
+    L.basis = take(off, 16ul * (size_t)L.nblk * ((size_t)1 << L.bshift) * npw);
+    L.btab = take(off, 4ul * L.S * L.nbmax);
+  } else {
+    L.basis = take(off, 16ul * L.S * (L.kmax + 1) * npw);
+  }
   L.l_active = take(off, 4ul * L.S);
   L.l_fill = take(off, 4ul * L.S);
   L.l_fillpairs = take(off, 4ul * L.S);
@@ -677,6 +698,9 @@ static sgw_status validate_solve(sgw_ctx *ctx, const sgw_ham *h_kq, int n_occ, c
   SGW_CHECK(o.precond >= SGW_PC_NONE && o.precond <= SGW_PC_LEARNED, "sternheimer_solve: unknown preconditioner");
   SGW_CHECK(o.guess == SGW_GUESS_ZERO || o.guess == SGW_GUESS_LEARNED, "sternheimer_solve: unknown initial guess");
   SGW_CHECK(o.fft_planes >= SGW_FFT_AUTO && o.fft_planes <= SGW_FFT_LDS, "sternheimer_solve: unknown plane kernel");
+  SGW_CHECK(o.basis_blocks == 0 ||
+                (o.basis_blocks > 0 && ((long)o.basis_blocks << kBasisBlockShift) >= (long)o.max_iter + 1),
+            "sternheimer_solve: basis_blocks must hold one pair's max_iter + 1 Krylov vectors");
   // preconditioners and guesses act in per-shift solves only: the per-shift solver, and the per-shift
   // phases of TAIL and MIXED (the multishift phase itself never uses them)
   SGW_CHECK(o.solver != SGW_SOLVER_MULTISHIFT || o.precision == SGW_MIXED ||
@@ -808,6 +832,12 @@ static sgw_status multishift_solve(sgw_ctx *ctx, const sgw_ham *h_kq, int n_occ,
   Sx.omega = (double *)(W + L.omega);
   Sx.eta = eta;
   Sx.alpha = o.alpha_pv;
+  int32_t *d_btab = L.pooled ? (int32_t *)(W + L.btab) : nullptr;
+  if (L.pooled) {
+    Sx.btab = d_btab;
+    Sx.nbmax = L.nbmax;
+    Sx.bshift = L.bshift;
+  }
   // Mixed precision: a matvec error at step k enters the shifted solutions weighted by their step-k
   // coefficients, which shrink with the residual (inexact Krylov theory); so a slot switches to
   // FP32 potential matvecs (~3e-8 relative error) once all its shifts' estimates are below
@@ -832,7 +862,10 @@ static sgw_status multishift_solve(sgw_ctx *ctx, const sgw_ham *h_kq, int n_occ,
   int *d_bad = (int *)(W + L.bad);
 
   // pinned staging: status[S] | active[S] | fill[S] | fillpairs[S] | final[S] | bad[16] | maxres[S]
-  if ((st = ensure_pinned(ctx, sizeof(int32_t) * (5ul * S + 16) + sizeof(double) * (S + 1))) != SGW_OK) return st;
+  // | block table[S][nbmax] (pooled basis)
+  const size_t ntab = L.pooled ? (size_t)S * L.nbmax : 0;
+  if ((st = ensure_pinned(ctx, sizeof(int32_t) * (5ul * S + 16 + ntab) + sizeof(double) * (S + 1))) != SGW_OK)
+    return st;
   int32_t *p_status = (int32_t *)ctx->pinned;
   int32_t *p_active = p_status + S;
   int32_t *p_fill = p_active + S;
@@ -840,6 +873,7 @@ static sgw_status multishift_solve(sgw_ctx *ctx, const sgw_ham *h_kq, int n_occ,
   int32_t *p_final = p_fillpairs + S;
   int32_t *p_bad = p_final + S;
   double *p_maxres = (double *)(((uintptr_t)(p_bad + 16) + 7) & ~(uintptr_t)7);
+  int32_t *p_btab = (int32_t *)(p_maxres + S);
   std::vector<char> slot_fp32(S, 0);
 
   // parameters
@@ -858,13 +892,42 @@ static sgw_status multishift_solve(sgw_ctx *ctx, const sgw_ham *h_kq, int n_occ,
   size_t next = 0;
   std::vector<int> slot_pair(S, -1), free_slots, active, done;
   for (int s = S - 1; s >= 0; --s) free_slots.push_back(s);
-  const VecSrc cur{Sx.basis, npw, d_active, Sx.kcur, Sx.slot_stride};
+  const VecSrc cur{Sx.basis, npw, d_active, Sx.kcur, Sx.slot_stride, Sx.btab, Sx.nbmax, Sx.bshift};
   const VecSrc xsrc = contiguous(X, npw);
   StepGraph graph;
   size_t finalized = 0;
   double ksum = 0;
   long kcount = 0;
   std::vector<int32_t> kc_host(S);
+
+  // Pooled basis: block table (host copy uploaded before the launches that read it), blocks owned
+  // per slot, free blocks; pairs restarted after an eviction wait in requeue.  kcn: a slot's
+  // Krylov dimension as of the last poll (0 when filled).
+  std::vector<int32_t> htab;
+  std::vector<int> nown, free_blk, kcn;
+  std::deque<int> requeue;
+  bool tab_dirty = false, stalled_prev = false;
+  if (L.pooled) {
+    htab.assign(ntab, 0);
+    nown.assign(S, 0);
+    kcn.assign(S, 0);
+    for (int b = L.nblk - 1; b >= 0; --b) free_blk.push_back(b);
+  }
+  // maps Krylov vectors 0..kneed of slot s; false (blocks taken so far kept) when the pool is empty
+  auto grow = [&](int s, int kneed) -> bool {
+    const int need = (kneed >> L.bshift) + 1;
+    while (nown[s] < need) {
+      if (free_blk.empty()) return false;
+      htab[(size_t)s * L.nbmax + nown[s]++] = free_blk.back();
+      free_blk.pop_back();
+      tab_dirty = true;
+    }
+    return true;
+  };
+  auto release = [&](int s) {
+    for (int i = 0; i < nown[s]; ++i) free_blk.push_back(htab[(size_t)s * L.nbmax + i]);
+    nown[s] = 0;
+  };
 
   auto finalize = [&](std::vector<int> &list) -> sgw_status {
     for (size_t off = 0; off < list.size(); off += F) {
@@ -890,6 +953,7 @@ static sgw_status multishift_solve(sgw_ctx *ctx, const sgw_ham *h_kq, int n_occ,
     for (int s : list) {
       slot_pair[s] = -1;
       free_slots.push_back(s);
+      if (L.pooled) release(s);
     }
     finalized += list.size();
     list.clear();
@@ -897,15 +961,60 @@ static sgw_status multishift_solve(sgw_ctx *ctx, const sgw_ham *h_kq, int n_occ,
   };
 
   while (finalized < (size_t)n_pairs) {
-    // refill free slots
+    // refill free slots; with a pooled basis a pair is admitted only with blocks for its first steps,
+    // and none while running pairs wait for blocks
     int nfill = 0;
-    while (!free_slots.empty() && next < queue.size()) {
+    while (!free_slots.empty() && (next < queue.size() || !requeue.empty()) && !(L.pooled && stalled_prev)) {
       const int s = free_slots.back();
+      if (L.pooled && !grow(s, std::min(L.M, L.kmax))) {
+        release(s);
+        break;
+      }
       free_slots.pop_back();
-      slot_pair[s] = queue[next++];
+      int pr;
+      if (!requeue.empty()) {
+        pr = requeue.front();
+        requeue.pop_front();
+      } else {
+        pr = queue[next++];
+      }
+      slot_pair[s] = pr;
+      if (L.pooled) kcn[s] = 0;
       p_fill[nfill] = s;
-      p_fillpairs[nfill] = slot_pair[s];
+      p_fillpairs[nfill] = pr;
       ++nfill;
+    }
+    // the slots that take steps this round: with a pooled basis, those whose next steps' vectors
+    // are mapped; when none of the running pairs can grow (and none was just admitted), the least
+    // advanced one gives its blocks back and restarts later
+    std::vector<int> run;
+    if (L.pooled) {
+      for (;;) {
+        run.clear();
+        for (int s : active)
+          if (grow(s, std::min(kcn[s] + L.M, L.kmax))) run.push_back(s);
+        if (!run.empty() || active.empty() || nfill > 0) break;
+        if (!done.empty()) {  // finished pairs still hold blocks: finalise them first
+          if ((st = finalize(done)) != SGW_OK) return st;
+          continue;
+        }
+        int e = active[0];
+        for (int s : active)
+          if (kcn[s] < kcn[e]) e = s;
+        release(e);
+        requeue.push_front(slot_pair[e]);
+        slot_pair[e] = -1;
+        free_slots.push_back(e);
+        active.erase(std::find(active.begin(), active.end(), e));
+      }
+      stalled_prev = run.size() < active.size();
+      if (tab_dirty) {
+        std::memcpy(p_btab, htab.data(), sizeof(int32_t) * ntab);
+        SGW_HIP(hipMemcpyAsync(d_btab, p_btab, sizeof(int32_t) * ntab, hipMemcpyHostToDevice, ctx->stream));
+        tab_dirty = false;
+      }
+    } else {
+      run = active;
     }
     if (nfill > 0) {
       SGW_HIP(hipMemcpyAsync(d_fill, p_fill, sizeof(int32_t) * nfill, hipMemcpyHostToDevice, ctx->stream));
@@ -919,20 +1028,21 @@ static sgw_status multishift_solve(sgw_ctx *ctx, const sgw_ham *h_kq, int n_occ,
       if ((st = slot_init(ctx, Sx, nfill, Y, Y2, d_fill, d_fillpairs)) != SGW_OK) return st;
       for (int i = 0; i < nfill; ++i) {
         active.push_back(p_fill[i]);
+        run.push_back(p_fill[i]);
         slot_fp32[p_fill[i]] = 0;
       }
     }
-    if (!active.empty()) {
+    if (!run.empty()) {
       // FP64 slots first, then the slots whose matvecs run with the FP32 potential
       int n64 = 0;
-      for (int s : active)
+      for (int s : run)
         if (!slot_fp32[s]) p_active[n64++] = s;
       int k32 = n64;
-      for (int s : active)
+      for (int s : run)
         if (slot_fp32[s]) p_active[k32++] = s;
-      const int na = (int)active.size();
+      const int na = (int)run.size();
       SGW_HIP(hipMemcpyAsync(d_active, p_active, sizeof(int32_t) * na, hipMemcpyHostToDevice, ctx->stream));
-      const VecSrc cur32{Sx.basis, npw, d_active + n64, Sx.kcur, Sx.slot_stride};
+      const VecSrc cur32{Sx.basis, npw, d_active + n64, Sx.kcur, Sx.slot_stride, Sx.btab, Sx.nbmax, Sx.bshift};
       auto steps = [&]() -> sgw_status {
         sgw_status s2;
         for (int step = 0; step < L.M; ++step) {
@@ -964,6 +1074,8 @@ static sgw_status multishift_solve(sgw_ctx *ctx, const sgw_ham *h_kq, int n_occ,
     if (mixed)
       SGW_HIP(hipMemcpyAsync(p_maxres, Sx.maxres, sizeof(double) * S, hipMemcpyDeviceToHost, ctx->stream));
     if ((st = sync(ctx)) != SGW_OK) return st;
+    if (L.pooled)
+      for (int s : active) kcn[s] = kc_host[s];
     if (mixed)
       for (int s : active) slot_fp32[s] = slot_fp32[s] || p_maxres[s] <= switch_res;
     std::vector<int> still;
@@ -976,8 +1088,9 @@ static sgw_status multishift_solve(sgw_ctx *ctx, const sgw_ham *h_kq, int n_occ,
       }
     }
     active.swap(still);
-    const bool refill_waiting = next < queue.size();
-    if (!done.empty() && (active.empty() || (int)done.size() >= F || (refill_waiting && (int)done.size() * 4 >= F))) {
+    const bool refill_waiting = next < queue.size() || !requeue.empty();
+    if (!done.empty() && (active.empty() || (int)done.size() >= F || (refill_waiting && (int)done.size() * 4 >= F) ||
+                          (L.pooled && stalled_prev))) {
       if ((st = finalize(done)) != SGW_OK) return st;
     }
   }

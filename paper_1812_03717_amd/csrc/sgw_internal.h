@@ -115,16 +115,25 @@ struct sgw_ham {
 namespace sgw {
 
 // Describes where vector a of a batch lives: base + a*ld, or, with a slot list,
-// base + list[a]*slot_stride (+ kidx[list[a]]*ld when kidx is given).
+// base + list[a]*slot_stride (+ kidx[list[a]]*ld when kidx is given).  With a block table (a
+// pooled Krylov basis), vector k of slot s is row k mod 2^bshift of block btab[s][k >> bshift],
+// each block 2^bshift rows of ld values from base.
 struct VecSrc {
   const double2 *base;
   long ld;
   const int32_t *list;
   const int32_t *kidx;
   long slot_stride;
+  const int32_t *btab = nullptr;
+  int nbmax = 0, bshift = 0;
   __host__ __device__ inline const double2 *ptr(int a) const {
     if (!list) return base + (long)a * ld;
     int s = list[a];
+    if (btab) {
+      const int k = kidx[s];
+      const long row = ((long)btab[s * nbmax + (k >> bshift)] << bshift) + (k & ((1 << bshift) - 1));
+      return base + row * ld;
+    }
     return base + (long)s * slot_stride + (kidx ? (long)kidx[s] * ld : 0L);
   }
 };

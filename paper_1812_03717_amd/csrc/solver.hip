@@ -141,7 +141,7 @@ __global__ __launch_bounds__(kRowThreads) void k_init(SolverState S, const doubl
   // right-hand side is zero to working precision
   const bool zero = !(nb > kZeroRhsRel * ns);
   if (zero && isfinite(nb)) nb = 0.0;
-  double2 *v0 = S.basis + (long)slot * S.slot_stride;
+  double2 *v0 = basis_vec(S, slot, 0);
   const double inv = nb > 0.0 ? 1.0 / nb : 0.0;
   for (int g = threadIdx.x; g < S.npw; g += kRowThreads) {
     if (nb == 0.0) bv[g] = make_double2(0.0, 0.0);
@@ -186,9 +186,9 @@ __global__ __launch_bounds__(kLzThreads) void k_lanczos(SolverState S, const int
   if (S.status[slot] != SLOT_RUNNING) return;
   const int k = S.kcur[slot];
   const int npw = S.npw;
-  const double2 *v = S.basis + (long)slot * S.slot_stride + (long)k * npw;
-  const double2 *vp = v - npw;
-  double2 *vn = const_cast<double2 *>(v) + npw;
+  const double2 *v = basis_vec(S, slot, k);
+  const double2 *vp = k > 0 ? basis_vec(S, slot, k - 1) : v;
+  double2 *vn = basis_vec(S, slot, k + 1);
   const double2 *y = Y + (long)a * npw;
   const double eps = S.eps[slot];
   const double bk = k > 0 ? S.beta[(long)slot * (S.kmax + 1) + k] : 0.0;
@@ -368,7 +368,6 @@ __global__ __launch_bounds__(kCmbThreads) void k_combine(SolverState S, const in
   const int nw = S.n_omega;
   const int j0 = jc * kCmbJ;
   const int g = gt * kCmbThreads + threadIdx.x;
-  const double2 *V = S.basis + (long)slot * S.slot_stride;
   double2 acc[kCmbJ];
 #pragma unroll
   for (int q = 0; q < kCmbJ; ++q) acc[q] = make_double2(0.0, 0.0);
@@ -387,7 +386,7 @@ __global__ __launch_bounds__(kCmbThreads) void k_combine(SolverState S, const in
         double2 vk[kCmbU];
 #pragma unroll
         for (int u = 0; u < kCmbU; ++u)
-          vk[u] = kb + u < kend ? V[(long)(k0 + kb + u) * S.npw + g] : make_double2(0.0, 0.0);
+          vk[u] = kb + u < kend ? basis_vec(S, slot, k0 + kb + u)[g] : make_double2(0.0, 0.0);
 #pragma unroll
         for (int u = 0; u < kCmbU; ++u) {
 #pragma unroll

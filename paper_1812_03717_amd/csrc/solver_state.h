@@ -30,7 +30,9 @@ struct SolverState {
   int npw, n_occ, n_omega, n_pert, kmax;
   long slot_stride;          // (kmax + 1) * npw
   const double2 *psi;        // [n_occ][npw] occupied states, internal order
-  double2 *basis;            // [slots][kmax + 1][npw]
+  double2 *basis;            // [slots][kmax + 1][npw], or a pool of blocks of 2^bshift vectors
+  const int32_t *btab = nullptr;  // pooled basis: [slots][nbmax] block of each 2^bshift Krylov vectors
+  int nbmax = 0, bshift = 0;
   double2 *bvec;             // [slots][npw] right-hand sides
   double *alpha_t;           // [slots][kmax] Lanczos diagonal
   double *beta;              // [slots][kmax + 1]; beta[0] = ||b||
@@ -48,6 +50,15 @@ struct SolverState {
   double alpha;              // coefficient of P_occ
   double tol_int;            // stop when every estimated residual is below this
 };
+
+// Krylov vector k of a slot, in the stored basis or through the block table of the pool
+__device__ __forceinline__ double2 *basis_vec(const SolverState &S, int slot, int k) {
+  if (S.btab) {
+    const long row = ((long)S.btab[slot * S.nbmax + (k >> S.bshift)] << S.bshift) + (k & ((1 << S.bshift) - 1));
+    return S.basis + row * S.npw;
+  }
+  return S.basis + (long)slot * S.slot_stride + (long)k * S.npw;
+}
 
 sgw_status rhs_source(sgw_ctx *ctx, const sgw_ham *h_kq, const sgw_ham *h_k, int n_vec, const int32_t *pairs,
                       int n_pert, const int32_t *dvm, const double2 *psi_v, long ld_psi, double2 *s, long lds);

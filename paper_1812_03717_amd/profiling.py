@@ -34,8 +34,8 @@ CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
 # sources that define each timed kernel
 KERNEL_SOURCES = {
     "hx_planes": ["planes.h", "fft_reg.h", "fft_lds.h", "twiddle_const.h", "hx.hip"],
-    "hx_sticks_inv": ["hx.hip", "planes.h", "fft_reg.h", "fft_lds.h", "twiddle_const.h"],
-    "hx_sticks_fwd": ["hx.hip", "planes.h", "fft_reg.h", "fft_lds.h", "twiddle_const.h"],
+    "hx_sticks_inv": ["hx.hip", "planes.h", "fft_reg.h", "fft_lds.h", "twiddle_const.h", "sgw_internal.h"],
+    "hx_sticks_fwd": ["hx.hip", "planes.h", "fft_reg.h", "fft_lds.h", "twiddle_const.h", "sgw_internal.h"],
     "proj_dot": ["projector.hip"],
     "proj_apply": ["projector.hip"],
 }

@@ -58,7 +58,7 @@ class sgw_opts(C.Structure):
                 ("guess", C.c_int32), ("tail_iter", C.c_int32), ("ps_max_iter", C.c_int32),
                 ("ps_slots", C.c_int32), ("mlp", C.c_void_p), ("hist_r", C.c_void_p), ("hist_x", C.c_void_p),
                 ("hist_iter", C.c_int32), ("mixed_switch", C.c_double), ("graph", C.c_int32),
-                ("fft_planes", C.c_int32)]
+                ("fft_planes", C.c_int32), ("basis_blocks", C.c_int32)]
 
 
 class sgw_problem(C.Structure):

@@ -63,17 +63,30 @@ def test_occupied_limit_is_reported(env):
 
 
 @pytest.mark.parametrize("kw", [dict(slots=1), dict(finalize_batch=1), dict(steps_per_sync=1),
-                                dict(slots=2, finalize_batch=1, steps_per_sync=3)],
+                                dict(slots=2, finalize_batch=1, steps_per_sync=3),
+                                # pooled Krylov basis: 19 blocks of 32 vectors are the least that max_iter
+                                # 600 allows; 12 slots outgrow them, so pairs wait for blocks and are
+                                # restarted after evictions
+                                dict(slots=12, basis_blocks=19), dict(slots=5, basis_blocks=20, steps_per_sync=3,
+                                                                      finalize_batch=1)],
                          ids=lambda k: ",".join(f"{a}={b}" for a, b in k.items()))
 def test_degenerate_scheduling_is_bit_identical(env, kw):
-    """Slot count, finalisation batch and poll interval change only the schedule: each pair's
-    arithmetic is per slot and per vector, so results must match the default bit for bit."""
+    """Slot count, finalisation batch, poll interval and a pooled basis change only the schedule:
+    each pair's arithmetic is per slot and per vector, so results must match the default bit for
+    bit."""
     from paper_1812_03717_amd import sgw
     ctx, p, d = env
     st0, x0, i0 = d.solve(tol=1e-10)
     st1, x1, i1 = d.solve(tol=1e-10, opts=sgw.sgw_opts_default(**kw))
     assert st0 == st1 == sgw.SGW_OK
     assert torch.equal(x0, x1) and torch.equal(i0, i1)
+
+
+def test_pooled_basis_rejects_a_pool_below_one_pair(env):
+    from paper_1812_03717_amd import sgw
+    ctx, p, d = env
+    with pytest.raises(sgw.SgwError):
+        d.solve(tol=1e-10, opts=sgw.sgw_opts_default(basis_blocks=18))  # 18 * 32 < max_iter + 1 = 601
 
 
 def test_empty_batch(env):
