@@ -239,10 +239,15 @@ typedef struct {
   int32_t fft_planes;       /* plane-pass kernel of the FP64 H.x (SGW_FFT_*); SGW_FFT_AUTO: the
                                context's setting (sgw_ctx_set_fft_planes) */
   int32_t basis_blocks;     /* Krylov bases of the multishift slots.  0: each slot holds max_iter + 1
-                               vectors.  > 0: the slots draw their vectors from a pool of this many
-                               blocks of 32 (at least (max_iter + 1) / 32 rounded up) as they grow; a
-                               pair that cannot grow waits, and when no running pair can grow the
-                               least advanced one is restarted later.  Results do not change. */
+                               vectors when the workspace budget allows one slot per (v,p) pair;
+                               otherwise 4x the slots draw their vectors from a pool of the same
+                               memory in blocks of 32 as they grow, a pair being admitted only when
+                               the pool can carry the admitted pairs to their expected Krylov
+                               dimension.  > 0: a pool of this many blocks (at least (max_iter + 1)
+                               / 32 rounded up), admitting whenever blocks for a pair's first steps
+                               are free.  A pair that cannot grow waits; when no running pair can
+                               grow, the least advanced one is restarted later.  Results do not
+                               change. */
 } sgw_opts;
 
 /* Fills *opts with the defaults. */

@@ -556,8 +556,10 @@ extern "C" sgw_status sgw_opts_default(sgw_opts *o) {
 namespace {
 
 constexpr size_t kAlign = 256;
-// pooled Krylov basis: 32 vectors per block
+// pooled Krylov basis: 32 vectors per block; when the budget cannot give every pair a full-size
+// basis, up to this many times the slots of full-size bases share a pool of the same memory
 constexpr int kBasisBlockShift = 5;
+constexpr int kPoolSlotFactor = 4;
 // workspace budget that sizes the automatic slot count: a third of one MI355X's 288 GB of HBM
 constexpr double kDefaultBudget = 96.0 * (1ull << 30);
 
@@ -631,6 +633,15 @@ Layout make_layout(const sgw_ham *h, int n_occ, int n_band, int n_pert, int n_om
   if (o.basis_blocks > 0) {
     L.pooled = true;
     L.nblk = o.basis_blocks;
+  } else if (o.slots <= 0 && S < n_pairs) {
+    // the budget cannot give every pair a full-size slot: more slots share a pool of the same size
+    const double fixed = (double)L.F * n_omega * (2.0 * npw * 16.0 + h->n[2] * h->n_stick * 16.0);
+    const double blk_bytes = (double)(1 << L.bshift) * npw * 16.0;
+    const double small = per_slot - (double)(L.kmax + 1) * npw * 16.0;  // a slot without its basis
+    S = std::max(1, std::min({n_pairs, 4096, kPoolSlotFactor * S}));
+    while (S > 1 && (kDefaultBudget - fixed - S * small) / blk_bytes < 2.0 * L.nbmax) --S;
+    L.pooled = true;
+    L.nblk = (int)std::max<double>(L.nbmax, (kDefaultBudget - fixed - S * small) / blk_bytes);
   }
   L.S = std::max(1, std::min(S, std::max(n_pairs, 1)));
   const long nfv = (long)L.F * n_omega;
@@ -928,6 +939,17 @@ static sgw_status multishift_solve(sgw_ctx *ctx, const sgw_ham *h_kq, int n_occ,
     for (int i = 0; i < nown[s]; ++i) free_blk.push_back(htab[(size_t)s * L.nbmax + i]);
     nown[s] = 0;
   };
+  // Admission by expected growth: a pair enters only if the pool can carry every admitted pair to
+  // its expected final Krylov dimension: max_iter until 16 pairs have finished, then the 90th
+  // percentile of theirs (the queue runs from the slowest bands down, so this overestimates).
+  // (a pool the caller sized admits whenever blocks for the first steps are free)
+  const bool careful = L.pooled && o.basis_blocks <= 0;
+  std::vector<int> kfin;
+  int kest = L.kmax;
+  auto expect_blocks = [&](int k_now) {
+    const int k = std::min(L.kmax, std::max(k_now + L.M, kest));
+    return (k >> L.bshift) + 1;
+  };
 
   auto finalize = [&](std::vector<int> &list) -> sgw_status {
     for (size_t off = 0; off < list.size(); off += F) {
@@ -964,12 +986,20 @@ static sgw_status multishift_solve(sgw_ctx *ctx, const sgw_ham *h_kq, int n_occ,
     // refill free slots; with a pooled basis a pair is admitted only with blocks for its first steps,
     // and none while running pairs wait for blocks
     int nfill = 0;
+    long committed = 0;  // blocks the admitted pairs are expected to need (pooled basis)
+    if (L.pooled) {
+      for (int s : active) committed += std::max(nown[s], expect_blocks(kcn[s]));
+      for (int s : done) committed += nown[s];
+    }
     while (!free_slots.empty() && (next < queue.size() || !requeue.empty()) && !(L.pooled && stalled_prev)) {
       const int s = free_slots.back();
+      if (careful && committed + expect_blocks(0) > L.nblk && !(active.empty() && done.empty() && nfill == 0))
+        break;
       if (L.pooled && !grow(s, std::min(L.M, L.kmax))) {
         release(s);
         break;
       }
+      if (L.pooled) committed += expect_blocks(0);
       free_slots.pop_back();
       int pr;
       if (!requeue.empty()) {
@@ -1085,7 +1115,14 @@ static sgw_status multishift_solve(sgw_ctx *ctx, const sgw_ham *h_kq, int n_occ,
         done.push_back(s);
         ksum += kc_host[s];
         ++kcount;
+        if (L.pooled) kfin.push_back(kc_host[s]);
       }
+    }
+    if (L.pooled && kfin.size() >= 16) {
+      std::vector<int> t = kfin;
+      const size_t q = t.size() * 9 / 10;
+      std::nth_element(t.begin(), t.begin() + q, t.end());
+      kest = std::min(L.kmax, t[q]);
     }
     active.swap(still);
     const bool refill_waiting = next < queue.size() || !requeue.empty();
