@@ -568,9 +568,10 @@ struct Layout {
   size_t psi, omega, epsb, dvm, pair, kcur, status, eps, alpha, beta, rho, res, maxres, conv, bvec, basis;
   size_t l_active, l_fill, l_fillpairs, l_final, Y, Y2, C, T, ycoef, cp, X, AX, bad, btab = 0;
   long c_rows = 0;
-  // pooled Krylov basis: blocks of 2^bshift vectors, nbmax per slot at most, nblk in the pool
+  // pooled Krylov basis: blocks of 2^bshift vectors, nbmax per slot at most, nblk in the pool;
+  // S_full: the slots that full-size bases would give
   bool pooled = false;
-  int bshift = 0, nbmax = 0, nblk = 0;
+  int bshift = 0, nbmax = 0, nblk = 0, S_full = 0;
   size_t total = 0;
 };
 
@@ -630,6 +631,7 @@ Layout make_layout(const sgw_ham *h, int n_occ, int n_band, int n_pert, int n_om
   // from a pool in blocks of 2^bshift as they grow, instead of each holding max_iter + 1
   L.bshift = kBasisBlockShift;
   L.nbmax = (L.kmax + 1 + (1 << L.bshift) - 1) >> L.bshift;
+  L.S_full = std::max(1, std::min(S, std::max(n_pairs, 1)));
   if (o.basis_blocks > 0) {
     L.pooled = true;
     L.nblk = o.basis_blocks;
@@ -1236,8 +1238,9 @@ sgw_opts fit_to_budget(const sgw_problem &p, sgw_opts o, size_t budget) {
   if (o.solver != SGW_SOLVER_MULTISHIFT) return o;
   const int n_omega = std::max(p.n_omega, 1);
   Layout L = make_layout(p.h_kq, p.n_occ, p.n_band, p.n_pert, n_omega, o);
-  o.slots = L.S;
+  o.slots = L.S_full;  // a worker's part holds full-size bases
   o.finalize_batch = L.F;
+  L = make_layout(p.h_kq, p.n_occ, p.n_band, p.n_pert, n_omega, o);
   while (L.total > budget && (o.slots > 1 || o.finalize_batch > 1)) {
     if (o.slots > 1) o.slots = std::max(1, o.slots * 3 / 4);
     if (o.finalize_batch > 1 && (o.slots == 1 || (long)o.finalize_batch * n_omega > o.slots))
