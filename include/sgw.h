@@ -288,7 +288,8 @@ sgw_status sternheimer_workspace_size(sgw_ctx *ctx, const sgw_ham *h_kq, int n_o
  * dpsi        device out [n_band][n_pert][n_omega][n_pw_kq]
  * info        device out [n_band][n_pert][n_omega]
  * Returns SGW_OK when every solve converged, SGW_NOT_CONVERGED when some did
- * not (their best iterate and flags are still written), or an error.
+ * not (their best iterate and flags are still written), or an error;
+ * SGW_ERR_UNSUPPORTED for n_occ > 256 or a k+q basis above 16384 plane waves.
  */
 sgw_status sternheimer_solve(sgw_ctx *ctx, const sgw_ham *h_kq, int n_occ, const sgw_c128 *psi_occ_kq,
                              const sgw_ham *h_k, int n_band, const sgw_c128 *psi_v, const double *eps_v,

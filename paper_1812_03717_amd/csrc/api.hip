@@ -732,7 +732,7 @@ static sgw_status validate_solve(sgw_ctx *ctx, const sgw_ham *h_kq, int n_occ, c
   SGW_CHECK(n_occ == 0 || psi_occ_kq, "sternheimer_solve: psi_occ_kq is NULL");
   for (int j = 0; j < n_omega; ++j) SGW_CHECK(std::isfinite(omega[j]), "sternheimer_solve: omega not finite");
   for (int v = 0; v < n_band; ++v) SGW_CHECK(std::isfinite(eps_v[v]), "sternheimer_solve: eps_v not finite");
-  if (lanczos_ept(h_kq->n_pw) > 32) return fail(SGW_ERR_UNSUPPORTED, "sternheimer_solve: basis above 16384");
+  if (h_kq->n_pw > 16384) return fail(SGW_ERR_UNSUPPORTED, "sternheimer_solve: basis above 16384");
   return check_miller_shift(dv_miller, n_pert);
 }
 

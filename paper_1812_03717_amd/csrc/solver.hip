@@ -173,8 +173,9 @@ __global__ __launch_bounds__(kRowThreads) void k_init(SolverState S, const doubl
 //   by the H.x and projector kernels
 // ---------------------------------------------------------------------------
 // threads per vector: 256 up to 4096 plane waves (one round of workgroups for ~1000 vectors on
-// 256 CUs at 16 values per thread), 512 above; values per thread EPT up to 32
-constexpr int kLzSmall = 256, kLzLarge = 512;
+// 256 CUs at 16 values per thread), 512 up to 8192, 1024 up to 16384 (large bases run with fewer
+// vectors per step than there are CUs, so each CU gets more waves in flight: 16 values per thread)
+constexpr int kLzSmall = 256, kLzLarge = 512, kLzHuge = 1024;
 
 template <int EPT, int kLzThreads>
 __global__ __launch_bounds__(kLzThreads) void k_lanczos(SolverState S, const int32_t *__restrict__ list,
@@ -569,9 +570,11 @@ sgw_status slot_init(sgw_ctx *ctx, const SolverState &S, int n_fill, const doubl
   return SGW_OK;
 }
 
-static int lanczos_threads(int npw) { return npw <= 16 * kLzSmall ? kLzSmall : kLzLarge; }
+static int lanczos_threads(int npw) {
+  return npw <= 16 * kLzSmall ? kLzSmall : npw <= 16 * kLzLarge ? kLzLarge : kLzHuge;
+}
 
-int lanczos_ept(int npw) {
+static int lanczos_ept(int npw) {
   const int nt = lanczos_threads(npw);
   int e = 1;
   while (e * nt < npw) e *= 2;
@@ -580,21 +583,25 @@ int lanczos_ept(int npw) {
 
 sgw_status lanczos_step(sgw_ctx *ctx, const SolverState &S, int n_active, const int32_t *list, const double2 *Y) {
   if (n_active <= 0) return SGW_OK;
+  if (S.npw > 16 * kLzHuge) return fail(SGW_ERR_UNSUPPORTED, "too many plane waves for the Lanczos kernel");
+  const int ept = lanczos_ept(S.npw);
+  const int nt = lanczos_threads(S.npw);
   PendingTiming tm;
   timing_begin(ctx, K_LANCZOS, n_active * (S.npw * 16.0 * 4), 0.0, &tm);
-  const int ept = lanczos_ept(S.npw);
-  const bool small = lanczos_threads(S.npw) == kLzSmall;
   switch (ept) {
 #define SGW_LZ(E)                                                                                          \
   case E:                                                                                                  \
-    if (small)                                                                                             \
+    if (nt == kLzSmall)                                                                                    \
       hipLaunchKernelGGL((k_lanczos<E, kLzSmall>), dim3(n_active), dim3(kLzSmall), 0, ctx->stream, S, list, \
                          Y);                                                                               \
-    else                                                                                                   \
+    else if (nt == kLzLarge)                                                                               \
       hipLaunchKernelGGL((k_lanczos<E, kLzLarge>), dim3(n_active), dim3(kLzLarge), 0, ctx->stream, S, list, \
                          Y);                                                                               \
+    else                                                                                                   \
+      hipLaunchKernelGGL((k_lanczos<E, kLzHuge>), dim3(n_active), dim3(kLzHuge), 0, ctx->stream, S, list,   \
+                         Y);                                                                               \
     break;
-    SGW_LZ(1) SGW_LZ(2) SGW_LZ(4) SGW_LZ(8) SGW_LZ(16) SGW_LZ(32)
+    SGW_LZ(1) SGW_LZ(2) SGW_LZ(4) SGW_LZ(8) SGW_LZ(16)
 #undef SGW_LZ
     default:
       return fail(SGW_ERR_UNSUPPORTED, "too many plane waves for the Lanczos kernel");

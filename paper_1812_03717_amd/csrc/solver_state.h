@@ -77,6 +77,5 @@ sgw_status residual(sgw_ctx *ctx, const SolverState &S, const int32_t *flist, in
                     sgw_solve_info *info, double tol, int *n_bad);
 // plane-major copies of the potential, FP64 and FP32
 sgw_status transpose_potential(sgw_ctx *ctx, const double *v, double *vt, float *vt32, const int n[3]);
-int lanczos_ept(int npw);
 
 }  // namespace sgw
