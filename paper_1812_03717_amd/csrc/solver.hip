@@ -342,15 +342,16 @@ __global__ void k_tridiag(SolverState S, const int32_t *__restrict__ flist, int 
 // x_j = sum_k ycoef[k][j] v_k  for every shift j of a slot
 // ---------------------------------------------------------------------------
 constexpr int kCmbThreads = 256;
-constexpr int kCmbJ = 16;
 constexpr int kCmbK = 32;
 constexpr int kCmbU = 8;  // basis values loaded ahead (divides kCmbK)
 // workgroups are dealt round-robin to the GPU's 8 XCDs (each with its own L2)
 constexpr int kXcds = 8;
 
-// One workgroup per (slot, tile of 256 plane waves, chunk of 16 shifts).  The chunks of a tile read
-// the same basis vectors; workgroup ids are arranged so that they run on one XCD (ids spaced by
-// kXcds, dispatched close together) and share that XCD's L2 copy of the tile.
+// One workgroup per (slot, tile of 256 plane waves, chunk of kCmbJ shifts; kCmbJ is 16 or 20,
+// whichever pads the shift count less, so 64 and 100 shifts split without a ragged chunk).  The
+// chunks of a tile read the same basis vectors; workgroup ids are arranged so that they run on one
+// XCD (ids spaced by kXcds, dispatched close together) and share that XCD's L2 copy of the tile.
+template <int kCmbJ>
 __global__ __launch_bounds__(kCmbThreads) void k_combine(SolverState S, const int32_t *__restrict__ flist,
                                                          const double2 *__restrict__ ycoef,
                                                          double2 *__restrict__ X, int gtiles, int jchunks,
@@ -626,14 +627,21 @@ sgw_status combine(sgw_ctx *ctx, const SolverState &S, const int32_t *flist, int
                    double2 *X, double est_kavg) {
   if (nf <= 0) return SGW_OK;
   const int gtiles = (S.npw + kCmbThreads - 1) / kCmbThreads;
-  const int jchunks = (S.n_omega + kCmbJ - 1) / kCmbJ;
+  const int nw = S.n_omega;
+  const bool j20 = (nw + 19) / 20 * 20 < (nw + 15) / 16 * 16;
+  const int cj = j20 ? 20 : 16;
+  const int jchunks = (nw + cj - 1) / cj;
   PendingTiming tm;
   const double bytes = nf * (est_kavg * S.npw * 16.0 + (double)S.n_omega * S.npw * 16.0);
   timing_begin(ctx, K_COMBINE, bytes, 8.0 * nf * est_kavg * S.npw * S.n_omega, &tm);
   const int ntiles = nf * gtiles;
   const long groups = (long)(ntiles + kXcds - 1) / kXcds * kXcds * jchunks;
-  hipLaunchKernelGGL(k_combine, dim3(groups), dim3(kCmbThreads), 0, ctx->stream, S, flist, ycoef, X, gtiles,
-                     jchunks, ntiles);
+  if (j20)
+    hipLaunchKernelGGL(k_combine<20>, dim3(groups), dim3(kCmbThreads), 0, ctx->stream, S, flist, ycoef, X, gtiles,
+                       jchunks, ntiles);
+  else
+    hipLaunchKernelGGL(k_combine<16>, dim3(groups), dim3(kCmbThreads), 0, ctx->stream, S, flist, ycoef, X, gtiles,
+                       jchunks, ntiles);
   timing_end(ctx, &tm);
   SGW_HIP(hipGetLastError());
   return SGW_OK;

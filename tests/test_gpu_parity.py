@@ -184,7 +184,7 @@ def test_solve_si64_shape_sampled_rows(ctx):
     psi_v /= np.linalg.norm(psi_v, axis=1, keepdims=True)
     eps_v = np.full(n_band, v.min() - 0.3)  # H >= min V(r) at k = 0
     dvm = np.array([[0, 0, 0], [1, -1, 0], [0, 2, 1]], np.int32)
-    omega = np.linspace(0.0, 5.0, 6) / cx.HA_EV
+    omega = np.linspace(0.0, 5.0, 20) / cx.HA_EV  # 20 shifts: the combination's 20-shift chunks
     eta, tol = 0.1 / cx.HA_EV, 1e-8
     d_occ = torch.from_numpy(psi_occ).to(ctx.device)
     d_v = torch.from_numpy(psi_v).to(ctx.device)
