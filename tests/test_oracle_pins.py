@@ -240,9 +240,70 @@ def check_generator_ground_state():
     assert p.gap() >= 1e-3
 
 
+def check_relative_residual_closed_form():
+    """Free electrons (V = V0): A0 - z is diagonal with entries 0.5|k+q+G|^2 + V0 - eps_v - z (+ alpha on
+    the occupied G = 0).  The exact solution has residual 0; moving one coefficient by delta leaves the
+    residual -(d_g - z) delta e_g, so relres = |d_g - z| |delta| / ||b|| exactly; b = 0 with x = 0 gives 0.
+    The diagonal entries are written out from the kinetic closed form, not taken from the oracle."""
+    A, tau = cx.fcc_primitive(A_LAT)
+    B = cx.reciprocal(A)
+    q = 0.1 * B[0]
+    v0, alpha = -0.7, 1.3
+    grid = (10, 10, 10)
+    mk = cx.g_sphere(B, np.zeros(3), 2.1)
+    mkq = cx.g_sphere(B, q, 2.1)
+    h_kq = so.hamiltonian(mkq, B, q, np.full(grid, v0))
+    psi_kq = np.zeros((1, len(mkq)), complex); psi_kq[0, 0] = 1.0
+    psi_k = np.zeros(len(mk), complex); psi_k[0] = 1.0
+    eps_v = v0
+    a0 = so.coulomb_operator(h_kq, psi_kq, eps_v, alpha)
+    m_p = np.array([0, -1, 1])
+    scale = 3.5                                        # ||b|| = 3.5, so a missing division shows
+    b = scale * so.rhs(psi_k, mk, mkq, m_p, psi_kq)
+    g = int(np.nonzero((mkq == m_p).all(1))[0][0])
+    kq = q + mkq.astype(float) @ B
+    d = 0.5 * (kq * kq).sum(1) + v0 - eps_v
+    d[0] += alpha                                      # G = 0 is the occupied state at k+q
+    for z in (0.0 + 0.01j, 0.45 - 0.02j, -0.3 + 0.2j):
+        x = np.zeros(len(mkq), complex)
+        x[g] = -scale / (d[g] - z)                     # b = -scale e_g
+        assert so.relative_residual(a0, x, b, z) <= 1e-15
+        for h, delta in ((g, 0.02 - 0.01j), (0, 0.3j), (len(mkq) - 1, -0.05)):
+            xp = x.copy()
+            xp[h] += delta
+            expect = abs(d[h] - z) * abs(delta) / scale
+            got = so.relative_residual(a0, xp, b, z)
+            assert abs(got - expect) <= 1e-13 * expect, (h, got, expect)
+    zero = np.zeros(len(mkq), complex)
+    assert so.relative_residual(a0, zero, zero, 0.2 + 0.01j) == 0.0
+
+
+def check_condition_number_svd():
+    """kappa of H - eps_v - z on the unoccupied space against the singular values of the operator
+    restricted to that space, Q^H (H - eps_v - z) Q with Q an orthonormal basis of the complement of
+    the occupied states (from a QR of the residual of random vectors, not from the eigenvectors),
+    computed by LAPACK's SVD; z complex, eps_v an occupied level and omega near it, where counting
+    the occupied levels would change kappa by orders of magnitude."""
+    P = _small_problem()
+    n_occ, psi_kq, h = P["n_occ"], P["psi_kq"], P["h_kq"]
+    n = h.shape[0]
+    rng = np.random.default_rng(7)
+    r = rng.standard_normal((n, n - n_occ)) + 1j * rng.standard_normal((n, n - n_occ))
+    r -= psi_kq.T @ (psi_kq.conj() @ r)                # off the occupied span
+    qc = np.linalg.qr(r)[0]
+    for v in (0, n_occ - 1):
+        eps_v = P["wk"][v]
+        for z in (0.0 + 0.002j, 0.3 + 0.05j, -0.2 + 0.01j, 1.5 + 0.1j):
+            m = qc.conj().T @ (h - (eps_v + z) * np.eye(n)) @ qc
+            s = np.linalg.svd(m, compute_uv=False)
+            expect = s.max() / s.min()
+            got = so.condition_number(P["wq"], n_occ, eps_v, z)
+            assert abs(got - expect) <= 1e-9 * expect, (v, z, got, expect)
+
+
 PINS = [check_kinetic_closed_form, check_hamiltonian_bruteforce, check_shifted_source_realspace,
         check_free_electron_closed_form, check_mpmath_tiny, check_routes_and_invariants,
-        check_linearity_and_reciprocity]
+        check_linearity_and_reciprocity, check_relative_residual_closed_form, check_condition_number_svd]
 
 
 @pytest.mark.parametrize("pin", PINS + [check_generator_ground_state], ids=lambda f: f.__name__)
@@ -266,6 +327,8 @@ _orig_kin = so.kinetic
 _orig_coef = so.potential_coefficients
 _orig_op = so.coulomb_operator
 _orig_spec = so.solve_spectral
+_orig_relres = so.relative_residual
+_orig_kappa = so.condition_number
 
 
 def _mut_transposed_potential(miller, B, kvec, v_grid):
@@ -293,6 +356,13 @@ MUTATIONS = {
     "operator_shift_sign": ("coulomb_operator", lambda h, po, e, a: _orig_op(h, po, -e, a)),
     "spectral_off_by_one": ("solve_spectral", lambda w, u, n, e, b, z: _orig_spec(w, u, n + 1, e, b, z)),
     "spectral_conj_shift": ("solve_spectral", lambda w, u, n, e, b, z: _orig_spec(w, u, n, e, b, np.conj(z))),
+    "relres_returns_zero": ("relative_residual", lambda a0, x, b, z: 0.0),
+    "relres_no_division": ("relative_residual",
+                           lambda a0, x, b, z: float(np.linalg.norm(b - (a0 @ x - z * x)))),
+    "relres_shift_sign": ("relative_residual", lambda a0, x, b, z: _orig_relres(a0, x, b, -z)),
+    "kappa_includes_occ": ("condition_number", lambda w, n, e, z: _orig_kappa(w, 0, e, z)),
+    "kappa_drops_eta": ("condition_number", lambda w, n, e, z: _orig_kappa(w, n, e, complex(z).real + 1e-300j)),
+    "kappa_inverted": ("condition_number", lambda w, n, e, z: 1.0 / _orig_kappa(w, n, e, z)),
 }
 
 
