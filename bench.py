@@ -1,24 +1,22 @@
 """Benchmark: Sternheimer solves/s on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload si16] [--no-cpu-baseline]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload si64] [--no-cpu-baseline]
 
-One step is one ``sternheimer_solve`` call over the whole workload: for the
-si16 crystal (16-atom diamond fcc 2x2x2 supercell, 4015 plane waves, 48^3
-grid) every one of 32 occupied bands x 50 plane-wave perturbations at one
-seeded q x 64 frequencies in [0, 40] eV with eta = 0.05 eV, tol 1e-8 on the
-true FP64 relative residual: 102,400 solves.  Inputs are resident in HBM
-before the timed region; a solve counts when its true residual meets tol.
+One step is one ``sternheimer_solve`` call over the whole workload.  The default workload is the
+largest single-GPU configuration, si64: the 64-atom diamond cell (conventional cubic 2x2x2,
+16,013 plane waves at k+q, 72^3 grid), every one of 128 occupied bands x 20 plane-wave
+perturbations at one seeded q x 100 frequencies in [0, 40] eV with eta = 0.05 eV, tol 1e-8 on the
+true FP64 relative residual: 256,000 solves, plain FP64 multishift (max_iter 3500).  Inputs are
+resident in HBM before the timed region; a solve counts when its true residual meets tol.
 
-The timed method (--precision, default mixed) is the multishift solver with
-FP32 potential matvecs late in each (band, perturbation) pair; the same number
-of steps of the plain FP64 solver is timed beside it for speedup_vs_plain_fp64.
-The JSON line carries the roofline of the dominant kernel (timed with HIP
-events on the library's stream during the plain FP64 steps) and the CPU oracle
-timed on a bounded sample of the same workload.
+The JSON line carries the roofline of the dominant kernel (timed with HIP events on the
+library's stream during the timed steps) and the CPU oracle timed on a bounded sample of the
+same workload: for si64 the oracle's direct route (dense H_{k+q}, the shifted operator of one
+band, one LU factorisation solving all perturbations at one frequency), scaled to the workload.
 
-    python bench.py --workload batch200     # 200 uneven systems, sternheimer_solve_batch
-    python bench.py --workload si64 --precision fp64 --max-iter 3500 --no-cpu-baseline
-                                            # 64-atom cell, 72^3 grid, 256,000 solves
+    python bench.py --workload si16 --precision mixed   # 16-atom cell, 48^3, 102,400 solves;
+                                                        # a plain FP64 leg is timed beside it
+    python bench.py --workload batch200                 # 200 uneven systems, sternheimer_solve_batch
 """
 from __future__ import annotations
 
@@ -90,15 +88,60 @@ def roofline(kernel, ks, workload, default_launch=True):
     return roof
 
 
-def cpu_baseline(problem, n_pairs_sample, log):
-    """Time the oracle (dense H_{k+q}, full eigendecomposition, spectral sums) on a sample of pairs."""
-    import oracle
+def _cpu_info():
+    """(threads the BLAS pool uses, CPU model string)."""
     try:
         import threadpoolctl
         info = threadpoolctl.threadpool_info()
         cores = max([i.get("num_threads", 0) for i in info] + [0]) or os.cpu_count()
     except Exception:  # pragma: no cover
         cores = os.cpu_count()
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:  # pragma: no cover
+        pass
+    return int(cores), model
+
+
+def cpu_baseline_lu(problem, log):
+    """Time the oracle's direct route on a bounded sample: the dense H_{k+q}, the shifted operator of
+    the top band, and one LU factorisation of (A0 - z) solving every perturbation's right-hand side at
+    one frequency.  Every (band, frequency) needs its own factorisation, so the whole workload costs
+    t_H + n_band t_op + n_band n_omega t_LU."""
+    import oracle.sternheimer_oracle as so
+    cores, model = _cpu_info()
+    p = problem
+    v, j = p.n_band - 1, 0
+    t0 = time.perf_counter()
+    h = so.hamiltonian(p.miller_kq, p.B, p.kvec + p.qvec, p.v_grid)
+    t_h = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    a0 = so.coulomb_operator(h, p.psi_kq, p.eps_k[v], 1.0)
+    del h
+    bs = np.array([so.rhs(p.psi_k[v], p.miller_k, p.miller_kq, p.dv_miller[q], p.psi_kq) for q in range(p.n_pert)])
+    t_op = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    so.solve_lu(a0, bs.T, p.omega[j] + 1j * p.eta)
+    t_lu = time.perf_counter() - t0
+    del a0
+    log(f"cpu oracle: H {t_h:.1f} s, operator + {p.n_pert} right-hand sides {t_op:.1f} s, one LU solve {t_lu:.1f} s")
+    t_full = t_h + p.n_band * t_op + p.n_band * p.n_omega * t_lu
+    return {"value": p.n_solves / t_full, "unit": "solves/s", "cores": cores, "kind": "oracle", "cpu": model,
+            "sample": f"oracle direct route on the host: dense H_k+q ({p.n_pw_kq} PW, {t_h:.1f} s), operator of "
+                      f"one band + its {p.n_pert} right-hand sides ({t_op:.1f} s), one LU factorisation solving "
+                      f"the {p.n_pert} perturbations at one frequency ({t_lu:.1f} s); value = {p.n_solves} "
+                      f"solves / (t_H + {p.n_band} t_op + {p.n_band * p.n_omega} t_LU)"}
+
+
+def cpu_baseline(problem, n_pairs_sample, log):
+    """Time the oracle (dense H_{k+q}, full eigendecomposition, spectral sums) on a sample of pairs."""
+    import oracle
+    cores, model = _cpu_info()
     p = problem
     t0 = time.perf_counter()
     setup = oracle.spectral_setup(p.miller_kq, p.B, p.kvec + p.qvec, p.v_grid)
@@ -115,7 +158,7 @@ def cpu_baseline(problem, n_pairs_sample, log):
     n_total_pairs = len(all_pairs)
     t_full = t_setup + t_pairs / len(pairs) * n_total_pairs
     value = n_total_pairs * p.n_omega / t_full
-    return {"value": value, "unit": "solves/s", "cores": int(cores), "kind": "oracle",
+    return {"value": value, "unit": "solves/s", "cores": int(cores), "kind": "oracle", "cpu": model,
             "sample": f"dense H_k+q + full eigh once ({t_setup:.1f} s) + spectral solves for {len(pairs)} of "
                       f"{n_total_pairs} (band, pert) pairs x {p.n_omega} omega ({t_pairs:.1f} s); value = "
                       f"all {n_total_pairs * p.n_omega} solves / (setup + per-pair time x {n_total_pairs})"}
@@ -209,13 +252,14 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="si16", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="si64", choices=sorted(WORKLOADS))
     ap.add_argument("--slots", type=int, default=0)
     ap.add_argument("--max-iter", type=int, default=0,
-                    help="Krylov steps per pair before a solve is flagged (0: the library default; si64 needs ~3500)")
-    ap.add_argument("--precision", choices=["fp64", "mixed"], default="mixed",
+                    help="Krylov steps per pair before a solve is flagged (0: 3500 for si64, else the library "
+                         "default)")
+    ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64",
                     help="the timed method; mixed: FP32 potential matvecs once a pair's residuals are small, "
-                         "FP64 refinement.  A plain FP64 leg is always timed beside it.")
+                         "FP64 refinement, with a plain FP64 leg timed beside it")
     ap.add_argument("--mixed-switch", type=float, default=0.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch-workers", type=int, default=4)
@@ -264,8 +308,9 @@ def main():
     kw = dict(precision=prec)
     if args.slots:
         kw["slots"] = args.slots
-    if args.max_iter:
-        kw["max_iter"] = args.max_iter
+    max_iter = args.max_iter or (3500 if args.workload == "si64" else 0)
+    if max_iter:
+        kw["max_iter"] = max_iter
     if args.mixed_switch:
         kw["mixed_switch"] = args.mixed_switch
     opts = sgw.sgw_opts_default(**kw)
@@ -343,13 +388,17 @@ def main():
         "plain_fp64_value": round(plain_value, 1),
         "dtype": "f64" if prec == sgw.FP64 else "f64+f32", "data": "synthetic",
         "config": {"workload": WORKLOADS[args.workload], "solves_per_step": problem.n_solves,
+                   "max_iter": max_iter or 600,
                    "method": "multishift Lanczos-FOM, stored basis, " +
                              ("FP64" if prec == sgw.FP64 else "FP64 with FP32 potential matvecs once a pair's "
                               "shift residuals are below 1e4*tol, FP64 per-shift refinement of any shift above tol")},
         "roofline": roof,
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(problem, args.cpu_sample_pairs, log)
+        if args.workload == "si64":
+            out["cpu_baseline"] = cpu_baseline_lu(problem, log)
+        else:
+            out["cpu_baseline"] = cpu_baseline(problem, args.cpu_sample_pairs, log)
     print(json.dumps(out), flush=True)
 
 

@@ -188,7 +188,7 @@ sgw_status sgw_apply_h(sgw_ctx *ctx, const sgw_ham *ham, int n_vec, const sgw_c1
  *   mode 0:  y = x - Psi (Psi^H x)          (the conduction projector 1 - P_occ)
  *   mode 1:  y = y + alpha * Psi (Psi^H x)   (the + alpha P_occ term of the operator)
  * psi: device [n_occ][n_pw] (rows are orthonormal occupied states), x, y: device
- * [n_vec][n_pw], caller's order.  x and y may not alias.
+ * [n_vec][n_pw], caller's order.  x and y may not alias.  n_occ above 256: SGW_ERR_UNSUPPORTED.
  */
 sgw_status sgw_apply_projector(sgw_ctx *ctx, const sgw_ham *ham, int n_occ, const sgw_c128 *psi,
                                int n_vec, const sgw_c128 *x, sgw_c128 *y, double alpha, int mode);
@@ -200,6 +200,7 @@ sgw_status sgw_apply_projector(sgw_ctx *ctx, const sgw_ham *ham, int n_occ, cons
  * k+q): s(G'') = psi_v(G'' - G_p) if G'' - G_p is in the basis at k, else 0.
  * psi_v: device [n_band][n_pw_k]; psi_occ_kq: device [n_occ][n_pw_kq];
  * dv_miller: host [n_pert][3]; b: device [n_band][n_pert][n_pw_kq].
+ * n_occ above 256: SGW_ERR_UNSUPPORTED.
  */
 sgw_status sgw_build_rhs(sgw_ctx *ctx, const sgw_ham *h_kq, int n_occ, const sgw_c128 *psi_occ_kq,
                          const sgw_ham *h_k, int n_band, const sgw_c128 *psi_v, int n_pert,
@@ -414,6 +415,23 @@ sgw_status sgw_operator_columns(sgw_ctx *ctx, const sgw_ham *ham, int n_occ, con
 sgw_status sgw_mlp_rows(sgw_ctx *ctx, const sgw_ham *ham, const double *diag, const double *off2, int n_vec,
                         const double *eps, const double *omega, double eta, const sgw_c128 *r, const sgw_c128 *b,
                         int stride, float *feat, float *target);
+
+/*
+ * Test hook of the per-shift solves' diagonal preconditioner and initial guess (not part of the
+ * paper: any diagonal preconditioner or guess leaves the solution of Sec. 2.3, Eqs. 6-8, unchanged).
+ * For n_vec systems with right-hand sides b (device [n_vec][n_pw], caller's order), band energies
+ * eps and frequencies omega (host [n_vec], Ha) and eta, writes the values the per-shift solver uses,
+ * computed by the same kernel:
+ *   m   device out [n_vec][n_pw]: SGW_PC_NONE 1; SGW_PC_TETER K(T_G / E_ref) (Teter, Payne, Allan,
+ *       Phys. Rev. B 40, 12255 (1989)) with E_ref = sum_G T_G |b_G|^2 / sum_G |b_G|^2, T_G = 0.5|k+G|^2;
+ *       SGW_PC_LEARNED s (o0 + i o1) from the BF16 rounding of mlp's weights, FP32 arithmetic;
+ *   x0  device out [n_vec][n_pw]: 0 for SGW_GUESS_ZERO, s (o2 + i o3) b_G for SGW_GUESS_LEARNED.
+ * mlp may be NULL unless the learned model is asked for.  Allocates temporary device buffers and
+ * returns after the GPU work has completed.
+ */
+sgw_status sgw_precond_values(sgw_ctx *ctx, const sgw_ham *ham, int precond, int guess, const sgw_mlp *mlp,
+                              int n_vec, const double *eps, const double *omega, double eta, const sgw_c128 *b,
+                              sgw_c128 *m, sgw_c128 *x0);
 
 #ifdef __cplusplus
 }

@@ -132,6 +132,23 @@ def teter(x):
     return p / (p + 16.0 * x ** 4)
 
 
+def teter_diagonal(kin, b):
+    """The per-shift Teter diagonal for right-hand side b: K(T_G / E_ref) with the kinetic energy
+    of b as the reference, E_ref = sum_G T_G |b_G|^2 / sum_G |b_G|^2 (1 for b = 0)."""
+    kin = np.asarray(kin, np.float64)
+    w = np.abs(np.asarray(b)) ** 2
+    eref = float(np.sum(kin * w) / np.sum(w)) if np.sum(w) > 0 else 1.0
+    return teter(kin / eref)
+
+
+def bf16_round(w):
+    """FP32 weights rounded to the nearest BF16 value (ties to even), as FP64: the weights the
+    solver's inference uses."""
+    u = np.ascontiguousarray(np.asarray(w, np.float32)).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16 << 16
+    return (u & 0xFFFFFFFF).astype(np.uint32).view(np.float32).astype(np.float64)
+
+
 def operator_columns(a0):
     """Column statistics of a dense operator: (Re diag, squared off-diagonal column norms)."""
     a0 = np.asarray(a0)

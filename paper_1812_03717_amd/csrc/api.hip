@@ -450,6 +450,8 @@ extern "C" sgw_status sgw_apply_projector(sgw_ctx *ctx, const sgw_ham *h, int n_
   if (!ctx || !h) return fail(SGW_ERR_INVALID_ARG, "sgw_apply_projector: NULL context or Hamiltonian");
   if (n_vec < 0 || n_occ < 0) return fail(SGW_ERR_INVALID_ARG, "sgw_apply_projector: negative size");
   if (mode != 0 && mode != 1) return fail(SGW_ERR_INVALID_ARG, "sgw_apply_projector: mode must be 0 or 1");
+  if (n_occ > kMaxOcc)
+    return fail(SGW_ERR_UNSUPPORTED, "sgw_apply_projector: n_occ above " + std::to_string(kMaxOcc));
   if (n_vec == 0) return SGW_OK;
   if (!x || !y || (n_occ > 0 && !psi)) return fail(SGW_ERR_INVALID_ARG, "sgw_apply_projector: NULL array");
   if (x == y) return fail(SGW_ERR_INVALID_ARG, "sgw_apply_projector: x and y alias");
@@ -481,6 +483,7 @@ extern "C" sgw_status sgw_build_rhs(sgw_ctx *ctx, const sgw_ham *h_kq, int n_occ
                                     const int32_t *dv_miller, sgw_c128 *b) {
   if (!ctx || !h_kq || !h_k) return fail(SGW_ERR_INVALID_ARG, "sgw_build_rhs: NULL context or Hamiltonian");
   if (n_occ < 0 || n_band < 0 || n_pert < 0) return fail(SGW_ERR_INVALID_ARG, "sgw_build_rhs: negative size");
+  if (n_occ > kMaxOcc) return fail(SGW_ERR_UNSUPPORTED, "sgw_build_rhs: n_occ above " + std::to_string(kMaxOcc));
   const int nvec = n_band * n_pert;
   if (nvec == 0) return SGW_OK;
   if (!psi_v || !dv_miller || !b || (n_occ > 0 && !psi_occ_kq))
@@ -778,6 +781,25 @@ static sgw_opts tail_phase_opts(const sgw_opts &o) {
   return m;
 }
 
+// Options of the FP64 per-shift refinement that may follow a plain multishift solve: as many per-shift
+// slots as fit in the multishift phase's own workspace (few shifts need it; it must not enlarge the
+// workspace), unless the caller set ps_slots.
+static sgw_opts refine_opts(const sgw_ham *h_kq, int n_occ, int n_band, int n_pert, int n_omega,
+                            const sgw_opts &o) {
+  sgw_opts r = o;
+  if (o.ps_slots > 0) return r;
+  const size_t ms = make_layout(h_kq, n_occ, n_band, n_pert, n_omega, o).total;
+  const long n_sys = (long)n_band * n_pert * n_omega;
+  const int n_sys_i = (int)std::min<long>(n_sys, 1L << 30);
+  int B = (int)std::max<long>(1, std::min<long>(n_sys, 8192));
+  for (;;) {
+    r.ps_slots = B;
+    if (B == 1 || ps_workspace_bytes(h_kq, n_occ, n_band, n_pert, n_omega, r, n_sys_i) <= ms) break;
+    B = std::max(1, B * 3 / 4);
+  }
+  return r;
+}
+
 static size_t solve_workspace_bytes(const sgw_ham *h_kq, int n_occ, int n_band, int n_pert, int n_omega,
                                     const sgw_opts &o) {
   const long n_sys = (long)n_band * n_pert * n_omega;
@@ -788,11 +810,13 @@ static size_t solve_workspace_bytes(const sgw_ham *h_kq, int n_occ, int n_band, 
     case SGW_SOLVER_TAIL:
       return std::max(make_layout(h_kq, n_occ, n_band, n_pert, n_omega, tail_phase_opts(o)).total,
                       ps_workspace_bytes(h_kq, n_occ, n_band, n_pert, n_omega, o, n_sys_i));
-    default:
-      if (o.precision == SGW_MIXED)  // FP64 per-shift refinement after the mixed multishift phase
-        return std::max(make_layout(h_kq, n_occ, n_band, n_pert, n_omega, o).total,
-                        ps_workspace_bytes(h_kq, n_occ, n_band, n_pert, n_omega, o, n_sys_i));
-      return make_layout(h_kq, n_occ, n_band, n_pert, n_omega, o).total;
+    default:  // FP64 per-shift refinement after the multishift phase reuses the workspace
+      return std::max(make_layout(h_kq, n_occ, n_band, n_pert, n_omega, o).total,
+                      ps_workspace_bytes(h_kq, n_occ, n_band, n_pert, n_omega,
+                                         o.precision == SGW_MIXED
+                                             ? o
+                                             : refine_opts(h_kq, n_occ, n_band, n_pert, n_omega, o),
+                                         n_sys_i));
   }
 }
 
@@ -1176,11 +1200,13 @@ static sgw_status run_solve(sgw_ctx *ctx, const sgw_problem &p, const sgw_opts &
       return st;
     return n_bad > 0 ? SGW_NOT_CONVERGED : SGW_OK;
   }
-  if (o.solver == SGW_SOLVER_MULTISHIFT && o.precision == SGW_FP64)
-    return multishift_solve(ctx, p.h_kq, p.n_occ, p.psi_occ_kq, p.h_k, p.n_band, p.psi_v, p.eps_v, p.n_pert,
-                            p.dv_miller, p.n_omega, p.omega, p.eta, p.tol, o, workspace, p.dpsi, p.info);
   // TAIL: multishift up to tail_iter; MIXED: multishift with FP32 potential matvecs.  Then the shifts
   // whose true FP64 residual is above tol continue per shift in FP64 from their multishift iterate.
+  // Plain FP64 multishift: only the shifts whose recurrence estimate met the stopping threshold while
+  // the true residual, recomputed from x, missed tol (rounding in the recurrence: tight tolerances
+  // near the FP64 floor of kappa * eps) are refined that way; shifts that hit max_iter or met
+  // non-finite values keep their flags.
+  const bool plain = o.solver == SGW_SOLVER_MULTISHIFT && o.precision == SGW_FP64;
   const sgw_opts o1 = o.solver == SGW_SOLVER_TAIL ? tail_phase_opts(o) : o;
   st = multishift_solve(ctx, p.h_kq, p.n_occ, p.psi_occ_kq, p.h_k, p.n_band, p.psi_v, p.eps_v, p.n_pert,
                         p.dv_miller, p.n_omega, p.omega, p.eta, p.tol, o1, workspace, p.dpsi, p.info);
@@ -1190,13 +1216,23 @@ static sgw_status run_solve(sgw_ctx *ctx, const sgw_problem &p, const sgw_opts &
   SGW_HIP(hipMemcpyAsync(hinfo.data(), p.info, sizeof(sgw_solve_info) * n_sys, hipMemcpyDeviceToHost, ctx->stream));
   if ((st = sync(ctx)) != SGW_OK) return st;
   std::vector<int32_t> tail;
-  for (long y = 0; y < n_sys; ++y)
-    if (!(hinfo[y].flags & SGW_FLAG_CONVERGED)) tail.push_back((int32_t)y);
+  bool left = false;  // a plain solve that stays unconverged whatever the refinement does
+  for (long y = 0; y < n_sys; ++y) {
+    const int fl = hinfo[y].flags;
+    if (fl & SGW_FLAG_CONVERGED) continue;
+    if (plain && (fl & (SGW_FLAG_MAXITER | SGW_FLAG_NONFINITE))) {
+      left = true;
+      continue;
+    }
+    tail.push_back((int32_t)y);
+  }
+  if (tail.empty()) return SGW_NOT_CONVERGED;
   int n_bad = 0;
-  if ((st = ps_solve(ctx, P, o, tail, true, workspace, workspace_bytes, (double2 *)p.dpsi, p.info, &n_bad)) !=
+  const sgw_opts o2 = plain ? refine_opts(p.h_kq, p.n_occ, p.n_band, p.n_pert, std::max(p.n_omega, 1), o) : o;
+  if ((st = ps_solve(ctx, P, o2, tail, true, workspace, workspace_bytes, (double2 *)p.dpsi, p.info, &n_bad)) !=
       SGW_OK)
     return st;
-  return n_bad > 0 ? SGW_NOT_CONVERGED : SGW_OK;
+  return (n_bad > 0 || left) ? SGW_NOT_CONVERGED : SGW_OK;
 }
 
 extern "C" sgw_status sternheimer_solve(sgw_ctx *ctx, const sgw_ham *h_kq, int n_occ, const sgw_c128 *psi_occ_kq,

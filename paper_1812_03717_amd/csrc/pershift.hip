@@ -12,6 +12,7 @@
 //            (Teter, Payne, Allan, Phys. Rev. B 40, 12255 (1989)), E_ref = <b|T|b>/<b|b>
 //   learned: (m, g) from the MLP of each plane wave's features, M_G = m_G, x0 = g (.) b
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <numeric>
 #include <string>
@@ -656,3 +657,65 @@ sgw_status ps_solve(sgw_ctx *ctx, const PsProblem &P, const sgw_opts &o, const s
 }
 
 }  // namespace sgw
+
+// ---------------------------------------------------------------------------
+// test hook: the diagonal preconditioner and initial guess of the per-shift solves
+// ---------------------------------------------------------------------------
+namespace {
+struct HookBuf {
+  void *p = nullptr;
+  ~HookBuf() {
+    if (p) hipFree(p);
+  }
+};
+}  // namespace
+
+extern "C" sgw_status sgw_precond_values(sgw_ctx *ctx, const sgw_ham *ham, int precond, int guess,
+                                         const sgw_mlp *mlp, int n_vec, const double *eps, const double *omega,
+                                         double eta, const sgw_c128 *b, sgw_c128 *m_out, sgw_c128 *x0_out) {
+  using namespace sgw;
+  if (!ctx || !ham) return fail(SGW_ERR_INVALID_ARG, "sgw_precond_values: NULL context or Hamiltonian");
+  if (n_vec < 0) return fail(SGW_ERR_INVALID_ARG, "sgw_precond_values: n_vec < 0");
+  if (precond < SGW_PC_NONE || precond > SGW_PC_LEARNED)
+    return fail(SGW_ERR_INVALID_ARG, "sgw_precond_values: unknown preconditioner");
+  if (guess != SGW_GUESS_ZERO && guess != SGW_GUESS_LEARNED)
+    return fail(SGW_ERR_INVALID_ARG, "sgw_precond_values: unknown initial guess");
+  if ((precond == SGW_PC_LEARNED || guess == SGW_GUESS_LEARNED) && (!mlp || mlp->device != ctx->device))
+    return fail(SGW_ERR_INVALID_ARG, "sgw_precond_values: the learned model needs an sgw_mlp of this device");
+  if (n_vec == 0) return SGW_OK;
+  if (!eps || !omega || !b || !m_out || !x0_out) return fail(SGW_ERR_INVALID_ARG, "sgw_precond_values: NULL array");
+  if (!std::isfinite(eta)) return fail(SGW_ERR_INVALID_ARG, "sgw_precond_values: eta not finite");
+  SGW_HIP(hipSetDevice(ctx->device));
+  const int npw = ham->n_pw;
+  const size_t vb = sizeof(double2) * (size_t)npw * n_vec;
+  HookBuf vec, par, lst;
+  SGW_HIP(hipMalloc(&vec.p, 3 * vb));
+  SGW_HIP(hipMalloc(&par.p, 3 * sizeof(double) * n_vec));
+  SGW_HIP(hipMalloc(&lst.p, sizeof(int32_t) * n_vec));
+  PsState S{};
+  S.npw = npw;
+  S.b = (double2 *)vec.p;
+  S.m = S.b + (size_t)npw * n_vec;
+  S.x = S.m + (size_t)npw * n_vec;
+  S.eps = (double *)par.p;
+  S.zr = S.eps + n_vec;
+  S.zi = S.zr + n_vec;
+  std::vector<double> hp(3 * (size_t)n_vec);
+  std::vector<int32_t> hl(n_vec);
+  for (int a = 0; a < n_vec; ++a) {
+    hp[a] = eps[a];
+    hp[n_vec + a] = omega[a];
+    hp[2 * n_vec + a] = eta;
+    hl[a] = a;
+  }
+  SGW_HIP(hipMemcpyAsync(par.p, hp.data(), sizeof(double) * hp.size(), hipMemcpyHostToDevice, ctx->stream));
+  SGW_HIP(hipMemcpyAsync(lst.p, hl.data(), sizeof(int32_t) * n_vec, hipMemcpyHostToDevice, ctx->stream));
+  sgw_status st;
+  if ((st = permute(ctx, npw, n_vec, (const double2 *)b, npw, S.b, npw, ham->d_i2u, 0)) != SGW_OK) return st;
+  if ((st = ps_precond(ctx, S, n_vec, (const int32_t *)lst.p, ham->d_kin, precond, mlp,
+                       guess == SGW_GUESS_LEARNED ? 1 : 0)) != SGW_OK)
+    return st;
+  if ((st = permute(ctx, npw, n_vec, S.m, npw, (double2 *)m_out, npw, ham->d_i2u, 1)) != SGW_OK) return st;
+  if ((st = permute(ctx, npw, n_vec, S.x, npw, (double2 *)x0_out, npw, ham->d_i2u, 1)) != SGW_OK) return st;
+  return sync(ctx);
+}

@@ -36,7 +36,7 @@ EXPORTED = [
     "sternheimer_workspace_size", "sternheimer_solve", "sgw_mlp_num_params", "sgw_mlp_create",
     "sgw_mlp_destroy", "sgw_mlp_get_weights", "sgw_mlp_set_weights", "sgw_mlp_forward", "sgw_mlp_grad",
     "sgw_mlp_train_step", "sgw_operator_columns", "sgw_mlp_rows", "sternheimer_batch_workspace_size",
-    "sternheimer_solve_batch", "sgw_autotune",
+    "sternheimer_solve_batch", "sgw_autotune", "sgw_precond_values",
 ]
 
 
@@ -114,6 +114,8 @@ def load_library(path: str = LIB_PATH):
         "sternheimer_solve_batch": [vp, C.c_int, C.POINTER(sgw_problem), C.c_int, vp, sz],
         "sgw_autotune": [vp, C.POINTER(sgw_problem), C.POINTER(sgw_opts), C.POINTER(dbl)],
         "sgw_mlp_rows": [vp, vp, vp, vp, C.c_int, C.POINTER(dbl), C.POINTER(dbl), dbl, vp, vp, C.c_int, vp, vp],
+        "sgw_precond_values": [vp, vp, C.c_int, C.c_int, vp, C.c_int, C.POINTER(dbl), C.POINTER(dbl), dbl, vp, vp,
+                               vp],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -513,3 +515,21 @@ def sgw_mlp_rows(ctx, ham, diag, off2, eps, omega, eta, r, b, stride=1):
                                        om.ctypes.data_as(C.POINTER(C.c_double)), float(eta), _ptr(r), _ptr(b),
                                        int(stride), _ptr(feat), _ptr(tgt)))
     return feat, tgt
+
+
+def sgw_precond_values(ctx, ham, precond, b, eps, omega, eta, guess=0, mlp=None):
+    """(m, x0): device complex128 [n_vec][n_pw], the per-shift solver's diagonal preconditioner and
+    initial guess for right-hand sides b (caller's order), band energies eps and frequencies omega."""
+    import torch
+    n_vec = int(b.shape[0])
+    _require(b, torch.complex128, ctx.device, (n_vec, ham.n_pw), "b")
+    e = np.ascontiguousarray(np.asarray(eps, np.float64).reshape(n_vec))
+    om = np.ascontiguousarray(np.asarray(omega, np.float64).reshape(n_vec))
+    m = torch.empty_like(b)
+    x0 = torch.empty_like(b)
+    _check(load_library().sgw_precond_values(ctx.handle, ham.handle, int(precond), int(guess),
+                                             mlp.handle if mlp is not None else C.c_void_p(0), n_vec,
+                                             e.ctypes.data_as(C.POINTER(C.c_double)),
+                                             om.ctypes.data_as(C.POINTER(C.c_double)), float(eta), _ptr(b),
+                                             _ptr(m), _ptr(x0)))
+    return m, x0

@@ -53,6 +53,10 @@ PROBLEMS = {
     "fcc1_g64": lambda: synth.small((1, 1, 1), grid=(64, 64, 64), n_omega=4, n_pert=2, seed=9700),
     # 48 x 48 planes, 24-point sticks: whole-line kernels
     "fcc221_g48": lambda: synth.small((2, 2, 1), n_omega=4, n_pert=2, seed=9400, ecut=6.0),
+    # 32^3: whole-line plane and stick kernels on 32-point lines (8 x 4 splits)
+    "fcc1_g32": lambda: synth.small((1, 1, 1), grid=(32, 32, 32), n_omega=4, n_pert=2, seed=9900),
+    # 32 x 48 planes, 24-point sticks: 32-point columns beside 48-point rows in one plane
+    "fcc1_g32x48x24": lambda: synth.small((1, 1, 1), grid=(32, 48, 24), n_omega=4, n_pert=2, seed=9950),
 }
 
 
@@ -73,7 +77,8 @@ def test_apply_h_matches_dense(ctx, name):
         assert err <= 1e-12
 
 
-@pytest.mark.parametrize("name", ["si2", "fcc1_q", "fcc1_g64", "fcc1_g72", "fcc312_g72", "fcc131_g72"])
+@pytest.mark.parametrize("name", ["si2", "fcc1_q", "fcc1_g64", "fcc1_g72", "fcc312_g72", "fcc131_g72", "fcc1_g32",
+                                  "fcc1_g32x48x24"])
 def test_apply_h_each_plane_kernel(ctx, name):
     """Every plane-pass kernel that applies to the grid, forced through sgw_ctx_set_fft_planes, gives
     H.x to rounding; the whole-plane LDS kernel applies everywhere, the two-thread kernel wherever the

@@ -176,6 +176,53 @@ def test_per_shift_edge_cases(ctx):
         d.solve(tol=1e-8, opts=sgw.sgw_opts_default(solver=sgw.SOLVER_PER_SHIFT, precond=sgw.PC_LEARNED))
 
 
+@pytest.mark.parametrize("mode", ["teter", "learned"])
+def test_precond_values_match_oracle(ctx, case, mode):
+    """The per-shift solver's diagonal preconditioner and learned initial guess, element by element, from
+    the kernel the solver runs (sgw_precond_values), against oracle.mlp_oracle: the Teter diagonal with
+    the kinetic energy of b as reference to 1e-14; the model with BF16-rounded weights in FP32
+    arithmetic to 2e-5 of the largest value (FP32 rounding of the features and of 64-term sums)."""
+    from paper_1812_03717_amd import sgw
+    p, d, pairs, xs, tol = case
+    n = d.h_kq.n_pw
+    b = sgw.sgw_build_rhs(ctx, d.h_kq, d.psi_occ_kq, d.h_k, d.psi_v, p.dv_miller).reshape(-1, n).contiguous()
+    n_vec = int(b.shape[0])
+    rng = np.random.default_rng(22)
+    eps = p.eps_k[np.arange(n_vec) // p.n_pert]
+    omega = rng.choice(p.omega, n_vec)
+    kin = so.kinetic(p.miller_kq, p.B, p.kvec + p.qvec)
+    bh = b.cpu().numpy()
+    if mode == "teter":
+        m, x0 = sgw.sgw_precond_values(ctx, d.h_kq, sgw.PC_TETER, b, eps, omega, p.eta)
+        m = m.cpu().numpy()
+        ref = np.array([mo.teter_diagonal(kin, bh[a]) for a in range(n_vec)])
+        err = np.abs(m - ref).max()
+        print("teter: max abs err", err, flush=True)
+        assert err <= 1e-14
+        assert torch.count_nonzero(x0).item() == 0
+        m1, _ = sgw.sgw_precond_values(ctx, d.h_kq, sgw.PC_NONE, b, eps, omega, p.eta)
+        assert torch.all(m1 == 1.0)
+        return
+    mlp = sgw.sgw_mlp_create(ctx, seed=7)
+    w = mlp.get_weights() + 0.2 * rng.standard_normal(sgw.sgw_mlp_num_params()).astype(np.float32)
+    mlp.set_weights(w)
+    m, x0 = sgw.sgw_precond_values(ctx, d.h_kq, sgw.PC_LEARNED, b, eps, omega, p.eta, guess=sgw.GUESS_LEARNED,
+                                   mlp=mlp)
+    m, x0 = m.cpu().numpy(), x0.cpu().numpy()
+    wb = mo.bf16_round(mlp.get_weights())
+    worst_m = worst_x = 0.0
+    for a in range(n_vec):
+        mr, gr = mo.model_outputs(wb, mo.features(kin, eps[a], omega[a], p.eta))
+        worst_m = max(worst_m, np.abs(m[a] - mr).max() / np.abs(mr).max())
+        xr = gr * bh[a]
+        worst_x = max(worst_x, np.abs(x0[a] - xr).max() / np.abs(xr).max())
+    print(f"learned: preconditioner rel err {worst_m:.2e}, guess rel err {worst_x:.2e}", flush=True)
+    assert worst_m <= 2e-5 and worst_x <= 2e-5
+    # the FP32 master weights differ from the BF16 ones the solver uses: the check sees the rounding
+    mr32, _ = mo.model_outputs(np.asarray(w, np.float64), mo.features(kin, eps[0], omega[0], p.eta))
+    assert np.abs(m[0] - mr32).max() / np.abs(mr32).max() > 1e-4
+
+
 def test_operator_columns_and_rows(ctx, case):
     """Column statistics of H + alpha P and the training rows built from them, against the oracle."""
     from paper_1812_03717_amd import sgw

@@ -1,0 +1,70 @@
+"""Full-size parity on the 64-atom workload (conventional cubic 2x2x2 diamond cell, 16,013 plane
+waves at k+q, 72^3 grid, 128 occupied bands x 20 perturbations x 100 frequencies in [0, 40] eV,
+eta 0.05 eV, tol 1e-8): 256,000 solves in the launch configuration bench.py times (plain FP64,
+max_iter 3500, default slots).
+
+Every solve must report a true FP64 relative residual <= tol, the converged flag and a negligible
+occupied component.  Sampled outputs are checked against the oracle's direct LU solve of the
+shifted operator (Sec. 2.3, Eqs. 6-8) on the host: the top occupied band, whose shifts near
+omega = 0 are the nearest to resonance, four perturbations, at omega = 0 (one LU factorisation of
+the 16,013 x 16,013 operator serves the four right-hand sides).  Bound: for a Hermitian operator
+with a complex shift every singular value of H - eps - z is at least |Im z| = eta, so
+||x - x*|| <= ||r|| / eta = relres ||b|| / eta.
+"""
+import numpy as np
+import pytest
+
+import oracle.sternheimer_oracle as so
+import synth
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+MAX_ITER = 3500
+
+
+@pytest.fixture(scope="module")
+def setup():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from tests.libutil import ensure_library
+    ensure_library()
+    from paper_1812_03717_amd import sgw
+    from paper_1812_03717_amd.workload import DeviceProblem
+    p = synth.si64()
+    ctx = sgw.sgw_ctx_create(0)
+    dev = DeviceProblem(ctx, p)
+    print(f"si64: {p.n_pw_kq} PW, n_occ {p.n_occ}, {p.n_solves} solves", flush=True)
+    return p, ctx, dev
+
+
+@pytest.mark.timeout(900)
+def test_si64_full_workload_sampled_vs_lu(setup):
+    from paper_1812_03717_amd import sgw
+    p, ctx, dev = setup
+    st, dpsi, info = dev.solve(opts=sgw.sgw_opts_default(max_iter=MAX_ITER))
+    torch.cuda.synchronize()
+    inf = sgw.info_to_numpy(info, (p.n_band, p.n_pert, p.n_omega))
+    print(f"si64 full: status {st}; iters {inf['iters'].min()}..{inf['iters'].max()}; "
+          f"max relres {inf['relres'].max():.3e}; max occ leak {inf['occ_leak'].max():.3e}", flush=True)
+    assert st == sgw.SGW_OK
+    assert np.all(inf["flags"] & sgw.FLAG_CONVERGED)
+    assert inf["relres"].max() <= p.tol
+    assert inf["occ_leak"].max() <= 1e-9
+    v, j = p.n_band - 1, 0
+    perts = [0, 5, 11, 19]
+    xs = dpsi[v, perts, j].cpu().numpy()
+    del dpsi
+    torch.cuda.empty_cache()
+    # the oracle on the host: dense H_{k+q}, the shifted operator, one LU for the four right-hand sides
+    h = so.hamiltonian(p.miller_kq, p.B, p.kvec + p.qvec, p.v_grid)
+    a0 = so.coulomb_operator(h, p.psi_kq, p.eps_k[v], 1.0)
+    del h
+    bs = np.array([so.rhs(p.psi_k[v], p.miller_k, p.miller_kq, p.dv_miller[q], p.psi_kq) for q in perts])
+    ref = so.solve_lu(a0, bs.T, p.omega[j] + 1j * p.eta).T
+    for i, q in enumerate(perts):
+        err = np.linalg.norm(xs[i] - ref[i])
+        bound = inf["relres"][v, q, j] * np.linalg.norm(bs[i]) / p.eta
+        print(f"  (v={v}, p={q}, omega={p.omega[j]:.3f}): |x - x*| = {err:.3e}, budget {bound:.3e}, "
+              f"rel err {err / np.linalg.norm(ref[i]):.3e}", flush=True)
+        assert err <= 1.01 * bound + 1e-12 * np.linalg.norm(ref[i])

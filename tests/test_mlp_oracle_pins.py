@@ -79,6 +79,29 @@ def check_teter():
     assert np.all(np.diff(k) < 0)
 
 
+def check_teter_diagonal():
+    """A right-hand side on one plane wave has E_ref = T_G there, so K = K(1) = 65/81 at that G; for
+    equal weights E_ref is the mean kinetic energy; the weights are |b|^2, not |b|."""
+    kin = np.array([0.5, 2.0, 4.0, 9.5])
+    b = np.array([0, 0, 3 - 4j, 0])
+    assert abs(mo.teter_diagonal(kin, b)[2] - 65.0 / 81.0) < 1e-15
+    ones = np.ones(4, complex)
+    assert np.allclose(mo.teter_diagonal(kin, ones), mo.teter(kin / kin.mean()), rtol=1e-15, atol=0)
+    b2 = np.array([1.0, 2.0, 0.0, 0.0])       # E_ref = (0.5 + 4 * 2) / 5 = 1.7
+    assert np.allclose(mo.teter_diagonal(kin, b2), mo.teter(kin / 1.7), rtol=1e-15, atol=0)
+
+
+def check_bf16_round():
+    """BF16 keeps 8 significant bits: exact values stay, halfway cases go to the even neighbour."""
+    x = np.array([1.0, -2.5, 1 + 2 ** -8, 1 + 3 * 2 ** -8, 1 + 2 ** -7 + 2 ** -9, 3.0e-5], np.float32)
+    r = mo.bf16_round(x)
+    assert r[0] == 1.0 and r[1] == -2.5
+    assert r[2] == 1.0                        # tie: 1 (even) rather than 1 + 2^-7
+    assert r[3] == 1 + 2 ** -6                # tie: 1 + 2^-6 (even) rather than 1 + 2^-7
+    assert r[4] == 1 + 2 ** -7                # below the midpoint to 1 + 2^-6
+    assert abs(r[5] - 3.0e-5) <= 2 ** -9 * 3.0e-5
+
+
 def check_operator_columns():
     """2x2 Hermitian [[1, 2+i], [2-i, 3]]: diagonal (1, 3), off-diagonal column norms (5, 5);
     and the column sums add up to the Frobenius norm of a random matrix."""
@@ -120,7 +143,7 @@ def check_rows_give_spai_objective():
 
 
 PINS = [check_fd_gradient, check_output_bias_closed_form, check_layer_orientation, check_features, check_teter,
-        check_operator_columns, check_rows_give_spai_objective]
+        check_operator_columns, check_rows_give_spai_objective, check_teter_diagonal, check_bf16_round]
 
 
 @pytest.mark.parametrize("pin", PINS, ids=lambda f: f.__name__)
@@ -129,7 +152,7 @@ def test_pin(pin):
 
 
 _orig = {name: getattr(mo, name) for name in ("grad", "loss", "forward", "features", "teter", "scale", "rows",
-                                              "spai_optimum", "operator_columns")}
+                                              "spai_optimum", "operator_columns", "teter_diagonal", "bf16_round")}
 
 
 def _rows_conj_d(kin, diag, off2, eps, omega, eta, r, b, stride=1):
@@ -163,6 +186,10 @@ MUTATIONS = {
     "rows_shift_sign": ("rows", _rows_conj_d),
     "spai_no_conj": ("spai_optimum", lambda d, c: d / (np.abs(d) ** 2 + c)),
     "columns_keep_diag": ("operator_columns", lambda a: (np.diag(a).real.copy(), np.sum(np.abs(a) ** 2, axis=0))),
+    "teter_eref_abs_weights": ("teter_diagonal", lambda kin, b: mo.teter(
+        np.asarray(kin) / (np.sum(np.asarray(kin) * np.abs(b)) / np.sum(np.abs(b))))),
+    "bf16_truncates": ("bf16_round", lambda w: (np.ascontiguousarray(np.asarray(w, np.float32)).view(np.uint32)
+                                                & np.uint32(0xFFFF0000)).view(np.float32).astype(np.float64)),
 }
 
 
