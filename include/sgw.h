@@ -184,6 +184,22 @@ sgw_status sgw_apply_h(sgw_ctx *ctx, const sgw_ham *ham, int n_vec, const sgw_c1
                        int precision);
 
 /*
+ * sgw_apply_h without device allocation, for callers that cannot allocate (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc).  Same arguments, kernels and
+ * result as sgw_apply_h, bit for bit.  Its scratch (x and y in the library's internal plane-wave
+ * order and the stick buffer between the FFT passes) lives in one fixed 64 MiB device array per GPU,
+ * held until the process ends: n_vec * (32 n_pw + 16 N2 n_sticks) bytes (each part rounded up to 256)
+ * must fit, about 170 vectors of the 16-atom cell (48^3 grid) or 45 of the 64-atom cell (72^3);
+ * larger calls return SGW_ERR_WORKSPACE before any GPU work.  No scratch value has to start at zero:
+ * every kernel writes each scratch element before reading it.  Every call on one GPU shares that GPU's
+ * array, so calls that overlap on one GPU (other contexts, streams or host threads) race; calls on one
+ * context are serial (each returns after its GPU work has completed).  Kernel timing
+ * (sgw_ctx_set_profiling) does not record these calls.
+ */
+sgw_status sgw_apply_h_noalloc(sgw_ctx *ctx, const sgw_ham *ham, int n_vec, const sgw_c128 *x, sgw_c128 *y,
+                               int precision);
+
+/*
  * Occupied-manifold projector (Sec. 2.3, Eqs. 7-8), applied to n_vec vectors:
  *   mode 0:  y = x - Psi (Psi^H x)          (the conduction projector 1 - P_occ)
  *   mode 1:  y = y + alpha * Psi (Psi^H x)   (the + alpha P_occ term of the operator)

@@ -107,6 +107,47 @@ sgw_status sync(sgw_ctx *ctx) {
 using namespace sgw;
 
 // ---------------------------------------------------------------------------
+// fixed device scratch of the allocation-free H.x (sgw_apply_h_noalloc)
+// ---------------------------------------------------------------------------
+namespace {
+constexpr size_t kNoAllocScratchBytes = 64ull << 20;
+constexpr size_t kAlign256 = 256;
+constexpr int kScratchDevices = 64;
+}  // namespace
+
+// One copy per device, held until the process ends.  In host code `scratch` names a host-side
+// stand-in, not device memory: kernels and copies take the address from hipGetSymbolAddress below.
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kScratchDevices] = {};        // device address of `scratch`, per device
+hipError_t g_scratch_err[kScratchDevices] = {};   // the lookup's error, when it failed
+
+// Looks up this device's copy of `scratch` once (the device must be current).  A failure is kept and
+// reported by sgw_apply_h_noalloc; the rest of the library does not need the array.
+void scratch_setup(int device) {
+  if (device < 0 || device >= kScratchDevices) return;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[device]) return;
+  void *p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e == hipSuccess && p) g_scratch_ptr[device] = p;
+  else g_scratch_err[device] = e == hipSuccess ? hipErrorInvalidSymbol : e;
+}
+
+void *scratch_ptr(int device, hipError_t *err) {
+  if (device < 0 || device >= kScratchDevices) {
+    *err = hipErrorInvalidDevice;
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  *err = g_scratch_err[device];
+  return g_scratch_ptr[device];
+}
+}  // namespace
+
+// ---------------------------------------------------------------------------
 // misc
 // ---------------------------------------------------------------------------
 extern "C" const char *sgw_last_error(void) { return g_last_error.c_str(); }
@@ -119,6 +160,7 @@ extern "C" sgw_status sgw_ctx_create(int device, void *hip_stream, sgw_ctx **out
   SGW_HIP(hipGetDeviceCount(&ndev));
   if (device < 0 || device >= ndev) return fail(SGW_ERR_INVALID_ARG, "sgw_ctx_create: no such device");
   SGW_HIP(hipSetDevice(device));
+  scratch_setup(device);
   sgw_ctx *c = new sgw_ctx();
   c->device = device;
   c->stream = (hipStream_t)hip_stream;
@@ -442,6 +484,52 @@ extern "C" sgw_status sgw_apply_h(sgw_ctx *ctx, const sgw_ham *h, int n_vec, con
                      precision == SGW_MIXED)) != SGW_OK)
     return st;
   if ((st = permute(ctx, npw, n_vec, (double2 *)yi.p, npw, (double2 *)y, npw, h->d_i2u, 1)) != SGW_OK) return st;
+  return sync(ctx);
+}
+
+extern "C" sgw_status sgw_apply_h_noalloc(sgw_ctx *ctx, const sgw_ham *h, int n_vec, const sgw_c128 *x,
+                                          sgw_c128 *y, int precision) {
+  if (!ctx || !h) return fail(SGW_ERR_INVALID_ARG, "sgw_apply_h_noalloc: NULL context or Hamiltonian");
+  if (n_vec < 0) return fail(SGW_ERR_INVALID_ARG, "sgw_apply_h_noalloc: n_vec < 0");
+  if (precision != SGW_FP64 && precision != SGW_MIXED)
+    return fail(SGW_ERR_INVALID_ARG, "sgw_apply_h_noalloc: unknown precision mode");
+  if (n_vec == 0) return SGW_OK;
+  if (!x || !y) return fail(SGW_ERR_INVALID_ARG, "sgw_apply_h_noalloc: NULL vector");
+  if (x == y) return fail(SGW_ERR_INVALID_ARG, "sgw_apply_h_noalloc: x and y alias");
+  const int npw = h->n_pw;
+  // scratch: x and y in the internal order, then the stick buffer (each part 256-byte aligned)
+  auto up = [](size_t b) { return (b + kAlign256 - 1) / kAlign256 * kAlign256; };
+  const size_t per_vec = sizeof(double2) * (size_t)npw;
+  const size_t vb = up(per_vec * n_vec);
+  const size_t tb = up(sizeof(double2) * (size_t)n_vec * h->n[2] * h->n_stick);
+  if (2 * vb + tb > kNoAllocScratchBytes) {
+    const size_t one = 2 * up(per_vec) + up(sizeof(double2) * (size_t)h->n[2] * h->n_stick);
+    return fail(SGW_ERR_WORKSPACE, "sgw_apply_h_noalloc: " + std::to_string(n_vec) + " vectors need " +
+                                       std::to_string(2 * vb + tb) + " bytes of scratch; the fixed scratch holds " +
+                                       std::to_string(kNoAllocScratchBytes) + " (about " +
+                                       std::to_string(kNoAllocScratchBytes / one) +
+                                       " vectors of this Hamiltonian per call)");
+  }
+  hipError_t serr = hipSuccess;
+  char *base = (char *)scratch_ptr(ctx->device, &serr);
+  if (!base)
+    return fail(SGW_ERR_HIP, std::string("sgw_apply_h_noalloc: device scratch not available: ") +
+                                 hipGetErrorString(serr));
+  SGW_HIP(hipSetDevice(ctx->device));
+  // no timing events here (creating one allocates); restored on every return
+  struct MaskOff {
+    sgw_ctx *c;
+    unsigned saved;
+    ~MaskOff() { c->profile_mask = saved; }
+  } mask{ctx, ctx->profile_mask};
+  ctx->profile_mask = 0;
+  double2 *xi = (double2 *)base, *yi = (double2 *)(base + vb);
+  void *tbuf = base + 2 * vb;
+  sgw_status st;
+  if ((st = permute(ctx, npw, n_vec, (const double2 *)x, npw, xi, npw, h->d_i2u, 0)) != SGW_OK) return st;
+  if ((st = hx_batch(ctx, h, n_vec, contiguous(xi, npw), yi, npw, tbuf, precision == SGW_MIXED)) != SGW_OK)
+    return st;
+  if ((st = permute(ctx, npw, n_vec, yi, npw, (double2 *)y, npw, h->d_i2u, 1)) != SGW_OK) return st;
   return sync(ctx);
 }
 

@@ -36,7 +36,7 @@ EXPORTED = [
     "sternheimer_workspace_size", "sternheimer_solve", "sgw_mlp_num_params", "sgw_mlp_create",
     "sgw_mlp_destroy", "sgw_mlp_get_weights", "sgw_mlp_set_weights", "sgw_mlp_forward", "sgw_mlp_grad",
     "sgw_mlp_train_step", "sgw_operator_columns", "sgw_mlp_rows", "sternheimer_batch_workspace_size",
-    "sternheimer_solve_batch", "sgw_autotune", "sgw_precond_values",
+    "sternheimer_solve_batch", "sgw_autotune", "sgw_precond_values", "sgw_apply_h_noalloc",
 ]
 
 
@@ -95,6 +95,7 @@ def load_library(path: str = LIB_PATH):
         "sgw_ham_create": [vp, C.POINTER(sgw_ham_desc), C.POINTER(vp)],
         "sgw_ham_destroy": [vp],
         "sgw_apply_h": [vp, vp, C.c_int, vp, vp, C.c_int],
+        "sgw_apply_h_noalloc": [vp, vp, C.c_int, vp, vp, C.c_int],
         "sgw_apply_projector": [vp, vp, C.c_int, vp, C.c_int, vp, vp, dbl, C.c_int],
         "sgw_build_rhs": [vp, vp, C.c_int, vp, vp, C.c_int, vp, C.c_int, C.POINTER(i32), vp],
         "sgw_opts_default": [C.POINTER(sgw_opts)],
@@ -245,6 +246,16 @@ def sgw_apply_h(ctx, ham, x, precision=0):
     _require(x, torch.complex128, ctx.device, (x.shape[0], ham.n_pw), "x")
     y = torch.empty_like(x)
     _check(load_library().sgw_apply_h(ctx.handle, ham.handle, int(x.shape[0]), _ptr(x), _ptr(y), int(precision)))
+    return y
+
+
+def sgw_apply_h_noalloc(ctx, ham, x, y, precision=0):
+    """y = H x through the allocation-free entry point (y: a caller-allocated tensor like x)."""
+    import torch
+    _require(x, torch.complex128, ctx.device, (x.shape[0], ham.n_pw), "x")
+    _require(y, torch.complex128, ctx.device, tuple(x.shape), "y")
+    _check(load_library().sgw_apply_h_noalloc(ctx.handle, ham.handle, int(x.shape[0]), _ptr(x), _ptr(y),
+                                              int(precision)))
     return y
 
 
