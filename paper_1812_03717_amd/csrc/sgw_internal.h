@@ -173,7 +173,9 @@ struct FftScope {
 // Projector pieces (internal order, FP64 MFMA).  The overlaps are produced as
 // partial sums over plane-wave chunks: cp[chunk][a][i] for chunk < n_chunks,
 // a < n_vec (leading dimension `rows` >= n_vec), i < n_occ.
-constexpr int kProjChunks = 16;
+constexpr int kProjChunks = 64;
+// plane waves per overlap chunk: chunk c holds plane waves [c * kProjChunkLen, (c + 1) * kProjChunkLen)
+constexpr int kProjChunkLen = 256;
 // worker streams of a batch solve
 constexpr int kMaxWorkers = 16;
 // number of chunks for n_pw plane waves; *kc receives the chunk length
