@@ -315,6 +315,31 @@ sgw_status sternheimer_solve(sgw_ctx *ctx, const sgw_ham *h_kq, int n_occ, const
                              size_t workspace_bytes, sgw_c128 *dpsi, sgw_solve_info *info);
 
 /*
+ * Green's function columns (Sec. 2.2, Eqs. 2-3): for every column index c < n_col and frequency
+ * j < n_omega, the solution of
+ *
+ *   (H_k - z_j) G_{.G'}(z_j) = -e_{G'},   G' = cols[c],   z_j = omega[j] + i*eta,
+ *
+ * i.e. column G' of G(z_j) = (z_j - H_k)^{-1}, with all frequencies sharing one Krylov space, as in
+ * sternheimer_solve (the same solver, options and flags; no occupied projector, no band energy).
+ * The paper takes the complex frequency on the side that satisfies the time ordering: here the
+ * caller chooses the sign of eta (eta > 0 above the chemical potential, eta < 0 below), one call
+ * per side.
+ * h_k         the Hamiltonian (its basis is the columns' and the solution's basis)
+ * cols        host [n_col], plane-wave indices G' in the caller's order, 0 <= cols[c] < n_pw
+ * omega       host [n_omega] (Ha); eta != 0; tol > 0 as in sternheimer_solve
+ * workspace   device, >= sgw_green_workspace_size bytes, 256-byte aligned
+ * g           device out [n_col][n_omega][n_pw]
+ * info        device out [n_col][n_omega] (relres = ||-e_{G'} - (H - z) x|| since ||e_{G'}|| = 1)
+ * Returns SGW_OK, SGW_NOT_CONVERGED (some solve missed tol; flags tell which) or an error.
+ */
+sgw_status sgw_green_workspace_size(sgw_ctx *ctx, const sgw_ham *h_k, int n_col, int n_omega,
+                                    const sgw_opts *opts, size_t *bytes);
+sgw_status sgw_green_solve(sgw_ctx *ctx, const sgw_ham *h_k, int n_col, const int32_t *cols, int n_omega,
+                           const double *omega, double eta, double tol, const sgw_opts *opts, void *workspace,
+                           size_t workspace_bytes, sgw_c128 *g, sgw_solve_info *info);
+
+/*
  * Batches of independent systems (each a Sternheimer problem of Sec. 2.3,
  * Eqs. 6-8, with its own Hamiltonians, bands, perturbations and frequencies).
  * The arguments of one sternheimer_solve call, plus per-system options and outputs.

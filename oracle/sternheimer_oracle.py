@@ -17,7 +17,9 @@ What it computes (Hartree units; every function cites the passage it follows):
 * the exact solution of every shifted system, by two direct routes: an LU
   solve of the shifted operator, and the sum over all unoccupied eigenstates
   that the Sternheimer approach avoids (Sec. 1 and Sec. 2.2);
-* the relative residual and the condition number used for the error budget.
+* the relative residual and the condition number used for the error budget;
+* the Green's function columns (Sec. 2.2, Eqs. 2-3): (H_k - z) G_{.G'}(z) = -e_{G'},
+  by the sum over all eigenstates that the linear equation replaces.
 
 The Krylov method itself is not reproduced: the iterative solver reaches
 (up to rounding) the exact solution of each shifted system, and that solution
@@ -168,4 +170,32 @@ def relative_residual(a0: np.ndarray, x: np.ndarray, b: np.ndarray, z: complex) 
 def condition_number(evals: np.ndarray, n_occ: int, eps_v: float, z: complex) -> float:
     """kappa of (H - eps_v - z) on the unoccupied space, from the exact spectrum."""
     lam = np.abs(evals[n_occ:] - eps_v - z)
+    return float(lam.max() / lam.min())
+
+
+# ---------------------------------------------------------------------------
+# Green's function (Sec. 2.2, Eqs. 2-3)
+# ---------------------------------------------------------------------------
+
+def green_columns_spectral(evals: np.ndarray, evecs: np.ndarray, cols, zs) -> np.ndarray:
+    """Columns G' = cols of G(z) = (z - H)^{-1}, the solution of (H - z) G_{.G'} = -e_{G'}, as the sum
+    over all eigenstates n of u_n(G) conj(u_n(G')) / (z - eps_n).  Returns [len(cols)][len(zs)][n_pw]."""
+    cols = np.asarray(cols, np.int64)
+    zs = np.atleast_1d(np.asarray(zs, complex))
+    w = evecs[cols, :].conj()                              # [col][n] conj(u_n(G'))
+    coef = w[:, None, :] / (zs[None, :, None] - evals[None, None, :])   # [col][z][n]
+    out = coef.reshape(-1, evals.size) @ evecs.T           # sum over n of u_n(G) coef[col][z][n]
+    return out.reshape(len(cols), len(zs), evecs.shape[0])
+
+
+def green_column_lu(h: np.ndarray, col: int, z: complex) -> np.ndarray:
+    """One column of G(z) by LU: solve (H - z) x = -e_col directly (Eq. 2)."""
+    e = np.zeros(h.shape[0], complex)
+    e[col] = -1.0
+    return sla.solve(h - z * np.eye(h.shape[0]), e)
+
+
+def green_condition_number(evals: np.ndarray, z: complex) -> float:
+    """kappa of H - z over the whole spectrum (no occupied projection in Eq. 3)."""
+    lam = np.abs(evals - z)
     return float(lam.max() / lam.min())

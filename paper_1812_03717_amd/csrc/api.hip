@@ -1352,6 +1352,86 @@ extern "C" sgw_status sternheimer_solve(sgw_ctx *ctx, const sgw_ham *h_kq, int n
 }
 
 // ---------------------------------------------------------------------------
+// Green's function columns (Sec. 2.2, Eqs. 2-3): (H_k - z_j) G_{.G'}(z_j) = -e_{G'}
+// ---------------------------------------------------------------------------
+namespace {
+
+size_t up256(size_t b) { return (b + kAlign - 1) / kAlign * kAlign; }
+
+// The Green's solve is the multishift solve with no occupied states, zero band energy, one
+// perturbation with G_p = 0 and the unit vectors e_{G'} as the "states": its right-hand side is then
+// b = -e_{G'} and its operator H - z.  Workspace: the solve's, then the unit vectors and the columns.
+sgw_problem green_problem(const sgw_ham *h_k, int n_col, int n_omega, const double *omega, double eta, double tol,
+                          const double *eps0, const int32_t *dvm0, sgw_c128 *g, sgw_solve_info *info) {
+  sgw_problem p;
+  std::memset(&p, 0, sizeof(p));
+  p.h_kq = h_k;
+  p.h_k = h_k;
+  p.n_occ = 0;
+  p.n_band = n_col;
+  p.n_pert = 1;
+  p.n_omega = n_omega;
+  p.psi_occ_kq = nullptr;
+  p.psi_v = nullptr;  // the unit vectors, set once they are on the device
+  p.eps_v = eps0;
+  p.dv_miller = dvm0;
+  p.omega = omega;
+  p.eta = eta;
+  p.tol = tol;
+  p.dpsi = g;
+  p.info = info;
+  return p;
+}
+
+}  // namespace
+
+extern "C" sgw_status sgw_green_workspace_size(sgw_ctx *ctx, const sgw_ham *h_k, int n_col, int n_omega,
+                                               const sgw_opts *opts, size_t *bytes) {
+  if (!ctx || !h_k || !bytes) return fail(SGW_ERR_INVALID_ARG, "sgw_green_workspace_size: NULL argument");
+  if (n_col < 0 || n_omega < 0) return fail(SGW_ERR_INVALID_ARG, "sgw_green_workspace_size: negative size");
+  const sgw_opts o = resolve_opts(opts);
+  if (o.solver < SGW_SOLVER_MULTISHIFT || o.solver > SGW_SOLVER_TAIL)
+    return fail(SGW_ERR_INVALID_ARG, "sgw_green_workspace_size: unknown solver");
+  const size_t base = up256(solve_workspace_bytes(h_k, 0, n_col, 1, std::max(n_omega, 1), o));
+  *bytes = base + up256(sizeof(double2) * (size_t)n_col * h_k->n_pw) + up256(sizeof(int32_t) * (size_t)n_col);
+  return SGW_OK;
+}
+
+extern "C" sgw_status sgw_green_solve(sgw_ctx *ctx, const sgw_ham *h_k, int n_col, const int32_t *cols, int n_omega,
+                                      const double *omega, double eta, double tol, const sgw_opts *opts,
+                                      void *workspace, size_t workspace_bytes, sgw_c128 *g, sgw_solve_info *info) {
+  SGW_CHECK(ctx && h_k, "sgw_green_solve: NULL context or Hamiltonian");
+  SGW_CHECK(n_col >= 0 && n_omega >= 0, "sgw_green_solve: negative size");
+  if ((long)n_col * n_omega == 0) return SGW_OK;
+  SGW_CHECK(cols && omega && g && info, "sgw_green_solve: NULL array");
+  const int npw = h_k->n_pw;
+  for (int c = 0; c < n_col; ++c)
+    SGW_CHECK(cols[c] >= 0 && cols[c] < npw, "sgw_green_solve: column index outside the basis");
+  if (!workspace) return fail(SGW_ERR_WORKSPACE, "sgw_green_solve: workspace missing");
+  const sgw_opts o = resolve_opts(opts);
+  const std::vector<double> eps0(n_col, 0.0);
+  const int32_t dvm0[3] = {0, 0, 0};
+  sgw_problem p = green_problem(h_k, n_col, n_omega, omega, eta, tol, eps0.data(), dvm0, g, info);
+  // validation with a stand-in for the device unit vectors (only their presence is checked)
+  p.psi_v = (const sgw_c128 *)workspace;
+  sgw_status st = check_problem(ctx, p, o);
+  if (st != SGW_OK) return st;
+  const size_t base = up256(problem_workspace_bytes(p, o));
+  const size_t need = base + up256(sizeof(double2) * (size_t)n_col * npw) + up256(sizeof(int32_t) * (size_t)n_col);
+  if (!workspace || workspace_bytes < need)
+    return fail(SGW_ERR_WORKSPACE, "sgw_green_solve: workspace needs " + std::to_string(need) + " bytes");
+  if (((uintptr_t)workspace) % kAlign != 0)
+    return fail(SGW_ERR_WORKSPACE, "sgw_green_solve: workspace must be 256-byte aligned");
+  SGW_HIP(hipSetDevice(ctx->device));
+  double2 *unit = (double2 *)((char *)workspace + base);
+  int32_t *dcols = (int32_t *)((char *)unit + up256(sizeof(double2) * (size_t)n_col * npw));
+  SGW_HIP(hipMemcpyAsync(dcols, cols, sizeof(int32_t) * n_col, hipMemcpyHostToDevice, ctx->stream));
+  if ((st = unit_columns(ctx, npw, n_col, dcols, unit)) != SGW_OK) return st;
+  p.psi_v = (const sgw_c128 *)unit;
+  return run_solve(ctx, p, o, workspace, base);
+}
+
+// ---------------------------------------------------------------------------
 // batches of systems and the autotuner
 // ---------------------------------------------------------------------------
 namespace {

@@ -504,6 +504,14 @@ __global__ __launch_bounds__(kRowThreads) void k_residual(SolverState S, const i
   }
 }
 
+// out[a] = e_{cols[a]} (caller's order): the sources of Green's function columns
+__global__ void k_unit_columns(int npw, const int32_t *__restrict__ cols, double2 *__restrict__ out, int tiles) {
+  const int a = blockIdx.x / tiles;
+  const int g = (blockIdx.x - a * tiles) * blockDim.x + threadIdx.x;
+  if (g >= npw) return;
+  out[(long)a * npw + g] = make_double2(g == cols[a] ? 1.0 : 0.0, 0.0);
+}
+
 __global__ void k_transpose_potential(const double *__restrict__ v, double *__restrict__ vt,
                                       float *__restrict__ vt32, int n0, int n1, int n2) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -656,6 +664,14 @@ sgw_status residual(sgw_ctx *ctx, const SolverState &S, const int32_t *flist, in
   hipLaunchKernelGGL(k_residual, dim3((long)nf * S.n_omega), dim3(kRowThreads), 0, ctx->stream, S, flist, X, AX, cp,
                      u2i, dpsi, info, tol, n_bad);
   timing_end(ctx, &tm);
+  SGW_HIP(hipGetLastError());
+  return SGW_OK;
+}
+
+sgw_status unit_columns(sgw_ctx *ctx, int npw, int n_col, const int32_t *cols, double2 *out) {
+  if (n_col <= 0) return SGW_OK;
+  const int tiles = (npw + 255) / 256;
+  hipLaunchKernelGGL(k_unit_columns, dim3((long)tiles * n_col), dim3(256), 0, ctx->stream, npw, cols, out, tiles);
   SGW_HIP(hipGetLastError());
   return SGW_OK;
 }

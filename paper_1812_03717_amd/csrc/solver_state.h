@@ -75,6 +75,8 @@ sgw_status combine(sgw_ctx *ctx, const SolverState &S, const int32_t *flist, int
 sgw_status residual(sgw_ctx *ctx, const SolverState &S, const int32_t *flist, int nf, const double2 *X,
                     const double2 *AX, const double2 *cp, long rows, const int32_t *u2i, double2 *dpsi,
                     sgw_solve_info *info, double tol, int *n_bad);
+// out[a][g] = 1 if g == cols[a] else 0, for a < n_col (device cols, caller's plane-wave order)
+sgw_status unit_columns(sgw_ctx *ctx, int npw, int n_col, const int32_t *cols, double2 *out);
 // plane-major copies of the potential, FP64 and FP32
 sgw_status transpose_potential(sgw_ctx *ctx, const double *v, double *vt, float *vt32, const int n[3]);
 

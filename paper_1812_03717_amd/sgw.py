@@ -37,6 +37,7 @@ EXPORTED = [
     "sgw_mlp_destroy", "sgw_mlp_get_weights", "sgw_mlp_set_weights", "sgw_mlp_forward", "sgw_mlp_grad",
     "sgw_mlp_train_step", "sgw_operator_columns", "sgw_mlp_rows", "sternheimer_batch_workspace_size",
     "sternheimer_solve_batch", "sgw_autotune", "sgw_precond_values", "sgw_apply_h_noalloc",
+    "sgw_green_workspace_size", "sgw_green_solve",
 ]
 
 
@@ -103,6 +104,9 @@ def load_library(path: str = LIB_PATH):
                                        C.POINTER(sz)],
         "sternheimer_solve": [vp, vp, C.c_int, vp, vp, C.c_int, vp, C.POINTER(dbl), C.c_int, C.POINTER(i32),
                               C.c_int, C.POINTER(dbl), dbl, dbl, C.POINTER(sgw_opts), vp, sz, vp, vp],
+        "sgw_green_workspace_size": [vp, vp, C.c_int, C.c_int, C.POINTER(sgw_opts), C.POINTER(sz)],
+        "sgw_green_solve": [vp, vp, C.c_int, C.POINTER(i32), C.c_int, C.POINTER(dbl), dbl, dbl, C.POINTER(sgw_opts),
+                            vp, sz, vp, vp],
         "sgw_mlp_create": [vp, C.POINTER(C.c_float), C.c_uint64, C.POINTER(vp)],
         "sgw_mlp_destroy": [vp],
         "sgw_mlp_get_weights": [vp, C.POINTER(C.c_float)],
@@ -344,6 +348,27 @@ def sternheimer_solve(ctx, h_kq, psi_occ_kq, h_k, psi_v, eps_v, dv_miller, omega
         om.ctypes.data_as(C.POINTER(C.c_double)), float(eta), float(tol), C.byref(o), _ptr(ws),
         C.c_size_t(ws.numel()), _ptr(dpsi), _ptr(info)))
     return st, dpsi, info
+
+
+def sgw_green_solve(ctx, h_k, cols, omega, eta, tol, opts=None, workspace=None, g=None, info=None):
+    """Green's function columns: returns (status, G [n_col][n_omega][n_pw] complex128, info uint8 tensor)."""
+    import torch
+    cl = np.ascontiguousarray(np.asarray(cols, np.int32).reshape(-1))
+    om = np.ascontiguousarray(np.asarray(omega, np.float64).reshape(-1))
+    n_col, n_omega = int(cl.shape[0]), int(om.shape[0])
+    o = opts if opts is not None else sgw_opts_default()
+    n = C.c_size_t()
+    _check(load_library().sgw_green_workspace_size(ctx.handle, h_k.handle, n_col, n_omega, C.byref(o), C.byref(n)))
+    ws = (workspace or Workspace(ctx)).get(int(n.value))
+    if g is None:
+        g = torch.empty((n_col, n_omega, h_k.n_pw), dtype=torch.complex128, device=ctx.device)
+    if info is None:
+        info = torch.empty(n_col * n_omega * INFO_DTYPE.itemsize, dtype=torch.uint8, device=ctx.device)
+    st = _check(load_library().sgw_green_solve(
+        ctx.handle, h_k.handle, n_col, cl.ctypes.data_as(C.POINTER(C.c_int32)), n_omega,
+        om.ctypes.data_as(C.POINTER(C.c_double)), float(eta), float(tol), C.byref(o), _ptr(ws),
+        C.c_size_t(ws.numel()), _ptr(g), _ptr(info)))
+    return st, g, info
 
 
 class Batch:

@@ -301,9 +301,59 @@ def check_condition_number_svd():
             assert abs(got - expect) <= 1e-9 * expect, (v, z, got, expect)
 
 
+def check_green_free_electron():
+    """V = V0: H diagonal, so G_{GG'}(z) = delta_{GG'} / (z - 0.5|k+G|^2 - V0) (Eqs. 2-3 with the kinetic
+    closed form); both the spectral sum and the LU route must give it, and the Green's kappa counts
+    every level (the lowest one near z makes it large)."""
+    A, tau = cx.fcc_primitive(A_LAT)
+    B = cx.reciprocal(A)
+    k = np.array([0.02, -0.01, 0.03])
+    v0 = -0.4
+    m = cx.g_sphere(B, k, 2.1)
+    h = so.hamiltonian(m, B, k, np.full((10, 10, 10), v0))
+    w, u = np.linalg.eigh(h)
+    kg = m.astype(float) @ B + k
+    t = 0.5 * (kg * kg).sum(1) + v0
+    cols = [0, 3, len(m) - 1]
+    zs = np.array([v0 + 0.001 + 0.002j, 0.7 - 0.01j, 2.5 + 0.3j])
+    gs = so.green_columns_spectral(w, u, cols, zs)
+    for ci, c in enumerate(cols):
+        for zi, z in enumerate(zs):
+            expect = np.zeros(len(m), complex)
+            expect[c] = 1.0 / (z - t[c])
+            assert np.allclose(gs[ci, zi], expect, rtol=0, atol=1e-13 * abs(expect[c]))
+            assert np.allclose(so.green_column_lu(h, c, z), expect, rtol=0, atol=1e-13 * abs(expect[c]))
+    kap = so.green_condition_number(w, zs[0])
+    assert abs(kap - np.abs(t - zs[0]).max() / np.abs(t - zs[0]).min()) <= 1e-12 * kap
+
+
+def check_green_routes_and_symmetry():
+    """Random local potential: spectral sum vs LU (two independent routes), the symmetry
+    G(z)^H = G(conj z) of a Hermitian H, and the first terms of the large-|z| expansion
+    G(z) = 1/z + H/z^2 + O(|z|^-3)."""
+    A, B, m, v = _tiny()
+    h = so.hamiltonian(m, B, np.zeros(3), v)
+    w, u = np.linalg.eigh(h)
+    n = len(m)
+    cols = list(range(n))
+    for z in (0.3 + 0.004j, -0.8 + 0.02j, 1.9 - 0.05j):
+        g = so.green_columns_spectral(w, u, cols, [z])[:, 0, :].T       # [G][G']
+        kap = so.green_condition_number(w, z)
+        for c in (0, n // 2, n - 1):
+            x = so.green_column_lu(h, c, z)
+            assert np.linalg.norm(g[:, c] - x) <= 1e-13 * kap * np.linalg.norm(x)
+        gc = so.green_columns_spectral(w, u, cols, [np.conj(z)])[:, 0, :].T
+        assert np.abs(g.conj().T - gc).max() <= 1e-12 * kap * np.abs(g).max()
+    z = 5e3 + 2e3j
+    g = so.green_columns_spectral(w, u, cols, [z])[:, 0, :].T
+    approx = np.eye(n) / z + h / z ** 2
+    assert np.abs(g - approx).max() <= 5 * np.abs(h @ h).max() / abs(z) ** 3
+
+
 PINS = [check_kinetic_closed_form, check_hamiltonian_bruteforce, check_shifted_source_realspace,
         check_free_electron_closed_form, check_mpmath_tiny, check_routes_and_invariants,
-        check_linearity_and_reciprocity, check_relative_residual_closed_form, check_condition_number_svd]
+        check_linearity_and_reciprocity, check_relative_residual_closed_form, check_condition_number_svd,
+        check_green_free_electron, check_green_routes_and_symmetry]
 
 
 @pytest.mark.parametrize("pin", PINS + [check_generator_ground_state], ids=lambda f: f.__name__)
@@ -328,6 +378,8 @@ _orig_coef = so.potential_coefficients
 _orig_op = so.coulomb_operator
 _orig_spec = so.solve_spectral
 _orig_relres = so.relative_residual
+_orig_green = so.green_columns_spectral
+_orig_green_lu = so.green_column_lu
 _orig_kappa = so.condition_number
 
 
@@ -363,6 +415,12 @@ MUTATIONS = {
     "kappa_includes_occ": ("condition_number", lambda w, n, e, z: _orig_kappa(w, 0, e, z)),
     "kappa_drops_eta": ("condition_number", lambda w, n, e, z: _orig_kappa(w, n, e, complex(z).real + 1e-300j)),
     "kappa_inverted": ("condition_number", lambda w, n, e, z: 1.0 / _orig_kappa(w, n, e, z)),
+    "green_sign": ("green_columns_spectral", lambda w, u, c, z: -_orig_green(w, u, c, z)),
+    "green_conj_shift": ("green_columns_spectral", lambda w, u, c, z: _orig_green(w, u, c, np.conj(z))),
+    "green_no_conj": ("green_columns_spectral",
+                      lambda w, u, c, z: np.einsum("gn,cn,zn->czg", u, u[np.asarray(c), :],
+                                                   1.0 / (np.atleast_1d(np.asarray(z, complex))[:, None] - w[None, :]))),
+    "green_lu_rhs_sign": ("green_column_lu", lambda h, c, z: -_orig_green_lu(h, c, z)),
 }
 
 
