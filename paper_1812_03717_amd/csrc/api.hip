@@ -657,7 +657,7 @@ constexpr double kDefaultBudget = 96.0 * (1ull << 30);
 struct Layout {
   int S = 0, F = 0, kmax = 0, M = 8;
   size_t psi, omega, epsb, dvm, pair, kcur, status, eps, alpha, beta, rho, res, maxres, conv, bvec, basis;
-  size_t l_active, l_fill, l_fillpairs, l_final, Y, Y2, C, T, ycoef, cp, X, AX, bad, btab = 0;
+  size_t l_active, l_fill, l_fillpairs, l_final, Y, Y2, C, T, ycoef, cp, order, X, AX, bad, btab = 0;
   long c_rows = 0;
   // pooled Krylov basis: blocks of 2^bshift vectors, nbmax per slot at most, nblk in the pool;
   // S_full: the slots that full-size bases would give
@@ -772,6 +772,7 @@ Layout make_layout(const sgw_ham *h, int n_occ, int n_band, int n_pert, int n_om
   L.T = take(off, 16ul * tv * h->n[2] * h->n_stick);
   L.ycoef = take(off, 16ul * L.F * L.kmax * n_omega);
   L.cp = take(off, 16ul * L.F * L.kmax * n_omega);
+  L.order = take(off, 4ul * L.F * n_omega);
   L.X = take(off, 16ul * nfv * npw);
   L.AX = take(off, 16ul * nfv * npw);
   L.bad = take(off, 64);
@@ -982,6 +983,7 @@ static sgw_status multishift_solve(sgw_ctx *ctx, const sgw_ham *h_kq, int n_occ,
   double2 *T = (double2 *)(W + L.T);
   double2 *ycoef = (double2 *)(W + L.ycoef);
   double2 *cp = (double2 *)(W + L.cp);
+  int32_t *sorder = (int32_t *)(W + L.order);
   double2 *X = (double2 *)(W + L.X);
   double2 *AX = (double2 *)(W + L.AX);
   int *d_bad = (int *)(W + L.bad);
@@ -1074,8 +1076,8 @@ static sgw_status multishift_solve(sgw_ctx *ctx, const sgw_ham *h_kq, int n_occ,
       std::memcpy(p_final, list.data() + off, sizeof(int32_t) * nf);
       SGW_HIP(hipMemcpyAsync(d_final, p_final, sizeof(int32_t) * nf, hipMemcpyHostToDevice, ctx->stream));
       sgw_status s2;
-      if ((s2 = tridiag(ctx, Sx, d_final, nf, ycoef, cp)) != SGW_OK) return s2;
-      if ((s2 = combine(ctx, Sx, d_final, nf, ycoef, X, kavg)) != SGW_OK) return s2;
+      if ((s2 = tridiag(ctx, Sx, d_final, nf, ycoef, cp, sorder)) != SGW_OK) return s2;
+      if ((s2 = combine(ctx, Sx, d_final, nf, ycoef, sorder, X, kavg)) != SGW_OK) return s2;
       const int nv = nf * n_omega;
       if ((s2 = proj_dot(ctx, npw, n_occ, Sx.psi, nv, xsrc, C, crow)) != SGW_OK) return s2;
       if ((s2 = hx_batch(ctx, h_kq, nv, xsrc, AX, npw, T)) != SGW_OK) return s2;

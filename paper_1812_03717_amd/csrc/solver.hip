@@ -267,20 +267,40 @@ __global__ __launch_bounds__(kLzThreads) void k_lanczos(SolverState S, const int
 }
 
 // ---------------------------------------------------------------------------
-// FOM coefficients per shift: (T_K - z_j) y = ||b|| e_0 (Thomas algorithm; the
+// FOM coefficients per shift: (T_Kj - z_j) y = ||b|| e_0 (Thomas algorithm; the
 // matrix is complex symmetric with a definite imaginary part, so elimination
-// without pivoting is stable)
+// without pivoting is stable).  K_j is the Krylov dimension at which shift j's
+// residual estimate met the stopping threshold (the pair's full dimension if it
+// never did): the FOM iterate there is that shift's solution, and the larger
+// spaces the pair's slower shifts needed are not used for it.  The kernel also
+// ranks the pair's shifts by (K_j, j), so that the combination can group shifts
+// of similar dimension.
 // ---------------------------------------------------------------------------
 constexpr int kTriBatch = 8;
 
+// Krylov dimension of shift j's solution in slot `slot`
+__device__ __forceinline__ int shift_dim(const SolverState &S, int slot, int j) {
+  const int K = S.kcur[slot];
+  const int c = S.conv[(long)slot * S.n_omega + j];
+  return c >= 1 && c < K ? c : K;
+}
+
 __global__ void k_tridiag(SolverState S, const int32_t *__restrict__ flist, int nf, double2 *__restrict__ ycoef,
-                          double2 *__restrict__ cp) {
+                          double2 *__restrict__ cp, int32_t *__restrict__ order) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= nf * S.n_omega) return;
   const int f = t / S.n_omega, j = t - f * S.n_omega;
   const int slot = flist[f];
-  const int K = S.kcur[slot];
   const int nw = S.n_omega;
+  const int K = shift_dim(S, slot, j);
+  {  // rank of shift j among the pair's shifts by (K_j, j)
+    int rank = 0;
+    for (int q = 0; q < nw; ++q) {
+      const int kq = shift_dim(S, slot, q);
+      rank += (kq < K || (kq == K && q < j)) ? 1 : 0;
+    }
+    order[(long)f * nw + rank] = j;
+  }
   const long base = (long)f * S.kmax * nw + j;
   const double *al = S.alpha_t + (long)slot * S.kmax;
   const double *be = S.beta + (long)slot * (S.kmax + 1);
@@ -348,15 +368,19 @@ constexpr int kCmbU = 8;  // basis values loaded ahead (divides kCmbK)
 constexpr int kXcds = 8;
 
 // One workgroup per (slot, tile of 256 plane waves, chunk of kCmbJ shifts; kCmbJ is 16 or 20,
-// whichever pads the shift count less, so 64 and 100 shifts split without a ragged chunk).  The
-// chunks of a tile read the same basis vectors; workgroup ids are arranged so that they run on one
-// XCD (ids spaced by kXcds, dispatched close together) and share that XCD's L2 copy of the tile.
+// whichever pads the shift count less, so 64 and 100 shifts split without a ragged chunk).  A
+// chunk holds kCmbJ consecutive shifts of the pair's order by Krylov dimension (k_tridiag), so it
+// runs only to the largest dimension among its own shifts.  The chunks of a tile read the same
+// basis vectors; workgroup ids are arranged so that they run on one XCD (ids spaced by kXcds,
+// dispatched close together) and share that XCD's L2 copy of the tile.
 template <int kCmbJ>
 __global__ __launch_bounds__(kCmbThreads) void k_combine(SolverState S, const int32_t *__restrict__ flist,
                                                          const double2 *__restrict__ ycoef,
+                                                         const int32_t *__restrict__ order,
                                                          double2 *__restrict__ X, int gtiles, int jchunks,
                                                          int ntiles) {
   __shared__ double2 yt[kCmbK][kCmbJ];
+  __shared__ int sj[kCmbJ], sk[kCmbJ];
   int b = blockIdx.x;
   const int xcd = b % kXcds;
   b /= kXcds;
@@ -366,9 +390,18 @@ __global__ __launch_bounds__(kCmbThreads) void k_combine(SolverState S, const in
   const int gt = tile % gtiles;
   const int f = tile / gtiles;
   const int slot = flist[f];
-  const int K = S.kcur[slot];
   const int nw = S.n_omega;
   const int j0 = jc * kCmbJ;
+  if (threadIdx.x < kCmbJ) {
+    const int jj = j0 + threadIdx.x;
+    const int j = jj < nw ? order[(long)f * nw + jj] : -1;
+    sj[threadIdx.x] = j;
+    sk[threadIdx.x] = j >= 0 ? shift_dim(S, slot, j) : 0;
+  }
+  __syncthreads();
+  int K = 0;  // the chunk's largest Krylov dimension
+#pragma unroll
+  for (int q = 0; q < kCmbJ; ++q) K = max(K, sk[q]);
   const int g = gt * kCmbThreads + threadIdx.x;
   double2 acc[kCmbJ];
 #pragma unroll
@@ -376,8 +409,9 @@ __global__ __launch_bounds__(kCmbThreads) void k_combine(SolverState S, const in
   for (int k0 = 0; k0 < K; k0 += kCmbK) {
     for (int i = threadIdx.x; i < kCmbK * kCmbJ; i += kCmbThreads) {
       const int kk = i / kCmbJ, q = i - kk * kCmbJ;
-      const int k = k0 + kk, j = j0 + q;
-      yt[kk][q] = (k < K && j < nw) ? ycoef[((long)f * S.kmax + k) * nw + j] : make_double2(0.0, 0.0);
+      const int k = k0 + kk, j = sj[q];
+      // coefficients past a shift's own dimension are zero
+      yt[kk][q] = (k < sk[q] && j >= 0) ? ycoef[((long)f * S.kmax + k) * nw + j] : make_double2(0.0, 0.0);
     }
     __syncthreads();
     if (g < S.npw) {
@@ -405,8 +439,8 @@ __global__ __launch_bounds__(kCmbThreads) void k_combine(SolverState S, const in
   if (g < S.npw) {
 #pragma unroll
     for (int q = 0; q < kCmbJ; ++q) {
-      const int j = j0 + q;
-      if (j < nw) X[((long)f * nw + j) * S.npw + g] = acc[q];
+      const int j = sj[q];
+      if (j >= 0) X[((long)f * nw + j) * S.npw + g] = acc[q];
     }
   }
 }
@@ -620,19 +654,20 @@ sgw_status lanczos_step(sgw_ctx *ctx, const SolverState &S, int n_active, const 
   return SGW_OK;
 }
 
-sgw_status tridiag(sgw_ctx *ctx, const SolverState &S, const int32_t *flist, int nf, double2 *ycoef, double2 *cp) {
+sgw_status tridiag(sgw_ctx *ctx, const SolverState &S, const int32_t *flist, int nf, double2 *ycoef, double2 *cp,
+                   int32_t *order) {
   if (nf <= 0) return SGW_OK;
   const int n = nf * S.n_omega;
   PendingTiming tm;
   timing_begin(ctx, K_TRIDIAG, 0.0, 0.0, &tm);
-  hipLaunchKernelGGL(k_tridiag, dim3((n + 63) / 64), dim3(64), 0, ctx->stream, S, flist, nf, ycoef, cp);
+  hipLaunchKernelGGL(k_tridiag, dim3((n + 63) / 64), dim3(64), 0, ctx->stream, S, flist, nf, ycoef, cp, order);
   timing_end(ctx, &tm);
   SGW_HIP(hipGetLastError());
   return SGW_OK;
 }
 
 sgw_status combine(sgw_ctx *ctx, const SolverState &S, const int32_t *flist, int nf, const double2 *ycoef,
-                   double2 *X, double est_kavg) {
+                   const int32_t *order, double2 *X, double est_kavg) {
   if (nf <= 0) return SGW_OK;
   const int gtiles = (S.npw + kCmbThreads - 1) / kCmbThreads;
   const int nw = S.n_omega;
@@ -645,11 +680,11 @@ sgw_status combine(sgw_ctx *ctx, const SolverState &S, const int32_t *flist, int
   const int ntiles = nf * gtiles;
   const long groups = (long)(ntiles + kXcds - 1) / kXcds * kXcds * jchunks;
   if (j20)
-    hipLaunchKernelGGL(k_combine<20>, dim3(groups), dim3(kCmbThreads), 0, ctx->stream, S, flist, ycoef, X, gtiles,
-                       jchunks, ntiles);
+    hipLaunchKernelGGL(k_combine<20>, dim3(groups), dim3(kCmbThreads), 0, ctx->stream, S, flist, ycoef, order, X,
+                       gtiles, jchunks, ntiles);
   else
-    hipLaunchKernelGGL(k_combine<16>, dim3(groups), dim3(kCmbThreads), 0, ctx->stream, S, flist, ycoef, X, gtiles,
-                       jchunks, ntiles);
+    hipLaunchKernelGGL(k_combine<16>, dim3(groups), dim3(kCmbThreads), 0, ctx->stream, S, flist, ycoef, order, X,
+                       gtiles, jchunks, ntiles);
   timing_end(ctx, &tm);
   SGW_HIP(hipGetLastError());
   return SGW_OK;

@@ -67,9 +67,12 @@ sgw_status slot_init(sgw_ctx *ctx, const SolverState &S, int n_fill, const doubl
                      const int32_t *fill_slots, const int32_t *fill_pairs);
 // Y[a] must hold (H + alpha P_occ) v_k of slot list[a]
 sgw_status lanczos_step(sgw_ctx *ctx, const SolverState &S, int n_active, const int32_t *list, const double2 *Y);
-sgw_status tridiag(sgw_ctx *ctx, const SolverState &S, const int32_t *flist, int nf, double2 *ycoef, double2 *cp);
+// FOM coefficients of each shift at its own Krylov dimension; order[f][rank] = the pair's shifts by
+// (dimension, index)
+sgw_status tridiag(sgw_ctx *ctx, const SolverState &S, const int32_t *flist, int nf, double2 *ycoef, double2 *cp,
+                   int32_t *order);
 sgw_status combine(sgw_ctx *ctx, const SolverState &S, const int32_t *flist, int nf, const double2 *ycoef,
-                   double2 *X, double est_kavg);
+                   const int32_t *order, double2 *X, double est_kavg);
 // AX must hold (H + alpha P_occ) X; cp[0] the overlaps of X (as proj_dot leaves them); u2i maps
 // caller to internal plane-wave indices (dpsi is written in the caller's order)
 sgw_status residual(sgw_ctx *ctx, const SolverState &S, const int32_t *flist, int nf, const double2 *X,

@@ -1,8 +1,8 @@
 """Full-size parity on the si16 workload, in the launch configuration bench.py times.
 
 Every one of the 102,400 solves (32 bands x 50 perturbations x 64 frequencies,
-tol 1e-8) must report a true FP64 relative residual <= tol and a negligible
-occupied component.  A seeded sample of solves is checked against the oracle's
+tol 1e-8) must report a true FP64 relative residual <= tol and an occupied
+component within the error budget.  A seeded sample of solves is checked against the oracle's
 direct LU solve with the rigorous error budget of a Hermitian operator with a
 complex shift: ||x - x*|| <= ||r|| / eta, since every singular value of
 H - eps - z is at least |Im z| = eta.  A second, smaller launch at tol 1e-12
@@ -35,6 +35,22 @@ def setup():
     return p, ctx, dev, h
 
 
+def _check_occ_leak(p, dev, dpsi, inf):
+    """Occupied component of every solution within the error budget: P_occ x* = 0 for the exact
+    solution (b is orthogonal to the occupied states, which the operator leaves invariant), so
+    ||P_occ x|| <= ||x - x*|| <= relres ||b|| / eta (every singular value of H - eps - z is at
+    least eta), plus 1e-10 ||x|| for the occupied states being eigenstates only to rounding."""
+    from paper_1812_03717_amd import sgw
+    b = sgw.sgw_build_rhs(dev.ctx, dev.h_kq, dev.psi_occ_kq, dev.h_k, dev.psi_v, p.dv_miller)
+    nb = torch.linalg.vector_norm(b, dim=-1).cpu().numpy()[:, :, None]
+    nx = np.stack([torch.linalg.vector_norm(dpsi[v], dim=-1).cpu().numpy() for v in range(p.n_band)])
+    leak = inf["occ_leak"] * nx
+    bound = 1.01 * inf["relres"] * nb / p.eta + 1e-10 * nx
+    print(f"  occupied leak: max {inf['occ_leak'].max():.2e} of |x|, max fraction of its budget "
+          f"{(leak / bound).max():.2e}", flush=True)
+    assert np.all(leak <= bound)
+
+
 def _lu_reference(p, h, v, q, om, eta):
     b = so.rhs(p.psi_k[v], p.miller_k, p.miller_kq, p.dv_miller[q], p.psi_kq)
     a0 = so.coulomb_operator(h, p.psi_kq, p.eps_k[v], 1.0)
@@ -56,7 +72,7 @@ def test_si16_full_workload(setup, precision):
     assert st == sgw.SGW_OK
     assert np.all(inf["flags"] & sgw.FLAG_CONVERGED)
     assert inf["relres"].max() <= p.tol
-    assert inf["occ_leak"].max() <= 1e-9
+    _check_occ_leak(p, dev, dpsi, inf)
     rng = np.random.default_rng(16)
     for _ in range(4):
         v, q, j = int(rng.integers(p.n_band)), int(rng.integers(p.n_pert)), int(rng.integers(p.n_omega))
