@@ -229,7 +229,7 @@ typedef struct {
   double tol_safety;        /* the recurrence stops when every shift's estimated residual
                                is below tol*tol_safety; <= 0 -> 0.5 */
   int32_t slots;            /* (v,p) pairs iterated concurrently; <= 0 -> automatic (as many as
-                               a 96 GiB workspace holds, at most all pairs) */
+                               a 144 GiB workspace holds, at most all pairs) */
   int32_t finalize_batch;   /* pairs per finalisation batch; <= 0 -> automatic */
   int32_t steps_per_sync;   /* Krylov steps between host polls; <= 0 -> 8 */
   int32_t solver;           /* SGW_SOLVER_* (default MULTISHIFT) */

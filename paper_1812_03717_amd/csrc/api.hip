@@ -651,8 +651,9 @@ constexpr size_t kAlign = 256;
 // basis, up to this many times the slots of full-size bases share a pool of the same memory
 constexpr int kBasisBlockShift = 5;
 constexpr int kPoolSlotFactor = 4;
-// workspace budget that sizes the automatic slot count: a third of one MI355X's 288 GB of HBM
-constexpr double kDefaultBudget = 96.0 * (1ull << 30);
+// workspace budget that sizes the automatic slot count: half of one MI355X's 288 GB of HBM, the
+// rest left to the caller's arrays (the 64-atom workload's solutions take 65 GB)
+constexpr double kDefaultBudget = 144.0 * (1ull << 30);
 
 struct Layout {
   int S = 0, F = 0, kmax = 0, M = 8;
