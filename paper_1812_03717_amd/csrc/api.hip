@@ -841,7 +841,14 @@ struct StepGraph {
   }
   template <class F>
   sgw_status capture(hipStream_t stream, F &&launches) {
-    if (exec) hipGraphExecDestroy(exec);
+    if (exec) {
+      // an executable graph is destroyed only once its last launch has completed (the solver
+      // re-captures after the poll has synchronised the stream; this keeps it so)
+      const hipError_t q = hipStreamQuery(stream);
+      if (q == hipErrorNotReady) return fail(SGW_ERR_HIP, "StepGraph: re-capture while the stream still runs");
+      if (q != hipSuccess) return fail(SGW_ERR_HIP, std::string("hipStreamQuery: ") + hipGetErrorString(q));
+      hipGraphExecDestroy(exec);
+    }
     exec = nullptr;
     na = -1;
     n64 = -1;
