@@ -60,7 +60,8 @@ def roofline(kernel, ks, workload, default_launch=True):
     peak; HBM figures are given beside it.  ``traffic`` comes from the committed
     rocprofv3 FETCH_SIZE/WRITE_SIZE summary, only while the kernel's sources
     still hash to the value recorded with those counters and the launches have
-    the size they had there (``default_launch``: no --slots override).
+    the size they had there (``default_launch``: no --slots override, and the
+    algorithmic bytes per launch within 2% of those of the counted run).
     """
     from paper_1812_03717_amd import profiling
     n = max(ks["launches"], 1)
@@ -73,7 +74,8 @@ def roofline(kernel, ks, workload, default_launch=True):
     if default_launch and os.path.exists(tfile):
         with open(tfile) as fh:
             t = json.load(fh)
-        if t.get("source_hash") == profiling.source_hash(kernel):
+        same_launch = abs(t.get("alg_bytes_per_launch", 0) - bytes_per_launch) <= 0.02 * bytes_per_launch
+        if t.get("source_hash") == profiling.source_hash(kernel) and same_launch:
             traffic = round(t["fetch_bytes_per_dispatch"] + t["write_bytes_per_dispatch"])
     roof = {"kernel": kernel, "traffic": traffic, "avg_launch_ms": round(avg_s * 1e3, 4), "launches": ks["launches"],
             "alg_bytes_per_launch": round(bytes_per_launch), "hbm_achieved_gbs": round(gbs, 1),

@@ -3,14 +3,19 @@
     python -m paper_1812_03717_amd.profiling top DB
     python -m paper_1812_03717_amd.profiling pmc DB
     python -m paper_1812_03717_amd.profiling traffic --kernel k_planes --fetch DB --write DB \
-        --copy-fetch DB --copy-write DB --copy-bytes N [--out FILE.json]
+        --copy-fetch DB --copy-write DB --copy-bytes N [--bench-line FILE] [--out FILE.json]
     python -m paper_1812_03717_amd.profiling mfma --pmc DB --trace DB --kernel k_proj_dot [--kernel ...]
     python -m paper_1812_03717_amd.profiling valu --pmc DB --trace DB --kernel k_planes_line [--alg-flops F]
+    python -m paper_1812_03717_amd.profiling stalls --pmc DB [--pmc DB ...] --kernel k_planes_pair
 
 ``traffic`` scales the per-dispatch FETCH_SIZE and WRITE_SIZE averages (KiB) of
 one kernel by what the same counters read for a plain device copy of known
 size, and records a hash of the kernel's sources so that a later change of the
-kernel marks the numbers stale (``source_hash``).
+kernel marks the numbers stale (``source_hash``).  With ``--bench-line`` (a file
+holding the JSON line that the counted bench run printed) it also records the
+algorithmic bytes per launch of that run, so that a later run whose launches
+have another size (another workspace budget, another batch) can tell that the
+counters do not describe its launches.
 
 ``mfma`` reports, per kernel, the FP64 matrix flops per dispatch
 (SQ_INSTS_VALU_MFMA_MOPS_F64 counts units of 512 flops), the achieved rate over
@@ -86,10 +91,16 @@ def pmc(db: str):
 
 
 def _avg(db, kernel_prefix, counter):
+    """(dispatches, average per dispatch) of a counter over every kernel whose name starts with
+    kernel_prefix (all template instances of it)"""
+    n_all, tot = 0, 0.0
     for (k, cn), (n, avg) in pmc(db).items():
         if cn == counter and k.startswith(kernel_prefix):
-            return n, avg
-    raise KeyError(f"{kernel_prefix}/{counter} not in {db}")
+            n_all += n
+            tot += n * avg
+    if not n_all:
+        raise KeyError(f"{kernel_prefix}/{counter} not in {db}")
+    return n_all, tot / n_all
 
 
 def traffic(kernel_prefix, fetch_db, write_db, copy_fetch_db, copy_write_db, copy_bytes):
@@ -151,6 +162,36 @@ def valu(pmc_db, trace_db, kernel_prefix):
     return r
 
 
+STALL_COUNTERS = ("SQ_WAVES", "SQ_WAVE_CYCLES", "SQ_BUSY_CYCLES", "SQ_WAIT_ANY", "SQ_WAIT_INST_ANY",
+                  "SQ_WAIT_INST_LDS", "SQ_ACTIVE_INST_ANY", "SQ_ACTIVE_INST_VALU", "SQ_ACTIVE_INST_LDS",
+                  "SQ_ACTIVE_INST_SCA", "SQ_INSTS_VALU", "SQ_INSTS_LDS", "SQ_INSTS_SALU", "SQ_LDS_BANK_CONFLICT",
+                  "SQ_LDS_IDX_ACTIVE")
+
+
+def stalls(pmc_dbs, kernel_prefix):
+    """Per-dispatch SQ counters of one kernel gathered from several counter passes, and the shares
+    of the waves' lifetime (SQ_WAVE_CYCLES) spent issuing VALU or LDS instructions and waiting."""
+    r = {}
+    for c in STALL_COUNTERS:
+        for db in pmc_dbs:
+            try:
+                r[c] = _avg(db, kernel_prefix, c)[1]
+                break
+            except KeyError:
+                continue
+    wc = r.get("SQ_WAVE_CYCLES")
+    if wc:
+        for c in ("SQ_WAIT_ANY", "SQ_WAIT_INST_ANY", "SQ_WAIT_INST_LDS", "SQ_ACTIVE_INST_ANY",
+                  "SQ_ACTIVE_INST_VALU", "SQ_ACTIVE_INST_LDS"):
+            if c in r:
+                r[c + "/wave_cycles"] = r[c] / wc
+    if r.get("SQ_WAVES") and "SQ_INSTS_VALU" in r:
+        r["valu_insts_per_wave"] = r["SQ_INSTS_VALU"] / r["SQ_WAVES"]
+    if r.get("SQ_LDS_IDX_ACTIVE") and "SQ_LDS_BANK_CONFLICT" in r:
+        r["lds_conflict/lds_active"] = r["SQ_LDS_BANK_CONFLICT"] / r["SQ_LDS_IDX_ACTIVE"]
+    return r
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -164,6 +205,7 @@ def main():
     for k in ("fetch", "write", "copy-fetch", "copy-write"):
         r.add_argument(f"--{k}", required=True)
     r.add_argument("--copy-bytes", type=float, required=True)
+    r.add_argument("--bench-line", help="file with the JSON line the counted bench run printed")
     r.add_argument("--out")
     m = sub.add_parser("mfma")
     m.add_argument("--pmc", required=True)
@@ -174,6 +216,9 @@ def main():
     v.add_argument("--trace", required=True)
     v.add_argument("--kernel", required=True)
     v.add_argument("--alg-flops", type=float, default=0.0, help="algorithmic flops per dispatch, if known")
+    s = sub.add_parser("stalls")
+    s.add_argument("--pmc", action="append", required=True)
+    s.add_argument("--kernel", required=True)
     a = ap.parse_args()
     if a.cmd == "top":
         # rocpd reports durations in microseconds
@@ -201,9 +246,20 @@ def main():
         print(f"  FP64 flops at full lanes          {r['fp64_flops_full_lanes'] / 1e9:.3f} GFLOP per dispatch")
         if a.alg_flops:
             print(f"  algorithmic / full-lane FP64 flops {a.alg_flops / r['fp64_flops_full_lanes']:.3f}")
+    elif a.cmd == "stalls":
+        print(f"{a.kernel}: per dispatch")
+        for k, v in stalls(a.pmc, a.kernel).items():
+            print(f"  {k:34s} {v:16.3f}" if v < 100 else f"  {k:34s} {v:16.0f}")
     else:
         res = traffic(a.kernel, a.fetch, a.write, a.copy_fetch, a.copy_write, a.copy_bytes)
         res["kernel"] = a.name
+        if a.bench_line:
+            with open(a.bench_line) as fh:
+                line = [ln for ln in fh if ln.lstrip().startswith("{")][-1]
+            roof = json.loads(line)["roofline"]
+            if roof.get("kernel") != a.name:
+                raise SystemExit(f"the bench line's dominant kernel is {roof.get('kernel')}, not {a.name}")
+            res["alg_bytes_per_launch"] = roof["alg_bytes_per_launch"]
         res["source_hash"] = source_hash(a.name)
         print(json.dumps(res, indent=1))
         if a.out:
