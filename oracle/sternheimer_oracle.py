@@ -9,7 +9,8 @@ What it computes (Hartree units; every function cites the passage it follows):
 
 * the plane-wave Hamiltonian at one Bloch vector as a dense matrix
   (Sec. 2.1, Eq. 1 and the text after it: kinetic part diagonal in
-  reciprocal space, local potential applied on the real-space grid);
+  reciprocal space, local potential applied on the real-space grid, and the
+  separable non-local part of the pseudopotential in reciprocal space);
 * the driving term of the density response, projected off the occupied
   manifold (Sec. 2.3, Eq. 8), with the sign reading documented in ``rhs``;
 * the Coulomb-response operator with the occupied projector (Sec. 2.3, Eq. 7)
@@ -37,6 +38,10 @@ Readings of the paper taken here:
 * The local potential is defined by its grid samples; its matrix element
   between plane waves m and m' is the discrete Fourier coefficient at the
   cyclic difference (m - m') mod N (grid-defined operator, aliasing included).
+* The non-local part of the pseudopotential is taken in the fully separable
+  form sum_p |beta_p> E_p <beta_p| with real E_p (any Hermitian coupling matrix
+  between the projectors of an atom reduces to it by diagonalisation); the
+  projector coefficients beta_p(G) are inputs.
 """
 from __future__ import annotations
 
@@ -64,8 +69,18 @@ def potential_coefficients(v_grid: np.ndarray) -> np.ndarray:
     return np.fft.fftn(np.asarray(v_grid, float)) / v_grid.size
 
 
-def hamiltonian(miller: np.ndarray, B: np.ndarray, kvec, v_grid: np.ndarray) -> np.ndarray:
-    """Dense plane-wave Hamiltonian H[i, j] = T_i delta_ij + V~[(m_i - m_j) mod N]."""
+def nonlocal_matrix(beta: np.ndarray, e_kb, rows=None) -> np.ndarray:
+    """Separable non-local pseudopotential between plane waves (Sec. 2.1, the text after Eq. 1: the
+    non-local part is represented in reciprocal space):
+    V_NL[i, j] = sum_p E_p beta_p(G_i) conj(beta_p(G_j)), for the rows i in `rows` (all if None)."""
+    b = np.asarray(beta, complex)
+    br = b if rows is None else b[:, np.asarray(rows, np.int64)]
+    return (br.T * np.asarray(e_kb, float)[None, :]) @ b.conj()
+
+
+def hamiltonian(miller: np.ndarray, B: np.ndarray, kvec, v_grid: np.ndarray, nl=None) -> np.ndarray:
+    """Dense plane-wave Hamiltonian H[i, j] = T_i delta_ij + V~[(m_i - m_j) mod N] (+ V_NL[i, j] when
+    nl = (beta, e_kb) is given)."""
     vq = potential_coefficients(v_grid)
     n0, n1, n2 = v_grid.shape
     m = np.asarray(miller, np.int64)
@@ -73,12 +88,15 @@ def hamiltonian(miller: np.ndarray, B: np.ndarray, kvec, v_grid: np.ndarray) -> 
            (m[:, None, 1] - m[None, :, 1]) % n1,
            (m[:, None, 2] - m[None, :, 2]) % n2]
     h[np.diag_indices_from(h)] += kinetic(miller, B, kvec)
+    if nl is not None:
+        h += nonlocal_matrix(nl[0], nl[1])
     return h
 
 
-def hamiltonian_rows(miller: np.ndarray, B: np.ndarray, kvec, v_grid: np.ndarray, rows) -> np.ndarray:
+def hamiltonian_rows(miller: np.ndarray, B: np.ndarray, kvec, v_grid: np.ndarray, rows, nl=None) -> np.ndarray:
     """Rows `rows` of the dense plane-wave Hamiltonian, by the same definition as `hamiltonian`:
-    H[i, j] = T_i delta_ij + V~[(m_i - m_j) mod N] (for bases too large to hold H whole)."""
+    H[i, j] = T_i delta_ij + V~[(m_i - m_j) mod N] (+ V_NL[i, j]) (for bases too large to hold H
+    whole)."""
     vq = potential_coefficients(v_grid)
     n0, n1, n2 = v_grid.shape
     m = np.asarray(miller, np.int64)
@@ -87,6 +105,8 @@ def hamiltonian_rows(miller: np.ndarray, B: np.ndarray, kvec, v_grid: np.ndarray
            (m[r, None, 1] - m[None, :, 1]) % n1,
            (m[r, None, 2] - m[None, :, 2]) % n2]
     h[np.arange(len(r)), r] += kinetic(miller, B, kvec)[r]
+    if nl is not None:
+        h += nonlocal_matrix(nl[0], nl[1], rows=r)
     return h
 
 

@@ -55,6 +55,11 @@ class Problem:
     dv_miller: np.ndarray       # [n_pert][3] int32, perturbation G_p
     tol: float
     seed: int
+    # separable non-local pseudopotential (None: local potential only): projectors at k and k+q
+    # ([n_proj][n_pw], rows in the order of miller_k / miller_kq) and their energies [n_proj] (Ha)
+    beta_k: np.ndarray = None
+    beta_kq: np.ndarray = None
+    e_kb: np.ndarray = None
 
     @property
     def kqvec(self):
@@ -85,6 +90,10 @@ class Problem:
         return self.eps_k[: self.n_band]
 
     @property
+    def n_proj(self):
+        return 0 if self.e_kb is None else int(self.e_kb.shape[0])
+
+    @property
     def n_solves(self):
         return self.n_band * self.n_pert * self.n_omega
 
@@ -94,9 +103,12 @@ class Problem:
 
 
 def make_problem(name, A, tau, grid, ecut, n_occ, omega_ev, eta_ev, n_pert, tol, seed,
-                 q_zero=False, n_band=None, noise=0.05, max_bumps=20, occ_window=0, min_gap=MIN_GAP_HA):
+                 q_zero=False, n_band=None, noise=0.05, max_bumps=20, occ_window=0, min_gap=MIN_GAP_HA,
+                 nonlocal_pp=False):
     """occ_window > 0: when the states n_occ - 1 and n_occ are (near-)degenerate, take the band count
-    within n_occ +- occ_window closest to n_occ that has a gap >= MIN_GAP_HA at k and k+q."""
+    within n_occ +- occ_window closest to n_occ that has a gap >= MIN_GAP_HA at k and k+q.
+    nonlocal_pp: add the synthetic s and p projectors of ``crystal.kb_projectors`` on every atom to the
+    Hamiltonian whose eigenstates are the reference states."""
     B = cx.reciprocal(A)
     kvec = np.zeros(3)
     target = n_occ
@@ -106,12 +118,14 @@ def make_problem(name, A, tau, grid, ecut, n_occ, omega_ev, eta_ev, n_pert, tol,
         v = cx.gaussian_potential(A, tau, grid, noise=noise, seed=s)
         mk = cx.g_sphere(B, kvec, ecut)
         mkq = mk if q_zero else cx.g_sphere(B, kvec + qvec, ecut)
+        nl_k = cx.kb_projectors(mk, B, kvec, A, tau) if nonlocal_pp else None
+        nl_kq = (nl_k if q_zero else cx.kb_projectors(mkq, B, kvec + qvec, A, tau)) if nonlocal_pp else None
         n_states = target + occ_window + 1
-        ek, pk = lowest_states(mk, B, kvec, v, n_states)
+        ek, pk = lowest_states(mk, B, kvec, v, n_states, nl_k)
         if q_zero:
             ekq, pkq = ek, pk
         else:
-            ekq, pkq = lowest_states(mkq, B, kvec + qvec, v, n_states)
+            ekq, pkq = lowest_states(mkq, B, kvec + qvec, v, n_states, nl_kq)
         cands = sorted(range(max(1, target - occ_window), target + occ_window + 1), key=lambda n: (abs(n - target), n))
         ok = [n for n in cands if min(ek[n] - ek[n - 1], ekq[n] - ekq[n - 1]) >= min_gap]
         if ok:
@@ -127,7 +141,9 @@ def make_problem(name, A, tau, grid, ecut, n_occ, omega_ev, eta_ev, n_pert, tol,
         eps_k=ek, psi_k=np.ascontiguousarray(pk[:n_occ]),
         eps_kq=ekq, psi_kq=np.ascontiguousarray(pkq[:n_occ]),
         omega=np.asarray(omega_ev, float) / cx.HA_EV, eta=float(eta_ev) / cx.HA_EV,
-        dv_miller=np.ascontiguousarray(pert.astype(np.int32)), tol=float(tol), seed=s)
+        dv_miller=np.ascontiguousarray(pert.astype(np.int32)), tol=float(tol), seed=s,
+        beta_k=None if nl_k is None else nl_k[0], beta_kq=None if nl_kq is None else nl_kq[0],
+        e_kb=None if nl_k is None else nl_k[1])
 
 
 @functools.lru_cache(maxsize=None)
@@ -157,8 +173,16 @@ def si64():
 
 
 @functools.lru_cache(maxsize=None)
+def si64nl():
+    """si64 with the synthetic non-local s and p projectors on every atom (256 projectors)."""
+    A, tau = cx.supercell(*cx.conventional_cubic(A_LAT), (2, 2, 2))
+    return make_problem("si64nl", A, tau, (72, 72, 72), 11.46, 128, cx.frequencies_ev(0, 40, 100), 0.05,
+                        20, 1e-8, 4000, occ_window=6, min_gap=3e-4, nonlocal_pp=True)
+
+
+@functools.lru_cache(maxsize=None)
 def small(cells=(1, 1, 1), grid=None, ecut=11.46, n_occ=None, n_omega=8, n_pert=3,
-          eta_ev=0.1, omega_hi_ev=20.0, q_zero=False, seed=9000, tol=1e-12, n_band=None):
+          eta_ev=0.1, omega_hi_ev=20.0, q_zero=False, seed=9000, tol=1e-12, n_band=None, nonlocal_pp=False):
     """Reduced fcc n0 x n1 x n2 cells of the same recipe (grid 24 n_d unless given)."""
     A, tau = cx.supercell(*cx.fcc_primitive(A_LAT), cells)
     if grid is None:
@@ -167,10 +191,10 @@ def small(cells=(1, 1, 1), grid=None, ecut=11.46, n_occ=None, n_omega=8, n_pert=
         n_occ = 2 * len(tau)
     return make_problem(f"small{cells}", A, tau, grid, ecut, n_occ,
                         cx.frequencies_ev(0, omega_hi_ev, n_omega), eta_ev, n_pert, tol, seed,
-                        q_zero=q_zero, n_band=n_band)
+                        q_zero=q_zero, n_band=n_band, nonlocal_pp=nonlocal_pp)
 
 
-CONFIGS = {"si2": si2, "si16": si16, "si64": si64}
+CONFIGS = {"si2": si2, "si16": si16, "si64": si64, "si64nl": si64nl}
 
 
 def _batch_system(args):

@@ -1,4 +1,4 @@
-"""Seeded synthetic crystals: lattices, plane-wave spheres, local potentials.
+"""Seeded synthetic crystals: lattices, plane-wave spheres, local potentials, non-local projectors.
 
 This module only *generates inputs*. It holds none of the Sternheimer method's
 arithmetic (no operator application, no projector, no solver). Both the HIP
@@ -129,6 +129,45 @@ def gaussian_potential(A: np.ndarray, tau: np.ndarray, grid, amp: float = 0.5,
     rng = np.random.default_rng(seed)
     u = rng.uniform(-1.0, 1.0, size=grid)
     return np.ascontiguousarray(v0.real * (1.0 + noise * u))
+
+
+def kb_projectors(miller: np.ndarray, B: np.ndarray, kvec, A: np.ndarray, tau: np.ndarray, r_c: float = 1.2,
+                  e_s: float = 0.6, e_p: float = -0.25, channels: str = "sp"):
+    """Synthetic separable (Kleinman-Bylander) non-local pseudopotential: projectors and energies.
+
+    For each atom a and channel (s: l = 0; p: l = 1, three real harmonics x, y, z), with
+    K = k + G_m and the Gaussian radial form exp(-|K|^2 r_c^2 / 2):
+
+        beta_{a,s}(G)   = N_s / sqrt(Omega) * exp(-|K|^2 r_c^2 / 2) * exp(-i K . tau_a)
+        beta_{a,p_d}(G) = N_p / sqrt(Omega) * (K_d r_c) * exp(-|K|^2 r_c^2 / 2) * exp(-i K . tau_a)
+
+    with N_s^2 = 8 pi^(3/2) r_c^3 and N_p^2 = 16 pi^(3/2) r_c^3, so that each projector has unit norm
+    in the complete-basis limit.  The operator they define is V_NL = sum_i |beta_i> E_i <beta_i|
+    (E_i = e_s or e_p), whose plane-wave matrix element between G and G' is
+    sum_i E_i beta_i(G) conj(beta_i(G')): the phase exp(-i (G - G') . tau_a) is the one the local
+    potential's structure factor carries.  Real pseudopotential files are not used; these stand in
+    for them with the same structure (one radial form per channel, atom-centred phases).
+
+    Returns (beta [n_proj][n_pw] complex128 in the order of ``miller``, e_kb [n_proj] float64),
+    projectors ordered by atom, then channel (s, p_x, p_y, p_z).
+    """
+    A = np.asarray(A, float)
+    omega = abs(np.linalg.det(A))
+    K = np.asarray(miller, float) @ np.asarray(B, float) + np.asarray(kvec, float)
+    radial = np.exp(-0.5 * (K * K).sum(1) * r_c * r_c) / np.sqrt(omega)
+    n_s = np.sqrt(8.0 * np.pi ** 1.5 * r_c ** 3)
+    n_p = np.sqrt(16.0 * np.pi ** 1.5 * r_c ** 3)
+    beta, ekb = [], []
+    for t in np.asarray(tau, float):
+        ph = radial * np.exp(-1j * (K @ t))
+        if "s" in channels:
+            beta.append(n_s * ph)
+            ekb.append(e_s)
+        if "p" in channels:
+            for d in range(3):
+                beta.append(n_p * r_c * K[:, d] * ph)
+                ekb.append(e_p)
+    return np.ascontiguousarray(np.array(beta, np.complex128)), np.array(ekb, float)
 
 
 def seeded_q(B: np.ndarray, seed: int) -> np.ndarray:

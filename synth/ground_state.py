@@ -8,7 +8,8 @@ inputs for the solver; nothing in the solver or its checks calls it.
 
 The Hamiltonian it diagonalises is the grid-defined operator: kinetic term
 0.5|k+G|^2 on the diagonal plus the cyclic convolution with the discrete
-Fourier coefficients of the sampled potential V(r_j).
+Fourier coefficients of the sampled potential V(r_j), plus, when given, the
+separable non-local term sum_i E_i beta_i beta_i^H.
 """
 from __future__ import annotations
 
@@ -35,7 +36,7 @@ def _potential_matrix(miller: np.ndarray, v_grid: np.ndarray) -> np.ndarray:
 GPU_EIGH_MIN_PW = 8000
 
 
-def _lowest_states_gpu(miller, B, kvec, v_grid, n_states):
+def _lowest_states_gpu(miller, B, kvec, v_grid, n_states, nl=None):
     """The same Hamiltonian and eigenpairs with torch.linalg.eigh on the GPU (rocSOLVER): for the
     64-atom cell the CPU eigensolver takes over a quarter of an hour.  Input generation only."""
     import torch
@@ -50,6 +51,11 @@ def _lowest_states_gpu(miller, B, kvec, v_grid, n_states):
         d = [(mr[:, None, a] - m[None, :, a]) % grid[a] for a in range(3)]
         h[r0:r0 + 2048] = vq[d[0], d[1], d[2]]
     h.diagonal().add_(torch.from_numpy(kinetic_energies(miller, B, kvec)).to(dev))
+    if nl is not None:
+        beta = torch.from_numpy(np.asarray(nl[0], np.complex128)).to(dev)
+        e = torch.from_numpy(np.asarray(nl[1], np.float64)).to(dev).to(torch.complex128)
+        h += (beta.T * e[None, :]) @ beta.conj()
+        del beta
     h = 0.5 * (h + h.conj().T)
     import sys
     import time
@@ -65,7 +71,7 @@ def _lowest_states_gpu(miller, B, kvec, v_grid, n_states):
     return w, u
 
 
-def _cache_path(miller, B, kvec, v_grid, n_states):
+def _cache_path(miller, B, kvec, v_grid, n_states, nl=None):
     """File of a cached eigensystem under $SYNTH_EIGH_CACHE (unset: no cache), keyed by the inputs."""
     root = os.environ.get("SYNTH_EIGH_CACHE")
     if not root:
@@ -73,11 +79,14 @@ def _cache_path(miller, B, kvec, v_grid, n_states):
     h = hashlib.sha256()
     for a in (np.asarray(miller, np.int64), np.asarray(B, float), np.asarray(kvec, float), np.asarray(v_grid, float)):
         h.update(np.ascontiguousarray(a).tobytes())
+    if nl is not None:
+        h.update(np.ascontiguousarray(np.asarray(nl[0], np.complex128)).tobytes())
+        h.update(np.ascontiguousarray(np.asarray(nl[1], np.float64)).tobytes())
     h.update(str(n_states).encode())
     return os.path.join(root, f"eigh_{h.hexdigest()[:24]}.npz")
 
 
-def lowest_states(miller: np.ndarray, B: np.ndarray, kvec, v_grid: np.ndarray, n_states: int):
+def lowest_states(miller: np.ndarray, B: np.ndarray, kvec, v_grid: np.ndarray, n_states: int, nl=None):
     """Lowest ``n_states`` eigenpairs of the plane-wave Hamiltonian.
 
     Returns (energies [n_states] in Ha ascending, states [n_states][n_pw] complex128,
@@ -85,18 +94,22 @@ def lowest_states(miller: np.ndarray, B: np.ndarray, kvec, v_grid: np.ndarray, n
     that its largest-magnitude coefficient (first one on ties) is real positive.
     With $SYNTH_EIGH_CACHE set, the result is stored there and later calls with the same
     inputs load it instead of diagonalising again (e.g. profiler runs that should not
-    trace the eigensolver).
+    trace the eigensolver).  ``nl`` = (beta [n_proj][n_pw], e_kb [n_proj]) adds the separable
+    non-local term.
     """
     n_states = min(n_states, miller.shape[0])
-    path = _cache_path(miller, B, kvec, v_grid, n_states)
+    path = _cache_path(miller, B, kvec, v_grid, n_states, nl)
     if path and os.path.exists(path):
         with np.load(path) as d:
             return d["w"], d["u"]
     if miller.shape[0] >= GPU_EIGH_MIN_PW and _gpu_present():
-        w, u = _lowest_states_gpu(miller, B, kvec, v_grid, n_states)
+        w, u = _lowest_states_gpu(miller, B, kvec, v_grid, n_states, nl)
     else:
         h = _potential_matrix(miller, v_grid)
         h[np.diag_indices_from(h)] += kinetic_energies(miller, B, kvec)
+        if nl is not None:
+            beta, e = np.asarray(nl[0], np.complex128), np.asarray(nl[1], float)
+            h += (beta.T * e[None, :]) @ beta.conj()
         h = 0.5 * (h + h.conj().T)
         w, u = sla.eigh(h, subset_by_index=[0, n_states - 1], driver="evr")
         u = u.T.copy()

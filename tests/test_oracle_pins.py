@@ -350,10 +350,66 @@ def check_green_routes_and_symmetry():
     assert np.abs(g - approx).max() <= 5 * np.abs(h @ h).max() / abs(z) ** 3
 
 
+def _nl_cell(ecut=2.5):
+    """fcc primitive cell with a basis whose Miller indices stay within |m| <= 3: on a 16-point grid
+    no difference m_i - m_j aliases, so the grid-defined local potential is exactly the Fourier series
+    of the continuous one."""
+    A, tau = cx.fcc_primitive(A_LAT)
+    B = cx.reciprocal(A)
+    k = np.array([0.031, -0.017, 0.052])
+    miller = cx.g_sphere(B, k, ecut)
+    assert np.abs(miller).max() <= 3 and len(miller) >= 20
+    return A, tau, B, k, miller, (16, 16, 16)
+
+
+def check_nonlocal_translation():
+    """Moving every atom by the same vector d multiplies the local potential's coefficients by
+    exp(-i G.d) and every projector by exp(-i (k+G).d), so the Hamiltonian must transform as
+    H(tau + d) = U H(tau) U^H with U = diag(exp(-i (k+G).d)).  This fixes the relative phase
+    convention of the non-local and local parts (a conjugated or transposed V_NL breaks it)."""
+    A, tau, B, k, miller, grid = _nl_cell()
+    d = np.array([0.37, -1.21, 0.58])
+    hs = []
+    for t in (tau, tau + d):
+        v = cx.gaussian_potential(A, t, grid, noise=0.0)
+        nl = cx.kb_projectors(miller, B, k, A, t, e_s=0.6, e_p=-0.45)
+        hs.append(so.hamiltonian(miller, B, k, v, nl=nl))
+    u = np.exp(-1j * ((miller @ B + k) @ d))
+    h1 = (u[:, None] * hs[0]) * u.conj()[None, :]
+    assert np.abs(hs[1] - h1).max() <= 1e-12 * np.abs(hs[0]).max()
+    # the non-local part is not negligible here
+    assert np.abs(so.nonlocal_matrix(*nl)).max() >= 0.05 * np.abs(hs[0]).max()
+    # sampled rows by the same definition
+    rows = np.array([0, 5, len(miller) - 1])
+    hr = so.hamiltonian_rows(miller, B, k, v, rows, nl=nl)
+    assert np.abs(hr - hs[1][rows]).max() <= 1e-14 * np.abs(hs[1]).max()
+
+
+def check_nonlocal_secular():
+    """Free electrons plus one projector: the eigenvalues of T + E beta beta^H away from the kinetic
+    levels are the roots of the secular equation E sum_G |beta_G|^2 / (lambda - T_G) = 1, and there is
+    one such root between consecutive distinct levels (rank-one update of a diagonal matrix)."""
+    A, tau, B, k, miller, grid = _nl_cell()
+    beta, _ = cx.kb_projectors(miller, B, k, A, tau[1:] + np.array([0.2, 0.1, -0.3]), channels="s")
+    e = 0.7
+    h = so.hamiltonian(miller, B, k, np.zeros(grid), nl=(beta, np.array([e])))
+    lam = np.linalg.eigvalsh(h)
+    t = 0.5 * ((miller @ B + k) ** 2).sum(1)      # kinetic closed form, written out here
+    w2 = np.abs(beta[0]) ** 2
+    far = [x for x in lam if np.abs(x - t).min() > 1e-3]
+    assert len(far) >= 5
+    for x in far:
+        f = e * np.sum(w2 / (x - t))
+        assert abs(f - 1.0) <= 1e-7, (x, f)
+    # interlacing: the largest root lies above max T (E > 0) and every level moved up
+    assert lam.max() > t.max() and np.all(np.sort(lam) >= np.sort(t) - 1e-12)
+
+
 PINS = [check_kinetic_closed_form, check_hamiltonian_bruteforce, check_shifted_source_realspace,
         check_free_electron_closed_form, check_mpmath_tiny, check_routes_and_invariants,
         check_linearity_and_reciprocity, check_relative_residual_closed_form, check_condition_number_svd,
-        check_green_free_electron, check_green_routes_and_symmetry]
+        check_green_free_electron, check_green_routes_and_symmetry, check_nonlocal_translation,
+        check_nonlocal_secular]
 
 
 @pytest.mark.parametrize("pin", PINS + [check_generator_ground_state], ids=lambda f: f.__name__)
@@ -383,8 +439,8 @@ _orig_green_lu = so.green_column_lu
 _orig_kappa = so.condition_number
 
 
-def _mut_transposed_potential(miller, B, kvec, v_grid):
-    h = _orig_ham(miller, B, kvec, v_grid)
+def _mut_transposed_potential(miller, B, kvec, v_grid, nl=None):
+    h = _orig_ham(miller, B, kvec, v_grid, nl=nl)
     return h.T.copy()
 
 
@@ -392,9 +448,12 @@ _orig_ham = so.hamiltonian
 _orig_rows = so.hamiltonian_rows
 
 
-def _mut_rows_index_swap(miller, B, kvec, v_grid, rows):
+def _mut_rows_index_swap(miller, B, kvec, v_grid, rows, nl=None):
     # V~ at m_j - m_i instead of m_i - m_j
-    return _orig_ham(miller, B, kvec, v_grid).T[np.asarray(rows)].copy()
+    return _orig_ham(miller, B, kvec, v_grid, nl=nl).T[np.asarray(rows)].copy()
+
+
+_orig_nl = so.nonlocal_matrix
 
 MUTATIONS = {
     "rhs_sign": ("rhs", lambda *a: -_orig_rhs(*a)),
@@ -421,6 +480,14 @@ MUTATIONS = {
                       lambda w, u, c, z: np.einsum("gn,cn,zn->czg", u, u[np.asarray(c), :],
                                                    1.0 / (np.atleast_1d(np.asarray(z, complex))[:, None] - w[None, :]))),
     "green_lu_rhs_sign": ("green_column_lu", lambda h, c, z: -_orig_green_lu(h, c, z)),
+    "nl_conjugated": ("nonlocal_matrix", lambda b, e, rows=None: np.conj(_orig_nl(b, e, rows))),
+    "nl_energy_dropped": ("nonlocal_matrix", lambda b, e, rows=None: _orig_nl(b, np.ones_like(e), rows)),
+    "nl_energy_sign": ("nonlocal_matrix", lambda b, e, rows=None: _orig_nl(b, -np.asarray(e), rows)),
+    "nl_energy_squared": ("nonlocal_matrix",
+                          lambda b, e, rows=None: _orig_nl(b, np.asarray(e) ** 2, rows)),
+    "nl_rows_conjugated": ("nonlocal_matrix",
+                           lambda b, e, rows=None: (_orig_nl(b, e, rows) if rows is None
+                                                    else np.conj(_orig_nl(b, e, rows)))),
 }
 
 
