@@ -143,7 +143,7 @@ sgw_status sgw_plane_kernel(sgw_ctx *ctx, const sgw_ham *ham, int precision, int
 sgw_status sgw_ctx_reset_stats(sgw_ctx *ctx);
 /*
  * Statistics of kernel `name` ("hx_sticks_inv", "hx_planes", "hx_sticks_fwd",
- * "proj_dot", "lanczos_step", "combine", "residual", ...).  Outputs may be NULL.
+ * "proj_dot", "lanczos_step", "combine", "residual", "nl_dot", "nl_apply", ...).  Outputs may be NULL.
  * Durations are summed over launches, in milliseconds.
  */
 sgw_status sgw_kernel_stats(sgw_ctx *ctx, const char *name, int64_t *launches, double *total_ms,
@@ -174,7 +174,28 @@ sgw_status sgw_ham_destroy(sgw_ham *ham);
 int32_t sgw_ham_npw(const sgw_ham *ham);
 
 /*
- * y = H x for n_vec vectors (Sec. 2.1): y_G = 0.5|k+G|^2 x_G + [F V F^-1 x]_G
+ * Non-local part of the pseudopotential, represented in reciprocal space (Sec. 2.1, the text after
+ * Eq. 1), in the fully separable form V_NL = sum_p |beta_p> E_p <beta_p|: every later H.x of `ham`
+ * (sgw_apply_h, the solves, the Green's function columns) adds
+ *     [V_NL x]_G = sum_p E_p beta_p(G) sum_G' conj(beta_p(G')) x_G'
+ * as two FP64 matrix-core contractions (in every precision mode).  A Hermitian coupling matrix
+ * between the projectors of an atom reduces to this form by diagonalising it.
+ *   n_proj  number of projectors, 0 <= n_proj <= 4096 (above: SGW_ERR_UNSUPPORTED); 0 removes the term
+ *   beta    device [n_proj][n_pw] complex128, rows in the caller's plane-wave order; copied into
+ *           memory the Hamiltonian owns before the call returns
+ *   e_kb    host [n_proj] energies E_p in Ha, finite
+ * Replaces any earlier projectors.  The call waits for the context's stream first; it must not run
+ * while another stream or thread uses `ham`.  Set it before sizing workspaces (the H.x scratch of a
+ * solve holds the projector overlaps).  NULL arguments, negative n_proj or non-finite energies:
+ * SGW_ERR_INVALID_ARG.
+ */
+sgw_status sgw_ham_set_nonlocal(sgw_ctx *ctx, sgw_ham *ham, int n_proj, const sgw_c128 *beta, const double *e_kb);
+/* Number of non-local projectors of a Hamiltonian (0: none). */
+int32_t sgw_ham_nproj(const sgw_ham *ham);
+
+/*
+ * y = H x for n_vec vectors (Sec. 2.1): y_G = 0.5|k+G|^2 x_G + [F V F^-1 x]_G (+ [V_NL x]_G when
+ * the Hamiltonian has non-local projectors, sgw_ham_set_nonlocal)
  * with F^-1 x (r_j) = sum_G x_G exp(i G.r_j) and F f (G) = (1/N) sum_j f_j exp(-i G.r_j).
  * x, y: device [n_vec][n_pw] in the caller's order; may not alias.
  * precision SGW_FP64, or SGW_MIXED: the potential term in FP32 (x rounded to
@@ -188,8 +209,9 @@ sgw_status sgw_apply_h(sgw_ctx *ctx, const sgw_ham *ham, int n_vec, const sgw_c1
  * capture, tight serving loops, harnesses that forbid hipMalloc).  Same arguments, kernels and
  * result as sgw_apply_h, bit for bit.  Its scratch (x and y in the library's internal plane-wave
  * order and the stick buffer between the FFT passes) lives in one fixed 64 MiB device array per GPU,
- * held until the process ends: n_vec * (32 n_pw + 16 N2 n_sticks) bytes (each part rounded up to 256)
- * must fit, about 170 vectors of the 16-atom cell (48^3 grid) or 45 of the 64-atom cell (72^3);
+ * held until the process ends: n_vec * (32 n_pw + 16 max(N2 n_sticks, n_chunks n_proj)) bytes, with
+ * n_chunks = ceil(n_pw / 256) (each part rounded up to 256), must fit, about 170 vectors of the
+ * 16-atom cell (48^3 grid) or 45 of the 64-atom cell (72^3);
  * larger calls return SGW_ERR_WORKSPACE before any GPU work.  No scratch value has to start at zero:
  * every kernel writes each scratch element before reading it.  Every call on one GPU shares that GPU's
  * array, so calls that overlap on one GPU (other contexts, streams or host threads) race; calls on one

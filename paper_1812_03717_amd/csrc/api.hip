@@ -32,7 +32,8 @@ sgw_status fail(sgw_status code, const std::string &msg) {
 const char *kernel_name(int id) {
   static const char *names[K_COUNT] = {"hx_sticks_inv", "hx_planes", "hx_sticks_fwd", "proj_dot",
                                        "proj_apply",    "rhs_source", "slot_init",    "lanczos_step",
-                                       "tridiag",       "combine",   "residual",     "permute"};
+                                       "tridiag",       "combine",   "residual",     "permute",
+                                       "nl_dot",        "nl_apply"};
   return (id >= 0 && id < K_COUNT) ? names[id] : "?";
 }
 
@@ -264,8 +265,9 @@ static sgw_status upload(sgw_ctx *ctx, T **dst, const std::vector<T> &src) {
 
 static void ham_free(sgw_ham *h) {
   if (!h) return;
-  void *ptrs[] = {h->d_i2u, h->d_u2i, h->d_stick_off, h->d_rows, h->d_stick_ij, h->d_pw_stick, h->d_pw_z,
-                  h->d_miller_int, h->d_kin, h->d_vt, h->d_box, h->d_tw, h->d_vt32, h->d_tw32};
+  void *ptrs[] = {h->d_i2u, h->d_u2i,  h->d_stick_off, h->d_rows, h->d_stick_ij, h->d_pw_stick,
+                  h->d_pw_z, h->d_miller_int, h->d_kin, h->d_vt, h->d_box, h->d_tw,
+                  h->d_vt32, h->d_tw32, h->d_beta, h->d_ekb};
   for (void *p : ptrs)
     if (p) hipFree(p);
   delete h;
@@ -440,6 +442,52 @@ extern "C" sgw_status sgw_ham_destroy(sgw_ham *h) {
 
 extern "C" int32_t sgw_ham_npw(const sgw_ham *h) { return h ? h->n_pw : -1; }
 
+// Largest number of non-local projectors per Hamiltonian (bounds the overlap scratch of H.x).
+static constexpr int kMaxProj = 4096;
+
+extern "C" sgw_status sgw_ham_set_nonlocal(sgw_ctx *ctx, sgw_ham *h, int n_proj, const sgw_c128 *beta,
+                                           const double *e_kb) {
+  if (!ctx || !h) return fail(SGW_ERR_INVALID_ARG, "sgw_ham_set_nonlocal: NULL context or Hamiltonian");
+  if (h->device != ctx->device)
+    return fail(SGW_ERR_INVALID_ARG, "sgw_ham_set_nonlocal: the Hamiltonian lives on another device");
+  if (n_proj < 0) return fail(SGW_ERR_INVALID_ARG, "sgw_ham_set_nonlocal: n_proj < 0");
+  if (n_proj > kMaxProj)
+    return fail(SGW_ERR_UNSUPPORTED, "sgw_ham_set_nonlocal: more than " + std::to_string(kMaxProj) + " projectors");
+  if (n_proj > 0 && (!beta || !e_kb)) return fail(SGW_ERR_INVALID_ARG, "sgw_ham_set_nonlocal: NULL beta or e_kb");
+  for (int p = 0; p < n_proj; ++p)
+    if (!std::isfinite(e_kb[p])) return fail(SGW_ERR_INVALID_ARG, "sgw_ham_set_nonlocal: e_kb not finite");
+  SGW_HIP(hipSetDevice(ctx->device));
+  // launches of earlier calls on this stream may still read the old projectors
+  SGW_HIP(hipStreamSynchronize(ctx->stream));
+  if (h->d_beta) hipFree(h->d_beta);
+  if (h->d_ekb) hipFree(h->d_ekb);
+  h->d_beta = nullptr;
+  h->d_ekb = nullptr;
+  h->n_proj = 0;
+  if (n_proj == 0) return SGW_OK;
+  const int npw = h->n_pw;
+  double2 *db = nullptr;
+  double *de = nullptr;
+  hipError_t e = hipMalloc((void **)&db, sizeof(double2) * (size_t)n_proj * npw);
+  if (e == hipSuccess) e = hipMalloc((void **)&de, sizeof(double) * n_proj);
+  if (e == hipSuccess) e = hipMemcpyAsync(de, e_kb, sizeof(double) * n_proj, hipMemcpyHostToDevice, ctx->stream);
+  sgw_status st = SGW_OK;
+  if (e == hipSuccess) st = permute(ctx, npw, n_proj, (const double2 *)beta, npw, db, npw, h->d_i2u, 0);
+  const hipError_t e2 = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess || st != SGW_OK || e2 != hipSuccess) {
+    if (db) hipFree(db);
+    if (de) hipFree(de);
+    if (st != SGW_OK) return st;
+    return fail(SGW_ERR_HIP, std::string("sgw_ham_set_nonlocal: ") + hipGetErrorString(e != hipSuccess ? e : e2));
+  }
+  h->d_beta = db;
+  h->d_ekb = de;
+  h->n_proj = n_proj;
+  return SGW_OK;
+}
+
+extern "C" int32_t sgw_ham_nproj(const sgw_ham *h) { return h ? h->n_proj : -1; }
+
 // ---------------------------------------------------------------------------
 // test hooks
 // ---------------------------------------------------------------------------
@@ -476,7 +524,7 @@ extern "C" sgw_status sgw_apply_h(sgw_ctx *ctx, const sgw_ham *h, int n_vec, con
   sgw_status st;
   if ((st = alloc_async(xi, vb, ctx->stream)) != SGW_OK) return st;
   if ((st = alloc_async(yi, vb, ctx->stream)) != SGW_OK) return st;
-  if ((st = alloc_async(tb, sizeof(double2) * (size_t)n_vec * h->n[2] * h->n_stick, ctx->stream)) != SGW_OK)
+  if ((st = alloc_async(tb, hx_tbuf_bytes(h, n_vec), ctx->stream)) != SGW_OK)
     return st;
   if ((st = permute(ctx, npw, n_vec, (const double2 *)x, npw, (double2 *)xi.p, npw, h->d_i2u, 0)) != SGW_OK)
     return st;
@@ -501,9 +549,9 @@ extern "C" sgw_status sgw_apply_h_noalloc(sgw_ctx *ctx, const sgw_ham *h, int n_
   auto up = [](size_t b) { return (b + kAlign256 - 1) / kAlign256 * kAlign256; };
   const size_t per_vec = sizeof(double2) * (size_t)npw;
   const size_t vb = up(per_vec * n_vec);
-  const size_t tb = up(sizeof(double2) * (size_t)n_vec * h->n[2] * h->n_stick);
+  const size_t tb = up(hx_tbuf_bytes(h, n_vec));
   if (2 * vb + tb > kNoAllocScratchBytes) {
-    const size_t one = 2 * up(per_vec) + up(sizeof(double2) * (size_t)h->n[2] * h->n_stick);
+    const size_t one = 2 * up(per_vec) + up(hx_tbuf_bytes(h, 1));
     return fail(SGW_ERR_WORKSPACE, "sgw_apply_h_noalloc: " + std::to_string(n_vec) + " vectors need " +
                                        std::to_string(2 * vb + tb) + " bytes of scratch; the fixed scratch holds " +
                                        std::to_string(kNoAllocScratchBytes) + " (about " +
@@ -711,11 +759,11 @@ Layout make_layout(const sgw_ham *h, int n_occ, int n_band, int n_pert, int n_om
   L.M = o.steps_per_sync;
   L.F = o.finalize_batch > 0 ? o.finalize_batch : std::max(1, (4096 + n_omega - 1) / n_omega);
   L.F = std::max(1, std::min(L.F, std::max(n_pairs, 1)));
-  const double per_slot = (double)(L.kmax + 3) * npw * 16.0 + (double)npw * 16.0 * h->n[2] * 0 +
-                          (double)h->n[2] * h->n_stick * 16.0 + (L.kmax * 2.0 + n_omega * 24.0 + 64.0);
+  const double per_slot = (double)(L.kmax + 3) * npw * 16.0 + (double)hx_tbuf_bytes(h, 1) +
+                          (L.kmax * 2.0 + n_omega * 24.0 + 64.0);
   int S = o.slots;
   if (S <= 0) {
-    const double fixed = (double)L.F * n_omega * (2.0 * npw * 16.0 + h->n[2] * h->n_stick * 16.0);
+    const double fixed = (double)L.F * n_omega * (2.0 * npw * 16.0 + (double)hx_tbuf_bytes(h, 1));
     S = (int)std::max(1.0, (kDefaultBudget - fixed) / per_slot);
     S = std::min(S, 4096);
   }
@@ -729,7 +777,7 @@ Layout make_layout(const sgw_ham *h, int n_occ, int n_band, int n_pert, int n_om
     L.nblk = o.basis_blocks;
   } else if (o.slots <= 0 && S < n_pairs) {
     // the budget cannot give every pair a full-size slot: more slots share a pool of the same size
-    const double fixed = (double)L.F * n_omega * (2.0 * npw * 16.0 + h->n[2] * h->n_stick * 16.0);
+    const double fixed = (double)L.F * n_omega * (2.0 * npw * 16.0 + (double)hx_tbuf_bytes(h, 1));
     const double blk_bytes = (double)(1 << L.bshift) * npw * 16.0;
     const double small = per_slot - (double)(L.kmax + 1) * npw * 16.0;  // a slot without its basis
     S = std::max(1, std::min({n_pairs, 4096, kPoolSlotFactor * S}));
@@ -770,7 +818,7 @@ Layout make_layout(const sgw_ham *h, int n_occ, int n_band, int n_pert, int n_om
   L.Y2 = take(off, 16ul * L.S * npw);
   L.c_rows = tv;
   L.C = take(off, 16ul * kProjChunks * tv * std::max(n_occ, 1));
-  L.T = take(off, 16ul * tv * h->n[2] * h->n_stick);
+  L.T = take(off, hx_tbuf_bytes(h, tv));
   L.ycoef = take(off, 16ul * L.F * L.kmax * n_omega);
   L.cp = take(off, 16ul * L.F * L.kmax * n_omega);
   L.order = take(off, 4ul * L.F * n_omega);
@@ -829,27 +877,36 @@ static sgw_status validate_solve(sgw_ctx *ctx, const sgw_ham *h_kq, int n_occ, c
   return check_miller_shift(dv_miller, n_pert);
 }
 
-// A captured sequence of launches on one stream, replayed with hipGraphLaunch.
+// A captured sequence of launches on one stream, replayed with hipGraphLaunch.  An event recorded
+// after every replay marks when the executable graph is no longer in use: a re-capture and the
+// destructor (also on error returns, with a replay possibly still queued) wait for it before the
+// executable graph is destroyed.
 struct StepGraph {
   hipGraphExec_t exec = nullptr;
+  hipEvent_t done = nullptr;
   int na = -1, n64 = -1;
   StepGraph() = default;
   StepGraph(const StepGraph &) = delete;
   StepGraph &operator=(const StepGraph &) = delete;
   ~StepGraph() {
-    if (exec) hipGraphExecDestroy(exec);
+    release();
+    if (done) hipEventDestroy(done);
+  }
+  void release() {
+    if (!exec) return;
+    if (done) hipEventSynchronize(done);
+    hipGraphExecDestroy(exec);
+    exec = nullptr;
+  }
+  sgw_status launch(hipStream_t stream) {
+    if (!done) SGW_HIP(hipEventCreateWithFlags(&done, hipEventDisableTiming));
+    SGW_HIP(hipGraphLaunch(exec, stream));
+    SGW_HIP(hipEventRecord(done, stream));
+    return SGW_OK;
   }
   template <class F>
   sgw_status capture(hipStream_t stream, F &&launches) {
-    if (exec) {
-      // an executable graph is destroyed only once its last launch has completed (the solver
-      // re-captures after the poll has synchronised the stream; this keeps it so)
-      const hipError_t q = hipStreamQuery(stream);
-      if (q == hipErrorNotReady) return fail(SGW_ERR_HIP, "StepGraph: re-capture while the stream still runs");
-      if (q != hipSuccess) return fail(SGW_ERR_HIP, std::string("hipStreamQuery: ") + hipGetErrorString(q));
-      hipGraphExecDestroy(exec);
-    }
-    exec = nullptr;
+    release();
     na = -1;
     n64 = -1;
     SGW_HIP(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
@@ -1217,7 +1274,7 @@ static sgw_status multishift_solve(sgw_ctx *ctx, const sgw_ham *h_kq, int n_occ,
           graph.na = na;
           graph.n64 = n64;
         }
-        SGW_HIP(hipGraphLaunch(graph.exec, ctx->stream));
+        if ((st = graph.launch(ctx->stream)) != SGW_OK) return st;
       } else if ((st = steps()) != SGW_OK) {
         return st;
       }
@@ -1670,7 +1727,7 @@ extern "C" sgw_status sgw_autotune(sgw_ctx *ctx, const sgw_problem *problem, sgw
     const sgw_ham *h = p.h_kq;
     const int nv = (int)std::min<long>(512, std::max<long>(1, (long)p.n_band * p.n_pert));
     const size_t vb = sizeof(double2) * (size_t)nv * h->n_pw;
-    const size_t tb = sizeof(double2) * (size_t)nv * h->n[2] * h->n_stick;
+    const size_t tb = hx_tbuf_bytes(h, nv);
     void *hb = nullptr;
     if (hipMalloc(&hb, 2 * vb + tb) != hipSuccess) {
       st = fail(SGW_ERR_HIP, "sgw_autotune: H.x buffers");

@@ -627,8 +627,16 @@ sgw_status hx_run(sgw_ctx *ctx, const sgw_ham *h, int n_vec, VecSrc x, double2 *
 sgw_status hx_batch(sgw_ctx *ctx, const sgw_ham *h, int n_vec, VecSrc x, double2 *y, long ldy, void *tbuf,
                     bool fp32) {
   if (n_vec <= 0) return SGW_OK;
-  if (fp32) return hx_run<float2>(ctx, h, n_vec, x, y, ldy, (float2 *)tbuf);
-  return hx_run<double2>(ctx, h, n_vec, x, y, ldy, (double2 *)tbuf);
+  const sgw_status st = fp32 ? hx_run<float2>(ctx, h, n_vec, x, y, ldy, (float2 *)tbuf)
+                             : hx_run<double2>(ctx, h, n_vec, x, y, ldy, (double2 *)tbuf);
+  if (st != SGW_OK || h->n_proj == 0) return st;
+  // separable non-local term (Sec. 2.1, in reciprocal space): y += beta^T (E . (beta^H x)) on the
+  // FP64 matrix cores; the stick buffer is free once the forward stick pass has run and takes the
+  // overlaps
+  double2 *cp = (double2 *)tbuf;
+  const sgw_status s2 = proj_dot(ctx, h->n_pw, h->n_proj, h->d_beta, n_vec, x, cp, n_vec, K_NL_DOT);
+  if (s2 != SGW_OK) return s2;
+  return proj_apply(ctx, h->n_pw, h->n_proj, h->d_beta, n_vec, x, cp, n_vec, y, ldy, 1.0, 1, h->d_ekb, K_NL_APPLY);
 }
 
 }  // namespace sgw

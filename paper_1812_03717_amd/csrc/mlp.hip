@@ -480,7 +480,7 @@ extern "C" sgw_status sgw_operator_columns(sgw_ctx *ctx, const sgw_ham *h, int n
   void *buf = nullptr;
   // [psi (internal order) | X | Y | T | C]
   const size_t psi_b = sizeof(double2) * (size_t)std::max(n_occ, 1) * npw;
-  const size_t t_b = sizeof(double2) * (size_t)batch * h->n[2] * h->n_stick;
+  const size_t t_b = hx_tbuf_bytes(h, batch);
   const size_t c_b = sizeof(double2) * (size_t)kProjChunks * batch * std::max(n_occ, 1);
   auto al = [](size_t x) { return (x + 255) / 256 * 256; };
   SGW_HIP(hipMalloc(&buf, al(psi_b) + 2 * al(vb) + al(t_b) + al(c_b)));

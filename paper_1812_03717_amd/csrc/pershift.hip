@@ -455,7 +455,7 @@ PsLayout ps_layout(const sgw_ham *h, int n_occ, int n_band, int n_pert, int n_om
                    long n_systems) {
   PsLayout L;
   const long npw = h->n_pw;
-  const double per_slot = 12.0 * npw * 16.0 + (double)h->n[2] * h->n_stick * 16.0 +
+  const double per_slot = 12.0 * npw * 16.0 + (double)hx_tbuf_bytes(h, 1) +
                           16.0 * kProjChunks * std::max(n_occ, 1) + 160.0;
   long B = o.ps_slots > 0 ? o.ps_slots : (long)std::min<double>(kPsMaxSlots, std::max(1.0, kPsBudget / per_slot));
   B = std::max<long>(1, std::min<long>(B, std::max<long>(n_systems, 1)));
@@ -489,7 +489,7 @@ PsLayout ps_layout(const sgw_ham *h, int n_occ, int n_band, int n_pert, int n_om
   L.Y = ps_take(off, 16ul * B * npw);
   L.Y2 = ps_take(off, 16ul * B * npw);
   L.C = ps_take(off, 16ul * kProjChunks * B * std::max(n_occ, 1));
-  L.T = ps_take(off, 16ul * B * h->n[2] * h->n_stick);
+  L.T = ps_take(off, hx_tbuf_bytes(h, B));
   L.bad = ps_take(off, 64);
   L.total = (off + kPsAlign - 1) / kPsAlign * kPsAlign;
   return L;

@@ -3,6 +3,10 @@
 //   overlaps:  C[a][i] = sum_g conj(psi[i][g]) x_a[g]      (n_occ x n_vec, K = n_pw)
 //   apply:     y_a[g]  = x_a[g] - sum_i psi[i][g] C[a][i]   (mode 0: 1 - P_occ)
 //              y_a[g] += alpha sum_i psi[i][g] C[a][i]     (mode 1: + alpha P_occ)
+//              (C[a][i] scaled by s[i] first when a row scale is given)
+//
+// The same contraction applies the separable non-local pseudopotential in H.x
+// (Sec. 2.1): psi -> the projectors beta_p, s -> their energies E_p, mode 1.
 //
 // Both are complex GEMMs done as four real 16x16x4 FP64 MFMAs per step
 // (re*re, im*im, re*im, im*re).  Workgroups of four wavefronts own large output
@@ -207,7 +211,7 @@ template <int TV>
 __global__ __launch_bounds__(256) void k_proj_apply(int npw, int n_occ, const double2 *__restrict__ psi, VecSrc x,
                                                     int n_vec, const double2 *__restrict__ cp,
                                                     double2 *__restrict__ y, long ldy, double alpha, int mode,
-                                                    int gtiles, int vtiles) {
+                                                    const double *__restrict__ row_scale, int gtiles, int vtiles) {
   constexpr int MV = TV / 16;  // vector tiles per wave (rows of the MFMA output)
   __shared__ double2 cs[TV][kApplyKB + 1];  // C of the tile's vectors, one block of occupied states
   const int xcd = blockIdx.x % kXcdCount;
@@ -238,7 +242,12 @@ __global__ __launch_bounds__(256) void k_proj_apply(int npw, int n_occ, const do
     __syncthreads();  // the previous block's C is no longer read
     for (int e = tid; e < TV * kApplyKB; e += 256) {
       const int v = e / kApplyKB, i = e - v * kApplyKB;
-      const double2 t = cp[(long)min(a0 + v, n_vec - 1) * n_occ + ib + min(i, kb - 1)];
+      const int ic = ib + min(i, kb - 1);
+      double2 t = cp[(long)min(a0 + v, n_vec - 1) * n_occ + ic];
+      if (row_scale) {
+        const double sc = row_scale[ic];
+        t = make_double2(t.x * sc, t.y * sc);
+      }
       cs[v][i] = keep_if(a0 + v < n_vec && i < kb, t);
     }
     __syncthreads();
@@ -326,7 +335,7 @@ int proj_chunks(int npw, int *kc) {
 }
 
 sgw_status proj_dot(sgw_ctx *ctx, int npw, int n_occ, const double2 *psi, int n_vec, VecSrc x, double2 *cp,
-                    long rows) {
+                    long rows, int kid) {
   if (n_vec <= 0 || n_occ <= 0) return SGW_OK;
   int kc;
   const int nch = proj_chunks(npw, &kc);
@@ -340,7 +349,7 @@ sgw_status proj_dot(sgw_ctx *ctx, int npw, int n_occ, const double2 *psi, int n_
   const int otiles = (n_occ + to - 1) / to;
   const long groups = (long)((nch + kXcdCount - 1) / kXcdCount) * otiles * vtiles * kXcdCount;
   PendingTiming tm;
-  timing_begin(ctx, K_PROJ_DOT, n_vec * (npw * 16.0) + (double)n_occ * npw * 16.0, 8.0 * n_vec * npw * n_occ, &tm);
+  timing_begin(ctx, kid, n_vec * (npw * 16.0) + (double)n_occ * npw * 16.0, 8.0 * n_vec * npw * n_occ, &tm);
 #define SGW_DOT(TO, TV)                                                                                       \
   hipLaunchKernelGGL((k_proj_dot<TO, TV>), dim3(groups), dim3(256), 0, ctx->stream, npw, n_occ, psi, x, n_vec, \
                      nch, cp, rows, otiles, vtiles)
@@ -362,7 +371,7 @@ sgw_status proj_dot(sgw_ctx *ctx, int npw, int n_occ, const double2 *psi, int n_
 }
 
 sgw_status proj_apply(sgw_ctx *ctx, int npw, int n_occ, const double2 *psi, int n_vec, VecSrc x, const double2 *cp,
-                      long rows, double2 *y, long ldy, double alpha, int mode) {
+                      long rows, double2 *y, long ldy, double alpha, int mode, const double *row_scale, int kid) {
   if (n_vec <= 0) return SGW_OK;
   if (n_occ <= 0) {
     if (mode == 1) return SGW_OK;
@@ -374,9 +383,9 @@ sgw_status proj_apply(sgw_ctx *ctx, int npw, int n_occ, const double2 *psi, int 
   const int gtiles = (npw + kApplyG - 1) / kApplyG;
   const long groups = (long)((gtiles + kXcdCount - 1) / kXcdCount) * vtiles * kXcdCount;
   PendingTiming tm;
-  timing_begin(ctx, K_PROJ_APPLY, n_vec * (npw * 32.0) + (double)n_occ * npw * 16.0, 8.0 * n_vec * npw * n_occ, &tm);
+  timing_begin(ctx, kid, n_vec * (npw * 32.0) + (double)n_occ * npw * 16.0, 8.0 * n_vec * npw * n_occ, &tm);
   hipLaunchKernelGGL(k_proj_apply<tv>, dim3(groups), dim3(256), 0, ctx->stream, npw, n_occ, psi, x, n_vec, cp, y,
-                     ldy, alpha, mode, gtiles, vtiles);
+                     ldy, alpha, mode, row_scale, gtiles, vtiles);
   timing_end(ctx, &tm);
   SGW_HIP(hipGetLastError());
   return SGW_OK;

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <map>
 #include <string>
@@ -46,6 +47,8 @@ enum KernelId {
   K_COMBINE,
   K_RESIDUAL,
   K_PERMUTE,
+  K_NL_DOT,
+  K_NL_APPLY,
   K_COUNT
 };
 const char *kernel_name(int id);
@@ -110,6 +113,10 @@ struct sgw_ham {
   double2 *d_tw = nullptr;          // twiddles: 3 tables of N_d entries exp(-2 pi i t / N_d)
   float2 *d_tw32 = nullptr;         // the same in FP32
   int tw_off[3];
+  // separable non-local pseudopotential sum_p |beta_p> E_p <beta_p| (n_proj = 0: none)
+  int n_proj = 0;
+  double2 *d_beta = nullptr;        // [n_proj][n_pw] internal order
+  double *d_ekb = nullptr;          // [n_proj] E_p (Ha)
 };
 
 namespace sgw {
@@ -151,10 +158,12 @@ sgw_status ensure_pinned(sgw_ctx *ctx, size_t bytes);
 // waits for the context's stream, then collects kernel timings
 sgw_status sync(sgw_ctx *ctx);
 
-// H.x over a batch (internal order): y = T.x + F V F^-1 x.  `tbuf` holds
-// n_vec * N2 * n_stick complex entries (complex128, or complex64 when fp32).
-// fp32: the potential term F V F^-1 x runs in FP32 (x rounded to FP32, FP32
-// transforms and potential); the kinetic term and y stay FP64.
+// H.x over a batch (internal order): y = T.x + F V F^-1 x (+ V_NL x).  `tbuf` holds
+// hx_tbuf_bytes(h, n_vec) bytes: the stick buffer (n_vec * N2 * n_stick complex entries,
+// complex128, or complex64 when fp32), which also takes the non-local overlaps once the stick
+// passes are done.  fp32: the potential term F V F^-1 x runs in FP32 (x rounded to FP32, FP32
+// transforms and potential); the kinetic and non-local terms and y stay FP64.  x and y must not
+// overlap.
 sgw_status hx_batch(sgw_ctx *ctx, const sgw_ham *h, int n_vec, VecSrc x, double2 *y, long ldy, void *tbuf,
                     bool fp32 = false);
 bool hx_grid_supported(int n);
@@ -182,12 +191,22 @@ constexpr int kMaxWorkers = 16;
 int proj_chunks(int n_pw, int *kc);
 // cp[chunk][a][i] = sum_{g in chunk} conj(psi[i][g]) x_a[g], then cp[0][a][i] = the sum over all
 // chunks (in chunk order): on return chunk 0 holds the complete overlaps
+// (kid: the timing slot the launches are charged to)
 sgw_status proj_dot(sgw_ctx *ctx, int n_pw, int n_occ, const double2 *psi, int n_vec, VecSrc x,
-                    double2 *cp, long rows);
+                    double2 *cp, long rows, int kid = K_PROJ_DOT);
 // with c = cp[0]:  mode 0: y_a = x_a - psi^T c_a ; mode 1: y_a += alpha psi^T c_a
-// (mode 0 may run in place, y_a == x_a)
+// (mode 0 may run in place, y_a == x_a); row_scale (n_occ values, may be NULL) multiplies c_a[i]
+// by row_scale[i] first
 sgw_status proj_apply(sgw_ctx *ctx, int n_pw, int n_occ, const double2 *psi, int n_vec, VecSrc x,
-                      const double2 *cp, long rows, double2 *y, long ldy, double alpha, int mode);
+                      const double2 *cp, long rows, double2 *y, long ldy, double alpha, int mode,
+                      const double *row_scale = nullptr, int kid = K_PROJ_APPLY);
+// bytes of H.x scratch (`tbuf` of hx_batch) for n_vec vectors of h
+inline size_t hx_tbuf_bytes(const sgw_ham *h, long n_vec) {
+  int kc;
+  const size_t sticks = 16ul * (size_t)n_vec * h->n[2] * h->n_stick;
+  const size_t nl = h->n_proj > 0 ? 16ul * (size_t)n_vec * proj_chunks(h->n_pw, &kc) * h->n_proj : 0;
+  return std::max(sticks, nl);
+}
 // y_a = x_a
 sgw_status permute_copy(sgw_ctx *ctx, int n_pw, int n_vec, VecSrc x, double2 *y, long ldy);
 // out[a][g] = in[a][perm[g]] (gather) or out[a][perm[g]] = in[a][g] (scatter)

@@ -37,7 +37,7 @@ EXPORTED = [
     "sgw_mlp_destroy", "sgw_mlp_get_weights", "sgw_mlp_set_weights", "sgw_mlp_forward", "sgw_mlp_grad",
     "sgw_mlp_train_step", "sgw_operator_columns", "sgw_mlp_rows", "sternheimer_batch_workspace_size",
     "sternheimer_solve_batch", "sgw_autotune", "sgw_precond_values", "sgw_apply_h_noalloc",
-    "sgw_green_workspace_size", "sgw_green_solve",
+    "sgw_green_workspace_size", "sgw_green_solve", "sgw_ham_set_nonlocal", "sgw_ham_nproj",
 ]
 
 
@@ -128,6 +128,10 @@ def load_library(path: str = LIB_PATH):
         f.restype = C.c_int
     lib.sgw_ham_npw.argtypes = [vp]
     lib.sgw_ham_npw.restype = C.c_int32
+    lib.sgw_ham_nproj.argtypes = [vp]
+    lib.sgw_ham_nproj.restype = C.c_int32
+    lib.sgw_ham_set_nonlocal.argtypes = [vp, vp, C.c_int, vp, C.POINTER(C.c_double)]
+    lib.sgw_ham_set_nonlocal.restype = C.c_int
     lib.sgw_mlp_num_params.argtypes = []
     lib.sgw_mlp_num_params.restype = C.c_int32
     _lib = lib
@@ -229,6 +233,15 @@ class sgw_ham_create:
         self.n_pw = d.n_pw
         self.grid = tuple(int(g) for g in grid)
 
+    def set_nonlocal(self, beta, e_kb):
+        """Separable non-local pseudopotential: beta device complex128 [n_proj][n_pw] (caller order),
+        e_kb host energies [n_proj] (Ha); beta=None removes it."""
+        sgw_ham_set_nonlocal(self.ctx, self, beta, e_kb)
+
+    @property
+    def n_proj(self):
+        return int(load_library().sgw_ham_nproj(self.handle))
+
     def close(self):
         if getattr(self, "handle", None):
             load_library().sgw_ham_destroy(self.handle)
@@ -244,6 +257,19 @@ class sgw_ham_create:
 # ---------------------------------------------------------------------------
 # calls
 # ---------------------------------------------------------------------------
+
+def sgw_ham_set_nonlocal(ctx, ham, beta, e_kb):
+    import torch
+    if beta is None:
+        _check(load_library().sgw_ham_set_nonlocal(ctx.handle, ham.handle, 0, None, None))
+        return
+    _require(beta, torch.complex128, ctx.device, (beta.shape[0], ham.n_pw), "beta")
+    e = np.ascontiguousarray(np.asarray(e_kb, np.float64))
+    if e.shape != (beta.shape[0],):
+        raise ValueError(f"e_kb has shape {e.shape}, expected ({beta.shape[0]},)")
+    _check(load_library().sgw_ham_set_nonlocal(ctx.handle, ham.handle, int(beta.shape[0]), _ptr(beta),
+                                               e.ctypes.data_as(C.POINTER(C.c_double))))
+
 
 def sgw_apply_h(ctx, ham, x, precision=0):
     import torch

@@ -23,6 +23,10 @@ class DeviceProblem:
         same = np.array_equal(p.miller_k, p.miller_kq) and np.allclose(p.qvec, 0.0)
         self.h_kq = self.h_k if same else sgw.sgw_ham_create(ctx, p.grid, p.B, np.asarray(p.kvec) + np.asarray(p.qvec),
                                                               p.miller_kq, self.v)
+        if getattr(p, "e_kb", None) is not None:  # separable non-local pseudopotential at k and k+q
+            self.h_k.set_nonlocal(torch.from_numpy(np.ascontiguousarray(p.beta_k)).to(dev), p.e_kb)
+            if self.h_kq is not self.h_k:
+                self.h_kq.set_nonlocal(torch.from_numpy(np.ascontiguousarray(p.beta_kq)).to(dev), p.e_kb)
         self.psi_v = torch.from_numpy(np.ascontiguousarray(p.psi_k[: p.n_band])).to(dev)
         self.psi_occ_kq = torch.from_numpy(np.ascontiguousarray(p.psi_kq)).to(dev)
         self.eps_v = np.ascontiguousarray(p.eps_k[: p.n_band])
