@@ -41,13 +41,16 @@ WORKLOADS = {
            "eta 0.1 eV, tol 1e-10",
     "si64": "si64: diamond conventional 2x2x2 (64 atoms), 16013 PW, 72^3 grid, 128 bands x 20 perts x 100 omega in "
             "[0,40] eV, eta 0.05 eV, tol 1e-8",
+    "si64nl": "si64nl: si64 with synthetic separable non-local s and p projectors on every atom (256, "
+              "Gaussian radial forms), 16013 PW, 72^3 grid, 128 bands x 20 perts x 100 omega in [0,40] eV, "
+              "eta 0.05 eV, tol 1e-8",
     "batch200": "batch200: 200 independent diamond fcc n0 x n1 x n2 cells (n_d in 1..3, 2-54 atoms), grid 24 n_d "
                 "per axis, Ecut 4 Ha (100-2800 PW), all ~2*atoms occupied bands, 16-128 omega in [0,40] eV, "
                 "4-16 perts at an own seeded q, eta 0.05 eV, tol 1e-8",
 }
 
 KERNELS = ["hx_sticks_inv", "hx_planes", "hx_sticks_fwd", "proj_dot", "proj_apply", "lanczos_step", "slot_init", "rhs_source",
-           "tridiag", "combine", "residual", "permute"]
+           "tridiag", "combine", "residual", "permute", "nl_dot", "nl_apply"]
 
 
 def roofline(kernel, ks, workload, default_launch=True):
@@ -120,7 +123,8 @@ def cpu_baseline_lu(problem, log):
     p = problem
     v, j = p.n_band - 1, 0
     t0 = time.perf_counter()
-    h = so.hamiltonian(p.miller_kq, p.B, p.kvec + p.qvec, p.v_grid)
+    nl = None if p.e_kb is None else (p.beta_kq, p.e_kb)
+    h = so.hamiltonian(p.miller_kq, p.B, p.kvec + p.qvec, p.v_grid, nl=nl)
     t_h = time.perf_counter() - t0
     t0 = time.perf_counter()
     a0 = so.coulomb_operator(h, p.psi_kq, p.eps_k[v], 1.0)
@@ -310,7 +314,7 @@ def main():
     kw = dict(precision=prec)
     if args.slots:
         kw["slots"] = args.slots
-    max_iter = args.max_iter or (3500 if args.workload == "si64" else 0)
+    max_iter = args.max_iter or (3500 if args.workload in ("si64", "si64nl") else 0)
     if max_iter:
         kw["max_iter"] = max_iter
     if args.mixed_switch:
@@ -329,9 +333,15 @@ def main():
         log(f"warmup {w}: status {st}, {time.perf_counter() - t:.3f} s")
     stats = {k: ctx.kernel_stats(k) for k in KERNELS}
     total = sum(s["ms"] for s in stats.values())
+    n_warm = max(args.warmup, 1)
+    split = {}  # per kernel, over the warmup solves (every launch timed): ms per step and achieved rates
     for k, s in sorted(stats.items(), key=lambda kv: -kv[1]["ms"]):
         if s["launches"]:
             log(f"  {k:14s} {s['ms']:9.2f} ms  {100 * s['ms'] / total:5.1f}%  launches {s['launches']}")
+            sec = s["ms"] * 1e-3
+            split[k] = {"ms_per_step": round(s["ms"] / n_warm, 1), "launches_per_step": s["launches"] // n_warm,
+                        "alg_GBps": round(s["bytes"] / sec / 1e9, 1),
+                        "alg_TFLOPs": round(s["flops"] / sec / 1e12, 2) if s["flops"] else None}
     dominant = max(stats, key=lambda k: stats[k]["ms"])
 
     step_s = []
@@ -395,9 +405,10 @@ def main():
                              ("FP64" if prec == sgw.FP64 else "FP64 with FP32 potential matvecs once a pair's "
                               "shift residuals are below 1e4*tol, FP64 per-shift refinement of any shift above tol")},
         "roofline": roof,
+        "kernel_split": split,
     }
     if not args.no_cpu_baseline:
-        if args.workload == "si64":
+        if args.workload in ("si64", "si64nl"):
             out["cpu_baseline"] = cpu_baseline_lu(problem, log)
         else:
             out["cpu_baseline"] = cpu_baseline(problem, args.cpu_sample_pairs, log)

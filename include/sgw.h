@@ -69,13 +69,20 @@ enum {
 enum {
   SGW_FP64 = 0,               /* complex128 throughout */
   SGW_MIXED = 1               /* a (v,p) pair's Krylov steps apply the potential term of H.x in
-                                 complex64 (FP32 transforms and V) once the estimated residuals of
-                                 all its shifts are below mixed_switch * tol (matvec errors made late enter
-                                 the solutions weighted by the shrinking step coefficients); the
-                                 projector, recurrences, basis and residuals stay FP64, and every
-                                 shift whose true FP64 residual is still above tol is then refined
-                                 by FP64 per-shift solves from its multishift iterate */
+                                 complex64 (FP32 transforms and V) and the occupied projector as a
+                                 split-BF16 contraction (SGW_PROJ_SPLIT_BF16) once the estimated
+                                 residuals of all its shifts are below mixed_switch * tol (matvec
+                                 errors made late enter the solutions weighted by the shrinking step
+                                 coefficients); the recurrences, basis and residuals stay FP64, and
+                                 every shift whose true FP64 residual is still above tol is then
+                                 refined by FP64 per-shift solves from its multishift iterate */
 };
+
+/* sgw_apply_projector: with this bit in `mode` the contraction runs on the BF16 matrix cores: every
+   FP64 value is split into three BF16 terms (h = bf16(v), m = bf16(v - h), l = bf16(v - h - m)),
+   each real product keeps the six largest term products, accumulated in FP32 (FP32-level accuracy,
+   the terms dropped are below 2^-24 relative) */
+enum { SGW_PROJ_SPLIT_BF16 = 16 };
 
 /* solver (sgw_opts.solver) */
 enum {
@@ -227,6 +234,7 @@ sgw_status sgw_apply_h_noalloc(sgw_ctx *ctx, const sgw_ham *ham, int n_vec, cons
  *   mode 1:  y = y + alpha * Psi (Psi^H x)   (the + alpha P_occ term of the operator)
  * psi: device [n_occ][n_pw] (rows are orthonormal occupied states), x, y: device
  * [n_vec][n_pw], caller's order.  x and y may not alias.  n_occ above 256: SGW_ERR_UNSUPPORTED.
+ * mode | SGW_PROJ_SPLIT_BF16: the same with the split-BF16 contraction (FP32-level accuracy).
  */
 sgw_status sgw_apply_projector(sgw_ctx *ctx, const sgw_ham *ham, int n_occ, const sgw_c128 *psi,
                                int n_vec, const sgw_c128 *x, sgw_c128 *y, double alpha, int mode);

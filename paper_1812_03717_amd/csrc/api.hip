@@ -585,6 +585,8 @@ extern "C" sgw_status sgw_apply_projector(sgw_ctx *ctx, const sgw_ham *h, int n_
                                           int n_vec, const sgw_c128 *x, sgw_c128 *y, double alpha, int mode) {
   if (!ctx || !h) return fail(SGW_ERR_INVALID_ARG, "sgw_apply_projector: NULL context or Hamiltonian");
   if (n_vec < 0 || n_occ < 0) return fail(SGW_ERR_INVALID_ARG, "sgw_apply_projector: negative size");
+  const bool split = (mode & SGW_PROJ_SPLIT_BF16) != 0;
+  mode &= ~SGW_PROJ_SPLIT_BF16;
   if (mode != 0 && mode != 1) return fail(SGW_ERR_INVALID_ARG, "sgw_apply_projector: mode must be 0 or 1");
   if (n_occ > kMaxOcc)
     return fail(SGW_ERR_UNSUPPORTED, "sgw_apply_projector: n_occ above " + std::to_string(kMaxOcc));
@@ -598,6 +600,17 @@ extern "C" sgw_status sgw_apply_projector(sgw_ctx *ctx, const sgw_ham *h, int n_
   if ((st = alloc_async(cb, sizeof(double2) * kProjChunks * (size_t)n_vec * std::max(n_occ, 1), ctx->stream)) !=
       SGW_OK)
     return st;
+  if (split) {
+    DevBuf sb;
+    if ((st = alloc_async(sb, proj_split_bytes(npw, n_occ), ctx->stream)) != SGW_OK) return st;
+    const VecSrc xs = contiguous((const double2 *)x, npw);
+    if ((st = proj_split(ctx, npw, n_occ, (const double2 *)psi, sb.p)) != SGW_OK) return st;
+    if ((st = proj_dot_bf16(ctx, npw, n_occ, sb.p, n_vec, xs, (double2 *)cb.p, n_vec)) != SGW_OK) return st;
+    if ((st = proj_apply_bf16(ctx, npw, n_occ, sb.p, n_vec, xs, (double2 *)cb.p, (double2 *)y, npw, alpha, mode)) !=
+        SGW_OK)
+      return st;
+    return sync(ctx);
+  }
   if ((st = proj_dot(ctx, npw, n_occ, (const double2 *)psi, n_vec, contiguous((const double2 *)x, npw),
                      (double2 *)cb.p, n_vec)) != SGW_OK)
     return st;
@@ -707,6 +720,7 @@ struct Layout {
   int S = 0, F = 0, kmax = 0, M = 8;
   size_t psi, omega, epsb, dvm, pair, kcur, status, eps, alpha, beta, rho, res, maxres, conv, bvec, basis;
   size_t l_active, l_fill, l_fillpairs, l_final, Y, Y2, C, T, ycoef, cp, order, X, AX, bad, btab = 0;
+  size_t psplit = 0;  // split-BF16 copy of the occupied states (mixed precision), 0: none
   long c_rows = 0;
   // pooled Krylov basis: blocks of 2^bshift vectors, nbmax per slot at most, nblk in the pool;
   // S_full: the slots that full-size bases would give
@@ -790,6 +804,7 @@ Layout make_layout(const sgw_ham *h, int n_occ, int n_band, int n_pert, int n_om
   const long tv = std::max<long>(L.S, nfv);
   size_t off = 0;
   L.psi = take(off, 16ul * std::max(n_occ, 1) * npw);
+  if (o.precision == SGW_MIXED && n_occ > 0) L.psplit = take(off, proj_split_bytes((int)npw, n_occ));
   L.omega = take(off, 8ul * n_omega);
   L.epsb = take(off, 8ul * std::max(n_band, 1));
   L.dvm = take(off, 12ul * std::max(n_pert, 1));
@@ -1076,6 +1091,9 @@ static sgw_status multishift_solve(sgw_ctx *ctx, const sgw_ham *h_kq, int n_occ,
   if ((st = permute(ctx, npw, n_occ, (const double2 *)psi_occ_kq, npw, (double2 *)Sx.psi, npw, h_kq->d_i2u, 0)) !=
       SGW_OK)
     return st;
+  // mixed precision: the slots in their FP32 phase apply the projector as a split-BF16 contraction
+  void *psplit = L.psplit ? (void *)(W + L.psplit) : nullptr;
+  if (psplit && (st = proj_split(ctx, npw, n_occ, Sx.psi, psplit)) != SGW_OK) return st;
 
   // work queue: the highest bands (slowest to converge) first
   std::vector<int> queue(n_pairs);
@@ -1091,6 +1109,7 @@ static sgw_status multishift_solve(sgw_ctx *ctx, const sgw_ham *h_kq, int n_occ,
   double ksum = 0;
   long kcount = 0;
   std::vector<int32_t> kc_host(S);
+  std::vector<int32_t> conv_host;  // convergence steps read back for the timing statistics
 
   // Pooled basis: block table (host copy uploaded before the launches that read it), blocks owned
   // per slot, free blocks; pairs restarted after an eviction wait in requeue.  kcn: a slot's
@@ -1138,11 +1157,29 @@ static sgw_status multishift_solve(sgw_ctx *ctx, const sgw_ham *h_kq, int n_occ,
       double kavg = 0;
       for (int f = 0; f < nf; ++f) kavg += kc_host[list[off + f]];
       kavg /= nf;
+      // mean dimension of the shifts' own solutions, for the combination's flop count (only while
+      // its launches are timed: it reads the convergence steps back)
+      double kshift = kavg;
+      if (ctx->profile_mask & (1u << K_COMBINE)) {
+        conv_host.resize((size_t)S * n_omega);
+        SGW_HIP(hipMemcpyAsync(conv_host.data(), Sx.conv, sizeof(int32_t) * conv_host.size(), hipMemcpyDeviceToHost,
+                               ctx->stream));
+        SGW_HIP(hipStreamSynchronize(ctx->stream));
+        double ks = 0;
+        for (int f = 0; f < nf; ++f) {
+          const int sl = list[off + f], K = kc_host[sl];
+          for (int j = 0; j < n_omega; ++j) {
+            const int c = conv_host[(size_t)sl * n_omega + j];
+            ks += (c >= 1 && c < K) ? c : K;
+          }
+        }
+        kshift = ks / ((double)nf * n_omega);
+      }
       std::memcpy(p_final, list.data() + off, sizeof(int32_t) * nf);
       SGW_HIP(hipMemcpyAsync(d_final, p_final, sizeof(int32_t) * nf, hipMemcpyHostToDevice, ctx->stream));
       sgw_status s2;
       if ((s2 = tridiag(ctx, Sx, d_final, nf, ycoef, cp, sorder)) != SGW_OK) return s2;
-      if ((s2 = combine(ctx, Sx, d_final, nf, ycoef, sorder, X, kavg)) != SGW_OK) return s2;
+      if ((s2 = combine(ctx, Sx, d_final, nf, ycoef, sorder, X, kavg, kshift)) != SGW_OK) return s2;
       const int nv = nf * n_omega;
       if ((s2 = proj_dot(ctx, npw, n_occ, Sx.psi, nv, xsrc, C, crow)) != SGW_OK) return s2;
       if ((s2 = hx_batch(ctx, h_kq, nv, xsrc, AX, npw, T)) != SGW_OK) return s2;
@@ -1257,10 +1294,18 @@ static sgw_status multishift_solve(sgw_ctx *ctx, const sgw_ham *h_kq, int n_occ,
       auto steps = [&]() -> sgw_status {
         sgw_status s2;
         for (int step = 0; step < L.M; ++step) {
-          if ((s2 = proj_dot(ctx, npw, n_occ, Sx.psi, na, cur, C, crow)) != SGW_OK) return s2;
+          // FP64 slots [0, n64), FP32-phase slots [n64, na): the overlaps of the latter go to rows n64..
+          // of C, their projector runs split-BF16
+          double2 *C32 = C + (long)n64 * n_occ;
+          double2 *Y32 = Y + (long)n64 * npw;
+          if ((s2 = proj_dot(ctx, npw, n_occ, Sx.psi, n64, cur, C, crow)) != SGW_OK) return s2;
+          if (na > n64 && (s2 = proj_dot_bf16(ctx, npw, n_occ, psplit, na - n64, cur32, C32, crow)) != SGW_OK) return s2;
           if ((s2 = hx_batch(ctx, h_kq, n64, cur, Y, npw, T)) != SGW_OK) return s2;
-          if ((s2 = hx_batch(ctx, h_kq, na - n64, cur32, Y + (long)n64 * npw, npw, T, true)) != SGW_OK) return s2;
-          if ((s2 = proj_apply(ctx, npw, n_occ, Sx.psi, na, cur, C, crow, Y, npw, o.alpha_pv, 1)) != SGW_OK) return s2;
+          if ((s2 = hx_batch(ctx, h_kq, na - n64, cur32, Y32, npw, T, true)) != SGW_OK) return s2;
+          if ((s2 = proj_apply(ctx, npw, n_occ, Sx.psi, n64, cur, C, crow, Y, npw, o.alpha_pv, 1)) != SGW_OK) return s2;
+          if (na > n64 &&
+              (s2 = proj_apply_bf16(ctx, npw, n_occ, psplit, na - n64, cur32, C32, Y32, npw, o.alpha_pv, 1)) != SGW_OK)
+            return s2;
           if ((s2 = lanczos_step(ctx, Sx, na, d_active, Y)) != SGW_OK) return s2;
         }
         return SGW_OK;

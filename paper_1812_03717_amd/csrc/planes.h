@@ -302,11 +302,13 @@ struct PotentialPost {
   }
 };
 
-// The line kernel holds max(N0, N1) values per thread: up to 48 (FP64: 192 of 256 VGPRs at 48).
-// Planes per workgroup: about 96 (FP64) or 192 (FP32) column threads, which measured best at
-// 48 x 48 (LDS and registers then allow 8 resp. 12 waves per CU).
+// The line kernel holds max(N0, N1) values per thread: up to 48 in FP64 (192 of 256 VGPRs at 48)
+// and up to 72 in FP32 (144 VGPRs at 72).  Planes per workgroup: about 96 (FP64) or 192 (FP32)
+// column threads, which measured best at 48 x 48 (LDS and registers then allow 8 resp. 12 waves per
+// CU).
 template <class C2, int N0, int N1> constexpr bool line_planes_fit() {
-  return N0 % 4 == 0 && N1 % 4 == 0 && N0 <= 48 && N1 <= 48 && LineSplit<N0>::a % 4 == 0 &&
+  constexpr int nmax = sizeof(C2) == 16 ? 48 : 72;
+  return N0 % 4 == 0 && N1 % 4 == 0 && N0 <= nmax && N1 <= nmax && LineSplit<N0>::a % 4 == 0 &&
          LineSplit<N1>::a % 4 == 0;
 }
 template <class C2, int N1> constexpr int line_plane_count() {
@@ -315,7 +317,7 @@ template <class C2, int N1> constexpr int line_plane_count() {
 template <int P, int N1> constexpr int line_plane_threads() { return (P * N1 + 63) / 64 * 64; }
 template <class C2, int N0, int N1> constexpr int line_waves_per_eu() {
   constexpr int n = N0 > N1 ? N0 : N1;
-  return sizeof(C2) == 16 ? (n <= 16 ? 4 : n <= 24 ? 3 : 2) : (n <= 24 ? 4 : 3);
+  return sizeof(C2) == 16 ? (n <= 16 ? 4 : n <= 24 ? 3 : 2) : (n <= 24 ? 4 : n <= 48 ? 3 : 2);
 }
 // true when every stick lies in the window the line kernel requires
 inline bool line_window_ok(const int n[3], int m0_lo, int n_row, int m1_lo, int m1_hi) {

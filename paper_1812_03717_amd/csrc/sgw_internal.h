@@ -207,6 +207,16 @@ inline size_t hx_tbuf_bytes(const sgw_ham *h, long n_vec) {
   const size_t nl = h->n_proj > 0 ? 16ul * (size_t)n_vec * proj_chunks(h->n_pw, &kc) * h->n_proj : 0;
   return std::max(sticks, nl);
 }
+// Split-BF16 projector (FP32-level accuracy on the BF16 matrix cores, FP32 accumulation): `split`
+// holds proj_split_bytes(n_pw, n_occ) bytes (256-byte aligned), written by proj_split from psi
+// (internal order); proj_dot_bf16 / proj_apply_bf16 then take the place of proj_dot / proj_apply
+// (same cp layout and modes).
+size_t proj_split_bytes(int n_pw, int n_occ);
+sgw_status proj_split(sgw_ctx *ctx, int n_pw, int n_occ, const double2 *psi, void *split);
+sgw_status proj_dot_bf16(sgw_ctx *ctx, int n_pw, int n_occ, const void *split, int n_vec, VecSrc x, double2 *cp,
+                         long rows);
+sgw_status proj_apply_bf16(sgw_ctx *ctx, int n_pw, int n_occ, const void *split, int n_vec, VecSrc x,
+                           const double2 *cp, double2 *y, long ldy, double alpha, int mode);
 // y_a = x_a
 sgw_status permute_copy(sgw_ctx *ctx, int n_pw, int n_vec, VecSrc x, double2 *y, long ldy);
 // out[a][g] = in[a][perm[g]] (gather) or out[a][perm[g]] = in[a][g] (scatter)

@@ -667,7 +667,7 @@ sgw_status tridiag(sgw_ctx *ctx, const SolverState &S, const int32_t *flist, int
 }
 
 sgw_status combine(sgw_ctx *ctx, const SolverState &S, const int32_t *flist, int nf, const double2 *ycoef,
-                   const int32_t *order, double2 *X, double est_kavg) {
+                   const int32_t *order, double2 *X, double est_kavg, double est_kshift) {
   if (nf <= 0) return SGW_OK;
   const int gtiles = (S.npw + kCmbThreads - 1) / kCmbThreads;
   const int nw = S.n_omega;
@@ -676,7 +676,7 @@ sgw_status combine(sgw_ctx *ctx, const SolverState &S, const int32_t *flist, int
   const int jchunks = (nw + cj - 1) / cj;
   PendingTiming tm;
   const double bytes = nf * (est_kavg * S.npw * 16.0 + (double)S.n_omega * S.npw * 16.0);
-  timing_begin(ctx, K_COMBINE, bytes, 8.0 * nf * est_kavg * S.npw * S.n_omega, &tm);
+  timing_begin(ctx, K_COMBINE, bytes, 8.0 * nf * est_kshift * S.npw * S.n_omega, &tm);
   const int ntiles = nf * gtiles;
   const long groups = (long)(ntiles + kXcds - 1) / kXcds * kXcds * jchunks;
   if (j20)

@@ -71,8 +71,9 @@ sgw_status lanczos_step(sgw_ctx *ctx, const SolverState &S, int n_active, const 
 // (dimension, index)
 sgw_status tridiag(sgw_ctx *ctx, const SolverState &S, const int32_t *flist, int nf, double2 *ycoef, double2 *cp,
                    int32_t *order);
+// (est_kavg: mean Krylov dimension of the pairs, est_kshift: of their shifts; timing statistics only)
 sgw_status combine(sgw_ctx *ctx, const SolverState &S, const int32_t *flist, int nf, const double2 *ycoef,
-                   const int32_t *order, double2 *X, double est_kavg);
+                   const int32_t *order, double2 *X, double est_kavg, double est_kshift);
 // AX must hold (H + alpha P_occ) X; cp[0] the overlaps of X (as proj_dot leaves them); u2i maps
 // caller to internal plane-wave indices (dpsi is written in the caller's order)
 sgw_status residual(sgw_ctx *ctx, const SolverState &S, const int32_t *flist, int nf, const double2 *X,

@@ -25,6 +25,7 @@ FP64, MIXED = 0, 1
 PC_NONE, PC_TETER, PC_LEARNED = 0, 1, 2
 GUESS_ZERO, GUESS_LEARNED = 0, 1
 FFT_AUTO, FFT_LINE, FFT_PAIR, FFT_LDS = 0, 1, 2, 3
+PROJ_SPLIT_BF16 = 16  # sgw_apply_projector mode bit: split-BF16 contraction
 
 INFO_DTYPE = np.dtype([("iters", "<i4"), ("flags", "<i4"), ("relres", "<f8"), ("occ_leak", "<f8")])
 

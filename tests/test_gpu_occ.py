@@ -71,6 +71,32 @@ def test_apply_projector_occupied_counts(ctx, basis, n_occ):
     assert np.abs(psi.conj() @ y0.T).max() <= 1e-12 * np.abs(y0).max() * np.sqrt(n)
 
 
+@pytest.mark.parametrize("n_occ", [17, 64, 65, 128, 256])
+def test_apply_projector_split_bf16(ctx, basis, n_occ):
+    """The split-BF16 contraction (the FP32 phase of mixed-precision solves): three BF16 terms per
+    value and the six largest term products leave under 2^-24 relative per product, and FP32
+    accumulation over 256-plane-wave chunks (overlaps) and n_occ states (apply) adds rounding of the
+    same order; bar 2e-6 of the largest projected entry (about 30 FP32 unit roundoffs), and above
+    1e-12 (it is not the FP64 path)."""
+    from paper_1812_03717_amd import sgw
+    ham, n, _ = basis
+    rng = np.random.default_rng(1000 + n_occ)
+    psi = np.linalg.qr(rng.standard_normal((n, n_occ)) + 1j * rng.standard_normal((n, n_occ)))[0].T.copy()
+    n_vec = 37
+    x = rng.standard_normal((n_vec, n)) + 1j * rng.standard_normal((n_vec, n))
+    d_psi = torch.from_numpy(psi).to(ctx.device)
+    xt = torch.from_numpy(x).to(ctx.device)
+    px = np.array([so.apply_occupied_projector(psi, xi) for xi in x])
+    y0 = sgw.sgw_apply_projector(ctx, ham, d_psi, xt, mode=0 | sgw.PROJ_SPLIT_BF16).cpu().numpy()
+    e0 = np.abs(y0 - (x - px)).max() / np.abs(px).max()
+    base = rng.standard_normal((n_vec, n)) + 1j * rng.standard_normal((n_vec, n))
+    y1 = sgw.sgw_apply_projector(ctx, ham, d_psi, xt, alpha=1.7, mode=1 | sgw.PROJ_SPLIT_BF16,
+                                 y=torch.from_numpy(base.copy()).to(ctx.device)).cpu().numpy()
+    e1 = np.abs(y1 - (base + 1.7 * px)).max() / np.abs(1.7 * px).max()
+    print(f"n_occ {n_occ} split BF16: mode 0 rel err {e0:.2e}, mode 1 rel err {e1:.2e}", flush=True)
+    assert 1e-12 < e0 <= 2e-6 and 1e-12 < e1 <= 2e-6
+
+
 def test_projector_rejects_too_many_states(ctx, basis):
     from paper_1812_03717_amd import sgw
     ham, n, _ = basis
