@@ -20,7 +20,11 @@ What it computes (Hartree units; every function cites the passage it follows):
   that the Sternheimer approach avoids (Sec. 1 and Sec. 2.2);
 * the relative residual and the condition number used for the error budget;
 * the Green's function columns (Sec. 2.2, Eqs. 2-3): (H_k - z) G_{.G'}(z) = -e_{G'},
-  by the sum over all eigenstates that the linear equation replaces.
+  by the sum over all eigenstates that the linear equation replaces;
+* the density response to the plane-wave perturbations (Sec. 2.3, Eq. 5), by the
+  sum over empty states and from given linear variations, the dielectric matrix
+  (Eq. 4), the correlation part of the screened interaction (Sec. 2.4, Eq. 9) and
+  the (optionally truncated) Coulomb potential (Sec. 2.6, Eq. 12).
 
 The Krylov method itself is not reproduced: the iterative solver reaches
 (up to rounding) the exact solution of each shifted system, and that solution
@@ -38,6 +42,12 @@ Readings of the paper taken here:
 * The local potential is defined by its grid samples; its matrix element
   between plane waves m and m' is the discrete Fourier coefficient at the
   cyclic difference (m - m') mod N (grid-defined operator, aliasing included).
+* The density response chi_{GG'} is the response to the unit perturbation
+  exp(i (q+G') . r); the Coulomb factor that Eq. 4 leaves implicit is the
+  potential v(q+G') of the perturbing charge, so eps_{GG'} = delta_{GG'} -
+  chi_{GG'} v(q+G'), and Eq. 9 puts v(q+G) on the rows of W_bar (together they
+  give W_bar = W - v with W = v (1 - chi v)^{-1}).  The +/- in Eq. 5 are the
+  variations at the complex frequencies z and -z.
 * The non-local part of the pseudopotential is taken in the fully separable
   form sum_p |beta_p> E_p <beta_p| with real E_p (any Hermitian coupling matrix
   between the projectors of an atom reduces to it by diagonalisation); the
@@ -219,3 +229,93 @@ def green_condition_number(evals: np.ndarray, z: complex) -> float:
     """kappa of H - z over the whole spectrum (no occupied projection in Eq. 3)."""
     lam = np.abs(evals - z)
     return float(lam.max() / lam.min())
+
+
+# ---------------------------------------------------------------------------
+# density response, dielectric matrix and screened interaction (Sec. 2.3, Eqs. 4-5; Sec. 2.4,
+# Eq. 9; Sec. 2.6, Eq. 12)
+# ---------------------------------------------------------------------------
+
+def cell_volume(B: np.ndarray) -> float:
+    """Unit-cell volume Omega = (2 pi)^3 / |det B| from the reciprocal lattice rows."""
+    return float((2.0 * np.pi) ** 3 / abs(np.linalg.det(np.asarray(B, float))))
+
+
+def coulomb(qg: np.ndarray, r_cut: float = 0.0) -> np.ndarray:
+    """Coulomb potential of each wave vector q + G (Cartesian rows, Hartree units): 4 pi / |q+G|^2, or
+    with the spherical truncation at r_cut > 0 (Sec. 2.6, Eq. 12) 4 pi / |q+G|^2 (1 - cos(|q+G| r_cut)),
+    whose value at q + G = 0 is its limit 2 pi r_cut^2."""
+    k = np.sqrt(np.einsum("gd,gd->g", np.asarray(qg, float), np.asarray(qg, float)))
+    if r_cut <= 0.0:
+        return 4.0 * np.pi / k ** 2
+    out = np.empty_like(k)
+    z = k == 0.0
+    out[~z] = 4.0 * np.pi / k[~z] ** 2 * (1.0 - np.cos(k[~z] * r_cut))
+    out[z] = 2.0 * np.pi * r_cut ** 2
+    return out
+
+
+def pair_matrix_elements(evecs_c: np.ndarray, psi_v: np.ndarray, miller_k, miller_kq, m_ps) -> np.ndarray:
+    """M[p][c] = <u_c | exp(i (q + G_p) . r) u_v> for the k+q states in the columns of evecs_c."""
+    return np.array([evecs_c.conj().T @ shifted_source(psi_v, miller_k, miller_kq, m_p) for m_p in m_ps])
+
+
+def density_response_spectral(evals: np.ndarray, evecs: np.ndarray, n_occ: int, psi_k: np.ndarray,
+                              eps_k: np.ndarray, miller_k, miller_kq, m_ps, zs, volume: float) -> np.ndarray:
+    """Density response chi[z][G][G'] to the unit perturbations exp(i (q + G') . r), at the wave vectors
+    q + G of the same set, by the sum over all empty states c at k+q that the Sternheimer route
+    replaces (Sec. 2.3, Eq. 5 with each linear variation written as that sum):
+
+        chi_{GG'}(z) = (2 / Omega) sum_v sum_c conj(M_cv(G)) M_cv(G') [1/(z - d_cv) - 1/(z + d_cv)],
+
+    d_cv = eps_c - eps_v, M_cv(G) = <u_c | exp(i (q+G) . r) u_v>; the factor 2 is the spin degeneracy
+    and the two terms are the variations at +z and -z.  psi_k rows: the occupied states at k (bands
+    v = 0 .. len(psi_k) - 1 with energies eps_k).  Returns [len(zs)][n_G][n_G]."""
+    zs = np.atleast_1d(np.asarray(zs, complex))
+    uc = evecs[:, n_occ:]
+    chi = np.zeros((len(zs), len(m_ps), len(m_ps)), complex)
+    for v in range(psi_k.shape[0]):
+        m = pair_matrix_elements(uc, psi_k[v], miller_k, miller_kq, m_ps)      # [G][c]
+        d = evals[n_occ:] - eps_k[v]
+        for j, z in enumerate(zs):
+            w = 1.0 / (z - d) - 1.0 / (z + d)
+            chi[j] += (m.conj() * w[None, :]) @ m.T
+    return 2.0 / volume * chi
+
+
+def density_response_from_solutions(psi_k: np.ndarray, miller_k, miller_kq, m_ps, psi_occ_kq: np.ndarray,
+                                    dpsi_plus: np.ndarray, dpsi_minus: np.ndarray, volume: float) -> np.ndarray:
+    """The same response from the linear variations themselves (Sec. 2.3, Eq. 5): the Fourier component
+    q + G of 2 sum_v u_v^* (du_v(z) + du_v(-z)) per unit cell, which on the plane-wave bases is
+
+        chi_{GG'}(z) = (2 / Omega) sum_v < (1 - P_occ) exp(i (q+G) . r) u_v | du_{v,G'}(z) + du_{v,G'}(-z) >
+
+    (the variations have no occupied component).  dpsi_plus / dpsi_minus: [n_band][n_G'][n_z][n_pw_kq],
+    the solutions at z and at -z.  Returns [n_z][n_G][n_G']."""
+    nb, npert, nz, _ = dpsi_plus.shape
+    chi = np.zeros((nz, npert, npert), complex)
+    for v in range(nb):
+        s = np.array([-rhs(psi_k[v], miller_k, miller_kq, m_p, psi_occ_kq) for m_p in m_ps])   # [G][pw]
+        x = dpsi_plus[v] + dpsi_minus[v]                                                      # [G'][z][pw]
+        chi += np.einsum("gp,hzp->zgh", s.conj(), x)
+    return 2.0 / volume * chi
+
+
+def dielectric(chi: np.ndarray, v: np.ndarray) -> np.ndarray:
+    """eps_{GG'} = delta_{GG'} - chi_{GG'} v(q + G') (Sec. 2.3, Eq. 4, with the Coulomb factor of the
+    perturbing potential restored on the columns)."""
+    n = chi.shape[-1]
+    return np.eye(n) - chi * np.asarray(v, float)[None, :]
+
+
+def screened_correlation(eps: np.ndarray, v: np.ndarray, zero_rows=()) -> np.ndarray:
+    """W_bar_{GG'} = v(q + G) (eps^{-1}_{GG'} - delta_{GG'}) (Sec. 2.4, Eq. 9); for the rows and columns
+    listed in zero_rows (q + G = 0) the off-diagonal elements are set to zero."""
+    n = eps.shape[-1]
+    w = np.asarray(v, float)[:, None] * (np.linalg.inv(eps) - np.eye(n))
+    for g in zero_rows:
+        keep = w[..., g, g].copy()
+        w[..., g, :] = 0.0
+        w[..., :, g] = 0.0
+        w[..., g, g] = keep
+    return w

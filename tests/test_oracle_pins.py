@@ -405,11 +405,125 @@ def check_nonlocal_secular():
     assert lam.max() > t.max() and np.all(np.sort(lam) >= np.sort(t) - 1e-12)
 
 
+M_PS = np.array([[1, 0, 0], [0, -1, 1], [1, 1, 0], [0, 0, -1]])
+
+
+def check_density_response_free_electron():
+    """V = V0: the states are single plane waves, M_cv(G) = 1 exactly when G_c = G_v + G, so chi is
+    diagonal with chi_GG(z) = (2/Omega) sum_v [G_v + G empty at k+q] (1/(z - d) - 1/(z + d)),
+    d = 0.5|k+q+G_v+G|^2 - 0.5|k+G_v|^2 (V0 cancels), written out here from the kinetic closed form;
+    then eps and W_bar are diagonal too: W_bar_GG = v_G (1 / (1 - chi_GG v_G) - 1)."""
+    A, tau = cx.fcc_primitive(A_LAT)
+    B = cx.reciprocal(A)
+    k = np.array([0.013, -0.021, 0.008])
+    q = np.array([0.071, 0.032, -0.045])
+    mk, mkq = cx.g_sphere(B, k, 2.5), cx.g_sphere(B, k + q, 2.5)
+    grid, v0, n_occ = (12, 12, 12), -0.4, 5
+    tk = 0.5 * ((mk @ B + k) ** 2).sum(1)
+    tq = 0.5 * ((mkq @ B + k + q) ** 2).sum(1)
+    occ_k = np.argsort(tk)[:n_occ]
+    occ_q = set(int(i) for i in np.argsort(tq)[:n_occ])
+    psi_k = np.zeros((n_occ, len(mk)), complex)
+    psi_k[np.arange(n_occ), occ_k] = 1.0
+    w, u = so.eigh(so.hamiltonian(mkq, B, k + q, np.full(grid, v0)))
+    omega = so.cell_volume(B)
+    assert abs(omega - abs(np.linalg.det(A))) <= 1e-12 * omega
+    zs = np.array([0.3 + 0.01j, -0.7 + 0.02j, 0.05j])
+    chi = so.density_response_spectral(w, u, n_occ, psi_k, tk[occ_k] + v0, mk, mkq, M_PS, zs, omega)
+    index_q = {tuple(m): i for i, m in enumerate(mkq)}
+    ref = np.zeros((len(zs), len(M_PS)), complex)
+    for gi, mp in enumerate(M_PS):
+        for vi in occ_k:
+            c = index_q.get(tuple(mk[vi] + mp))
+            if c is None or c in occ_q:
+                continue
+            d = tq[c] - tk[vi]
+            ref[:, gi] += 1.0 / (zs - d) - 1.0 / (zs + d)
+    ref *= 2.0 / omega
+    assert np.abs(ref).min() > 0
+    for j in range(len(zs)):
+        assert np.allclose(chi[j], np.diag(ref[j]), rtol=0, atol=1e-12 * np.abs(ref).max())
+    qg = (M_PS + 0.0) @ B + q
+    vq = 4.0 * np.pi / (qg ** 2).sum(1)
+    wb = so.screened_correlation(so.dielectric(chi, so.coulomb(qg)), so.coulomb(qg))
+    for j in range(len(zs)):
+        expect = vq * (1.0 / (1.0 - ref[j] * vq) - 1.0)
+        assert np.allclose(wb[j], np.diag(expect), rtol=1e-12, atol=1e-13 * np.abs(expect).max())
+
+
+def check_density_response_routes():
+    """chi by the sum over empty states against chi from LU solutions at z and -z (independent
+    routes), its symmetries chi(-z) = chi(z) and chi(z)^H = chi(conj z), its sign at z = 0 (Hermitian,
+    negative semidefinite), and W_bar = v (eps^-1 - 1) against W - v with W = (1 - v chi)^{-1} v, the
+    other factor order."""
+    P = _small_problem()
+    n_occ, psi_kq = P["n_occ"], P["psi_kq"]
+    omega = so.cell_volume(P["B"])
+    zs = np.array([0.3 + 0.004j, -1.1 + 0.01j])
+    chi = so.density_response_spectral(P["wq"], P["uq"], n_occ, P["psi_k"], P["wk"], P["mk"], P["mkq"], M_PS,
+                                       zs, omega)
+    dp = np.zeros((n_occ, len(M_PS), len(zs), len(P["mkq"])), complex)
+    dm = np.zeros_like(dp)
+    for v in range(n_occ):
+        a0 = so.coulomb_operator(P["h_kq"], psi_kq, P["wk"][v], 1.0)
+        for gi, mp in enumerate(M_PS):
+            b = so.rhs(P["psi_k"][v], P["mk"], P["mkq"], mp, psi_kq)
+            for j, z in enumerate(zs):
+                dp[v, gi, j] = so.solve_lu(a0, b, z)
+                dm[v, gi, j] = so.solve_lu(a0, b, -z)
+    chi2 = so.density_response_from_solutions(P["psi_k"], P["mk"], P["mkq"], M_PS, psi_kq, dp, dm, omega)
+    assert np.abs(chi2 - chi).max() <= 1e-10 * np.abs(chi).max()
+    chi_m = so.density_response_spectral(P["wq"], P["uq"], n_occ, P["psi_k"], P["wk"], P["mk"], P["mkq"], M_PS,
+                                         -zs, omega)
+    assert np.abs(chi_m - chi).max() <= 1e-12 * np.abs(chi).max()
+    chi_c = so.density_response_spectral(P["wq"], P["uq"], n_occ, P["psi_k"], P["wk"], P["mk"], P["mkq"], M_PS,
+                                         np.conj(zs), omega)
+    assert np.abs(np.conj(np.swapaxes(chi, 1, 2)) - chi_c).max() <= 1e-12 * np.abs(chi).max()
+    # static response at q = 0 (every empty level above every occupied one): Hermitian, <= 0
+    P0 = _small_problem(q=(0.0, 0.0, 0.0))
+    assert P0["wq"][n_occ] - P0["wk"][n_occ - 1] > 1e-3
+    chi0 = so.density_response_spectral(P0["wq"], P0["uq"], n_occ, P0["psi_k"], P0["wk"], P0["mk"], P0["mkq"],
+                                        M_PS, [0.0], omega)[0]
+    assert np.abs(chi0 - chi0.conj().T).max() <= 1e-13 * np.abs(chi0).max()
+    ev = np.linalg.eigvalsh(chi0)
+    assert ev.max() <= 1e-13 * np.abs(ev).max() and ev.min() < 0
+    qg = (M_PS + 0.0) @ P["B"] + np.array([0.04, -0.03, 0.09])
+    v = so.coulomb(qg)
+    wb = so.screened_correlation(so.dielectric(chi, v), v)
+    n = len(M_PS)
+    for j in range(len(zs)):
+        w_full = np.linalg.solve(np.eye(n) - v[:, None] * chi[j], np.diag(v))
+        assert np.abs(wb[j] - (w_full - np.diag(v))).max() <= 1e-12 * np.abs(w_full).max()
+    # the rule for q + G = 0 (Sec. 2.4): that row's and column's off-diagonal elements are zero
+    wz = so.screened_correlation(so.dielectric(chi, v), v, zero_rows=[1])
+    off = ~np.eye(n, dtype=bool)
+    assert np.all(wz[:, 1, off[1]] == 0) and np.all(wz[:, off[:, 1], 1] == 0)
+    keep = np.ones((n, n), bool)
+    keep[1, :] = keep[:, 1] = False
+    keep[1, 1] = True
+    assert np.array_equal(wz[:, keep], wb[:, keep])
+
+
+def check_coulomb_truncation():
+    """Bare: 4 pi / |q|^2 at |q|^2 = 0.25; spherical truncation: its series 2 pi R^2 (1 - (qR)^2 / 12)
+    at small q and 2 pi R^2 at q = 0, the bare value times (1 - cos qR) elsewhere with cos qR = -1 at
+    qR = pi (twice the bare value)."""
+    v = so.coulomb(np.array([[0.3, 0.0, 0.4]]))
+    assert abs(v[0] - 16.0 * np.pi) <= 1e-13 * v[0]
+    r = 7.5
+    q = np.array([[1e-3, 0.0, 0.0], [0.0, 0.0, 0.0], [0.0, np.pi / r, 0.0]])
+    vt = so.coulomb(q, r_cut=r)
+    assert abs(vt[0] - 2 * np.pi * r * r * (1 - (1e-3 * r) ** 2 / 12)) <= 1e-9 * vt[0]
+    assert vt[1] == 2 * np.pi * r * r
+    assert abs(vt[2] - 2.0 * 4.0 * np.pi / (np.pi / r) ** 2) <= 1e-12 * vt[2]
+
+
 PINS = [check_kinetic_closed_form, check_hamiltonian_bruteforce, check_shifted_source_realspace,
         check_free_electron_closed_form, check_mpmath_tiny, check_routes_and_invariants,
         check_linearity_and_reciprocity, check_relative_residual_closed_form, check_condition_number_svd,
         check_green_free_electron, check_green_routes_and_symmetry, check_nonlocal_translation,
-        check_nonlocal_secular]
+        check_nonlocal_secular, check_density_response_free_electron, check_density_response_routes,
+        check_coulomb_truncation]
 
 
 @pytest.mark.parametrize("pin", PINS + [check_generator_ground_state], ids=lambda f: f.__name__)
@@ -454,6 +568,35 @@ def _mut_rows_index_swap(miller, B, kvec, v_grid, rows, nl=None):
 
 
 _orig_nl = so.nonlocal_matrix
+_orig_chi = so.density_response_spectral
+_orig_chi_sol = so.density_response_from_solutions
+_orig_eps = so.dielectric
+_orig_wbar = so.screened_correlation
+_orig_coul = so.coulomb
+
+
+def _chi_one_term(w, u, n, pk, ek, mk, mkq, mps, zs, vol):
+    # only the variation at +z
+    zs = np.atleast_1d(np.asarray(zs, complex))
+    out = np.zeros((len(zs), len(mps), len(mps)), complex)
+    for v in range(pk.shape[0]):
+        m = so.pair_matrix_elements(u[:, n:], pk[v], mk, mkq, mps)
+        d = w[n:] - ek[v]
+        for j, z in enumerate(zs):
+            out[j] += (m.conj() * (1.0 / (z - d))[None, :]) @ m.T
+    return 2.0 / vol * out
+
+
+def _chi_conj_pairs(w, u, n, pk, ek, mk, mkq, mps, zs, vol):
+    # conj on the perturbation's element instead of the density component's
+    zs = np.atleast_1d(np.asarray(zs, complex))
+    out = np.zeros((len(zs), len(mps), len(mps)), complex)
+    for v in range(pk.shape[0]):
+        m = so.pair_matrix_elements(u[:, n:], pk[v], mk, mkq, mps)
+        d = w[n:] - ek[v]
+        for j, z in enumerate(zs):
+            out[j] += (m * (1.0 / (z - d) - 1.0 / (z + d))[None, :]) @ m.conj().T
+    return 2.0 / vol * out
 
 MUTATIONS = {
     "rhs_sign": ("rhs", lambda *a: -_orig_rhs(*a)),
@@ -480,6 +623,24 @@ MUTATIONS = {
                       lambda w, u, c, z: np.einsum("gn,cn,zn->czg", u, u[np.asarray(c), :],
                                                    1.0 / (np.atleast_1d(np.asarray(z, complex))[:, None] - w[None, :]))),
     "green_lu_rhs_sign": ("green_column_lu", lambda h, c, z: -_orig_green_lu(h, c, z)),
+    "chi_sign": ("density_response_spectral", lambda *a: -_orig_chi(*a)),
+    "chi_no_spin": ("density_response_spectral", lambda *a: 0.5 * _orig_chi(*a)),
+    "chi_one_frequency": ("density_response_spectral", _chi_one_term),
+    "chi_conj_pairs": ("density_response_spectral", _chi_conj_pairs),
+    "chi_no_volume": ("density_response_spectral", lambda *a: _orig_chi(*a) * a[-1]),
+    "chi_solutions_plus_only": ("density_response_from_solutions",
+                                lambda pk, mk, mkq, mps, po, dp, dm, vol:
+                                _orig_chi_sol(pk, mk, mkq, mps, po, dp, 0 * dm, vol)),
+    "chi_solutions_sign": ("density_response_from_solutions", lambda *a: -_orig_chi_sol(*a)),
+    "eps_rows": ("dielectric", lambda chi, v: np.eye(chi.shape[-1]) - chi * np.asarray(v)[:, None]),
+    "eps_no_coulomb": ("dielectric", lambda chi, v: np.eye(chi.shape[-1]) - chi),
+    "wbar_columns": ("screened_correlation",
+                     lambda eps, v, zero_rows=(): np.asarray(v)[None, :] *
+                     (np.linalg.inv(eps) - np.eye(eps.shape[-1]))),
+    "coulomb_no_4pi": ("coulomb", lambda qg, r_cut=0.0: _orig_coul(qg, r_cut) / (4 * np.pi)),
+    "coulomb_trunc_limit": ("coulomb", lambda qg, r_cut=0.0: np.where(
+        np.einsum("gd,gd->g", np.asarray(qg, float), np.asarray(qg, float)) == 0, np.pi * r_cut ** 2,
+        _orig_coul(qg, r_cut))),
     "nl_conjugated": ("nonlocal_matrix", lambda b, e, rows=None: np.conj(_orig_nl(b, e, rows))),
     "nl_energy_dropped": ("nonlocal_matrix", lambda b, e, rows=None: _orig_nl(b, np.ones_like(e), rows)),
     "nl_energy_sign": ("nonlocal_matrix", lambda b, e, rows=None: _orig_nl(b, -np.asarray(e), rows)),
