@@ -170,6 +170,98 @@ def cpu_baseline(problem, n_pairs_sample, log):
                       f"all {n_total_pairs * p.n_omega} solves / (setup + per-pair time x {n_total_pairs})"}
 
 
+def bench_dielectric(args, log, problem, ctx, dev):
+    """The screening path on one GPU: for each chunk of bands, the solves at z_j = omega_j + i eta and at
+    -z_j, then the density response of the chunk added into chi (the chunks bound the memory of the two
+    solution arrays); finally eps, eps^-1 and W_bar per frequency.  One step is the whole path;
+    `value` counts the solves of both signs per second of it."""
+    import torch
+    from paper_1812_03717_amd import sgw
+    p = problem
+    nbc = min(args.dielectric, p.n_band)
+    max_iter = args.max_iter or (3500 if args.workload in ("si64", "si64nl") else 0)
+    kw = {"max_iter": max_iter} if max_iter else {}
+    opts = sgw.sgw_opts_default(**kw)
+    ws = sgw.Workspace(ctx)
+    shape = (nbc, p.n_pert, p.n_omega, p.n_pw_kq)
+    dp = torch.empty(shape, dtype=torch.complex128, device=ctx.device)
+    dm = torch.empty(shape, dtype=torch.complex128, device=ctx.device)
+    info = torch.empty(nbc * p.n_pert * p.n_omega * sgw.INFO_DTYPE.itemsize, dtype=torch.uint8, device=ctx.device)
+    chi = torch.empty((p.n_omega, p.n_pert, p.n_pert), dtype=torch.complex128, device=ctx.device)
+    consumer_s, solve_s, n_ok = [], [], 0
+
+    def step():
+        nonlocal n_ok
+        t_solve = t_cons = 0.0
+        for c0 in range(0, p.n_band, nbc):
+            bands = list(range(c0, min(c0 + nbc, p.n_band)))
+            nb = len(bands)
+            psi = dev.psi_v[c0:c0 + nb].contiguous()
+            eps_v = dev.eps_v[c0:c0 + nb]
+            for sgn, out in ((1.0, dp), (-1.0, dm)):
+                t = time.perf_counter()
+                st, _, inf = sgw.sternheimer_solve(ctx, dev.h_kq, dev.psi_occ_kq, dev.h_k, psi, eps_v, p.dv_miller,
+                                                   sgn * p.omega, sgn * p.eta, p.tol, opts=opts, workspace=ws,
+                                                   dpsi=out[:nb], info=info[: nb * p.n_pert * p.n_omega *
+                                                                              sgw.INFO_DTYPE.itemsize])
+                inf = sgw.info_to_numpy(inf)
+                n_ok += int(np.count_nonzero((inf["flags"] & sgw.FLAG_CONVERGED) != 0))
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t
+                t_solve += dt
+                log(f"  bands {c0}..{c0 + nb - 1} at {'+' if sgn > 0 else '-'}z: {dt:.3f} s, status {st}, "
+                    f"iters max {inf['iters'].max()}")
+            t = time.perf_counter()
+            sgw.sgw_density_response(ctx, dev.h_kq, dev.psi_occ_kq, dev.h_k, psi, p.dv_miller, dp[:nb], dm[:nb],
+                                     chi=chi, accumulate=c0 > 0)
+            torch.cuda.synchronize()
+            t_cons += time.perf_counter() - t
+        t = time.perf_counter()
+        out = sgw.sgw_screened_coulomb(ctx, dev.h_kq, dev.h_k, p.dv_miller, chi)
+        torch.cuda.synchronize()
+        t_cons += time.perf_counter() - t
+        solve_s.append(t_solve)
+        consumer_s.append(t_cons)
+        return out
+
+    ctx.set_profiling("chi_dot,dielectric")
+    for w in range(args.warmup):
+        step()
+        log(f"warmup {w}: solves {solve_s[-1]:.3f} s, density response + W_bar {consumer_s[-1]:.3f} s")
+    ctx.reset_stats()
+    solve_s.clear()
+    consumer_s.clear()
+    n_ok = 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        eps, inv, wbar = step()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    n_total = 2 * p.n_solves * args.steps
+    log(f"timed: {args.steps} steps in {el:.3f} s; converged {n_ok}/{n_total}; solves {sum(solve_s):.3f} s, "
+        f"density response + W_bar {sum(consumer_s):.3f} s")
+    split = {}
+    for k in ("chi_dot", "dielectric"):
+        s = ctx.kernel_stats(k)
+        if s["launches"]:
+            sec = s["ms"] * 1e-3
+            split[k] = {"ms_per_step": round(s["ms"] / args.steps, 2), "launches_per_step": s["launches"] // args.steps,
+                        "alg_GBps": round(s["bytes"] / sec / 1e9, 1),
+                        "alg_TFLOPs": round(s["flops"] / sec / 1e12, 2)}
+    w = wbar.cpu().numpy()
+    print(json.dumps({
+        "metric": "Sternheimer solves/s (band x omega x pert, at z and -z) through chi, eps^-1 and W_bar",
+        "value": round(n_ok / el, 1), "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(1e3 * el / args.steps, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": WORKLOADS[args.workload] + "; solves at z and -z, density response, eps^-1, W_bar",
+                   "band_chunk": nbc, "solves_per_step": 2 * p.n_solves, "max_iter": max_iter or 600},
+        "consumer_ms_per_step": round(1e3 * sum(consumer_s) / args.steps, 2),
+        "solve_ms_per_step": round(1e3 * sum(solve_s) / args.steps, 2),
+        "kernel_split": split, "wbar_head_w0": [float(w[0, 0, 0].real), float(w[0, 0, 0].imag)]}))
+
+
 def bench_batch(args, log):
     """Batches of uneven systems: sternheimer_solve_batch over all of them (one step) after autotuning
     each system class; the same systems solved one after another with default options give the
@@ -271,6 +363,9 @@ def main():
     ap.add_argument("--batch-workers", type=int, default=4)
     ap.add_argument("--batch-max-iter", type=int, default=4000)
     ap.add_argument("--cpu-sample-pairs", type=int, default=160)
+    ap.add_argument("--dielectric", type=int, default=0, metavar="BANDS",
+                    help="time the screening path instead: solves at z and -z for BANDS bands at a time, the "
+                         "density response accumulated over the band chunks, eps, eps^-1 and W_bar")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 5 device-to-device copies of MIB MiB (HBM counter calibration) and exit")
     args = ap.parse_args()
@@ -309,6 +404,8 @@ def main():
         f"({time.perf_counter() - t0:.1f} s)")
     ctx = sgw.sgw_ctx_create(0)
     dev = DeviceProblem(ctx, problem)
+    if args.dielectric:
+        return bench_dielectric(args, log, problem, ctx, dev)
     ws = sgw.Workspace(ctx)
     prec = sgw.MIXED if args.precision == "mixed" else sgw.FP64
     kw = dict(precision=prec)

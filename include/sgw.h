@@ -229,6 +229,54 @@ sgw_status sgw_apply_h_noalloc(sgw_ctx *ctx, const sgw_ham *ham, int n_vec, cons
                                int precision);
 
 /*
+ * Density response to the plane-wave perturbations (Sec. 2.3, Eq. 5), from the linear variations
+ * that two sternheimer_solve calls return: dpsi_plus at the shifts z_j = omega_j + i eta and
+ * dpsi_minus at -z_j (omega -> -omega_j, eta -> -eta), both [n_band][n_pert][n_omega][n_pw_kq]
+ * device arrays in the layout sternheimer_solve writes.  With the same h_kq, psi_occ_kq, h_k, psi_v
+ * and dv_miller as those solves:
+ *     chi[j][g][h] (+)= weight * (2 / Omega) * sum_v < exp(i (q+G_g) . r) u_v | dpsi_{v,h}(z_j) + dpsi_{v,h}(-z_j) >
+ * i.e. the Fourier component q + G_g of 2 sum_v u_v^* (du_v(z) + du_v(-z)) per unit cell (Omega
+ * from h_kq's reciprocal lattice; 2: spin), the response at q + G_g to the unit perturbation
+ * exp(i (q+G_h) . r).  The bra is taken as (1 - P_occ) exp(i (q+G) . r) u_v (the variations have no
+ * occupied component).  weight: the Brillouin-zone weight of the k point (1 / N_k for a uniform
+ * grid); accumulate = 0 overwrites chi, 1 adds to it (a sum over k points).
+ *   chi  device [n_omega][n_pert][n_pert] complex128, out (or in/out)
+ * Allocates its scratch (the right-hand sides of all bands, n_band * n_pert * n_pw_kq complex, and
+ * the band's overlap partials); returns after the GPU work.  NULL arrays, negative sizes or a
+ * non-finite weight: SGW_ERR_INVALID_ARG.
+ */
+sgw_status sgw_density_response(sgw_ctx *ctx, const sgw_ham *h_kq, int n_occ, const sgw_c128 *psi_occ_kq,
+                                const sgw_ham *h_k, int n_band, const sgw_c128 *psi_v, int n_pert,
+                                const int32_t *dv_miller, int n_omega, const sgw_c128 *dpsi_plus,
+                                const sgw_c128 *dpsi_minus, double weight, int accumulate, sgw_c128 *chi);
+
+/*
+ * Coulomb potential of the wave vectors q + G_p (Hartree units; q = k of h_kq minus k of h_k,
+ * G_p = dv_miller[p] on h_kq's reciprocal lattice): 4 pi / |q+G|^2, or with r_cut > 0 the spherical
+ * truncation (Sec. 2.6, Eq. 12) 4 pi / |q+G|^2 (1 - cos(|q+G| r_cut)), 2 pi r_cut^2 at q + G = 0.
+ *   v  host [n_pert] out
+ * q + G = 0 with r_cut <= 0: SGW_ERR_INVALID_ARG.
+ */
+sgw_status sgw_coulomb(const sgw_ham *h_kq, const sgw_ham *h_k, int n_pert, const int32_t *dv_miller, double r_cut,
+                       double *v);
+
+/*
+ * Dielectric matrix, its inverse and the correlation part of the screened interaction per frequency
+ * (Sec. 2.3, Eq. 4; Sec. 2.4, Eq. 9), from chi of sgw_density_response and v of sgw_coulomb:
+ *     eps_{gh}   = delta_{gh} - chi_{gh} v_h          (the perturbing charge's potential on the columns)
+ *     W_bar_{gh} = v_g (eps^{-1}_{gh} - delta_{gh})   (rows), off-diagonal elements zero in the row and
+ *                                                      column of a q + G = 0 (Sec. 2.4)
+ * (together W_bar = W - v with W = v (1 - chi v)^{-1}).  eps^{-1} by Gauss-Jordan elimination with
+ * partial pivoting in FP64, one workgroup per frequency.
+ *   chi                 device [n_omega][n_pert][n_pert] in
+ *   eps, eps_inv, wbar  device [n_omega][n_pert][n_pert] out; any may be NULL
+ * n_pert above 64: SGW_ERR_UNSUPPORTED.  Errors of sgw_coulomb are passed on.
+ */
+sgw_status sgw_screened_coulomb(sgw_ctx *ctx, const sgw_ham *h_kq, const sgw_ham *h_k, int n_pert,
+                                const int32_t *dv_miller, double r_cut, int n_omega, const sgw_c128 *chi,
+                                sgw_c128 *eps, sgw_c128 *eps_inv, sgw_c128 *wbar);
+
+/*
  * Occupied-manifold projector (Sec. 2.3, Eqs. 7-8), applied to n_vec vectors:
  *   mode 0:  y = x - Psi (Psi^H x)          (the conduction projector 1 - P_occ)
  *   mode 1:  y = y + alpha * Psi (Psi^H x)   (the + alpha P_occ term of the operator)

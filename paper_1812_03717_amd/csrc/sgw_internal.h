@@ -49,6 +49,8 @@ enum KernelId {
   K_PERMUTE,
   K_NL_DOT,
   K_NL_APPLY,
+  K_CHI_DOT,
+  K_DIELECTRIC,
   K_COUNT
 };
 const char *kernel_name(int id);

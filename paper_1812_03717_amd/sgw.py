@@ -39,6 +39,7 @@ EXPORTED = [
     "sgw_mlp_train_step", "sgw_operator_columns", "sgw_mlp_rows", "sternheimer_batch_workspace_size",
     "sternheimer_solve_batch", "sgw_autotune", "sgw_precond_values", "sgw_apply_h_noalloc",
     "sgw_green_workspace_size", "sgw_green_solve", "sgw_ham_set_nonlocal", "sgw_ham_nproj",
+    "sgw_density_response", "sgw_coulomb", "sgw_screened_coulomb",
 ]
 
 
@@ -100,6 +101,10 @@ def load_library(path: str = LIB_PATH):
         "sgw_apply_h_noalloc": [vp, vp, C.c_int, vp, vp, C.c_int],
         "sgw_apply_projector": [vp, vp, C.c_int, vp, C.c_int, vp, vp, dbl, C.c_int],
         "sgw_build_rhs": [vp, vp, C.c_int, vp, vp, C.c_int, vp, C.c_int, C.POINTER(i32), vp],
+        "sgw_density_response": [vp, vp, C.c_int, vp, vp, C.c_int, vp, C.c_int, C.POINTER(i32), C.c_int, vp, vp,
+                                 dbl, C.c_int, vp],
+        "sgw_coulomb": [vp, vp, C.c_int, C.POINTER(i32), dbl, C.POINTER(dbl)],
+        "sgw_screened_coulomb": [vp, vp, vp, C.c_int, C.POINTER(i32), dbl, C.c_int, vp, vp, vp, vp],
         "sgw_opts_default": [C.POINTER(sgw_opts)],
         "sternheimer_workspace_size": [vp, vp, C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(sgw_opts),
                                        C.POINTER(sz)],
@@ -312,6 +317,54 @@ def sgw_build_rhs(ctx, h_kq, psi_occ_kq, h_k, psi_v, dv_miller):
                                         h_k.handle, n_band, _ptr(psi_v), n_pert,
                                         dvm.ctypes.data_as(C.POINTER(C.c_int32)), _ptr(b)))
     return b
+
+
+def sgw_density_response(ctx, h_kq, psi_occ_kq, h_k, psi_v, dv_miller, dpsi_plus, dpsi_minus, weight=1.0,
+                         chi=None, accumulate=False):
+    """chi[j][g][h] (+)= weight * (2/Omega) sum_v <exp(i(q+G_g).r) u_v | dpsi_{v,h}(z_j) + dpsi_{v,h}(-z_j)>;
+    dpsi_plus / dpsi_minus: [n_band][n_pert][n_omega][n_pw_kq] from solves at z and -z."""
+    import torch
+    dvm = np.ascontiguousarray(np.asarray(dv_miller, np.int32).reshape(-1, 3))
+    n_band, n_pert = int(psi_v.shape[0]), int(dvm.shape[0])
+    n_omega = int(dpsi_plus.shape[2])
+    shape = (n_band, n_pert, n_omega, h_kq.n_pw)
+    _require(psi_v, torch.complex128, ctx.device, (n_band, h_k.n_pw), "psi_v")
+    _require(psi_occ_kq, torch.complex128, ctx.device, (psi_occ_kq.shape[0], h_kq.n_pw), "psi_occ_kq")
+    _require(dpsi_plus, torch.complex128, ctx.device, shape, "dpsi_plus")
+    _require(dpsi_minus, torch.complex128, ctx.device, shape, "dpsi_minus")
+    if chi is None:
+        chi = torch.empty((n_omega, n_pert, n_pert), dtype=torch.complex128, device=ctx.device)
+        accumulate = False
+    _require(chi, torch.complex128, ctx.device, (n_omega, n_pert, n_pert), "chi")
+    _check(load_library().sgw_density_response(ctx.handle, h_kq.handle, int(psi_occ_kq.shape[0]), _ptr(psi_occ_kq),
+                                               h_k.handle, n_band, _ptr(psi_v), n_pert,
+                                               dvm.ctypes.data_as(C.POINTER(C.c_int32)), n_omega, _ptr(dpsi_plus),
+                                               _ptr(dpsi_minus), float(weight), int(bool(accumulate)), _ptr(chi)))
+    return chi
+
+
+def sgw_coulomb(h_kq, h_k, dv_miller, r_cut=0.0):
+    """v(q + G_p) (host float64 [n_pert]), bare or spherically truncated at r_cut."""
+    dvm = np.ascontiguousarray(np.asarray(dv_miller, np.int32).reshape(-1, 3))
+    v = np.zeros(dvm.shape[0], np.float64)
+    _check(load_library().sgw_coulomb(h_kq.handle, h_k.handle, int(dvm.shape[0]),
+                                      dvm.ctypes.data_as(C.POINTER(C.c_int32)), float(r_cut),
+                                      v.ctypes.data_as(C.POINTER(C.c_double))))
+    return v
+
+
+def sgw_screened_coulomb(ctx, h_kq, h_k, dv_miller, chi, r_cut=0.0):
+    """(eps, eps_inv, wbar), each [n_omega][n_pert][n_pert] on the device, from chi."""
+    import torch
+    dvm = np.ascontiguousarray(np.asarray(dv_miller, np.int32).reshape(-1, 3))
+    n_pert = int(dvm.shape[0])
+    n_omega = int(chi.shape[0])
+    _require(chi, torch.complex128, ctx.device, (n_omega, n_pert, n_pert), "chi")
+    eps, inv, wbar = (torch.empty_like(chi) for _ in range(3))
+    _check(load_library().sgw_screened_coulomb(ctx.handle, h_kq.handle, h_k.handle, n_pert,
+                                               dvm.ctypes.data_as(C.POINTER(C.c_int32)), float(r_cut), n_omega,
+                                               _ptr(chi), _ptr(eps), _ptr(inv), _ptr(wbar)))
+    return eps, inv, wbar
 
 
 def sgw_opts_default(**overrides):

@@ -1,0 +1,148 @@
+"""GPU parity of the consumers of the linear variations: the density response (Sec. 2.3, Eq. 5),
+the dielectric matrix (Eq. 4) and W_bar (Sec. 2.4, Eq. 9) with the bare and truncated Coulomb
+potential (Sec. 2.6, Eq. 12), against the oracle.
+
+* chi from the library's own solves at z and -z (sternheimer_solve with omega, eta and with
+  -omega, -eta) against the oracle's sum over empty states: the solves carry relative errors up to
+  kappa * tol_eff <= 5e-9 each, so 1e-8 of the largest entry.
+* eps, eps^-1 and W_bar from a given chi against the oracle's formulas and numpy's inverse:
+  1e-12 relative (FP64 Gauss-Jordan; these matrices are well conditioned).
+* the q + G = 0 rule with the truncated potential, accumulation over k-point weights, errors.
+"""
+import numpy as np
+import pytest
+
+import oracle.sternheimer_oracle as so
+from synth import configs
+from synth import crystal as cx
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from tests.libutil import ensure_library
+    ensure_library()
+    from paper_1812_03717_amd import sgw
+    c = sgw.sgw_ctx_create(0)
+    yield c
+    torch.cuda.synchronize()
+
+
+CASES = {
+    # 2-atom cell at a seeded q, 24^3 grid (whole-line kernels)
+    "fcc1_q": lambda: configs.small((1, 1, 1), n_omega=5, n_pert=5, seed=9100),
+    # 4-atom cell, 48 x 24 x 24 grid (two-thread 48-point planes), more perturbations
+    "fcc211_q": lambda: configs.small((2, 1, 1), grid=(48, 24, 24), n_omega=4, n_pert=8, seed=9200, ecut=8.0),
+}
+
+
+def _solve_pm(ctx, d, p, tol):
+    """The variations at z_j = omega_j + i eta and at -z_j."""
+    from paper_1812_03717_amd import sgw
+    out = []
+    for sgn in (1.0, -1.0):
+        st, dpsi, info = sgw.sternheimer_solve(ctx, d.h_kq, d.psi_occ_kq, d.h_k, d.psi_v, d.eps_v, p.dv_miller,
+                                               sgn * p.omega, sgn * p.eta, tol)
+        inf = sgw.info_to_numpy(info)
+        assert st == sgw.SGW_OK, sgw.load_library().sgw_last_error()
+        assert np.all(inf["flags"] & sgw.FLAG_CONVERGED) and inf["relres"].max() <= tol
+        out.append(dpsi)
+    return out
+
+
+def _oracle_chi(p):
+    h = so.hamiltonian(p.miller_kq, p.B, p.kqvec, p.v_grid)
+    w, u = so.eigh(h)
+    zs = p.omega + 1j * p.eta
+    chi = so.density_response_spectral(w, u, p.n_occ, p.psi_k[: p.n_band], p.eps_k[: p.n_band], p.miller_k,
+                                       p.miller_kq, p.dv_miller, zs, so.cell_volume(p.B))
+    kap = max(so.condition_number(w, p.n_occ, p.eps_k[v], s * z)
+              for v in range(p.n_band) for z in zs for s in (1, -1))
+    return chi, kap
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_density_response_matches_oracle(ctx, name):
+    from paper_1812_03717_amd import sgw
+    from paper_1812_03717_amd.workload import DeviceProblem
+    p = CASES[name]()
+    d = DeviceProblem(ctx, p)
+    ref, kap = _oracle_chi(p)
+    tol = max(2e-13, min(1e-10, 1e-8 / (2.0 * kap)))
+    dp, dm = _solve_pm(ctx, d, p, tol)
+    chi = sgw.sgw_density_response(ctx, d.h_kq, d.psi_occ_kq, d.h_k, d.psi_v, p.dv_miller, dp, dm).cpu().numpy()
+    err = np.abs(chi - ref).max() / np.abs(ref).max()
+    print(name, p.n_pw_kq, "PW,", p.n_band, "bands,", p.n_pert, "perts: kappa", kap, "tol", tol, "chi rel err", err,
+          flush=True)
+    assert err <= 1e-8
+    # the same from the oracle's formula on the library's own variations (contraction only)
+    chi_sol = so.density_response_from_solutions(p.psi_k[: p.n_band], p.miller_k, p.miller_kq, p.dv_miller, p.psi_kq,
+                                                  dp.cpu().numpy(), dm.cpu().numpy(), so.cell_volume(p.B))
+    err_c = np.abs(chi - chi_sol).max() / np.abs(chi_sol).max()
+    print(name, "contraction vs oracle on the same variations", err_c, flush=True)
+    assert err_c <= 1e-12
+    # accumulation over k-point weights: two halves add up to the whole
+    acc = sgw.sgw_density_response(ctx, d.h_kq, d.psi_occ_kq, d.h_k, d.psi_v, p.dv_miller, dp, dm, weight=0.25)
+    sgw.sgw_density_response(ctx, d.h_kq, d.psi_occ_kq, d.h_k, d.psi_v, p.dv_miller, dp, dm, weight=0.75, chi=acc,
+                             accumulate=True)
+    assert np.abs(acc.cpu().numpy() - chi).max() <= 1e-14 * np.abs(chi).max()
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_screened_coulomb_matches_oracle(ctx, name):
+    from paper_1812_03717_amd import sgw
+    from paper_1812_03717_amd.workload import DeviceProblem
+    p = CASES[name]()
+    d = DeviceProblem(ctx, p)
+    chi, _ = _oracle_chi(p)
+    qg = (p.dv_miller + 0.0) @ p.B + p.qvec
+    for r_cut in (0.0, 6.0):
+        v = sgw.sgw_coulomb(d.h_kq, d.h_k, p.dv_miller, r_cut=r_cut)
+        assert np.allclose(v, so.coulomb(qg, r_cut), rtol=1e-13, atol=0)
+        eps, inv, wbar = sgw.sgw_screened_coulomb(ctx, d.h_kq, d.h_k, p.dv_miller,
+                                                  torch.from_numpy(chi).to(ctx.device), r_cut=r_cut)
+        eps, inv, wbar = eps.cpu().numpy(), inv.cpu().numpy(), wbar.cpu().numpy()
+        e_ref = so.dielectric(chi, v)
+        w_ref = so.screened_correlation(e_ref, v)
+        assert np.abs(eps - e_ref).max() <= 1e-15 * np.abs(e_ref).max()
+        e_inv = np.abs(inv - np.linalg.inv(e_ref)).max() / np.abs(inv).max()
+        e_w = np.abs(wbar - w_ref).max() / np.abs(w_ref).max()
+        cond = max(np.linalg.cond(e) for e in e_ref)
+        print(name, "r_cut", r_cut, "cond(eps)", cond, "eps^-1 rel err", e_inv, "W_bar rel err", e_w, flush=True)
+        assert e_inv <= 1e-13 * cond and e_w <= 1e-13 * cond
+        # eps eps^-1 = 1
+        assert np.abs(np.einsum("zab,zbc->zac", e_ref, inv) - np.eye(p.n_pert)).max() <= 1e-13 * cond
+
+
+def test_zero_wave_vector_and_errors(ctx):
+    """q = 0 with G = 0 among the perturbations: its variation is zero (the source lies in the occupied
+    space), the bare potential is refused, the truncated one gives 2 pi r_cut^2 there and W_bar keeps
+    only the diagonal element of that row and column (Sec. 2.4)."""
+    from paper_1812_03717_amd import sgw
+    from paper_1812_03717_amd.workload import DeviceProblem
+    p = configs.si2()
+    d = DeviceProblem(ctx, p)
+    dvm = np.array([[0, 0, 0], [1, 0, 0], [0, 1, -1]], np.int32)
+    with pytest.raises(sgw.SgwError):
+        sgw.sgw_coulomb(d.h_kq, d.h_k, dvm)
+    v = sgw.sgw_coulomb(d.h_kq, d.h_k, dvm, r_cut=5.0)
+    assert v[0] == 2 * np.pi * 25.0
+    rng = np.random.default_rng(4)
+    chi = (rng.standard_normal((3, 3, 3)) + 1j * rng.standard_normal((3, 3, 3))) * 1e-3
+    eps, inv, wbar = sgw.sgw_screened_coulomb(ctx, d.h_kq, d.h_k, dvm, torch.from_numpy(chi).to(ctx.device),
+                                              r_cut=5.0)
+    w_ref = so.screened_correlation(so.dielectric(chi, v), v, zero_rows=[0])
+    wb = wbar.cpu().numpy()
+    assert np.all(wb[:, 0, 1:] == 0) and np.all(wb[:, 1:, 0] == 0)
+    assert np.abs(wb - w_ref).max() <= 1e-12 * np.abs(w_ref).max()
+    with pytest.raises(sgw.SgwError):   # more wave vectors than the in-LDS inversion takes
+        big = np.array([[i, 1, 0] for i in range(65)], np.int32)
+        sgw.sgw_screened_coulomb(ctx, d.h_kq, d.h_k, big, torch.zeros((1, 65, 65), dtype=torch.complex128,
+                                                                       device=ctx.device))
+    lib = sgw.load_library()
+    assert lib.sgw_density_response(ctx.handle, d.h_kq.handle, 0, None, d.h_k.handle, 1, None, 1, None, 1, None, None,
+                                    1.0, 0, None) == sgw.SGW_ERR_INVALID_ARG
