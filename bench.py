@@ -289,7 +289,7 @@ def bench_batch(args, log):
     tune_ms = sum(batch.autotune(i) for i in range(len(devs)))
     log(f"autotune: {tune_ms / 1e3:.2f} s (wall {time.perf_counter() - t:.2f} s); steps_per_sync/graph chosen: "
         f"{sorted({(it['problem'].opts.steps_per_sync, it['problem'].opts.graph) for it in batch.items})}; "
-        f"plane kernel (1 line, 2 pair, 3 LDS) per grid: "
+        f"plane kernel (1 line, 2 pair, 3 LDS, 4 three-thread) per grid: "
         f"{sorted({(tuple(devs[i].h_kq.grid), it['problem'].opts.fft_planes) for i, it in enumerate(batch.items)})}")
     workers = args.batch_workers
 

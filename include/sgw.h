@@ -99,17 +99,19 @@ enum { SGW_GUESS_ZERO = 0, SGW_GUESS_LEARNED = 1 };
 /*
  * Kernel of the plane pass of the FP64 H.x (sgw_opts.fft_planes, sgw_ctx_set_fft_planes): the
  * 2D inverse FFT of a plane, the potential and the 2D forward FFT (Sec. 2.1).
- *   SGW_FFT_AUTO  the built-in choice: LINE where it applies, else PAIR, else LDS
+ *   SGW_FFT_AUTO  the built-in choice: LINE where it applies, else TRI, else PAIR, else LDS
  *   SGW_FFT_LINE  one thread per row or column, the whole line in registers: lines of at most 48
  *                 points whose sticks lie in the central half of the plane (|m| < N/4)
  *   SGW_FFT_PAIR  two threads per line, split by real-space parity: lines of at most 72 points in
  *                 the central half
  *   SGW_FFT_LDS   the whole plane in LDS, radix stages exchanged through it: every grid
+ *   SGW_FFT_TRI   three threads per line, split by the real-space index mod 3: lines of 24, 48 or
+ *                 72 points in the central half
  * A kernel that does not apply to a grid falls back to the built-in choice; the FP32 potential
  * path of SGW_MIXED always takes the built-in choice (PAIR has no FP32 form).  All give H.x to
  * rounding.
  */
-enum { SGW_FFT_AUTO = 0, SGW_FFT_LINE = 1, SGW_FFT_PAIR = 2, SGW_FFT_LDS = 3 };
+enum { SGW_FFT_AUTO = 0, SGW_FFT_LINE = 1, SGW_FFT_PAIR = 2, SGW_FFT_LDS = 3, SGW_FFT_TRI = 4 };
 
 typedef struct sgw_ctx sgw_ctx;
 typedef struct sgw_ham sgw_ham;

@@ -182,7 +182,7 @@ extern "C" sgw_status sgw_ctx_destroy(sgw_ctx *ctx) {
 
 extern "C" sgw_status sgw_ctx_set_fft_planes(sgw_ctx *ctx, int fft_planes) {
   if (!ctx) return fail(SGW_ERR_INVALID_ARG, "ctx is NULL");
-  if (fft_planes < SGW_FFT_AUTO || fft_planes > SGW_FFT_LDS)
+  if (fft_planes < SGW_FFT_AUTO || fft_planes > SGW_FFT_TRI)
     return fail(SGW_ERR_INVALID_ARG, "sgw_ctx_set_fft_planes: unknown plane kernel");
   ctx->fft_planes = fft_planes;
   return SGW_OK;
@@ -866,7 +866,7 @@ static sgw_status validate_solve(sgw_ctx *ctx, const sgw_ham *h_kq, int n_occ, c
   SGW_CHECK(o.solver >= SGW_SOLVER_MULTISHIFT && o.solver <= SGW_SOLVER_TAIL, "sternheimer_solve: unknown solver");
   SGW_CHECK(o.precond >= SGW_PC_NONE && o.precond <= SGW_PC_LEARNED, "sternheimer_solve: unknown preconditioner");
   SGW_CHECK(o.guess == SGW_GUESS_ZERO || o.guess == SGW_GUESS_LEARNED, "sternheimer_solve: unknown initial guess");
-  SGW_CHECK(o.fft_planes >= SGW_FFT_AUTO && o.fft_planes <= SGW_FFT_LDS, "sternheimer_solve: unknown plane kernel");
+  SGW_CHECK(o.fft_planes >= SGW_FFT_AUTO && o.fft_planes <= SGW_FFT_TRI, "sternheimer_solve: unknown plane kernel");
   SGW_CHECK(o.basis_blocks == 0 ||
                 (o.basis_blocks > 0 && ((long)o.basis_blocks << kBasisBlockShift) >= (long)o.max_iter + 1),
             "sternheimer_solve: basis_blocks must hold one pair's max_iter + 1 Krylov vectors");
@@ -1783,7 +1783,7 @@ extern "C" sgw_status sgw_autotune(sgw_ctx *ctx, const sgw_problem *problem, sgw
       const double2 *x = (const double2 *)hb;
       double2 *y = (double2 *)((char *)hb + vb);
       void *t = (char *)hb + 2 * vb;
-      for (int v = SGW_FFT_LINE; v <= SGW_FFT_LDS && st >= 0; ++v) {
+      for (int v = SGW_FFT_LINE; v <= SGW_FFT_TRI && st >= 0; ++v) {
         FftScope fs(tctx, v);
         if (hx_plane_kernel(tctx, h, false) != v) continue;  // does not apply here
         double ms = 0;

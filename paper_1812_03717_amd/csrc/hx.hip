@@ -496,11 +496,15 @@ template <class C2, int N0, int N1>
 int plane_kernel(const sgw_ctx *ctx, const sgw_ham *h) {
   const bool win = line_window_ok(h->n, h->m0_lo, h->n_row, h->m1_lo, h->m1_hi);
   const bool line = win && line_planes_fit<C2, N0, N1>(), pair = win && pair_planes_fit<C2, N0, N1>();
+  const bool tri = win && sizeof(C2) == 16 && tri_planes_fit<N0, N1>();
   const int want = ctx->fft_active ? ctx->fft_active : ctx->fft_planes;
   if (want == SGW_FFT_LINE && line) return SGW_FFT_LINE;
   if (want == SGW_FFT_PAIR && pair) return SGW_FFT_PAIR;
+  if (want == SGW_FFT_TRI && tri) return SGW_FFT_TRI;
   if (want == SGW_FFT_LDS) return SGW_FFT_LDS;
-  return line ? SGW_FFT_LINE : pair ? SGW_FFT_PAIR : SGW_FFT_LDS;
+  // built-in choice: the whole-line kernel where a line fits one thread, else the three-thread split
+  // (24, 48, 72 points), else the two-thread one (64), else the whole plane in LDS
+  return line ? SGW_FFT_LINE : tri ? SGW_FFT_TRI : pair ? SGW_FFT_PAIR : SGW_FFT_LDS;
 }
 
 template <class C2, int N0, int N1>
@@ -528,6 +532,12 @@ sgw_status launch_planes(sgw_ctx *ctx, const sgw_ham *h, int n_vec, C2 *tbuf) {
   if constexpr (pair_planes_fit<C2, N0, N1>()) {
     if (use == SGW_FFT_PAIR)
       hipLaunchKernelGGL((k_planes_pair<N0, N1>), dim3(blocks), dim3(pair_plane_threads<N0, N1>()), 0, ctx->stream,
+                         (double2 *)tbuf, h->n[2], h->n_stick, h->d_rows, h->d_stick_ij, h->m0_lo, h->n_row,
+                         h->d_vt);
+  }
+  if constexpr (sizeof(C2) == 16 && tri_planes_fit<N0, N1>()) {
+    if (use == SGW_FFT_TRI)
+      hipLaunchKernelGGL((k_planes_tri<N0, N1>), dim3(blocks), dim3(tri_plane_threads<N0, N1>()), 0, ctx->stream,
                          (double2 *)tbuf, h->n[2], h->n_stick, h->d_rows, h->d_stick_ij, h->m0_lo, h->n_row,
                          h->d_vt);
   }

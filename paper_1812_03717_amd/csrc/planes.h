@@ -576,4 +576,181 @@ void k_planes_pair(double2 *__restrict__ T, int n2, int n_stick, const int4 *__r
   }
 }
 
+
+// Three-thread variant for FP64 planes: the real-space index of a line splits by its residue r mod 3,
+// n = 3m + r (N = 3L), so each of three threads holds L = N/3 values (24 at 72 points: ~100 fewer
+// VGPRs than the two-thread split, three waves per SIMD instead of two).  Under the central-half
+// window (k < N/4 or k >= 3N/4), k mod L takes every residue rho once or twice: rho < N/4 from the
+// lower half (k = rho), rho >= N/12 from the upper half (k = rho + 2L).  Then
+//   x[3m + r] = sum_rho Y_r[rho] w_L^(m rho),  Y_r[rho] = sum_{k in window, k = rho mod L} X[k] w_N^(r k)
+// and the forward's window outputs are
+//   X'[k] = sum_r w_N^(-r k) Z_r[k mod L],      Z_r = forward L-point transform of x'[3m + r].
+// The three residues' forward contributions are added through LDS (r = 2 writes, r = 1 and r = 0 add
+// in turn).  Window slot s of a line holds k = s (s < N/4) or k = s + N/2 (s >= N/4).
+template <int N0, int N1> constexpr bool tri_planes_fit() {
+  return N0 % 12 == 0 && N1 % 12 == 0 && N0 >= 24 && N1 >= 24 && N0 <= 72 && N1 <= 72;
+}
+template <int N0, int N1> constexpr int tri_plane_threads() {
+  return ((3 * N1 > 3 * (N0 / 2) ? 3 * N1 : 3 * (N0 / 2)) + 63) / 64 * 64;
+}
+
+// y[rho] = Y_R[rho] from the window slots src[s * stride] (inverse: SIGN = +1)
+template <int N, int R>
+__device__ __forceinline__ void tri_fold(const double2 *src, int stride, double2 *y) {
+  constexpr int L = N / 3, Q = N / 4, H = N / 2, LO = N / 12;
+#pragma unroll
+  for (int rho = 0; rho < L; ++rho) {
+    double2 v = make_double2(0.0, 0.0);
+    if (rho < Q) v = twiddle_c<N, +1>(src[rho * stride], R * rho);
+    if (rho >= LO) v = c_add(v, twiddle_c<N, +1>(src[(rho + 2 * L - H) * stride], R * (rho + 2 * L)));
+    y[rho] = v;
+  }
+}
+// the window slots' forward contributions w_N^(-R k) Z[k mod L]: dst[s * stride] = (ADD ? dst + : ) c_s
+template <int N, int R, bool ADD>
+__device__ __forceinline__ void tri_unfold(const double2 *z, double2 *dst, int stride) {
+  constexpr int L = N / 3, Q = N / 4, H = N / 2;
+#pragma unroll
+  for (int s = 0; s < H; ++s) {
+    const int k = s < Q ? s : s + H;
+    const double2 c = twiddle_c<N, -1>(z[k % L], R * k);
+    dst[s * stride] = ADD ? c_add(dst[s * stride], c) : c;
+  }
+}
+template <int N, bool ADD>
+__device__ __forceinline__ void tri_unfold_r(int r, const double2 *z, double2 *dst, int stride) {
+  if (r == 0) tri_unfold<N, 0, ADD>(z, dst, stride);
+  else if (r == 1) tri_unfold<N, 1, ADD>(z, dst, stride);
+  else tri_unfold<N, 2, ADD>(z, dst, stride);
+}
+
+template <int N0, int N1>
+__global__ __launch_bounds__((tri_plane_threads<N0, N1>())) __attribute__((amdgpu_waves_per_eu(3)))
+void k_planes_tri(double2 *__restrict__ T, int n2, int n_stick, const int4 *__restrict__ rows,
+                  const int *__restrict__ stick_ij, int m0_lo, int n_row, const double *__restrict__ vt) {
+  constexpr int NT = tri_plane_threads<N0, N1>();
+  constexpr int LD = N1 + 1;
+  constexpr int H0 = N0 / 2, Q0 = N0 / 4, H1 = N1 / 2, Q1 = N1 / 4, L0 = N0 / 3, L1 = N1 / 3;
+  __shared__ double2 buf[H0][LD];
+  const long q = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int z = (int)(q % n2);
+  double2 *Tq = T + q * n_stick;
+  const double *vz = vt + (long)z * N0 * N1;
+  const double2 zero = make_double2(0.0, 0.0);
+  auto slot_of = [](int m0) { return m0 >= 0 ? m0 : m0 + H0; };
+
+  // window rows without sticks read as zero in the axis-0 pass
+  const int n_below = m0_lo + Q0, n_empty = H0 - n_row;
+  for (int e = tid; e < n_empty * LD; e += NT) {
+    const int k = e / LD, c = e - k * LD;
+    const int m0 = k < n_below ? -Q0 + k : m0_lo + n_row + (k - n_below);
+    buf[slot_of(m0)][c] = zero;
+  }
+
+  // ---- axis 1, inverse: (residue, stick row) per thread; residue r writes the columns 3m + r ----
+  const bool row_act = tid < 3 * n_row;
+  const int rr = row_act ? tid / n_row : 0;
+  const int t = tid - rr * n_row;
+  const int srow = slot_of(m0_lo + t);
+  // the row's window values go to its LDS row by slot first (each of the three threads loads a third)
+  if (row_act) {
+    const int4 ri = rows[t];
+    const double2 *run = Tq + (ri.x - ri.y);  // run[m1]: the row's stick at m1
+    double2 w[H1 / 3];
+#pragma unroll
+    for (int u = 0; u < H1 / 3; ++u) {
+      const int j = 3 * u + rr;
+      const int m1 = j < Q1 ? j : j - H1;
+      w[u] = zero;
+      if (m1 >= ri.y && m1 <= ri.z) w[u] = run[m1];
+    }
+#pragma unroll
+    for (int u = 0; u < H1 / 3; ++u) buf[srow][3 * u + rr] = w[u];
+  }
+  __syncthreads();
+  double2 xr[L1];
+  if (row_act) {
+    if (rr == 0) tri_fold<N1, 0>(&buf[srow][0], 1, xr);
+    else if (rr == 1) tri_fold<N1, 1>(&buf[srow][0], 1, xr);
+    else tri_fold<N1, 2>(&buf[srow][0], 1, xr);
+    half_line_dft<L1, +1>(xr);
+  }
+  __syncthreads();  // the row's window slots have been read
+  if (row_act) {
+#pragma unroll
+    for (int m = 0; m < L1; ++m) buf[srow][3 * m + rr] = xr[m];
+  }
+  __syncthreads();
+
+  // ---- axis 0: inverse, times V(r), forward; (residue, column) per thread ----
+  {
+    const bool act = tid < 3 * N1;
+    const int r = act ? tid / N1 : 0;
+    const int i1 = tid - r * N1;
+    double2 x[L0];
+    if (act) {
+      const double2 *col = &buf[0][i1];
+      if (r == 0) tri_fold<N0, 0>(col, LD, x);
+      else if (r == 1) tri_fold<N0, 1>(col, LD, x);
+      else tri_fold<N0, 2>(col, LD, x);
+      half_line_dft<L0, +1>(x);
+      const double *vc = vz + r * N1 + i1;  // V at i0 = 3m + r
+#pragma unroll
+      for (int m = 0; m < L0; ++m) x[m] = c_scale(x[m], vc[3 * m * N1]);
+      half_line_dft<L0, -1>(x);
+    }
+    __syncthreads();  // every column's window slots have been read
+    if (act && r == 2) tri_unfold_r<N0, false>(2, x, &buf[0][i1], LD);
+    __syncthreads();
+    if (act && r == 1) tri_unfold_r<N0, true>(1, x, &buf[0][i1], LD);
+    __syncthreads();
+    if (act && r == 0) tri_unfold_r<N0, true>(0, x, &buf[0][i1], LD);
+    __syncthreads();
+  }
+
+  // ---- axis 1, forward: (residue, stick row) per thread; window column k <- sum of residues ----
+  {
+    double2 x[L1];
+    if (row_act) {
+#pragma unroll
+      for (int m = 0; m < L1; ++m) x[m] = buf[srow][3 * m + rr];
+      half_line_dft<L1, -1>(x);
+    }
+    __syncthreads();  // the row's real-space values have been read
+    // window column slot s sits at column s (s < N1/4) or s + N1/2
+    if (row_act && rr == 2) {
+#pragma unroll
+      for (int s = 0; s < H1; ++s) {
+        const int k = s < Q1 ? s : s + H1;
+        buf[srow][k] = twiddle_c<N1, -1>(x[k % L1], 2 * k);
+      }
+    }
+    __syncthreads();
+    if (row_act && rr == 1) {
+#pragma unroll
+      for (int s = 0; s < H1; ++s) {
+        const int k = s < Q1 ? s : s + H1;
+        buf[srow][k] = c_add(buf[srow][k], twiddle_c<N1, -1>(x[k % L1], k));
+      }
+    }
+    __syncthreads();
+    if (row_act && rr == 0) {
+#pragma unroll
+      for (int s = 0; s < H1; ++s) {
+        const int k = s < Q1 ? s : s + H1;
+        buf[srow][k] = c_add(buf[srow][k], x[k % L1]);
+      }
+    }
+    __syncthreads();
+  }
+
+  // ---- gather the sticks, one per thread ----
+  for (int s = tid; s < n_stick; s += NT) {
+    const int ij = stick_ij[s];
+    const int i0 = ij >> 16;
+    Tq[s] = buf[i0 < Q0 ? i0 : i0 - H0][ij & 0xffff];
+  }
+}
+
 }  // namespace sgw

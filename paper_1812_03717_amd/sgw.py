@@ -24,7 +24,7 @@ SOLVER_MULTISHIFT, SOLVER_PER_SHIFT, SOLVER_TAIL = 0, 1, 2
 FP64, MIXED = 0, 1
 PC_NONE, PC_TETER, PC_LEARNED = 0, 1, 2
 GUESS_ZERO, GUESS_LEARNED = 0, 1
-FFT_AUTO, FFT_LINE, FFT_PAIR, FFT_LDS = 0, 1, 2, 3
+FFT_AUTO, FFT_LINE, FFT_PAIR, FFT_LDS, FFT_TRI = 0, 1, 2, 3, 4
 PROJ_SPLIT_BF16 = 16  # sgw_apply_projector mode bit: split-BF16 contraction
 
 INFO_DTYPE = np.dtype([("iters", "<i4"), ("flags", "<i4"), ("relres", "<f8"), ("occ_leak", "<f8")])

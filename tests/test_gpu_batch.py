@@ -112,7 +112,7 @@ def test_autotune(ctx, systems, singles):
     print("autotune", ps[0].name, "ms", ms, "steps_per_sync", o.steps_per_sync, "graph", o.graph,
           "plane kernel", o.fft_planes, flush=True)
     assert ms > 0 and o.steps_per_sync in (4, 8, 16) and o.graph in (0, 1)
-    assert o.fft_planes in (sgw.FFT_LINE, sgw.FFT_PAIR, sgw.FFT_LDS)
+    assert o.fft_planes in (sgw.FFT_LINE, sgw.FFT_PAIR, sgw.FFT_LDS, sgw.FFT_TRI)
     assert b.autotune(0) == 0.0  # cached for this system class
     assert b.solve(n_workers=2) == sgw.SGW_OK
     # the batch reproduces the one-system solve under the same (tuned) options bit for bit

@@ -83,7 +83,7 @@ def test_apply_h_each_plane_kernel(ctx, name):
     """Every plane-pass kernel that applies to the grid, forced through sgw_ctx_set_fft_planes, gives
     H.x to rounding; the whole-plane LDS kernel applies everywhere, the two-thread kernel wherever the
     sticks lie in the central half of the plane (all these grids but si2's), the whole-line kernel
-    there up to 48 points."""
+    there up to 48 points, the three-thread kernel there on 24-, 48- and 72-point lines."""
     from paper_1812_03717_amd import sgw
     p = PROBLEMS[name]()
     d = _dev(ctx, p)
@@ -93,7 +93,7 @@ def test_apply_h_each_plane_kernel(ctx, name):
     yr = x @ so.hamiltonian(p.miller_kq, p.B, p.kvec + p.qvec, p.v_grid).T
     ran = []
     try:
-        for v in (sgw.FFT_LINE, sgw.FFT_PAIR, sgw.FFT_LDS):
+        for v in (sgw.FFT_LINE, sgw.FFT_PAIR, sgw.FFT_LDS, sgw.FFT_TRI):
             ctx.set_fft_planes(v)
             k = ctx.plane_kernel(d.h_kq)
             y = sgw.sgw_apply_h(ctx, d.h_kq, torch.from_numpy(x).to(ctx.device)).cpu().numpy()
@@ -106,17 +106,21 @@ def test_apply_h_each_plane_kernel(ctx, name):
     assert ran[2] == sgw.FFT_LDS
     assert ran[1] == (sgw.FFT_LDS if name == "si2" else sgw.FFT_PAIR)
     line_fits = name != "si2" and max(p.v_grid.shape[:2]) <= 48
-    assert ran[0] == (sgw.FFT_LINE if line_fits else sgw.FFT_PAIR if name != "si2" else sgw.FFT_LDS)
+    tri_fits = name != "si2" and all(n % 12 == 0 for n in p.v_grid.shape[:2])
+    auto = (sgw.FFT_LINE if line_fits else sgw.FFT_TRI if tri_fits else sgw.FFT_PAIR if name != "si2"
+            else sgw.FFT_LDS)
+    assert ran[0] == (sgw.FFT_LINE if line_fits else auto)
+    assert ran[3] == (sgw.FFT_TRI if tri_fits else auto)
 
 
-@pytest.mark.parametrize("kernel", ["pair", "lds"])
+@pytest.mark.parametrize("kernel", ["pair", "lds", "tri"])
 def test_solve_each_plane_kernel(ctx, kernel):
     """The solver with its plane kernel forced through sgw_opts.fft_planes (24^3, where the built-in
     choice is the whole-line kernel), against the oracle at the bar of test_solve_matches_oracle."""
     from paper_1812_03717_amd import sgw
     p = PROBLEMS["fcc1_q"]()
     d = _dev(ctx, p)
-    v = {"pair": sgw.FFT_PAIR, "lds": sgw.FFT_LDS}[kernel]
+    v = {"pair": sgw.FFT_PAIR, "lds": sgw.FFT_LDS, "tri": sgw.FFT_TRI}[kernel]
     opts = sgw.sgw_opts_default(fft_planes=v)
     assert ctx.plane_kernel(d.h_kq) == sgw.FFT_LINE
     pairs = [(b, q) for b in range(p.n_band) for q in range(p.n_pert)]
@@ -137,10 +141,11 @@ def test_solve_each_plane_kernel(ctx, kernel):
         d.solve(tol=tol, opts=sgw.sgw_opts_default(fft_planes=7))
 
 
-def test_apply_h_si64_shape_sampled(ctx):
+@pytest.mark.parametrize("kernel", ["auto", "pair"])
+def test_apply_h_si64_shape_sampled(ctx, kernel):
     """72^3 grid at the si64 size (64-atom cubic cell, ~16,000 plane waves, sticks filling most of the
     central-half window): 48 sampled rows of H, from the oracle's definition, against the FP64 H.x of
-    64 vectors."""
+    64 vectors, with the built-in plane kernel (the three-thread one) and with the two-thread one."""
     from paper_1812_03717_amd import sgw
     from synth import configs
     from synth import crystal as cx
@@ -155,7 +160,12 @@ def test_apply_h_si64_shape_sampled(ctx):
     n = miller.shape[0]
     rng = np.random.default_rng(72)
     x = rng.standard_normal((64, n)) + 1j * rng.standard_normal((64, n))
-    y = sgw.sgw_apply_h(ctx, ham, torch.from_numpy(x).to(ctx.device)).cpu().numpy()
+    try:
+        ctx.set_fft_planes(sgw.FFT_PAIR if kernel == "pair" else sgw.FFT_AUTO)
+        assert ctx.plane_kernel(ham) == (sgw.FFT_PAIR if kernel == "pair" else sgw.FFT_TRI)
+        y = sgw.sgw_apply_h(ctx, ham, torch.from_numpy(x).to(ctx.device)).cpu().numpy()
+    finally:
+        ctx.set_fft_planes(sgw.FFT_AUTO)
     rows = rng.choice(n, 48, replace=False)
     ref = x @ so.hamiltonian_rows(miller, B, q, v, rows).T
     err = np.abs(y[:, rows] - ref).max() / np.abs(ref).max()
