@@ -345,6 +345,10 @@ typedef struct {
                                are free.  A pair that cannot grow waits; when no running pair can
                                grow, the least advanced one is restarted later.  Results do not
                                change. */
+  const double *shift_imag; /* optional host [n_omega]: shift j is omega[j] + i shift_imag[j] (each
+                               finite) instead of omega[j] + i eta, e.g. frequencies on the
+                               imaginary axis; NULL: eta for every shift.  The shifts still share
+                               one Krylov space (any complex shift of the Hermitian operator does) */
 } sgw_opts;
 
 /* Fills *opts with the defaults. */

@@ -24,7 +24,10 @@ What it computes (Hartree units; every function cites the passage it follows):
 * the density response to the plane-wave perturbations (Sec. 2.3, Eq. 5), by the
   sum over empty states and from given linear variations, the dielectric matrix
   (Eq. 4), the correlation part of the screened interaction (Sec. 2.4, Eq. 9) and
-  the (optionally truncated) Coulomb potential (Sec. 2.6, Eq. 12).
+  the (optionally truncated) Coulomb potential (Sec. 2.6, Eq. 12);
+* the diagonal correlation self-energy on the imaginary axis (Sec. 2.4, Eq. 10),
+  the AAA rational continuation (Sec. 2.7), the spectral function and the
+  linearised quasiparticle energy (Sec. 2.8, Eqs. 16-17).
 
 The Krylov method itself is not reproduced: the iterative solver reaches
 (up to rounding) the exact solution of each shifted system, and that solution
@@ -48,6 +51,11 @@ Readings of the paper taken here:
   chi_{GG'} v(q+G'), and Eq. 9 puts v(q+G) on the rows of W_bar (together they
   give W_bar = W - v with W = v (1 - chi v)^{-1}).  The +/- in Eq. 5 are the
   variations at the complex frequencies z and -z.
+* Eq. 10 on the imaginary axis (alpha = -1): Sigma(i w) = -(1/2pi) sum_j w_j
+  G(mu + i w'_j) W_bar(i (w'_j - w)) with the chemical potential mu in the
+  gap; its diagonal element in state n is the sum over the W_bar plane waves of
+  W_bar_{GG'} <t_G| G |t_G'> / Omega, t_G = exp(-i (q+G) . r) u_n.  The
+  renormalisation of Eq. 17 is read as Z = 1 / (1 - Re dSigma/dw).
 * The non-local part of the pseudopotential is taken in the fully separable
   form sum_p |beta_p> E_p <beta_p| with real E_p (any Hermitian coupling matrix
   between the projectors of an atom reduces to it by diagonalisation); the
@@ -319,3 +327,96 @@ def screened_correlation(eps: np.ndarray, v: np.ndarray, zero_rows=()) -> np.nda
         w[..., :, g] = 0.0
         w[..., g, g] = keep
     return w
+
+
+# ---------------------------------------------------------------------------
+# correlation self-energy on the imaginary axis, analytic continuation and spectral function
+# (Sec. 2.4, Eq. 10; Sec. 2.7; Sec. 2.8, Eqs. 15-17)
+# ---------------------------------------------------------------------------
+
+def green_pair_elements_spectral(evals: np.ndarray, evecs: np.ndarray, psi_n: np.ndarray, miller_k, miller_kmq,
+                                 m_gs, zs) -> np.ndarray:
+    """M[z][G][G'] = < t_G | G(z) | t_G' > with t_G = exp(-i (q+G) . r) u_n on the k-q basis and the
+    Green's function G(z) = (z - H_{k-q})^{-1} = sum_m u_m u_m^H / (z - eps_m) over all eigenstates
+    (Sec. 2.2): the pair of plane-wave factors that the real-space product G(r,r') W_bar(r,r') of Eq. 10
+    puts around G in a diagonal matrix element.  ``evecs`` columns: eigenvectors of H_{k-q}."""
+    zs = np.atleast_1d(np.asarray(zs, complex))
+    t = np.array([shifted_source(psi_n, miller_k, miller_kmq, -np.asarray(m, np.int64)) for m in m_gs])   # [G][pw]
+    c = evecs.conj().T @ t.T                                     # c[m][G] = <u_m | t_G>
+    out = np.empty((len(zs), len(m_gs), len(m_gs)), complex)
+    for j, z in enumerate(zs):
+        out[j] = (c.conj().T * (1.0 / (z - evals))[None, :]) @ c
+    return out
+
+
+def green_pair_elements_lu(h: np.ndarray, psi_n: np.ndarray, miller_k, miller_kmq, m_gs, z) -> np.ndarray:
+    """The same for one z by LU: x_G' = (z - H)^{-1} t_G' directly, then < t_G | x_G' >."""
+    t = np.array([shifted_source(psi_n, miller_k, miller_kmq, -np.asarray(m, np.int64)) for m in m_gs])
+    x = sla.solve(z * np.eye(h.shape[0]) - h, t.T)
+    return t.conj() @ x
+
+
+def sigma_c_imag(m_elem: np.ndarray, wbar_at: np.ndarray, weights, volume: float) -> np.ndarray:
+    """Diagonal matrix element of the correlation self-energy on the imaginary axis (Sec. 2.4, Eq. 10 with
+    alpha = -1): Sigma(i w_k) = -(1 / (2 pi Omega)) sum_j w_j sum_{G,G'} W_bar_{GG'}(i (w'_j - w_k)) M_{GG'}(mu + i w'_j),
+    the real-space product of G and W_bar written on the plane waves of both.
+    m_elem: [n_w'][G][G'] (green_pair_elements at the integration frequencies), wbar_at: [n_k][n_w'][G][G']
+    (W_bar at each difference), weights: [n_w'].  Returns [n_k]."""
+    w = np.asarray(weights, float)
+    return -np.einsum("j,kjgh,jgh->k", w, wbar_at, m_elem) / (2.0 * np.pi * volume)
+
+
+def aaa(zs, fs, tol: float = 1e-13, mmax: int = 100):
+    """Rational approximation by the adaptive Antoulas-Anderson algorithm (Sec. 2.7; Nakatsukasa, Sete and
+    Trefethen 2018): support points are added greedily where the current approximant is worst, the
+    barycentric weights are the right singular vector of the smallest singular value of the Loewner
+    matrix of the other points, until max |f - r| <= tol * max |f|.  Returns (z_sup, f_sup, w_sup) of
+    r(z) = sum_s w_s f_s / (z - z_s) / sum_s w_s / (z - z_s)."""
+    z = np.asarray(zs, complex)
+    f = np.asarray(fs, complex)
+    rest = np.ones(len(z), bool)
+    r = np.full(len(z), f.mean())
+    sup = []
+    w = np.zeros(0, complex)
+    for _ in range(min(mmax, len(z) - 1)):
+        err = np.where(rest, np.abs(f - r), -1.0)
+        j = int(np.argmax(err))
+        sup.append(j)
+        rest[j] = False
+        zs_, fs_ = z[sup], f[sup]
+        c = 1.0 / (z[rest][:, None] - zs_[None, :])
+        a = (f[rest][:, None] - fs_[None, :]) * c
+        w = np.linalg.svd(a)[2][-1].conj()
+        r = f.copy()
+        r[rest] = (c @ (w * fs_)) / (c @ w)
+        if np.abs(f - r).max() <= tol * np.abs(f).max():
+            break
+    return z[sup], f[sup], w
+
+
+def aaa_eval(z_sup, f_sup, w_sup, zs) -> np.ndarray:
+    """r(z) of an aaa() approximant (the support values at the support points)."""
+    zs = np.atleast_1d(np.asarray(zs, complex))
+    out = np.empty(len(zs), complex)
+    for i, z in enumerate(zs):
+        d = z - z_sup
+        hit = d == 0
+        if hit.any():
+            out[i] = f_sup[np.argmax(hit)]
+        else:
+            out[i] = np.sum(w_sup * f_sup / d) / np.sum(w_sup / d)
+    return out
+
+
+def spectral_function(omega, sigma, eps_n: float, delta: float) -> np.ndarray:
+    """A(w) = -Im Sigma^c(w) / (pi |w - eps_n - Sigma^c(w) - delta|^2) (Sec. 2.8, Eq. 16; delta = Sigma^x -
+    V^xc, the static part of Sigma^xc - V^xc, given)."""
+    s = np.asarray(sigma, complex)
+    return -s.imag / (np.pi * np.abs(np.asarray(omega, float) - eps_n - s - delta) ** 2)
+
+
+def quasiparticle(eps_n: float, sigma_at_eps: complex, dsigma_at_eps: complex, delta: float):
+    """Linearised quasiparticle energy (Sec. 2.8, Eq. 17): eps + Z (Re Sigma^c(eps) + delta) with the
+    renormalisation Z = 1 / (1 - Re dSigma^c/dw at eps).  Returns (eps_qp, Z)."""
+    z = 1.0 / (1.0 - np.real(dsigma_at_eps))
+    return eps_n + z * (np.real(sigma_at_eps) + delta), z

@@ -761,6 +761,7 @@ sgw_opts resolve_opts(const sgw_opts *in) {
     o.fft_planes = in->fft_planes;
     o.basis_blocks = in->basis_blocks;
     if (in->mixed_switch > 0) o.mixed_switch = in->mixed_switch;
+    o.shift_imag = in->shift_imag;
   }
   return o;
 }
@@ -805,7 +806,7 @@ Layout make_layout(const sgw_ham *h, int n_occ, int n_band, int n_pert, int n_om
   size_t off = 0;
   L.psi = take(off, 16ul * std::max(n_occ, 1) * npw);
   if (o.precision == SGW_MIXED && n_occ > 0) L.psplit = take(off, proj_split_bytes((int)npw, n_occ));
-  L.omega = take(off, 8ul * n_omega);
+  L.omega = take(off, 16ul * n_omega);  // omega, then the per-shift imaginary parts
   L.epsb = take(off, 8ul * std::max(n_band, 1));
   L.dvm = take(off, 12ul * std::max(n_pert, 1));
   L.pair = take(off, 4ul * L.S);
@@ -860,7 +861,13 @@ static sgw_status validate_solve(sgw_ctx *ctx, const sgw_ham *h_kq, int n_occ, c
   SGW_CHECK(o.precision == SGW_FP64 || o.solver != SGW_SOLVER_PER_SHIFT,
             "sternheimer_solve: the per-shift solver runs in FP64 only");
   SGW_CHECK(o.max_iter >= 1 && o.max_iter <= 100000, "sternheimer_solve: max_iter out of range");
-  SGW_CHECK(std::isfinite(eta) && eta != 0.0, "sternheimer_solve: eta must be finite and non-zero");
+  if (o.shift_imag) {
+    SGW_CHECK(std::isfinite(eta), "sternheimer_solve: eta not finite");
+    for (int j = 0; j < n_omega; ++j)
+      SGW_CHECK(std::isfinite(o.shift_imag[j]), "sternheimer_solve: shift_imag not finite");
+  } else {
+    SGW_CHECK(std::isfinite(eta) && eta != 0.0, "sternheimer_solve: eta must be finite and non-zero");
+  }
   SGW_CHECK(std::isfinite(tol) && tol > 0.0, "sternheimer_solve: tol must be positive");
   SGW_CHECK(std::isfinite(o.alpha_pv) && o.alpha_pv > 0.0, "sternheimer_solve: alpha_pv must be positive");
   SGW_CHECK(o.solver >= SGW_SOLVER_MULTISHIFT && o.solver <= SGW_SOLVER_TAIL, "sternheimer_solve: unknown solver");
@@ -1085,6 +1092,11 @@ static sgw_status multishift_solve(sgw_ctx *ctx, const sgw_ham *h_kq, int n_occ,
 
   // parameters
   SGW_HIP(hipMemcpyAsync((void *)Sx.omega, omega, sizeof(double) * n_omega, hipMemcpyHostToDevice, ctx->stream));
+  if (o.shift_imag) {
+    Sx.eta_j = Sx.omega + n_omega;
+    SGW_HIP(hipMemcpyAsync((void *)Sx.eta_j, o.shift_imag, sizeof(double) * n_omega, hipMemcpyHostToDevice,
+                           ctx->stream));
+  }
   SGW_HIP(hipMemcpyAsync((void *)Sx.eps_band, eps_v, sizeof(double) * n_band, hipMemcpyHostToDevice, ctx->stream));
   SGW_HIP(hipMemcpyAsync(d_dvm, dv_miller, sizeof(int32_t) * 3 * n_pert, hipMemcpyHostToDevice, ctx->stream));
   SGW_HIP(hipMemsetAsync(d_bad, 0, sizeof(int), ctx->stream));

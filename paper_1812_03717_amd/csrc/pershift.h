@@ -66,7 +66,8 @@ enum PcMode { PC_NONE = 0, PC_TETER = 1, PC_LEARNED = 2 };
 // launchers (pershift.hip)
 // slot parameters of system sys[a] (index (v*n_pert + p)*n_omega + j) into slot list[a]
 sgw_status ps_setup(sgw_ctx *ctx, const PsState &S, int n, const int32_t *list, const int32_t *sys,
-                    const double *eps_band, const double *omega, double eta, int n_pert, int n_omega);
+                    const double *eps_band, const double *omega, double eta, const double *eta_j, int n_pert,
+                    int n_omega);
 // x of slot list[a] from dpsi[out_index] (caller order)
 sgw_status ps_load_x(sgw_ctx *ctx, const PsState &S, int n, const int32_t *list, const double2 *dpsi);
 sgw_status ps_rhs(sgw_ctx *ctx, const PsState &S, int n, const int32_t *list, const double2 *src,

@@ -44,7 +44,7 @@ __device__ __forceinline__ void cdot_acc(double2 a, double2 b, double *acc) {
 
 __global__ void k_ps_setup(PsState S, int n, const int32_t *__restrict__ list, const int32_t *__restrict__ sys,
                            const double *__restrict__ eps_band, const double *__restrict__ omega, double eta,
-                           int n_pert, int n_omega) {
+                           const double *__restrict__ eta_j, int n_pert, int n_omega) {
   const int a = blockIdx.x * blockDim.x + threadIdx.x;
   if (a >= n) return;
   const int i = list[a], y = sys[a];
@@ -53,7 +53,7 @@ __global__ void k_ps_setup(PsState S, int n, const int32_t *__restrict__ list, c
   S.pair[i] = pair;
   S.eps[i] = eps_band[pair / n_pert];
   S.zr[i] = omega[j];
-  S.zi[i] = eta;
+  S.zi[i] = eta_j ? eta_j[j] : eta;
   S.status[i] = PS_RUNNING;
   S.iters[i] = 0;
 }
@@ -386,10 +386,11 @@ __global__ __launch_bounds__(kPsThreads) void k_ps_final(PsState S, const int32_
   } while (0)
 
 sgw_status ps_setup(sgw_ctx *ctx, const PsState &S, int n, const int32_t *list, const int32_t *sys,
-                    const double *eps_band, const double *omega, double eta, int n_pert, int n_omega) {
+                    const double *eps_band, const double *omega, double eta, const double *eta_j, int n_pert,
+                    int n_omega) {
   if (n <= 0) return SGW_OK;
   hipLaunchKernelGGL(k_ps_setup, dim3((n + 255) / 256), dim3(256), 0, ctx->stream, S, n, list, sys, eps_band, omega,
-                     eta, n_pert, n_omega);
+                     eta, eta_j, n_pert, n_omega);
   SGW_HIP(hipGetLastError());
   return SGW_OK;
 }
@@ -464,7 +465,7 @@ PsLayout ps_layout(const sgw_ham *h, int n_occ, int n_band, int n_pert, int n_om
   L.crow = B;
   size_t off = 0;
   L.psi = ps_take(off, 16ul * std::max(n_occ, 1) * npw);
-  L.omega = ps_take(off, 8ul * std::max(n_omega, 1));
+  L.omega = ps_take(off, 16ul * std::max(n_omega, 1));  // omega, then the per-shift imaginary parts
   L.epsb = ps_take(off, 8ul * std::max(n_band, 1));
   L.dvm = ps_take(off, 12ul * std::max(n_pert, 1));
   L.status = ps_take(off, 4ul * B);
@@ -566,6 +567,12 @@ sgw_status ps_solve(sgw_ctx *ctx, const PsProblem &P, const sgw_opts &o, const s
   int32_t *p_final = p_active + B, *p_bad = p_final + B;
 
   SGW_HIP(hipMemcpyAsync(d_omega, P.omega, sizeof(double) * P.n_omega, hipMemcpyHostToDevice, ctx->stream));
+  const double *d_eta_j = nullptr;
+  if (o.shift_imag) {
+    d_eta_j = d_omega + P.n_omega;
+    SGW_HIP(hipMemcpyAsync((void *)d_eta_j, o.shift_imag, sizeof(double) * P.n_omega, hipMemcpyHostToDevice,
+                           ctx->stream));
+  }
   SGW_HIP(hipMemcpyAsync(d_epsb, P.eps_v, sizeof(double) * P.n_band, hipMemcpyHostToDevice, ctx->stream));
   SGW_HIP(hipMemcpyAsync(d_dvm, P.dv_miller, sizeof(int32_t) * 3 * P.n_pert, hipMemcpyHostToDevice, ctx->stream));
   SGW_HIP(hipMemsetAsync(d_bad, 0, sizeof(int), ctx->stream));
@@ -600,7 +607,8 @@ sgw_status ps_solve(sgw_ctx *ctx, const PsProblem &P, const sgw_opts &o, const s
       SGW_HIP(hipMemcpyAsync(d_fill, p_fill, sizeof(int32_t) * nfill, hipMemcpyHostToDevice, ctx->stream));
       SGW_HIP(hipMemcpyAsync(d_sys, p_sys, sizeof(int32_t) * nfill, hipMemcpyHostToDevice, ctx->stream));
       SGW_HIP(hipMemcpyAsync(d_pairs, p_pairs, sizeof(int32_t) * nfill, hipMemcpyHostToDevice, ctx->stream));
-      if ((st = ps_setup(ctx, S, nfill, d_fill, d_sys, d_epsb, d_omega, P.eta, P.n_pert, P.n_omega)) != SGW_OK)
+      if ((st = ps_setup(ctx, S, nfill, d_fill, d_sys, d_epsb, d_omega, P.eta, d_eta_j, P.n_pert, P.n_omega)) !=
+          SGW_OK)
         return st;
       if ((st = rhs_source(ctx, h, P.h_k, nfill, d_pairs, P.n_pert, d_dvm, P.psi_v, P.h_k->n_pw, Y, npw)) != SGW_OK)
         return st;

@@ -237,7 +237,7 @@ __global__ __launch_bounds__(kLzThreads) void k_lanczos(SolverState S, const int
   double rmax = 0.0;
   for (int j = threadIdx.x; j < S.n_omega; j += kLzThreads) {
     const long idx = (long)slot * S.n_omega + j;
-    double2 rho = make_double2(ak - S.omega[j], -S.eta);
+    double2 rho = make_double2(ak - S.omega[j], -(S.eta_j ? S.eta_j[j] : S.eta));
     if (k > 0) {
       const double2 rp = S.rho[idx];
       const double d = bk * bk / (rp.x * rp.x + rp.y * rp.y);
@@ -304,7 +304,7 @@ __global__ void k_tridiag(SolverState S, const int32_t *__restrict__ flist, int 
   const long base = (long)f * S.kmax * nw + j;
   const double *al = S.alpha_t + (long)slot * S.kmax;
   const double *be = S.beta + (long)slot * (S.kmax + 1);
-  const double zr = S.omega[j], zi = S.eta;
+  const double zr = S.omega[j], zi = S.eta_j ? S.eta_j[j] : S.eta;
   double2 dprev = make_double2(0.0, 0.0), cprev = make_double2(0.0, 0.0);
   // the recurrence's inputs (alpha, beta) and, going back, its stored pivots are loaded kTriBatch
   // steps at a time, ahead of the dependent arithmetic
@@ -469,7 +469,7 @@ __global__ __launch_bounds__(kRowThreads) void k_residual(SolverState S, const i
   const double2 *ax = AX + (long)fj * npw;  // H x + alpha P_occ x
   const double2 *b = S.bvec + (long)slot * npw;
   const double eps = S.eps[slot];
-  const double zr = S.omega[j], zi = S.eta;
+  const double zr = S.omega[j], zi = S.eta_j ? S.eta_j[j] : S.eta;
   double2 *out = dpsi + ((long)pair * S.n_omega + j) * npw;
   double acc[3] = {0.0, 0.0, 0.0};
   const double er = eps + zr;

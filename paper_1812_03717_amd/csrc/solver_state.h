@@ -47,6 +47,7 @@ struct SolverState {
   const double *eps_band;    // [n_band]
   const double *omega;       // [n_omega]
   double eta;
+  const double *eta_j = nullptr;  // [n_omega] per-shift imaginary parts, or NULL: eta for all
   double alpha;              // coefficient of P_occ
   double tol_int;            // stop when every estimated residual is below this
 };

@@ -61,7 +61,8 @@ class sgw_opts(C.Structure):
                 ("guess", C.c_int32), ("tail_iter", C.c_int32), ("ps_max_iter", C.c_int32),
                 ("ps_slots", C.c_int32), ("mlp", C.c_void_p), ("hist_r", C.c_void_p), ("hist_x", C.c_void_p),
                 ("hist_iter", C.c_int32), ("mixed_switch", C.c_double), ("graph", C.c_int32),
-                ("fft_planes", C.c_int32), ("basis_blocks", C.c_int32)]
+                ("fft_planes", C.c_int32), ("basis_blocks", C.c_int32),
+                ("shift_imag", C.POINTER(C.c_double))]
 
 
 class sgw_problem(C.Structure):
@@ -376,6 +377,10 @@ def sgw_opts_default(**overrides):
             v = v.handle.value
         elif k in ("hist_r", "hist_x") and v is not None and hasattr(v, "data_ptr"):
             v = v.data_ptr()
+        elif k == "shift_imag" and v is not None:
+            arr = np.ascontiguousarray(np.asarray(v, np.float64))
+            o._shift_imag = arr  # keeps the host array alive with the options
+            v = arr.ctypes.data_as(C.POINTER(C.c_double))
         setattr(o, k, v)
     return o
 

@@ -518,12 +518,116 @@ def check_coulomb_truncation():
     assert abs(vt[2] - 2.0 * 4.0 * np.pi / (np.pi / r) ** 2) <= 1e-12 * vt[2]
 
 
+def check_green_pair_free_electron():
+    """V = V0 and a plane-wave state u_n = e_{G_n}: t_G = exp(-i(q+G).r) u_n is the plane wave G_n - G at
+    k-q, so <t_G| (z - H)^{-1} |t_G'> = delta_GG' / (z - 0.5|k-q+G_n-G|^2 - V0); with a diagonal
+    W_bar_GG(i nu) = c_G / (nu^2 + a^2) the self-energy of Eq. 10 is the explicit sum
+    -(1/(2 pi Omega)) sum_j w_j sum_G c_G / ((w'_j - w)^2 + a^2) / (mu + i w'_j - e_G), written out here."""
+    A, tau = cx.fcc_primitive(A_LAT)
+    B = cx.reciprocal(A)
+    k = np.array([0.011, -0.007, 0.019])
+    q = np.array([0.052, -0.031, 0.044])
+    mk, mkmq = cx.g_sphere(B, k, 2.5), cx.g_sphere(B, k - q, 2.5)
+    grid, v0 = (12, 12, 12), -0.3
+    w, u = so.eigh(so.hamiltonian(mkmq, B, k - q, np.full(grid, v0)))
+    n_idx = 3
+    psi = np.zeros(len(mk), complex)
+    psi[n_idx] = 1.0
+    zs = np.array([0.1 + 0.05j, 0.1 + 0.4j, 0.1 - 0.3j])
+    mel = so.green_pair_elements_spectral(w, u, psi, mk, mkmq, M_PS, zs)
+    index = {tuple(m): i for i, m in enumerate(mkmq)}
+    e = []
+    for mp in M_PS:
+        g = index[tuple(mk[n_idx] - mp)]
+        kg = (mkmq[g] + 0.0) @ B + (k - q)
+        e.append(0.5 * kg @ kg + v0)
+    e = np.array(e)
+    for j, z in enumerate(zs):
+        assert np.allclose(mel[j], np.diag(1.0 / (z - e)), rtol=0, atol=1e-13 * np.abs(1.0 / (z - e)).max())
+    mu, a = 0.1, 0.7
+    c = np.array([0.9, 0.5, 1.3, 0.2])
+    wp = np.linspace(-3.0, 3.0, 41)
+    wq = np.full(wp.size, wp[1] - wp[0])
+    wout = np.array([0.0, 0.45, -1.2])
+    m_int = so.green_pair_elements_spectral(w, u, psi, mk, mkmq, M_PS, mu + 1j * wp)
+    wbar_at = np.zeros((len(wout), len(wp), 4, 4), complex)
+    for kk, wo in enumerate(wout):
+        for j, x in enumerate(wp):
+            wbar_at[kk, j] = np.diag(c / ((x - wo) ** 2 + a * a))
+    omega = so.cell_volume(B)
+    sig = so.sigma_c_imag(m_int, wbar_at, wq, omega)
+    for kk, wo in enumerate(wout):
+        ref = -sum(wq[j] * np.sum(c / ((wp[j] - wo) ** 2 + a * a) / (mu + 1j * wp[j] - e))
+                   for j in range(len(wp))) / (2 * np.pi * omega)
+        assert abs(sig[kk] - ref) <= 1e-13 * abs(ref), (sig[kk], ref)
+
+
+def check_green_pair_routes():
+    """<t_G| G(z) |t_G'> by the sum over all eigenstates against LU solves, on the small random problem
+    (k - q basis from q -> -q), and G(z)^H = G(conj z)."""
+    P = _small_problem()
+    h = P["h_kq"]
+    zs = [0.2 + 0.05j, -0.4 + 0.3j]
+    mel = so.green_pair_elements_spectral(P["wq"], P["uq"], P["psi_k"][1], P["mk"], P["mkq"], M_PS, zs)
+    for j, z in enumerate(zs):
+        ref = so.green_pair_elements_lu(h, P["psi_k"][1], P["mk"], P["mkq"], M_PS, z)
+        assert np.abs(mel[j] - ref).max() <= 1e-11 * np.abs(ref).max()
+    melc = so.green_pair_elements_spectral(P["wq"], P["uq"], P["psi_k"][1], P["mk"], P["mkq"], M_PS, np.conj(zs))
+    assert np.abs(np.conj(np.swapaxes(mel, 1, 2)) - melc).max() <= 1e-12 * np.abs(mel).max()
+    # Eq. 10's contraction is the quadratic form sum_m (c_m^H W c_m) / (z - eps_m) of the pair amplitudes
+    # c_m(G) = <u_m | t_G> for a Hermitian (complex) W_bar
+    rng = np.random.default_rng(8)
+    x = rng.standard_normal((4, 4)) + 1j * rng.standard_normal((4, 4))
+    wb = x + x.conj().T
+    t = np.array([so.shifted_source(P["psi_k"][1], P["mk"], P["mkq"], -mp) for mp in M_PS])
+    c = P["uq"].conj().T @ t.T                                # [m][G]
+    vol = so.cell_volume(P["B"])
+    for j, z in enumerate(zs):
+        quad = np.einsum("mg,gh,mh->m", c.conj(), wb, c)
+        ref = -np.sum(quad / (z - P["wq"])) / (2 * np.pi * vol)
+        sig = so.sigma_c_imag(mel[j:j + 1], wb[None, None], [1.0], vol)[0]
+        assert abs(sig - ref) <= 1e-12 * abs(ref)
+
+
+def check_aaa_rational():
+    """A rational function with four poles below the real axis, sampled on the imaginary axis, is
+    reproduced by AAA on the real axis (its continuation) to 1e-8, with at most a few more support
+    points than its degree; constants come back exactly."""
+    p = np.array([0.3 - 0.05j, -0.8 - 0.1j, 1.5 - 0.2j, 2.2 - 0.08j])
+    a = np.array([0.4, 1.1, -0.6, 0.3])
+    f = lambda z: np.sum(a[None, :] / (np.asarray(z, complex)[:, None] - p[None, :]), axis=1)
+    zi = 1j * np.linspace(0.02, 4.0, 60)
+    zs, fs, ws = so.aaa(zi, f(zi), tol=1e-13)
+    assert len(zs) <= 8
+    zr = np.linspace(-2.0, 3.0, 101) + 0.01j
+    err = np.abs(so.aaa_eval(zs, fs, ws, zr) - f(zr)).max() / np.abs(f(zr)).max()
+    assert err <= 1e-8, err
+    zc, fc, wc = so.aaa(zi, np.full(zi.size, 2.5 - 1j))
+    assert np.allclose(so.aaa_eval(zc, fc, wc, zr), 2.5 - 1j, rtol=1e-14, atol=0)
+
+
+def check_spectral_and_quasiparticle():
+    """A constant Sigma = s_r + i s_i (s_i < 0) gives a Lorentzian of unit weight centred at
+    eps + s_r + delta; a linear Sigma(w) = s0 + s1 (w - eps) gives the root of w - eps - Sigma(w) - delta
+    = 0, eps + (s0 + delta) / (1 - s1), as the linearised quasiparticle energy, with Z = 1 / (1 - s1)."""
+    eps, delta, sr, si = 0.2, -0.05, 0.13, -0.02
+    w = np.linspace(-40.0, 40.0, 800001)
+    a = so.spectral_function(w, np.full(w.size, sr + 1j * si), eps, delta)
+    assert abs(np.trapezoid(a, w) - 1.0) <= 2e-3
+    assert abs(w[np.argmax(a)] - (eps + sr + delta)) <= 1e-4
+    s0, s1 = 0.07 - 0.01j, -0.35
+    eq, z = so.quasiparticle(eps, s0, s1, delta)
+    assert abs(eq - (eps + (s0.real + delta) / (1 - s1))) <= 1e-15 and abs(z - 1 / (1 - s1)) <= 1e-15
+    assert abs(eq - eps - (s0.real + s1 * (eq - eps)) - delta) <= 1e-15
+
+
 PINS = [check_kinetic_closed_form, check_hamiltonian_bruteforce, check_shifted_source_realspace,
         check_free_electron_closed_form, check_mpmath_tiny, check_routes_and_invariants,
         check_linearity_and_reciprocity, check_relative_residual_closed_form, check_condition_number_svd,
         check_green_free_electron, check_green_routes_and_symmetry, check_nonlocal_translation,
         check_nonlocal_secular, check_density_response_free_electron, check_density_response_routes,
-        check_coulomb_truncation]
+        check_coulomb_truncation, check_green_pair_free_electron, check_green_pair_routes, check_aaa_rational,
+        check_spectral_and_quasiparticle]
 
 
 @pytest.mark.parametrize("pin", PINS + [check_generator_ground_state], ids=lambda f: f.__name__)
@@ -573,6 +677,11 @@ _orig_chi_sol = so.density_response_from_solutions
 _orig_eps = so.dielectric
 _orig_wbar = so.screened_correlation
 _orig_coul = so.coulomb
+_orig_gpe = so.green_pair_elements_spectral
+_orig_sig = so.sigma_c_imag
+_orig_aaa = so.aaa
+_orig_spec_fn = so.spectral_function
+_orig_qp = so.quasiparticle
 
 
 def _chi_one_term(w, u, n, pk, ek, mk, mkq, mps, zs, vol):
@@ -641,6 +750,17 @@ MUTATIONS = {
     "coulomb_trunc_limit": ("coulomb", lambda qg, r_cut=0.0: np.where(
         np.einsum("gd,gd->g", np.asarray(qg, float), np.asarray(qg, float)) == 0, np.pi * r_cut ** 2,
         _orig_coul(qg, r_cut))),
+    "green_pair_resolvent_sign": ("green_pair_elements_spectral", lambda *a: -_orig_gpe(*a)),
+    "green_pair_transposed": ("green_pair_elements_spectral",
+                              lambda *a: np.swapaxes(_orig_gpe(*a), 1, 2)),
+    "sigma_sign": ("sigma_c_imag", lambda *a: -_orig_sig(*a)),
+    "sigma_no_volume": ("sigma_c_imag", lambda m, w, q, vol: _orig_sig(m, w, q, 1.0)),
+    "sigma_w_transposed": ("sigma_c_imag", lambda m, w, q, vol: _orig_sig(m, np.swapaxes(w, 2, 3), q, vol)),
+    "aaa_unconjugated_weights": ("aaa", lambda zs, fs, tol=1e-13, mmax=100: (lambda r: (r[0], r[1], np.conj(r[2])))(
+        _orig_aaa(zs, fs, tol, mmax))),
+    "spectral_sign": ("spectral_function", lambda *a: -_orig_spec_fn(*a)),
+    "qp_z_not_inverted": ("quasiparticle", lambda e, s, ds, d: (e + (1 - np.real(ds)) * (np.real(s) + d),
+                                                                 1 - np.real(ds))),
     "nl_conjugated": ("nonlocal_matrix", lambda b, e, rows=None: np.conj(_orig_nl(b, e, rows))),
     "nl_energy_dropped": ("nonlocal_matrix", lambda b, e, rows=None: _orig_nl(b, np.ones_like(e), rows)),
     "nl_energy_sign": ("nonlocal_matrix", lambda b, e, rows=None: _orig_nl(b, -np.asarray(e), rows)),
