@@ -345,6 +345,115 @@ def bench_batch(args, log):
     print(json.dumps(out), flush=True)
 
 
+def sigma_frequencies(n_int=32, n_out=12, h=0.25):
+    """Imaginary-axis meshes of the self-energy path: integration frequencies w'_j = h (j + 1/2),
+    j = -n_int/2 .. n_int/2 - 1 (midpoint rule, weight h each), outputs w_k = h k, k < n_out; the
+    differences w'_j - w_k all lie on the half-integer mesh h (m + 1/2), where W_bar is needed.
+    Returns (w_int, weights, w_out, nu, w_index)."""
+    j = np.arange(-(n_int // 2), n_int - n_int // 2)
+    w_int = h * (j + 0.5)
+    w_out = h * np.arange(n_out)
+    m = j[None, :] - np.arange(n_out)[:, None]
+    m_all = np.arange(m.min(), m.max() + 1)
+    return w_int, np.full(n_int, h), w_out, h * (m_all + 0.5), (m - m.min()).astype(np.int32)
+
+
+def bench_sigma(args, log, problem, ctx, dev):
+    """The correlation self-energy path of the top STATES bands on one GPU: W_bar on the imaginary-axis
+    mesh comes first, untimed (solves at +-i nu over all bands, density response, eps^-1); one step is
+    then the Green's function pair elements (multishift solves at mu + i w'_j for every state and
+    wave vector), the frequency convolution Sigma^c(i w_k), an AAA fit per state, the spectral
+    function on 2001 real frequencies and the quasiparticle energies.  `value` counts the pair-element
+    solves per second of the step."""
+    import torch
+    from paper_1812_03717_amd import sgw
+    p = problem
+    n_st = min(args.sigma, p.n_band)
+    max_iter = args.max_iter or (3500 if args.workload in ("si64", "si64nl") else 0)
+    kw = {"max_iter": max_iter} if max_iter else {}
+    w_int, q_int, w_out, nu, w_index = sigma_frequencies()
+    ws = sgw.Workspace(ctx)
+    # W_bar(i nu) from all bands, in chunks of 32 bands (untimed)
+    t = time.perf_counter()
+    nbc = min(32, p.n_band)
+    zero = np.zeros(len(nu))
+    chi = torch.empty((len(nu), p.n_pert, p.n_pert), dtype=torch.complex128, device=ctx.device)
+    for c0 in range(0, p.n_band, nbc):
+        nb = min(nbc, p.n_band - c0)
+        psi = dev.psi_v[c0:c0 + nb].contiguous()
+        sols = []
+        for sgn in (1.0, -1.0):
+            o = sgw.sgw_opts_default(shift_imag=sgn * nu, **kw)
+            st, x, _ = sgw.sternheimer_solve(ctx, dev.h_kq, dev.psi_occ_kq, dev.h_k, psi, dev.eps_v[c0:c0 + nb],
+                                             p.dv_miller, zero, 0.0, p.tol, opts=o, workspace=ws)
+            sols.append(x)
+        sgw.sgw_density_response(ctx, dev.h_kq, dev.psi_occ_kq, dev.h_k, psi, p.dv_miller, sols[0], sols[1], chi=chi,
+                                 accumulate=c0 > 0)
+        del sols
+        log(f"  W_bar: bands {c0}..{c0 + nb - 1} at +-i nu ({len(nu)} frequencies), status {st}")
+    _, _, wbar = sgw.sgw_screened_coulomb(ctx, dev.h_kq, dev.h_k, p.dv_miller, chi)
+    torch.cuda.synchronize()
+    log(f"W_bar on {len(nu)} imaginary frequencies: {time.perf_counter() - t:.1f} s (untimed)")
+    states = list(range(p.n_band - n_st, p.n_band))
+    psi_n = dev.psi_v[states[0]:].contiguous()
+    eps_n = np.asarray(p.eps_k[states], np.float64)
+    mu = 0.5 * (p.eps_kq[p.n_occ - 1] + p.eps_kq[p.n_occ])
+    opts = sgw.sgw_opts_default(**kw)
+    omega = np.linspace(-1.0, 1.0, 2001)
+    vol = float(abs(np.linalg.det(p.A)))
+    stage = {"pair_elements": [], "sigma_c": [], "aaa": [], "spectral": []}
+    n_ok = 0
+
+    def step():
+        nonlocal n_ok
+        t0 = time.perf_counter()
+        st, m, info = sgw.sgw_green_pair_elements(ctx, dev.h_kq, dev.h_k, psi_n, p.dv_miller, mu, w_int, p.tol,
+                                                  opts=opts, workspace=ws)
+        inf = sgw.info_to_numpy(info)
+        n_ok += int(np.count_nonzero((inf["flags"] & sgw.FLAG_CONVERGED) != 0))
+        t1 = time.perf_counter()
+        sig = sgw.sgw_sigma_c(ctx, m, q_int, wbar, w_index, vol).cpu().numpy()
+        t2 = time.perf_counter()
+        fits = [sgw.sgw_aaa_fit(1j * w_out, sig[n], tol=1e-12) for n in range(n_st)]
+        t3 = time.perf_counter()
+        _, a = sgw.sgw_spectral_function(ctx, fits, omega, 1e-3, eps_n, np.zeros(n_st))
+        qp = [sgw.sgw_quasiparticle(f, e, 0.0) for f, e in zip(fits, eps_n)]
+        torch.cuda.synchronize()
+        t4 = time.perf_counter()
+        for k, dt in zip(stage, (t1 - t0, t2 - t1, t3 - t2, t4 - t3)):
+            stage[k].append(dt)
+        log(f"  pair elements {t1 - t0:.3f} s (status {st}, iters max {inf['iters'].max()}), Sigma^c {t2 - t1:.4f} s, "
+            f"AAA {t3 - t2:.4f} s, A(w) + E_qp {t4 - t3:.4f} s")
+        return sig, qp
+
+    for _ in range(args.warmup):
+        step()
+    for v in stage.values():
+        v.clear()
+    n_ok = 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        sig, qp = step()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    n_solves = n_st * p.n_pert * len(w_int)
+    log(f"timed: {args.steps} steps in {el:.3f} s; converged {n_ok}/{n_solves * args.steps}")
+    print(json.dumps({
+        "metric": "Green's function pair-element solves/s (state x wave vector x imaginary frequency) through "
+                  "Sigma^c, AAA continuation and A(w)",
+        "value": round(n_ok / el, 1), "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(1e3 * el / args.steps, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": WORKLOADS[args.workload] + f"; Sigma^c of the top {n_st} bands: pair elements at "
+                   f"mu + i w' ({len(w_int)} midpoint frequencies, h 0.25 Ha), W_bar at {len(nu)} frequencies "
+                   f"(untimed), Sigma^c at {len(w_out)} frequencies, AAA, A(w) on 2001 points",
+                   "solves_per_step": n_solves, "max_iter": max_iter or 600},
+        "stage_ms_per_step": {k: round(1e3 * sum(v) / args.steps, 3) for k, v in stage.items()},
+        "sigma_c_top_state_iw0": [float(sig[-1, 0].real), float(sig[-1, 0].imag)],
+        "z_factors": [round(z, 4) for _, z in qp]}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -366,6 +475,9 @@ def main():
     ap.add_argument("--dielectric", type=int, default=0, metavar="BANDS",
                     help="time the screening path instead: solves at z and -z for BANDS bands at a time, the "
                          "density response accumulated over the band chunks, eps, eps^-1 and W_bar")
+    ap.add_argument("--sigma", type=int, default=0, metavar="STATES",
+                    help="time the self-energy path of the top STATES bands instead (W_bar untimed): Green's "
+                         "function pair elements, Sigma^c on the imaginary axis, AAA, A(w), E_qp")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 5 device-to-device copies of MIB MiB (HBM counter calibration) and exit")
     args = ap.parse_args()
@@ -406,6 +518,8 @@ def main():
     dev = DeviceProblem(ctx, problem)
     if args.dielectric:
         return bench_dielectric(args, log, problem, ctx, dev)
+    if args.sigma:
+        return bench_sigma(args, log, problem, ctx, dev)
     ws = sgw.Workspace(ctx)
     prec = sgw.MIXED if args.precision == "mixed" else sgw.FP64
     kw = dict(precision=prec)

@@ -399,6 +399,75 @@ sgw_status sternheimer_solve(sgw_ctx *ctx, const sgw_ham *h_kq, int n_occ, const
                              size_t workspace_bytes, sgw_c128 *dpsi, sgw_solve_info *info);
 
 /*
+ * Pair elements of the Green's function for the correlation self-energy (Sec. 2.4, Eq. 10; Sec. 2.2):
+ *     m[n][j][g][h] = < t_{n,g} | (z_j - H)^{-1} | t_{n,h} >,   t_{n,g} = exp(-i (q+G_g) . r) u_n,
+ * z_j = mu + i w_imag[j] (mu: the chemical potential, in the gap), q = k of h_k minus k of h_kmq,
+ * G_g = g_miller[g] on h_kmq's reciprocal lattice.  All z_j of one (n, h) share one Krylov space (the
+ * multishift solver with per-shift imaginary parts, no occupied projector, zero band energy: the
+ * solve of (H - z_j) x = -t_{n,h}); the bra is a plane-wave contraction on the FP64 matrix cores.
+ *   psi_n    device [n_band][n_pw of h_k] states u_n at k (caller's order)
+ *   g_miller host [n_g][3], w_imag host [n_freq] (finite)
+ *   opts     solver options (NULL: defaults; its shift_imag is replaced by w_imag)
+ *   m_out    device [n_band][n_freq][n_g][n_g] out;  info  device [n_band][n_g][n_freq] or NULL
+ *   workspace device, >= sgw_green_pair_workspace_size bytes (same sizes and opts), 256-byte aligned:
+ *            the solver's workspace, the solutions (n_band n_g n_freq vectors of h_kmq's basis), the
+ *            right-hand sides and the overlaps; nothing is allocated
+ * Returns the solve's status (SGW_NOT_CONVERGED when a solve missed tol; m_out is still written),
+ * SGW_ERR_WORKSPACE for a missing, short or misaligned workspace.
+ */
+sgw_status sgw_green_pair_workspace_size(sgw_ctx *ctx, const sgw_ham *h_kmq, int n_band, int n_g, int n_freq,
+                                         const sgw_opts *opts, size_t *bytes);
+sgw_status sgw_green_pair_elements(sgw_ctx *ctx, const sgw_ham *h_kmq, const sgw_ham *h_k, int n_band,
+                                   const sgw_c128 *psi_n, int n_g, const int32_t *g_miller, double mu, int n_freq,
+                                   const double *w_imag, double tol, const sgw_opts *opts, void *workspace,
+                                   size_t workspace_bytes, sgw_c128 *m_out, sgw_solve_info *info);
+
+/*
+ * Diagonal correlation self-energy on the imaginary axis (Sec. 2.4, Eq. 10 with alpha = -1):
+ *     sigma[n][k] = -(1 / (2 pi volume)) sum_j weights[j] sum_{g,h} wbar[w_index[k][j]][g][h] m_elem[n][j][g][h]
+ * the integration frequencies w'_j of m_elem (sgw_green_pair_elements) weighted by weights[j], W_bar
+ * (sgw_screened_coulomb) taken at i (w'_j - w_k) through w_index (host [n_out][n_freq], values
+ * < n_w).  volume: the unit cell's, bohr^3.
+ *   m_elem device [n_band][n_freq][n_g][n_g]; wbar device [n_w][n_g][n_g]; sigma device [n_band][n_out]
+ */
+sgw_status sgw_sigma_c(sgw_ctx *ctx, int n_band, int n_g, int n_freq, const sgw_c128 *m_elem, const double *weights,
+                       int n_w, const sgw_c128 *wbar, int n_out, const int32_t *w_index, double volume,
+                       sgw_c128 *sigma);
+
+/*
+ * Rational approximation of f at the points z by the adaptive Antoulas-Anderson algorithm (Sec. 2.7):
+ * support points are added where the approximant is worst, the barycentric weights are the right
+ * singular vector of the smallest singular value of the Loewner matrix of the other points (one-sided
+ * Jacobi SVD), until max |f - r| <= tol max |f| or max_terms (at most n - 1) support points;
+ *     r(x) = sum_s w_s f_s / (x - z_s) / sum_s w_s / (x - z_s).
+ * Host arrays: z, f [n] in (distinct, finite); z_sup, f_sup, w_sup [max_terms] out; *n_sup out.
+ * Runs in the calling thread (a few small SVDs); no GPU work.
+ */
+sgw_status sgw_aaa_fit(int n, const sgw_c128 *z, const sgw_c128 *f, double tol, int max_terms, int *n_sup,
+                       sgw_c128 *z_sup, sgw_c128 *f_sup, sgw_c128 *w_sup);
+
+/*
+ * Spectral function of each state (Sec. 2.8, Eq. 16) on real frequencies from its continued
+ * self-energy: Sigma^c(w + i broad) = r_n(w + i broad) of the state's AAA approximant and
+ *     A_n(w) = -Im Sigma^c(w) / (pi |w - eps_n - Sigma^c(w) - delta_n|^2),
+ * delta_n = Sigma^x_n - V^xc_n (the static part, given).
+ *   n_sup host [n_band]; z_sup, f_sup, w_sup host [n_band][n_sup_max]; omega host [n_omega];
+ *   eps_n, delta host [n_band]; sigma device [n_band][n_omega] out (or NULL); a device [n_band][n_omega]
+ *   out (or NULL)
+ */
+sgw_status sgw_spectral_function(sgw_ctx *ctx, int n_band, int n_sup_max, const int32_t *n_sup,
+                                 const sgw_c128 *z_sup, const sgw_c128 *f_sup, const sgw_c128 *w_sup, int n_omega,
+                                 const double *omega, double broad, const double *eps_n, const double *delta,
+                                 sgw_c128 *sigma, double *a);
+
+/*
+ * Linearised quasiparticle energy (Sec. 2.8, Eq. 17) from a state's approximant r:
+ * eps_qp = eps_n + Z (Re r(eps_n) + delta), Z = 1 / (1 - Re r'(eps_n)).  Host only.
+ */
+sgw_status sgw_quasiparticle(int n_sup, const sgw_c128 *z_sup, const sgw_c128 *f_sup, const sgw_c128 *w_sup,
+                             double eps_n, double delta, double *eps_qp, double *z_factor);
+
+/*
  * Green's function columns (Sec. 2.2, Eqs. 2-3): for every column index c < n_col and frequency
  * j < n_omega, the solution of
  *

@@ -17,7 +17,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libsgw.so")
-SOURCES = ["api.hip", "hx.hip", "solver.hip", "projector.hip", "pershift.hip", "mlp.hip", "dielectric.hip"]
+SOURCES = ["api.hip", "hx.hip", "solver.hip", "projector.hip", "pershift.hip", "mlp.hip", "dielectric.hip",
+           "selfenergy.hip"]
 ARCH = "gfx950"
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -39,7 +39,8 @@ EXPORTED = [
     "sgw_mlp_train_step", "sgw_operator_columns", "sgw_mlp_rows", "sternheimer_batch_workspace_size",
     "sternheimer_solve_batch", "sgw_autotune", "sgw_precond_values", "sgw_apply_h_noalloc",
     "sgw_green_workspace_size", "sgw_green_solve", "sgw_ham_set_nonlocal", "sgw_ham_nproj",
-    "sgw_density_response", "sgw_coulomb", "sgw_screened_coulomb",
+    "sgw_density_response", "sgw_coulomb", "sgw_screened_coulomb", "sgw_green_pair_workspace_size",
+    "sgw_green_pair_elements", "sgw_sigma_c", "sgw_aaa_fit", "sgw_spectral_function", "sgw_quasiparticle",
 ]
 
 
@@ -106,6 +107,15 @@ def load_library(path: str = LIB_PATH):
                                  dbl, C.c_int, vp],
         "sgw_coulomb": [vp, vp, C.c_int, C.POINTER(i32), dbl, C.POINTER(dbl)],
         "sgw_screened_coulomb": [vp, vp, vp, C.c_int, C.POINTER(i32), dbl, C.c_int, vp, vp, vp, vp],
+        "sgw_green_pair_workspace_size": [vp, vp, C.c_int, C.c_int, C.c_int, C.POINTER(sgw_opts), C.POINTER(sz)],
+        "sgw_green_pair_elements": [vp, vp, vp, C.c_int, vp, C.c_int, C.POINTER(i32), dbl, C.c_int, C.POINTER(dbl),
+                                    dbl, C.POINTER(sgw_opts), vp, sz, vp, vp],
+        "sgw_sigma_c": [vp, C.c_int, C.c_int, C.c_int, vp, C.POINTER(dbl), C.c_int, vp, C.c_int, C.POINTER(i32), dbl,
+                        vp],
+        "sgw_aaa_fit": [C.c_int, vp, vp, dbl, C.c_int, C.POINTER(C.c_int), vp, vp, vp],
+        "sgw_spectral_function": [vp, C.c_int, C.c_int, C.POINTER(i32), vp, vp, vp, C.c_int, C.POINTER(dbl), dbl,
+                                  C.POINTER(dbl), C.POINTER(dbl), vp, vp],
+        "sgw_quasiparticle": [C.c_int, vp, vp, vp, dbl, dbl, C.POINTER(dbl), C.POINTER(dbl)],
         "sgw_opts_default": [C.POINTER(sgw_opts)],
         "sternheimer_workspace_size": [vp, vp, C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(sgw_opts),
                                        C.POINTER(sz)],
@@ -366,6 +376,91 @@ def sgw_screened_coulomb(ctx, h_kq, h_k, dv_miller, chi, r_cut=0.0):
                                                dvm.ctypes.data_as(C.POINTER(C.c_int32)), float(r_cut), n_omega,
                                                _ptr(chi), _ptr(eps), _ptr(inv), _ptr(wbar)))
     return eps, inv, wbar
+
+
+def _dptr(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def sgw_green_pair_elements(ctx, h_kmq, h_k, psi_n, g_miller, mu, w_imag, tol, opts=None, workspace=None):
+    """(status, m [n_band][n_freq][n_g][n_g], info): <t_g| (mu + i w_j - H)^{-1} |t_h>, t_g = exp(-i(q+G_g).r) u_n."""
+    import torch
+    _require(psi_n, torch.complex128, ctx.device, (psi_n.shape[0], h_k.n_pw), "psi_n")
+    g = np.ascontiguousarray(np.asarray(g_miller, np.int32).reshape(-1, 3))
+    w = np.ascontiguousarray(np.asarray(w_imag, np.float64))
+    n_band, n_g, n_freq = int(psi_n.shape[0]), int(g.shape[0]), int(w.shape[0])
+    lib = load_library()
+    o = C.byref(opts) if opts is not None else None
+    n = C.c_size_t()
+    _check(lib.sgw_green_pair_workspace_size(ctx.handle, h_kmq.handle, n_band, n_g, n_freq, o, C.byref(n)))
+    ws = (workspace or Workspace(ctx)).get(int(n.value))
+    m = torch.empty((n_band, n_freq, n_g, n_g), dtype=torch.complex128, device=ctx.device)
+    info = torch.empty(n_band * n_g * n_freq * INFO_DTYPE.itemsize, dtype=torch.uint8, device=ctx.device)
+    st = _check(lib.sgw_green_pair_elements(ctx.handle, h_kmq.handle, h_k.handle, n_band, _ptr(psi_n), n_g,
+                                            g.ctypes.data_as(C.POINTER(C.c_int32)), float(mu), n_freq, _dptr(w),
+                                            float(tol), o, _ptr(ws), C.c_size_t(ws.numel()), _ptr(m), _ptr(info)))
+    return st, m, info
+
+
+def sgw_sigma_c(ctx, m_elem, weights, wbar, w_index, volume):
+    """sigma [n_band][n_out] on the device; w_index host int [n_out][n_freq] into wbar's frequencies."""
+    import torch
+    n_band, n_freq, n_g = int(m_elem.shape[0]), int(m_elem.shape[1]), int(m_elem.shape[2])
+    _require(m_elem, torch.complex128, ctx.device, (n_band, n_freq, n_g, n_g), "m_elem")
+    _require(wbar, torch.complex128, ctx.device, (wbar.shape[0], n_g, n_g), "wbar")
+    idx = np.ascontiguousarray(np.asarray(w_index, np.int32))
+    wq = np.ascontiguousarray(np.asarray(weights, np.float64))
+    if idx.ndim != 2 or idx.shape[1] != n_freq or wq.shape != (n_freq,):
+        raise ValueError("w_index must be [n_out][n_freq] and weights [n_freq]")
+    sigma = torch.empty((n_band, idx.shape[0]), dtype=torch.complex128, device=ctx.device)
+    _check(load_library().sgw_sigma_c(ctx.handle, n_band, n_g, n_freq, _ptr(m_elem), _dptr(wq), int(wbar.shape[0]),
+                                      _ptr(wbar), int(idx.shape[0]), idx.ctypes.data_as(C.POINTER(C.c_int32)),
+                                      float(volume), _ptr(sigma)))
+    return sigma
+
+
+def sgw_aaa_fit(z, f, tol=1e-13, max_terms=100):
+    """(z_sup, f_sup, w_sup) numpy complex arrays of the AAA approximant (host computation)."""
+    z = np.ascontiguousarray(np.asarray(z, np.complex128))
+    f = np.ascontiguousarray(np.asarray(f, np.complex128))
+    mt = int(min(max_terms, len(z) - 1))
+    zs, fs, ws = (np.zeros(max(mt, 1), np.complex128) for _ in range(3))
+    n = C.c_int()
+    _check(load_library().sgw_aaa_fit(len(z), z.ctypes.data_as(C.c_void_p), f.ctypes.data_as(C.c_void_p),
+                                      float(tol), mt, C.byref(n), zs.ctypes.data_as(C.c_void_p),
+                                      fs.ctypes.data_as(C.c_void_p), ws.ctypes.data_as(C.c_void_p)))
+    return zs[:n.value].copy(), fs[:n.value].copy(), ws[:n.value].copy()
+
+
+def sgw_spectral_function(ctx, fits, omega, broad, eps_n, delta):
+    """(sigma [n_band][n_omega], a [n_band][n_omega]) device tensors from per-state AAA fits."""
+    import torch
+    n_band = len(fits)
+    nmax = max(len(f[0]) for f in fits)
+    zs, fs, ws = (np.zeros((n_band, nmax), np.complex128) for _ in range(3))
+    ns = np.zeros(n_band, np.int32)
+    for i, (a, b, c) in enumerate(fits):
+        ns[i] = len(a)
+        zs[i, :len(a)], fs[i, :len(a)], ws[i, :len(a)] = a, b, c
+    om = np.ascontiguousarray(np.asarray(omega, np.float64))
+    e = np.ascontiguousarray(np.asarray(eps_n, np.float64))
+    d = np.ascontiguousarray(np.asarray(delta, np.float64))
+    sigma = torch.empty((n_band, len(om)), dtype=torch.complex128, device=ctx.device)
+    a = torch.empty((n_band, len(om)), dtype=torch.float64, device=ctx.device)
+    _check(load_library().sgw_spectral_function(ctx.handle, n_band, nmax, ns.ctypes.data_as(C.POINTER(C.c_int32)),
+                                                zs.ctypes.data_as(C.c_void_p), fs.ctypes.data_as(C.c_void_p),
+                                                ws.ctypes.data_as(C.c_void_p), len(om), _dptr(om), float(broad),
+                                                _dptr(e), _dptr(d), _ptr(sigma), _ptr(a)))
+    return sigma, a
+
+
+def sgw_quasiparticle(fit, eps_n, delta):
+    zs, fs, ws = (np.ascontiguousarray(x, np.complex128) for x in fit)
+    e, z = C.c_double(), C.c_double()
+    _check(load_library().sgw_quasiparticle(len(zs), zs.ctypes.data_as(C.c_void_p), fs.ctypes.data_as(C.c_void_p),
+                                            ws.ctypes.data_as(C.c_void_p), float(eps_n), float(delta), C.byref(e),
+                                            C.byref(z)))
+    return e.value, z.value
 
 
 def sgw_opts_default(**overrides):

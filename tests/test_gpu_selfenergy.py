@@ -1,0 +1,214 @@
+"""GPU parity of the correlation self-energy path against the oracle: the Green's function pair
+elements (Sec. 2.2 with the plane-wave factors of Sec. 2.4, Eq. 10), the frequency convolution of
+Eq. 10, and the continued self-energy's spectral function (Sec. 2.7; Sec. 2.8, Eq. 16).
+
+* pair elements < t_G | G(mu + i w) | t_G' > from the library's multishift solves with per-shift
+  imaginary parts against the oracle's sum over all eigenstates: each solve carries a relative error
+  up to kappa * tol, so kappa * tol of the largest element, with kappa of H - z over the spectrum.
+* Sigma^c from given pair elements and W_bar: a contraction, 1e-13 relative.
+* the whole chain on a 2-atom cell at a seeded q: chi at i nu (solves at +-i nu through shift_imag),
+  W_bar, pair elements, Sigma^c(i w) against the oracle's chain from its own definitions; the errors
+  of the two solve stages add up, 1e-7 of the largest value.
+* the spectral function of an AAA fit of the library's Sigma^c against the oracle's evaluation of the
+  same fit: 1e-12 relative (barycentric sums in FP64).
+"""
+import numpy as np
+import pytest
+
+import oracle.sternheimer_oracle as so
+from synth import configs
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from tests.libutil import ensure_library
+    ensure_library()
+    from paper_1812_03717_amd import sgw
+    c = sgw.sgw_ctx_create(0)
+    yield c
+    torch.cuda.synchronize()
+
+
+@pytest.fixture(scope="module")
+def prob(ctx):
+    from paper_1812_03717_amd.workload import DeviceProblem
+    p = configs.small((1, 1, 1), n_omega=4, n_pert=5, seed=9300)
+    d = DeviceProblem(ctx, p)
+    h = so.hamiltonian(p.miller_kq, p.B, p.kqvec, p.v_grid)
+    w, u = so.eigh(h)
+    mu = 0.5 * (w[p.n_occ - 1] + w[p.n_occ])
+    return p, d, w, u, mu
+
+
+W_INT = np.array([-2.5, -1.0, -0.4, -0.1, 0.1, 0.4, 1.0, 2.5])       # integration frequencies w'_j (Ha)
+Q_INT = np.array([0.9, 0.6, 0.45, 0.3, 0.3, 0.45, 0.6, 0.9])         # their weights
+
+
+def _pair_tol(w, mu, freqs, tol):
+    return max(so.green_condition_number(w, mu + 1j * f) for f in freqs) * tol
+
+
+def test_pair_elements_match_oracle(ctx, prob):
+    from paper_1812_03717_amd import sgw
+    p, d, w, u, mu = prob
+    tol = 1e-11
+    st, m, info = sgw.sgw_green_pair_elements(ctx, d.h_kq, d.h_k, d.psi_v, p.dv_miller, mu, W_INT, tol)
+    assert st == sgw.SGW_OK, sgw.load_library().sgw_last_error()
+    inf = sgw.info_to_numpy(info)
+    assert np.all(inf["flags"] & sgw.FLAG_CONVERGED) and inf["relres"].max() <= tol
+    m = m.cpu().numpy()
+    assert m.shape == (p.n_band, len(W_INT), p.n_pert, p.n_pert)
+    bound = _pair_tol(w, mu, W_INT, tol)
+    for n in range(p.n_band):
+        ref = so.green_pair_elements_spectral(w, u, p.psi_k[n], p.miller_k, p.miller_kq, p.dv_miller, mu + 1j * W_INT)
+        err = np.abs(m[n] - ref).max() / np.abs(ref).max()
+        print("band", n, "pair elements rel err", err, "bound", bound, flush=True)
+        assert err <= max(bound, 1e-12)
+    # G(z)^H = G(z*): M(mu - i w)[G][G'] = conj(M(mu + i w)[G'][G])
+    half = len(W_INT) // 2
+    mirror = np.conj(np.swapaxes(m[:, ::-1][:, :half], 2, 3))
+    assert np.abs(m[:, :half] - mirror).max() <= 10 * bound * np.abs(m).max()
+
+
+def test_sigma_contraction(ctx):
+    from paper_1812_03717_amd import sgw
+    rng = np.random.default_rng(31)
+    n_band, n_g, n_freq, n_w, n_out = 3, 7, 6, 5, 4
+    m = rng.standard_normal((n_band, n_freq, n_g, n_g)) + 1j * rng.standard_normal((n_band, n_freq, n_g, n_g))
+    wb = rng.standard_normal((n_w, n_g, n_g)) + 1j * rng.standard_normal((n_w, n_g, n_g))
+    q = rng.uniform(0.1, 1.0, n_freq)
+    idx = rng.integers(0, n_w, (n_out, n_freq)).astype(np.int32)
+    vol = 270.0
+    sig = sgw.sgw_sigma_c(ctx, torch.from_numpy(m).to(ctx.device), q, torch.from_numpy(wb).to(ctx.device), idx,
+                          vol).cpu().numpy()
+    for n in range(n_band):
+        ref = so.sigma_c_imag(m[n], wb[idx], q, vol)
+        assert np.abs(sig[n] - ref).max() <= 1e-13 * np.abs(ref).max()
+    with pytest.raises(sgw.SgwError):
+        sgw.sgw_sigma_c(ctx, torch.from_numpy(m).to(ctx.device), q, torch.from_numpy(wb).to(ctx.device),
+                        idx + n_w, vol)
+    with pytest.raises(sgw.SgwError):
+        sgw.sgw_sigma_c(ctx, torch.from_numpy(m).to(ctx.device), q, torch.from_numpy(wb).to(ctx.device), idx, 0.0)
+
+
+def test_sigma_chain_and_spectral_function(ctx, prob):
+    from paper_1812_03717_amd import sgw
+    p, d, w, u, mu = prob
+    vol = so.cell_volume(p.B)
+    w_out = np.linspace(0.05, 3.0, 12)                                  # Sigma^c(i w_k)
+    diff = W_INT[None, :] - w_out[:, None]
+    nus, inv = np.unique(np.round(diff, 12), return_inverse=True)
+    idx = inv.reshape(diff.shape).astype(np.int32)
+    assert np.all(nus != 0)
+    # chi(i nu): solves at z = +-i nu through per-shift imaginary parts (omega = 0)
+    tol = 1e-11
+    zero = np.zeros(len(nus))
+    sols = []
+    for sgn in (1.0, -1.0):
+        o = sgw.sgw_opts_default(shift_imag=sgn * nus)
+        st, dpsi, info = sgw.sternheimer_solve(ctx, d.h_kq, d.psi_occ_kq, d.h_k, d.psi_v, d.eps_v, p.dv_miller, zero,
+                                               0.0, tol, opts=o)
+        assert st == sgw.SGW_OK, sgw.load_library().sgw_last_error()
+        sols.append(dpsi)
+    chi = sgw.sgw_density_response(ctx, d.h_kq, d.psi_occ_kq, d.h_k, d.psi_v, p.dv_miller, sols[0], sols[1])
+    chi_ref = so.density_response_spectral(w, u, p.n_occ, p.psi_k[: p.n_band], p.eps_k[: p.n_band], p.miller_k,
+                                           p.miller_kq, p.dv_miller, 1j * nus, vol)
+    e_chi = np.abs(chi.cpu().numpy() - chi_ref).max() / np.abs(chi_ref).max()
+    print("chi(i nu) rel err", e_chi, flush=True)
+    assert e_chi <= 1e-8
+    _, _, wbar = sgw.sgw_screened_coulomb(ctx, d.h_kq, d.h_k, p.dv_miller, chi)
+    qg = (p.dv_miller + 0.0) @ p.B + p.qvec
+    wbar_ref = so.screened_correlation(so.dielectric(chi_ref, so.coulomb(qg)), so.coulomb(qg))
+    st, m, _ = sgw.sgw_green_pair_elements(ctx, d.h_kq, d.h_k, d.psi_v, p.dv_miller, mu, W_INT, tol)
+    assert st == sgw.SGW_OK
+    sigma = sgw.sgw_sigma_c(ctx, m, Q_INT, wbar, idx, vol).cpu().numpy()
+    sig_ref = np.array([so.sigma_c_imag(so.green_pair_elements_spectral(w, u, p.psi_k[n], p.miller_k, p.miller_kq,
+                                                                         p.dv_miller, mu + 1j * W_INT),
+                                        wbar_ref[idx], Q_INT, vol) for n in range(p.n_band)])
+    e_sig = np.abs(sigma - sig_ref).max() / np.abs(sig_ref).max()
+    print("Sigma^c(i w) rel err", e_sig, "max |Sigma|", np.abs(sig_ref).max(), flush=True)
+    assert e_sig <= 1e-7
+    # continuation of each state's Sigma^c and its spectral function on the real axis
+    fits = [sgw.sgw_aaa_fit(1j * w_out, sigma[n], tol=1e-10, max_terms=8) for n in range(p.n_band)]
+    omega = np.linspace(-1.0, 1.0, 333)
+    broad = 0.01
+    eps_n = p.eps_k[: p.n_band]
+    delta = np.linspace(-0.05, 0.05, p.n_band)
+    s_lib, a_lib = sgw.sgw_spectral_function(ctx, fits, omega, broad, eps_n, delta)
+    s_lib, a_lib = s_lib.cpu().numpy(), a_lib.cpu().numpy()
+    for n, (zs, fs, ws) in enumerate(fits):
+        s_ref = so.aaa_eval(zs, fs, ws, omega + 1j * broad)
+        a_ref = so.spectral_function(omega, s_ref, eps_n[n], delta[n])
+        assert np.abs(s_lib[n] - s_ref).max() <= 1e-12 * np.abs(s_ref).max()
+        assert np.abs(a_lib[n] - a_ref).max() <= 1e-12 * np.abs(a_ref).max()
+        # the library's fit reproduces the data as well as the oracle's fit of the same data
+        zo, fo, wo = so.aaa(1j * w_out, sigma[n], tol=1e-10, mmax=8)
+        e_orc = np.abs(so.aaa_eval(zo, fo, wo, 1j * w_out) - sigma[n]).max()
+        e_lib = np.abs(so.aaa_eval(zs, fs, ws, 1j * w_out) - sigma[n]).max()
+        assert e_lib <= max(10 * e_orc, 1e-9 * np.abs(sigma[n]).max())
+
+
+def test_pair_elements_errors(ctx, prob):
+    from paper_1812_03717_amd import sgw
+    p, d, _, _, mu = prob
+    with pytest.raises(sgw.SgwError):
+        sgw.sgw_green_pair_elements(ctx, d.h_kq, d.h_k, d.psi_v, p.dv_miller, mu, [0.1, np.nan], 1e-10)
+    with pytest.raises(sgw.SgwError):
+        sgw.sgw_green_pair_elements(ctx, d.h_kq, d.h_k, d.psi_v, p.dv_miller, np.inf, [0.1], 1e-10)
+    lib = sgw.load_library()
+    assert lib.sgw_green_pair_elements(ctx.handle, d.h_kq.handle, d.h_k.handle, 0, None, 0, None, mu, 0, None,
+                                       1e-10, None, None, 0, None, None) == sgw.SGW_OK
+    # a workspace below the reported size is refused before any work
+    import ctypes as C
+    n = C.c_size_t()
+    assert lib.sgw_green_pair_workspace_size(ctx.handle, d.h_kq.handle, p.n_band, p.n_pert, 3, None,
+                                             C.byref(n)) == sgw.SGW_OK
+    ws = torch.empty(n.value, dtype=torch.uint8, device=ctx.device)
+    m = torch.empty((p.n_band, 3, p.n_pert, p.n_pert), dtype=torch.complex128, device=ctx.device)
+    g = np.ascontiguousarray(p.dv_miller, np.int32)
+    w = np.array([0.1, 0.5, 1.0])
+    assert lib.sgw_green_pair_elements(ctx.handle, d.h_kq.handle, d.h_k.handle, p.n_band, d.psi_v.data_ptr(),
+                                       p.n_pert, g.ctypes.data_as(C.POINTER(C.c_int32)), mu, 3,
+                                       w.ctypes.data_as(C.POINTER(C.c_double)), 1e-10, None, ws.data_ptr(),
+                                       n.value - 256, m.data_ptr(), None) == sgw.SGW_ERR_WORKSPACE
+    # with the reported size and no info array: the records go to the workspace
+    assert lib.sgw_green_pair_elements(ctx.handle, d.h_kq.handle, d.h_k.handle, p.n_band, d.psi_v.data_ptr(),
+                                       p.n_pert, g.ctypes.data_as(C.POINTER(C.c_int32)), mu, 3,
+                                       w.ctypes.data_as(C.POINTER(C.c_double)), 1e-10, None, ws.data_ptr(),
+                                       n.value, m.data_ptr(), None) == sgw.SGW_OK
+    _, ref, _ = sgw.sgw_green_pair_elements(ctx, d.h_kq, d.h_k, d.psi_v, p.dv_miller, mu, w, 1e-10)
+    assert torch.equal(m, ref)
+    assert lib.sgw_sigma_c(ctx.handle, 0, 0, 0, None, None, 0, None, 0, None, 1.0, None) == sgw.SGW_OK
+
+
+@pytest.mark.parametrize("solver", ["multishift", "per_shift"])
+def test_shift_imag_solves(ctx, prob, solver):
+    """Shifts omega_j + i s_j with their own imaginary parts of both signs (one Krylov space in the
+    multishift solver) against the oracle's sum over empty states at each shift."""
+    from paper_1812_03717_amd import sgw
+    p, d, w, u, _ = prob
+    rng = np.random.default_rng(77)
+    om = rng.uniform(-0.3, 0.6, 7)
+    si = rng.uniform(0.02, 1.5, 7) * rng.choice([-1.0, 1.0], 7)
+    tol = 1e-11
+    o = sgw.sgw_opts_default(shift_imag=si, solver=sgw.SOLVER_PER_SHIFT if solver == "per_shift" else
+                             sgw.SOLVER_MULTISHIFT)
+    st, x, info = sgw.sternheimer_solve(ctx, d.h_kq, d.psi_occ_kq, d.h_k, d.psi_v, d.eps_v, p.dv_miller, om, 0.0, tol,
+                                        opts=o)
+    assert st == sgw.SGW_OK, sgw.load_library().sgw_last_error()
+    inf = sgw.info_to_numpy(info)
+    assert np.all(inf["flags"] & sgw.FLAG_CONVERGED) and inf["relres"].max() <= tol
+    x = x.cpu().numpy()
+    zs = om + 1j * si
+    for v in range(p.n_band):
+        kap = max(so.condition_number(w, p.n_occ, p.eps_k[v], z) for z in zs)
+        for q in range(p.n_pert):
+            b = so.rhs(p.psi_k[v], p.miller_k, p.miller_kq, p.dv_miller[q], p.psi_kq)
+            ref = so.solve_spectral(w, u, p.n_occ, p.eps_k[v], b, zs)
+            err = np.linalg.norm(x[v, q] - ref, axis=1) / np.linalg.norm(ref, axis=1)
+            assert err.max() <= max(2 * kap * tol, 1e-12), (v, q, err.max(), kap)
