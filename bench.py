@@ -17,6 +17,7 @@ band, one LU factorisation solving all perturbations at one frequency), scaled t
     python bench.py --workload si16 --precision mixed   # 16-atom cell, 48^3, 102,400 solves;
                                                         # a plain FP64 leg is timed beside it
     python bench.py --workload batch200                 # 200 uneven systems, sternheimer_solve_batch
+    python bench.py --workload batch200e11              # the same at Ecut 11.46 Ha (inputs: GPU eigensolver)
 """
 from __future__ import annotations
 
@@ -47,6 +48,9 @@ WORKLOADS = {
     "batch200": "batch200: 200 independent diamond fcc n0 x n1 x n2 cells (n_d in 1..3, 2-54 atoms), grid 24 n_d "
                 "per axis, Ecut 4 Ha (100-2800 PW), all ~2*atoms occupied bands, 16-128 omega in [0,40] eV, "
                 "4-16 perts at an own seeded q, eta 0.05 eV, tol 1e-8",
+    "batch200e11": "batch200e11: the same 200 systems' recipe at Ecut 11.46 Ha (531-13539 PW; grids 24^3-72^3), all "
+                   "~2*atoms occupied bands (4-109), 16-128 omega in [0,40] eV, 4-16 perts at an own seeded q, "
+                   "eta 0.05 eV, tol 1e-8",
 }
 
 KERNELS = ["hx_sticks_inv", "hx_planes", "hx_sticks_fwd", "proj_dot", "proj_apply", "lanczos_step", "slot_init", "rhs_source",
@@ -272,25 +276,58 @@ def bench_batch(args, log):
     from paper_1812_03717_amd.workload import DeviceProblem
 
     t0 = time.perf_counter()
-    problems = synth.batch(200, workers=min(16, os.cpu_count() or 1))
+    # at 11.46 Ha the bases reach 13,539 plane waves: the generator's eigensolver runs on the GPU from
+    # 5,000 plane waves (the host pool takes the smaller systems meanwhile), and the large cells' levels
+    # at the occupation edge are ~5e-4 Ha apart, so the smallest accepted gap there is 3e-4 Ha
+    kw = dict(ecut=11.46, gpu_min_pw=5000, min_gap=3e-4) if args.workload == "batch200e11" else {}
+    problems = synth.batch(200, workers=min(16, os.cpu_count() or 1), **kw)
     n_solves = sum(p.n_solves for p in problems)
     log(f"generated 200 systems, {n_solves} solves ({time.perf_counter() - t0:.1f} s)")
     ctx = sgw.sgw_ctx_create(0)
     devs = [DeviceProblem(ctx, p) for p in problems]
     ws = sgw.Workspace(ctx)
-    batch = sgw.Batch(ctx)
+    # the outputs of all systems at 11.46 Ha (~0.3 TB) exceed the HBM beside the workspace: the systems
+    # go in consecutive groups whose outputs fit one caller-owned buffer, one batched call per group
+    # (one group at 4 Ha); the sequential reference writes into the same buffer
+    sizes = [p.n_solves * p.n_pw_kq for p in problems]
+    cap = max(max(sizes), (args.batch_output_gib << 30) // 16)
+    groups, cur, acc = [], [], 0
+    for i, n in enumerate(sizes):
+        if cur and acc + n > cap:
+            groups.append(cur)
+            cur, acc = [], 0
+        cur.append(i)
+        acc += n
+    groups.append(cur)
+    outbuf = torch.empty(max(sum(sizes[i] for i in g) for g in groups), dtype=torch.complex128, device=ctx.device)
+
+    def views(g):
+        off, vs = 0, []
+        for i in g:
+            p = problems[i]
+            vs.append(outbuf[off:off + sizes[i]].view(p.n_band, p.n_pert, p.n_omega, p.n_pw_kq))
+            off += sizes[i]
+        return vs
+
     # the largest cells (72^3, ~110 bands, dense spectrum in the frequency window) need up to ~4000
     # Krylov steps for their upper bands; the slot count is fitted to the workspace
     opts = lambda: sgw.sgw_opts_default(max_iter=args.batch_max_iter)
-    for d in devs:
-        p = d.problem
-        batch.add(d.h_kq, d.psi_occ_kq, d.h_k, d.psi_v, d.eps_v, p.dv_miller, p.omega, p.eta, p.tol, opts=opts())
+    batches = []
+    for g in groups:
+        b = sgw.Batch(ctx)
+        for i, v in zip(g, views(g)):
+            d, p = devs[i], problems[i]
+            b.add(d.h_kq, d.psi_occ_kq, d.h_k, d.psi_v, d.eps_v, p.dv_miller, p.omega, p.eta, p.tol, opts=opts(),
+                  dpsi=v)
+        batches.append(b)
+    items = [it for b in batches for it in b.items]
     t = time.perf_counter()
-    tune_ms = sum(batch.autotune(i) for i in range(len(devs)))
-    log(f"autotune: {tune_ms / 1e3:.2f} s (wall {time.perf_counter() - t:.2f} s); steps_per_sync/graph chosen: "
-        f"{sorted({(it['problem'].opts.steps_per_sync, it['problem'].opts.graph) for it in batch.items})}; "
+    tune_ms = sum(b.autotune(i) for b in batches for i in range(len(b.items)))
+    log(f"{len(groups)} group(s) of {[len(g) for g in groups]} systems; "
+        f"autotune: {tune_ms / 1e3:.2f} s (wall {time.perf_counter() - t:.2f} s); steps_per_sync/graph chosen: "
+        f"{sorted({(it['problem'].opts.steps_per_sync, it['problem'].opts.graph) for it in items})}; "
         f"plane kernel (1 line, 2 pair, 3 LDS, 4 three-thread) per grid: "
-        f"{sorted({(tuple(devs[i].h_kq.grid), it['problem'].opts.fft_planes) for i, it in enumerate(batch.items)})}")
+        f"{sorted({(tuple(devs[i].h_kq.grid), it['problem'].opts.fft_planes) for i, it in enumerate(items)})}")
     workers = args.batch_workers
 
     def ok_count(items):
@@ -304,16 +341,17 @@ def bench_batch(args, log):
     torch.cuda.synchronize()
     t = time.perf_counter()
     seq_ok = 0
-    for d, it in zip(devs, batch.items):
-        st, _, info = d.solve(workspace=ws, opts=opts())
-        inf = sgw.info_to_numpy(info)
-        seq_ok += int(np.count_nonzero((inf["flags"] & sgw.FLAG_CONVERGED) != 0))
+    for g in groups:
+        for i, v in zip(g, views(g)):
+            st, _, info = devs[i].solve(workspace=ws, opts=opts(), dpsi=v)
+            inf = sgw.info_to_numpy(info)
+            seq_ok += int(np.count_nonzero((inf["flags"] & sgw.FLAG_CONVERGED) != 0))
     torch.cuda.synchronize()
     seq_s = time.perf_counter() - t
     log(f"sequential: {seq_s:.3f} s, converged {seq_ok}/{n_solves}")
     for w in range(max(args.warmup, 1)):
         t = time.perf_counter()
-        st = batch.solve(n_workers=workers, workspace=ws)
+        st = [b.solve(n_workers=workers, workspace=ws) for b in batches]
         torch.cuda.synchronize()
         log(f"warmup {w}: status {st}, {time.perf_counter() - t:.3f} s")
     ctx.reset_stats()
@@ -322,8 +360,9 @@ def bench_batch(args, log):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        batch.solve(n_workers=workers, workspace=ws)
-        n_ok += ok_count(batch.items)
+        for b in batches:
+            b.solve(n_workers=workers, workspace=ws)
+            n_ok += ok_count(b.items)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     ctx.set_profiling(None)
@@ -336,13 +375,97 @@ def bench_batch(args, log):
         "ms_per_step": round(1e3 * elapsed / args.steps, 3), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "speedup_vs_sequential": round(value / (seq_ok / seq_s), 3), "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": WORKLOADS["batch200"], "solves_per_step": n_solves, "workers": workers,
+        "config": {"workload": WORKLOADS[args.workload], "solves_per_step": n_solves, "workers": workers,
+                   "groups": len(groups),
                    "autotune_s": round(tune_ms / 1e3, 3), "sequential_solves_per_s": round(seq_ok / seq_s, 1),
                    "max_iter": args.batch_max_iter,
                    "method": "plain FP64 multishift Lanczos-FOM, batched over worker streams, autotuned"},
-        "roofline": roofline("hx_planes", ks, "batch200"),
+        "roofline": roofline("hx_planes", ks, args.workload),
     }
     print(json.dumps(out), flush=True)
+
+
+def bench_learned(args, log):
+    """The learned preconditioner and guess on held-out cells.  The model is trained on the GPU (the
+    library's kernels) from per-shift residual histories of a 16-atom subset (5 bands x 4
+    perturbations x 16 omega of the si16 workload) and three cells of the batch recipe (4 Ha); it
+    is then evaluated on cells with seeds of their own, 16, 36 and 64 atoms at 48^3 to 72^3 with
+    64 frequencies (bands lowest, middle and highest x 4 perturbations x 64 omega each), as the
+    per-shift solver's preconditioner against the Teter diagonal (the fallback), with the multishift
+    solver beside them.  Every solve is decided by its true FP64 residual (tol 1e-8)."""
+    import torch
+    import synth
+    from paper_1812_03717_amd import sgw, training
+    from paper_1812_03717_amd.workload import DeviceProblem
+    ctx = sgw.sgw_ctx_create(0)
+    ws = sgw.Workspace(ctx)
+    t0 = time.perf_counter()
+    train_sets = [(synth.si16(), [0, 8, 16, 24, 31], range(4), slice(None, None, 4))]
+    train_sets += [(p, range(p.n_band), range(p.n_pert), slice(None)) for p in
+                   synth.batch(3, seed0=9600, cells_max=2, n_omega_range=(16, 32), n_pert_range=(4, 6), workers=3)]
+    feats, tgts = [], []
+    for p, bands, perts, osel in train_sets:
+        d = DeviceProblem(ctx, p)
+        f, t = training.collect_rows(ctx, d, bands, perts, p.omega[osel], workspace=ws)
+        feats.append(f)
+        tgts.append(t)
+        del d
+    feat, tgt = torch.cat(feats), torch.cat(tgts)
+    del feats, tgts
+    mlp = sgw.sgw_mlp_create(ctx, seed=1)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    losses = training.train(ctx, mlp, feat, tgt, steps=2000, lr=2e-3, batch=32768)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t1
+    log(f"training: {feat.shape[0]} rows from {len(train_sets)} systems ({t1 - t0:.1f} s), 2000 Adam steps "
+        f"{train_s:.2f} s, loss {losses[0]:.4f} -> {np.mean(losses[-20:]):.4f}")
+    del feat, tgt
+    # iteration limits that let the near-resonant top bands converge in every mode (a multishift Krylov
+    # step is one operator application, a BiCGStab iteration two)
+    modes = {"multishift": dict(max_iter=4000),
+             "teter": dict(solver=sgw.SOLVER_PER_SHIFT, precond=sgw.PC_TETER, ps_max_iter=4000),
+             "learned": dict(solver=sgw.SOLVER_PER_SHIFT, precond=sgw.PC_LEARNED, mlp=mlp, ps_max_iter=4000)}
+    cells = {}
+    tot = {m: [0, 0.0] for m in modes}
+    for name, seed in (("fcc222", 9801), ("fcc233", 9802), ("conv222", 9803)):
+        p = synth.held_out(name, seed)
+        d = DeviceProblem(ctx, p)
+        bands = [0, p.n_occ // 2, p.n_occ - 1]
+        res = {}
+        for m, kw in modes.items():
+            opts = sgw.sgw_opts_default(**kw)
+            d.solve(opts=opts, workspace=ws, bands=bands)   # warm-up (slots, graphs, workspace)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            st, _, info = d.solve(opts=opts, workspace=ws, bands=bands)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t
+            inf = sgw.info_to_numpy(info)
+            conv = int(np.count_nonzero(inf["flags"] & sgw.FLAG_CONVERGED))
+            res[m] = {"iterations": int(inf["iters"].sum()), "converged": conv, "solves": int(inf.size),
+                      "s": round(dt, 3), "solves_per_s": round(conv / dt, 1)}
+            tot[m][0] += conv
+            tot[m][1] += dt
+        log(f"{p.name}: {p.n_pw_kq} PW, grid {p.grid}, n_occ {p.n_occ}, bands {bands}: {res}")
+        cells[p.name] = {"n_pw": p.n_pw_kq, "grid": list(p.grid), "n_occ": p.n_occ, "bands": bands, **res}
+    ratio = [cells[c]["learned"]["iterations"] / cells[c]["teter"]["iterations"] for c in cells]
+    print(json.dumps({
+        "metric": "per-shift solves/s at true FP64 rel. residual <= 1e-8 with the learned preconditioner and guess "
+                  "on held-out cells (Teter fallback and the multishift solver beside it)",
+        "value": round(tot["learned"][0] / tot["learned"][1], 1), "unit": "solves/s", "n_gpus": 1, "steps": 1,
+        "warmup": 1, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "held-out diamond cells, seeds 9801-9803: fcc 2x2x2 (16 atoms, 48^3), fcc 2x3x3 "
+                               "(36 atoms, 48x72x72), conventional 2x2x2 (64 atoms, 72^3), Ecut 11.46 Ha, 3 bands x "
+                               "4 perts x 64 omega in [0,40] eV each, eta 0.05 eV, tol 1e-8; model 5-64-64-4 trained "
+                               "on si16 and batch-recipe cells (other seeds)",
+                   "train_s": round(train_s, 2)},
+        "learned_over_teter_iterations": [round(r, 3) for r in ratio],
+        "teter_solves_per_s": round(tot["teter"][0] / tot["teter"][1], 1),
+        "multishift_solves_per_s": round(tot["multishift"][0] / tot["multishift"][1], 1),
+        "cells": cells}), flush=True)
+    mlp.close()
 
 
 def sigma_frequencies(n_int=32, n_out=12, h=0.25):
@@ -471,10 +594,15 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch-workers", type=int, default=4)
     ap.add_argument("--batch-max-iter", type=int, default=4000)
+    ap.add_argument("--batch-output-gib", type=int, default=100,
+                    help="device memory for the batch outputs; systems are grouped to fit it")
     ap.add_argument("--cpu-sample-pairs", type=int, default=160)
     ap.add_argument("--dielectric", type=int, default=0, metavar="BANDS",
                     help="time the screening path instead: solves at z and -z for BANDS bands at a time, the "
                          "density response accumulated over the band chunks, eps, eps^-1 and W_bar")
+    ap.add_argument("--learned", action="store_true",
+                    help="train the learned preconditioner and compare it with the Teter fallback on held-out "
+                         "16-, 36- and 64-atom cells with 64 frequencies")
     ap.add_argument("--sigma", type=int, default=0, metavar="STATES",
                     help="time the self-energy path of the top STATES bands instead (W_bar untimed): Green's "
                          "function pair elements, Sigma^c on the imaginary axis, AAA, A(w), E_qp")
@@ -508,7 +636,9 @@ def main():
         log("no GPU available")
         sys.exit(1)
     sgw.load_library()
-    if args.workload == "batch200":
+    if args.learned:
+        return bench_learned(args, log)
+    if args.workload in ("batch200", "batch200e11"):
         return bench_batch(args, log)
     t0 = time.perf_counter()
     problem = getattr(synth, args.workload)()

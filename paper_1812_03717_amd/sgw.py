@@ -559,7 +559,8 @@ class Batch:
         self.ctx = ctx
         self.items = []
 
-    def add(self, h_kq, psi_occ_kq, h_k, psi_v, eps_v, dv_miller, omega, eta, tol, opts=None):
+    def add(self, h_kq, psi_occ_kq, h_k, psi_v, eps_v, dv_miller, omega, eta, tol, opts=None, dpsi=None):
+        """dpsi: optional caller-owned output tensor [n_band][n_pert][n_omega][n_pw_kq] (else allocated)."""
         import torch
         _require(psi_v, torch.complex128, self.ctx.device, (psi_v.shape[0], h_k.n_pw), "psi_v")
         _require(psi_occ_kq, torch.complex128, self.ctx.device, (psi_occ_kq.shape[0], h_kq.n_pw), "psi_occ_kq")
@@ -567,7 +568,10 @@ class Batch:
         om = np.ascontiguousarray(np.asarray(omega, np.float64))
         dvm = np.ascontiguousarray(np.asarray(dv_miller, np.int32).reshape(-1, 3))
         n_band, n_pert, n_omega = int(psi_v.shape[0]), int(dvm.shape[0]), int(om.shape[0])
-        dpsi = torch.empty((n_band, n_pert, n_omega, h_kq.n_pw), dtype=torch.complex128, device=self.ctx.device)
+        if dpsi is None:
+            dpsi = torch.empty((n_band, n_pert, n_omega, h_kq.n_pw), dtype=torch.complex128, device=self.ctx.device)
+        else:
+            _require(dpsi, torch.complex128, self.ctx.device, (n_band, n_pert, n_omega, h_kq.n_pw), "dpsi")
         info = torch.empty(n_band * n_pert * n_omega * INFO_DTYPE.itemsize, dtype=torch.uint8, device=self.ctx.device)
         p = sgw_problem()
         p.h_kq, p.h_k = h_kq.handle.value, h_k.handle.value

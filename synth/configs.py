@@ -25,7 +25,7 @@ import functools
 import numpy as np
 
 from . import crystal as cx
-from .ground_state import lowest_states
+from .ground_state import _gpu_present, lowest_states
 
 A_LAT = 10.26
 MIN_GAP_HA = 1e-3
@@ -104,11 +104,11 @@ class Problem:
 
 def make_problem(name, A, tau, grid, ecut, n_occ, omega_ev, eta_ev, n_pert, tol, seed,
                  q_zero=False, n_band=None, noise=0.05, max_bumps=20, occ_window=0, min_gap=MIN_GAP_HA,
-                 nonlocal_pp=False):
+                 nonlocal_pp=False, gpu_min_pw=None):
     """occ_window > 0: when the states n_occ - 1 and n_occ are (near-)degenerate, take the band count
     within n_occ +- occ_window closest to n_occ that has a gap >= MIN_GAP_HA at k and k+q.
     nonlocal_pp: add the synthetic s and p projectors of ``crystal.kb_projectors`` on every atom to the
-    Hamiltonian whose eigenstates are the reference states."""
+    Hamiltonian whose eigenstates are the reference states.  gpu_min_pw: see ``lowest_states``."""
     B = cx.reciprocal(A)
     kvec = np.zeros(3)
     target = n_occ
@@ -121,11 +121,11 @@ def make_problem(name, A, tau, grid, ecut, n_occ, omega_ev, eta_ev, n_pert, tol,
         nl_k = cx.kb_projectors(mk, B, kvec, A, tau) if nonlocal_pp else None
         nl_kq = (nl_k if q_zero else cx.kb_projectors(mkq, B, kvec + qvec, A, tau)) if nonlocal_pp else None
         n_states = target + occ_window + 1
-        ek, pk = lowest_states(mk, B, kvec, v, n_states, nl_k)
+        ek, pk = lowest_states(mk, B, kvec, v, n_states, nl_k, gpu_min_pw=gpu_min_pw)
         if q_zero:
             ekq, pkq = ek, pk
         else:
-            ekq, pkq = lowest_states(mkq, B, kvec + qvec, v, n_states, nl_kq)
+            ekq, pkq = lowest_states(mkq, B, kvec + qvec, v, n_states, nl_kq, gpu_min_pw=gpu_min_pw)
         cands = sorted(range(max(1, target - occ_window), target + occ_window + 1), key=lambda n: (abs(n - target), n))
         ok = [n for n in cands if min(ek[n] - ek[n - 1], ekq[n] - ekq[n - 1]) >= min_gap]
         if ok:
@@ -194,34 +194,75 @@ def small(cells=(1, 1, 1), grid=None, ecut=11.46, n_occ=None, n_omega=8, n_pert=
                         q_zero=q_zero, n_band=n_band, nonlocal_pp=nonlocal_pp)
 
 
+@functools.lru_cache(maxsize=None)
+def held_out(name, seed):
+    """Cells for evaluating the learned preconditioner, with seeds of their own: "fcc222" (16 atoms,
+    48^3), "fcc233" (36 atoms, 48 x 72 x 72) or "conv222" (the 64-atom conventional cell, 72^3);
+    E_cut 11.46 Ha, all ~2*atoms bands occupied (the nearest count within +-6 with a gap >= 3e-4 Ha),
+    64 omega in [0, 40] eV, eta 0.05 eV, 4 perturbations at a seeded q, tol 1e-8."""
+    if name == "conv222":
+        A, tau = cx.supercell(*cx.conventional_cubic(A_LAT), (2, 2, 2))
+        grid = (72, 72, 72)
+    else:
+        cells = {"fcc222": (2, 2, 2), "fcc233": (2, 3, 3)}[name]
+        A, tau = cx.supercell(*cx.fcc_primitive(A_LAT), cells)
+        grid = tuple(24 * c for c in cells)
+    return make_problem(f"{name}_s{seed}", A, tau, grid, 11.46, 2 * len(tau), cx.frequencies_ev(0, 40, 64), 0.05,
+                        4, 1e-8, seed, occ_window=6, min_gap=3e-4, gpu_min_pw=5000)
+
+
 CONFIGS = {"si2": si2, "si16": si16, "si64": si64, "si64nl": si64nl}
 
 
-def _batch_system(args):
-    i, seed0, ecut, cells_max, n_omega_range, n_pert_range, tol, threads = args
-    from threadpoolctl import threadpool_limits
+def _batch_cells(i, seed0, cells_max, n_omega_range, n_pert_range):
     rng = np.random.default_rng([seed0 + i, 1])
     cells = tuple(int(c) for c in rng.integers(1, cells_max + 1, 3))
     n_omega = int(rng.integers(n_omega_range[0], n_omega_range[1] + 1))
     n_pert = int(rng.integers(n_pert_range[0], n_pert_range[1] + 1))
+    return cells, n_omega, n_pert
+
+
+def _batch_system(args):
+    i, seed0, ecut, cells_max, n_omega_range, n_pert_range, tol, threads, gpu_min_pw, min_gap = args
+    from threadpoolctl import threadpool_limits
+    cells, n_omega, n_pert = _batch_cells(i, seed0, cells_max, n_omega_range, n_pert_range)
     A, tau = cx.supercell(*cx.fcc_primitive(A_LAT), cells)
     with threadpool_limits(threads):
         return make_problem(f"batch{i}{cells}", A, tau, tuple(24 * c for c in cells), ecut, 2 * len(tau),
-                            cx.frequencies_ev(0, 40, n_omega), 0.05, n_pert, tol, seed0 + i, occ_window=6)
+                            cx.frequencies_ev(0, 40, n_omega), 0.05, n_pert, tol, seed0 + i, occ_window=6,
+                            gpu_min_pw=gpu_min_pw, min_gap=min_gap)
 
 
 def batch(n_sys=200, seed0=3000, ecut=4.0, cells_max=3, n_omega_range=(16, 128), n_pert_range=(4, 16), tol=1e-8,
-          workers=8):
+          workers=8, gpu_min_pw=None, min_gap=MIN_GAP_HA):
     """Independent systems of uneven size: fcc n0 x n1 x n2 cells (n_d uniform in 1..cells_max, 2-54
     atoms), grid 24 n_d per axis, all 2*atoms occupied bands, n_omega and n_pert uniform in their
     ranges, frequencies linspace(0, 40 eV), eta 0.05 eV, one seeded q each; system i has seed seed0 + i.
     Where states 2*atoms - 1 and 2*atoms are degenerate the nearest band count (within +-6) with a gap
     is occupied instead.
-    Generated in `workers` processes (dense eigensolver per system)."""
-    args = [(i, seed0, ecut, cells_max, n_omega_range, n_pert_range, tol, 2) for i in range(n_sys)]
+    Generated in `workers` processes (dense eigensolver per system on the CPU).  With gpu_min_pw set
+    and a GPU present, the systems whose basis at k has at least that many plane waves are generated
+    in this process with the eigensolver on the GPU (while the pool does the others).  min_gap: the
+    smallest gap at the occupation edge (see make_problem)."""
+    big = set()
+    if gpu_min_pw is not None and _gpu_present():
+        for i in range(n_sys):
+            cells, _, _ = _batch_cells(i, seed0, cells_max, n_omega_range, n_pert_range)
+            A, _ = cx.supercell(*cx.fcc_primitive(A_LAT), cells)
+            if cx.g_sphere(cx.reciprocal(A), np.zeros(3), ecut).shape[0] >= gpu_min_pw:
+                big.add(i)
+    no_gpu = 1 << 62
+    args = [(i, seed0, ecut, cells_max, n_omega_range, n_pert_range, tol, 2, gpu_min_pw if i in big else no_gpu,
+             min_gap) for i in range(n_sys)]
     if workers <= 1:
         return [_batch_system(a) for a in args]
     import concurrent.futures as cf
     import multiprocessing as mp
+    out = [None] * n_sys
     with cf.ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn")) as ex:
-        return list(ex.map(_batch_system, args))
+        futs = {ex.submit(_batch_system, a): a[0] for a in args if a[0] not in big}
+        for i in sorted(big):
+            out[i] = _batch_system(args[i])
+        for f in cf.as_completed(futs):
+            out[futs[f]] = f.result()
+    return out

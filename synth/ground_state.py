@@ -86,7 +86,8 @@ def _cache_path(miller, B, kvec, v_grid, n_states, nl=None):
     return os.path.join(root, f"eigh_{h.hexdigest()[:24]}.npz")
 
 
-def lowest_states(miller: np.ndarray, B: np.ndarray, kvec, v_grid: np.ndarray, n_states: int, nl=None):
+def lowest_states(miller: np.ndarray, B: np.ndarray, kvec, v_grid: np.ndarray, n_states: int, nl=None,
+                  gpu_min_pw=None):
     """Lowest ``n_states`` eigenpairs of the plane-wave Hamiltonian.
 
     Returns (energies [n_states] in Ha ascending, states [n_states][n_pw] complex128,
@@ -95,14 +96,15 @@ def lowest_states(miller: np.ndarray, B: np.ndarray, kvec, v_grid: np.ndarray, n
     With $SYNTH_EIGH_CACHE set, the result is stored there and later calls with the same
     inputs load it instead of diagonalising again (e.g. profiler runs that should not
     trace the eigensolver).  ``nl`` = (beta [n_proj][n_pw], e_kb [n_proj]) adds the separable
-    non-local term.
+    non-local term.  ``gpu_min_pw``: basis size from which the eigensolver runs on the GPU when one
+    is present (None: GPU_EIGH_MIN_PW).
     """
     n_states = min(n_states, miller.shape[0])
     path = _cache_path(miller, B, kvec, v_grid, n_states, nl)
     if path and os.path.exists(path):
         with np.load(path) as d:
             return d["w"], d["u"]
-    if miller.shape[0] >= GPU_EIGH_MIN_PW and _gpu_present():
+    if miller.shape[0] >= (GPU_EIGH_MIN_PW if gpu_min_pw is None else gpu_min_pw) and _gpu_present():
         w, u = _lowest_states_gpu(miller, B, kvec, v_grid, n_states, nl)
     else:
         h = _potential_matrix(miller, v_grid)
