@@ -518,7 +518,9 @@ typedef struct {
 /*
  * Workspace for sternheimer_solve_batch with n_workers workers: n_workers equal
  * parts, each large enough for every system with its slot count fitted to a
- * per-worker share of the default memory budget.
+ * per-worker share of the default memory budget, and (n_workers > 1) at least
+ * the single-solve workspace of every system that fills the GPU by itself (at
+ * least 128 band x perturbation pairs of at least 4,096 plane waves).
  */
 sgw_status sternheimer_batch_workspace_size(sgw_ctx *ctx, int n_sys, const sgw_problem *problems, int n_workers,
                                             size_t *bytes);
@@ -528,7 +530,10 @@ sgw_status sternheimer_batch_workspace_size(sgw_ctx *ctx, int n_sys, const sgw_p
  * queue in order of decreasing predicted cost and solve them exactly as
  * sternheimer_solve would (results are identical), each in its own part of the
  * workspace; a multishift system's slot count is lowered to fit that part.
- * Small systems thereby share the GPU.  The workers start after the work already
+ * Small systems thereby share the GPU.  With n_workers > 1, the systems that
+ * fill the GPU by themselves (see above) run first, one at a time over the whole
+ * workspace with the options of a single solve (a share would cut their slots).
+ * The workers start after the work already
  * enqueued on the context's stream; the call returns when all systems are done.
  * Returns the first error (problems[i].status tells which), else SGW_NOT_CONVERGED
  * if any system did not converge, else SGW_OK.  Kernel timing statistics of the

@@ -1578,6 +1578,13 @@ sgw_opts fit_to_budget(const sgw_problem &p, sgw_opts o, size_t budget) {
   return o;
 }
 
+// A system whose launches alone fill the GPU (at least 128 (band, perturbation) pairs of at least
+// 4,096 plane waves: 128 vectors give >= 6,000 plane workgroups on a 48-point grid) loses more to a
+// worker's share of the workspace (fewer slots, hence fewer vectors per launch) than it gains from
+// running beside others: in a batch over several workers such systems run first, one at a time over
+// the whole workspace with the options of a single solve.
+bool fills_gpu(const sgw_problem &p) { return p.h_kq->n_pw >= 4096 && (long)p.n_band * p.n_pert >= 128; }
+
 double predicted_cost(const sgw_problem &p) {
   const double npw = p.h_kq->n_pw;
   const double grid = (double)p.h_kq->n[0] * p.h_kq->n[1] * p.h_kq->n[2];
@@ -1595,14 +1602,18 @@ extern "C" sgw_status sternheimer_batch_workspace_size(sgw_ctx *ctx, int n_sys, 
   if (n_sys < 0 || n_workers < 1 || n_workers > kMaxWorkers)
     return fail(SGW_ERR_INVALID_ARG, "sternheimer_batch_workspace_size: bad n_sys or n_workers");
   const size_t budget = (size_t)(kDefaultBudget / n_workers) / kAlign * kAlign;
-  size_t part = 0;
+  size_t part = 0, alone = 0;
   for (int i = 0; i < n_sys; ++i) {
     if (!problems[i].h_kq) return fail(SGW_ERR_INVALID_ARG, "sternheimer_batch_workspace_size: NULL Hamiltonian");
-    const sgw_opts o = fit_to_budget(problems[i], resolve_opts(&problems[i].opts), budget);
-    part = std::max(part, problem_workspace_bytes(problems[i], o));
+    const sgw_opts o = resolve_opts(&problems[i].opts);
+    if (n_workers > 1 && fills_gpu(problems[i])) {
+      alone = std::max(alone, problem_workspace_bytes(problems[i], o));
+    } else {
+      part = std::max(part, problem_workspace_bytes(problems[i], fit_to_budget(problems[i], o, budget)));
+    }
   }
   part = (part + kAlign - 1) / kAlign * kAlign;
-  *bytes = part * n_workers;
+  *bytes = std::max(part * n_workers, (alone + kAlign - 1) / kAlign * kAlign);
   return SGW_OK;
 }
 
@@ -1614,7 +1625,9 @@ extern "C" sgw_status sternheimer_solve_batch(sgw_ctx *ctx, int n_sys, sgw_probl
   if (n_sys == 0) return SGW_OK;
   SGW_CHECK(workspace && ((uintptr_t)workspace) % kAlign == 0, "sternheimer_solve_batch: workspace missing or unaligned");
   const size_t part = workspace_bytes / n_workers / kAlign * kAlign;
+  const size_t whole = workspace_bytes / kAlign * kAlign;
   std::vector<sgw_opts> opts(n_sys);
+  std::vector<char> alone(n_sys, 0);
   for (int i = 0; i < n_sys; ++i) {
     sgw_problem &p = problems[i];
     p.status = SGW_OK;
@@ -1626,19 +1639,22 @@ extern "C" sgw_status sternheimer_solve_batch(sgw_ctx *ctx, int n_sys, sgw_probl
       p.status = st;
       return fail(st, "problem " + std::to_string(i) + ": " + sgw_last_error());
     }
-    opts[i] = fit_to_budget(p, o, part);
-    if (problem_workspace_bytes(p, opts[i]) > part) {
+    alone[i] = n_workers > 1 && fills_gpu(p);
+    const size_t room = alone[i] ? whole : part;
+    opts[i] = alone[i] && problem_workspace_bytes(p, o) <= whole ? o : fit_to_budget(p, o, room);
+    if (problem_workspace_bytes(p, opts[i]) > room) {
       p.status = SGW_ERR_WORKSPACE;
       return fail(SGW_ERR_WORKSPACE, "sternheimer_solve_batch: problem " + std::to_string(i) +
-                                         " does not fit the per-worker workspace of " + std::to_string(part) +
-                                         " bytes");
+                                         " does not fit the workspace of " + std::to_string(room) + " bytes");
     }
   }
-  // longest predicted first over the workers
+  // longest predicted first: the systems that fill the GPU one at a time, then the others over the workers
   std::vector<int> order(n_sys);
   std::iota(order.begin(), order.end(), 0);
   std::stable_sort(order.begin(), order.end(),
                    [&](int a, int b) { return predicted_cost(problems[a]) > predicted_cost(problems[b]); });
+  std::stable_partition(order.begin(), order.end(), [&](int i) { return alone[i] != 0; });
+  const int n_alone = (int)std::count(alone.begin(), alone.end(), 1);
   SGW_HIP(hipSetDevice(ctx->device));
   // the workers' streams wait for the work already queued on the caller's stream
   hipEvent_t ready = nullptr;
@@ -1661,11 +1677,35 @@ extern "C" sgw_status sternheimer_solve_batch(sgw_ctx *ctx, int n_sys, sgw_probl
     if (hipStreamWaitEvent(workers[w].stream, ready, 0) != hipSuccess)
       st = fail(SGW_ERR_HIP, "sternheimer_solve_batch: hipStreamWaitEvent failed");
   }
-  std::atomic<int> next{0};
+  std::atomic<int> next{n_alone};
   std::atomic<bool> abort_flag{false};
   std::mutex mu;
   std::string first_error;
   sgw_status first_status = SGW_OK;
+  auto record = [&](int i, int w, sgw_status s, double ms) {
+    problems[i].status = s;
+    problems[i].worker = w;
+    problems[i].ms = ms;
+    if (s < 0) {
+      std::lock_guard<std::mutex> lock(mu);
+      if (first_status == SGW_OK) {
+        first_status = s;
+        first_error = "problem " + std::to_string(i) + ": " + sgw_last_error();
+      }
+      abort_flag = true;
+    }
+  };
+  // the systems that fill the GPU, one at a time over the whole workspace on worker 0's stream; that
+  // stream is drained before the workers' shares of the workspace are reused
+  for (int k = 0; k < n_alone && st == SGW_OK && !abort_flag; ++k) {
+    const int i = order[k];
+    const auto t0 = std::chrono::steady_clock::now();
+    const sgw_status s = run_solve(workers[0].ctx, problems[i], opts[i], workspace, whole);
+    const auto t1 = std::chrono::steady_clock::now();
+    record(i, 0, s, std::chrono::duration<double, std::milli>(t1 - t0).count());
+  }
+  if (st == SGW_OK && n_alone > 0 && hipStreamSynchronize(workers[0].stream) != hipSuccess)
+    st = fail(SGW_ERR_HIP, "sternheimer_solve_batch: hipStreamSynchronize failed");
   auto work = [&](int w) {
     if (hipSetDevice(ctx->device) != hipSuccess) {
       abort_flag = true;
@@ -1679,20 +1719,10 @@ extern "C" sgw_status sternheimer_solve_batch(sgw_ctx *ctx, int n_sys, sgw_probl
       const auto t0 = std::chrono::steady_clock::now();
       const sgw_status s = run_solve(workers[w].ctx, problems[i], opts[i], base, part);
       const auto t1 = std::chrono::steady_clock::now();
-      problems[i].status = s;
-      problems[i].worker = w;
-      problems[i].ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
-      if (s < 0) {
-        std::lock_guard<std::mutex> lock(mu);
-        if (first_status == SGW_OK) {
-          first_status = s;
-          first_error = "problem " + std::to_string(i) + ": " + sgw_last_error();
-        }
-        abort_flag = true;
-      }
+      record(i, w, s, std::chrono::duration<double, std::milli>(t1 - t0).count());
     }
   };
-  if (st == SGW_OK) {
+  if (st == SGW_OK && !abort_flag) {
     std::vector<std::thread> threads;
     for (int w = 1; w < n_workers; ++w) threads.emplace_back(work, w);
     work(0);

@@ -66,6 +66,13 @@ def test_batch_full_cutoff_sampled_vs_lu(setup):
         nb = torch.linalg.vector_norm(bv, dim=-1).cpu().numpy()[:, :, None]
         nx = torch.linalg.vector_norm(it["dpsi"], dim=-1).cpu().numpy()
         assert np.all(inf["occ_leak"] * nx <= 1.01 * inf["relres"] * nb / p.eta + 1e-10 * nx)
+    # fcc333 and fcc323 fill the GPU and run alone over the whole workspace, fcc231 on a worker's share:
+    # both routes reproduce the single solves bit for bit
+    for k in ("fcc323", "fcc231"):
+        st1, x1, info1 = devs[k].solve(opts=sgw.sgw_opts_default(max_iter=4000))
+        it = b.items[names.index(k)]
+        assert st1 == sgw.SGW_OK and torch.equal(x1, it["dpsi"]) and torch.equal(info1, it["info"]), k
+        del x1
     p = ps["fcc333"]
     it = b.items[names.index("fcc333")]
     inf = sgw.info_to_numpy(it["info"], (p.n_band, p.n_pert, p.n_omega))
