@@ -40,7 +40,12 @@ def setup():
         print(f"{name}: {p.name} {p.n_pw_kq} PW, grid {p.grid}, n_occ {p.n_occ}, {p.n_solves} solves", flush=True)
     ctx = sgw.sgw_ctx_create(0)
     devs = {k: DeviceProblem(ctx, p) for k, p in ps.items()}
-    return ctx, ps, devs
+    yield ctx, ps, devs
+    # the batch's workspace (~144 GiB) stays in torch's cache after the test: hand it back before
+    # later tests carve small blocks out of it
+    del devs
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
 
 
 @pytest.mark.timeout(900)

@@ -32,6 +32,7 @@ def setup():
     from paper_1812_03717_amd import sgw
     from paper_1812_03717_amd.workload import DeviceProblem
     p = synth.si64()
+    torch.cuda.empty_cache()  # the solve's ~144 GiB workspace needs the blocks earlier tests left cached
     ctx = sgw.sgw_ctx_create(0)
     dev = DeviceProblem(ctx, p)
     print(f"si64: {p.n_pw_kq} PW, n_occ {p.n_occ}, {p.n_solves} solves", flush=True)
