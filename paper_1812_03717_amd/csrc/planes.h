@@ -585,8 +585,11 @@ void k_planes_pair(double2 *__restrict__ T, int n2, int n_stick, const int4 *__r
 //   x[3m + r] = sum_rho Y_r[rho] w_L^(m rho),  Y_r[rho] = sum_{k in window, k = rho mod L} X[k] w_N^(r k)
 // and the forward's window outputs are
 //   X'[k] = sum_r w_N^(-r k) Z_r[k mod L],      Z_r = forward L-point transform of x'[3m + r].
-// The three residues' forward contributions are added through LDS (r = 2 writes, r = 1 and r = 0 add
-// in turn).  Window slot s of a line holds k = s (s < N/4) or k = s + N/2 (s >= N/4).
+// The three residues' forward contributions are added through LDS: along axis 0 (columns) in three
+// rounds (r = 2 writes, r = 1 and r = 0 add in turn); along axis 1 (rows) each residue stores its Z_r
+// in the row (3L = N columns), and then one thread per (row, third of the window slots) sums the
+// three residues of its slots in the same order and writes them back.  Window slot s of a line holds
+// k = s (s < N/4) or k = s + N/2 (s >= N/4).
 template <int N0, int N1> constexpr bool tri_planes_fit() {
   return N0 % 12 == 0 && N1 % 12 == 0 && N0 >= 24 && N1 >= 24 && N0 <= 72 && N1 <= 72;
 }
@@ -622,6 +625,29 @@ __device__ __forceinline__ void tri_unfold_r(int r, const double2 *z, double2 *d
   if (r == 0) tri_unfold<N, 0, ADD>(z, dst, stride);
   else if (r == 1) tri_unfold<N, 1, ADD>(z, dst, stride);
   else tri_unfold<N, 2, ADD>(z, dst, stride);
+}
+
+// window slots s of block G (s in [G H/3, (G + 1) H/3), column k = s or s + N/2) of a line whose
+// residue transforms Z_r sit at line[r * L + m]: o[j] = (w^(-2k) Z_2 + w^(-k) Z_1) + Z_0 at k mod L
+template <int N, int G>
+__device__ __forceinline__ void tri_gather(const double2 *line, double2 *o) {
+  constexpr int L = N / 3, Q = N / 4, H = N / 2, HB = H / 3;
+#pragma unroll
+  for (int j = 0; j < HB; ++j) {
+    const int s = G * HB + j;
+    const int k = s < Q ? s : s + H;
+    const double2 c2 = twiddle_c<N, -1>(line[2 * L + k % L], 2 * k);
+    o[j] = c_add(c_add(c2, twiddle_c<N, -1>(line[L + k % L], k)), line[k % L]);
+  }
+}
+template <int N, int G>
+__device__ __forceinline__ void tri_scatter(const double2 *o, double2 *line) {
+  constexpr int Q = N / 4, H = N / 2, HB = H / 3;
+#pragma unroll
+  for (int j = 0; j < HB; ++j) {
+    const int s = G * HB + j;
+    line[s < Q ? s : s + H] = o[j];
+  }
 }
 
 template <int N0, int N1>
@@ -709,7 +735,8 @@ void k_planes_tri(double2 *__restrict__ T, int n2, int n_stick, const int4 *__re
     __syncthreads();
   }
 
-  // ---- axis 1, forward: (residue, stick row) per thread; window column k <- sum of residues ----
+  // ---- axis 1, forward: (residue, stick row) per thread for the transforms; then the window
+  //      columns of a row are summed over the residues by (slot block, stick row) threads ----
   {
     double2 x[L1];
     if (row_act) {
@@ -718,29 +745,29 @@ void k_planes_tri(double2 *__restrict__ T, int n2, int n_stick, const int4 *__re
       half_line_dft<L1, -1>(x);
     }
     __syncthreads();  // the row's real-space values have been read
-    // window column slot s sits at column s (s < N1/4) or s + N1/2
-    if (row_act && rr == 2) {
+    if (row_act) {  // Z_rr at columns rr * L1 + m of the row
 #pragma unroll
-      for (int s = 0; s < H1; ++s) {
-        const int k = s < Q1 ? s : s + H1;
-        buf[srow][k] = twiddle_c<N1, -1>(x[k % L1], 2 * k);
-      }
+      for (int m = 0; m < L1; ++m) buf[srow][rr * L1 + m] = x[m];
     }
     __syncthreads();
-    if (row_act && rr == 1) {
-#pragma unroll
-      for (int s = 0; s < H1; ++s) {
-        const int k = s < Q1 ? s : s + H1;
-        buf[srow][k] = c_add(buf[srow][k], twiddle_c<N1, -1>(x[k % L1], k));
-      }
+    // block g of the window slots (H1 / 3 of them) of row tg; with at least three waves, block g is
+    // wave g (the compile-time slots then do not diverge within a wave)
+    constexpr int HB = H1 / 3;
+    const int g = NT >= 192 ? tid >> 6 : (n_row > 0 ? tid / n_row : 3);
+    const int tg = NT >= 192 ? (tid & 63) : tid - g * n_row;
+    const bool gact = g < 3 && tg < n_row;
+    const int grow = slot_of(m0_lo + (gact ? tg : 0));
+    double2 o[HB];
+    if (gact) {
+      if (g == 0) tri_gather<N1, 0>(&buf[grow][0], o);
+      else if (g == 1) tri_gather<N1, 1>(&buf[grow][0], o);
+      else tri_gather<N1, 2>(&buf[grow][0], o);
     }
-    __syncthreads();
-    if (row_act && rr == 0) {
-#pragma unroll
-      for (int s = 0; s < H1; ++s) {
-        const int k = s < Q1 ? s : s + H1;
-        buf[srow][k] = c_add(buf[srow][k], x[k % L1]);
-      }
+    __syncthreads();  // every row's residue transforms have been read
+    if (gact) {
+      if (g == 0) tri_scatter<N1, 0>(o, &buf[grow][0]);
+      else if (g == 1) tri_scatter<N1, 1>(o, &buf[grow][0]);
+      else tri_scatter<N1, 2>(o, &buf[grow][0]);
     }
     __syncthreads();
   }
