@@ -1244,7 +1244,7 @@ static sgw_status multishift_solve(sgw_ctx *ctx, const sgw_ham *h_kq, int n_occ,
       p_fillpairs[nfill] = pr;
       ++nfill;
     }
-    // the slots that take steps this round: with a pooled basis, those whose next steps' vectors
+    // the slots that take steps in this pass of the scheduler: with a pooled basis, those whose next steps' vectors
     // are mapped; when none of the running pairs can grow (and none was just admitted), the least
     // advanced one gives its blocks back and restarts later
     std::vector<int> run;
