@@ -47,3 +47,27 @@ def test_aaa_errors(sgw):
         sgw.sgw_aaa_fit([1j, 1j], [1.0, 2.0])          # repeated point
     with pytest.raises(sgw.SgwError):
         sgw.sgw_aaa_fit([1j, 2j], [1.0, np.nan])
+
+
+def test_aaa_special_cases(sgw):
+    """A constant needs one support point; a single pole is exact with two (r = (a z + b) / (z - p)
+    has type (1, 1)); max_terms caps the support; two points allow one support point."""
+    z = 1j * np.linspace(0.1, 3.0, 25)
+    zs, fs, ws = sgw.sgw_aaa_fit(z, np.full(25, 0.7 - 0.2j), tol=1e-13)
+    assert len(zs) == 1 and np.allclose(so.aaa_eval(zs, fs, ws, [0.3, -1.0 + 0.5j]), 0.7 - 0.2j, rtol=0, atol=1e-15)
+    p = 0.4 - 0.1j
+    f = lambda x: (2.0 * x + 1.0) / (x - p)
+    zs, fs, ws = sgw.sgw_aaa_fit(z, f(z), tol=1e-13)
+    assert len(zs) <= 3
+    x = np.linspace(-2.0, 2.0, 41) + 0.05j
+    assert np.abs(so.aaa_eval(zs, fs, ws, x) - f(x)).max() <= 1e-10 * np.abs(f(x)).max()
+    zs, _, _ = sgw.sgw_aaa_fit(z, _rational(z), tol=0.0, max_terms=4)
+    assert len(zs) == 4
+    # two points: at most n - 1 = 1 support point (the Loewner matrix needs a remaining row), the one
+    # farthest from the mean first; both sides agree
+    z2, f2 = np.array([0.5j, 2.0j]), np.array([1.0 + 1.0j, -0.5j])
+    zs, fs, ws = sgw.sgw_aaa_fit(z2, f2, tol=0.0)
+    zo, fo, wo = so.aaa(z2, f2, tol=0.0)
+    assert len(zs) == 1 and np.array_equal(zs, zo) and np.array_equal(fs, fo)
+    e_qp, zf = sgw.sgw_quasiparticle((np.array([1j]), np.array([0.1 + 0.0j]), np.array([1.0 + 0.0j])), 0.2, 0.05)
+    assert abs(zf - 1.0) < 1e-15 and abs(e_qp - (0.2 + 0.1 + 0.05)) < 1e-15   # a constant: Z = 1
