@@ -356,6 +356,14 @@ def green_pair_elements_lu(h: np.ndarray, psi_n: np.ndarray, miller_k, miller_km
     return t.conj() @ x
 
 
+def sigma_c(m_elem: np.ndarray, wbar_at: np.ndarray, weights, volume: float, alpha: complex) -> np.ndarray:
+    """Diagonal matrix element of the correlation self-energy (Sec. 2.4, Eq. 10): alpha / (2 pi Omega)
+    sum_j w_j sum_{G,G'} W_bar_{GG'}(w'_j - w_k) M_{GG'}(z_j), with alpha = -1 along the imaginary axis and
+    alpha = i along the real axis.  Shapes as in sigma_c_imag."""
+    w = np.asarray(weights, float)
+    return alpha * np.einsum("j,kjgh,jgh->k", w, wbar_at, m_elem) / (2.0 * np.pi * volume)
+
+
 def sigma_c_imag(m_elem: np.ndarray, wbar_at: np.ndarray, weights, volume: float) -> np.ndarray:
     """Diagonal matrix element of the correlation self-energy on the imaginary axis (Sec. 2.4, Eq. 10 with
     alpha = -1): Sigma(i w_k) = -(1 / (2 pi Omega)) sum_j w_j sum_{G,G'} W_bar_{GG'}(i (w'_j - w_k)) M_{GG'}(mu + i w'_j),

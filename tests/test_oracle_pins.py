@@ -621,13 +621,42 @@ def check_spectral_and_quasiparticle():
     assert abs(eq - eps - (s0.real + s1 * (eq - eps)) - delta) <= 1e-15
 
 
+def check_sigma_plasmon_pole():
+    """Eq. 10 for one state and one plane wave with a plasmon-pole W_bar(nu) = A [1/(nu - Om + i eta) -
+    1/(nu + Om - i eta)] and the time-ordered G(w') = 1/(w' - eps + i eta sgn(eps - mu)): closing the
+    contour gives Sigma(w) = A / (w - eps - Om + 2 i eta) for an empty state and A / (w - eps + Om - 2 i eta)
+    for an occupied one; along the imaginary axis (alpha = -1, G(mu + i w'), W_bar(i nu) = A [1/(i nu - Om) -
+    1/(i nu + Om)]) the same poles give Sigma(mu + i w) = A / (mu + i w - eps -+ Om).  The oracle's sums on
+    a fine uniform grid (trapezoid, exponentially accurate for these analytic integrands; 1/w'^3 tails)
+    must match to 1e-6."""
+    amp, om, eta, mu = 0.7, 0.9, 0.1, 0.0
+    h, lim = 0.005, 200.0
+    wp = np.arange(-lim, lim + h / 2, h)
+    wq = np.full(len(wp), h)
+    for eps in (0.5, -0.4):
+        s = 1.0 if eps > mu else -1.0
+        g_real = (1.0 / (wp - eps + 1j * eta * s))[:, None, None]
+        g_imag = (1.0 / (mu + 1j * wp - eps))[:, None, None]
+        for w in (-0.3, 0.2, 1.1):
+            nu = wp - w
+            wb = amp * (1.0 / (nu - om + 1j * eta) - 1.0 / (nu + om - 1j * eta))
+            sig = so.sigma_c(g_real, wb[None, :, None, None], wq, 1.0, 1j)[0]
+            ref = amp / (w - eps - s * om + 2j * s * eta)
+            assert abs(sig - ref) <= 1e-6 * abs(ref), (eps, w, sig, ref)
+            wi = amp * (1.0 / (1j * nu - om) - 1.0 / (1j * nu + om))
+            ref_i = amp / (mu + 1j * w - eps - s * om)
+            for sig_i in (so.sigma_c(g_imag, wi[None, :, None, None], wq, 1.0, -1.0)[0],
+                          so.sigma_c_imag(g_imag, wi[None, :, None, None], wq, 1.0)[0]):
+                assert abs(sig_i - ref_i) <= 1e-6 * abs(ref_i), (eps, w, sig_i, ref_i)
+
+
 PINS = [check_kinetic_closed_form, check_hamiltonian_bruteforce, check_shifted_source_realspace,
         check_free_electron_closed_form, check_mpmath_tiny, check_routes_and_invariants,
         check_linearity_and_reciprocity, check_relative_residual_closed_form, check_condition_number_svd,
         check_green_free_electron, check_green_routes_and_symmetry, check_nonlocal_translation,
         check_nonlocal_secular, check_density_response_free_electron, check_density_response_routes,
         check_coulomb_truncation, check_green_pair_free_electron, check_green_pair_routes, check_aaa_rational,
-        check_spectral_and_quasiparticle]
+        check_spectral_and_quasiparticle, check_sigma_plasmon_pole]
 
 
 @pytest.mark.parametrize("pin", PINS + [check_generator_ground_state], ids=lambda f: f.__name__)
@@ -679,6 +708,7 @@ _orig_wbar = so.screened_correlation
 _orig_coul = so.coulomb
 _orig_gpe = so.green_pair_elements_spectral
 _orig_sig = so.sigma_c_imag
+_orig_sigma = so.sigma_c
 _orig_aaa = so.aaa
 _orig_spec_fn = so.spectral_function
 _orig_qp = so.quasiparticle
@@ -756,6 +786,9 @@ MUTATIONS = {
     "sigma_sign": ("sigma_c_imag", lambda *a: -_orig_sig(*a)),
     "sigma_no_volume": ("sigma_c_imag", lambda m, w, q, vol: _orig_sig(m, w, q, 1.0)),
     "sigma_w_transposed": ("sigma_c_imag", lambda m, w, q, vol: _orig_sig(m, np.swapaxes(w, 2, 3), q, vol)),
+    "sigma_alpha_conjugated": ("sigma_c", lambda m, w, q, vol, a: _orig_sigma(m, w, q, vol, np.conj(a))),
+    "sigma_alpha_dropped": ("sigma_c", lambda m, w, q, vol, a: _orig_sigma(m, w, q, vol, 1.0)),
+    "sigma_no_2pi": ("sigma_c", lambda m, w, q, vol, a: 2 * np.pi * _orig_sigma(m, w, q, vol, a)),
     "aaa_unconjugated_weights": ("aaa", lambda zs, fs, tol=1e-13, mmax=100: (lambda r: (r[0], r[1], np.conj(r[2])))(
         _orig_aaa(zs, fs, tol, mmax))),
     "spectral_sign": ("spectral_function", lambda *a: -_orig_spec_fn(*a)),
