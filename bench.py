@@ -482,21 +482,34 @@ def sigma_frequencies(n_int=32, n_out=12, h=0.25):
 
 
 def bench_sigma(args, log, problem, ctx, dev):
-    """The correlation self-energy path of the top STATES bands on one GPU: W_bar on the imaginary-axis
-    mesh comes first, untimed (solves at +-i nu over all bands, density response, eps^-1); one step is
-    then the Green's function pair elements (multishift solves at mu + i w'_j for every state and
-    wave vector), the frequency convolution Sigma^c(i w_k), an AAA fit per state, the spectral
-    function on 2001 real frequencies and the quasiparticle energies.  `value` counts the pair-element
-    solves per second of the step."""
+    """The correlation self-energy path of the top STATES bands on one GPU (Eq. 10).  Imaginary axis
+    (default): W_bar on the imaginary-axis mesh first, untimed (solves at +-i nu over all bands,
+    density response, eps^-1); one step is then the Green's function pair elements (multishift solves
+    at mu + i w'_j for every state and wave vector), the frequency convolution Sigma^c(i w_k), an AAA
+    fit per state, the spectral function on 2001 real frequencies and the quasiparticle energies.
+    Real axis (--sigma-axis real): W_bar at the real differences nu + i eta (eta = 0.15 eV), untimed;
+    one step is the pair elements at the time-ordered w'_j + i eta sgn(w'_j - mu) and Sigma^c(w_k)
+    with alpha = i.  `value` counts the pair-element solves per second of the step."""
     import torch
     from paper_1812_03717_amd import sgw
     p = problem
+    real = args.sigma_axis == "real"
     n_st = min(args.sigma, p.n_band)
     max_iter = args.max_iter or (3500 if args.workload in ("si64", "si64nl") else 0)
     kw = {"max_iter": max_iter} if max_iter else {}
-    w_int, q_int, w_out, nu, w_index = sigma_frequencies()
+    mu = 0.5 * (p.eps_kq[p.n_occ - 1] + p.eps_kq[p.n_occ])
+    eta_r = 0.15 / 27.211386245988
+    if real:
+        # w'_j = mu + h (j + 1/2), j = -32..31 (h = 0.125 Ha), outputs mu + h k, k = -8..7
+        w_int, q_int, w_out, nu, w_index = sigma_frequencies(n_int=64, n_out=16, h=0.125)
+        w_int, w_out = mu + w_int, mu + w_out - 8 * 0.125
+        diff = w_int[None, :] - w_out[:, None]
+        nu, inv = np.unique(np.round(diff, 12), return_inverse=True)
+        w_index = inv.reshape(diff.shape).astype(np.int32)
+    else:
+        w_int, q_int, w_out, nu, w_index = sigma_frequencies()
     ws = sgw.Workspace(ctx)
-    # W_bar(i nu) from all bands, in chunks of 32 bands (untimed)
+    # W_bar from all bands, in chunks of 32 bands (untimed)
     t = time.perf_counter()
     nbc = min(32, p.n_band)
     zero = np.zeros(len(nu))
@@ -506,21 +519,27 @@ def bench_sigma(args, log, problem, ctx, dev):
         psi = dev.psi_v[c0:c0 + nb].contiguous()
         sols = []
         for sgn in (1.0, -1.0):
-            o = sgw.sgw_opts_default(shift_imag=sgn * nu, **kw)
-            st, x, _ = sgw.sternheimer_solve(ctx, dev.h_kq, dev.psi_occ_kq, dev.h_k, psi, dev.eps_v[c0:c0 + nb],
-                                             p.dv_miller, zero, 0.0, p.tol, opts=o, workspace=ws)
+            if real:
+                o = sgw.sgw_opts_default(**kw)
+                st, x, _ = sgw.sternheimer_solve(ctx, dev.h_kq, dev.psi_occ_kq, dev.h_k, psi, dev.eps_v[c0:c0 + nb],
+                                                 p.dv_miller, sgn * nu, sgn * eta_r, p.tol, opts=o, workspace=ws)
+            else:
+                o = sgw.sgw_opts_default(shift_imag=sgn * nu, **kw)
+                st, x, _ = sgw.sternheimer_solve(ctx, dev.h_kq, dev.psi_occ_kq, dev.h_k, psi, dev.eps_v[c0:c0 + nb],
+                                                 p.dv_miller, zero, 0.0, p.tol, opts=o, workspace=ws)
             sols.append(x)
         sgw.sgw_density_response(ctx, dev.h_kq, dev.psi_occ_kq, dev.h_k, psi, p.dv_miller, sols[0], sols[1], chi=chi,
                                  accumulate=c0 > 0)
         del sols
-        log(f"  W_bar: bands {c0}..{c0 + nb - 1} at +-i nu ({len(nu)} frequencies), status {st}")
+        log(f"  W_bar: bands {c0}..{c0 + nb - 1} at +-{'(nu + i eta)' if real else 'i nu'} ({len(nu)} frequencies), "
+            f"status {st}")
     _, _, wbar = sgw.sgw_screened_coulomb(ctx, dev.h_kq, dev.h_k, p.dv_miller, chi)
     torch.cuda.synchronize()
-    log(f"W_bar on {len(nu)} imaginary frequencies: {time.perf_counter() - t:.1f} s (untimed)")
+    log(f"W_bar on {len(nu)} {'real' if real else 'imaginary'} frequencies: {time.perf_counter() - t:.1f} s (untimed)")
     states = list(range(p.n_band - n_st, p.n_band))
     psi_n = dev.psi_v[states[0]:].contiguous()
     eps_n = np.asarray(p.eps_k[states], np.float64)
-    mu = 0.5 * (p.eps_kq[p.n_occ - 1] + p.eps_kq[p.n_occ])
+    z_g = w_int + 1j * eta_r * np.sign(w_int - mu) if real else mu + 1j * w_int
     opts = sgw.sgw_opts_default(**kw)
     omega = np.linspace(-1.0, 1.0, 2001)
     vol = float(abs(np.linalg.det(p.A)))
@@ -530,17 +549,20 @@ def bench_sigma(args, log, problem, ctx, dev):
     def step():
         nonlocal n_ok
         t0 = time.perf_counter()
-        st, m, info = sgw.sgw_green_pair_elements(ctx, dev.h_kq, dev.h_k, psi_n, p.dv_miller, mu, w_int, p.tol,
-                                                  opts=opts, workspace=ws)
+        st, m, info = sgw.sgw_green_pair_elements(ctx, dev.h_kq, dev.h_k, psi_n, p.dv_miller, z_g, p.tol, opts=opts,
+                                                  workspace=ws)
         inf = sgw.info_to_numpy(info)
         n_ok += int(np.count_nonzero((inf["flags"] & sgw.FLAG_CONVERGED) != 0))
         t1 = time.perf_counter()
-        sig = sgw.sgw_sigma_c(ctx, m, q_int, wbar, w_index, vol).cpu().numpy()
+        sig = sgw.sgw_sigma_c(ctx, m, q_int, wbar, w_index, vol, alpha=1j if real else -1.0).cpu().numpy()
         t2 = time.perf_counter()
-        fits = [sgw.sgw_aaa_fit(1j * w_out, sig[n], tol=1e-12) for n in range(n_st)]
+        qp = []
+        if not real:
+            fits = [sgw.sgw_aaa_fit(1j * w_out, sig[n], tol=1e-12) for n in range(n_st)]
         t3 = time.perf_counter()
-        _, a = sgw.sgw_spectral_function(ctx, fits, omega, 1e-3, eps_n, np.zeros(n_st))
-        qp = [sgw.sgw_quasiparticle(f, e, 0.0) for f, e in zip(fits, eps_n)]
+        if not real:
+            _, a = sgw.sgw_spectral_function(ctx, fits, omega, 1e-3, eps_n, np.zeros(n_st))
+            qp = [sgw.sgw_quasiparticle(f, e, 0.0) for f, e in zip(fits, eps_n)]
         torch.cuda.synchronize()
         t4 = time.perf_counter()
         for k, dt in zip(stage, (t1 - t0, t2 - t1, t3 - t2, t4 - t3)):
@@ -562,19 +584,27 @@ def bench_sigma(args, log, problem, ctx, dev):
     el = time.perf_counter() - t0
     n_solves = n_st * p.n_pert * len(w_int)
     log(f"timed: {args.steps} steps in {el:.3f} s; converged {n_ok}/{n_solves * args.steps}")
-    print(json.dumps({
-        "metric": "Green's function pair-element solves/s (state x wave vector x imaginary frequency) through "
-                  "Sigma^c, AAA continuation and A(w)",
+    if real:
+        desc = (f"; Sigma^c of the top {n_st} bands along the real axis: pair elements at w' + i eta sgn(w' - mu) "
+                f"({len(w_int)} frequencies, h 0.125 Ha, eta 0.15 eV), W_bar at {len(nu)} frequencies nu + i eta "
+                f"(untimed), Sigma^c at {len(w_out)} frequencies (alpha = i)")
+    else:
+        desc = (f"; Sigma^c of the top {n_st} bands: pair elements at mu + i w' ({len(w_int)} midpoint frequencies, "
+                f"h 0.25 Ha), W_bar at {len(nu)} frequencies (untimed), Sigma^c at {len(w_out)} frequencies, AAA, "
+                f"A(w) on 2001 points")
+    out = {
+        "metric": "Green's function pair-element solves/s (state x wave vector x frequency) through Sigma^c"
+                  + ("" if real else ", AAA continuation and A(w)"),
         "value": round(n_ok / el, 1), "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(1e3 * el / args.steps, 3), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": WORKLOADS[args.workload] + f"; Sigma^c of the top {n_st} bands: pair elements at "
-                   f"mu + i w' ({len(w_int)} midpoint frequencies, h 0.25 Ha), W_bar at {len(nu)} frequencies "
-                   f"(untimed), Sigma^c at {len(w_out)} frequencies, AAA, A(w) on 2001 points",
+        "config": {"workload": WORKLOADS[args.workload] + desc, "axis": args.sigma_axis,
                    "solves_per_step": n_solves, "max_iter": max_iter or 600},
         "stage_ms_per_step": {k: round(1e3 * sum(v) / args.steps, 3) for k, v in stage.items()},
-        "sigma_c_top_state_iw0": [float(sig[-1, 0].real), float(sig[-1, 0].imag)],
-        "z_factors": [round(z, 4) for _, z in qp]}))
+        "sigma_c_top_state_w0": [float(sig[-1, 0].real), float(sig[-1, 0].imag)]}
+    if qp:
+        out["z_factors"] = [round(z, 4) for _, z in qp]
+    print(json.dumps(out))
 
 
 def main():
@@ -606,6 +636,8 @@ def main():
     ap.add_argument("--sigma", type=int, default=0, metavar="STATES",
                     help="time the self-energy path of the top STATES bands instead (W_bar untimed): Green's "
                          "function pair elements, Sigma^c on the imaginary axis, AAA, A(w), E_qp")
+    ap.add_argument("--sigma-axis", choices=["imag", "real"], default="imag",
+                    help="frequency convolution of --sigma along the imaginary axis (then AAA) or the real axis")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 5 device-to-device copies of MIB MiB (HBM counter calibration) and exit")
     args = ap.parse_args()

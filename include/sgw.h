@@ -401,13 +401,15 @@ sgw_status sternheimer_solve(sgw_ctx *ctx, const sgw_ham *h_kq, int n_occ, const
 /*
  * Pair elements of the Green's function for the correlation self-energy (Sec. 2.4, Eq. 10; Sec. 2.2):
  *     m[n][j][g][h] = < t_{n,g} | (z_j - H)^{-1} | t_{n,h} >,   t_{n,g} = exp(-i (q+G_g) . r) u_n,
- * z_j = mu + i w_imag[j] (mu: the chemical potential, in the gap), q = k of h_k minus k of h_kmq,
- * G_g = g_miller[g] on h_kmq's reciprocal lattice.  All z_j of one (n, h) share one Krylov space (the
- * multishift solver with per-shift imaginary parts, no occupied projector, zero band energy: the
- * solve of (H - z_j) x = -t_{n,h}); the bra is a plane-wave contraction on the FP64 matrix cores.
+ * z_j = z_re[j] + i z_im[j], q = k of h_k minus k of h_kmq, G_g = g_miller[g] on h_kmq's reciprocal
+ * lattice.  On the imaginary axis z_j = mu + i w'_j (mu: the chemical potential, in the gap); on the
+ * real axis z_j = w'_j + i eta_j with the sign of eta_j chosen by the caller for the time ordering
+ * (positive above mu, negative below).  All z_j of one (n, h) share one Krylov space (the multishift
+ * solver with per-shift imaginary parts, no occupied projector, zero band energy: the solve of
+ * (H - z_j) x = -t_{n,h}); the bra is a plane-wave contraction on the FP64 matrix cores.
  *   psi_n    device [n_band][n_pw of h_k] states u_n at k (caller's order)
- *   g_miller host [n_g][3], w_imag host [n_freq] (finite)
- *   opts     solver options (NULL: defaults; its shift_imag is replaced by w_imag)
+ *   g_miller host [n_g][3]; z_re, z_im host [n_freq] (finite)
+ *   opts     solver options (NULL: defaults; its shift_imag is replaced by z_im)
  *   m_out    device [n_band][n_freq][n_g][n_g] out;  info  device [n_band][n_g][n_freq] or NULL
  *   workspace device, >= sgw_green_pair_workspace_size bytes (same sizes and opts), 256-byte aligned:
  *            the solver's workspace, the solutions (n_band n_g n_freq vectors of h_kmq's basis), the
@@ -418,21 +420,24 @@ sgw_status sternheimer_solve(sgw_ctx *ctx, const sgw_ham *h_kq, int n_occ, const
 sgw_status sgw_green_pair_workspace_size(sgw_ctx *ctx, const sgw_ham *h_kmq, int n_band, int n_g, int n_freq,
                                          const sgw_opts *opts, size_t *bytes);
 sgw_status sgw_green_pair_elements(sgw_ctx *ctx, const sgw_ham *h_kmq, const sgw_ham *h_k, int n_band,
-                                   const sgw_c128 *psi_n, int n_g, const int32_t *g_miller, double mu, int n_freq,
-                                   const double *w_imag, double tol, const sgw_opts *opts, void *workspace,
-                                   size_t workspace_bytes, sgw_c128 *m_out, sgw_solve_info *info);
+                                   const sgw_c128 *psi_n, int n_g, const int32_t *g_miller, int n_freq,
+                                   const double *z_re, const double *z_im, double tol, const sgw_opts *opts,
+                                   void *workspace, size_t workspace_bytes, sgw_c128 *m_out,
+                                   sgw_solve_info *info);
 
 /*
- * Diagonal correlation self-energy on the imaginary axis (Sec. 2.4, Eq. 10 with alpha = -1):
- *     sigma[n][k] = -(1 / (2 pi volume)) sum_j weights[j] sum_{g,h} wbar[w_index[k][j]][g][h] m_elem[n][j][g][h]
- * the integration frequencies w'_j of m_elem (sgw_green_pair_elements) weighted by weights[j], W_bar
- * (sgw_screened_coulomb) taken at i (w'_j - w_k) through w_index (host [n_out][n_freq], values
+ * Diagonal correlation self-energy (Sec. 2.4, Eq. 10):
+ *     sigma[n][k] = (alpha / (2 pi volume)) sum_j weights[j] sum_{g,h} wbar[w_index[k][j]][g][h] m_elem[n][j][g][h]
+ * alpha = alpha_re + i alpha_im: -1 for the convolution along the imaginary axis (frequencies i w'_j,
+ * W_bar at i (w'_j - w_k)), i along the real axis (W_bar at w'_j - w_k).  m_elem: the pair elements at
+ * the integration frequencies (sgw_green_pair_elements), weighted by weights[j]; W_bar
+ * (sgw_screened_coulomb) at the needed differences through w_index (host [n_out][n_freq], values
  * < n_w).  volume: the unit cell's, bohr^3.
  *   m_elem device [n_band][n_freq][n_g][n_g]; wbar device [n_w][n_g][n_g]; sigma device [n_band][n_out]
  */
 sgw_status sgw_sigma_c(sgw_ctx *ctx, int n_band, int n_g, int n_freq, const sgw_c128 *m_elem, const double *weights,
                        int n_w, const sgw_c128 *wbar, int n_out, const int32_t *w_index, double volume,
-                       sgw_c128 *sigma);
+                       double alpha_re, double alpha_im, sgw_c128 *sigma);
 
 /*
  * Rational approximation of f at the points z by the adaptive Antoulas-Anderson algorithm (Sec. 2.7):

@@ -1,13 +1,14 @@
-// Correlation self-energy on the imaginary axis (Sec. 2.4, Eq. 10), its rational continuation to the
-// real axis by AAA (Sec. 2.7), the spectral function and the linearised quasiparticle energy
-// (Sec. 2.8, Eqs. 16-17).
+// Correlation self-energy (Sec. 2.4, Eq. 10) on the imaginary axis or the real axis, its rational
+// continuation to the real axis by AAA (Sec. 2.7), the spectral function and the linearised
+// quasiparticle energy (Sec. 2.8, Eqs. 16-17).
 //
 // The diagonal element of Eq. 10 in a state n, with G and W_bar expanded in the plane waves q + G of
 // W_bar, is
-//     Sigma_n(i w) = -(1 / (2 pi Omega)) sum_j w_j sum_{G,G'} W_bar_{GG'}(i (w'_j - w)) < t_G | G(mu + i w'_j) | t_G' >,
-// t_G = exp(-i (q+G) . r) u_n at k - q.  The pair elements come from the multishift solver: with no
-// occupied projector and a zero band energy, the solve of (H - z) x = -t_G' for all shifts
-// z_j = mu + i w'_j at once gives x = G(z_j) t_G' (the shifts now differ in their imaginary parts), and
+//     Sigma_n(w) = (alpha / (2 pi Omega)) sum_j w_j sum_{G,G'} W_bar_{GG'}(w'_j - w) < t_G | G(z_j) | t_G' >,
+// t_G = exp(-i (q+G) . r) u_n at k - q, alpha = -1 on the imaginary axis (z_j = mu + i w'_j) and i on the
+// real axis (z_j = w'_j shifted off the axis by the caller).  The pair elements come from the multishift
+// solver: with no occupied projector and a zero band energy, the solve of (H - z) x = -t_G' for all
+// shifts z_j at once gives x = G(z_j) t_G' (each shift with its own imaginary part), and
 // the bra is the same plane-wave shift of u_n (minus the right-hand side of that solve): an overlap
 // contraction on the FP64 matrix cores, as for the density response.  The frequency convolution is a
 // small reduction per (n, w) on the GPU.  AAA is a greedy sequence of small SVDs (a few hundred
@@ -45,10 +46,11 @@ __global__ void k_pair_store(const double2 *__restrict__ c, int n_g, int n_freq,
   m[e] = make_double2(-t.x, -t.y);
 }
 
-// sigma[n][k] = scale * sum_j w_j sum_{g,h} wbar[idx[k][j]][g][h] m[n][j][g][h]; one workgroup per (n, k)
+// sigma[n][k] = scale * sum_j w_j sum_{g,h} wbar[idx[k][j]][g][h] m[n][j][g][h] (complex scale); one
+// workgroup per (n, k)
 __global__ __launch_bounds__(256) void k_sigma(int n_g, int n_freq, int n_out, const double2 *__restrict__ m,
                                                const double *__restrict__ wq, const double2 *__restrict__ wbar,
-                                               const int32_t *__restrict__ idx, double scale,
+                                               const int32_t *__restrict__ idx, double2 scale,
                                                double2 *__restrict__ sigma) {
   __shared__ double2 part[256];
   const int n = blockIdx.x / n_out, k = blockIdx.x - n * n_out;
@@ -68,7 +70,7 @@ __global__ __launch_bounds__(256) void k_sigma(int n_g, int n_freq, int n_out, c
     if (threadIdx.x < s) part[threadIdx.x] = c_add(part[threadIdx.x], part[threadIdx.x + s]);
     __syncthreads();
   }
-  if (threadIdx.x == 0) sigma[(long)n * n_out + k] = make_double2(scale * part[0].x, scale * part[0].y);
+  if (threadIdx.x == 0) sigma[(long)n * n_out + k] = c_mul(scale, part[0]);
 }
 
 // Sigma^c(w + i d) from each state's barycentric approximant, and A(w) of Eq. 16
@@ -208,22 +210,22 @@ extern "C" sgw_status sgw_green_pair_workspace_size(sgw_ctx *ctx, const sgw_ham 
 }
 
 extern "C" sgw_status sgw_green_pair_elements(sgw_ctx *ctx, const sgw_ham *h_kmq, const sgw_ham *h_k, int n_band,
-                                              const sgw_c128 *psi_n, int n_g, const int32_t *g_miller, double mu,
-                                              int n_freq, const double *w_imag, double tol, const sgw_opts *opts,
+                                              const sgw_c128 *psi_n, int n_g, const int32_t *g_miller, int n_freq,
+                                              const double *z_re, const double *z_im, double tol, const sgw_opts *opts,
                                               void *workspace, size_t workspace_bytes, sgw_c128 *m_out,
                                               sgw_solve_info *info) {
   if (!ctx || !h_kmq || !h_k) return fail(SGW_ERR_INVALID_ARG, "sgw_green_pair_elements: NULL context or Hamiltonian");
   if (n_band < 0 || n_g < 0 || n_freq < 0) return fail(SGW_ERR_INVALID_ARG, "sgw_green_pair_elements: negative size");
   if ((long)n_band * n_g * n_freq == 0) return SGW_OK;
-  if (!psi_n || !g_miller || !w_imag || !m_out)
+  if (!psi_n || !g_miller || !z_re || !z_im || !m_out)
     return fail(SGW_ERR_INVALID_ARG, "sgw_green_pair_elements: NULL array");
-  if (!std::isfinite(mu)) return fail(SGW_ERR_INVALID_ARG, "sgw_green_pair_elements: mu not finite");
   for (int j = 0; j < n_freq; ++j)
-    if (!std::isfinite(w_imag[j])) return fail(SGW_ERR_INVALID_ARG, "sgw_green_pair_elements: frequency not finite");
+    if (!std::isfinite(z_re[j]) || !std::isfinite(z_im[j]))
+      return fail(SGW_ERR_INVALID_ARG, "sgw_green_pair_elements: frequency not finite");
   sgw_opts o;
   if (opts) o = *opts;
   else sgw_opts_default(&o);
-  o.shift_imag = w_imag;
+  o.shift_imag = z_im;
   PairLayout L;
   sgw_status st = pair_layout(ctx, h_kmq, n_band, n_g, n_freq, &o, &L);
   if (st != SGW_OK) return st;
@@ -238,11 +240,11 @@ extern "C" sgw_status sgw_green_pair_elements(sgw_ctx *ctx, const sgw_ham *h_kmq
   sgw_solve_info *inf_p = info ? info : (sgw_solve_info *)(w + L.info);
   std::vector<int32_t> dv(3 * (size_t)n_g);
   for (int i = 0; i < 3 * n_g; ++i) dv[i] = -g_miller[i];  // t_G = exp(-i (q+G) . r) u_n
-  std::vector<double> zero_eps(n_band, 0.0), om(n_freq, mu);
+  std::vector<double> zero_eps(n_band, 0.0);
   const int npw = h_kmq->n_pw;
-  // x = (H - z_j)^{-1} (-t_G') = G(z_j) t_G' for z_j = mu + i w_j
+  // x = (H - z_j)^{-1} (-t_G') = G(z_j) t_G' for z_j = z_re[j] + i z_im[j]
   const sgw_status solved = sternheimer_solve(ctx, h_kmq, 0, nullptr, h_k, n_band, psi_n, zero_eps.data(), n_g,
-                                              dv.data(), n_freq, om.data(), 0.0, tol, &o, w + L.solver, L.x,
+                                              dv.data(), n_freq, z_re, 0.0, tol, &o, w + L.solver, L.x,
                                               (sgw_c128 *)x, inf_p);
   if (solved < 0) return solved;
   // the right-hand sides b_G = -t_G of every band
@@ -264,13 +266,15 @@ extern "C" sgw_status sgw_green_pair_elements(sgw_ctx *ctx, const sgw_ham *h_kmq
 
 extern "C" sgw_status sgw_sigma_c(sgw_ctx *ctx, int n_band, int n_g, int n_freq, const sgw_c128 *m_elem,
                                   const double *weights, int n_w, const sgw_c128 *wbar, int n_out,
-                                  const int32_t *w_index, double volume, sgw_c128 *sigma) {
+                                  const int32_t *w_index, double volume, double alpha_re, double alpha_im,
+                                  sgw_c128 *sigma) {
   if (!ctx) return fail(SGW_ERR_INVALID_ARG, "sgw_sigma_c: NULL context");
   if (n_band < 0 || n_g < 0 || n_freq < 0 || n_w < 0 || n_out < 0)
     return fail(SGW_ERR_INVALID_ARG, "sgw_sigma_c: negative size");
   if ((long)n_band * n_out == 0) return SGW_OK;
   if (!m_elem || !weights || !wbar || !w_index || !sigma) return fail(SGW_ERR_INVALID_ARG, "sgw_sigma_c: NULL array");
   if (!(volume > 0.0) || !std::isfinite(volume)) return fail(SGW_ERR_INVALID_ARG, "sgw_sigma_c: volume must be positive");
+  if (!std::isfinite(alpha_re) || !std::isfinite(alpha_im)) return fail(SGW_ERR_INVALID_ARG, "sgw_sigma_c: alpha not finite");
   for (long e = 0; e < (long)n_out * n_freq; ++e)
     if (w_index[e] < 0 || w_index[e] >= n_w) return fail(SGW_ERR_INVALID_ARG, "sgw_sigma_c: w_index out of range");
   for (int j = 0; j < n_freq; ++j)
@@ -285,7 +289,8 @@ extern "C" sgw_status sgw_sigma_c(sgw_ctx *ctx, int n_band, int n_g, int n_freq,
                          ctx->stream));
   hipLaunchKernelGGL(k_sigma, dim3((long)n_band * n_out), dim3(256), 0, ctx->stream, n_g, n_freq, n_out,
                      (const double2 *)m_elem, (const double *)dw.p, (const double2 *)wbar, (const int32_t *)di.p,
-                     -1.0 / (2.0 * M_PI * volume), (double2 *)sigma);
+                     make_double2(alpha_re / (2.0 * M_PI * volume), alpha_im / (2.0 * M_PI * volume)),
+                     (double2 *)sigma);
   SGW_HIP(hipGetLastError());
   return sync(ctx);
 }

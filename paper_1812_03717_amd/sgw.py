@@ -108,10 +108,10 @@ def load_library(path: str = LIB_PATH):
         "sgw_coulomb": [vp, vp, C.c_int, C.POINTER(i32), dbl, C.POINTER(dbl)],
         "sgw_screened_coulomb": [vp, vp, vp, C.c_int, C.POINTER(i32), dbl, C.c_int, vp, vp, vp, vp],
         "sgw_green_pair_workspace_size": [vp, vp, C.c_int, C.c_int, C.c_int, C.POINTER(sgw_opts), C.POINTER(sz)],
-        "sgw_green_pair_elements": [vp, vp, vp, C.c_int, vp, C.c_int, C.POINTER(i32), dbl, C.c_int, C.POINTER(dbl),
-                                    dbl, C.POINTER(sgw_opts), vp, sz, vp, vp],
+        "sgw_green_pair_elements": [vp, vp, vp, C.c_int, vp, C.c_int, C.POINTER(i32), C.c_int, C.POINTER(dbl),
+                                    C.POINTER(dbl), dbl, C.POINTER(sgw_opts), vp, sz, vp, vp],
         "sgw_sigma_c": [vp, C.c_int, C.c_int, C.c_int, vp, C.POINTER(dbl), C.c_int, vp, C.c_int, C.POINTER(i32), dbl,
-                        vp],
+                        dbl, dbl, vp],
         "sgw_aaa_fit": [C.c_int, vp, vp, dbl, C.c_int, C.POINTER(C.c_int), vp, vp, vp],
         "sgw_spectral_function": [vp, C.c_int, C.c_int, C.POINTER(i32), vp, vp, vp, C.c_int, C.POINTER(dbl), dbl,
                                   C.POINTER(dbl), C.POINTER(dbl), vp, vp],
@@ -382,13 +382,15 @@ def _dptr(a):
     return a.ctypes.data_as(C.POINTER(C.c_double))
 
 
-def sgw_green_pair_elements(ctx, h_kmq, h_k, psi_n, g_miller, mu, w_imag, tol, opts=None, workspace=None):
-    """(status, m [n_band][n_freq][n_g][n_g], info): <t_g| (mu + i w_j - H)^{-1} |t_h>, t_g = exp(-i(q+G_g).r) u_n."""
+def sgw_green_pair_elements(ctx, h_kmq, h_k, psi_n, g_miller, z, tol, opts=None, workspace=None):
+    """(status, m [n_band][n_freq][n_g][n_g], info): <t_g| (z_j - H)^{-1} |t_h>, t_g = exp(-i(q+G_g).r) u_n, at the
+    complex frequencies z (e.g. mu + 1j * w' on the imaginary axis)."""
     import torch
     _require(psi_n, torch.complex128, ctx.device, (psi_n.shape[0], h_k.n_pw), "psi_n")
     g = np.ascontiguousarray(np.asarray(g_miller, np.int32).reshape(-1, 3))
-    w = np.ascontiguousarray(np.asarray(w_imag, np.float64))
-    n_band, n_g, n_freq = int(psi_n.shape[0]), int(g.shape[0]), int(w.shape[0])
+    zz = np.atleast_1d(np.asarray(z, np.complex128))
+    zr, zi = np.ascontiguousarray(zz.real), np.ascontiguousarray(zz.imag)
+    n_band, n_g, n_freq = int(psi_n.shape[0]), int(g.shape[0]), int(zz.shape[0])
     lib = load_library()
     o = C.byref(opts) if opts is not None else None
     n = C.c_size_t()
@@ -397,13 +399,14 @@ def sgw_green_pair_elements(ctx, h_kmq, h_k, psi_n, g_miller, mu, w_imag, tol, o
     m = torch.empty((n_band, n_freq, n_g, n_g), dtype=torch.complex128, device=ctx.device)
     info = torch.empty(n_band * n_g * n_freq * INFO_DTYPE.itemsize, dtype=torch.uint8, device=ctx.device)
     st = _check(lib.sgw_green_pair_elements(ctx.handle, h_kmq.handle, h_k.handle, n_band, _ptr(psi_n), n_g,
-                                            g.ctypes.data_as(C.POINTER(C.c_int32)), float(mu), n_freq, _dptr(w),
+                                            g.ctypes.data_as(C.POINTER(C.c_int32)), n_freq, _dptr(zr), _dptr(zi),
                                             float(tol), o, _ptr(ws), C.c_size_t(ws.numel()), _ptr(m), _ptr(info)))
     return st, m, info
 
 
-def sgw_sigma_c(ctx, m_elem, weights, wbar, w_index, volume):
-    """sigma [n_band][n_out] on the device; w_index host int [n_out][n_freq] into wbar's frequencies."""
+def sgw_sigma_c(ctx, m_elem, weights, wbar, w_index, volume, alpha=-1.0):
+    """sigma [n_band][n_out] on the device; w_index host int [n_out][n_freq] into wbar's frequencies;
+    alpha = -1 (imaginary axis) or 1j (real axis)."""
     import torch
     n_band, n_freq, n_g = int(m_elem.shape[0]), int(m_elem.shape[1]), int(m_elem.shape[2])
     _require(m_elem, torch.complex128, ctx.device, (n_band, n_freq, n_g, n_g), "m_elem")
@@ -412,10 +415,11 @@ def sgw_sigma_c(ctx, m_elem, weights, wbar, w_index, volume):
     wq = np.ascontiguousarray(np.asarray(weights, np.float64))
     if idx.ndim != 2 or idx.shape[1] != n_freq or wq.shape != (n_freq,):
         raise ValueError("w_index must be [n_out][n_freq] and weights [n_freq]")
+    a = complex(alpha)
     sigma = torch.empty((n_band, idx.shape[0]), dtype=torch.complex128, device=ctx.device)
     _check(load_library().sgw_sigma_c(ctx.handle, n_band, n_g, n_freq, _ptr(m_elem), _dptr(wq), int(wbar.shape[0]),
                                       _ptr(wbar), int(idx.shape[0]), idx.ctypes.data_as(C.POINTER(C.c_int32)),
-                                      float(volume), _ptr(sigma)))
+                                      float(volume), a.real, a.imag, _ptr(sigma)))
     return sigma
 
 
