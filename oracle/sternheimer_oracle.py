@@ -25,9 +25,9 @@ What it computes (Hartree units; every function cites the passage it follows):
   sum over empty states and from given linear variations, the dielectric matrix
   (Eq. 4), the correlation part of the screened interaction (Sec. 2.4, Eq. 9) and
   the (optionally truncated) Coulomb potential (Sec. 2.6, Eq. 12);
-* the diagonal correlation self-energy on the imaginary axis (Sec. 2.4, Eq. 10),
-  the AAA rational continuation (Sec. 2.7), the spectral function and the
-  linearised quasiparticle energy (Sec. 2.8, Eqs. 16-17).
+* the diagonal correlation self-energy on the imaginary or the real axis (Sec. 2.4,
+  Eq. 10), the AAA and Pade rational continuations (Sec. 2.7), the spectral function
+  and the linearised quasiparticle energy (Sec. 2.8, Eqs. 16-17).
 
 The Krylov method itself is not reproduced: the iterative solver reaches
 (up to rounding) the exact solution of each shifted system, and that solution
@@ -414,6 +414,34 @@ def aaa_eval(z_sup, f_sup, w_sup, zs) -> np.ndarray:
         else:
             out[i] = np.sum(w_sup * f_sup / d) / np.sum(w_sup / d)
     return out
+
+
+def pade_coefficients(zs, fs) -> np.ndarray:
+    """Coefficients a_p of the N-point Pade interpolant in continued-fraction form (Sec. 2.7 compares it
+    with AAA; Vidberg and Serene 1977): g_1(z_i) = f_i, g_p(z_i) = (g_{p-1}(z_{p-1}) - g_{p-1}(z_i)) /
+    ((z_i - z_{p-1}) g_{p-1}(z_i)) for i >= p, a_p = g_p(z_p)."""
+    z = np.asarray(zs, complex)
+    g = np.array(fs, complex)
+    a = np.empty(len(z), complex)
+    a[0] = g[0]
+    for p in range(1, len(z)):
+        g[p:] = (g[p - 1] - g[p:]) / ((z[p:] - z[p - 1]) * g[p:])
+        a[p] = g[p]
+    return a
+
+
+def pade_eval(zs, a, x) -> np.ndarray:
+    """C(x) = a_1 / (1 + a_2 (x - z_1) / (1 + a_3 (x - z_2) / (1 + ...))), by the three-term recursion
+    A_{n+1} = A_n + (x - z_n) a_{n+1} A_{n-1} (the same for B), C = A_N / B_N."""
+    z = np.asarray(zs, complex)
+    x = np.atleast_1d(np.asarray(x, complex))
+    a_prev, a_cur = np.zeros_like(x), np.full_like(x, a[0])
+    b_prev, b_cur = np.ones_like(x), np.ones_like(x)
+    for n in range(1, len(a)):
+        t = (x - z[n - 1]) * a[n]
+        a_prev, a_cur = a_cur, a_cur + t * a_prev
+        b_prev, b_cur = b_cur, b_cur + t * b_prev
+    return a_cur / b_cur
 
 
 def spectral_function(omega, sigma, eps_n: float, delta: float) -> np.ndarray:

@@ -650,13 +650,43 @@ def check_sigma_plasmon_pole():
                 assert abs(sig_i - ref_i) <= 1e-6 * abs(ref_i), (eps, w, sig_i, ref_i)
 
 
+def check_pade():
+    """The N-point Pade interpolant: it reproduces the samples, recovers a type-(1, 1) function
+    exactly from 7 points and a 3-pole function from 13, and its three-term evaluation equals the
+    nested continued fraction a_1 / (1 + a_2 (x - z_1) / (1 + ...)) written out from the inside."""
+    pole = 0.4 - 0.1j
+    f = lambda x: (2.0 * x + 1.0) / (x - pole)
+    z = 1j * np.linspace(0.1, 3.0, 7)
+    a = so.pade_coefficients(z, f(z))
+    x = np.linspace(-2.0, 2.0, 17) + 0.05j
+    assert np.abs(so.pade_eval(z, a, z) - f(z)).max() <= 1e-13 * np.abs(f(z)).max()
+    assert np.abs(so.pade_eval(z, a, x) - f(x)).max() <= 1e-11 * np.abs(f(x)).max()
+
+    def rat(q):
+        poles = np.array([0.3 - 0.05j, -0.8 - 0.1j, 1.5 - 0.2j])
+        res = np.array([0.4, 1.1, -0.6])
+        return np.sum(res[None, :] / (np.asarray(q, complex)[:, None] - poles[None, :]), axis=1)
+
+    z = 1j * np.linspace(0.05, 3.0, 13)
+    a = so.pade_coefficients(z, rat(z))
+    assert np.abs(so.pade_eval(z, a, x) - rat(x)).max() <= 1e-9 * np.abs(rat(x)).max()
+    z4 = np.array([0.5j, 1.0j, 1.7j, 2.2j])
+    f4 = np.array([1 + 1j, 0.5 - 0.2j, 0.1 + 0.3j, -0.4j])
+    a = so.pade_coefficients(z4, f4)
+    for xv in (0.3 + 0.2j, -1.0 + 0.05j):
+        v = 1.0 + 0j
+        for n in range(len(a) - 1, 0, -1):
+            v = 1.0 + a[n] * (xv - z4[n - 1]) / v
+        assert abs(a[0] / v - so.pade_eval(z4, a, [xv])[0]) <= 1e-14
+
+
 PINS = [check_kinetic_closed_form, check_hamiltonian_bruteforce, check_shifted_source_realspace,
         check_free_electron_closed_form, check_mpmath_tiny, check_routes_and_invariants,
         check_linearity_and_reciprocity, check_relative_residual_closed_form, check_condition_number_svd,
         check_green_free_electron, check_green_routes_and_symmetry, check_nonlocal_translation,
         check_nonlocal_secular, check_density_response_free_electron, check_density_response_routes,
         check_coulomb_truncation, check_green_pair_free_electron, check_green_pair_routes, check_aaa_rational,
-        check_spectral_and_quasiparticle, check_sigma_plasmon_pole]
+        check_spectral_and_quasiparticle, check_sigma_plasmon_pole, check_pade]
 
 
 @pytest.mark.parametrize("pin", PINS + [check_generator_ground_state], ids=lambda f: f.__name__)
@@ -709,6 +739,8 @@ _orig_coul = so.coulomb
 _orig_gpe = so.green_pair_elements_spectral
 _orig_sig = so.sigma_c_imag
 _orig_sigma = so.sigma_c
+_orig_pade = so.pade_coefficients
+_orig_pade_eval = so.pade_eval
 _orig_aaa = so.aaa
 _orig_spec_fn = so.spectral_function
 _orig_qp = so.quasiparticle
@@ -789,6 +821,8 @@ MUTATIONS = {
     "sigma_alpha_conjugated": ("sigma_c", lambda m, w, q, vol, a: _orig_sigma(m, w, q, vol, np.conj(a))),
     "sigma_alpha_dropped": ("sigma_c", lambda m, w, q, vol, a: _orig_sigma(m, w, q, vol, 1.0)),
     "sigma_no_2pi": ("sigma_c", lambda m, w, q, vol, a: 2 * np.pi * _orig_sigma(m, w, q, vol, a)),
+    "pade_coefficients_conjugated": ("pade_coefficients", lambda z, f: np.conj(_orig_pade(z, f))),
+    "pade_eval_wrong_node": ("pade_eval", lambda z, a, x: _orig_pade_eval(np.roll(np.asarray(z), -1), a, x)),
     "aaa_unconjugated_weights": ("aaa", lambda zs, fs, tol=1e-13, mmax=100: (lambda r: (r[0], r[1], np.conj(r[2])))(
         _orig_aaa(zs, fs, tol, mmax))),
     "spectral_sign": ("spectral_function", lambda *a: -_orig_spec_fn(*a)),
