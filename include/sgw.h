@@ -452,6 +452,17 @@ sgw_status sgw_aaa_fit(int n, const sgw_c128 *z, const sgw_c128 *f, double tol, 
                        sgw_c128 *z_sup, sgw_c128 *f_sup, sgw_c128 *w_sup);
 
 /*
+ * N-point Pade interpolant of f at the points z in continued-fraction form (the continuation Sec. 2.7
+ * compares with AAA; Vidberg-Serene recursion):
+ *     C(x) = a_0 / (1 + a_1 (x - z_0) / (1 + a_2 (x - z_1) / (1 + ...))),  C(z_i) = f_i.
+ * sgw_pade_fit: a host [n] out; SGW_ERR_INVALID_ARG for repeated or non-finite points or a breakdown
+ * (a zero intermediate value).  sgw_pade_eval: C at the host points x [n_x] into out [n_x], by the
+ * three-term recursion of the numerators and denominators.  Host only.
+ */
+sgw_status sgw_pade_fit(int n, const sgw_c128 *z, const sgw_c128 *f, sgw_c128 *a);
+sgw_status sgw_pade_eval(int n, const sgw_c128 *z, const sgw_c128 *a, int n_x, const sgw_c128 *x, sgw_c128 *out);
+
+/*
  * Spectral function of each state (Sec. 2.8, Eq. 16) on real frequencies from its continued
  * self-energy: Sigma^c(w + i broad) = r_n(w + i broad) of the state's AAA approximant and
  *     A_n(w) = -Im Sigma^c(w) / (pi |w - eps_n - Sigma^c(w) - delta_n|^2),

@@ -366,6 +366,57 @@ extern "C" sgw_status sgw_aaa_fit(int n, const sgw_c128 *z, const sgw_c128 *f, d
   return SGW_OK;
 }
 
+extern "C" sgw_status sgw_pade_fit(int n, const sgw_c128 *z, const sgw_c128 *f, sgw_c128 *a) {
+  if (n < 1 || !z || !f || !a) return fail(SGW_ERR_INVALID_ARG, "sgw_pade_fit: need a point and non-NULL arrays");
+  std::vector<cplx> zz(n), g(n);
+  for (int i = 0; i < n; ++i) {
+    zz[i] = cplx(z[i].re, z[i].im);
+    g[i] = cplx(f[i].re, f[i].im);
+    if (!std::isfinite(zz[i].real()) || !std::isfinite(zz[i].imag()) || !std::isfinite(g[i].real()) ||
+        !std::isfinite(g[i].imag()))
+      return fail(SGW_ERR_INVALID_ARG, "sgw_pade_fit: point not finite");
+  }
+  for (int i = 0; i < n; ++i)
+    for (int k = i + 1; k < n; ++k)
+      if (zz[i] == zz[k]) return fail(SGW_ERR_INVALID_ARG, "sgw_pade_fit: repeated point");
+  // g_p(z_i) = (g_{p-1}(z_{p-1}) - g_{p-1}(z_i)) / ((z_i - z_{p-1}) g_{p-1}(z_i)), a_p = g_p(z_p), in place
+  a[0] = {g[0].real(), g[0].imag()};
+  for (int p = 1; p < n; ++p) {
+    const cplx gp = g[p - 1];
+    for (int i = p; i < n; ++i) {
+      if (g[i] == cplx(0.0, 0.0)) return fail(SGW_ERR_INVALID_ARG, "sgw_pade_fit: the continued fraction breaks down");
+      g[i] = (gp - g[i]) / ((zz[i] - zz[p - 1]) * g[i]);
+    }
+    a[p] = {g[p].real(), g[p].imag()};
+    // a zero coefficient would cut the fraction short of the later points
+    if (g[p] == cplx(0.0, 0.0) && p < n - 1)
+      return fail(SGW_ERR_INVALID_ARG, "sgw_pade_fit: the continued fraction breaks down");
+  }
+  return SGW_OK;
+}
+
+extern "C" sgw_status sgw_pade_eval(int n, const sgw_c128 *z, const sgw_c128 *a, int n_x, const sgw_c128 *x,
+                                    sgw_c128 *out) {
+  if (n < 1 || n_x < 0 || !z || !a || (n_x > 0 && (!x || !out)))
+    return fail(SGW_ERR_INVALID_ARG, "sgw_pade_eval: bad arguments");
+  for (int e = 0; e < n_x; ++e) {
+    const cplx xv(x[e].re, x[e].im);
+    // A_{k+1} = A_k + (x - z_k) a_{k+1} A_{k-1}, the same for B; C = A_n / B_n
+    cplx ap(0.0, 0.0), ac(a[0].re, a[0].im), bp(1.0, 0.0), bc(1.0, 0.0);
+    for (int k = 1; k < n; ++k) {
+      const cplx t = (xv - cplx(z[k - 1].re, z[k - 1].im)) * cplx(a[k].re, a[k].im);
+      const cplx an = ac + t * ap, bn = bc + t * bp;
+      ap = ac;
+      ac = an;
+      bp = bc;
+      bc = bn;
+    }
+    const cplx c = ac / bc;
+    out[e] = {c.real(), c.imag()};
+  }
+  return SGW_OK;
+}
+
 extern "C" sgw_status sgw_spectral_function(sgw_ctx *ctx, int n_band, int n_sup_max, const int32_t *n_sup,
                                             const sgw_c128 *z_sup, const sgw_c128 *f_sup, const sgw_c128 *w_sup,
                                             int n_omega, const double *omega, double broad, const double *eps_n,

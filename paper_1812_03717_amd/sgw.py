@@ -41,6 +41,7 @@ EXPORTED = [
     "sgw_green_workspace_size", "sgw_green_solve", "sgw_ham_set_nonlocal", "sgw_ham_nproj",
     "sgw_density_response", "sgw_coulomb", "sgw_screened_coulomb", "sgw_green_pair_workspace_size",
     "sgw_green_pair_elements", "sgw_sigma_c", "sgw_aaa_fit", "sgw_spectral_function", "sgw_quasiparticle",
+    "sgw_pade_fit", "sgw_pade_eval",
 ]
 
 
@@ -116,6 +117,8 @@ def load_library(path: str = LIB_PATH):
         "sgw_spectral_function": [vp, C.c_int, C.c_int, C.POINTER(i32), vp, vp, vp, C.c_int, C.POINTER(dbl), dbl,
                                   C.POINTER(dbl), C.POINTER(dbl), vp, vp],
         "sgw_quasiparticle": [C.c_int, vp, vp, vp, dbl, dbl, C.POINTER(dbl), C.POINTER(dbl)],
+        "sgw_pade_fit": [C.c_int, vp, vp, vp],
+        "sgw_pade_eval": [C.c_int, vp, vp, C.c_int, vp, vp],
         "sgw_opts_default": [C.POINTER(sgw_opts)],
         "sternheimer_workspace_size": [vp, vp, C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(sgw_opts),
                                        C.POINTER(sz)],
@@ -434,6 +437,26 @@ def sgw_aaa_fit(z, f, tol=1e-13, max_terms=100):
                                       float(tol), mt, C.byref(n), zs.ctypes.data_as(C.c_void_p),
                                       fs.ctypes.data_as(C.c_void_p), ws.ctypes.data_as(C.c_void_p)))
     return zs[:n.value].copy(), fs[:n.value].copy(), ws[:n.value].copy()
+
+
+def sgw_pade_fit(z, f):
+    """Continued-fraction coefficients a (numpy complex) of the Pade interpolant of f at z (host)."""
+    z = np.ascontiguousarray(np.asarray(z, np.complex128))
+    f = np.ascontiguousarray(np.asarray(f, np.complex128))
+    a = np.zeros(len(z), np.complex128)
+    _check(load_library().sgw_pade_fit(len(z), z.ctypes.data_as(C.c_void_p), f.ctypes.data_as(C.c_void_p),
+                                       a.ctypes.data_as(C.c_void_p)))
+    return a
+
+
+def sgw_pade_eval(z, a, x):
+    z = np.ascontiguousarray(np.asarray(z, np.complex128))
+    a = np.ascontiguousarray(np.asarray(a, np.complex128))
+    x = np.ascontiguousarray(np.atleast_1d(np.asarray(x, np.complex128)))
+    out = np.zeros(len(x), np.complex128)
+    _check(load_library().sgw_pade_eval(len(z), z.ctypes.data_as(C.c_void_p), a.ctypes.data_as(C.c_void_p), len(x),
+                                        x.ctypes.data_as(C.c_void_p), out.ctypes.data_as(C.c_void_p)))
+    return out
 
 
 def sgw_spectral_function(ctx, fits, omega, broad, eps_n, delta):

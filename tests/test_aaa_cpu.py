@@ -1,6 +1,6 @@
-"""The library's AAA fit and quasiparticle step (host code, no GPU) against the oracle (Sec. 2.7;
-Sec. 2.8, Eq. 17): on a rational function sampled on the imaginary axis both reproduce its values on
-the real axis, pick the same support points, and give the same continuation."""
+"""The library's AAA and Pade fits and the quasiparticle step (host code, no GPU) against the oracle
+(Sec. 2.7; Sec. 2.8, Eq. 17): on a rational function sampled on the imaginary axis both reproduce its
+values on the real axis, AAA picks the same support points, and the continuations agree."""
 import numpy as np
 import pytest
 
@@ -71,3 +71,29 @@ def test_aaa_special_cases(sgw):
     assert len(zs) == 1 and np.array_equal(zs, zo) and np.array_equal(fs, fo)
     e_qp, zf = sgw.sgw_quasiparticle((np.array([1j]), np.array([0.1 + 0.0j]), np.array([1.0 + 0.0j])), 0.2, 0.05)
     assert abs(zf - 1.0) < 1e-15 and abs(e_qp - (0.2 + 0.1 + 0.05)) < 1e-15   # a constant: Z = 1
+
+
+def test_pade_matches_oracle(sgw):
+    """_rational has 5 poles: 11 points determine it (type (4, 5)), and every coefficient is then a
+    well-conditioned function of the data; with more points the later coefficients fit rounding
+    noise on either side, so 21 points are compared through the continued function only."""
+    zi = 1j * np.linspace(0.05, 3.0, 11)
+    f = _rational(zi)
+    a = sgw.sgw_pade_fit(zi, f)
+    a_ref = so.pade_coefficients(zi, f)
+    assert np.abs(a - a_ref).max() <= 1e-9 * np.abs(a_ref).max()
+    x = np.linspace(-2.0, 2.0, 101) + 0.05j
+    exact = _rational(x)
+    c = sgw.sgw_pade_eval(zi, a, x)
+    assert np.abs(c - so.pade_eval(zi, a_ref, x)).max() <= 1e-9 * np.abs(exact).max()
+    assert np.abs(c - exact).max() <= 1e-7 * np.abs(exact).max()
+    assert np.abs(sgw.sgw_pade_eval(zi, a, zi) - f).max() <= 1e-12 * np.abs(f).max()
+    z21 = 1j * np.linspace(0.05, 3.0, 21)
+    c21 = sgw.sgw_pade_eval(z21, sgw.sgw_pade_fit(z21, _rational(z21)), x)
+    assert np.abs(c21 - exact).max() <= 1e-5 * np.abs(exact).max()
+    with pytest.raises(sgw.SgwError):
+        sgw.sgw_pade_fit([1j, 1j], [1.0, 2.0])          # repeated point
+    with pytest.raises(sgw.SgwError):
+        sgw.sgw_pade_fit([1j, 2j, 3j], [1.0, 2.0, 1.0])  # g_2(z_3) = 0: a zero denominator
+    with pytest.raises(sgw.SgwError):
+        sgw.sgw_pade_fit([1j, 2j, 3j], [1.0, 1.0, 2.0])  # a_2 = 0 would cut the fraction short
