@@ -621,6 +621,9 @@ def main():
                     help="the timed method; mixed: FP32 potential matvecs once a pair's residuals are small, "
                          "FP64 refinement, with a plain FP64 leg timed beside it")
     ap.add_argument("--mixed-switch", type=float, default=0.0)
+    ap.add_argument("--solver", choices=["multishift", "block"], default="multishift",
+                    help="block: one block Krylov space per band over its perturbations (FP64; max_iter then "
+                         "limits the block steps, 0: 240 for si64)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch-workers", type=int, default=4)
     ap.add_argument("--batch-max-iter", type=int, default=4000)
@@ -687,7 +690,13 @@ def main():
     kw = dict(precision=prec)
     if args.slots:
         kw["slots"] = args.slots
-    max_iter = args.max_iter or (3500 if args.workload in ("si64", "si64nl") else 0)
+    block = args.solver == "block"
+    if block:
+        if prec != sgw.FP64:
+            log("the block solver runs in FP64 only")
+            sys.exit(2)
+        kw["solver"] = sgw.SOLVER_BLOCK
+    max_iter = args.max_iter or ((240 if block else 3500) if args.workload in ("si64", "si64nl") else 0)
     if max_iter:
         kw["max_iter"] = max_iter
     if args.mixed_switch:
@@ -774,7 +783,9 @@ def main():
         "dtype": "f64" if prec == sgw.FP64 else "f64+f32", "data": "synthetic",
         "config": {"workload": WORKLOADS[args.workload], "solves_per_step": problem.n_solves,
                    "max_iter": max_iter or 600,
-                   "method": "multishift Lanczos-FOM, stored basis, " +
+                   "method": ("block Lanczos-FOM over each band's perturbations (block steps <= max_iter), FP64, "
+                              "per-shift refinement of any shift whose true residual misses tol") if block else
+                             "multishift Lanczos-FOM, stored basis, " +
                              ("FP64" if prec == sgw.FP64 else "FP64 with FP32 potential matvecs once a pair's "
                               "shift residuals are below 1e4*tol, FP64 per-shift refinement of any shift above tol")},
         "roofline": roof,

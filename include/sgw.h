@@ -88,9 +88,20 @@ enum { SGW_PROJ_SPLIT_BF16 = 16 };
 enum {
   SGW_SOLVER_MULTISHIFT = 0,  /* all shifts of one (v,p) share one Krylov space (Sec. 2.2) */
   SGW_SOLVER_PER_SHIFT = 1,   /* every (v,p,z) its own preconditioned BiCGStab solve */
-  SGW_SOLVER_TAIL = 2         /* multishift up to Krylov dimension tail_iter, then the shifts
+  SGW_SOLVER_TAIL = 2,        /* multishift up to Krylov dimension tail_iter, then the shifts
                                  still above tol continue per shift, warm-started from the
                                  multishift iterate */
+  SGW_SOLVER_BLOCK = 3        /* all perturbations and shifts of one band v share one block Krylov
+                                 space (block Lanczos over the n_pert right-hand sides, FOM
+                                 solutions per shift; Secs. 2.2-2.3): FP64 only, no preconditioner
+                                 or guess, n_pert <= 32 (above: SGW_ERR_UNSUPPORTED); max_iter
+                                 limits the block steps, info.iters reports them; slots > 0 caps
+                                 the bands iterated together (default: as many as a 144 GiB
+                                 workspace holds, all bands if it can); solves whose estimate met
+                                 the threshold while the true residual missed tol are refined per
+                                 shift, as after the plain multishift solver; right-hand sides
+                                 of one band that are linearly dependent (or zero) are rejected
+                                 with SGW_ERR_UNSUPPORTED */
 };
 /* diagonal preconditioner of the per-shift solves (sgw_opts.precond) */
 enum { SGW_PC_NONE = 0, SGW_PC_TETER = 1, SGW_PC_LEARNED = 2 };

@@ -176,6 +176,7 @@ extern "C" sgw_status sgw_ctx_destroy(sgw_ctx *ctx) {
   timing_collect(ctx);
   for (auto e : ctx->event_pool) hipEventDestroy(e);
   if (ctx->pinned) hipHostFree(ctx->pinned);
+  blas_release(ctx);
   delete ctx;
   return SGW_OK;
 }
@@ -870,7 +871,16 @@ static sgw_status validate_solve(sgw_ctx *ctx, const sgw_ham *h_kq, int n_occ, c
   }
   SGW_CHECK(std::isfinite(tol) && tol > 0.0, "sternheimer_solve: tol must be positive");
   SGW_CHECK(std::isfinite(o.alpha_pv) && o.alpha_pv > 0.0, "sternheimer_solve: alpha_pv must be positive");
-  SGW_CHECK(o.solver >= SGW_SOLVER_MULTISHIFT && o.solver <= SGW_SOLVER_TAIL, "sternheimer_solve: unknown solver");
+  SGW_CHECK(o.solver >= SGW_SOLVER_MULTISHIFT && o.solver <= SGW_SOLVER_BLOCK, "sternheimer_solve: unknown solver");
+  if (o.solver == SGW_SOLVER_BLOCK) {
+    SGW_CHECK(o.precision == SGW_FP64, "sternheimer_solve: the block solver runs in FP64 only");
+    SGW_CHECK(o.precond == SGW_PC_NONE && o.guess == SGW_GUESS_ZERO,
+              "sternheimer_solve: the block solver takes no preconditioner or initial guess");
+    SGW_CHECK(o.hist_iter == 0, "sternheimer_solve: the block solver keeps no residual history");
+    if (n_pert > kBlockMaxPert)
+      return fail(SGW_ERR_UNSUPPORTED, "sternheimer_solve: the block solver takes at most " +
+                                           std::to_string(kBlockMaxPert) + " perturbations");
+  }
   SGW_CHECK(o.precond >= SGW_PC_NONE && o.precond <= SGW_PC_LEARNED, "sternheimer_solve: unknown preconditioner");
   SGW_CHECK(o.guess == SGW_GUESS_ZERO || o.guess == SGW_GUESS_LEARNED, "sternheimer_solve: unknown initial guess");
   SGW_CHECK(o.fft_planes >= SGW_FFT_AUTO && o.fft_planes <= SGW_FFT_TRI, "sternheimer_solve: unknown plane kernel");
@@ -964,7 +974,8 @@ static sgw_opts refine_opts(const sgw_ham *h_kq, int n_occ, int n_band, int n_pe
                             const sgw_opts &o) {
   sgw_opts r = o;
   if (o.ps_slots > 0) return r;
-  const size_t ms = make_layout(h_kq, n_occ, n_band, n_pert, n_omega, o).total;
+  const size_t ms = o.solver == SGW_SOLVER_BLOCK ? block_workspace_bytes(h_kq, n_occ, n_band, n_pert, n_omega, o)
+                                                 : make_layout(h_kq, n_occ, n_band, n_pert, n_omega, o).total;
   const long n_sys = (long)n_band * n_pert * n_omega;
   const int n_sys_i = (int)std::min<long>(n_sys, 1L << 30);
   int B = (int)std::max<long>(1, std::min<long>(n_sys, 8192));
@@ -981,6 +992,10 @@ static size_t solve_workspace_bytes(const sgw_ham *h_kq, int n_occ, int n_band, 
   const long n_sys = (long)n_band * n_pert * n_omega;
   const int n_sys_i = (int)std::min<long>(n_sys, 1L << 30);
   switch (o.solver) {
+    case SGW_SOLVER_BLOCK:  // the per-shift refinement reuses the workspace, as after the multishift solver
+      return std::max(block_workspace_bytes(h_kq, n_occ, n_band, n_pert, n_omega, o),
+                      ps_workspace_bytes(h_kq, n_occ, n_band, n_pert, n_omega,
+                                         refine_opts(h_kq, n_occ, n_band, n_pert, n_omega, o), n_sys_i));
     case SGW_SOLVER_PER_SHIFT:
       return ps_workspace_bytes(h_kq, n_occ, n_band, n_pert, n_omega, o, n_sys_i);
     case SGW_SOLVER_TAIL:
@@ -1002,7 +1017,7 @@ extern "C" sgw_status sternheimer_workspace_size(sgw_ctx *ctx, const sgw_ham *h_
   if (n_occ < 0 || n_band < 0 || n_pert < 0 || n_omega < 0)
     return fail(SGW_ERR_INVALID_ARG, "sternheimer_workspace_size: negative size");
   const sgw_opts o = resolve_opts(opts);
-  if (o.solver < SGW_SOLVER_MULTISHIFT || o.solver > SGW_SOLVER_TAIL)
+  if (o.solver < SGW_SOLVER_MULTISHIFT || o.solver > SGW_SOLVER_BLOCK)
     return fail(SGW_ERR_INVALID_ARG, "sternheimer_workspace_size: unknown solver");
   *bytes = solve_workspace_bytes(h_kq, n_occ, n_band, n_pert, std::max(n_omega, 1), o);
   return SGW_OK;
@@ -1418,10 +1433,15 @@ static sgw_status run_solve(sgw_ctx *ctx, const sgw_problem &p, const sgw_opts &
   // the true residual, recomputed from x, missed tol (rounding in the recurrence: tight tolerances
   // near the FP64 floor of kappa * eps) are refined that way; shifts that hit max_iter or met
   // non-finite values keep their flags.
-  const bool plain = o.solver == SGW_SOLVER_MULTISHIFT && o.precision == SGW_FP64;
+  // The block solver is refined the same way as plain FP64 multishift.
+  const bool plain = (o.solver == SGW_SOLVER_MULTISHIFT && o.precision == SGW_FP64) || o.solver == SGW_SOLVER_BLOCK;
   const sgw_opts o1 = o.solver == SGW_SOLVER_TAIL ? tail_phase_opts(o) : o;
-  st = multishift_solve(ctx, p.h_kq, p.n_occ, p.psi_occ_kq, p.h_k, p.n_band, p.psi_v, p.eps_v, p.n_pert,
-                        p.dv_miller, p.n_omega, p.omega, p.eta, p.tol, o1, workspace, p.dpsi, p.info);
+  if (o.solver == SGW_SOLVER_BLOCK)
+    st = block_solve(ctx, p.h_kq, p.n_occ, p.psi_occ_kq, p.h_k, p.n_band, p.psi_v, p.eps_v, p.n_pert, p.dv_miller,
+                     p.n_omega, p.omega, p.eta, p.tol, o, workspace, workspace_bytes, p.dpsi, p.info);
+  else
+    st = multishift_solve(ctx, p.h_kq, p.n_occ, p.psi_occ_kq, p.h_k, p.n_band, p.psi_v, p.eps_v, p.n_pert,
+                          p.dv_miller, p.n_omega, p.omega, p.eta, p.tol, o1, workspace, p.dpsi, p.info);
   if (st != SGW_OK && st != SGW_NOT_CONVERGED) return st;
   if (st == SGW_OK) return SGW_OK;
   std::vector<sgw_solve_info> hinfo(n_sys);

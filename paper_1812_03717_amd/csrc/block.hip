@@ -1,0 +1,677 @@
+// Block multishift solver (SGW_SOLVER_BLOCK): one block Krylov space per band over all its
+// perturbations (Sec. 2.3, Eqs. 6-8; the shifted systems of Sec. 2.2).
+//
+// The perturbations p of band v share the operator A_v = H - eps_v + alpha P_occ, so the block Krylov
+// space K_k(A_v, [b_1 .. b_s]) serves every right-hand side, and, being shift invariant, every
+// frequency z_j.  Block Lanczos (three-term block recurrence, no reorthogonalisation):
+//     V_0 R_0 = B,   W = A V_j - V_{j-1} B_j^H,   A_j = V_j^H W,   W -= V_j A_j,   V_{j+1} B_{j+1} = W,
+// the orthonormalisations by Cholesky QR done twice.  With T_k the Hermitian block tridiagonal matrix
+// (diagonal A_j, sub-diagonal B_{j+1}), the FOM solution of shift z is X(z) = V Y(z) with
+// (T_k - z) Y(z) = E_0 R_0, and its residual is B_k (last block of Y(z)).  The last block follows from
+// a forward block recurrence per shift, D_j = A_j - z - B_j D_{j-1}^-1 B_j^H, F_j = -B_j D_{j-1}^-1
+// F_{j-1}, Y_last = D_j^-1 F_j, so the residual estimates cost s x s work per step and shift.  At the
+// end the block tridiagonal systems are solved per shift (block Thomas) and X = V Y is one matrix
+// product per band; the true FP64 residual of every solution decides, as in the other solvers.
+//
+// The block operations other than H.x and the occupied projector (the library's kernels) are
+// batched products of plain matrices (rocBLAS zgemm), a Cholesky and triangular inverse per band and
+// the s x s shift recurrences (kernels here).  Blocks hold at most kBlockMaxPert perturbations.
+#include <rocblas/rocblas.h>
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "fft_lds.h"
+#include "sgw_internal.h"
+#include "solver_state.h"
+
+namespace sgw {
+namespace {
+
+constexpr size_t kBA = 256;
+size_t up(size_t b) { return (b + kBA - 1) / kBA * kBA; }
+
+// Workspace of one chunk of nbc bands; kb = block steps + 1 stored blocks
+struct BlkLayout {
+  int nbc = 0, kb = 0, s = 0, nsub = 0;
+  size_t basis, rhs, y, w, v2, gram, rfac, rinv, ablk, bblk, r0, bnorm, dinv, ff, res, thomas, ycat, xout, list,
+      c, t, psi, omega, eps, dvm, bad, total;
+};
+
+BlkLayout blk_layout(const sgw_ham *h, int n_occ, int nbc, int s, int n_omega, int kb) {
+  BlkLayout L;
+  L.nbc = nbc;
+  L.kb = kb;
+  L.s = s;
+  const size_t npw = h->n_pw, nv = (size_t)nbc * s, ss = (size_t)s * s;
+  L.nsub = (int)std::max<size_t>(nv, 1024);  // vectors per H.x launch in the residual pass
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += up(bytes);
+    return o;
+  };
+  L.basis = take(16 * (size_t)kb * nv * npw);
+  L.rhs = take(16 * nv * npw);
+  L.y = take(16 * std::max<size_t>(nv, L.nsub) * npw);
+  L.w = take(16 * nv * npw);
+  L.v2 = take(16 * nv * npw);
+  L.gram = take(16 * nbc * ss);
+  L.rfac = take(16 * nbc * ss);
+  L.rinv = take(16 * nbc * ss);
+  L.ablk = take(16 * (size_t)kb * nbc * ss);
+  L.bblk = take(16 * (size_t)(kb + 1) * nbc * ss);
+  L.r0 = take(16 * nbc * ss);
+  L.bnorm = take(8 * nv);
+  L.dinv = take(16 * (size_t)nbc * n_omega * ss);
+  L.ff = take(16 * (size_t)nbc * n_omega * ss);
+  L.res = take(8 * (size_t)nbc * n_omega);
+  L.thomas = take(16 * 2 * (size_t)kb * nbc * n_omega * ss);
+  L.ycat = take(16 * (size_t)kb * s * nv * n_omega);
+  L.xout = take(16 * nv * n_omega * npw);
+  L.list = take(4 * std::max<size_t>(nv, L.nsub));
+  L.c = take(16 * kProjChunks * std::max<size_t>(nv, L.nsub) * std::max(n_occ, 1));
+  L.t = take(hx_tbuf_bytes(h, std::max<size_t>(nv, L.nsub)));
+  L.psi = take(16 * (size_t)std::max(n_occ, 1) * npw);
+  L.omega = take(16 * (size_t)n_omega);
+  L.eps = take(8 * (size_t)nbc);
+  L.dvm = take(4 * 3 * (size_t)s);
+  L.bad = take(8);
+  L.total = off;
+  return L;
+}
+
+// block steps allowed: max_iter, the limit on the operator applications to each right-hand side
+int blk_steps(const sgw_opts &o) { return std::max(1, o.max_iter); }
+
+// bands per chunk: the largest count (at most `cap` when cap > 0) whose layout fits `budget` (at least
+// one), then evened out over the chunks that n_band needs
+int blk_chunk(const sgw_ham *h, int n_occ, int n_band, int s, int n_omega, int kb, double budget, int cap) {
+  int lo = 1, hi = cap > 0 ? std::min(cap, n_band) : n_band;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) / 2;
+    if ((double)blk_layout(h, n_occ, mid, s, n_omega, kb).total <= budget) lo = mid;
+    else hi = mid - 1;
+  }
+  const int n_chunks = (n_band + lo - 1) / lo;
+  return (n_band + n_chunks - 1) / n_chunks;
+}
+
+// ---------------------------------------------------------------------------
+// kernels
+// ---------------------------------------------------------------------------
+// list[b s + c] = index of vector c of band b's block j in the basis [b][kb][s][npw]
+__global__ void k_blk_list(int32_t *list, int nbc, int s, int kb, int j) {
+  const int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= nbc * s) return;
+  const int b = a / s, c = a - b * s;
+  list[a] = (b * kb + j) * s + c;
+}
+
+// w[a] = y[a] - eps[band] v[a] (v through the list)
+__global__ void k_blk_shift_eps(int npw, int s, const double2 *__restrict__ y, const double2 *__restrict__ basis,
+                                const int32_t *__restrict__ list, const double *__restrict__ eps,
+                                double2 *__restrict__ w) {
+  const int a = blockIdx.x;
+  const int g = blockIdx.y * blockDim.x + threadIdx.x;
+  if (g >= npw) return;
+  const double e = eps[a / s];
+  const double2 v = basis[(long)list[a] * npw + g], t = y[(long)a * npw + g];
+  w[(long)a * npw + g] = make_double2(t.x - e * v.x, t.y - e * v.y);
+}
+
+// M = (M + M^H) / 2 for the nbc s x s blocks (column-major)
+__global__ void k_blk_hermitize(double2 *m, int s) {
+  double2 *mb = m + (long)blockIdx.x * s * s;
+  for (int e = threadIdx.x; e < s * s; e += blockDim.x) {
+    const int i = e % s, j = e / s;
+    if (i > j) continue;
+    const double2 a = mb[i + j * s], b = mb[j + i * s];
+    const double2 h = make_double2(0.5 * (a.x + b.x), 0.5 * (a.y - b.y));
+    mb[i + j * s] = h;
+    mb[j + i * s] = make_double2(h.x, -h.y);
+  }
+}
+
+// Cholesky G = R^H R (R upper) of each band's Gram matrix, R^-1, and rout = R rprev (or R); a pivot
+// below rel_floor of the largest diagonal sets *bad
+__global__ __launch_bounds__(64) void k_blk_chol(const double2 *__restrict__ gram, const double2 *__restrict__ rprev,
+                                                 double2 *__restrict__ rout, double2 *__restrict__ rinv, int s,
+                                                 int *bad) {
+  __shared__ double2 R[kBlockMaxPert][kBlockMaxPert + 1];
+  __shared__ double2 Ri[kBlockMaxPert][kBlockMaxPert + 1];
+  __shared__ int fail;
+  const long base = (long)blockIdx.x * s * s;
+  const int t = threadIdx.x;
+  if (t == 0) fail = 0;
+  for (int e = t; e < s * s; e += blockDim.x) {
+    const int i = e % s, j = e / s;
+    R[i][j] = i <= j ? gram[base + e] : make_double2(0.0, 0.0);
+    Ri[i][j] = make_double2(0.0, 0.0);
+  }
+  __syncthreads();
+  double gmax = 0.0;
+  for (int i = 0; i < s; ++i) gmax = fmax(gmax, R[i][i].x);
+  for (int k = 0; k < s; ++k) {
+    // R[k][k] and row k to the right; rows above k are final
+    if (t == 0) {
+      double d = R[k][k].x;
+      for (int i = 0; i < k; ++i) d -= R[i][k].x * R[i][k].x + R[i][k].y * R[i][k].y;
+      if (!(d > 1e-26 * gmax)) {
+        fail = 1;
+        d = 1e-26 * gmax + 1e-300;
+      }
+      R[k][k] = make_double2(sqrt(d), 0.0);
+    }
+    __syncthreads();
+    for (int j = k + 1 + t; j < s; j += blockDim.x) {
+      double2 v = R[k][j];
+      for (int i = 0; i < k; ++i) v = c_sub(v, c_mul(c_conj(R[i][k]), R[i][j]));
+      const double inv = 1.0 / R[k][k].x;
+      R[k][j] = make_double2(v.x * inv, v.y * inv);
+    }
+    __syncthreads();
+  }
+  // R^-1 column by column (back substitution), one thread per column
+  for (int j = t; j < s; j += blockDim.x) {
+    for (int i = j; i >= 0; --i) {
+      double2 v = i == j ? make_double2(1.0, 0.0) : make_double2(0.0, 0.0);
+      for (int l = i + 1; l <= j; ++l) v = c_sub(v, c_mul(R[i][l], Ri[l][j]));
+      const double inv = 1.0 / R[i][i].x;
+      Ri[i][j] = make_double2(v.x * inv, v.y * inv);
+    }
+  }
+  __syncthreads();
+  for (int e = t; e < s * s; e += blockDim.x) {
+    const int i = e % s, j = e / s;
+    rinv[base + e] = Ri[i][j];
+    double2 v = make_double2(0.0, 0.0);
+    if (rprev) {
+      for (int l = i; l <= j; ++l) v = c_add(v, c_mul(R[i][l], rprev[base + l + j * s]));
+    } else {
+      v = R[i][j];
+    }
+    rout[base + e] = v;
+  }
+  if (t == 0 && fail) atomicOr(bad, 1);
+}
+
+// s x s blocks in LDS, [row][col] with a padded row.  Every helper is entered and left by all
+// threads of the block (256 threads: each holds at most 4 of the s^2 <= 1024 entries).
+using Blk = double2 (*)[kBlockMaxPert + 1];
+constexpr int kBlkThreads = 256;
+static_assert(kBlkThreads * 4 >= kBlockMaxPert * kBlockMaxPert, "4 entries per thread");
+
+__device__ __forceinline__ void blk_load(Blk M, const double2 *src, int s) {
+  for (int e = threadIdx.x; e < s * s; e += kBlkThreads) M[e % s][e / s] = src[e];
+  __syncthreads();
+}
+
+__device__ __forceinline__ void blk_store(double2 *dst, Blk M, int s) {
+  for (int e = threadIdx.x; e < s * s; e += kBlkThreads) dst[e] = M[e % s][e / s];
+  __syncthreads();
+}
+
+// C = sgn op(A) op(B) (mode 0) or C = C - op(A) op(B) (mode 1), op = ^H where ha / hb; C may be
+// A or B: the products are formed in registers before any entry is written
+__device__ void blk_mm(Blk C, Blk A, bool ha, Blk B, bool hb, int s, double sgn, int mode) {
+  double2 acc[4];
+  int r = 0;
+  for (int e = threadIdx.x; e < s * s; e += kBlkThreads, ++r) {
+    const int i = e % s, j = e / s;
+    double2 v = make_double2(0.0, 0.0);
+    for (int l = 0; l < s; ++l) {
+      const double2 a = ha ? c_conj(A[l][i]) : A[i][l];
+      const double2 b = hb ? c_conj(B[j][l]) : B[l][j];
+      v = c_add(v, c_mul(a, b));
+    }
+    acc[r] = mode ? c_sub(C[i][j], v) : make_double2(sgn * v.x, sgn * v.y);
+  }
+  __syncthreads();
+  r = 0;
+  for (int e = threadIdx.x; e < s * s; e += kBlkThreads, ++r) C[e % s][e / s] = acc[r];
+  __syncthreads();
+}
+
+// M = A - M - z I (M holds a product, A a block in global memory)
+__device__ __forceinline__ void blk_diff_shift(Blk M, const double2 *A, double2 z, int s) {
+  for (int e = threadIdx.x; e < s * s; e += kBlkThreads) {
+    const int i = e % s, j = e / s;
+    double2 v = c_sub(A[e], M[i][j]);
+    if (i == j) v = c_sub(v, z);
+    M[i][j] = v;
+  }
+  __syncthreads();
+}
+
+// in-place inverse of M by Gauss-Jordan elimination with partial pivoting (row exchanges recorded in
+// perm, undone on the columns at the end)
+__device__ void blk_inverse(Blk M, int s, int *perm) {
+  for (int i = threadIdx.x; i < s; i += kBlkThreads) perm[i] = i;
+  __syncthreads();
+  for (int k = 0; k < s; ++k) {
+    if (threadIdx.x == 0) {
+      int p = k;
+      double best = -1.0;
+      for (int i = k; i < s; ++i) {
+        const double a = M[i][k].x * M[i][k].x + M[i][k].y * M[i][k].y;
+        if (a > best) {
+          best = a;
+          p = i;
+        }
+      }
+      if (p != k) {
+        for (int j = 0; j < s; ++j) {
+          const double2 tmp = M[k][j];
+          M[k][j] = M[p][j];
+          M[p][j] = tmp;
+        }
+        const int tp = perm[k];
+        perm[k] = perm[p];
+        perm[p] = tp;
+      }
+      const double2 d = M[k][k];
+      const double q = 1.0 / (d.x * d.x + d.y * d.y);
+      const double2 dinv = make_double2(d.x * q, -d.y * q);
+      for (int j = 0; j < s; ++j) M[k][j] = j == k ? dinv : c_mul(M[k][j], dinv);
+    }
+    __syncthreads();
+    // rows i != k: columns j != k lose M[i][k] times the scaled pivot row ...
+    for (int e = threadIdx.x; e < s * s; e += kBlkThreads) {
+      const int i = e % s, j = e / s;
+      if (i != k && j != k) M[i][j] = c_sub(M[i][j], c_mul(M[i][k], M[k][j]));
+    }
+    __syncthreads();
+    // ... and column k becomes -M[i][k] / pivot
+    for (int i = threadIdx.x; i < s; i += kBlkThreads)
+      if (i != k) M[i][k] = c_mul(make_double2(-M[i][k].x, -M[i][k].y), M[k][k]);
+    __syncthreads();
+  }
+  // inverse of A = (inverse of the row-exchanged matrix) with its columns put back: column l goes to
+  // perm[l]; each thread moves one row
+  for (int i = threadIdx.x; i < s; i += kBlkThreads) {
+    double2 row[kBlockMaxPert];
+    for (int j = 0; j < s; ++j) row[j] = M[i][j];
+    for (int j = 0; j < s; ++j) M[i][perm[j]] = row[j];
+  }
+  __syncthreads();
+}
+
+// Per (band, shift), one block of 256 threads: step j of the forward block recurrence of (T - z) and
+// the residual estimate of the FOM solutions after j + 1 block steps.  ablk = A_j, bprev = B_j
+// (j > 0), bnext = B_{j+1} of every band; dinv, ff hold D_{j-1}^-1, F_{j-1} of the (band, shift) and
+// take D_j^-1, F_j.  res[band][shift] = largest over the block's columns c of
+// ||B_{j+1} D_j^-1 F_j e_c|| / ||b_c||.
+__global__ __launch_bounds__(kBlkThreads) void k_blk_shift(int s, int n_omega, int j,
+                                                         const double2 *__restrict__ ablk,
+                                                         const double2 *__restrict__ bprev,
+                                                         const double2 *__restrict__ bnext,
+                                                         const double2 *__restrict__ r0,
+                                                         const double *__restrict__ bnorm,
+                                                         const double2 *__restrict__ zs, double2 *__restrict__ dinv,
+                                                         double2 *__restrict__ ff, double *__restrict__ res) {
+  __shared__ double2 X1[kBlockMaxPert][kBlockMaxPert + 1], X2[kBlockMaxPert][kBlockMaxPert + 1],
+      X3[kBlockMaxPert][kBlockMaxPert + 1];
+  __shared__ int perm[kBlockMaxPert];
+  __shared__ double cres[kBlockMaxPert];
+  const int b = blockIdx.x / n_omega, k = blockIdx.x - b * n_omega;
+  const long bo = (long)b * s * s, so = ((long)b * n_omega + k) * s * s;
+  if (j == 0) {
+    blk_load(X1, r0 + bo, s);  // F_0 = R_0
+    for (int e = threadIdx.x; e < s * s; e += kBlkThreads) X3[e % s][e / s] = make_double2(0.0, 0.0);
+    __syncthreads();
+  } else {
+    blk_load(X1, dinv + so, s);
+    blk_load(X2, bprev + bo, s);
+    blk_mm(X3, X2, false, X1, false, s, 1.0, 0);   // L = B_j D_{j-1}^-1
+    blk_load(X1, ff + so, s);
+    blk_mm(X1, X3, false, X1, false, s, -1.0, 0);  // F_j = -L F_{j-1}
+    blk_mm(X3, X3, false, X2, true, s, 1.0, 0);    // L B_j^H
+  }
+  blk_diff_shift(X3, ablk + bo, zs[k], s);  // D_j = A_j - L B_j^H - z
+  blk_inverse(X3, s, perm);
+  blk_store(dinv + so, X3, s);
+  blk_store(ff + so, X1, s);
+  blk_mm(X2, X3, false, X1, false, s, 1.0, 0);  // last block of Y = D_j^-1 F_j
+  blk_load(X1, bnext + bo, s);
+  blk_mm(X1, X1, false, X2, false, s, 1.0, 0);  // B_{j+1} Y_last
+  for (int c = threadIdx.x; c < s; c += kBlkThreads) {
+    double n2 = 0.0;
+    for (int i = 0; i < s; ++i) n2 += X1[i][c].x * X1[i][c].x + X1[i][c].y * X1[i][c].y;
+    const double nb = bnorm[b * s + c];
+    cres[c] = nb > 0.0 ? sqrt(n2) / nb : 0.0;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = 0.0;
+    for (int c = 0; c < s; ++c) m = fmax(m, isfinite(cres[c]) ? cres[c] : 1e300);
+    res[(long)b * n_omega + k] = m;
+  }
+}
+
+// Per (band, shift): block LU solve of (T_k - z) Y = E_0 R_0 over k block steps (forward: D_i, G_i as
+// in k_blk_shift, kept in scratch; backward: Y_{k-1} = D_{k-1}^-1 G_{k-1},
+// Y_i = D_i^-1 (G_i - B_{i+1}^H Y_{i+1})).  Y goes to ycat[b] at rows i s + r, column c n_omega + shift
+// (leading dimension ldy).
+__global__ __launch_bounds__(kBlkThreads) void k_blk_solve(int s, int n_omega, int k, int nbc,
+                                                         const double2 *__restrict__ ablk,
+                                                         const double2 *__restrict__ bblk,
+                                                         const double2 *__restrict__ r0,
+                                                         const double2 *__restrict__ zs, double2 *__restrict__ scratch,
+                                                         double2 *__restrict__ ycat, long ldy, long ycat_stride) {
+  __shared__ double2 X1[kBlockMaxPert][kBlockMaxPert + 1], X2[kBlockMaxPert][kBlockMaxPert + 1],
+      X3[kBlockMaxPert][kBlockMaxPert + 1];
+  __shared__ int perm[kBlockMaxPert];
+  const int b = blockIdx.x / n_omega, sh = blockIdx.x - b * n_omega;
+  const long ss = (long)s * s;
+  const double2 z = zs[sh];
+  double2 *scr = scratch + ((long)b * n_omega + sh) * 2 * k * ss;  // step i: D_i^-1, then G_i
+  for (int i = 0; i < k; ++i) {
+    if (i == 0) {
+      blk_load(X1, r0 + (long)b * ss, s);
+      for (int e = threadIdx.x; e < s * s; e += kBlkThreads) X3[e % s][e / s] = make_double2(0.0, 0.0);
+      __syncthreads();
+    } else {
+      blk_load(X1, scr + (long)(i - 1) * 2 * ss, s);
+      blk_load(X2, bblk + ((long)i * nbc + b) * ss, s);
+      blk_mm(X3, X2, false, X1, false, s, 1.0, 0);
+      blk_load(X1, scr + (long)(i - 1) * 2 * ss + ss, s);
+      blk_mm(X1, X3, false, X1, false, s, -1.0, 0);
+      blk_mm(X3, X3, false, X2, true, s, 1.0, 0);
+    }
+    blk_diff_shift(X3, ablk + ((long)i * nbc + b) * ss, z, s);
+    blk_inverse(X3, s, perm);
+    blk_store(scr + (long)i * 2 * ss, X3, s);
+    blk_store(scr + (long)i * 2 * ss + ss, X1, s);
+  }
+  double2 *yb = ycat + (long)b * ycat_stride;
+  for (int i = k - 1; i >= 0; --i) {
+    blk_load(X1, scr + (long)i * 2 * ss + ss, s);  // G_i
+    if (i < k - 1) {
+      blk_load(X3, bblk + ((long)(i + 1) * nbc + b) * ss, s);
+      blk_mm(X1, X3, true, X2, false, s, 1.0, 1);  // G_i - B_{i+1}^H Y_{i+1}
+    }
+    blk_load(X3, scr + (long)i * 2 * ss, s);
+    blk_mm(X2, X3, false, X1, false, s, 1.0, 0);  // Y_i
+    for (int e = threadIdx.x; e < s * s; e += kBlkThreads) {
+      const int r = e % s, c = e / s;
+      yb[(long)(i * s + r) + (long)(c * n_omega + sh) * ldy] = X2[r][c];
+    }
+    __syncthreads();
+  }
+}
+
+// True FP64 residuals of a run of solution vectors: x[a] (internal order), y[a] = (H + alpha P) x[a],
+// vector a = (band, pert, shift) = first + a; relres = ||b - (y - eps x - z x)|| / ||b||, occupied
+// leak ||psi^H x|| / ||x|| from the overlaps cp[a][i]
+__global__ __launch_bounds__(256) void k_blk_residual(int npw, int n_occ, int s, int n_omega, long first,
+                                                      const double2 *__restrict__ x, const double2 *__restrict__ y,
+                                                      const double2 *__restrict__ rhs, const double *__restrict__ eps,
+                                                      const double2 *__restrict__ zs, const double2 *__restrict__ cp,
+                                                      double tol, int iters, int maxed, sgw_solve_info *info,
+                                                      long info_first, int *bad) {
+  __shared__ double red[3][256];
+  const long a = blockIdx.x;
+  const long v = first + a;  // (b * s + c) * n_omega + k within the chunk
+  const int k = (int)(v % n_omega);
+  const long bc = v / n_omega;
+  const int b = (int)(bc / s);
+  const double2 z = zs[k];
+  const double e = eps[b];
+  const double2 *xa = x + a * npw, *ya = y + a * npw, *ba = rhs + bc * npw;
+  double rr = 0.0, bb = 0.0, xx = 0.0;
+  for (int g = threadIdx.x; g < npw; g += 256) {
+    const double2 xv = xa[g], yv = ya[g], bv = ba[g];
+    // (A - z) x = y - eps x - z x
+    const double ax = yv.x - e * xv.x - (z.x * xv.x - z.y * xv.y);
+    const double ay = yv.y - e * xv.y - (z.x * xv.y + z.y * xv.x);
+    const double rx = bv.x - ax, ry = bv.y - ay;
+    rr += rx * rx + ry * ry;
+    bb += bv.x * bv.x + bv.y * bv.y;
+    xx += xv.x * xv.x + xv.y * xv.y;
+  }
+  red[0][threadIdx.x] = rr;
+  red[1][threadIdx.x] = bb;
+  red[2][threadIdx.x] = xx;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h)
+      for (int q = 0; q < 3; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    double occ = 0.0;
+    for (int i = 0; i < n_occ; ++i) {
+      const double2 c = cp[a * n_occ + i];
+      occ += c.x * c.x + c.y * c.y;
+    }
+    const double nb = sqrt(red[1][0]), nx = sqrt(red[2][0]);
+    const double rel = nb > 0.0 ? sqrt(red[0][0]) / nb : 0.0;
+    sgw_solve_info o;
+    o.iters = iters;
+    o.relres = rel;
+    o.occ_leak = nx > 0.0 ? sqrt(occ) / nx : 0.0;
+    int fl = 0;
+    if (!isfinite(rel)) fl |= SGW_FLAG_NONFINITE;
+    else if (nb == 0.0) fl |= SGW_FLAG_CONVERGED | SGW_FLAG_ZERO_RHS;
+    else if (rel <= tol) fl |= SGW_FLAG_CONVERGED;
+    else fl |= maxed ? SGW_FLAG_MAXITER : 0;
+    o.flags = fl;
+    info[info_first + v] = o;
+    if (!(fl & SGW_FLAG_CONVERGED)) atomicOr(bad, 1);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// rocBLAS
+// ---------------------------------------------------------------------------
+rocblas_handle blas(sgw_ctx *ctx) {
+  if (!ctx->blas) {
+    rocblas_handle h = nullptr;
+    if (rocblas_create_handle(&h) != rocblas_status_success) return nullptr;
+    ctx->blas = h;
+  }
+  rocblas_handle h = (rocblas_handle)ctx->blas;
+  rocblas_set_stream(h, ctx->stream);
+  return h;
+}
+
+// C_b = alpha op(A_b) B_b + beta C_b over nbatch (column-major, strides in elements)
+sgw_status zgemm(sgw_ctx *ctx, rocblas_operation ta, rocblas_operation tb, int m, int n, int k, double2 alpha,
+                 const double2 *A, long lda, long sa, const double2 *B, long ldb, long sb, double2 beta, double2 *C,
+                 long ldc, long sc, int nbatch) {
+  rocblas_handle h = blas(ctx);
+  if (!h) return fail(SGW_ERR_HIP, "block solver: rocblas_create_handle failed");
+  const rocblas_double_complex al(alpha.x, alpha.y), be(beta.x, beta.y);
+  const rocblas_status r = rocblas_zgemm_strided_batched(
+      h, ta, tb, m, n, k, &al, (const rocblas_double_complex *)A, lda, sa, (const rocblas_double_complex *)B, ldb, sb,
+      &be, (rocblas_double_complex *)C, ldc, sc, nbatch);
+  if (r != rocblas_status_success) return fail(SGW_ERR_HIP, "block solver: rocblas_zgemm_strided_batched failed");
+  return SGW_OK;
+}
+
+}  // namespace
+
+void blas_release(sgw_ctx *ctx) {
+  if (ctx && ctx->blas) {
+    rocblas_destroy_handle((rocblas_handle)ctx->blas);
+    ctx->blas = nullptr;
+  }
+}
+
+size_t block_workspace_bytes(const sgw_ham *h_kq, int n_occ, int n_band, int n_pert, int n_omega,
+                             const sgw_opts &o) {
+  if (n_band <= 0 || n_pert <= 0) return 256;
+  const int kb = blk_steps(o) + 1;
+  const int nbc = blk_chunk(h_kq, n_occ, n_band, n_pert, n_omega, kb, kBlockBudget, o.slots);
+  return blk_layout(h_kq, n_occ, nbc, n_pert, n_omega, kb).total;
+}
+
+sgw_status block_solve(sgw_ctx *ctx, const sgw_ham *h_kq, int n_occ, const sgw_c128 *psi_occ_kq, const sgw_ham *h_k,
+                       int n_band, const sgw_c128 *psi_v, const double *eps_v, int n_pert, const int32_t *dv_miller,
+                       int n_omega, const double *omega, double eta, double tol, const sgw_opts &o, void *workspace,
+                       size_t workspace_bytes, sgw_c128 *dpsi, sgw_solve_info *info) {
+  const int s = n_pert;
+  if (s > kBlockMaxPert) return fail(SGW_ERR_UNSUPPORTED, "block solver: more than 32 perturbations per band");
+  const int npw = h_kq->n_pw;
+  const int kb = blk_steps(o) + 1;
+  const int nbc = blk_chunk(h_kq, n_occ, n_band, s, n_omega, kb, (double)workspace_bytes, o.slots);
+  const BlkLayout L = blk_layout(h_kq, n_occ, nbc, s, n_omega, kb);
+  if (L.total > workspace_bytes) return fail(SGW_ERR_WORKSPACE, "block solver: workspace too small for one band");
+  char *Wb = (char *)workspace;
+  auto P = [&](size_t off) { return (double2 *)(Wb + off); };
+  double2 *basis = P(L.basis), *rhs = P(L.rhs), *Y = P(L.y), *Wv = P(L.w), *V2 = P(L.v2), *gram = P(L.gram),
+          *rfac = P(L.rfac), *rinv = P(L.rinv), *ablk = P(L.ablk), *bblk = P(L.bblk), *r0 = P(L.r0),
+          *dinv = P(L.dinv), *ff = P(L.ff), *thomas = P(L.thomas), *ycat = P(L.ycat), *xout = P(L.xout),
+          *C = P(L.c), *psi = P(L.psi), *zs = P(L.omega);
+  double *bnorm = (double *)(Wb + L.bnorm), *res = (double *)(Wb + L.res), *deps = (double *)(Wb + L.eps);
+  int32_t *list = (int32_t *)(Wb + L.list);
+  int *bad = (int *)(Wb + L.bad);
+  void *T = Wb + L.t;
+  const long ss = (long)s * s;
+  const double2 one = make_double2(1.0, 0.0), zero = make_double2(0.0, 0.0), mone = make_double2(-1.0, 0.0);
+  sgw_status st;
+
+  // shifts z_j = omega_j + i eta_j, occupied states in internal order, dv_miller on the device
+  std::vector<double2> hz(n_omega);
+  for (int j = 0; j < n_omega; ++j) hz[j] = make_double2(omega[j], o.shift_imag ? o.shift_imag[j] : eta);
+  SGW_HIP(hipMemcpyAsync(zs, hz.data(), sizeof(double2) * n_omega, hipMemcpyHostToDevice, ctx->stream));
+  if ((st = permute(ctx, npw, n_occ, (const double2 *)psi_occ_kq, npw, psi, npw, h_kq->d_i2u, 0)) != SGW_OK) return st;
+  int32_t *ddvm = (int32_t *)(Wb + L.dvm);
+  SGW_HIP(hipMemcpyAsync(ddvm, dv_miller, sizeof(int32_t) * 3 * s, hipMemcpyHostToDevice, ctx->stream));
+  std::vector<int32_t> hpairs(std::max<size_t>((size_t)nbc * s, (size_t)L.nsub));
+  bool any_bad = false;
+  const double tol_int = tol * o.tol_safety;
+
+  for (int b0 = 0; b0 < n_band; b0 += nbc) {
+    const int nb = std::min(nbc, n_band - b0);
+    const int nv = nb * s;
+    SGW_HIP(hipMemsetAsync(bad, 0, 8, ctx->stream));
+    SGW_HIP(hipMemcpyAsync(deps, eps_v + b0, sizeof(double) * nb, hipMemcpyHostToDevice, ctx->stream));
+    // right-hand sides in internal order: rhs = (1 - P) s (the solution is negated on the way out)
+    for (int a = 0; a < nv; ++a) hpairs[a] = (b0 + a / s) * s + a % s;
+    SGW_HIP(hipMemcpyAsync(list, hpairs.data(), sizeof(int32_t) * nv, hipMemcpyHostToDevice, ctx->stream));
+    if ((st = rhs_source(ctx, h_kq, h_k, nv, list, s, ddvm, (const double2 *)psi_v, h_k->n_pw, Y, npw)) != SGW_OK)
+      return st;
+    if ((st = proj_dot(ctx, npw, n_occ, psi, nv, contiguous(Y, npw), C, nv)) != SGW_OK) return st;
+    if ((st = proj_apply(ctx, npw, n_occ, psi, nv, contiguous(Y, npw), C, nv, rhs, npw, 1.0, 0)) != SGW_OK) return st;
+    // column norms of every band's block (for the residual estimates): diagonal of rhs^H rhs
+    if ((st = zgemm(ctx, rocblas_operation_conjugate_transpose, rocblas_operation_none, s, s, npw, one, rhs, npw,
+                    (long)s * npw, rhs, npw, (long)s * npw, zero, gram, s, ss, nb)) != SGW_OK)
+      return st;
+    {
+      std::vector<double2> hg((size_t)nb * ss);
+      SGW_HIP(hipMemcpyAsync(hg.data(), gram, sizeof(double2) * nb * ss, hipMemcpyDeviceToHost, ctx->stream));
+      if ((st = sync(ctx)) != SGW_OK) return st;
+      std::vector<double> hn(nv);
+      for (int b = 0; b < nb; ++b)
+        for (int c = 0; c < s; ++c) hn[b * s + c] = std::sqrt(std::max(hg[(size_t)b * ss + c + c * s].x, 0.0));
+      SGW_HIP(hipMemcpyAsync(bnorm, hn.data(), sizeof(double) * nv, hipMemcpyHostToDevice, ctx->stream));
+    }
+    // V_0 R_0 = rhs (Cholesky QR twice)
+    auto orth = [&](const double2 *src, double2 *dst, double2 *rout) -> sgw_status {
+      sgw_status s2;
+      if ((s2 = zgemm(ctx, rocblas_operation_conjugate_transpose, rocblas_operation_none, s, s, npw, one, src, npw,
+                      (long)s * npw, src, npw, (long)s * npw, zero, gram, s, ss, nb)) != SGW_OK)
+        return s2;
+      hipLaunchKernelGGL(k_blk_chol, dim3(nb), dim3(64), 0, ctx->stream, gram, (const double2 *)nullptr, rfac, rinv,
+                         s, bad);
+      if ((s2 = zgemm(ctx, rocblas_operation_none, rocblas_operation_none, npw, s, s, one, src, npw, (long)s * npw,
+                      rinv, s, ss, zero, V2, npw, (long)s * npw, nb)) != SGW_OK)
+        return s2;
+      if ((s2 = zgemm(ctx, rocblas_operation_conjugate_transpose, rocblas_operation_none, s, s, npw, one, V2, npw,
+                      (long)s * npw, V2, npw, (long)s * npw, zero, gram, s, ss, nb)) != SGW_OK)
+        return s2;
+      hipLaunchKernelGGL(k_blk_chol, dim3(nb), dim3(64), 0, ctx->stream, gram, (const double2 *)rfac, rout, rinv, s,
+                         bad);
+      // dst (strided per band in the basis) = V2 R2^-1
+      return zgemm(ctx, rocblas_operation_none, rocblas_operation_none, npw, s, s, one, V2, npw, (long)s * npw, rinv,
+                   s, ss, zero, dst, npw, (long)kb * s * npw, nb);
+    };
+    if ((st = orth(rhs, basis, r0)) != SGW_OK) return st;
+    // block Lanczos steps with the residual estimates of every (band, shift)
+    int k = 0;
+    bool converged = false;
+    std::vector<double> hres((size_t)nb * n_omega);
+    // host polls: every step once a step is large enough to hide the round trip
+    const int poll = (long)nv * npw >= (1L << 22) ? 1 : std::max(1, o.steps_per_sync);
+    for (int j = 0; j + 1 < kb; ++j) {
+      hipLaunchKernelGGL(k_blk_list, dim3((nv + 255) / 256), dim3(256), 0, ctx->stream, list, nb, s, kb, j);
+      const VecSrc vj = listed(basis, npw, list);
+      if ((st = proj_dot(ctx, npw, n_occ, psi, nv, vj, C, nv)) != SGW_OK) return st;
+      if ((st = hx_batch(ctx, h_kq, nv, vj, Y, npw, T)) != SGW_OK) return st;
+      if ((st = proj_apply(ctx, npw, n_occ, psi, nv, vj, C, nv, Y, npw, o.alpha_pv, 1)) != SGW_OK) return st;
+      hipLaunchKernelGGL(k_blk_shift_eps, dim3(nv, (npw + 255) / 256), dim3(256), 0, ctx->stream, npw, s,
+                         (const double2 *)Y, (const double2 *)basis, (const int32_t *)list, (const double *)deps, Wv);
+      double2 *vj_ptr = basis + (long)j * s * npw;  // band 0; bands strided by kb s npw
+      if (j > 0) {  // W -= V_{j-1} B_j^H
+        if ((st = zgemm(ctx, rocblas_operation_none, rocblas_operation_conjugate_transpose, npw, s, s, mone,
+                        vj_ptr - (long)s * npw, npw, (long)kb * s * npw, bblk + (long)j * nbc * ss, s, ss, one, Wv,
+                        npw, (long)s * npw, nb)) != SGW_OK)
+          return st;
+      }
+      double2 *aj = ablk + (long)j * nbc * ss;
+      if ((st = zgemm(ctx, rocblas_operation_conjugate_transpose, rocblas_operation_none, s, s, npw, one, vj_ptr, npw,
+                      (long)kb * s * npw, Wv, npw, (long)s * npw, zero, aj, s, ss, nb)) != SGW_OK)
+        return st;
+      hipLaunchKernelGGL(k_blk_hermitize, dim3(nb), dim3(256), 0, ctx->stream, aj, s);
+      if ((st = zgemm(ctx, rocblas_operation_none, rocblas_operation_none, npw, s, s, mone, vj_ptr, npw,
+                      (long)kb * s * npw, aj, s, ss, one, Wv, npw, (long)s * npw, nb)) != SGW_OK)
+        return st;
+      if ((st = orth(Wv, vj_ptr + (long)s * npw, bblk + (long)(j + 1) * nbc * ss)) != SGW_OK) return st;
+      hipLaunchKernelGGL(k_blk_shift, dim3(nb * n_omega), dim3(kBlkThreads), 0, ctx->stream, s, n_omega, j,
+                         (const double2 *)aj, (const double2 *)(bblk + (long)j * nbc * ss),
+                         (const double2 *)(bblk + (long)(j + 1) * nbc * ss), (const double2 *)r0,
+                         (const double *)bnorm, (const double2 *)zs, dinv, ff, res);
+      SGW_HIP(hipGetLastError());
+      k = j + 1;
+      if (k % poll == 0 || k + 1 >= kb) {
+        SGW_HIP(hipMemcpyAsync(hres.data(), res, sizeof(double) * nb * n_omega, hipMemcpyDeviceToHost, ctx->stream));
+        if ((st = sync(ctx)) != SGW_OK) return st;
+        double worst = 0.0;
+        for (double r : hres) worst = std::max(worst, std::isfinite(r) ? r : 1e300);
+        if (worst <= tol_int) {
+          converged = true;
+          break;
+        }
+      }
+    }
+    int hbad = 0;
+    SGW_HIP(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    if ((st = sync(ctx)) != SGW_OK) return st;
+    if (hbad) return fail(SGW_ERR_UNSUPPORTED, "block solver: a block lost rank (dependent right-hand sides)");
+    // solutions: Y(z) per shift, X = V Y per band, to the caller's order with the sign of b
+    hipLaunchKernelGGL(k_blk_solve, dim3(nb * n_omega), dim3(kBlkThreads), 0, ctx->stream, s, n_omega, k, nbc,
+                       (const double2 *)ablk, (const double2 *)bblk, (const double2 *)r0, (const double2 *)zs, thomas,
+                       ycat, (long)kb * s, (long)kb * s * s * n_omega);
+    SGW_HIP(hipGetLastError());
+    if ((st = zgemm(ctx, rocblas_operation_none, rocblas_operation_none, npw, s * n_omega, k * s, one, basis, npw,
+                    (long)kb * s * npw, ycat, (long)kb * s, (long)kb * s * s * n_omega, zero, xout, npw,
+                    (long)s * n_omega * npw, nb)) != SGW_OK)
+      return st;
+    const long nsol = (long)nv * n_omega;
+    // true residuals in runs of nsub solutions
+    for (long f = 0; f < nsol; f += L.nsub) {
+      const int m = (int)std::min<long>(L.nsub, nsol - f);
+      const VecSrc xs = contiguous(xout + f * npw, npw);
+      if ((st = proj_dot(ctx, npw, n_occ, psi, m, xs, C, m)) != SGW_OK) return st;
+      if ((st = hx_batch(ctx, h_kq, m, xs, Y, npw, T)) != SGW_OK) return st;
+      if ((st = proj_apply(ctx, npw, n_occ, psi, m, xs, C, m, Y, npw, o.alpha_pv, 1)) != SGW_OK) return st;
+      hipLaunchKernelGGL(k_blk_residual, dim3(m), dim3(256), 0, ctx->stream, npw, n_occ, s, n_omega, f,
+                         (const double2 *)(xout + f * npw), (const double2 *)Y, (const double2 *)rhs,
+                         (const double *)deps, (const double2 *)zs, (const double2 *)C, tol, k,
+                         converged ? 0 : 1, info, (long)b0 * s * n_omega, bad);
+      SGW_HIP(hipGetLastError());
+    }
+    if ((st = permute(ctx, npw, (int)nsol, xout, npw, (double2 *)dpsi + (long)b0 * s * n_omega * npw, npw,
+                      h_kq->d_i2u, 1, -1.0)) != SGW_OK)
+      return st;
+    SGW_HIP(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    if ((st = sync(ctx)) != SGW_OK) return st;
+    any_bad = any_bad || hbad;
+  }
+  return any_bad ? SGW_NOT_CONVERGED : SGW_OK;
+}
+
+}  // namespace sgw

@@ -82,6 +82,8 @@ struct sgw_ctx {
   size_t pinned_bytes = 0;
   // autotuned options per system class (grid / n_pw / n_occ / n_omega)
   std::map<std::string, sgw_opts> tuned;
+  // rocBLAS handle of the block solver (created on its first use, bound to `stream`)
+  void *blas = nullptr;
 };
 
 // Device-resident index maps of one Hamiltonian.  "internal" order is
@@ -224,5 +226,17 @@ sgw_status permute_copy(sgw_ctx *ctx, int n_pw, int n_vec, VecSrc x, double2 *y,
 // out[a][g] = in[a][perm[g]] (gather) or out[a][perm[g]] = in[a][g] (scatter)
 sgw_status permute(sgw_ctx *ctx, int n_pw, int n_vec, const double2 *in, long ldin, double2 *out,
                    long ldout, const int32_t *perm, int scatter, double scale = 1.0);
+
+// Block solver (SGW_SOLVER_BLOCK): one block Krylov space per band over its perturbations.
+constexpr int kBlockMaxPert = 32;                        // perturbations per band (block size)
+constexpr double kBlockBudget = 144.0 * (1ull << 30);   // workspace the band chunks are sized for
+size_t block_workspace_bytes(const sgw_ham *h_kq, int n_occ, int n_band, int n_pert, int n_omega,
+                             const sgw_opts &o);
+sgw_status block_solve(sgw_ctx *ctx, const sgw_ham *h_kq, int n_occ, const sgw_c128 *psi_occ_kq, const sgw_ham *h_k,
+                       int n_band, const sgw_c128 *psi_v, const double *eps_v, int n_pert, const int32_t *dv_miller,
+                       int n_omega, const double *omega, double eta, double tol, const sgw_opts &o, void *workspace,
+                       size_t workspace_bytes, sgw_c128 *dpsi, sgw_solve_info *info);
+// releases the context's rocBLAS handle
+void blas_release(sgw_ctx *ctx);
 
 }  // namespace sgw

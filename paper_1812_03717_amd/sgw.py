@@ -20,7 +20,7 @@ SGW_OK, SGW_NOT_CONVERGED = 0, 1
 SGW_ERR_INVALID_ARG, SGW_ERR_HIP, SGW_ERR_WORKSPACE, SGW_ERR_UNSUPPORTED = -1, -2, -3, -4
 FLAG_CONVERGED, FLAG_MAXITER, FLAG_BREAKDOWN, FLAG_NONFINITE, FLAG_ZERO_RHS = 1, 2, 4, 8, 16
 FLAG_PER_SHIFT = 32
-SOLVER_MULTISHIFT, SOLVER_PER_SHIFT, SOLVER_TAIL = 0, 1, 2
+SOLVER_MULTISHIFT, SOLVER_PER_SHIFT, SOLVER_TAIL, SOLVER_BLOCK = 0, 1, 2, 3
 FP64, MIXED = 0, 1
 PC_NONE, PC_TETER, PC_LEARNED = 0, 1, 2
 GUESS_ZERO, GUESS_LEARNED = 0, 1

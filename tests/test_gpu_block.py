@@ -1,0 +1,130 @@
+"""GPU: the block solver (SGW_SOLVER_BLOCK: one block Krylov space per band over its perturbations,
+FOM solutions per shift; Secs. 2.2-2.3, Eqs. 6-8) through the C ABI, against the oracle.
+
+The solutions of the block space are the solutions of the same linear systems, so the block solver
+is held to the multishift solver's bar: 1e-8 relative per solve against the oracle's spectral
+solve, at tol_eff = 1e-8 / (2 kappa).  Bands split over several chunks (opts.slots), imaginary-axis
+shifts (opts.shift_imag), a non-local pseudopotential and the argument checks are covered too.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import oracle.sternheimer_oracle as so
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from tests.libutil import ensure_library
+    ensure_library()
+    from paper_1812_03717_amd import sgw
+    c = sgw.sgw_ctx_create(0)
+    yield c
+    torch.cuda.synchronize()
+
+
+def _reference(p, shifts_imag=None):
+    """Exact solutions of every (v, p, z) by the oracle's spectral solve, and tol_eff."""
+    pairs = [(v, q) for v in range(p.n_band) for q in range(p.n_pert)]
+    _, w, u = oracle.spectral_setup(p.miller_kq, p.B, p.kvec + p.qvec, p.v_grid)
+    zs = p.omega + 1j * (p.eta if shifts_imag is None else np.asarray(shifts_imag))
+    xs = np.array([so.solve_spectral(w, u, p.n_occ, float(p.eps_k[v]),
+                                     so.rhs(p.psi_k[v], p.miller_k, p.miller_kq, p.dv_miller[q], p.psi_kq), zs)
+                   for v, q in pairs])
+    kap = max(so.condition_number(w, p.n_occ, p.eps_k[v], z) for v in range(p.n_band) for z in zs)
+    return pairs, xs, min(p.tol, 1e-8 / (2.0 * kap))
+
+
+def _check(p, pairs, xs, dpsi, inf, tol):
+    from paper_1812_03717_amd import sgw
+    assert np.all(inf["flags"] & sgw.FLAG_CONVERGED), inf["flags"]
+    assert inf["relres"].max() <= tol
+    assert inf["occ_leak"].max() <= 1e-10
+    worst = 0.0
+    for i, (v, q) in enumerate(pairs):
+        for j in range(p.n_omega):
+            ref = xs[i, j]
+            err = np.linalg.norm(dpsi[v, q, j] - ref) / np.linalg.norm(ref)
+            worst = max(worst, err)
+            assert err <= 1e-8, (v, q, j, err)
+    return worst
+
+
+@pytest.mark.parametrize("cells,n_pert,slots", [((1, 1, 1), 5, 0), ((1, 1, 1), 5, 3), ((2, 1, 1), 8, 0)])
+def test_block_matches_oracle(ctx, cells, n_pert, slots):
+    from paper_1812_03717_amd import sgw
+    from paper_1812_03717_amd.workload import DeviceProblem
+    p = synth.small(cells, n_omega=6, n_pert=n_pert, seed=9100)
+    pairs, xs, tol = _reference(p)
+    d = DeviceProblem(ctx, p)
+    st, dpsi, info = d.solve(tol=tol, opts=sgw.sgw_opts_default(solver=sgw.SOLVER_BLOCK, slots=slots))
+    inf = sgw.info_to_numpy(info, (p.n_band, p.n_pert, p.n_omega))
+    if st != sgw.SGW_OK:
+        bad = ~(inf["flags"] & sgw.FLAG_CONVERGED).astype(bool)
+        print(f"tol {tol:.3e}: {bad.sum()} unconverged, flags {np.unique(inf['flags'][bad])}, relres "
+              f"{inf['relres'][bad].min():.3e}..{inf['relres'][bad].max():.3e}", flush=True)
+    assert st == sgw.SGW_OK, sgw.load_library().sgw_last_error()
+    worst = _check(p, pairs, xs, dpsi.cpu().numpy(), inf, tol)
+    # the multishift solver on the same systems: every scalar Krylov space is at least as long as the
+    # block space's step count
+    st1, _, info1 = d.solve(tol=tol)
+    inf1 = sgw.info_to_numpy(info1, (p.n_band, p.n_pert, p.n_omega))
+    refined = inf["flags"] & sgw.FLAG_PER_SHIFT != 0
+    print(f"{p.name} n_pert {n_pert} slots {slots}: worst rel err {worst:.2e}, block steps "
+          f"{inf['iters'][~refined].max()}, {refined.sum()} of {refined.size} refined per shift, multishift "
+          f"dimension {inf1['iters'].max()}", flush=True)
+    assert st1 == sgw.SGW_OK and inf["iters"][~refined].max() <= inf1["iters"].max()
+
+
+def test_block_imaginary_axis(ctx):
+    from paper_1812_03717_amd import sgw
+    from paper_1812_03717_amd.workload import DeviceProblem
+    p = synth.small((1, 1, 1), n_omega=5, n_pert=4, seed=9107)
+    eta_j = np.linspace(0.02, 1.5, p.n_omega)
+    pairs, xs, tol = _reference(p, eta_j)
+    d = DeviceProblem(ctx, p)
+    opts = sgw.sgw_opts_default(solver=sgw.SOLVER_BLOCK, shift_imag=eta_j)
+    st, dpsi, info = d.solve(tol=tol, opts=opts)
+    assert st == sgw.SGW_OK, sgw.load_library().sgw_last_error()
+    _check(p, pairs, xs, dpsi.cpu().numpy(), sgw.info_to_numpy(info, (p.n_band, p.n_pert, p.n_omega)), tol)
+
+
+def test_block_nonlocal(ctx):
+    from paper_1812_03717_amd import sgw
+    from paper_1812_03717_amd.workload import DeviceProblem
+    p = synth.small((1, 1, 1), n_omega=4, n_pert=3, seed=9111, nonlocal_pp=True)
+    d = DeviceProblem(ctx, p)
+    st, dpsi, info = d.solve(opts=sgw.sgw_opts_default(solver=sgw.SOLVER_BLOCK))
+    assert st == sgw.SGW_OK, sgw.load_library().sgw_last_error()
+    inf = sgw.info_to_numpy(info, (p.n_band, p.n_pert, p.n_omega))
+    st1, x1, info1 = d.solve()
+    assert st1 == sgw.SGW_OK
+    # both solutions meet tol on the same well-conditioned systems: they agree to the error budget
+    # relres ||b|| / eta of each
+    bv = sgw.sgw_build_rhs(ctx, d.h_kq, d.psi_occ_kq, d.h_k, d.psi_v, p.dv_miller)
+    nb = torch.linalg.vector_norm(bv, dim=-1).cpu().numpy()[:, :, None]
+    inf1 = sgw.info_to_numpy(info1, (p.n_band, p.n_pert, p.n_omega))
+    diff = torch.linalg.vector_norm(dpsi - x1, dim=-1).cpu().numpy()
+    assert np.all(diff <= 1.01 * (inf["relres"] + inf1["relres"]) * nb / p.eta + 1e-14)
+
+
+def test_block_errors(ctx):
+    from paper_1812_03717_amd import sgw
+    from paper_1812_03717_amd.workload import DeviceProblem
+    p = synth.small((1, 1, 1), n_omega=2, n_pert=3, seed=9100)
+    d = DeviceProblem(ctx, p)
+    for bad in ({"precision": sgw.MIXED}, {"precond": sgw.PC_TETER}):
+        with pytest.raises(sgw.SgwError) as e:
+            d.solve(opts=sgw.sgw_opts_default(solver=sgw.SOLVER_BLOCK, **bad))
+        assert e.value.code == sgw.SGW_ERR_INVALID_ARG, bad
+    q = synth.small((1, 1, 1), n_omega=2, n_pert=33, seed=9100)
+    with pytest.raises(sgw.SgwError) as e:
+        DeviceProblem(ctx, q).solve(opts=sgw.sgw_opts_default(solver=sgw.SOLVER_BLOCK))
+    assert e.value.code == sgw.SGW_ERR_UNSUPPORTED
