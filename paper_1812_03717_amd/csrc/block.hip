@@ -30,13 +30,15 @@ namespace sgw {
 namespace {
 
 constexpr size_t kBA = 256;
+constexpr int kGramRows = 256;  // plane waves per partial sum of the skinny products
+constexpr int kGramTile = 32;   // rows staged in LDS at a time
 size_t up(size_t b) { return (b + kBA - 1) / kBA * kBA; }
 
 // Workspace of one chunk of nbc bands; kb = block steps + 1 stored blocks
 struct BlkLayout {
   int nbc = 0, kb = 0, s = 0, nsub = 0;
-  size_t basis, rhs, y, w, v2, gram, rfac, rinv, ablk, bblk, r0, bnorm, dinv, ff, res, thomas, ycat, xout, list,
-      c, t, psi, omega, eps, dvm, bad, total;
+  size_t basis, rhs, y, w, v2, gram, part, rfac, rinv, ablk, bblk, r0, bnorm, dinv, ff, res, thomas, ycat, xout, list,
+      c, t, psi, omega, eps, conv, ord, dvm, bad, total;
 };
 
 BlkLayout blk_layout(const sgw_ham *h, int n_occ, int nbc, int s, int n_omega, int kb) {
@@ -58,6 +60,7 @@ BlkLayout blk_layout(const sgw_ham *h, int n_occ, int nbc, int s, int n_omega, i
   L.w = take(16 * nv * npw);
   L.v2 = take(16 * nv * npw);
   L.gram = take(16 * nbc * ss);
+  L.part = take(16 * (size_t)((npw + kGramRows - 1) / kGramRows) * nbc * ss);
   L.rfac = take(16 * nbc * ss);
   L.rinv = take(16 * nbc * ss);
   L.ablk = take(16 * (size_t)kb * nbc * ss);
@@ -76,6 +79,8 @@ BlkLayout blk_layout(const sgw_ham *h, int n_occ, int nbc, int s, int n_omega, i
   L.psi = take(16 * (size_t)std::max(n_occ, 1) * npw);
   L.omega = take(16 * (size_t)n_omega);
   L.eps = take(8 * (size_t)nbc);
+  L.conv = take(4 * (size_t)nbc * n_omega);
+  L.ord = take(8 * (size_t)n_omega);
   L.dvm = take(4 * 3 * (size_t)s);
   L.bad = take(8);
   L.total = off;
@@ -131,6 +136,60 @@ __global__ void k_blk_hermitize(double2 *m, int s) {
     const double2 h = make_double2(0.5 * (a.x + b.x), 0.5 * (a.y - b.y));
     mb[i + j * s] = h;
     mb[j + i * s] = make_double2(h.x, -h.y);
+  }
+}
+
+// Skinny products C_b = A_b^H B_b (s x s, column-major) of every band's n_pw x s blocks, in two
+// deterministic passes: partial sums over chunks of kGramRows plane waves (one workgroup per chunk and
+// band, rows staged through LDS with coalesced column loads), then the chunks summed in order.
+
+__global__ __launch_bounds__(256) void k_blk_gram(int npw, int s, const double2 *__restrict__ A, long sa,
+                                                  const double2 *__restrict__ B, long sb, double2 *__restrict__ part) {
+  __shared__ double2 As[kGramTile][kBlockMaxPert + 1], Bs[kGramTile][kBlockMaxPert + 1];
+  const int chunk = blockIdx.x, b = blockIdx.y, nb = gridDim.y;
+  const double2 *a = A + (long)b * sa, *bb = B + (long)b * sb;
+  const int t = threadIdx.x;
+  double2 acc[4];
+  for (int r = 0; r < 4; ++r) acc[r] = make_double2(0.0, 0.0);
+  const int g_end = min(npw, (chunk + 1) * kGramRows);
+  for (int g0 = chunk * kGramRows; g0 < g_end; g0 += kGramTile) {
+    const int rows = min(kGramTile, g_end - g0);
+    for (int e = t; e < kGramTile * s; e += 256) {
+      const int r = e % kGramTile, c = e / kGramTile;
+      const bool in = r < rows;
+      As[r][c] = in ? a[(long)c * npw + g0 + r] : make_double2(0.0, 0.0);
+      Bs[r][c] = in ? bb[(long)c * npw + g0 + r] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = t + 256 * q;
+      if (e < s * s) {
+        const int i = e % s, j = e / s;
+        double2 v = acc[q];
+        for (int r = 0; r < kGramTile; ++r) {
+          const double2 x = As[r][i], y = Bs[r][j];
+          v.x += x.x * y.x + x.y * y.y;
+          v.y += x.x * y.y - x.y * y.x;
+        }
+        acc[q] = v;
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int e = t + 256 * q;
+    if (e < s * s) part[((long)chunk * nb + b) * s * s + e] = acc[q];
+  }
+}
+
+__global__ void k_blk_gram_sum(int n_chunks, int nb, int ss, const double2 *__restrict__ part, double2 *__restrict__ c) {
+  const int b = blockIdx.x;
+  for (int e = threadIdx.x; e < ss; e += blockDim.x) {
+    double2 v = make_double2(0.0, 0.0);
+    for (int k = 0; k < n_chunks; ++k) v = c_add(v, part[((long)k * nb + b) * ss + e]);
+    c[(long)b * ss + e] = v;
   }
 }
 
@@ -217,20 +276,26 @@ __device__ __forceinline__ void blk_store(double2 *dst, Blk M, int s) {
 // A or B: the products are formed in registers before any entry is written
 __device__ void blk_mm(Blk C, Blk A, bool ha, Blk B, bool hb, int s, double sgn, int mode) {
   double2 acc[4];
-  int r = 0;
-  for (int e = threadIdx.x; e < s * s; e += kBlkThreads, ++r) {
-    const int i = e % s, j = e / s;
-    double2 v = make_double2(0.0, 0.0);
-    for (int l = 0; l < s; ++l) {
-      const double2 a = ha ? c_conj(A[l][i]) : A[i][l];
-      const double2 b = hb ? c_conj(B[j][l]) : B[l][j];
-      v = c_add(v, c_mul(a, b));
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int e = threadIdx.x + kBlkThreads * r;
+    if (e < s * s) {
+      const int i = e % s, j = e / s;
+      double2 v = make_double2(0.0, 0.0);
+      for (int l = 0; l < s; ++l) {
+        const double2 a = ha ? c_conj(A[l][i]) : A[i][l];
+        const double2 b = hb ? c_conj(B[j][l]) : B[l][j];
+        v = c_add(v, c_mul(a, b));
+      }
+      acc[r] = mode ? c_sub(C[i][j], v) : make_double2(sgn * v.x, sgn * v.y);
     }
-    acc[r] = mode ? c_sub(C[i][j], v) : make_double2(sgn * v.x, sgn * v.y);
   }
   __syncthreads();
-  r = 0;
-  for (int e = threadIdx.x; e < s * s; e += kBlkThreads, ++r) C[e % s][e / s] = acc[r];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int e = threadIdx.x + kBlkThreads * r;
+    if (e < s * s) C[e % s][e / s] = acc[r];
+  }
   __syncthreads();
 }
 
@@ -289,11 +354,18 @@ __device__ void blk_inverse(Blk M, int s, int *perm) {
     __syncthreads();
   }
   // inverse of A = (inverse of the row-exchanged matrix) with its columns put back: column l goes to
-  // perm[l]; each thread moves one row
-  for (int i = threadIdx.x; i < s; i += kBlkThreads) {
-    double2 row[kBlockMaxPert];
-    for (int j = 0; j < s; ++j) row[j] = M[i][j];
-    for (int j = 0; j < s; ++j) M[i][perm[j]] = row[j];
+  // perm[l] (up to 4 entries per thread, read before any is written)
+  double2 v[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int e = threadIdx.x + kBlkThreads * r;
+    if (e < s * s) v[r] = M[e % s][e / s];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int e = threadIdx.x + kBlkThreads * r;
+    if (e < s * s) M[e % s][perm[e / s]] = v[r];
   }
   __syncthreads();
 }
@@ -302,7 +374,8 @@ __device__ void blk_inverse(Blk M, int s, int *perm) {
 // the residual estimate of the FOM solutions after j + 1 block steps.  ablk = A_j, bprev = B_j
 // (j > 0), bnext = B_{j+1} of every band; dinv, ff hold D_{j-1}^-1, F_{j-1} of the (band, shift) and
 // take D_j^-1, F_j.  res[band][shift] = largest over the block's columns c of
-// ||B_{j+1} D_j^-1 F_j e_c|| / ||b_c||.
+// ||B_{j+1} D_j^-1 F_j e_c|| / ||b_c||; once it is at most tol_int, conv[band][shift] = j + 1 and the
+// shift's recurrence stops (its FOM solution is taken at that step).
 __global__ __launch_bounds__(kBlkThreads) void k_blk_shift(int s, int n_omega, int j,
                                                          const double2 *__restrict__ ablk,
                                                          const double2 *__restrict__ bprev,
@@ -310,12 +383,14 @@ __global__ __launch_bounds__(kBlkThreads) void k_blk_shift(int s, int n_omega, i
                                                          const double2 *__restrict__ r0,
                                                          const double *__restrict__ bnorm,
                                                          const double2 *__restrict__ zs, double2 *__restrict__ dinv,
-                                                         double2 *__restrict__ ff, double *__restrict__ res) {
+                                                         double2 *__restrict__ ff, double *__restrict__ res,
+                                                         int32_t *__restrict__ conv, double tol_int) {
   __shared__ double2 X1[kBlockMaxPert][kBlockMaxPert + 1], X2[kBlockMaxPert][kBlockMaxPert + 1],
       X3[kBlockMaxPert][kBlockMaxPert + 1];
   __shared__ int perm[kBlockMaxPert];
   __shared__ double cres[kBlockMaxPert];
   const int b = blockIdx.x / n_omega, k = blockIdx.x - b * n_omega;
+  if (conv[(long)b * n_omega + k] >= 0) return;  // the whole block leaves together
   const long bo = (long)b * s * s, so = ((long)b * n_omega + k) * s * s;
   if (j == 0) {
     blk_load(X1, r0 + bo, s);  // F_0 = R_0
@@ -347,19 +422,23 @@ __global__ __launch_bounds__(kBlkThreads) void k_blk_shift(int s, int n_omega, i
     double m = 0.0;
     for (int c = 0; c < s; ++c) m = fmax(m, isfinite(cres[c]) ? cres[c] : 1e300);
     res[(long)b * n_omega + k] = m;
+    if (m <= tol_int) conv[(long)b * n_omega + k] = j + 1;
   }
 }
 
 // Per (band, shift): block LU solve of (T_k - z) Y = E_0 R_0 over k block steps (forward: D_i, G_i as
 // in k_blk_shift, kept in scratch; backward: Y_{k-1} = D_{k-1}^-1 G_{k-1},
-// Y_i = D_i^-1 (G_i - B_{i+1}^H Y_{i+1})).  Y goes to ycat[b] at rows i s + r, column c n_omega + shift
-// (leading dimension ldy).
+// Y_i = D_i^-1 (G_i - B_{i+1}^H Y_{i+1})), over the shift's own step count kk (conv, else k).  Y goes
+// to ycat[b] at rows i s + r, column pos[shift] s + c (leading dimension ldy); rows kk s .. k s - 1
+// are zeroed.
 __global__ __launch_bounds__(kBlkThreads) void k_blk_solve(int s, int n_omega, int k, int nbc,
                                                          const double2 *__restrict__ ablk,
                                                          const double2 *__restrict__ bblk,
                                                          const double2 *__restrict__ r0,
                                                          const double2 *__restrict__ zs, double2 *__restrict__ scratch,
-                                                         double2 *__restrict__ ycat, long ldy, long ycat_stride) {
+                                                         double2 *__restrict__ ycat, long ldy, long ycat_stride,
+                                                         const int32_t *__restrict__ conv,
+                                                         const int32_t *__restrict__ pos) {
   __shared__ double2 X1[kBlockMaxPert][kBlockMaxPert + 1], X2[kBlockMaxPert][kBlockMaxPert + 1],
       X3[kBlockMaxPert][kBlockMaxPert + 1];
   __shared__ int perm[kBlockMaxPert];
@@ -367,7 +446,15 @@ __global__ __launch_bounds__(kBlkThreads) void k_blk_solve(int s, int n_omega, i
   const long ss = (long)s * s;
   const double2 z = zs[sh];
   double2 *scr = scratch + ((long)b * n_omega + sh) * 2 * k * ss;  // step i: D_i^-1, then G_i
-  for (int i = 0; i < k; ++i) {
+  const int cv = conv[(long)b * n_omega + sh];
+  const int kk = cv >= 0 ? cv : k;
+  const long col0 = (long)pos[sh] * s;
+  double2 *yb = ycat + (long)b * ycat_stride;
+  for (int e = threadIdx.x; e < (k - kk) * s * s; e += kBlkThreads) {
+    const int r = e % ((k - kk) * s), c = e / ((k - kk) * s);
+    yb[(long)(kk * s + r) + (col0 + c) * ldy] = make_double2(0.0, 0.0);
+  }
+  for (int i = 0; i < kk; ++i) {
     if (i == 0) {
       blk_load(X1, r0 + (long)b * ss, s);
       for (int e = threadIdx.x; e < s * s; e += kBlkThreads) X3[e % s][e / s] = make_double2(0.0, 0.0);
@@ -385,10 +472,9 @@ __global__ __launch_bounds__(kBlkThreads) void k_blk_solve(int s, int n_omega, i
     blk_store(scr + (long)i * 2 * ss, X3, s);
     blk_store(scr + (long)i * 2 * ss + ss, X1, s);
   }
-  double2 *yb = ycat + (long)b * ycat_stride;
-  for (int i = k - 1; i >= 0; --i) {
+  for (int i = kk - 1; i >= 0; --i) {
     blk_load(X1, scr + (long)i * 2 * ss + ss, s);  // G_i
-    if (i < k - 1) {
+    if (i < kk - 1) {
       blk_load(X3, bblk + ((long)(i + 1) * nbc + b) * ss, s);
       blk_mm(X1, X3, true, X2, false, s, 1.0, 1);  // G_i - B_{i+1}^H Y_{i+1}
     }
@@ -396,27 +482,34 @@ __global__ __launch_bounds__(kBlkThreads) void k_blk_solve(int s, int n_omega, i
     blk_mm(X2, X3, false, X1, false, s, 1.0, 0);  // Y_i
     for (int e = threadIdx.x; e < s * s; e += kBlkThreads) {
       const int r = e % s, c = e / s;
-      yb[(long)(i * s + r) + (long)(c * n_omega + sh) * ldy] = X2[r][c];
+      yb[(long)(i * s + r) + (col0 + c) * ldy] = X2[r][c];
     }
     __syncthreads();
   }
 }
 
-// True FP64 residuals of a run of solution vectors: x[a] (internal order), y[a] = (H + alpha P) x[a],
-// vector a = (band, pert, shift) = first + a; relres = ||b - (y - eps x - z x)|| / ||b||, occupied
-// leak ||psi^H x|| / ||x|| from the overlaps cp[a][i]
+// True FP64 residuals of a run of solution vectors: x[a] (internal order), y[a] = (H + alpha P) x[a].
+// Solution first + a of the chunk is band b, shift ord[p], perturbation c for first + a =
+// (b n_omega + p) s + c; relres = ||b - (y - eps x - z x)|| / ||b||, occupied leak ||psi^H x|| / ||x||
+// from the overlaps cp[a][i]; iters = the shift's step count (conv, else k_final, then MAXITER when
+// the residual misses tol)
 __global__ __launch_bounds__(256) void k_blk_residual(int npw, int n_occ, int s, int n_omega, long first,
                                                       const double2 *__restrict__ x, const double2 *__restrict__ y,
                                                       const double2 *__restrict__ rhs, const double *__restrict__ eps,
                                                       const double2 *__restrict__ zs, const double2 *__restrict__ cp,
-                                                      double tol, int iters, int maxed, sgw_solve_info *info,
+                                                      double tol, int k_final, const int32_t *__restrict__ conv,
+                                                      const int32_t *__restrict__ ord, sgw_solve_info *info,
                                                       long info_first, int *bad) {
   __shared__ double red[3][256];
   const long a = blockIdx.x;
-  const long v = first + a;  // (b * s + c) * n_omega + k within the chunk
-  const int k = (int)(v % n_omega);
-  const long bc = v / n_omega;
-  const int b = (int)(bc / s);
+  const long xi = first + a;
+  const int c = (int)(xi % s);
+  const long bp = xi / s;
+  const int b = (int)(bp / n_omega);
+  const int k = ord[bp - (long)b * n_omega];
+  const long bc = (long)b * s + c;
+  const long v = bc * n_omega + k;  // (band, perturbation, shift) within the chunk
+  const int cv = conv[(long)b * n_omega + k];
   const double2 z = zs[k];
   const double e = eps[b];
   const double2 *xa = x + a * npw, *ya = y + a * npw, *ba = rhs + bc * npw;
@@ -443,24 +536,38 @@ __global__ __launch_bounds__(256) void k_blk_residual(int npw, int n_occ, int s,
   if (threadIdx.x == 0) {
     double occ = 0.0;
     for (int i = 0; i < n_occ; ++i) {
-      const double2 c = cp[a * n_occ + i];
-      occ += c.x * c.x + c.y * c.y;
+      const double2 q = cp[a * n_occ + i];
+      occ += q.x * q.x + q.y * q.y;
     }
     const double nb = sqrt(red[1][0]), nx = sqrt(red[2][0]);
     const double rel = nb > 0.0 ? sqrt(red[0][0]) / nb : 0.0;
     sgw_solve_info o;
-    o.iters = iters;
+    o.iters = cv >= 0 ? cv : k_final;
     o.relres = rel;
     o.occ_leak = nx > 0.0 ? sqrt(occ) / nx : 0.0;
     int fl = 0;
     if (!isfinite(rel)) fl |= SGW_FLAG_NONFINITE;
     else if (nb == 0.0) fl |= SGW_FLAG_CONVERGED | SGW_FLAG_ZERO_RHS;
     else if (rel <= tol) fl |= SGW_FLAG_CONVERGED;
-    else fl |= maxed ? SGW_FLAG_MAXITER : 0;
+    else fl |= cv < 0 ? SGW_FLAG_MAXITER : 0;
     o.flags = fl;
     info[info_first + v] = o;
     if (!(fl & SGW_FLAG_CONVERGED)) atomicOr(bad, 1);
   }
+}
+
+// dpsi of the chunk in the caller's order and layout: vector (b s + c) n_omega + shift, plane wave g
+// = -x[(b n_omega + pos[shift]) s + c][u2i[g]]
+__global__ void k_blk_out(int npw, int s, int n_omega, const double2 *__restrict__ x, const int32_t *__restrict__ pos,
+                          const int32_t *__restrict__ u2i, double2 *__restrict__ out, int tiles) {
+  const long o = blockIdx.x / tiles;
+  const int g = (int)(blockIdx.x - o * tiles) * blockDim.x + threadIdx.x;
+  if (g >= npw) return;
+  const int sh = (int)(o % n_omega);
+  const long bc = o / n_omega;
+  const int b = (int)(bc / s), c = (int)(bc - (long)b * s);
+  const double2 v = x[(((long)b * n_omega + pos[sh]) * s + c) * npw + u2i[g]];
+  out[o * npw + g] = make_double2(-v.x, -v.y);
 }
 
 // ---------------------------------------------------------------------------
@@ -488,6 +595,52 @@ sgw_status zgemm(sgw_ctx *ctx, rocblas_operation ta, rocblas_operation tb, int m
       h, ta, tb, m, n, k, &al, (const rocblas_double_complex *)A, lda, sa, (const rocblas_double_complex *)B, ldb, sb,
       &be, (rocblas_double_complex *)C, ldc, sc, nbatch);
   if (r != rocblas_status_success) return fail(SGW_ERR_HIP, "block solver: rocblas_zgemm_strided_batched failed");
+  return SGW_OK;
+}
+
+// Split the shifts, in order ord (step counts k[ord[p]] non-increasing), into at most kGroups runs
+// [cut[g], cut[g + 1]) minimising the sum over runs of (length x the run's first step count): the work
+// of the products X = V Y taken run by run.
+constexpr int kGroups = 6;
+std::vector<int> shift_runs(const std::vector<int> &ord, const std::vector<int> &k) {
+  const int n = (int)ord.size();
+  const int G = std::min(kGroups, n);
+  const double inf = 1e300;
+  // best[g][p]: least cost of the first p shifts in g runs
+  std::vector<std::vector<double>> best(G + 1, std::vector<double>(n + 1, inf));
+  std::vector<std::vector<int>> from(G + 1, std::vector<int>(n + 1, 0));
+  best[0][0] = 0.0;
+  for (int g = 1; g <= G; ++g)
+    for (int p = 1; p <= n; ++p)
+      for (int q = 0; q < p; ++q) {
+        if (best[g - 1][q] >= inf) continue;
+        const double c = best[g - 1][q] + (double)(p - q) * k[ord[q]];
+        if (c < best[g][p]) {
+          best[g][p] = c;
+          from[g][p] = q;
+        }
+      }
+  int g = 1;
+  for (int h = 1; h <= G; ++h)
+    if (best[h][n] < best[g][n]) g = h;
+  std::vector<int> cut;
+  for (int p = n; g > 0; --g) {
+    cut.push_back(p);
+    p = from[g][p];
+  }
+  cut.push_back(0);
+  std::reverse(cut.begin(), cut.end());
+  return cut;
+}
+
+// C_b = A_b^H B_b for the nb bands' n_pw x s blocks (band strides sa, sb), C contiguous s x s blocks
+sgw_status gram(sgw_ctx *ctx, int npw, int s, int nb, const double2 *A, long sa, const double2 *B, long sb,
+                double2 *part, double2 *C) {
+  const int n_chunks = (npw + kGramRows - 1) / kGramRows;
+  hipLaunchKernelGGL(k_blk_gram, dim3(n_chunks, nb), dim3(256), 0, ctx->stream, npw, s, A, sa, B, sb, part);
+  hipLaunchKernelGGL(k_blk_gram_sum, dim3(nb), dim3(256), 0, ctx->stream, n_chunks, nb, s * s,
+                     (const double2 *)part, C);
+  SGW_HIP(hipGetLastError());
   return SGW_OK;
 }
 
@@ -521,12 +674,13 @@ sgw_status block_solve(sgw_ctx *ctx, const sgw_ham *h_kq, int n_occ, const sgw_c
   if (L.total > workspace_bytes) return fail(SGW_ERR_WORKSPACE, "block solver: workspace too small for one band");
   char *Wb = (char *)workspace;
   auto P = [&](size_t off) { return (double2 *)(Wb + off); };
-  double2 *basis = P(L.basis), *rhs = P(L.rhs), *Y = P(L.y), *Wv = P(L.w), *V2 = P(L.v2), *gram = P(L.gram),
+  double2 *basis = P(L.basis), *rhs = P(L.rhs), *Y = P(L.y), *Wv = P(L.w), *V2 = P(L.v2), *gbuf = P(L.gram), *part = P(L.part),
           *rfac = P(L.rfac), *rinv = P(L.rinv), *ablk = P(L.ablk), *bblk = P(L.bblk), *r0 = P(L.r0),
           *dinv = P(L.dinv), *ff = P(L.ff), *thomas = P(L.thomas), *ycat = P(L.ycat), *xout = P(L.xout),
           *C = P(L.c), *psi = P(L.psi), *zs = P(L.omega);
   double *bnorm = (double *)(Wb + L.bnorm), *res = (double *)(Wb + L.res), *deps = (double *)(Wb + L.eps);
-  int32_t *list = (int32_t *)(Wb + L.list);
+  int32_t *list = (int32_t *)(Wb + L.list), *conv = (int32_t *)(Wb + L.conv), *dpos = (int32_t *)(Wb + L.ord),
+          *dord = dpos + n_omega;
   int *bad = (int *)(Wb + L.bad);
   void *T = Wb + L.t;
   const long ss = (long)s * s;
@@ -548,6 +702,7 @@ sgw_status block_solve(sgw_ctx *ctx, const sgw_ham *h_kq, int n_occ, const sgw_c
     const int nb = std::min(nbc, n_band - b0);
     const int nv = nb * s;
     SGW_HIP(hipMemsetAsync(bad, 0, 8, ctx->stream));
+    SGW_HIP(hipMemsetAsync(conv, 0xff, sizeof(int32_t) * nb * n_omega, ctx->stream));  // -1: running
     SGW_HIP(hipMemcpyAsync(deps, eps_v + b0, sizeof(double) * nb, hipMemcpyHostToDevice, ctx->stream));
     // right-hand sides in internal order: rhs = (1 - P) s (the solution is negated on the way out)
     for (int a = 0; a < nv; ++a) hpairs[a] = (b0 + a / s) * s + a % s;
@@ -557,12 +712,10 @@ sgw_status block_solve(sgw_ctx *ctx, const sgw_ham *h_kq, int n_occ, const sgw_c
     if ((st = proj_dot(ctx, npw, n_occ, psi, nv, contiguous(Y, npw), C, nv)) != SGW_OK) return st;
     if ((st = proj_apply(ctx, npw, n_occ, psi, nv, contiguous(Y, npw), C, nv, rhs, npw, 1.0, 0)) != SGW_OK) return st;
     // column norms of every band's block (for the residual estimates): diagonal of rhs^H rhs
-    if ((st = zgemm(ctx, rocblas_operation_conjugate_transpose, rocblas_operation_none, s, s, npw, one, rhs, npw,
-                    (long)s * npw, rhs, npw, (long)s * npw, zero, gram, s, ss, nb)) != SGW_OK)
-      return st;
+    if ((st = gram(ctx, npw, s, nb, rhs, (long)s * npw, rhs, (long)s * npw, part, gbuf)) != SGW_OK) return st;
     {
       std::vector<double2> hg((size_t)nb * ss);
-      SGW_HIP(hipMemcpyAsync(hg.data(), gram, sizeof(double2) * nb * ss, hipMemcpyDeviceToHost, ctx->stream));
+      SGW_HIP(hipMemcpyAsync(hg.data(), gbuf, sizeof(double2) * nb * ss, hipMemcpyDeviceToHost, ctx->stream));
       if ((st = sync(ctx)) != SGW_OK) return st;
       std::vector<double> hn(nv);
       for (int b = 0; b < nb; ++b)
@@ -572,18 +725,14 @@ sgw_status block_solve(sgw_ctx *ctx, const sgw_ham *h_kq, int n_occ, const sgw_c
     // V_0 R_0 = rhs (Cholesky QR twice)
     auto orth = [&](const double2 *src, double2 *dst, double2 *rout) -> sgw_status {
       sgw_status s2;
-      if ((s2 = zgemm(ctx, rocblas_operation_conjugate_transpose, rocblas_operation_none, s, s, npw, one, src, npw,
-                      (long)s * npw, src, npw, (long)s * npw, zero, gram, s, ss, nb)) != SGW_OK)
-        return s2;
-      hipLaunchKernelGGL(k_blk_chol, dim3(nb), dim3(64), 0, ctx->stream, gram, (const double2 *)nullptr, rfac, rinv,
+      if ((s2 = gram(ctx, npw, s, nb, src, (long)s * npw, src, (long)s * npw, part, gbuf)) != SGW_OK) return s2;
+      hipLaunchKernelGGL(k_blk_chol, dim3(nb), dim3(64), 0, ctx->stream, gbuf, (const double2 *)nullptr, rfac, rinv,
                          s, bad);
       if ((s2 = zgemm(ctx, rocblas_operation_none, rocblas_operation_none, npw, s, s, one, src, npw, (long)s * npw,
                       rinv, s, ss, zero, V2, npw, (long)s * npw, nb)) != SGW_OK)
         return s2;
-      if ((s2 = zgemm(ctx, rocblas_operation_conjugate_transpose, rocblas_operation_none, s, s, npw, one, V2, npw,
-                      (long)s * npw, V2, npw, (long)s * npw, zero, gram, s, ss, nb)) != SGW_OK)
-        return s2;
-      hipLaunchKernelGGL(k_blk_chol, dim3(nb), dim3(64), 0, ctx->stream, gram, (const double2 *)rfac, rout, rinv, s,
+      if ((s2 = gram(ctx, npw, s, nb, V2, (long)s * npw, V2, (long)s * npw, part, gbuf)) != SGW_OK) return s2;
+      hipLaunchKernelGGL(k_blk_chol, dim3(nb), dim3(64), 0, ctx->stream, gbuf, (const double2 *)rfac, rout, rinv, s,
                          bad);
       // dst (strided per band in the basis) = V2 R2^-1
       return zgemm(ctx, rocblas_operation_none, rocblas_operation_none, npw, s, s, one, V2, npw, (long)s * npw, rinv,
@@ -592,7 +741,6 @@ sgw_status block_solve(sgw_ctx *ctx, const sgw_ham *h_kq, int n_occ, const sgw_c
     if ((st = orth(rhs, basis, r0)) != SGW_OK) return st;
     // block Lanczos steps with the residual estimates of every (band, shift)
     int k = 0;
-    bool converged = false;
     std::vector<double> hres((size_t)nb * n_omega);
     // host polls: every step once a step is large enough to hide the round trip
     const int poll = (long)nv * npw >= (1L << 22) ? 1 : std::max(1, o.steps_per_sync);
@@ -612,9 +760,7 @@ sgw_status block_solve(sgw_ctx *ctx, const sgw_ham *h_kq, int n_occ, const sgw_c
           return st;
       }
       double2 *aj = ablk + (long)j * nbc * ss;
-      if ((st = zgemm(ctx, rocblas_operation_conjugate_transpose, rocblas_operation_none, s, s, npw, one, vj_ptr, npw,
-                      (long)kb * s * npw, Wv, npw, (long)s * npw, zero, aj, s, ss, nb)) != SGW_OK)
-        return st;
+      if ((st = gram(ctx, npw, s, nb, vj_ptr, (long)kb * s * npw, Wv, (long)s * npw, part, aj)) != SGW_OK) return st;
       hipLaunchKernelGGL(k_blk_hermitize, dim3(nb), dim3(256), 0, ctx->stream, aj, s);
       if ((st = zgemm(ctx, rocblas_operation_none, rocblas_operation_none, npw, s, s, mone, vj_ptr, npw,
                       (long)kb * s * npw, aj, s, ss, one, Wv, npw, (long)s * npw, nb)) != SGW_OK)
@@ -623,7 +769,7 @@ sgw_status block_solve(sgw_ctx *ctx, const sgw_ham *h_kq, int n_occ, const sgw_c
       hipLaunchKernelGGL(k_blk_shift, dim3(nb * n_omega), dim3(kBlkThreads), 0, ctx->stream, s, n_omega, j,
                          (const double2 *)aj, (const double2 *)(bblk + (long)j * nbc * ss),
                          (const double2 *)(bblk + (long)(j + 1) * nbc * ss), (const double2 *)r0,
-                         (const double *)bnorm, (const double2 *)zs, dinv, ff, res);
+                         (const double *)bnorm, (const double2 *)zs, dinv, ff, res, conv, tol_int);
       SGW_HIP(hipGetLastError());
       k = j + 1;
       if (k % poll == 0 || k + 1 >= kb) {
@@ -631,25 +777,47 @@ sgw_status block_solve(sgw_ctx *ctx, const sgw_ham *h_kq, int n_occ, const sgw_c
         if ((st = sync(ctx)) != SGW_OK) return st;
         double worst = 0.0;
         for (double r : hres) worst = std::max(worst, std::isfinite(r) ? r : 1e300);
-        if (worst <= tol_int) {
-          converged = true;
-          break;
-        }
+        if (worst <= tol_int) break;
       }
     }
     int hbad = 0;
     SGW_HIP(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
     if ((st = sync(ctx)) != SGW_OK) return st;
     if (hbad) return fail(SGW_ERR_UNSUPPORTED, "block solver: a block lost rank (dependent right-hand sides)");
-    // solutions: Y(z) per shift, X = V Y per band, to the caller's order with the sign of b
+    // Solutions: Y(z) per (band, shift) at the shift's own step count, X = V Y per band.  The shifts
+    // are ordered by their largest step count over the chunk's bands and split into up to kGroups runs
+    // (least total inner dimension), one batched product per run with that run's inner dimension.
+    std::vector<int32_t> hconv((size_t)nb * n_omega);
+    SGW_HIP(hipMemcpyAsync(hconv.data(), conv, sizeof(int32_t) * nb * n_omega, hipMemcpyDeviceToHost, ctx->stream));
+    if ((st = sync(ctx)) != SGW_OK) return st;
+    std::vector<int> ksh(n_omega, 0), ord(n_omega), pos(n_omega);
+    for (int b = 0; b < nb; ++b)
+      for (int j = 0; j < n_omega; ++j) {
+        const int c = hconv[(size_t)b * n_omega + j];
+        ksh[j] = std::max(ksh[j], c >= 0 ? c : k);
+      }
+    for (int j = 0; j < n_omega; ++j) ord[j] = j;
+    std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return ksh[x] > ksh[y]; });
+    for (int p = 0; p < n_omega; ++p) pos[ord[p]] = p;
+    const std::vector<int> cut = shift_runs(ord, ksh);
+    std::vector<int32_t> hmap(2 * (size_t)n_omega);
+    for (int j = 0; j < n_omega; ++j) {
+      hmap[j] = pos[j];
+      hmap[n_omega + j] = ord[j];
+    }
+    SGW_HIP(hipMemcpyAsync(dpos, hmap.data(), sizeof(int32_t) * 2 * n_omega, hipMemcpyHostToDevice, ctx->stream));
     hipLaunchKernelGGL(k_blk_solve, dim3(nb * n_omega), dim3(kBlkThreads), 0, ctx->stream, s, n_omega, k, nbc,
                        (const double2 *)ablk, (const double2 *)bblk, (const double2 *)r0, (const double2 *)zs, thomas,
-                       ycat, (long)kb * s, (long)kb * s * s * n_omega);
+                       ycat, (long)kb * s, (long)kb * s * s * n_omega, (const int32_t *)conv, (const int32_t *)dpos);
     SGW_HIP(hipGetLastError());
-    if ((st = zgemm(ctx, rocblas_operation_none, rocblas_operation_none, npw, s * n_omega, k * s, one, basis, npw,
-                    (long)kb * s * npw, ycat, (long)kb * s, (long)kb * s * s * n_omega, zero, xout, npw,
-                    (long)s * n_omega * npw, nb)) != SGW_OK)
-      return st;
+    for (size_t g = 0; g + 1 < cut.size(); ++g) {
+      const int p0 = cut[g], p1 = cut[g + 1], kg = ksh[ord[p0]];
+      if ((st = zgemm(ctx, rocblas_operation_none, rocblas_operation_none, npw, (p1 - p0) * s, kg * s, one, basis,
+                      npw, (long)kb * s * npw, ycat + (long)p0 * s * kb * s, (long)kb * s,
+                      (long)kb * s * s * n_omega, zero, xout + (long)p0 * s * npw, npw, (long)s * n_omega * npw,
+                      nb)) != SGW_OK)
+        return st;
+    }
     const long nsol = (long)nv * n_omega;
     // true residuals in runs of nsub solutions
     for (long f = 0; f < nsol; f += L.nsub) {
@@ -661,12 +829,16 @@ sgw_status block_solve(sgw_ctx *ctx, const sgw_ham *h_kq, int n_occ, const sgw_c
       hipLaunchKernelGGL(k_blk_residual, dim3(m), dim3(256), 0, ctx->stream, npw, n_occ, s, n_omega, f,
                          (const double2 *)(xout + f * npw), (const double2 *)Y, (const double2 *)rhs,
                          (const double *)deps, (const double2 *)zs, (const double2 *)C, tol, k,
-                         converged ? 0 : 1, info, (long)b0 * s * n_omega, bad);
+                         (const int32_t *)conv, (const int32_t *)dord, info, (long)b0 * s * n_omega, bad);
       SGW_HIP(hipGetLastError());
     }
-    if ((st = permute(ctx, npw, (int)nsol, xout, npw, (double2 *)dpsi + (long)b0 * s * n_omega * npw, npw,
-                      h_kq->d_i2u, 1, -1.0)) != SGW_OK)
-      return st;
+    {
+      const int tiles = (npw + 255) / 256;
+      hipLaunchKernelGGL(k_blk_out, dim3(nsol * tiles), dim3(256), 0, ctx->stream, npw, s, n_omega,
+                         (const double2 *)xout, (const int32_t *)dpos, (const int32_t *)h_kq->d_u2i,
+                         (double2 *)dpsi + (long)b0 * s * n_omega * npw, tiles);
+      SGW_HIP(hipGetLastError());
+    }
     SGW_HIP(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
     if ((st = sync(ctx)) != SGW_OK) return st;
     any_bad = any_bad || hbad;
