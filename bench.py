@@ -623,7 +623,7 @@ def main():
     ap.add_argument("--mixed-switch", type=float, default=0.0)
     ap.add_argument("--solver", choices=["multishift", "block"], default="multishift",
                     help="block: one block Krylov space per band over its perturbations (FP64; max_iter then "
-                         "limits the block steps, 0: 240 for si64)")
+                         "limits the block steps, 0: 160 for si64)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch-workers", type=int, default=4)
     ap.add_argument("--batch-max-iter", type=int, default=4000)
@@ -696,7 +696,7 @@ def main():
             log("the block solver runs in FP64 only")
             sys.exit(2)
         kw["solver"] = sgw.SOLVER_BLOCK
-    max_iter = args.max_iter or ((240 if block else 3500) if args.workload in ("si64", "si64nl") else 0)
+    max_iter = args.max_iter or ((160 if block else 3500) if args.workload in ("si64", "si64nl") else 0)
     if max_iter:
         kw["max_iter"] = max_iter
     if args.mixed_switch:

@@ -32,13 +32,14 @@ namespace {
 constexpr size_t kBA = 256;
 constexpr int kGramRows = 256;  // plane waves per partial sum of the skinny products
 constexpr int kGramTile = 32;   // rows staged in LDS at a time
+constexpr int kRunShifts = 32;  // shifts whose solutions are formed together at the end
 size_t up(size_t b) { return (b + kBA - 1) / kBA * kBA; }
 
 // Workspace of one chunk of nbc bands; kb = block steps + 1 stored blocks
 struct BlkLayout {
-  int nbc = 0, kb = 0, s = 0, nsub = 0;
-  size_t basis, rhs, y, w, v2, gram, part, rfac, rinv, ablk, bblk, r0, bnorm, dinv, ff, res, thomas, ycat, xout, list,
-      c, t, psi, omega, eps, conv, ord, dvm, bad, total;
+  int nbc = 0, kb = 0, s = 0, run = 0;
+  size_t basis, abasis, pov, rhs, y, w, v2, gram, part, rfac, rinv, ablk, bblk, r0, bnorm, dinv, ff, res, thomas,
+      ycat, xg, axg, qg, list, c, t, psi, omega, eps, conv, ord, dvm, bad, total;
 };
 
 BlkLayout blk_layout(const sgw_ham *h, int n_occ, int nbc, int s, int n_omega, int kb) {
@@ -47,7 +48,8 @@ BlkLayout blk_layout(const sgw_ham *h, int n_occ, int nbc, int s, int n_omega, i
   L.kb = kb;
   L.s = s;
   const size_t npw = h->n_pw, nv = (size_t)nbc * s, ss = (size_t)s * s;
-  L.nsub = (int)std::max<size_t>(nv, 1024);  // vectors per H.x launch in the residual pass
+  L.run = std::min(n_omega, kRunShifts);
+  const size_t no = std::max(n_occ, 1);
   size_t off = 0;
   auto take = [&](size_t bytes) {
     const size_t o = off;
@@ -55,8 +57,10 @@ BlkLayout blk_layout(const sgw_ham *h, int n_occ, int nbc, int s, int n_omega, i
     return o;
   };
   L.basis = take(16 * (size_t)kb * nv * npw);
+  L.abasis = take(16 * (size_t)kb * nv * npw);
+  L.pov = take(16 * (size_t)kb * nv * no);
   L.rhs = take(16 * nv * npw);
-  L.y = take(16 * std::max<size_t>(nv, L.nsub) * npw);
+  L.y = take(16 * nv * npw);
   L.w = take(16 * nv * npw);
   L.v2 = take(16 * nv * npw);
   L.gram = take(16 * nbc * ss);
@@ -72,10 +76,12 @@ BlkLayout blk_layout(const sgw_ham *h, int n_occ, int nbc, int s, int n_omega, i
   L.res = take(8 * (size_t)nbc * n_omega);
   L.thomas = take(16 * 2 * (size_t)kb * nbc * n_omega * ss);
   L.ycat = take(16 * (size_t)kb * s * nv * n_omega);
-  L.xout = take(16 * nv * n_omega * npw);
-  L.list = take(4 * std::max<size_t>(nv, L.nsub));
-  L.c = take(16 * kProjChunks * std::max<size_t>(nv, L.nsub) * std::max(n_occ, 1));
-  L.t = take(hx_tbuf_bytes(h, std::max<size_t>(nv, L.nsub)));
+  L.xg = take(16 * nv * L.run * npw);
+  L.axg = take(16 * nv * L.run * npw);
+  L.qg = take(16 * nv * L.run * no);
+  L.list = take(4 * nv);
+  L.c = take(16 * kProjChunks * nv * no);
+  L.t = take(hx_tbuf_bytes(h, nv));
   L.psi = take(16 * (size_t)std::max(n_occ, 1) * npw);
   L.omega = take(16 * (size_t)n_omega);
   L.eps = take(8 * (size_t)nbc);
@@ -115,15 +121,18 @@ __global__ void k_blk_list(int32_t *list, int nbc, int s, int kb, int j) {
 }
 
 // w[a] = y[a] - eps[band] v[a] (v through the list)
+// w[a] = y[a] - eps[band] v[a], and y[a] = (H + alpha P) v[a] kept beside v[a] (abasis, same list)
 __global__ void k_blk_shift_eps(int npw, int s, const double2 *__restrict__ y, const double2 *__restrict__ basis,
                                 const int32_t *__restrict__ list, const double *__restrict__ eps,
-                                double2 *__restrict__ w) {
+                                double2 *__restrict__ w, double2 *__restrict__ abasis) {
   const int a = blockIdx.x;
   const int g = blockIdx.y * blockDim.x + threadIdx.x;
   if (g >= npw) return;
   const double e = eps[a / s];
-  const double2 v = basis[(long)list[a] * npw + g], t = y[(long)a * npw + g];
+  const long slot = (long)list[a] * npw + g;
+  const double2 v = basis[slot], t = y[(long)a * npw + g];
   w[(long)a * npw + g] = make_double2(t.x - e * v.x, t.y - e * v.y);
+  abasis[slot] = t;
 }
 
 // M = (M + M^H) / 2 for the nbc s x s blocks (column-major)
@@ -488,41 +497,45 @@ __global__ __launch_bounds__(kBlkThreads) void k_blk_solve(int s, int n_omega, i
   }
 }
 
-// True FP64 residuals of a run of solution vectors: x[a] (internal order), y[a] = (H + alpha P) x[a].
-// Solution first + a of the chunk is band b, shift ord[p], perturbation c for first + a =
-// (b n_omega + p) s + c; relres = ||b - (y - eps x - z x)|| / ||b||, occupied leak ||psi^H x|| / ||x||
-// from the overlaps cp[a][i]; iters = the shift's step count (conv, else k_final, then MAXITER when
-// the residual misses tol)
-__global__ __launch_bounds__(256) void k_blk_residual(int npw, int n_occ, int s, int n_omega, long first,
-                                                      const double2 *__restrict__ x, const double2 *__restrict__ y,
-                                                      const double2 *__restrict__ rhs, const double *__restrict__ eps,
-                                                      const double2 *__restrict__ zs, const double2 *__restrict__ cp,
-                                                      double tol, int k_final, const int32_t *__restrict__ conv,
-                                                      const int32_t *__restrict__ ord, sgw_solve_info *info,
-                                                      long info_first, int *bad) {
+// Per solution of a run of shifts (positions p0 .. p0 + len - 1 of the order ord): its true FP64
+// residual from X = V Y and (H + alpha P) X = (AV) Y, both formed from the stored products, and the
+// solution in the caller's order and sign.  Block a: band b, position p0 + l, perturbation c for
+// a = (b len + l) s + c; x, ax at vector (b run + l) s + c of xg, axg (q: the overlaps psi^H x).
+// relres = ||b - (ax - eps x - z x)|| / ||b||, occ_leak = ||q|| / ||x||, iters = the shift's step count
+// (conv, else k_final, then MAXITER when the residual misses tol); dpsi[g] = -x[u2i[g]].
+__global__ __launch_bounds__(256) void k_blk_final(int npw, int n_occ, int s, int n_omega, int len, int p0, int run,
+                                                   const double2 *__restrict__ xg, const double2 *__restrict__ axg,
+                                                   const double2 *__restrict__ qg, const double2 *__restrict__ rhs,
+                                                   const double *__restrict__ eps, const double2 *__restrict__ zs,
+                                                   const int32_t *__restrict__ ord, const int32_t *__restrict__ conv,
+                                                   int k_final, double tol, const int32_t *__restrict__ u2i,
+                                                   double2 *__restrict__ dpsi, sgw_solve_info *info, int *bad) {
   __shared__ double red[3][256];
   const long a = blockIdx.x;
-  const long xi = first + a;
-  const int c = (int)(xi % s);
-  const long bp = xi / s;
-  const int b = (int)(bp / n_omega);
-  const int k = ord[bp - (long)b * n_omega];
-  const long bc = (long)b * s + c;
-  const long v = bc * n_omega + k;  // (band, perturbation, shift) within the chunk
-  const int cv = conv[(long)b * n_omega + k];
-  const double2 z = zs[k];
+  const int c = (int)(a % s);
+  const long bl = a / s;
+  const int b = (int)(bl / len), l = (int)(bl - (long)b * len);
+  const int sh = ord[p0 + l];
+  const long xv = ((long)b * run + l) * s + c;
+  const double2 *xa = xg + xv * npw, *ya = axg + xv * npw, *ba = rhs + ((long)b * s + c) * npw;
+  const double2 z = zs[sh];
   const double e = eps[b];
-  const double2 *xa = x + a * npw, *ya = y + a * npw, *ba = rhs + bc * npw;
   double rr = 0.0, bb = 0.0, xx = 0.0;
   for (int g = threadIdx.x; g < npw; g += 256) {
-    const double2 xv = xa[g], yv = ya[g], bv = ba[g];
+    const double2 x = xa[g], y = ya[g], bv = ba[g];
     // (A - z) x = y - eps x - z x
-    const double ax = yv.x - e * xv.x - (z.x * xv.x - z.y * xv.y);
-    const double ay = yv.y - e * xv.y - (z.x * xv.y + z.y * xv.x);
+    const double ax = y.x - e * x.x - (z.x * x.x - z.y * x.y);
+    const double ay = y.y - e * x.y - (z.x * x.y + z.y * x.x);
     const double rx = bv.x - ax, ry = bv.y - ay;
     rr += rx * rx + ry * ry;
     bb += bv.x * bv.x + bv.y * bv.y;
-    xx += xv.x * xv.x + xv.y * xv.y;
+    xx += x.x * x.x + x.y * x.y;
+  }
+  const long o = ((long)b * s + c) * n_omega + sh;
+  double2 *out = dpsi + o * npw;
+  for (int g = threadIdx.x; g < npw; g += 256) {
+    const double2 x = xa[u2i[g]];
+    out[g] = make_double2(-x.x, -x.y);
   }
   red[0][threadIdx.x] = rr;
   red[1][threadIdx.x] = bb;
@@ -536,38 +549,25 @@ __global__ __launch_bounds__(256) void k_blk_residual(int npw, int n_occ, int s,
   if (threadIdx.x == 0) {
     double occ = 0.0;
     for (int i = 0; i < n_occ; ++i) {
-      const double2 q = cp[a * n_occ + i];
+      const double2 q = qg[xv * n_occ + i];
       occ += q.x * q.x + q.y * q.y;
     }
+    const int cv = conv[(long)b * n_omega + sh];
     const double nb = sqrt(red[1][0]), nx = sqrt(red[2][0]);
     const double rel = nb > 0.0 ? sqrt(red[0][0]) / nb : 0.0;
-    sgw_solve_info o;
-    o.iters = cv >= 0 ? cv : k_final;
-    o.relres = rel;
-    o.occ_leak = nx > 0.0 ? sqrt(occ) / nx : 0.0;
+    sgw_solve_info r;
+    r.iters = cv >= 0 ? cv : k_final;
+    r.relres = rel;
+    r.occ_leak = nx > 0.0 ? sqrt(occ) / nx : 0.0;
     int fl = 0;
     if (!isfinite(rel)) fl |= SGW_FLAG_NONFINITE;
     else if (nb == 0.0) fl |= SGW_FLAG_CONVERGED | SGW_FLAG_ZERO_RHS;
     else if (rel <= tol) fl |= SGW_FLAG_CONVERGED;
     else fl |= cv < 0 ? SGW_FLAG_MAXITER : 0;
-    o.flags = fl;
-    info[info_first + v] = o;
+    r.flags = fl;
+    info[o] = r;
     if (!(fl & SGW_FLAG_CONVERGED)) atomicOr(bad, 1);
   }
-}
-
-// dpsi of the chunk in the caller's order and layout: vector (b s + c) n_omega + shift, plane wave g
-// = -x[(b n_omega + pos[shift]) s + c][u2i[g]]
-__global__ void k_blk_out(int npw, int s, int n_omega, const double2 *__restrict__ x, const int32_t *__restrict__ pos,
-                          const int32_t *__restrict__ u2i, double2 *__restrict__ out, int tiles) {
-  const long o = blockIdx.x / tiles;
-  const int g = (int)(blockIdx.x - o * tiles) * blockDim.x + threadIdx.x;
-  if (g >= npw) return;
-  const int sh = (int)(o % n_omega);
-  const long bc = o / n_omega;
-  const int b = (int)(bc / s), c = (int)(bc - (long)b * s);
-  const double2 v = x[(((long)b * n_omega + pos[sh]) * s + c) * npw + u2i[g]];
-  out[o * npw + g] = make_double2(-v.x, -v.y);
 }
 
 // ---------------------------------------------------------------------------
@@ -676,8 +676,9 @@ sgw_status block_solve(sgw_ctx *ctx, const sgw_ham *h_kq, int n_occ, const sgw_c
   auto P = [&](size_t off) { return (double2 *)(Wb + off); };
   double2 *basis = P(L.basis), *rhs = P(L.rhs), *Y = P(L.y), *Wv = P(L.w), *V2 = P(L.v2), *gbuf = P(L.gram), *part = P(L.part),
           *rfac = P(L.rfac), *rinv = P(L.rinv), *ablk = P(L.ablk), *bblk = P(L.bblk), *r0 = P(L.r0),
-          *dinv = P(L.dinv), *ff = P(L.ff), *thomas = P(L.thomas), *ycat = P(L.ycat), *xout = P(L.xout),
-          *C = P(L.c), *psi = P(L.psi), *zs = P(L.omega);
+          *dinv = P(L.dinv), *ff = P(L.ff), *thomas = P(L.thomas), *ycat = P(L.ycat), *xg = P(L.xg),
+          *axg = P(L.axg), *qg = P(L.qg), *abasis = P(L.abasis), *pov = P(L.pov), *C = P(L.c), *psi = P(L.psi),
+          *zs = P(L.omega);
   double *bnorm = (double *)(Wb + L.bnorm), *res = (double *)(Wb + L.res), *deps = (double *)(Wb + L.eps);
   int32_t *list = (int32_t *)(Wb + L.list), *conv = (int32_t *)(Wb + L.conv), *dpos = (int32_t *)(Wb + L.ord),
           *dord = dpos + n_omega;
@@ -694,7 +695,7 @@ sgw_status block_solve(sgw_ctx *ctx, const sgw_ham *h_kq, int n_occ, const sgw_c
   if ((st = permute(ctx, npw, n_occ, (const double2 *)psi_occ_kq, npw, psi, npw, h_kq->d_i2u, 0)) != SGW_OK) return st;
   int32_t *ddvm = (int32_t *)(Wb + L.dvm);
   SGW_HIP(hipMemcpyAsync(ddvm, dv_miller, sizeof(int32_t) * 3 * s, hipMemcpyHostToDevice, ctx->stream));
-  std::vector<int32_t> hpairs(std::max<size_t>((size_t)nbc * s, (size_t)L.nsub));
+  std::vector<int32_t> hpairs((size_t)nbc * s);
   bool any_bad = false;
   const double tol_int = tol * o.tol_safety;
 
@@ -748,10 +749,15 @@ sgw_status block_solve(sgw_ctx *ctx, const sgw_ham *h_kq, int n_occ, const sgw_c
       hipLaunchKernelGGL(k_blk_list, dim3((nv + 255) / 256), dim3(256), 0, ctx->stream, list, nb, s, kb, j);
       const VecSrc vj = listed(basis, npw, list);
       if ((st = proj_dot(ctx, npw, n_occ, psi, nv, vj, C, nv)) != SGW_OK) return st;
+      if (n_occ > 0)  // psi^H V_j kept per band: [b][kb][s][n_occ]
+        SGW_HIP(hipMemcpy2DAsync(pov + (long)j * s * n_occ, sizeof(double2) * kb * s * n_occ, C,
+                                 sizeof(double2) * s * n_occ, sizeof(double2) * s * n_occ, nb,
+                                 hipMemcpyDeviceToDevice, ctx->stream));
       if ((st = hx_batch(ctx, h_kq, nv, vj, Y, npw, T)) != SGW_OK) return st;
       if ((st = proj_apply(ctx, npw, n_occ, psi, nv, vj, C, nv, Y, npw, o.alpha_pv, 1)) != SGW_OK) return st;
       hipLaunchKernelGGL(k_blk_shift_eps, dim3(nv, (npw + 255) / 256), dim3(256), 0, ctx->stream, npw, s,
-                         (const double2 *)Y, (const double2 *)basis, (const int32_t *)list, (const double *)deps, Wv);
+                         (const double2 *)Y, (const double2 *)basis, (const int32_t *)list, (const double *)deps, Wv,
+                         abasis);
       double2 *vj_ptr = basis + (long)j * s * npw;  // band 0; bands strided by kb s npw
       if (j > 0) {  // W -= V_{j-1} B_j^H
         if ((st = zgemm(ctx, rocblas_operation_none, rocblas_operation_conjugate_transpose, npw, s, s, mone,
@@ -810,34 +816,31 @@ sgw_status block_solve(sgw_ctx *ctx, const sgw_ham *h_kq, int n_occ, const sgw_c
                        (const double2 *)ablk, (const double2 *)bblk, (const double2 *)r0, (const double2 *)zs, thomas,
                        ycat, (long)kb * s, (long)kb * s * s * n_omega, (const int32_t *)conv, (const int32_t *)dpos);
     SGW_HIP(hipGetLastError());
+    // per run of at most L.run shifts: X = V Y, (H + alpha P) X = (AV) Y and psi^H X = (psi^H V) Y, then
+    // the true residuals and the output
+    const long ldy = (long)kb * s, ystride = (long)kb * s * s * n_omega;
     for (size_t g = 0; g + 1 < cut.size(); ++g) {
-      const int p0 = cut[g], p1 = cut[g + 1], kg = ksh[ord[p0]];
-      if ((st = zgemm(ctx, rocblas_operation_none, rocblas_operation_none, npw, (p1 - p0) * s, kg * s, one, basis,
-                      npw, (long)kb * s * npw, ycat + (long)p0 * s * kb * s, (long)kb * s,
-                      (long)kb * s * s * n_omega, zero, xout + (long)p0 * s * npw, npw, (long)s * n_omega * npw,
-                      nb)) != SGW_OK)
-        return st;
-    }
-    const long nsol = (long)nv * n_omega;
-    // true residuals in runs of nsub solutions
-    for (long f = 0; f < nsol; f += L.nsub) {
-      const int m = (int)std::min<long>(L.nsub, nsol - f);
-      const VecSrc xs = contiguous(xout + f * npw, npw);
-      if ((st = proj_dot(ctx, npw, n_occ, psi, m, xs, C, m)) != SGW_OK) return st;
-      if ((st = hx_batch(ctx, h_kq, m, xs, Y, npw, T)) != SGW_OK) return st;
-      if ((st = proj_apply(ctx, npw, n_occ, psi, m, xs, C, m, Y, npw, o.alpha_pv, 1)) != SGW_OK) return st;
-      hipLaunchKernelGGL(k_blk_residual, dim3(m), dim3(256), 0, ctx->stream, npw, n_occ, s, n_omega, f,
-                         (const double2 *)(xout + f * npw), (const double2 *)Y, (const double2 *)rhs,
-                         (const double *)deps, (const double2 *)zs, (const double2 *)C, tol, k,
-                         (const int32_t *)conv, (const int32_t *)dord, info, (long)b0 * s * n_omega, bad);
-      SGW_HIP(hipGetLastError());
-    }
-    {
-      const int tiles = (npw + 255) / 256;
-      hipLaunchKernelGGL(k_blk_out, dim3(nsol * tiles), dim3(256), 0, ctx->stream, npw, s, n_omega,
-                         (const double2 *)xout, (const int32_t *)dpos, (const int32_t *)h_kq->d_u2i,
-                         (double2 *)dpsi + (long)b0 * s * n_omega * npw, tiles);
-      SGW_HIP(hipGetLastError());
+      for (int p0 = cut[g]; p0 < cut[g + 1]; p0 += L.run) {
+        const int len = std::min(L.run, cut[g + 1] - p0), kg = ksh[ord[p0]];
+        const double2 *yc = ycat + (long)p0 * s * ldy;
+        if ((st = zgemm(ctx, rocblas_operation_none, rocblas_operation_none, npw, len * s, kg * s, one, basis, npw,
+                        (long)kb * s * npw, yc, ldy, ystride, zero, xg, npw, (long)s * L.run * npw, nb)) != SGW_OK)
+          return st;
+        if ((st = zgemm(ctx, rocblas_operation_none, rocblas_operation_none, npw, len * s, kg * s, one, abasis, npw,
+                        (long)kb * s * npw, yc, ldy, ystride, zero, axg, npw, (long)s * L.run * npw, nb)) != SGW_OK)
+          return st;
+        if (n_occ > 0 &&
+            (st = zgemm(ctx, rocblas_operation_none, rocblas_operation_none, n_occ, len * s, kg * s, one, pov, n_occ,
+                        (long)kb * s * n_occ, yc, ldy, ystride, zero, qg, n_occ, (long)s * L.run * n_occ, nb)) !=
+                SGW_OK)
+          return st;
+        hipLaunchKernelGGL(k_blk_final, dim3(nb * len * s), dim3(256), 0, ctx->stream, npw, n_occ, s, n_omega, len,
+                           p0, L.run, (const double2 *)xg, (const double2 *)axg, (const double2 *)qg,
+                           (const double2 *)rhs, (const double *)deps, (const double2 *)zs, (const int32_t *)dord,
+                           (const int32_t *)conv, k, tol, (const int32_t *)h_kq->d_u2i,
+                           (double2 *)dpsi + (long)b0 * s * n_omega * npw, info + (long)b0 * s * n_omega, bad);
+        SGW_HIP(hipGetLastError());
+      }
     }
     SGW_HIP(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
     if ((st = sync(ctx)) != SGW_OK) return st;
