@@ -33,6 +33,7 @@ constexpr size_t kBA = 256;
 constexpr int kGramRows = 256;  // plane waves per partial sum of the skinny products
 constexpr int kGramTile = 32;   // rows staged in LDS at a time
 constexpr int kRunShifts = 32;  // shifts whose solutions are formed together at the end
+constexpr int kSubBands = 8;    // bands whose solutions share one shift order and step counts
 size_t up(size_t b) { return (b + kBA - 1) / kBA * kBA; }
 
 // Workspace of one chunk of nbc bands; kb = block steps + 1 stored blocks
@@ -86,7 +87,7 @@ BlkLayout blk_layout(const sgw_ham *h, int n_occ, int nbc, int s, int n_omega, i
   L.omega = take(16 * (size_t)n_omega);
   L.eps = take(8 * (size_t)nbc);
   L.conv = take(4 * (size_t)nbc * n_omega);
-  L.ord = take(8 * (size_t)n_omega);
+  L.ord = take(8 * (size_t)nbc * n_omega);
   L.dvm = take(4 * 3 * (size_t)s);
   L.bad = take(8);
   L.total = off;
@@ -438,7 +439,7 @@ __global__ __launch_bounds__(kBlkThreads) void k_blk_shift(int s, int n_omega, i
 // Per (band, shift): block LU solve of (T_k - z) Y = E_0 R_0 over k block steps (forward: D_i, G_i as
 // in k_blk_shift, kept in scratch; backward: Y_{k-1} = D_{k-1}^-1 G_{k-1},
 // Y_i = D_i^-1 (G_i - B_{i+1}^H Y_{i+1})), over the shift's own step count kk (conv, else k).  Y goes
-// to ycat[b] at rows i s + r, column pos[shift] s + c (leading dimension ldy); rows kk s .. k s - 1
+// to ycat[b] at rows i s + r, column pos[b][shift] s + c (leading dimension ldy); rows kk s .. k s - 1
 // are zeroed.
 __global__ __launch_bounds__(kBlkThreads) void k_blk_solve(int s, int n_omega, int k, int nbc,
                                                          const double2 *__restrict__ ablk,
@@ -457,7 +458,7 @@ __global__ __launch_bounds__(kBlkThreads) void k_blk_solve(int s, int n_omega, i
   double2 *scr = scratch + ((long)b * n_omega + sh) * 2 * k * ss;  // step i: D_i^-1, then G_i
   const int cv = conv[(long)b * n_omega + sh];
   const int kk = cv >= 0 ? cv : k;
-  const long col0 = (long)pos[sh] * s;
+  const long col0 = (long)pos[(long)b * n_omega + sh] * s;
   double2 *yb = ycat + (long)b * ycat_stride;
   for (int e = threadIdx.x; e < (k - kk) * s * s; e += kBlkThreads) {
     const int r = e % ((k - kk) * s), c = e / ((k - kk) * s);
@@ -680,8 +681,7 @@ sgw_status block_solve(sgw_ctx *ctx, const sgw_ham *h_kq, int n_occ, const sgw_c
           *axg = P(L.axg), *qg = P(L.qg), *abasis = P(L.abasis), *pov = P(L.pov), *C = P(L.c), *psi = P(L.psi),
           *zs = P(L.omega);
   double *bnorm = (double *)(Wb + L.bnorm), *res = (double *)(Wb + L.res), *deps = (double *)(Wb + L.eps);
-  int32_t *list = (int32_t *)(Wb + L.list), *conv = (int32_t *)(Wb + L.conv), *dpos = (int32_t *)(Wb + L.ord),
-          *dord = dpos + n_omega;
+  int32_t *list = (int32_t *)(Wb + L.list), *conv = (int32_t *)(Wb + L.conv), *dpos = (int32_t *)(Wb + L.ord);
   int *bad = (int *)(Wb + L.bad);
   void *T = Wb + L.t;
   const long ss = (long)s * s;
@@ -790,56 +790,71 @@ sgw_status block_solve(sgw_ctx *ctx, const sgw_ham *h_kq, int n_occ, const sgw_c
     SGW_HIP(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
     if ((st = sync(ctx)) != SGW_OK) return st;
     if (hbad) return fail(SGW_ERR_UNSUPPORTED, "block solver: a block lost rank (dependent right-hand sides)");
-    // Solutions: Y(z) per (band, shift) at the shift's own step count, X = V Y per band.  The shifts
-    // are ordered by their largest step count over the chunk's bands and split into up to kGroups runs
-    // (least total inner dimension), one batched product per run with that run's inner dimension.
+    // Solutions: Y(z) per (band, shift) at the shift's own step count, X = V Y per band.  Within each
+    // group of kSubBands bands the shifts are ordered by their largest step count over the group and
+    // split into up to kGroups runs (least total inner dimension), one batched product per run piece
+    // with that run's inner dimension.
     std::vector<int32_t> hconv((size_t)nb * n_omega);
     SGW_HIP(hipMemcpyAsync(hconv.data(), conv, sizeof(int32_t) * nb * n_omega, hipMemcpyDeviceToHost, ctx->stream));
     if ((st = sync(ctx)) != SGW_OK) return st;
-    std::vector<int> ksh(n_omega, 0), ord(n_omega), pos(n_omega);
-    for (int b = 0; b < nb; ++b)
-      for (int j = 0; j < n_omega; ++j) {
-        const int c = hconv[(size_t)b * n_omega + j];
-        ksh[j] = std::max(ksh[j], c >= 0 ? c : k);
+    const int nsb = (nb + kSubBands - 1) / kSubBands;
+    std::vector<std::vector<int>> sb_ksh(nsb, std::vector<int>(n_omega, 0)), sb_ord(nsb), sb_cut(nsb);
+    std::vector<int32_t> hmap((size_t)(nb + nsb) * n_omega);  // pos[b][shift], then ord[group][p]
+    for (int q = 0; q < nsb; ++q) {
+      const int b_lo = q * kSubBands, b_hi = std::min(nb, b_lo + kSubBands);
+      std::vector<int> &ksh = sb_ksh[q], &ord = sb_ord[q];
+      for (int b = b_lo; b < b_hi; ++b)
+        for (int j = 0; j < n_omega; ++j) {
+          const int c = hconv[(size_t)b * n_omega + j];
+          ksh[j] = std::max(ksh[j], c >= 0 ? c : k);
+        }
+      ord.resize(n_omega);
+      for (int j = 0; j < n_omega; ++j) ord[j] = j;
+      std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return ksh[x] > ksh[y]; });
+      for (int p = 0; p < n_omega; ++p) {
+        for (int b = b_lo; b < b_hi; ++b) hmap[(size_t)b * n_omega + ord[p]] = p;
+        hmap[(size_t)(nb + q) * n_omega + p] = ord[p];
       }
-    for (int j = 0; j < n_omega; ++j) ord[j] = j;
-    std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return ksh[x] > ksh[y]; });
-    for (int p = 0; p < n_omega; ++p) pos[ord[p]] = p;
-    const std::vector<int> cut = shift_runs(ord, ksh);
-    std::vector<int32_t> hmap(2 * (size_t)n_omega);
-    for (int j = 0; j < n_omega; ++j) {
-      hmap[j] = pos[j];
-      hmap[n_omega + j] = ord[j];
+      sb_cut[q] = shift_runs(ord, ksh);
     }
-    SGW_HIP(hipMemcpyAsync(dpos, hmap.data(), sizeof(int32_t) * 2 * n_omega, hipMemcpyHostToDevice, ctx->stream));
+    SGW_HIP(hipMemcpyAsync(dpos, hmap.data(), sizeof(int32_t) * hmap.size(), hipMemcpyHostToDevice, ctx->stream));
     hipLaunchKernelGGL(k_blk_solve, dim3(nb * n_omega), dim3(kBlkThreads), 0, ctx->stream, s, n_omega, k, nbc,
                        (const double2 *)ablk, (const double2 *)bblk, (const double2 *)r0, (const double2 *)zs, thomas,
                        ycat, (long)kb * s, (long)kb * s * s * n_omega, (const int32_t *)conv, (const int32_t *)dpos);
     SGW_HIP(hipGetLastError());
-    // per run of at most L.run shifts: X = V Y, (H + alpha P) X = (AV) Y and psi^H X = (psi^H V) Y, then
-    // the true residuals and the output
+    // per run piece of at most L.run shifts: X = V Y, (H + alpha P) X = (AV) Y and psi^H X = (psi^H V) Y,
+    // then the true residuals and the output
     const long ldy = (long)kb * s, ystride = (long)kb * s * s * n_omega;
-    for (size_t g = 0; g + 1 < cut.size(); ++g) {
-      for (int p0 = cut[g]; p0 < cut[g + 1]; p0 += L.run) {
-        const int len = std::min(L.run, cut[g + 1] - p0), kg = ksh[ord[p0]];
-        const double2 *yc = ycat + (long)p0 * s * ldy;
-        if ((st = zgemm(ctx, rocblas_operation_none, rocblas_operation_none, npw, len * s, kg * s, one, basis, npw,
-                        (long)kb * s * npw, yc, ldy, ystride, zero, xg, npw, (long)s * L.run * npw, nb)) != SGW_OK)
-          return st;
-        if ((st = zgemm(ctx, rocblas_operation_none, rocblas_operation_none, npw, len * s, kg * s, one, abasis, npw,
-                        (long)kb * s * npw, yc, ldy, ystride, zero, axg, npw, (long)s * L.run * npw, nb)) != SGW_OK)
-          return st;
-        if (n_occ > 0 &&
-            (st = zgemm(ctx, rocblas_operation_none, rocblas_operation_none, n_occ, len * s, kg * s, one, pov, n_occ,
-                        (long)kb * s * n_occ, yc, ldy, ystride, zero, qg, n_occ, (long)s * L.run * n_occ, nb)) !=
-                SGW_OK)
-          return st;
-        hipLaunchKernelGGL(k_blk_final, dim3(nb * len * s), dim3(256), 0, ctx->stream, npw, n_occ, s, n_omega, len,
-                           p0, L.run, (const double2 *)xg, (const double2 *)axg, (const double2 *)qg,
-                           (const double2 *)rhs, (const double *)deps, (const double2 *)zs, (const int32_t *)dord,
-                           (const int32_t *)conv, k, tol, (const int32_t *)h_kq->d_u2i,
-                           (double2 *)dpsi + (long)b0 * s * n_omega * npw, info + (long)b0 * s * n_omega, bad);
-        SGW_HIP(hipGetLastError());
+    for (int q = 0; q < nsb; ++q) {
+      const int b_lo = q * kSubBands, nq = std::min(kSubBands, nb - b_lo);
+      const std::vector<int> &cut = sb_cut[q], &ord = sb_ord[q], &ksh = sb_ksh[q];
+      const int32_t *dord = dpos + (size_t)(nb + q) * n_omega;
+      for (size_t g = 0; g + 1 < cut.size(); ++g) {
+        for (int p0 = cut[g]; p0 < cut[g + 1]; p0 += L.run) {
+          const int len = std::min(L.run, cut[g + 1] - p0), kg = ksh[ord[p0]];
+          const double2 *yc = ycat + (long)b_lo * ystride + (long)p0 * s * ldy;
+          const long vo = (long)b_lo * kb * s;  // first basis vector of the group
+          if ((st = zgemm(ctx, rocblas_operation_none, rocblas_operation_none, npw, len * s, kg * s, one,
+                          basis + vo * npw, npw, (long)kb * s * npw, yc, ldy, ystride, zero, xg, npw,
+                          (long)s * L.run * npw, nq)) != SGW_OK)
+            return st;
+          if ((st = zgemm(ctx, rocblas_operation_none, rocblas_operation_none, npw, len * s, kg * s, one,
+                          abasis + vo * npw, npw, (long)kb * s * npw, yc, ldy, ystride, zero, axg, npw,
+                          (long)s * L.run * npw, nq)) != SGW_OK)
+            return st;
+          if (n_occ > 0 &&
+              (st = zgemm(ctx, rocblas_operation_none, rocblas_operation_none, n_occ, len * s, kg * s, one,
+                          pov + vo * n_occ, n_occ, (long)kb * s * n_occ, yc, ldy, ystride, zero, qg, n_occ,
+                          (long)s * L.run * n_occ, nq)) != SGW_OK)
+            return st;
+          hipLaunchKernelGGL(k_blk_final, dim3(nq * len * s), dim3(256), 0, ctx->stream, npw, n_occ, s, n_omega,
+                             len, p0, L.run, (const double2 *)xg, (const double2 *)axg, (const double2 *)qg,
+                             (const double2 *)(rhs + (long)b_lo * s * npw), (const double *)(deps + b_lo),
+                             (const double2 *)zs, dord, (const int32_t *)(conv + (long)b_lo * n_omega), k, tol,
+                             (const int32_t *)h_kq->d_u2i, (double2 *)dpsi + (long)(b0 + b_lo) * s * n_omega * npw,
+                             info + (long)(b0 + b_lo) * s * n_omega, bad);
+          SGW_HIP(hipGetLastError());
+        }
       }
     }
     SGW_HIP(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));

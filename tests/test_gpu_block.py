@@ -3,7 +3,8 @@ FOM solutions per shift; Secs. 2.2-2.3, Eqs. 6-8) through the C ABI, against the
 
 The solutions of the block space are the solutions of the same linear systems, so the block solver
 is held to the multishift solver's bar: 1e-8 relative per solve against the oracle's spectral
-solve, at tol_eff = 1e-8 / (2 kappa).  Bands split over several chunks (opts.slots), imaginary-axis
+solve, at tol_eff = 1e-8 / (2 kappa).  Bands split over several chunks (opts.slots) and, with 16
+bands, over two groups of the final products (each with its own shift order), imaginary-axis
 shifts (opts.shift_imag), a non-local pseudopotential and the argument checks are covered too.
 """
 import numpy as np
@@ -57,7 +58,8 @@ def _check(p, pairs, xs, dpsi, inf, tol):
     return worst
 
 
-@pytest.mark.parametrize("cells,n_pert,slots", [((1, 1, 1), 5, 0), ((1, 1, 1), 5, 3), ((2, 1, 1), 8, 0)])
+@pytest.mark.parametrize("cells,n_pert,slots", [((1, 1, 1), 5, 0), ((1, 1, 1), 5, 3), ((2, 1, 1), 8, 0),
+                                               ((2, 2, 1), 4, 0), ((2, 2, 1), 4, 11)])
 def test_block_matches_oracle(ctx, cells, n_pert, slots):
     from paper_1812_03717_amd import sgw
     from paper_1812_03717_amd.workload import DeviceProblem
