@@ -6,8 +6,10 @@ One step is one ``sternheimer_solve`` call over the whole workload.  The default
 largest single-GPU configuration, si64: the 64-atom diamond cell (conventional cubic 2x2x2,
 16,013 plane waves at k+q, 72^3 grid), every one of 128 occupied bands x 20 plane-wave
 perturbations at one seeded q x 100 frequencies in [0, 40] eV with eta = 0.05 eV, tol 1e-8 on the
-true FP64 relative residual: 256,000 solves, plain FP64 multishift (max_iter 3500).  Inputs are
-resident in HBM before the timed region; a solve counts when its true residual meets tol.
+true FP64 relative residual: 256,000 solves.  The default method is the block solver in FP64 (one
+block Krylov space per band over its 20 perturbations, at most 160 block steps), with the plain FP64
+multishift solver (max_iter 3500) timed beside it on the same systems.  Inputs are resident in HBM
+before the timed region; a solve counts when its true residual meets tol.
 
 The JSON line carries the roofline of the dominant kernel (timed with HIP events on the
 library's stream during the timed steps) and the CPU oracle timed on a bounded sample of the
@@ -34,6 +36,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 FP64_VECTOR_TFLOPS = 78.6      # MI355X FP64 vector (256 CU x 2.4 GHz x 128 flop/clk)
+FP64_MFMA_TFLOPS = 78.6        # MI355X dense FP64 matrix
 
 WORKLOADS = {
     "si16": "si16: diamond fcc 2x2x2 (16 atoms), 4015 PW, 48^3 grid, 32 bands x 50 perts x 64 omega in [0,40] eV, "
@@ -54,7 +57,7 @@ WORKLOADS = {
 }
 
 KERNELS = ["hx_sticks_inv", "hx_planes", "hx_sticks_fwd", "proj_dot", "proj_apply", "lanczos_step", "slot_init", "rhs_source",
-           "tridiag", "combine", "residual", "permute", "nl_dot", "nl_apply"]
+           "tridiag", "combine", "residual", "permute", "nl_dot", "nl_apply", "blk_product"]
 
 
 def roofline(kernel, ks, workload, default_launch=True):
@@ -87,7 +90,11 @@ def roofline(kernel, ks, workload, default_launch=True):
     roof = {"kernel": kernel, "traffic": traffic, "avg_launch_ms": round(avg_s * 1e3, 4), "launches": ks["launches"],
             "alg_bytes_per_launch": round(bytes_per_launch), "hbm_achieved_gbs": round(gbs, 1),
             "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
-    if flops_per_launch > 0:
+    if kernel == "blk_product":  # complex FP64 products on the matrix cores (rocBLAS zgemm)
+        tf = flops_per_launch / avg_s / 1e12
+        roof.update({"bound": "mfma", "achieved": round(tf, 2), "peak": FP64_MFMA_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(tf / FP64_MFMA_TFLOPS, 4), "alg_flops_per_launch": round(flops_per_launch)})
+    elif flops_per_launch > 0:
         tf = flops_per_launch / avg_s / 1e12
         roof.update({"bound": "alu", "achieved": round(tf, 2), "peak": FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(tf / FP64_VECTOR_TFLOPS, 4), "alg_flops_per_launch": round(flops_per_launch)})
@@ -621,9 +628,13 @@ def main():
                     help="the timed method; mixed: FP32 potential matvecs once a pair's residuals are small, "
                          "FP64 refinement, with a plain FP64 leg timed beside it")
     ap.add_argument("--mixed-switch", type=float, default=0.0)
-    ap.add_argument("--solver", choices=["multishift", "block"], default="multishift",
-                    help="block: one block Krylov space per band over its perturbations (FP64; max_iter then "
-                         "limits the block steps, 0: 160 for si64)")
+    ap.add_argument("--solver", choices=["multishift", "block"], default=None,
+                    help="block (default in FP64): one block Krylov space per band over its perturbations "
+                         "(max_iter then limits the block steps, 0: 160 for si64), with the multishift solver "
+                         "timed beside it; multishift (default with --precision mixed): one Krylov space per "
+                         "(band, perturbation)")
+    ap.add_argument("--compare-steps", type=int, default=2,
+                    help="timed steps of the multishift solver beside the block solver (0: none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch-workers", type=int, default=4)
     ap.add_argument("--batch-max-iter", type=int, default=4000)
@@ -690,6 +701,8 @@ def main():
     kw = dict(precision=prec)
     if args.slots:
         kw["slots"] = args.slots
+    if args.solver is None:
+        args.solver = "block" if args.precision == "fp64" else "multishift"
     block = args.solver == "block"
     if block:
         if prec != sgw.FP64:
@@ -756,7 +769,29 @@ def main():
             f"{int(np.count_nonzero((inf['flags'] & sgw.FLAG_PER_SHIFT) != 0))}")
 
     # timed steps of the chosen method; plain FP64 beside it, with events around the dominant kernel
-    if prec == sgw.FP64:
+    multishift = None
+    if block:
+        elapsed, n_ok, inf = timed(opts, dominant)
+        med_ms = 1e3 * float(np.median(step_s))
+        report("timed (block fp64)", elapsed, n_ok, inf)
+        p_el, p_ok = elapsed, n_ok
+        ks = ctx.kernel_stats(dominant)
+        if args.compare_steps > 0:
+            # the multishift solver on the same systems (its own max_iter), fewer steps
+            mkw = {k: v for k, v in kw.items() if k != "solver"}
+            mkw["max_iter"] = args.max_iter or (3500 if args.workload in ("si64", "si64nl") else 600)
+            mopts = sgw.sgw_opts_default(**mkw)
+            dev.solve(opts=mopts, workspace=ws, dpsi=dpsi, info=info)
+            torch.cuda.synchronize()
+            saved = args.steps
+            args.steps = args.compare_steps
+            m_el, m_ok, m_inf = timed(mopts, None)
+            args.steps = saved
+            report(f"timed (multishift fp64, {args.compare_steps} steps)", m_el, m_ok, m_inf)
+            multishift = {"value": round(m_ok / m_el, 1), "steps": args.compare_steps,
+                          "ms_per_step": round(1e3 * m_el / args.compare_steps, 3), "max_iter": mkw["max_iter"],
+                          "converged": m_ok}
+    elif prec == sgw.FP64:
         elapsed, n_ok, inf = timed(opts, dominant)
         med_ms = 1e3 * float(np.median(step_s))
         report("timed (plain fp64)", elapsed, n_ok, inf)
@@ -768,9 +803,10 @@ def main():
         plain = sgw.sgw_opts_default(**{k: v for k, v in kw.items() if k in ("slots", "max_iter")})
         p_el, p_ok, p_inf = timed(plain, dominant)
         report("timed (plain fp64)", p_el, p_ok, p_inf)
-    ks = ctx.kernel_stats(dominant)
+    if not block:
+        ks = ctx.kernel_stats(dominant)
     roof = roofline(dominant, ks, args.workload, default_launch=not args.slots)
-    roof["leg"] = "plain FP64 timed steps"
+    roof["leg"] = "block FP64 timed steps" if block else "plain FP64 timed steps"
     value = n_ok / elapsed
     plain_value = p_ok / p_el
     out = {
@@ -778,8 +814,7 @@ def main():
         "value": round(value, 1), "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(1e3 * elapsed / args.steps, 3), "step_ms_median": round(med_ms, 3),
         "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "speedup_vs_plain_fp64": round(value / plain_value, 4),
-        "plain_fp64_value": round(plain_value, 1),
+        "vs_baseline": None,
         "dtype": "f64" if prec == sgw.FP64 else "f64+f32", "data": "synthetic",
         "config": {"workload": WORKLOADS[args.workload], "solves_per_step": problem.n_solves,
                    "max_iter": max_iter or 600,
@@ -791,6 +826,13 @@ def main():
         "roofline": roof,
         "kernel_split": split,
     }
+    if block:
+        if multishift:
+            out["multishift_fp64"] = multishift
+            out["speedup_vs_multishift"] = round(value / multishift["value"], 4)
+    else:
+        out["speedup_vs_plain_fp64"] = round(value / plain_value, 4)
+        out["plain_fp64_value"] = round(plain_value, 1)
     if not args.no_cpu_baseline:
         if args.workload in ("si64", "si64nl"):
             out["cpu_baseline"] = cpu_baseline_lu(problem, log)

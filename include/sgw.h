@@ -163,7 +163,9 @@ sgw_status sgw_plane_kernel(sgw_ctx *ctx, const sgw_ham *ham, int precision, int
 sgw_status sgw_ctx_reset_stats(sgw_ctx *ctx);
 /*
  * Statistics of kernel `name` ("hx_sticks_inv", "hx_planes", "hx_sticks_fwd",
- * "proj_dot", "lanczos_step", "combine", "residual", "nl_dot", "nl_apply", ...).  Outputs may be NULL.
+ * "proj_dot", "lanczos_step", "combine", "residual", "nl_dot", "nl_apply", "blk_product" (the block
+ * solver's final batched products X = V Y, (AV) Y, (psi^H V) Y, one rocBLAS launch each), ...).
+ * Outputs may be NULL.
  * Durations are summed over launches, in milliseconds.
  */
 sgw_status sgw_kernel_stats(sgw_ctx *ctx, const char *name, int64_t *launches, double *total_ms,

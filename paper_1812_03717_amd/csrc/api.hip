@@ -33,7 +33,8 @@ const char *kernel_name(int id) {
   static const char *names[K_COUNT] = {"hx_sticks_inv", "hx_planes", "hx_sticks_fwd", "proj_dot",
                                        "proj_apply",    "rhs_source", "slot_init",    "lanczos_step",
                                        "tridiag",       "combine",   "residual",     "permute",
-                                       "nl_dot",        "nl_apply",  "chi_dot",      "dielectric"};
+                                       "nl_dot",        "nl_apply",  "chi_dot",      "dielectric",
+                                       "blk_product"};
   return (id >= 0 && id < K_COUNT) ? names[id] : "?";
 }
 

@@ -585,16 +585,22 @@ rocblas_handle blas(sgw_ctx *ctx) {
   return h;
 }
 
-// C_b = alpha op(A_b) B_b + beta C_b over nbatch (column-major, strides in elements)
+// C_b = alpha op(A_b) B_b + beta C_b over nbatch (column-major, strides in elements); kid >= 0: the
+// launch is timed under that id with its algorithmic bytes (A, B read, C written) and flops
 sgw_status zgemm(sgw_ctx *ctx, rocblas_operation ta, rocblas_operation tb, int m, int n, int k, double2 alpha,
                  const double2 *A, long lda, long sa, const double2 *B, long ldb, long sb, double2 beta, double2 *C,
-                 long ldc, long sc, int nbatch) {
+                 long ldc, long sc, int nbatch, int kid = -1) {
   rocblas_handle h = blas(ctx);
   if (!h) return fail(SGW_ERR_HIP, "block solver: rocblas_create_handle failed");
   const rocblas_double_complex al(alpha.x, alpha.y), be(beta.x, beta.y);
+  PendingTiming tm;
+  if (kid >= 0)
+    timing_begin(ctx, kid, 16.0 * nbatch * ((double)m * k + (double)k * n + (double)m * n),
+                 8.0 * nbatch * (double)m * n * k, &tm);
   const rocblas_status r = rocblas_zgemm_strided_batched(
       h, ta, tb, m, n, k, &al, (const rocblas_double_complex *)A, lda, sa, (const rocblas_double_complex *)B, ldb, sb,
       &be, (rocblas_double_complex *)C, ldc, sc, nbatch);
+  if (kid >= 0) timing_end(ctx, &tm);
   if (r != rocblas_status_success) return fail(SGW_ERR_HIP, "block solver: rocblas_zgemm_strided_batched failed");
   return SGW_OK;
 }
@@ -836,16 +842,16 @@ sgw_status block_solve(sgw_ctx *ctx, const sgw_ham *h_kq, int n_occ, const sgw_c
           const long vo = (long)b_lo * kb * s;  // first basis vector of the group
           if ((st = zgemm(ctx, rocblas_operation_none, rocblas_operation_none, npw, len * s, kg * s, one,
                           basis + vo * npw, npw, (long)kb * s * npw, yc, ldy, ystride, zero, xg, npw,
-                          (long)s * L.run * npw, nq)) != SGW_OK)
+                          (long)s * L.run * npw, nq, K_BLK_PRODUCT)) != SGW_OK)
             return st;
           if ((st = zgemm(ctx, rocblas_operation_none, rocblas_operation_none, npw, len * s, kg * s, one,
                           abasis + vo * npw, npw, (long)kb * s * npw, yc, ldy, ystride, zero, axg, npw,
-                          (long)s * L.run * npw, nq)) != SGW_OK)
+                          (long)s * L.run * npw, nq, K_BLK_PRODUCT)) != SGW_OK)
             return st;
           if (n_occ > 0 &&
               (st = zgemm(ctx, rocblas_operation_none, rocblas_operation_none, n_occ, len * s, kg * s, one,
                           pov + vo * n_occ, n_occ, (long)kb * s * n_occ, yc, ldy, ystride, zero, qg, n_occ,
-                          (long)s * L.run * n_occ, nq)) != SGW_OK)
+                          (long)s * L.run * n_occ, nq, K_BLK_PRODUCT)) != SGW_OK)
             return st;
           hipLaunchKernelGGL(k_blk_final, dim3(nq * len * s), dim3(256), 0, ctx->stream, npw, n_occ, s, n_omega,
                              len, p0, L.run, (const double2 *)xg, (const double2 *)axg, (const double2 *)qg,

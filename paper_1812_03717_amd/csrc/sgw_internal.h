@@ -51,6 +51,7 @@ enum KernelId {
   K_NL_APPLY,
   K_CHI_DOT,
   K_DIELECTRIC,
+  K_BLK_PRODUCT,
   K_COUNT
 };
 const char *kernel_name(int id);

@@ -7,6 +7,7 @@
     python -m paper_1812_03717_amd.profiling mfma --pmc DB --trace DB --kernel k_proj_dot [--kernel ...]
     python -m paper_1812_03717_amd.profiling valu --pmc DB --trace DB --kernel k_planes_line [--alg-flops F]
     python -m paper_1812_03717_amd.profiling stalls --pmc DB [--pmc DB ...] --kernel k_planes_pair
+    python -m paper_1812_03717_amd.profiling blkprod DB
 
 ``traffic`` scales the per-dispatch FETCH_SIZE and WRITE_SIZE averages (KiB) of
 one kernel by what the same counters read for a plain device copy of known
@@ -192,6 +193,24 @@ def stalls(pmc_dbs, kernel_prefix):
     return r
 
 
+def blk_products(db: str):
+    """The block solver's final products: rocBLAS kernels (Cijk_*) whose latest preceding block-solver
+    kernel (k_blk_*) is k_blk_solve or k_blk_final, i.e. the launches timed as "blk_product".
+    Returns {dispatches, total_ms, avg_us, kernels}."""
+    c = sqlite3.connect(db)
+    last, durs, names = None, [], collections.Counter()
+    for name, dur in c.execute("select name, duration from kernels order by start"):
+        m = re.search(r"k_blk_\w+", name)
+        if m:
+            last = m.group(0)
+        elif name.startswith("Cijk") and last in ("k_blk_solve", "k_blk_final"):
+            durs.append(dur)
+            names[name.split("_MT")[0] + "_MT" + name.split("_MT")[1].split("_")[0]] += 1
+    tot = sum(durs)
+    return {"dispatches": len(durs), "total_ms": tot / 1e6, "avg_us": tot / max(len(durs), 1) / 1e3,
+            "kernels": dict(names)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -216,6 +235,8 @@ def main():
     v.add_argument("--trace", required=True)
     v.add_argument("--kernel", required=True)
     v.add_argument("--alg-flops", type=float, default=0.0, help="algorithmic flops per dispatch, if known")
+    b = sub.add_parser("blkprod")
+    b.add_argument("db")
     s = sub.add_parser("stalls")
     s.add_argument("--pmc", action="append", required=True)
     s.add_argument("--kernel", required=True)
@@ -225,6 +246,12 @@ def main():
         print(f"{'kernel':40s} {'calls':>7s} {'total_ms':>10s} {'avg_us':>9s} {'pct':>6s}")
         for n, calls, tot, avg, pct in top(a.db):
             print(f"{n:40s} {calls:7d} {tot / 1e3:10.2f} {avg:9.2f} {pct:6.2f}")
+    elif a.cmd == "blkprod":
+        r = blk_products(a.db)
+        print(f"block solver final products: {r['dispatches']} dispatches, {r['total_ms']:.2f} ms, "
+              f"avg {r['avg_us']:.2f} us")
+        for k, n in r["kernels"].items():
+            print(f"  {k}: {n}")
     elif a.cmd == "pmc":
         for (k, cn), (n, avg) in sorted(pmc(a.db).items()):
             unit = " KiB" if cn in ("FETCH_SIZE", "WRITE_SIZE") else ""

@@ -1,7 +1,8 @@
 """Full-size parity on the 64-atom workload (conventional cubic 2x2x2 diamond cell, 16,013 plane
 waves at k+q, 72^3 grid, 128 occupied bands x 20 perturbations x 100 frequencies in [0, 40] eV,
-eta 0.05 eV, tol 1e-8): 256,000 solves in the launch configuration bench.py times (plain FP64,
-max_iter 3500, default slots).
+eta 0.05 eV, tol 1e-8): 256,000 solves in the launch configurations bench.py times: the block solver
+(FP64, at most 160 block steps, default chunks) and the plain FP64 multishift solver (max_iter 3500,
+default slots).
 
 Every solve must report a true FP64 relative residual <= tol, the converged flag and an occupied
 component within the error budget (||P_occ x|| <= relres ||b|| / eta).  Sampled outputs are checked against the oracle's direct LU solve of the
@@ -20,7 +21,8 @@ import synth
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
-MAX_ITER = 3500
+MAX_ITER = {"multishift": 3500, "block": 160}
+FREQ, PERTS = 0, [0, 5, 11, 19]
 
 
 @pytest.fixture(scope="module")
@@ -39,14 +41,32 @@ def setup():
     return p, ctx, dev
 
 
+@pytest.fixture(scope="module")
+def reference(setup):
+    """The oracle on the host: dense H_{k+q}, the shifted operator of the top band, one LU
+    factorisation for the four right-hand sides at omega = 0."""
+    p, _, _ = setup
+    v, j = p.n_band - 1, FREQ
+    print("si64 reference: dense LU of the shifted operator on the host", flush=True)
+    h = so.hamiltonian(p.miller_kq, p.B, p.kvec + p.qvec, p.v_grid)
+    a0 = so.coulomb_operator(h, p.psi_kq, p.eps_k[v], 1.0)
+    del h
+    bs = np.array([so.rhs(p.psi_k[v], p.miller_k, p.miller_kq, p.dv_miller[q], p.psi_kq) for q in PERTS])
+    ref = so.solve_lu(a0, bs.T, p.omega[j] + 1j * p.eta).T
+    return bs, ref
+
+
 @pytest.mark.timeout(900)
-def test_si64_full_workload_sampled_vs_lu(setup):
+@pytest.mark.parametrize("solver", ["block", "multishift"])
+def test_si64_full_workload_sampled_vs_lu(setup, reference, solver):
     from paper_1812_03717_amd import sgw
     p, ctx, dev = setup
-    st, dpsi, info = dev.solve(opts=sgw.sgw_opts_default(max_iter=MAX_ITER))
+    kw = {"solver": sgw.SOLVER_BLOCK} if solver == "block" else {}
+    torch.cuda.empty_cache()
+    st, dpsi, info = dev.solve(opts=sgw.sgw_opts_default(max_iter=MAX_ITER[solver], **kw))
     torch.cuda.synchronize()
     inf = sgw.info_to_numpy(info, (p.n_band, p.n_pert, p.n_omega))
-    print(f"si64 full: status {st}; iters {inf['iters'].min()}..{inf['iters'].max()}; "
+    print(f"si64 full ({solver}): status {st}; iters {inf['iters'].min()}..{inf['iters'].max()}; "
           f"max relres {inf['relres'].max():.3e}; max occ leak {inf['occ_leak'].max():.3e}", flush=True)
     assert st == sgw.SGW_OK
     assert np.all(inf["flags"] & sgw.FLAG_CONVERGED)
@@ -57,18 +77,12 @@ def test_si64_full_workload_sampled_vs_lu(setup):
     del b
     nx = np.stack([torch.linalg.vector_norm(dpsi[v], dim=-1).cpu().numpy() for v in range(p.n_band)])
     assert np.all(inf["occ_leak"] * nx <= 1.01 * inf["relres"] * nb / p.eta + 1e-10 * nx)
-    v, j = p.n_band - 1, 0
-    perts = [0, 5, 11, 19]
-    xs = dpsi[v, perts, j].cpu().numpy()
+    v, j = p.n_band - 1, FREQ
+    xs = dpsi[v, PERTS, j].cpu().numpy()
     del dpsi
     torch.cuda.empty_cache()
-    # the oracle on the host: dense H_{k+q}, the shifted operator, one LU for the four right-hand sides
-    h = so.hamiltonian(p.miller_kq, p.B, p.kvec + p.qvec, p.v_grid)
-    a0 = so.coulomb_operator(h, p.psi_kq, p.eps_k[v], 1.0)
-    del h
-    bs = np.array([so.rhs(p.psi_k[v], p.miller_k, p.miller_kq, p.dv_miller[q], p.psi_kq) for q in perts])
-    ref = so.solve_lu(a0, bs.T, p.omega[j] + 1j * p.eta).T
-    for i, q in enumerate(perts):
+    bs, ref = reference
+    for i, q in enumerate(PERTS):
         err = np.linalg.norm(xs[i] - ref[i])
         bound = inf["relres"][v, q, j] * np.linalg.norm(bs[i]) / p.eta
         print(f"  (v={v}, p={q}, omega={p.omega[j]:.3f}): |x - x*| = {err:.3e}, budget {bound:.3e}, "
