@@ -1,6 +1,6 @@
 """Summaries of rocprofv3 results (rocpd SQLite databases) for the library's kernels.
 
-    python -m paper_1812_03717_amd.profiling top DB
+    python -m paper_1812_03717_amd.profiling top DB [--since KERNEL]
     python -m paper_1812_03717_amd.profiling pmc DB
     python -m paper_1812_03717_amd.profiling traffic --kernel k_planes --fetch DB --write DB \
         --copy-fetch DB --copy-write DB --copy-bytes N [--bench-line FILE] [--out FILE.json]
@@ -72,11 +72,24 @@ def short_name(n: str) -> str:
     return out
 
 
-def top(db: str):
+def top(db: str, since: str | None = None):
+    """(kernel, calls, total_us, avg_us, pct) by total duration; with `since`, only the dispatches from
+    the first one whose name contains `since` on (e.g. the solves, without the input generation)."""
     c = sqlite3.connect(db)
-    rows = c.execute("select name, total_calls, total_duration, average, percentage from top_kernels "
-                     "order by total_duration desc").fetchall()
-    return [(short_name(n), calls, tot, avg, pct) for n, calls, tot, avg, pct in rows]
+    if not since:
+        rows = c.execute("select name, total_calls, total_duration, average, percentage from top_kernels "
+                         "order by total_duration desc").fetchall()
+        return [(short_name(n), calls, tot, avg, pct) for n, calls, tot, avg, pct in rows]
+    agg = collections.defaultdict(lambda: [0, 0.0])
+    on = False
+    for name, dur in c.execute("select name, duration from kernels order by start"):
+        on = on or since in name
+        if on:
+            k = name.split("_MI")[0][:40] if name.startswith("Cijk") else short_name(name)
+            agg[k][0] += 1
+            agg[k][1] += dur / 1e3  # ns -> us
+    tot_all = sum(v[1] for v in agg.values()) or 1.0
+    return sorted(((k, n, t, t / n, 100.0 * t / tot_all) for k, (n, t) in agg.items()), key=lambda r: -r[2])
 
 
 @functools.lru_cache(maxsize=None)
@@ -216,6 +229,7 @@ def main():
     sub = ap.add_subparsers(dest="cmd", required=True)
     t = sub.add_parser("top")
     t.add_argument("db")
+    t.add_argument("--since", help="only dispatches from the first kernel whose name contains this on")
     p = sub.add_parser("pmc")
     p.add_argument("db")
     r = sub.add_parser("traffic")
@@ -244,7 +258,7 @@ def main():
     if a.cmd == "top":
         # rocpd reports durations in microseconds
         print(f"{'kernel':40s} {'calls':>7s} {'total_ms':>10s} {'avg_us':>9s} {'pct':>6s}")
-        for n, calls, tot, avg, pct in top(a.db):
+        for n, calls, tot, avg, pct in top(a.db, a.since):
             print(f"{n:40s} {calls:7d} {tot / 1e3:10.2f} {avg:9.2f} {pct:6.2f}")
     elif a.cmd == "blkprod":
         r = blk_products(a.db)
