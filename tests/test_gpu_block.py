@@ -130,3 +130,61 @@ def test_block_errors(ctx):
     with pytest.raises(sgw.SgwError) as e:
         DeviceProblem(ctx, q).solve(opts=sgw.sgw_opts_default(solver=sgw.SOLVER_BLOCK))
     assert e.value.code == sgw.SGW_ERR_UNSUPPORTED
+
+
+def test_block_edges(ctx):
+    """Empty inputs; no occupied states (b = -s, operator H - eps_v - z) against the oracle's LU solve;
+    one perturbation (a block of one vector); three bands in chunks of two (a ragged last chunk)."""
+    from paper_1812_03717_amd import sgw
+    from paper_1812_03717_amd.workload import DeviceProblem
+    p = synth.small((1, 1, 1), n_omega=5, n_pert=3, seed=9100)
+    d = DeviceProblem(ctx, p)
+    blk = sgw.sgw_opts_default(solver=sgw.SOLVER_BLOCK)
+    for kw in (dict(bands=[]), dict(perts=[]), dict(omega=[])):
+        st, dpsi, _ = d.solve(opts=blk, **kw)
+        assert st == sgw.SGW_OK and dpsi.numel() == 0
+    empty = torch.zeros((0, d.h_kq.n_pw), dtype=torch.complex128, device=ctx.device)
+    st, dpsi, _ = sgw.sternheimer_solve(ctx, d.h_kq, empty, d.h_k, d.psi_v[:2].contiguous(), d.eps_v[:2],
+                                        p.dv_miller[:2], p.omega, p.eta, 1e-12, opts=blk)
+    assert st == sgw.SGW_OK, sgw.load_library().sgw_last_error()
+    x = dpsi.cpu().numpy()
+    h = so.hamiltonian(p.miller_kq, p.B, p.kvec + p.qvec, p.v_grid)
+    none = np.zeros((0, h.shape[0]), complex)
+    for v in range(2):
+        a0 = so.coulomb_operator(h, none, p.eps_k[v], 1.0)
+        for q in range(2):
+            b = so.rhs(p.psi_k[v], p.miller_k, p.miller_kq, p.dv_miller[q], none)
+            for j in range(len(p.omega)):
+                ref = so.solve_lu(a0, b, p.omega[j] + 1j * p.eta)
+                assert np.linalg.norm(x[v, q, j] - ref) <= 1e-8 * np.linalg.norm(ref), (v, q, j)
+    pairs, xs, tol = _reference(p)
+    for kw, o in ((dict(perts=[1]), blk),
+                  (dict(bands=[0, 1, 2]), sgw.sgw_opts_default(solver=sgw.SOLVER_BLOCK, slots=2))):
+        st, dpsi, info = d.solve(tol=tol, opts=o, **kw)
+        assert st == sgw.SGW_OK, sgw.load_library().sgw_last_error()
+        bands = kw.get("bands", list(range(p.n_band)))
+        perts = kw.get("perts", list(range(p.n_pert)))
+        inf = sgw.info_to_numpy(info, (len(bands), len(perts), p.n_omega))
+        assert np.all(inf["flags"] & sgw.FLAG_CONVERGED) and inf["relres"].max() <= tol
+        got = dpsi.cpu().numpy()
+        for bi, v in enumerate(bands):
+            for qi, q in enumerate(perts):
+                ref = xs[pairs.index((v, q))]
+                err = np.linalg.norm(got[bi, qi] - ref, axis=-1) / np.linalg.norm(ref, axis=-1)
+                assert err.max() <= 1e-8, (kw, v, q, err.max())
+
+
+def test_block_small_basis_tight_tol(ctx):
+    """The 2-atom cell (a basis of a few hundred plane waves) at tol 1e-12: the block space nears the
+    whole basis before the last shifts converge."""
+    from paper_1812_03717_amd import sgw
+    from paper_1812_03717_amd.workload import DeviceProblem
+    p = synth.si2()
+    pairs, xs, tol = _reference(p)
+    d = DeviceProblem(ctx, p)
+    st, dpsi, info = d.solve(tol=tol, opts=sgw.sgw_opts_default(solver=sgw.SOLVER_BLOCK))
+    assert st == sgw.SGW_OK, sgw.load_library().sgw_last_error()
+    inf = sgw.info_to_numpy(info, (p.n_band, p.n_pert, p.n_omega))
+    print(f"si2 ({p.n_pw_kq} PW, {p.n_pert} perturbations): block steps {inf['iters'].max()}, tol {tol:.1e}",
+          flush=True)
+    _check(p, pairs, xs, dpsi.cpu().numpy(), inf, tol)
