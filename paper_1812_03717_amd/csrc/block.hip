@@ -39,7 +39,7 @@ size_t up(size_t b) { return (b + kBA - 1) / kBA * kBA; }
 // Workspace of one chunk of nbc bands; kb = block steps + 1 stored blocks
 struct BlkLayout {
   int nbc = 0, kb = 0, s = 0, run = 0;
-  size_t basis, abasis, pov, rhs, y, w, v2, gram, part, rfac, rinv, ablk, bblk, r0, bnorm, dinv, ff, res, thomas,
+  size_t basis, abasis, pov, rhs, y, w, v2, gram, coef, part, rfac, rinv, ablk, bblk, r0, bnorm, dinv, ff, res, thomas,
       ycat, xg, axg, qg, list, c, t, psi, omega, eps, conv, ord, dvm, bad, total;
 };
 
@@ -65,6 +65,7 @@ BlkLayout blk_layout(const sgw_ham *h, int n_occ, int nbc, int s, int n_omega, i
   L.w = take(16 * nv * npw);
   L.v2 = take(16 * nv * npw);
   L.gram = take(16 * nbc * ss);
+  L.coef = take(16 * 2 * (size_t)nbc * ss);
   L.part = take(16 * (size_t)((npw + kGramRows - 1) / kGramRows) * nbc * ss);
   L.rfac = take(16 * nbc * ss);
   L.rinv = take(16 * nbc * ss);
@@ -122,33 +123,6 @@ __global__ void k_blk_list(int32_t *list, int nbc, int s, int kb, int j) {
 }
 
 // w[a] = y[a] - eps[band] v[a] (v through the list)
-// w[a] = y[a] - eps[band] v[a], and y[a] = (H + alpha P) v[a] kept beside v[a] (abasis, same list)
-__global__ void k_blk_shift_eps(int npw, int s, const double2 *__restrict__ y, const double2 *__restrict__ basis,
-                                const int32_t *__restrict__ list, const double *__restrict__ eps,
-                                double2 *__restrict__ w, double2 *__restrict__ abasis) {
-  const int a = blockIdx.x;
-  const int g = blockIdx.y * blockDim.x + threadIdx.x;
-  if (g >= npw) return;
-  const double e = eps[a / s];
-  const long slot = (long)list[a] * npw + g;
-  const double2 v = basis[slot], t = y[(long)a * npw + g];
-  w[(long)a * npw + g] = make_double2(t.x - e * v.x, t.y - e * v.y);
-  abasis[slot] = t;
-}
-
-// M = (M + M^H) / 2 for the nbc s x s blocks (column-major)
-__global__ void k_blk_hermitize(double2 *m, int s) {
-  double2 *mb = m + (long)blockIdx.x * s * s;
-  for (int e = threadIdx.x; e < s * s; e += blockDim.x) {
-    const int i = e % s, j = e / s;
-    if (i > j) continue;
-    const double2 a = mb[i + j * s], b = mb[j + i * s];
-    const double2 h = make_double2(0.5 * (a.x + b.x), 0.5 * (a.y - b.y));
-    mb[i + j * s] = h;
-    mb[j + i * s] = make_double2(h.x, -h.y);
-  }
-}
-
 // Skinny products C_b = A_b^H B_b (s x s, column-major) of every band's n_pw x s blocks, in two
 // deterministic passes: partial sums over chunks of kGramRows plane waves (one workgroup per chunk and
 // band, rows staged through LDS with coalesced column loads), then the chunks summed in order.
@@ -197,9 +171,80 @@ __global__ __launch_bounds__(256) void k_blk_gram(int npw, int s, const double2 
 __global__ void k_blk_gram_sum(int n_chunks, int nb, int ss, const double2 *__restrict__ part, double2 *__restrict__ c) {
   const int b = blockIdx.x;
   for (int e = threadIdx.x; e < ss; e += blockDim.x) {
-    double2 v = make_double2(0.0, 0.0);
-    for (int k = 0; k < n_chunks; ++k) v = c_add(v, part[((long)k * nb + b) * ss + e]);
-    c[(long)b * ss + e] = v;
+    double2 v[4] = {make_double2(0.0, 0.0), make_double2(0.0, 0.0), make_double2(0.0, 0.0),
+                    make_double2(0.0, 0.0)};
+    int k = 0;
+    for (; k + 4 <= n_chunks; k += 4)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) v[q] = c_add(v[q], part[((long)(k + q) * nb + b) * ss + e]);
+    for (; k < n_chunks; ++k) v[0] = c_add(v[0], part[((long)k * nb + b) * ss + e]);
+    c[(long)b * ss + e] = c_add(c_add(v[0], v[1]), c_add(v[2], v[3]));
+  }
+}
+
+// Thin combinations out_b = sgn src_b coef_b (+ base_b) for every band b (blockIdx.y): src_b is n_pw x K
+// (K <= 2 s, columns n_pw apart), coef_b K x s column-major (band stride K s, staged in LDS), one plane
+// wave per thread with its SM >= s outputs in registers; copy (may be NULL) receives base_b too.
+template <int SM>
+__global__ __launch_bounds__(256) void k_blk_comb(int npw, int s, int K, const double2 *__restrict__ src, long ssrc,
+                                                  const double2 *__restrict__ coef, double sgn,
+                                                  const double2 *__restrict__ base, long sbase,
+                                                  double2 *__restrict__ out, long sout, double2 *__restrict__ copy,
+                                                  long scopy) {
+  __shared__ double2 Cs[2 * kBlockMaxPert][SM];
+  const int b = blockIdx.y;
+  const double2 *cb = coef + (long)b * K * s;
+  for (int e = threadIdx.x; e < K * s; e += 256) Cs[e % K][e / K] = cb[e];
+  __syncthreads();
+  const int g = blockIdx.x * 256 + threadIdx.x;
+  if (g >= npw) return;
+  double2 acc[SM];
+#pragma unroll
+  for (int c = 0; c < SM; ++c) acc[c] = make_double2(0.0, 0.0);
+  const double2 *sb = src + (long)b * ssrc + g;
+  for (int l = 0; l < K; ++l) {
+    const double2 x = sb[(long)l * npw];
+#pragma unroll
+    for (int c = 0; c < SM; ++c) {
+      if (c < s) {
+        const double2 m = Cs[l][c];
+        acc[c].x += x.x * m.x - x.y * m.y;
+        acc[c].y += x.x * m.y + x.y * m.x;
+      }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < SM; ++c) {
+    if (c < s) {
+      double2 v = make_double2(sgn * acc[c].x, sgn * acc[c].y);
+      if (base) {
+        const double2 y = base[(long)b * sbase + (long)c * npw + g];
+        v = c_add(v, y);
+        if (copy) copy[(long)b * scopy + (long)c * npw + g] = y;
+      }
+      out[(long)b * sout + (long)c * npw + g] = v;
+    }
+  }
+}
+
+// Per band: A_j = (G + G^H)/2 - eps I into ablk, and the coefficients of W = Y - [V_{j-1} V_j] coef,
+// coef = [B_j^H ; (G + G^H)/2] (2s x s, column-major; j = 0: the lower block alone, s x s)
+__global__ void k_blk_coef(int s, int j, const double2 *__restrict__ g, const double2 *__restrict__ bj,
+                           const double *__restrict__ eps, double2 *__restrict__ aj, double2 *__restrict__ coef) {
+  const int b = blockIdx.x;
+  const long ss = (long)s * s;
+  const int K = j > 0 ? 2 * s : s, off = j > 0 ? s : 0;
+  const double2 *gb = g + b * ss;
+  for (int e = threadIdx.x; e < s * s; e += blockDim.x) {
+    const int r = e % s, c = e / s;
+    const double2 x = gb[r + c * s], y = gb[c + r * s];
+    const double2 h = make_double2(0.5 * (x.x + y.x), 0.5 * (x.y - y.y));
+    aj[b * ss + e] = r == c ? make_double2(h.x - eps[b], 0.0) : h;
+    coef[(long)b * K * s + off + r + (long)c * K] = r == c ? make_double2(h.x, 0.0) : h;
+    if (j > 0) {
+      const double2 t = bj[b * ss + c + r * s];  // (B_j^H)[r][c] = conj(B_j[c][r])
+      coef[(long)b * K * s + r + (long)c * K] = make_double2(t.x, -t.y);
+    }
   }
 }
 
@@ -640,6 +685,23 @@ std::vector<int> shift_runs(const std::vector<int> &ord, const std::vector<int> 
   return cut;
 }
 
+// out_b = sgn src_b coef_b (+ base_b, copied to copy_b when copy is given) for the nb bands
+sgw_status comb(sgw_ctx *ctx, int npw, int s, int nb, int K, const double2 *src, long ssrc, const double2 *coef,
+                double sgn, const double2 *base, long sbase, double2 *out, long sout, double2 *copy = nullptr,
+                long scopy = 0) {
+  const dim3 grid((npw + 255) / 256, nb);
+#define SGW_COMB(SM)                                                                                            \
+  hipLaunchKernelGGL(k_blk_comb<SM>, grid, dim3(256), 0, ctx->stream, npw, s, K, src, ssrc, coef, sgn, base, sbase, \
+                     out, sout, copy, scopy)
+  if (s <= 8) SGW_COMB(8);
+  else if (s <= 16) SGW_COMB(16);
+  else if (s <= 24) SGW_COMB(24);
+  else SGW_COMB(32);
+#undef SGW_COMB
+  SGW_HIP(hipGetLastError());
+  return SGW_OK;
+}
+
 // C_b = A_b^H B_b for the nb bands' n_pw x s blocks (band strides sa, sb), C contiguous s x s blocks
 sgw_status gram(sgw_ctx *ctx, int npw, int s, int nb, const double2 *A, long sa, const double2 *B, long sb,
                 double2 *part, double2 *C) {
@@ -681,7 +743,8 @@ sgw_status block_solve(sgw_ctx *ctx, const sgw_ham *h_kq, int n_occ, const sgw_c
   if (L.total > workspace_bytes) return fail(SGW_ERR_WORKSPACE, "block solver: workspace too small for one band");
   char *Wb = (char *)workspace;
   auto P = [&](size_t off) { return (double2 *)(Wb + off); };
-  double2 *basis = P(L.basis), *rhs = P(L.rhs), *Y = P(L.y), *Wv = P(L.w), *V2 = P(L.v2), *gbuf = P(L.gram), *part = P(L.part),
+  double2 *basis = P(L.basis), *rhs = P(L.rhs), *Y = P(L.y), *Wv = P(L.w), *V2 = P(L.v2), *gbuf = P(L.gram), *cbuf = P(L.coef),
+          *part = P(L.part),
           *rfac = P(L.rfac), *rinv = P(L.rinv), *ablk = P(L.ablk), *bblk = P(L.bblk), *r0 = P(L.r0),
           *dinv = P(L.dinv), *ff = P(L.ff), *thomas = P(L.thomas), *ycat = P(L.ycat), *xg = P(L.xg),
           *axg = P(L.axg), *qg = P(L.qg), *abasis = P(L.abasis), *pov = P(L.pov), *C = P(L.c), *psi = P(L.psi),
@@ -691,7 +754,7 @@ sgw_status block_solve(sgw_ctx *ctx, const sgw_ham *h_kq, int n_occ, const sgw_c
   int *bad = (int *)(Wb + L.bad);
   void *T = Wb + L.t;
   const long ss = (long)s * s;
-  const double2 one = make_double2(1.0, 0.0), zero = make_double2(0.0, 0.0), mone = make_double2(-1.0, 0.0);
+  const double2 one = make_double2(1.0, 0.0), zero = make_double2(0.0, 0.0);
   sgw_status st;
 
   // shifts z_j = omega_j + i eta_j, occupied states in internal order, dv_miller on the device
@@ -735,15 +798,13 @@ sgw_status block_solve(sgw_ctx *ctx, const sgw_ham *h_kq, int n_occ, const sgw_c
       if ((s2 = gram(ctx, npw, s, nb, src, (long)s * npw, src, (long)s * npw, part, gbuf)) != SGW_OK) return s2;
       hipLaunchKernelGGL(k_blk_chol, dim3(nb), dim3(64), 0, ctx->stream, gbuf, (const double2 *)nullptr, rfac, rinv,
                          s, bad);
-      if ((s2 = zgemm(ctx, rocblas_operation_none, rocblas_operation_none, npw, s, s, one, src, npw, (long)s * npw,
-                      rinv, s, ss, zero, V2, npw, (long)s * npw, nb)) != SGW_OK)
+      if ((s2 = comb(ctx, npw, s, nb, s, src, (long)s * npw, rinv, 1.0, nullptr, 0, V2, (long)s * npw)) != SGW_OK)
         return s2;
       if ((s2 = gram(ctx, npw, s, nb, V2, (long)s * npw, V2, (long)s * npw, part, gbuf)) != SGW_OK) return s2;
       hipLaunchKernelGGL(k_blk_chol, dim3(nb), dim3(64), 0, ctx->stream, gbuf, (const double2 *)rfac, rout, rinv, s,
                          bad);
       // dst (strided per band in the basis) = V2 R2^-1
-      return zgemm(ctx, rocblas_operation_none, rocblas_operation_none, npw, s, s, one, V2, npw, (long)s * npw, rinv,
-                   s, ss, zero, dst, npw, (long)kb * s * npw, nb);
+      return comb(ctx, npw, s, nb, s, V2, (long)s * npw, rinv, 1.0, nullptr, 0, dst, (long)kb * s * npw);
     };
     if ((st = orth(rhs, basis, r0)) != SGW_OK) return st;
     // block Lanczos steps with the residual estimates of every (band, shift)
@@ -761,21 +822,16 @@ sgw_status block_solve(sgw_ctx *ctx, const sgw_ham *h_kq, int n_occ, const sgw_c
                                  hipMemcpyDeviceToDevice, ctx->stream));
       if ((st = hx_batch(ctx, h_kq, nv, vj, Y, npw, T)) != SGW_OK) return st;
       if ((st = proj_apply(ctx, npw, n_occ, psi, nv, vj, C, nv, Y, npw, o.alpha_pv, 1)) != SGW_OK) return st;
-      hipLaunchKernelGGL(k_blk_shift_eps, dim3(nv, (npw + 255) / 256), dim3(256), 0, ctx->stream, npw, s,
-                         (const double2 *)Y, (const double2 *)basis, (const int32_t *)list, (const double *)deps, Wv,
-                         abasis);
+      // Y = (H + alpha P) V_j; G = V_j^H Y; A_j = herm(G) - eps I;
+      // W = Y - V_{j-1} B_j^H - V_j herm(G) = (H + alpha P - eps) V_j - V_{j-1} B_j^H - V_j A_j, and Y kept as AV
       double2 *vj_ptr = basis + (long)j * s * npw;  // band 0; bands strided by kb s npw
-      if (j > 0) {  // W -= V_{j-1} B_j^H
-        if ((st = zgemm(ctx, rocblas_operation_none, rocblas_operation_conjugate_transpose, npw, s, s, mone,
-                        vj_ptr - (long)s * npw, npw, (long)kb * s * npw, bblk + (long)j * nbc * ss, s, ss, one, Wv,
-                        npw, (long)s * npw, nb)) != SGW_OK)
-          return st;
-      }
       double2 *aj = ablk + (long)j * nbc * ss;
-      if ((st = gram(ctx, npw, s, nb, vj_ptr, (long)kb * s * npw, Wv, (long)s * npw, part, aj)) != SGW_OK) return st;
-      hipLaunchKernelGGL(k_blk_hermitize, dim3(nb), dim3(256), 0, ctx->stream, aj, s);
-      if ((st = zgemm(ctx, rocblas_operation_none, rocblas_operation_none, npw, s, s, mone, vj_ptr, npw,
-                      (long)kb * s * npw, aj, s, ss, one, Wv, npw, (long)s * npw, nb)) != SGW_OK)
+      if ((st = gram(ctx, npw, s, nb, vj_ptr, (long)kb * s * npw, Y, (long)s * npw, part, gbuf)) != SGW_OK) return st;
+      hipLaunchKernelGGL(k_blk_coef, dim3(nb), dim3(256), 0, ctx->stream, s, j, (const double2 *)gbuf,
+                         (const double2 *)(bblk + (long)j * nbc * ss), (const double *)deps, aj, cbuf);
+      if ((st = comb(ctx, npw, s, nb, j > 0 ? 2 * s : s, j > 0 ? vj_ptr - (long)s * npw : vj_ptr,
+                     (long)kb * s * npw, cbuf, -1.0, Y, (long)s * npw, Wv, (long)s * npw,
+                     abasis + (long)j * s * npw, (long)kb * s * npw)) != SGW_OK)
         return st;
       if ((st = orth(Wv, vj_ptr + (long)s * npw, bblk + (long)(j + 1) * nbc * ss)) != SGW_OK) return st;
       hipLaunchKernelGGL(k_blk_shift, dim3(nb * n_omega), dim3(kBlkThreads), 0, ctx->stream, s, n_omega, j,
