@@ -370,32 +370,47 @@ __device__ __forceinline__ void blk_diff_shift(Blk M, const double2 *A, double2 
 __device__ void blk_inverse(Blk M, int s, int *perm) {
   for (int i = threadIdx.x; i < s; i += kBlkThreads) perm[i] = i;
   __syncthreads();
+  __shared__ int piv;
   for (int k = 0; k < s; ++k) {
-    if (threadIdx.x == 0) {
-      int p = k;
-      double best = -1.0;
-      for (int i = k; i < s; ++i) {
-        const double a = M[i][k].x * M[i][k].x + M[i][k].y * M[i][k].y;
-        if (a > best) {
-          best = a;
-          p = i;
+    // pivot: the largest |M[i][k]| over rows i >= k (s <= 32 rows: one wave, butterfly argmax)
+    if (threadIdx.x < 64) {
+      const int i = k + threadIdx.x;
+      double a = -1.0;
+      int idx = s;
+      if (i < s) {
+        a = M[i][k].x * M[i][k].x + M[i][k].y * M[i][k].y;
+        idx = i;
+      }
+      for (int off = 32; off > 0; off >>= 1) {
+        const double oa = __shfl_xor(a, off);
+        const int oi = __shfl_xor(idx, off);
+        if (oa > a || (oa == a && oi < idx)) {
+          a = oa;
+          idx = oi;
         }
       }
-      if (p != k) {
-        for (int j = 0; j < s; ++j) {
-          const double2 tmp = M[k][j];
-          M[k][j] = M[p][j];
-          M[p][j] = tmp;
-        }
+      if (threadIdx.x == 0) piv = idx;
+    }
+    __syncthreads();
+    const int p = piv;
+    if (p != k) {  // the same for the whole block
+      for (int j = threadIdx.x; j < s; j += kBlkThreads) {
+        const double2 tmp = M[k][j];
+        M[k][j] = M[p][j];
+        M[p][j] = tmp;
+      }
+      if (threadIdx.x == 0) {
         const int tp = perm[k];
         perm[k] = perm[p];
         perm[p] = tp;
       }
-      const double2 d = M[k][k];
-      const double q = 1.0 / (d.x * d.x + d.y * d.y);
-      const double2 dinv = make_double2(d.x * q, -d.y * q);
-      for (int j = 0; j < s; ++j) M[k][j] = j == k ? dinv : c_mul(M[k][j], dinv);
+      __syncthreads();
     }
+    const double2 d = M[k][k];
+    const double q = 1.0 / (d.x * d.x + d.y * d.y);
+    const double2 dinv = make_double2(d.x * q, -d.y * q);
+    __syncthreads();  // every thread holds the pivot before row k is scaled
+    for (int j = threadIdx.x; j < s; j += kBlkThreads) M[k][j] = j == k ? dinv : c_mul(M[k][j], dinv);
     __syncthreads();
     // rows i != k: columns j != k lose M[i][k] times the scaled pivot row ...
     for (int e = threadIdx.x; e < s * s; e += kBlkThreads) {
