@@ -99,9 +99,11 @@ enum {
                                  the bands iterated together (default: as many as a 144 GiB
                                  workspace holds, all bands if it can); solves whose estimate met
                                  the threshold while the true residual missed tol are refined per
-                                 shift, as after the plain multishift solver; right-hand sides
-                                 of one band that are linearly dependent (or zero) are rejected
-                                 with SGW_ERR_UNSUPPORTED */
+                                 shift, as after the plain multishift solver; a band whose block
+                                 loses rank (linearly dependent or zero right-hand sides, or a
+                                 block space that stops growing in some direction) keeps the steps
+                                 before it, and its solutions that miss tol are refined the same
+                                 way */
 };
 /* diagonal preconditioner of the per-shift solves (sgw_opts.precond) */
 enum { SGW_PC_NONE = 0, SGW_PC_TETER = 1, SGW_PC_LEARNED = 2 };

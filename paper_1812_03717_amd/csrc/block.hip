@@ -40,7 +40,7 @@ size_t up(size_t b) { return (b + kBA - 1) / kBA * kBA; }
 struct BlkLayout {
   int nbc = 0, kb = 0, s = 0, run = 0;
   size_t basis, abasis, pov, rhs, y, w, v2, gram, coef, part, rfac, rinv, ablk, bblk, r0, bnorm, dinv, ff, res, thomas,
-      ycat, xg, axg, qg, list, c, t, psi, omega, eps, conv, ord, dvm, bad, total;
+      ycat, xg, axg, qg, list, c, t, psi, omega, eps, conv, ord, dvm, bstep, kband, bad, total;
 };
 
 BlkLayout blk_layout(const sgw_ham *h, int n_occ, int nbc, int s, int n_omega, int kb) {
@@ -90,6 +90,8 @@ BlkLayout blk_layout(const sgw_ham *h, int n_occ, int nbc, int s, int n_omega, i
   L.conv = take(4 * (size_t)nbc * n_omega);
   L.ord = take(8 * (size_t)nbc * n_omega);
   L.dvm = take(4 * 3 * (size_t)s);
+  L.bstep = take(4 * (size_t)nbc);
+  L.kband = take(4 * (size_t)nbc);
   L.bad = take(8);
   L.total = off;
   return L;
@@ -249,10 +251,11 @@ __global__ void k_blk_coef(int s, int j, const double2 *__restrict__ g, const do
 }
 
 // Cholesky G = R^H R (R upper) of each band's Gram matrix, R^-1, and rout = R rprev (or R); a pivot
-// below rel_floor of the largest diagonal sets *bad
+// below 1e-26 of the largest diagonal entry (a block that lost rank) lowers bstep[band] to `step`, the
+// index of the basis block being formed
 __global__ __launch_bounds__(64) void k_blk_chol(const double2 *__restrict__ gram, const double2 *__restrict__ rprev,
                                                  double2 *__restrict__ rout, double2 *__restrict__ rinv, int s,
-                                                 int *bad) {
+                                                 int *bstep, int step) {
   __shared__ double2 R[kBlockMaxPert][kBlockMaxPert + 1];
   __shared__ double2 Ri[kBlockMaxPert][kBlockMaxPert + 1];
   __shared__ int fail;
@@ -308,7 +311,7 @@ __global__ __launch_bounds__(64) void k_blk_chol(const double2 *__restrict__ gra
     }
     rout[base + e] = v;
   }
-  if (t == 0 && fail) atomicOr(bad, 1);
+  if (t == 0 && fail) atomicMin(bstep + blockIdx.x, step);
 }
 
 // s x s blocks in LDS, [row][col] with a padded row.  Every helper is entered and left by all
@@ -508,7 +511,8 @@ __global__ __launch_bounds__(kBlkThreads) void k_blk_solve(int s, int n_omega, i
                                                          const double2 *__restrict__ zs, double2 *__restrict__ scratch,
                                                          double2 *__restrict__ ycat, long ldy, long ycat_stride,
                                                          const int32_t *__restrict__ conv,
-                                                         const int32_t *__restrict__ pos) {
+                                                         const int32_t *__restrict__ pos,
+                                                         const int32_t *__restrict__ kband) {
   __shared__ double2 X1[kBlockMaxPert][kBlockMaxPert + 1], X2[kBlockMaxPert][kBlockMaxPert + 1],
       X3[kBlockMaxPert][kBlockMaxPert + 1];
   __shared__ int perm[kBlockMaxPert];
@@ -516,8 +520,8 @@ __global__ __launch_bounds__(kBlkThreads) void k_blk_solve(int s, int n_omega, i
   const long ss = (long)s * s;
   const double2 z = zs[sh];
   double2 *scr = scratch + ((long)b * n_omega + sh) * 2 * k * ss;  // step i: D_i^-1, then G_i
-  const int cv = conv[(long)b * n_omega + sh];
-  const int kk = cv >= 0 ? cv : k;
+  const int cv = conv[(long)b * n_omega + sh], kbb = kband[b];
+  const int kk = cv >= 0 && cv <= kbb ? cv : kbb;  // a band whose block lost rank keeps its valid steps
   const long col0 = (long)pos[(long)b * n_omega + sh] * s;
   double2 *yb = ycat + (long)b * ycat_stride;
   for (int e = threadIdx.x; e < (k - kk) * s * s; e += kBlkThreads) {
@@ -563,13 +567,15 @@ __global__ __launch_bounds__(kBlkThreads) void k_blk_solve(int s, int n_omega, i
 // solution in the caller's order and sign.  Block a: band b, position p0 + l, perturbation c for
 // a = (b len + l) s + c; x, ax at vector (b run + l) s + c of xg, axg (q: the overlaps psi^H x).
 // relres = ||b - (ax - eps x - z x)|| / ||b||, occ_leak = ||q|| / ||x||, iters = the shift's step count
-// (conv, else k_final, then MAXITER when the residual misses tol); dpsi[g] = -x[u2i[g]].
+// (conv, else the band's kband; MAXITER when the residual misses tol after all k_final steps, no flag
+// for a band whose block lost rank earlier, so that it is refined per shift); dpsi[g] = -x[u2i[g]].
 __global__ __launch_bounds__(256) void k_blk_final(int npw, int n_occ, int s, int n_omega, int len, int p0, int run,
                                                    const double2 *__restrict__ xg, const double2 *__restrict__ axg,
                                                    const double2 *__restrict__ qg, const double2 *__restrict__ rhs,
                                                    const double *__restrict__ eps, const double2 *__restrict__ zs,
                                                    const int32_t *__restrict__ ord, const int32_t *__restrict__ conv,
-                                                   int k_final, double tol, const int32_t *__restrict__ u2i,
+                                                   const int32_t *__restrict__ kband, int k_final, double tol,
+                                                   const int32_t *__restrict__ u2i,
                                                    double2 *__restrict__ dpsi, sgw_solve_info *info, int *bad) {
   __shared__ double red[3][256];
   const long a = blockIdx.x;
@@ -613,18 +619,19 @@ __global__ __launch_bounds__(256) void k_blk_final(int npw, int n_occ, int s, in
       const double2 q = qg[xv * n_occ + i];
       occ += q.x * q.x + q.y * q.y;
     }
-    const int cv = conv[(long)b * n_omega + sh];
+    const int kbb = kband[b];
+    const int cv = conv[(long)b * n_omega + sh] <= kbb ? conv[(long)b * n_omega + sh] : -1;
     const double nb = sqrt(red[1][0]), nx = sqrt(red[2][0]);
     const double rel = nb > 0.0 ? sqrt(red[0][0]) / nb : 0.0;
     sgw_solve_info r;
-    r.iters = cv >= 0 ? cv : k_final;
+    r.iters = cv >= 0 ? cv : kbb;
     r.relres = rel;
     r.occ_leak = nx > 0.0 ? sqrt(occ) / nx : 0.0;
     int fl = 0;
     if (!isfinite(rel)) fl |= SGW_FLAG_NONFINITE;
     else if (nb == 0.0) fl |= SGW_FLAG_CONVERGED | SGW_FLAG_ZERO_RHS;
     else if (rel <= tol) fl |= SGW_FLAG_CONVERGED;
-    else fl |= cv < 0 ? SGW_FLAG_MAXITER : 0;
+    else fl |= cv < 0 && kbb == k_final ? SGW_FLAG_MAXITER : 0;  // a band that lost rank: refined
     r.flags = fl;
     info[o] = r;
     if (!(fl & SGW_FLAG_CONVERGED)) atomicOr(bad, 1);
@@ -766,7 +773,7 @@ sgw_status block_solve(sgw_ctx *ctx, const sgw_ham *h_kq, int n_occ, const sgw_c
           *zs = P(L.omega);
   double *bnorm = (double *)(Wb + L.bnorm), *res = (double *)(Wb + L.res), *deps = (double *)(Wb + L.eps);
   int32_t *list = (int32_t *)(Wb + L.list), *conv = (int32_t *)(Wb + L.conv), *dpos = (int32_t *)(Wb + L.ord);
-  int *bad = (int *)(Wb + L.bad);
+  int *bad = (int *)(Wb + L.bad), *bstep = (int *)(Wb + L.bstep), *kband = (int *)(Wb + L.kband);
   void *T = Wb + L.t;
   const long ss = (long)s * s;
   const double2 one = make_double2(1.0, 0.0), zero = make_double2(0.0, 0.0);
@@ -788,6 +795,7 @@ sgw_status block_solve(sgw_ctx *ctx, const sgw_ham *h_kq, int n_occ, const sgw_c
     const int nv = nb * s;
     SGW_HIP(hipMemsetAsync(bad, 0, 8, ctx->stream));
     SGW_HIP(hipMemsetAsync(conv, 0xff, sizeof(int32_t) * nb * n_omega, ctx->stream));  // -1: running
+    SGW_HIP(hipMemsetAsync(bstep, 0x7f, sizeof(int) * nb, ctx->stream));                // no rank loss
     SGW_HIP(hipMemcpyAsync(deps, eps_v + b0, sizeof(double) * nb, hipMemcpyHostToDevice, ctx->stream));
     // right-hand sides in internal order: rhs = (1 - P) s (the solution is negated on the way out)
     for (int a = 0; a < nv; ++a) hpairs[a] = (b0 + a / s) * s + a % s;
@@ -808,26 +816,35 @@ sgw_status block_solve(sgw_ctx *ctx, const sgw_ham *h_kq, int n_occ, const sgw_c
       SGW_HIP(hipMemcpyAsync(bnorm, hn.data(), sizeof(double) * nv, hipMemcpyHostToDevice, ctx->stream));
     }
     // V_0 R_0 = rhs (Cholesky QR twice)
-    auto orth = [&](const double2 *src, double2 *dst, double2 *rout) -> sgw_status {
+    // (step: the index of the basis block formed; a band whose Cholesky fails keeps blocks 0 .. step - 1)
+    auto orth = [&](const double2 *src, double2 *dst, double2 *rout, int step) -> sgw_status {
       sgw_status s2;
       if ((s2 = gram(ctx, npw, s, nb, src, (long)s * npw, src, (long)s * npw, part, gbuf)) != SGW_OK) return s2;
       hipLaunchKernelGGL(k_blk_chol, dim3(nb), dim3(64), 0, ctx->stream, gbuf, (const double2 *)nullptr, rfac, rinv,
-                         s, bad);
+                         s, bstep, step);
       if ((s2 = comb(ctx, npw, s, nb, s, src, (long)s * npw, rinv, 1.0, nullptr, 0, V2, (long)s * npw)) != SGW_OK)
         return s2;
       if ((s2 = gram(ctx, npw, s, nb, V2, (long)s * npw, V2, (long)s * npw, part, gbuf)) != SGW_OK) return s2;
       hipLaunchKernelGGL(k_blk_chol, dim3(nb), dim3(64), 0, ctx->stream, gbuf, (const double2 *)rfac, rout, rinv, s,
-                         bad);
+                         bstep, step);
       // dst (strided per band in the basis) = V2 R2^-1
       return comb(ctx, npw, s, nb, s, V2, (long)s * npw, rinv, 1.0, nullptr, 0, dst, (long)kb * s * npw);
     };
-    if ((st = orth(rhs, basis, r0)) != SGW_OK) return st;
-    // block Lanczos steps with the residual estimates of every (band, shift)
+    if ((st = orth(rhs, basis, r0, 0)) != SGW_OK) return st;
+    // block Lanczos steps with the residual estimates of every (band, shift).  A band whose block loses
+    // rank (dependent right-hand sides, or a block space that stops growing in some direction) keeps
+    // its valid blocks: its later steps are ignored, its solutions are taken at that step count and
+    // any that miss tol are refined per shift.
     int k = 0;
     std::vector<double> hres((size_t)nb * n_omega);
+    std::vector<int> hbstep(nb);
+    SGW_HIP(hipMemcpyAsync(hbstep.data(), bstep, sizeof(int) * nb, hipMemcpyDeviceToHost, ctx->stream));
+    if ((st = sync(ctx)) != SGW_OK) return st;
+    bool all_lost = true;
+    for (int b = 0; b < nb; ++b) all_lost = all_lost && hbstep[b] <= 0;
     // host polls: every step once a step is large enough to hide the round trip
     const int poll = (long)nv * npw >= (1L << 22) ? 1 : std::max(1, o.steps_per_sync);
-    for (int j = 0; j + 1 < kb; ++j) {
+    for (int j = 0; j + 1 < kb && !all_lost; ++j) {
       hipLaunchKernelGGL(k_blk_list, dim3((nv + 255) / 256), dim3(256), 0, ctx->stream, list, nb, s, kb, j);
       const VecSrc vj = listed(basis, npw, list);
       if ((st = proj_dot(ctx, npw, n_occ, psi, nv, vj, C, nv)) != SGW_OK) return st;
@@ -848,7 +865,7 @@ sgw_status block_solve(sgw_ctx *ctx, const sgw_ham *h_kq, int n_occ, const sgw_c
                      (long)kb * s * npw, cbuf, -1.0, Y, (long)s * npw, Wv, (long)s * npw,
                      abasis + (long)j * s * npw, (long)kb * s * npw)) != SGW_OK)
         return st;
-      if ((st = orth(Wv, vj_ptr + (long)s * npw, bblk + (long)(j + 1) * nbc * ss)) != SGW_OK) return st;
+      if ((st = orth(Wv, vj_ptr + (long)s * npw, bblk + (long)(j + 1) * nbc * ss, j + 1)) != SGW_OK) return st;
       hipLaunchKernelGGL(k_blk_shift, dim3(nb * n_omega), dim3(kBlkThreads), 0, ctx->stream, s, n_omega, j,
                          (const double2 *)aj, (const double2 *)(bblk + (long)j * nbc * ss),
                          (const double2 *)(bblk + (long)(j + 1) * nbc * ss), (const double2 *)r0,
@@ -857,16 +874,26 @@ sgw_status block_solve(sgw_ctx *ctx, const sgw_ham *h_kq, int n_occ, const sgw_c
       k = j + 1;
       if (k % poll == 0 || k + 1 >= kb) {
         SGW_HIP(hipMemcpyAsync(hres.data(), res, sizeof(double) * nb * n_omega, hipMemcpyDeviceToHost, ctx->stream));
+        SGW_HIP(hipMemcpyAsync(hbstep.data(), bstep, sizeof(int) * nb, hipMemcpyDeviceToHost, ctx->stream));
         if ((st = sync(ctx)) != SGW_OK) return st;
         double worst = 0.0;
-        for (double r : hres) worst = std::max(worst, std::isfinite(r) ? r : 1e300);
+        for (int b = 0; b < nb; ++b) {
+          if (hbstep[b] <= k) continue;  // lost rank: done at its valid steps
+          for (int q = 0; q < n_omega; ++q) {
+            const double r = hres[(size_t)b * n_omega + q];
+            worst = std::max(worst, std::isfinite(r) ? r : 1e300);
+          }
+        }
         if (worst <= tol_int) break;
       }
     }
-    int hbad = 0;
-    SGW_HIP(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    // every band's valid step count
+    SGW_HIP(hipMemcpyAsync(hbstep.data(), bstep, sizeof(int) * nb, hipMemcpyDeviceToHost, ctx->stream));
     if ((st = sync(ctx)) != SGW_OK) return st;
-    if (hbad) return fail(SGW_ERR_UNSUPPORTED, "block solver: a block lost rank (dependent right-hand sides)");
+    std::vector<int32_t> hkband(nb);
+    for (int b = 0; b < nb; ++b) hkband[b] = std::min(k, std::max(hbstep[b], 0));
+    SGW_HIP(hipMemcpyAsync(kband, hkband.data(), sizeof(int32_t) * nb, hipMemcpyHostToDevice, ctx->stream));
+    int hbad = 0;
     // Solutions: Y(z) per (band, shift) at the shift's own step count, X = V Y per band.  Within each
     // group of kSubBands bands the shifts are ordered by their largest step count over the group and
     // split into up to kGroups runs (least total inner dimension), one batched product per run piece
@@ -883,7 +910,7 @@ sgw_status block_solve(sgw_ctx *ctx, const sgw_ham *h_kq, int n_occ, const sgw_c
       for (int b = b_lo; b < b_hi; ++b)
         for (int j = 0; j < n_omega; ++j) {
           const int c = hconv[(size_t)b * n_omega + j];
-          ksh[j] = std::max(ksh[j], c >= 0 ? c : k);
+          ksh[j] = std::max(ksh[j], c >= 0 && c <= hkband[b] ? c : hkband[b]);
         }
       ord.resize(n_omega);
       for (int j = 0; j < n_omega; ++j) ord[j] = j;
@@ -897,7 +924,8 @@ sgw_status block_solve(sgw_ctx *ctx, const sgw_ham *h_kq, int n_occ, const sgw_c
     SGW_HIP(hipMemcpyAsync(dpos, hmap.data(), sizeof(int32_t) * hmap.size(), hipMemcpyHostToDevice, ctx->stream));
     hipLaunchKernelGGL(k_blk_solve, dim3(nb * n_omega), dim3(kBlkThreads), 0, ctx->stream, s, n_omega, k, nbc,
                        (const double2 *)ablk, (const double2 *)bblk, (const double2 *)r0, (const double2 *)zs, thomas,
-                       ycat, (long)kb * s, (long)kb * s * s * n_omega, (const int32_t *)conv, (const int32_t *)dpos);
+                       ycat, (long)kb * s, (long)kb * s * s * n_omega, (const int32_t *)conv, (const int32_t *)dpos,
+                       (const int32_t *)kband);
     SGW_HIP(hipGetLastError());
     // per run piece of at most L.run shifts: X = V Y, (H + alpha P) X = (AV) Y and psi^H X = (psi^H V) Y,
     // then the true residuals and the output
@@ -911,23 +939,32 @@ sgw_status block_solve(sgw_ctx *ctx, const sgw_ham *h_kq, int n_occ, const sgw_c
           const int len = std::min(L.run, cut[g + 1] - p0), kg = ksh[ord[p0]];
           const double2 *yc = ycat + (long)b_lo * ystride + (long)p0 * s * ldy;
           const long vo = (long)b_lo * kb * s;  // first basis vector of the group
-          if ((st = zgemm(ctx, rocblas_operation_none, rocblas_operation_none, npw, len * s, kg * s, one,
-                          basis + vo * npw, npw, (long)kb * s * npw, yc, ldy, ystride, zero, xg, npw,
-                          (long)s * L.run * npw, nq, K_BLK_PRODUCT)) != SGW_OK)
-            return st;
-          if ((st = zgemm(ctx, rocblas_operation_none, rocblas_operation_none, npw, len * s, kg * s, one,
-                          abasis + vo * npw, npw, (long)kb * s * npw, yc, ldy, ystride, zero, axg, npw,
-                          (long)s * L.run * npw, nq, K_BLK_PRODUCT)) != SGW_OK)
-            return st;
-          if (n_occ > 0 &&
-              (st = zgemm(ctx, rocblas_operation_none, rocblas_operation_none, n_occ, len * s, kg * s, one,
-                          pov + vo * n_occ, n_occ, (long)kb * s * n_occ, yc, ldy, ystride, zero, qg, n_occ,
-                          (long)s * L.run * n_occ, nq, K_BLK_PRODUCT)) != SGW_OK)
-            return st;
+          if (kg == 0) {  // every band of the group lost rank at the start: X = 0, refined per shift
+            const size_t xb = sizeof(double2) * (size_t)nq * s * L.run * npw;
+            SGW_HIP(hipMemsetAsync(xg, 0, xb, ctx->stream));
+            SGW_HIP(hipMemsetAsync(axg, 0, xb, ctx->stream));
+            if (n_occ > 0)
+              SGW_HIP(hipMemsetAsync(qg, 0, sizeof(double2) * (size_t)nq * s * L.run * n_occ, ctx->stream));
+          } else {
+            if ((st = zgemm(ctx, rocblas_operation_none, rocblas_operation_none, npw, len * s, kg * s, one,
+                            basis + vo * npw, npw, (long)kb * s * npw, yc, ldy, ystride, zero, xg, npw,
+                            (long)s * L.run * npw, nq, K_BLK_PRODUCT)) != SGW_OK)
+              return st;
+            if ((st = zgemm(ctx, rocblas_operation_none, rocblas_operation_none, npw, len * s, kg * s, one,
+                            abasis + vo * npw, npw, (long)kb * s * npw, yc, ldy, ystride, zero, axg, npw,
+                            (long)s * L.run * npw, nq, K_BLK_PRODUCT)) != SGW_OK)
+              return st;
+            if (n_occ > 0 &&
+                (st = zgemm(ctx, rocblas_operation_none, rocblas_operation_none, n_occ, len * s, kg * s, one,
+                            pov + vo * n_occ, n_occ, (long)kb * s * n_occ, yc, ldy, ystride, zero, qg, n_occ,
+                            (long)s * L.run * n_occ, nq, K_BLK_PRODUCT)) != SGW_OK)
+              return st;
+          }
           hipLaunchKernelGGL(k_blk_final, dim3(nq * len * s), dim3(256), 0, ctx->stream, npw, n_occ, s, n_omega,
                              len, p0, L.run, (const double2 *)xg, (const double2 *)axg, (const double2 *)qg,
                              (const double2 *)(rhs + (long)b_lo * s * npw), (const double *)(deps + b_lo),
-                             (const double2 *)zs, dord, (const int32_t *)(conv + (long)b_lo * n_omega), k, tol,
+                             (const double2 *)zs, dord, (const int32_t *)(conv + (long)b_lo * n_omega),
+                             (const int32_t *)(kband + b_lo), k, tol,
                              (const int32_t *)h_kq->d_u2i, (double2 *)dpsi + (long)(b0 + b_lo) * s * n_omega * npw,
                              info + (long)(b0 + b_lo) * s * n_omega, bad);
           SGW_HIP(hipGetLastError());

@@ -174,6 +174,31 @@ def test_block_edges(ctx):
                 assert err.max() <= 1e-8, (kw, v, q, err.max())
 
 
+def test_block_duplicate_perturbation(ctx):
+    """A perturbation given twice: the band's block has rank s - 1 in exact arithmetic.  Rounding leaves
+    a pivot ~1e-16 of the largest, above the rank-loss threshold, so the block carries a rounding
+    direction in place of the duplicate (a larger space, not a wrong one); whichever way a solve
+    ends, directly or refined per shift, it must meet tol and match the oracle."""
+    from paper_1812_03717_amd import sgw
+    from paper_1812_03717_amd.workload import DeviceProblem
+    p = synth.small((1, 1, 1), n_omega=4, n_pert=3, seed=9100)
+    pairs, xs, tol = _reference(p)
+    d = DeviceProblem(ctx, p)
+    perts = [0, 0, 2]
+    st, dpsi, info = d.solve(tol=tol, opts=sgw.sgw_opts_default(solver=sgw.SOLVER_BLOCK), perts=perts)
+    assert st == sgw.SGW_OK, sgw.load_library().sgw_last_error()
+    inf = sgw.info_to_numpy(info, (p.n_band, len(perts), p.n_omega))
+    assert np.all(inf["flags"] & sgw.FLAG_CONVERGED) and inf["relres"].max() <= tol
+    print(f"duplicate perturbation: {np.count_nonzero(inf['flags'] & sgw.FLAG_PER_SHIFT)} of {inf.size} "
+          f"refined per shift", flush=True)
+    got = dpsi.cpu().numpy()
+    for v in range(p.n_band):
+        for qi, q in enumerate(perts):
+            ref = xs[pairs.index((v, q))]
+            err = np.linalg.norm(got[v, qi] - ref, axis=-1) / np.linalg.norm(ref, axis=-1)
+            assert err.max() <= 1e-8, (v, q, err.max())
+
+
 def test_block_small_basis_tight_tol(ctx):
     """The 2-atom cell (a basis of a few hundred plane waves) at tol 1e-12: the block space nears the
     whole basis before the last shifts converge."""
