@@ -78,9 +78,10 @@ BlkLayout blk_layout(const sgw_ham *h, int n_occ, int nbc, int s, int n_omega, i
   L.res = take(8 * (size_t)nbc * n_omega);
   L.thomas = take(16 * 2 * (size_t)kb * nbc * n_omega * ss);
   L.ycat = take(16 * (size_t)kb * s * nv * n_omega);
-  L.xg = take(16 * nv * L.run * npw);
-  L.axg = take(16 * nv * L.run * npw);
-  L.qg = take(16 * nv * L.run * no);
+  const size_t nvg = (size_t)std::min(nbc, kSubBands) * s;  // vectors of one group of bands
+  L.xg = take(16 * nvg * L.run * npw);
+  L.axg = take(16 * nvg * L.run * npw);
+  L.qg = take(16 * nvg * L.run * no);
   L.list = take(4 * nv);
   L.c = take(16 * kProjChunks * nv * no);
   L.t = take(hx_tbuf_bytes(h, nv));
