@@ -762,8 +762,9 @@ def main():
         ctx.set_profiling(None)
         return el, n_ok, inf
 
-    def report(tag, el, n_ok, inf):
-        log(f"{tag}: {args.steps} steps in {el:.3f} s; converged {n_ok}/{problem.n_solves * args.steps}; "
+    def report(tag, el, n_ok, inf, steps=None):
+        steps = steps or args.steps
+        log(f"{tag}: {steps} steps in {el:.3f} s; converged {n_ok}/{problem.n_solves * steps}; "
             f"iters min/mean/max {inf['iters'].min()}/{inf['iters'].mean():.1f}/{inf['iters'].max()}; "
             f"max relres {inf['relres'].max():.3e}; refined per shift "
             f"{int(np.count_nonzero((inf['flags'] & sgw.FLAG_PER_SHIFT) != 0))}")
@@ -787,7 +788,7 @@ def main():
             args.steps = args.compare_steps
             m_el, m_ok, m_inf = timed(mopts, None)
             args.steps = saved
-            report(f"timed (multishift fp64, {args.compare_steps} steps)", m_el, m_ok, m_inf)
+            report("timed (multishift fp64)", m_el, m_ok, m_inf, steps=args.compare_steps)
             multishift = {"value": round(m_ok / m_el, 1), "steps": args.compare_steps,
                           "ms_per_step": round(1e3 * m_el / args.compare_steps, 3), "max_iter": mkw["max_iter"],
                           "converged": m_ok}
