@@ -4,18 +4,22 @@
 // The perturbations p of band v share the operator A_v = H - eps_v + alpha P_occ, so the block Krylov
 // space K_k(A_v, [b_1 .. b_s]) serves every right-hand side, and, being shift invariant, every
 // frequency z_j.  Block Lanczos (three-term block recurrence, no reorthogonalisation):
-//     V_0 R_0 = B,   W = A V_j - V_{j-1} B_j^H,   A_j = V_j^H W,   W -= V_j A_j,   V_{j+1} B_{j+1} = W,
+//     V_0 R_0 = B,   A_j = V_j^H A_v V_j,   W = A_v V_j - V_{j-1} B_j^H - V_j A_j,   V_{j+1} B_{j+1} = W,
 // the orthonormalisations by Cholesky QR done twice.  With T_k the Hermitian block tridiagonal matrix
 // (diagonal A_j, sub-diagonal B_{j+1}), the FOM solution of shift z is X(z) = V Y(z) with
-// (T_k - z) Y(z) = E_0 R_0, and its residual is B_k (last block of Y(z)).  The last block follows from
-// a forward block recurrence per shift, D_j = A_j - z - B_j D_{j-1}^-1 B_j^H, F_j = -B_j D_{j-1}^-1
-// F_{j-1}, Y_last = D_j^-1 F_j, so the residual estimates cost s x s work per step and shift.  At the
-// end the block tridiagonal systems are solved per shift (block Thomas) and X = V Y is one matrix
-// product per band; the true FP64 residual of every solution decides, as in the other solvers.
+// (T_k - z) Y(z) = E_0 R_0, and its residual is V_k B_k (last block of Y(z)).  The last block follows
+// from a forward block recurrence per shift, D_j = A_j - z - B_j D_{j-1}^-1 B_j^H, F_j = -B_j
+// D_{j-1}^-1 F_{j-1}, Y_last = D_j^-1 F_j, so the residual estimates cost s x s work per step and
+// shift; a shift stops at the step where its estimate meets the threshold.  At the end the block
+// tridiagonal systems are solved per shift (block Thomas) over each shift's own step count, and
+// X = V Y, (H + alpha P) X = (AV) Y and Psi^H X = (Psi^H V) Y come out of batched products, AV and
+// Psi^H V being kept from the recurrence; the true FP64 residual of every solution decides, as in the
+// other solvers.
 //
-// The block operations other than H.x and the occupied projector (the library's kernels) are
-// batched products of plain matrices (rocBLAS zgemm), a Cholesky and triangular inverse per band and
-// the s x s shift recurrences (kernels here).  Blocks hold at most kBlockMaxPert perturbations.
+// H.x and the occupied projector are the library's kernels; the s x s Gram products, the thin
+// n_pw x s combinations, the Cholesky factors and the shift recurrences are kernels here; the final
+// products are rocBLAS zgemm (plain library products on the FP64 matrix cores).  Blocks hold at most
+// kBlockMaxPert perturbations.
 #include <rocblas/rocblas.h>
 
 #include <algorithm>
