@@ -572,14 +572,15 @@ __global__ __launch_bounds__(kBlkThreads) void k_blk_solve(int s, int n_omega, i
 // solution in the caller's order and sign.  Block a: band b, position p0 + l, perturbation c for
 // a = (b len + l) s + c; x, ax at vector (b run + l) s + c of xg, axg (q: the overlaps psi^H x).
 // relres = ||b - (ax - eps x - z x)|| / ||b||, occ_leak = ||q|| / ||x||, iters = the shift's step count
-// (conv, else the band's kband; MAXITER when the residual misses tol after all k_final steps, no flag
-// for a band whose block lost rank earlier, so that it is refined per shift); dpsi[g] = -x[u2i[g]].
+// (conv, else the band's kband; MAXITER when the residual misses tol after the step limit (maxed), no
+// flag for a band whose block lost rank, so that it is refined per shift); dpsi[g] = -x[u2i[g]].
 __global__ __launch_bounds__(256) void k_blk_final(int npw, int n_occ, int s, int n_omega, int len, int p0, int run,
                                                    const double2 *__restrict__ xg, const double2 *__restrict__ axg,
                                                    const double2 *__restrict__ qg, const double2 *__restrict__ rhs,
                                                    const double *__restrict__ eps, const double2 *__restrict__ zs,
                                                    const int32_t *__restrict__ ord, const int32_t *__restrict__ conv,
-                                                   const int32_t *__restrict__ kband, int k_final, double tol,
+                                                   const int32_t *__restrict__ kband, int k_final, int maxed,
+                                                   double tol,
                                                    const int32_t *__restrict__ u2i,
                                                    double2 *__restrict__ dpsi, sgw_solve_info *info, int *bad) {
   __shared__ double red[3][256];
@@ -636,7 +637,7 @@ __global__ __launch_bounds__(256) void k_blk_final(int npw, int n_occ, int s, in
     if (!isfinite(rel)) fl |= SGW_FLAG_NONFINITE;
     else if (nb == 0.0) fl |= SGW_FLAG_CONVERGED | SGW_FLAG_ZERO_RHS;
     else if (rel <= tol) fl |= SGW_FLAG_CONVERGED;
-    else fl |= cv < 0 && kbb == k_final ? SGW_FLAG_MAXITER : 0;  // a band that lost rank: refined
+    else fl |= cv < 0 && maxed && kbb == k_final ? SGW_FLAG_MAXITER : 0;  // a band that lost rank: refined
     r.flags = fl;
     info[o] = r;
     if (!(fl & SGW_FLAG_CONVERGED)) atomicOr(bad, 1);
@@ -969,7 +970,7 @@ sgw_status block_solve(sgw_ctx *ctx, const sgw_ham *h_kq, int n_occ, const sgw_c
                              len, p0, L.run, (const double2 *)xg, (const double2 *)axg, (const double2 *)qg,
                              (const double2 *)(rhs + (long)b_lo * s * npw), (const double *)(deps + b_lo),
                              (const double2 *)zs, dord, (const int32_t *)(conv + (long)b_lo * n_omega),
-                             (const int32_t *)(kband + b_lo), k, tol,
+                             (const int32_t *)(kband + b_lo), k, k + 1 >= kb ? 1 : 0, tol,
                              (const int32_t *)h_kq->d_u2i, (double2 *)dpsi + (long)(b0 + b_lo) * s * n_omega * npw,
                              info + (long)(b0 + b_lo) * s * n_omega, bad);
           SGW_HIP(hipGetLastError());

@@ -213,3 +213,21 @@ def test_block_small_basis_tight_tol(ctx):
     print(f"si2 ({p.n_pw_kq} PW, {p.n_pert} perturbations): block steps {inf['iters'].max()}, tol {tol:.1e}",
           flush=True)
     _check(p, pairs, xs, dpsi.cpu().numpy(), inf, tol)
+
+
+def test_block_space_exhausted(ctx):
+    """A 1-atom-per-cell-like basis of ~100 plane waves with 12 perturbations: after 8 block steps the
+    block space nears the whole basis and the next block loses rank.  The solves that the block space
+    has not finished are refined per shift (not flagged as hitting the step limit) and every solve
+    meets tol."""
+    from paper_1812_03717_amd import sgw
+    from paper_1812_03717_amd.workload import DeviceProblem
+    p = synth.small((1, 1, 1), ecut=4.0, n_omega=6, n_pert=12, seed=9120)
+    pairs, xs, tol = _reference(p)
+    d = DeviceProblem(ctx, p)
+    st, dpsi, info = d.solve(tol=tol, opts=sgw.sgw_opts_default(solver=sgw.SOLVER_BLOCK))
+    inf = sgw.info_to_numpy(info, (p.n_band, p.n_pert, p.n_omega))
+    print(f"{p.n_pw_kq} PW x 12 perturbations: block steps {inf['iters'].max()}, "
+          f"{np.count_nonzero(inf['flags'] & sgw.FLAG_PER_SHIFT)} of {inf.size} refined per shift", flush=True)
+    assert st == sgw.SGW_OK, sgw.load_library().sgw_last_error()
+    _check(p, pairs, xs, dpsi.cpu().numpy(), inf, tol)
