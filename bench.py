@@ -20,6 +20,7 @@ band, one LU factorisation solving all perturbations at one frequency), scaled t
                                                         # a plain FP64 leg is timed beside it
     python bench.py --workload batch200                 # 200 uneven systems, sternheimer_solve_batch
     python bench.py --workload batch200e11              # the same at Ecut 11.46 Ha (inputs: GPU eigensolver)
+                                                        # (block solver; --batch-solver multishift)
 """
 from __future__ import annotations
 
@@ -318,7 +319,11 @@ def bench_batch(args, log):
 
     # the largest cells (72^3, ~110 bands, dense spectrum in the frequency window) need up to ~4000
     # Krylov steps for their upper bands; the slot count is fitted to the workspace
-    opts = lambda: sgw.sgw_opts_default(max_iter=args.batch_max_iter)
+    block = args.batch_solver == "block"
+    if block:  # one block space per band over its perturbations; no autotuning (multishift settings)
+        opts = lambda: sgw.sgw_opts_default(solver=sgw.SOLVER_BLOCK, max_iter=args.batch_block_steps)
+    else:
+        opts = lambda: sgw.sgw_opts_default(max_iter=args.batch_max_iter)
     batches = []
     for g in groups:
         b = sgw.Batch(ctx)
@@ -329,7 +334,7 @@ def bench_batch(args, log):
         batches.append(b)
     items = [it for b in batches for it in b.items]
     t = time.perf_counter()
-    tune_ms = sum(b.autotune(i) for b in batches for i in range(len(b.items)))
+    tune_ms = 0.0 if block else sum(b.autotune(i) for b in batches for i in range(len(b.items)))
     log(f"{len(groups)} group(s) of {[len(g) for g in groups]} systems; "
         f"autotune: {tune_ms / 1e3:.2f} s (wall {time.perf_counter() - t:.2f} s); steps_per_sync/graph chosen: "
         f"{sorted({(it['problem'].opts.steps_per_sync, it['problem'].opts.graph) for it in items})}; "
@@ -344,6 +349,14 @@ def bench_batch(args, log):
             n += int(np.count_nonzero((inf["flags"] & sgw.FLAG_CONVERGED) != 0))
         return n
 
+    # one workspace for the sequential and the batched runs, sized once: growing it between systems
+    # would hold the old and the new buffer together
+    need = max([b.workspace_size(workers) for b in batches] +
+               [sgw.sternheimer_workspace_size(ctx, devs[i].h_kq, problems[i].n_occ, problems[i].n_band,
+                                               problems[i].n_pert, problems[i].n_omega, opts())
+                for i in range(len(problems))])
+    ws.get(need)
+    log(f"workspace {need / 2**30:.1f} GiB")
     # sequential reference: one system at a time, default options, the library's own stream
     torch.cuda.synchronize()
     t = time.perf_counter()
@@ -385,8 +398,10 @@ def bench_batch(args, log):
         "config": {"workload": WORKLOADS[args.workload], "solves_per_step": n_solves, "workers": workers,
                    "groups": len(groups),
                    "autotune_s": round(tune_ms / 1e3, 3), "sequential_solves_per_s": round(seq_ok / seq_s, 1),
-                   "max_iter": args.batch_max_iter,
-                   "method": "plain FP64 multishift Lanczos-FOM, batched over worker streams, autotuned"},
+                   "max_iter": args.batch_block_steps if block else args.batch_max_iter,
+                   "method": ("FP64 block Lanczos-FOM over each band's perturbations, batched over worker "
+                              "streams" if block else
+                              "plain FP64 multishift Lanczos-FOM, batched over worker streams, autotuned")},
         "roofline": roofline("hx_planes", ks, args.workload),
     }
     print(json.dumps(out), flush=True)
@@ -638,6 +653,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch-workers", type=int, default=4)
     ap.add_argument("--batch-max-iter", type=int, default=4000)
+    ap.add_argument("--batch-solver", choices=["multishift", "block"], default="block",
+                    help="solver of the batch workloads (block: at most --batch-block-steps block steps; "
+                         "multishift: --batch-max-iter Krylov steps, autotuned)")
+    ap.add_argument("--batch-block-steps", type=int, default=600)
     ap.add_argument("--batch-output-gib", type=int, default=100,
                     help="device memory for the batch outputs; systems are grouped to fit it")
     ap.add_argument("--cpu-sample-pairs", type=int, default=160)

@@ -1581,9 +1581,22 @@ extern "C" sgw_status sgw_green_solve(sgw_ctx *ctx, const sgw_ham *h_k, int n_co
 // ---------------------------------------------------------------------------
 namespace {
 
-// Multishift options whose workspace fits `budget` bytes: the slot count (and the
-// finalisation batch) are lowered from the requested or automatic values.
+// Options whose workspace fits `budget` bytes.  Multishift: the slot count (and the finalisation batch)
+// are lowered from the requested or automatic values.  Block: the bands per chunk (slots) are the most
+// that fit, at least one.
 sgw_opts fit_to_budget(const sgw_problem &p, sgw_opts o, size_t budget) {
+  if (o.solver == SGW_SOLVER_BLOCK) {
+    int lo = 1, hi = std::max(1, o.slots > 0 ? std::min(o.slots, p.n_band) : p.n_band);
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) / 2;
+      sgw_opts t = o;
+      t.slots = mid;
+      if (problem_workspace_bytes(p, t) <= budget) lo = mid;
+      else hi = mid - 1;
+    }
+    o.slots = lo;
+    return o;
+  }
   if (o.solver != SGW_SOLVER_MULTISHIFT) return o;
   const int n_omega = std::max(p.n_omega, 1);
   Layout L = make_layout(p.h_kq, p.n_occ, p.n_band, p.n_pert, n_omega, o);
