@@ -3,8 +3,8 @@ the dielectric matrix (Eq. 4) and W_bar (Sec. 2.4, Eq. 9) with the bare and trun
 potential (Sec. 2.6, Eq. 12), against the oracle.
 
 * chi from the library's own solves at z and -z (sternheimer_solve with omega, eta and with
-  -omega, -eta) against the oracle's sum over empty states: the solves carry relative errors up to
-  kappa * tol_eff <= 5e-9 each, so 1e-8 of the largest entry.
+  -omega, -eta; the multishift and the block solver) against the oracle's sum over empty states: the
+  solves carry relative errors up to kappa * tol_eff <= 5e-9 each, so 1e-8 of the largest entry.
 * eps, eps^-1 and W_bar from a given chi against the oracle's formulas and numpy's inverse:
   1e-12 relative (FP64 Gauss-Jordan; these matrices are well conditioned).
 * the q + G = 0 rule with the truncated potential, accumulation over k-point weights, errors.
@@ -40,13 +40,14 @@ CASES = {
 }
 
 
-def _solve_pm(ctx, d, p, tol):
-    """The variations at z_j = omega_j + i eta and at -z_j."""
+def _solve_pm(ctx, d, p, tol, solver="multishift"):
+    """The variations at z_j = omega_j + i eta and at -z_j (multishift or block solver)."""
     from paper_1812_03717_amd import sgw
+    opts = sgw.sgw_opts_default(solver=sgw.SOLVER_BLOCK) if solver == "block" else None
     out = []
     for sgn in (1.0, -1.0):
         st, dpsi, info = sgw.sternheimer_solve(ctx, d.h_kq, d.psi_occ_kq, d.h_k, d.psi_v, d.eps_v, p.dv_miller,
-                                               sgn * p.omega, sgn * p.eta, tol)
+                                               sgn * p.omega, sgn * p.eta, tol, opts=opts)
         inf = sgw.info_to_numpy(info)
         assert st == sgw.SGW_OK, sgw.load_library().sgw_last_error()
         assert np.all(inf["flags"] & sgw.FLAG_CONVERGED) and inf["relres"].max() <= tol
@@ -65,18 +66,19 @@ def _oracle_chi(p):
     return chi, kap
 
 
+@pytest.mark.parametrize("solver", ["multishift", "block"])
 @pytest.mark.parametrize("name", sorted(CASES))
-def test_density_response_matches_oracle(ctx, name):
+def test_density_response_matches_oracle(ctx, name, solver):
     from paper_1812_03717_amd import sgw
     from paper_1812_03717_amd.workload import DeviceProblem
     p = CASES[name]()
     d = DeviceProblem(ctx, p)
     ref, kap = _oracle_chi(p)
     tol = max(2e-13, min(1e-10, 1e-8 / (2.0 * kap)))
-    dp, dm = _solve_pm(ctx, d, p, tol)
+    dp, dm = _solve_pm(ctx, d, p, tol, solver)
     chi = sgw.sgw_density_response(ctx, d.h_kq, d.psi_occ_kq, d.h_k, d.psi_v, p.dv_miller, dp, dm).cpu().numpy()
     err = np.abs(chi - ref).max() / np.abs(ref).max()
-    print(name, p.n_pw_kq, "PW,", p.n_band, "bands,", p.n_pert, "perts: kappa", kap, "tol", tol, "chi rel err", err,
+    print(name, solver, p.n_pw_kq, "PW,", p.n_band, "bands,", p.n_pert, "perts: kappa", kap, "tol", tol, "chi rel err", err,
           flush=True)
     assert err <= 1e-8
     # the same from the oracle's formula on the library's own variations (contraction only)
