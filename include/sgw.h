@@ -94,7 +94,8 @@ enum {
   SGW_SOLVER_BLOCK = 3        /* all perturbations and shifts of one band v share one block Krylov
                                  space (block Lanczos over the n_pert right-hand sides, FOM
                                  solutions per shift; Secs. 2.2-2.3): FP64 only, no preconditioner
-                                 or guess, n_pert <= 32 (above: SGW_ERR_UNSUPPORTED); max_iter
+                                 or guess; more than 32 perturbations are split into ceil(n_pert/32)
+                                 blocks of near-equal size, solved one after another; max_iter
                                  limits the block steps, info.iters reports them; slots > 0 caps
                                  the bands iterated together (default: as many as a 144 GiB
                                  workspace holds, all bands if it can); solves whose estimate met

@@ -878,9 +878,6 @@ static sgw_status validate_solve(sgw_ctx *ctx, const sgw_ham *h_kq, int n_occ, c
     SGW_CHECK(o.precond == SGW_PC_NONE && o.guess == SGW_GUESS_ZERO,
               "sternheimer_solve: the block solver takes no preconditioner or initial guess");
     SGW_CHECK(o.hist_iter == 0, "sternheimer_solve: the block solver keeps no residual history");
-    if (n_pert > kBlockMaxPert)
-      return fail(SGW_ERR_UNSUPPORTED, "sternheimer_solve: the block solver takes at most " +
-                                           std::to_string(kBlockMaxPert) + " perturbations");
   }
   SGW_CHECK(o.precond >= SGW_PC_NONE && o.precond <= SGW_PC_LEARNED, "sternheimer_solve: unknown preconditioner");
   SGW_CHECK(o.guess == SGW_GUESS_ZERO || o.guess == SGW_GUESS_LEARNED, "sternheimer_solve: unknown initial guess");

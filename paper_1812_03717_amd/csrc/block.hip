@@ -570,11 +570,13 @@ __global__ __launch_bounds__(kBlkThreads) void k_blk_solve(int s, int n_omega, i
 // Per solution of a run of shifts (positions p0 .. p0 + len - 1 of the order ord): its true FP64
 // residual from X = V Y and (H + alpha P) X = (AV) Y, both formed from the stored products, and the
 // solution in the caller's order and sign.  Block a: band b, position p0 + l, perturbation c for
-// a = (b len + l) s + c; x, ax at vector (b run + l) s + c of xg, axg (q: the overlaps psi^H x).
+// a = (b len + l) s + c, the caller's perturbation pert0 + c of n_pert; x, ax at vector (b run + l) s + c
+// of xg, axg (q: the overlaps psi^H x).
 // relres = ||b - (ax - eps x - z x)|| / ||b||, occ_leak = ||q|| / ||x||, iters = the shift's step count
 // (conv, else the band's kband; MAXITER when the residual misses tol after the step limit (maxed), no
 // flag for a band whose block lost rank, so that it is refined per shift); dpsi[g] = -x[u2i[g]].
-__global__ __launch_bounds__(256) void k_blk_final(int npw, int n_occ, int s, int n_omega, int len, int p0, int run,
+__global__ __launch_bounds__(256) void k_blk_final(int npw, int n_occ, int s, int n_pert, int pert0, int n_omega,
+                                                   int len, int p0, int run,
                                                    const double2 *__restrict__ xg, const double2 *__restrict__ axg,
                                                    const double2 *__restrict__ qg, const double2 *__restrict__ rhs,
                                                    const double *__restrict__ eps, const double2 *__restrict__ zs,
@@ -604,7 +606,7 @@ __global__ __launch_bounds__(256) void k_blk_final(int npw, int n_occ, int s, in
     bb += bv.x * bv.x + bv.y * bv.y;
     xx += x.x * x.x + x.y * x.y;
   }
-  const long o = ((long)b * s + c) * n_omega + sh;
+  const long o = ((long)b * n_pert + pert0 + c) * n_omega + sh;  // caller's (band, perturbation, shift)
   double2 *out = dpsi + o * npw;
   for (int g = threadIdx.x; g < npw; g += 256) {
     const double2 x = xa[u2i[g]];
@@ -615,7 +617,7 @@ __global__ __launch_bounds__(256) void k_blk_final(int npw, int n_occ, int s, in
   red[2][threadIdx.x] = xx;
   __syncthreads();
   for (int h = 128; h > 0; h >>= 1) {
-    if (threadIdx.x < h)
+    if ((int)threadIdx.x < h)
       for (int q = 0; q < 3; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + h];
     __syncthreads();
   }
@@ -741,6 +743,16 @@ sgw_status gram(sgw_ctx *ctx, int npw, int s, int nb, const double2 *A, long sa,
   return SGW_OK;
 }
 
+// blocks of at most kBlockMaxPert perturbations, as equal as possible: group g of n_groups starts at
+// first(g) and holds size(g) perturbations
+struct PertGroups {
+  int n_pert, n_groups;
+  explicit PertGroups(int n) : n_pert(n), n_groups(std::max(1, (n + kBlockMaxPert - 1) / kBlockMaxPert)) {}
+  int size(int g) const { return n_pert / n_groups + (g < n_pert % n_groups ? 1 : 0); }
+  int first(int g) const { return g * (n_pert / n_groups) + std::min(g, n_pert % n_groups); }
+  int largest() const { return size(0); }
+};
+
 }  // namespace
 
 void blas_release(sgw_ctx *ctx) {
@@ -754,16 +766,21 @@ size_t block_workspace_bytes(const sgw_ham *h_kq, int n_occ, int n_band, int n_p
                              const sgw_opts &o) {
   if (n_band <= 0 || n_pert <= 0) return 256;
   const int kb = blk_steps(o) + 1;
-  const int nbc = blk_chunk(h_kq, n_occ, n_band, n_pert, n_omega, kb, kBlockBudget, o.slots);
-  return blk_layout(h_kq, n_occ, nbc, n_pert, n_omega, kb).total;
+  const int s = PertGroups(n_pert).largest();
+  const int nbc = blk_chunk(h_kq, n_occ, n_band, s, n_omega, kb, kBlockBudget, o.slots);
+  return blk_layout(h_kq, n_occ, nbc, s, n_omega, kb).total;
 }
 
-sgw_status block_solve(sgw_ctx *ctx, const sgw_ham *h_kq, int n_occ, const sgw_c128 *psi_occ_kq, const sgw_ham *h_k,
-                       int n_band, const sgw_c128 *psi_v, const double *eps_v, int n_pert, const int32_t *dv_miller,
-                       int n_omega, const double *omega, double eta, double tol, const sgw_opts &o, void *workspace,
-                       size_t workspace_bytes, sgw_c128 *dpsi, sgw_solve_info *info) {
-  const int s = n_pert;
-  if (s > kBlockMaxPert) return fail(SGW_ERR_UNSUPPORTED, "block solver: more than 32 perturbations per band");
+namespace {
+
+// The perturbations pert0 .. pert0 + s - 1 of the caller's n_pert (dv_miller: theirs, s rows) as one
+// block per band; dpsi and info are the caller's whole arrays.
+sgw_status block_group(sgw_ctx *ctx, const sgw_ham *h_kq, int n_occ, const sgw_c128 *psi_occ_kq, const sgw_ham *h_k,
+                       int n_band, const sgw_c128 *psi_v, const double *eps_v, int n_pert, int pert0, int s,
+                       const int32_t *dv_miller, int n_omega, const double *omega, double eta, double tol,
+                       const sgw_opts &o, void *workspace, size_t workspace_bytes, sgw_c128 *dpsi,
+                       sgw_solve_info *info) {
+  if (s > kBlockMaxPert || s < 1) return fail(SGW_ERR_INVALID_ARG, "block solver: bad block size");
   const int npw = h_kq->n_pw;
   const int kb = blk_steps(o) + 1;
   const int nbc = blk_chunk(h_kq, n_occ, n_band, s, n_omega, kb, (double)workspace_bytes, o.slots);
@@ -966,13 +983,13 @@ sgw_status block_solve(sgw_ctx *ctx, const sgw_ham *h_kq, int n_occ, const sgw_c
                             (long)s * L.run * n_occ, nq, K_BLK_PRODUCT)) != SGW_OK)
               return st;
           }
-          hipLaunchKernelGGL(k_blk_final, dim3(nq * len * s), dim3(256), 0, ctx->stream, npw, n_occ, s, n_omega,
-                             len, p0, L.run, (const double2 *)xg, (const double2 *)axg, (const double2 *)qg,
+          hipLaunchKernelGGL(k_blk_final, dim3(nq * len * s), dim3(256), 0, ctx->stream, npw, n_occ, s, n_pert,
+                             pert0, n_omega, len, p0, L.run, (const double2 *)xg, (const double2 *)axg, (const double2 *)qg,
                              (const double2 *)(rhs + (long)b_lo * s * npw), (const double *)(deps + b_lo),
                              (const double2 *)zs, dord, (const int32_t *)(conv + (long)b_lo * n_omega),
                              (const int32_t *)(kband + b_lo), k, k + 1 >= kb ? 1 : 0, tol,
-                             (const int32_t *)h_kq->d_u2i, (double2 *)dpsi + (long)(b0 + b_lo) * s * n_omega * npw,
-                             info + (long)(b0 + b_lo) * s * n_omega, bad);
+                             (const int32_t *)h_kq->d_u2i, (double2 *)dpsi + (long)(b0 + b_lo) * n_pert * n_omega * npw,
+                             info + (long)(b0 + b_lo) * n_pert * n_omega, bad);
           SGW_HIP(hipGetLastError());
         }
       }
@@ -982,6 +999,25 @@ sgw_status block_solve(sgw_ctx *ctx, const sgw_ham *h_kq, int n_occ, const sgw_c
     any_bad = any_bad || hbad;
   }
   return any_bad ? SGW_NOT_CONVERGED : SGW_OK;
+}
+
+
+}  // namespace
+
+sgw_status block_solve(sgw_ctx *ctx, const sgw_ham *h_kq, int n_occ, const sgw_c128 *psi_occ_kq, const sgw_ham *h_k,
+                       int n_band, const sgw_c128 *psi_v, const double *eps_v, int n_pert, const int32_t *dv_miller,
+                       int n_omega, const double *omega, double eta, double tol, const sgw_opts &o, void *workspace,
+                       size_t workspace_bytes, sgw_c128 *dpsi, sgw_solve_info *info) {
+  const PertGroups G(n_pert);
+  bool missed = false;
+  for (int g = 0; g < G.n_groups; ++g) {
+    const sgw_status st = block_group(ctx, h_kq, n_occ, psi_occ_kq, h_k, n_band, psi_v, eps_v, n_pert, G.first(g),
+                                      G.size(g), dv_miller + 3 * G.first(g), n_omega, omega, eta, tol, o, workspace,
+                                      workspace_bytes, dpsi, info);
+    if (st != SGW_OK && st != SGW_NOT_CONVERGED) return st;
+    missed = missed || st == SGW_NOT_CONVERGED;
+  }
+  return missed ? SGW_NOT_CONVERGED : SGW_OK;
 }
 
 }  // namespace sgw

@@ -5,7 +5,8 @@ The solutions of the block space are the solutions of the same linear systems, s
 is held to the multishift solver's bar: 1e-8 relative per solve against the oracle's spectral
 solve, at tol_eff = 1e-8 / (2 kappa).  Bands split over several chunks (opts.slots) and, with 16
 bands, over two groups of the final products (each with its own shift order), imaginary-axis
-shifts (opts.shift_imag), a non-local pseudopotential and the argument checks are covered too.
+shifts (opts.shift_imag), a non-local pseudopotential, more than 32 perturbations (several blocks per
+band) and the argument checks are covered too.
 """
 import numpy as np
 import pytest
@@ -126,10 +127,19 @@ def test_block_errors(ctx):
         with pytest.raises(sgw.SgwError) as e:
             d.solve(opts=sgw.sgw_opts_default(solver=sgw.SOLVER_BLOCK, **bad))
         assert e.value.code == sgw.SGW_ERR_INVALID_ARG, bad
-    q = synth.small((1, 1, 1), n_omega=2, n_pert=33, seed=9100)
-    with pytest.raises(sgw.SgwError) as e:
-        DeviceProblem(ctx, q).solve(opts=sgw.sgw_opts_default(solver=sgw.SOLVER_BLOCK))
-    assert e.value.code == sgw.SGW_ERR_UNSUPPORTED
+
+
+def test_block_more_than_32_perturbations(ctx):
+    """33 perturbations: two blocks of 17 and 16 per band, solved one after the other, each writing its
+    perturbations of the caller's arrays; against the oracle."""
+    from paper_1812_03717_amd import sgw
+    from paper_1812_03717_amd.workload import DeviceProblem
+    p = synth.small((1, 1, 1), n_omega=3, n_pert=33, seed=9100)
+    pairs, xs, tol = _reference(p)
+    d = DeviceProblem(ctx, p)
+    st, dpsi, info = d.solve(tol=tol, opts=sgw.sgw_opts_default(solver=sgw.SOLVER_BLOCK))
+    assert st == sgw.SGW_OK, sgw.load_library().sgw_last_error()
+    _check(p, pairs, xs, dpsi.cpu().numpy(), sgw.info_to_numpy(info, (p.n_band, p.n_pert, p.n_omega)), tol)
 
 
 def test_block_edges(ctx):
