@@ -44,6 +44,8 @@ KERNEL_SOURCES = {
     "hx_sticks_fwd": ["hx.hip", "planes.h", "fft_reg.h", "fft_lds.h", "twiddle_const.h", "sgw_internal.h"],
     "proj_dot": ["projector.hip"],
     "proj_apply": ["projector.hip"],
+    # rocBLAS products whose shapes and count the block solver sets
+    "blk_product": ["block.hip"],
 }
 
 
