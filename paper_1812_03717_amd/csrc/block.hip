@@ -43,7 +43,7 @@ size_t up(size_t b) { return (b + kBA - 1) / kBA * kBA; }
 // Workspace of one chunk of nbc bands; kb = block steps + 1 stored blocks
 struct BlkLayout {
   int nbc = 0, kb = 0, s = 0, run = 0;
-  size_t basis, abasis, pov, rhs, y, w, v2, gram, coef, part, rfac, rinv, ablk, bblk, r0, bnorm, dinv, ff, res, thomas,
+  size_t basis, abasis, pov, rhs, y, w, v2, gram, coef, part, rfac, rinv, ablk, bblk, r0, bnorm, res, thomas,
       ycat, xg, axg, qg, list, c, t, psi, omega, eps, conv, ord, dvm, bstep, kband, bad, total;
 };
 
@@ -77,8 +77,6 @@ BlkLayout blk_layout(const sgw_ham *h, int n_occ, int nbc, int s, int n_omega, i
   L.bblk = take(16 * (size_t)(kb + 1) * nbc * ss);
   L.r0 = take(16 * nbc * ss);
   L.bnorm = take(8 * nv);
-  L.dinv = take(16 * (size_t)nbc * n_omega * ss);
-  L.ff = take(16 * (size_t)nbc * n_omega * ss);
   L.res = take(8 * (size_t)nbc * n_omega);
   L.thomas = take(16 * 2 * (size_t)kb * nbc * n_omega * ss);
   L.ycat = take(16 * (size_t)kb * s * nv * n_omega);
@@ -450,8 +448,8 @@ __device__ void blk_inverse(Blk M, int s, int *perm) {
 
 // Per (band, shift), one block of 256 threads: step j of the forward block recurrence of (T - z) and
 // the residual estimate of the FOM solutions after j + 1 block steps.  ablk = A_j, bprev = B_j
-// (j > 0), bnext = B_{j+1} of every band; dinv, ff hold D_{j-1}^-1, F_{j-1} of the (band, shift) and
-// take D_j^-1, F_j.  res[band][shift] = largest over the block's columns c of
+// (j > 0), bnext = B_{j+1} of every band; the (band, shift)'s history in hist (kb steps of D_i^-1 and
+// F_i) holds D_{j-1}^-1, F_{j-1} and takes D_j^-1, F_j, kept for the final block solve.  res[band][shift] = largest over the block's columns c of
 // ||B_{j+1} D_j^-1 F_j e_c|| / ||b_c||; once it is at most tol_int, conv[band][shift] = j + 1 and the
 // shift's recurrence stops (its FOM solution is taken at that step).
 __global__ __launch_bounds__(kBlkThreads) void k_blk_shift(int s, int n_omega, int j,
@@ -460,8 +458,8 @@ __global__ __launch_bounds__(kBlkThreads) void k_blk_shift(int s, int n_omega, i
                                                          const double2 *__restrict__ bnext,
                                                          const double2 *__restrict__ r0,
                                                          const double *__restrict__ bnorm,
-                                                         const double2 *__restrict__ zs, double2 *__restrict__ dinv,
-                                                         double2 *__restrict__ ff, double *__restrict__ res,
+                                                         const double2 *__restrict__ zs, double2 *__restrict__ hist,
+                                                         int kb, double *__restrict__ res,
                                                          int32_t *__restrict__ conv, double tol_int) {
   __shared__ double2 X1[kBlockMaxPert][kBlockMaxPert + 1], X2[kBlockMaxPert][kBlockMaxPert + 1],
       X3[kBlockMaxPert][kBlockMaxPert + 1];
@@ -469,23 +467,24 @@ __global__ __launch_bounds__(kBlkThreads) void k_blk_shift(int s, int n_omega, i
   __shared__ double cres[kBlockMaxPert];
   const int b = blockIdx.x / n_omega, k = blockIdx.x - b * n_omega;
   if (conv[(long)b * n_omega + k] >= 0) return;  // the whole block leaves together
-  const long bo = (long)b * s * s, so = ((long)b * n_omega + k) * s * s;
+  const long ss = (long)s * s, bo = (long)b * ss;
+  double2 *hk = hist + ((long)b * n_omega + k) * 2 * kb * ss;  // step i: D_i^-1, then F_i
   if (j == 0) {
     blk_load(X1, r0 + bo, s);  // F_0 = R_0
     for (int e = threadIdx.x; e < s * s; e += kBlkThreads) X3[e % s][e / s] = make_double2(0.0, 0.0);
     __syncthreads();
   } else {
-    blk_load(X1, dinv + so, s);
+    blk_load(X1, hk + (long)(j - 1) * 2 * ss, s);
     blk_load(X2, bprev + bo, s);
     blk_mm(X3, X2, false, X1, false, s, 1.0, 0);   // L = B_j D_{j-1}^-1
-    blk_load(X1, ff + so, s);
+    blk_load(X1, hk + (long)(j - 1) * 2 * ss + ss, s);
     blk_mm(X1, X3, false, X1, false, s, -1.0, 0);  // F_j = -L F_{j-1}
     blk_mm(X3, X3, false, X2, true, s, 1.0, 0);    // L B_j^H
   }
   blk_diff_shift(X3, ablk + bo, zs[k], s);  // D_j = A_j - L B_j^H - z
   blk_inverse(X3, s, perm);
-  blk_store(dinv + so, X3, s);
-  blk_store(ff + so, X1, s);
+  blk_store(hk + (long)j * 2 * ss, X3, s);
+  blk_store(hk + (long)j * 2 * ss + ss, X1, s);
   blk_mm(X2, X3, false, X1, false, s, 1.0, 0);  // last block of Y = D_j^-1 F_j
   blk_load(X1, bnext + bo, s);
   blk_mm(X1, X1, false, X2, false, s, 1.0, 0);  // B_{j+1} Y_last
@@ -504,27 +503,24 @@ __global__ __launch_bounds__(kBlkThreads) void k_blk_shift(int s, int n_omega, i
   }
 }
 
-// Per (band, shift): block LU solve of (T_k - z) Y = E_0 R_0 over k block steps (forward: D_i, G_i as
-// in k_blk_shift, kept in scratch; backward: Y_{k-1} = D_{k-1}^-1 G_{k-1},
-// Y_i = D_i^-1 (G_i - B_{i+1}^H Y_{i+1})), over the shift's own step count kk (conv, else k).  Y goes
+// Per (band, shift): block LU solve of (T_k - z) Y = E_0 R_0 over the shift's own step count kk (conv,
+// else the band's kband): the forward sweep (D_i^-1, G_i) is the one k_blk_shift kept in scratch, the
+// backward one is Y_{kk-1} = D_{kk-1}^-1 G_{kk-1}, Y_i = D_i^-1 (G_i - B_{i+1}^H Y_{i+1}).  Y goes
 // to ycat[b] at rows i s + r, column pos[b][shift] s + c (leading dimension ldy); rows kk s .. k s - 1
 // are zeroed.
-__global__ __launch_bounds__(kBlkThreads) void k_blk_solve(int s, int n_omega, int k, int nbc,
-                                                         const double2 *__restrict__ ablk,
+__global__ __launch_bounds__(kBlkThreads) void k_blk_solve(int s, int n_omega, int k, int kb, int nbc,
                                                          const double2 *__restrict__ bblk,
-                                                         const double2 *__restrict__ r0,
-                                                         const double2 *__restrict__ zs, double2 *__restrict__ scratch,
+                                                         const double2 *__restrict__ scratch,
                                                          double2 *__restrict__ ycat, long ldy, long ycat_stride,
                                                          const int32_t *__restrict__ conv,
                                                          const int32_t *__restrict__ pos,
                                                          const int32_t *__restrict__ kband) {
   __shared__ double2 X1[kBlockMaxPert][kBlockMaxPert + 1], X2[kBlockMaxPert][kBlockMaxPert + 1],
       X3[kBlockMaxPert][kBlockMaxPert + 1];
-  __shared__ int perm[kBlockMaxPert];
   const int b = blockIdx.x / n_omega, sh = blockIdx.x - b * n_omega;
   const long ss = (long)s * s;
-  const double2 z = zs[sh];
-  double2 *scr = scratch + ((long)b * n_omega + sh) * 2 * k * ss;  // step i: D_i^-1, then G_i
+  // the forward recurrence of k_blk_shift: step i holds D_i^-1, then G_i (= F_i)
+  const double2 *scr = scratch + ((long)b * n_omega + sh) * 2 * kb * ss;
   const int cv = conv[(long)b * n_omega + sh], kbb = kband[b];
   const int kk = cv >= 0 && cv <= kbb ? cv : kbb;  // a band whose block lost rank keeps its valid steps
   const long col0 = (long)pos[(long)b * n_omega + sh] * s;
@@ -532,24 +528,6 @@ __global__ __launch_bounds__(kBlkThreads) void k_blk_solve(int s, int n_omega, i
   for (int e = threadIdx.x; e < (k - kk) * s * s; e += kBlkThreads) {
     const int r = e % ((k - kk) * s), c = e / ((k - kk) * s);
     yb[(long)(kk * s + r) + (col0 + c) * ldy] = make_double2(0.0, 0.0);
-  }
-  for (int i = 0; i < kk; ++i) {
-    if (i == 0) {
-      blk_load(X1, r0 + (long)b * ss, s);
-      for (int e = threadIdx.x; e < s * s; e += kBlkThreads) X3[e % s][e / s] = make_double2(0.0, 0.0);
-      __syncthreads();
-    } else {
-      blk_load(X1, scr + (long)(i - 1) * 2 * ss, s);
-      blk_load(X2, bblk + ((long)i * nbc + b) * ss, s);
-      blk_mm(X3, X2, false, X1, false, s, 1.0, 0);
-      blk_load(X1, scr + (long)(i - 1) * 2 * ss + ss, s);
-      blk_mm(X1, X3, false, X1, false, s, -1.0, 0);
-      blk_mm(X3, X3, false, X2, true, s, 1.0, 0);
-    }
-    blk_diff_shift(X3, ablk + ((long)i * nbc + b) * ss, z, s);
-    blk_inverse(X3, s, perm);
-    blk_store(scr + (long)i * 2 * ss, X3, s);
-    blk_store(scr + (long)i * 2 * ss + ss, X1, s);
   }
   for (int i = kk - 1; i >= 0; --i) {
     blk_load(X1, scr + (long)i * 2 * ss + ss, s);  // G_i
@@ -791,7 +769,7 @@ sgw_status block_group(sgw_ctx *ctx, const sgw_ham *h_kq, int n_occ, const sgw_c
   double2 *basis = P(L.basis), *rhs = P(L.rhs), *Y = P(L.y), *Wv = P(L.w), *V2 = P(L.v2), *gbuf = P(L.gram), *cbuf = P(L.coef),
           *part = P(L.part),
           *rfac = P(L.rfac), *rinv = P(L.rinv), *ablk = P(L.ablk), *bblk = P(L.bblk), *r0 = P(L.r0),
-          *dinv = P(L.dinv), *ff = P(L.ff), *thomas = P(L.thomas), *ycat = P(L.ycat), *xg = P(L.xg),
+          *thomas = P(L.thomas), *ycat = P(L.ycat), *xg = P(L.xg),
           *axg = P(L.axg), *qg = P(L.qg), *abasis = P(L.abasis), *pov = P(L.pov), *C = P(L.c), *psi = P(L.psi),
           *zs = P(L.omega);
   double *bnorm = (double *)(Wb + L.bnorm), *res = (double *)(Wb + L.res), *deps = (double *)(Wb + L.eps);
@@ -892,7 +870,7 @@ sgw_status block_group(sgw_ctx *ctx, const sgw_ham *h_kq, int n_occ, const sgw_c
       hipLaunchKernelGGL(k_blk_shift, dim3(nb * n_omega), dim3(kBlkThreads), 0, ctx->stream, s, n_omega, j,
                          (const double2 *)aj, (const double2 *)(bblk + (long)j * nbc * ss),
                          (const double2 *)(bblk + (long)(j + 1) * nbc * ss), (const double2 *)r0,
-                         (const double *)bnorm, (const double2 *)zs, dinv, ff, res, conv, tol_int);
+                         (const double *)bnorm, (const double2 *)zs, thomas, kb, res, conv, tol_int);
       SGW_HIP(hipGetLastError());
       k = j + 1;
       if (k % poll == 0 || k + 1 >= kb) {
@@ -945,9 +923,9 @@ sgw_status block_group(sgw_ctx *ctx, const sgw_ham *h_kq, int n_occ, const sgw_c
       sb_cut[q] = shift_runs(ord, ksh);
     }
     SGW_HIP(hipMemcpyAsync(dpos, hmap.data(), sizeof(int32_t) * hmap.size(), hipMemcpyHostToDevice, ctx->stream));
-    hipLaunchKernelGGL(k_blk_solve, dim3(nb * n_omega), dim3(kBlkThreads), 0, ctx->stream, s, n_omega, k, nbc,
-                       (const double2 *)ablk, (const double2 *)bblk, (const double2 *)r0, (const double2 *)zs, thomas,
-                       ycat, (long)kb * s, (long)kb * s * s * n_omega, (const int32_t *)conv, (const int32_t *)dpos,
+    hipLaunchKernelGGL(k_blk_solve, dim3(nb * n_omega), dim3(kBlkThreads), 0, ctx->stream, s, n_omega, k, kb, nbc,
+                       (const double2 *)bblk, (const double2 *)thomas, ycat, (long)kb * s,
+                       (long)kb * s * s * n_omega, (const int32_t *)conv, (const int32_t *)dpos,
                        (const int32_t *)kband);
     SGW_HIP(hipGetLastError());
     // per run piece of at most L.run shifts: X = V Y, (H + alpha P) X = (AV) Y and psi^H X = (psi^H V) Y,
