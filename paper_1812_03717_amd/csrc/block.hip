@@ -137,6 +137,7 @@ __global__ __launch_bounds__(256) void k_blk_gram(int npw, int s, const double2 
   __shared__ double2 As[kGramTile][kBlockMaxPert + 1], Bs[kGramTile][kBlockMaxPert + 1];
   const int chunk = blockIdx.x, b = blockIdx.y, nb = gridDim.y;
   const double2 *a = A + (long)b * sa, *bb = B + (long)b * sb;
+  const bool same = a == bb;  // a Gram matrix A^H A: one tile serves both sides
   const int t = threadIdx.x;
   double2 acc[4];
   for (int r = 0; r < 4; ++r) acc[r] = make_double2(0.0, 0.0);
@@ -147,7 +148,7 @@ __global__ __launch_bounds__(256) void k_blk_gram(int npw, int s, const double2 
       const int r = e % kGramTile, c = e / kGramTile;
       const bool in = r < rows;
       As[r][c] = in ? a[(long)c * npw + g0 + r] : make_double2(0.0, 0.0);
-      Bs[r][c] = in ? bb[(long)c * npw + g0 + r] : make_double2(0.0, 0.0);
+      if (!same) Bs[r][c] = in ? bb[(long)c * npw + g0 + r] : make_double2(0.0, 0.0);
     }
     __syncthreads();
 #pragma unroll
@@ -157,7 +158,7 @@ __global__ __launch_bounds__(256) void k_blk_gram(int npw, int s, const double2 
         const int i = e % s, j = e / s;
         double2 v = acc[q];
         for (int r = 0; r < kGramTile; ++r) {
-          const double2 x = As[r][i], y = Bs[r][j];
+          const double2 x = As[r][i], y = same ? As[r][j] : Bs[r][j];
           v.x += x.x * y.x + x.y * y.y;
           v.y += x.x * y.y - x.y * y.x;
         }
