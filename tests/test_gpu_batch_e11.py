@@ -6,7 +6,8 @@ at the occupation edge are ~5e-4 Ha apart, so the band count is the nearest with
 a gap of at least 3e-4 Ha at k and k+q (the reading of the 64-atom workload).
 
 Every solve must converge with a true FP64 relative residual <= tol and an occupied component
-within the error budget relres ||b|| / eta.  The largest cell is sampled against the oracle's
+within the error budget relres ||b|| / eta; the batch is solved with the multishift solver and again
+with the block solver.  The largest cell is sampled against the oracle's
 direct LU solve of the shifted operator (Sec. 2.3, Eqs. 6-8) on the host: its top occupied band
 at the lowest frequency, two perturbations (one factorisation of the 13,539 x 13,539 operator);
 bound ||x - x*|| <= relres ||b|| / eta, since every singular value of H - eps - z is at least eta.
@@ -93,4 +94,42 @@ def test_batch_full_cutoff_sampled_vs_lu(setup):
         bound = inf["relres"][v, q, j] * np.linalg.norm(bs[i]) / p.eta
         print(f"  fcc333 (v={v}, p={q}, omega={p.omega[j]:.3f}): |x - x*| = {err:.3e}, budget {bound:.3e}, "
               f"rel err {err / np.linalg.norm(ref[i]):.3e}", flush=True)
+        assert err <= 1.01 * bound + 1e-12 * np.linalg.norm(ref[i])
+
+
+@pytest.mark.timeout(900)
+def test_batch_full_cutoff_block_solver(setup):
+    """The same three systems batched with the block solver (the batch benchmark's default, at most
+    600 block steps): every solve converges, and the largest cell matches the oracle's LU solve within
+    relres ||b|| / eta at the same sample."""
+    from paper_1812_03717_amd import sgw
+    ctx, ps, devs = setup
+    b = sgw.Batch(ctx)
+    names = list(SEEDS)
+    for k in names:
+        d, p = devs[k], ps[k]
+        b.add(d.h_kq, d.psi_occ_kq, d.h_k, d.psi_v, d.eps_v, p.dv_miller, p.omega, p.eta, p.tol,
+              opts=sgw.sgw_opts_default(solver=sgw.SOLVER_BLOCK, max_iter=600))
+    st = b.solve(n_workers=3)
+    assert st == sgw.SGW_OK, sgw.load_library().sgw_last_error()
+    for k, it in zip(names, b.items):
+        p = ps[k]
+        inf = sgw.info_to_numpy(it["info"], (p.n_band, p.n_pert, p.n_omega))
+        print(f"{k} (block): steps {inf['iters'].min()}..{inf['iters'].max()}, max relres {inf['relres'].max():.3e}, "
+              f"{it['ms']:.1f} ms", flush=True)
+        assert np.all(inf["flags"] & sgw.FLAG_CONVERGED) and inf["relres"].max() <= p.tol
+    p = ps["fcc333"]
+    it = b.items[names.index("fcc333")]
+    inf = sgw.info_to_numpy(it["info"], (p.n_band, p.n_pert, p.n_omega))
+    v, j, perts = p.n_band - 1, 0, [0, p.n_pert - 1]
+    xs = it["dpsi"][v, perts, j].cpu().numpy()
+    h = so.hamiltonian(p.miller_kq, p.B, p.kvec + p.qvec, p.v_grid)
+    a0 = so.coulomb_operator(h, p.psi_kq, p.eps_k[v], 1.0)
+    del h
+    bs = np.array([so.rhs(p.psi_k[v], p.miller_k, p.miller_kq, p.dv_miller[q], p.psi_kq) for q in perts])
+    ref = so.solve_lu(a0, bs.T, p.omega[j] + 1j * p.eta).T
+    for i, q in enumerate(perts):
+        err = np.linalg.norm(xs[i] - ref[i])
+        bound = inf["relres"][v, q, j] * np.linalg.norm(bs[i]) / p.eta
+        print(f"  fcc333 block (v={v}, p={q}): |x - x*| = {err:.3e}, budget {bound:.3e}", flush=True)
         assert err <= 1.01 * bound + 1e-12 * np.linalg.norm(ref[i])
