@@ -509,7 +509,8 @@ sgw_status sgw_quasiparticle(int n_sup, const sgw_c128 *z_sup, const sgw_c128 *f
  * sternheimer_solve (the same solver, options and flags; no occupied projector, no band energy).
  * The paper takes the complex frequency on the side that satisfies the time ordering: here the
  * caller chooses the sign of eta (eta > 0 above the chemical potential, eta < 0 below), one call
- * per side.
+ * per side.  With opts.solver = SGW_SOLVER_BLOCK the columns share one block Krylov space (the
+ * operator is the same for all of them): blocks of at most 32 columns, info.iters in block steps.
  * h_k         the Hamiltonian (its basis is the columns' and the solution's basis)
  * cols        host [n_col], plane-wave indices G' in the caller's order, 0 <= cols[c] < n_pw
  * omega       host [n_omega] (Ha); eta != 0; tol > 0 as in sternheimer_solve

@@ -1532,9 +1532,11 @@ extern "C" sgw_status sgw_green_workspace_size(sgw_ctx *ctx, const sgw_ham *h_k,
   if (!ctx || !h_k || !bytes) return fail(SGW_ERR_INVALID_ARG, "sgw_green_workspace_size: NULL argument");
   if (n_col < 0 || n_omega < 0) return fail(SGW_ERR_INVALID_ARG, "sgw_green_workspace_size: negative size");
   const sgw_opts o = resolve_opts(opts);
-  if (o.solver < SGW_SOLVER_MULTISHIFT || o.solver > SGW_SOLVER_TAIL)
+  if (o.solver < SGW_SOLVER_MULTISHIFT || o.solver > SGW_SOLVER_BLOCK)
     return fail(SGW_ERR_INVALID_ARG, "sgw_green_workspace_size: unknown solver");
-  const size_t base = up256(solve_workspace_bytes(h_k, 0, n_col, 1, std::max(n_omega, 1), o));
+  // block solver: the columns as the perturbations of one right-hand side family (see sgw_green_solve)
+  const bool blk = o.solver == SGW_SOLVER_BLOCK;
+  const size_t base = up256(solve_workspace_bytes(h_k, 0, blk ? 1 : n_col, blk ? n_col : 1, std::max(n_omega, 1), o));
   *bytes = base + up256(sizeof(double2) * (size_t)n_col * h_k->n_pw) + up256(sizeof(int32_t) * (size_t)n_col);
   return SGW_OK;
 }
@@ -1554,6 +1556,20 @@ extern "C" sgw_status sgw_green_solve(sgw_ctx *ctx, const sgw_ham *h_k, int n_co
   const std::vector<double> eps0(n_col, 0.0);
   const int32_t dvm0[3] = {0, 0, 0};
   sgw_problem p = green_problem(h_k, n_col, n_omega, omega, eta, tol, eps0.data(), dvm0, g, info);
+  // Block solver: the operator H_k - z is the same for every column, so the columns are the
+  // perturbations of one band: e_{G'} is the unit vector at G_0 = cols[0] shifted by G' - G_0, and the
+  // n_col right-hand sides share one block Krylov space (the output layout is the same).
+  const bool blk = o.solver == SGW_SOLVER_BLOCK;
+  std::vector<int32_t> dvb;
+  if (blk) {
+    dvb.resize(3 * (size_t)n_col);
+    const int32_t *m = h_k->miller.data();
+    for (int c = 0; c < n_col; ++c)
+      for (int a = 0; a < 3; ++a) dvb[3 * c + a] = m[3 * cols[c] + a] - m[3 * cols[0] + a];
+    p.n_band = 1;
+    p.n_pert = n_col;
+    p.dv_miller = dvb.data();
+  }
   // validation with a stand-in for the device unit vectors (only their presence is checked)
   p.psi_v = (const sgw_c128 *)workspace;
   sgw_status st = check_problem(ctx, p, o);
@@ -1568,7 +1584,7 @@ extern "C" sgw_status sgw_green_solve(sgw_ctx *ctx, const sgw_ham *h_k, int n_co
   double2 *unit = (double2 *)((char *)workspace + base);
   int32_t *dcols = (int32_t *)((char *)unit + up256(sizeof(double2) * (size_t)n_col * npw));
   SGW_HIP(hipMemcpyAsync(dcols, cols, sizeof(int32_t) * n_col, hipMemcpyHostToDevice, ctx->stream));
-  if ((st = unit_columns(ctx, npw, n_col, dcols, unit)) != SGW_OK) return st;
+  if ((st = unit_columns(ctx, npw, blk ? 1 : n_col, dcols, unit)) != SGW_OK) return st;
   p.psi_v = (const sgw_c128 *)unit;
   return run_solve(ctx, p, o, workspace, base);
 }

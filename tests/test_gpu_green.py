@@ -38,9 +38,10 @@ CASES = {
 }
 
 
+@pytest.mark.parametrize("solver", ["multishift", "block"])
 @pytest.mark.parametrize("name", sorted(CASES))
 @pytest.mark.parametrize("side", [1.0, -1.0], ids=["eta+", "eta-"])
-def test_green_columns_match_oracle(ctx, name, side):
+def test_green_columns_match_oracle(ctx, name, side, solver):
     from paper_1812_03717_amd import sgw
     from paper_1812_03717_amd.workload import DeviceProblem
     make, cols, n_om = CASES[name]
@@ -54,10 +55,11 @@ def test_green_columns_match_oracle(ctx, name, side):
     zs = omega + 1j * eta
     kap = max(so.green_condition_number(w, z) for z in zs)
     tol = max(2e-13, min(1e-10, 1e-8 / (2.0 * kap)))
+    kw = {"solver": sgw.SOLVER_BLOCK} if solver == "block" else {}
     st, g, info = sgw.sgw_green_solve(ctx, d.h_k, cols, omega, eta, tol,
-                                      opts=sgw.sgw_opts_default(max_iter=3000))
+                                      opts=sgw.sgw_opts_default(max_iter=3000, **kw))
     inf = sgw.info_to_numpy(info, (len(cols), n_om))
-    print(f"{name} eta {eta:+.2e}: kappa {kap:.2e}, tol {tol:.1e}, status {st}, iters "
+    print(f"{name} {solver} eta {eta:+.2e}: kappa {kap:.2e}, tol {tol:.1e}, status {st}, iters "
           f"{inf['iters'].min()}..{inf['iters'].max()}, max relres {inf['relres'].max():.2e}", flush=True)
     assert st == sgw.SGW_OK, sgw.load_library().sgw_last_error()
     assert np.all(inf["flags"] & sgw.FLAG_CONVERGED) and inf["relres"].max() <= tol
