@@ -127,7 +127,6 @@ __global__ void k_blk_list(int32_t *list, int nbc, int s, int kb, int j) {
   list[a] = (b * kb + j) * s + c;
 }
 
-// w[a] = y[a] - eps[band] v[a] (v through the list)
 // Skinny products C_b = A_b^H B_b (s x s, column-major) of every band's n_pw x s blocks, in two
 // deterministic passes: partial sums over chunks of kGramRows plane waves (one workgroup per chunk and
 // band, rows staged through LDS with coalesced column loads), then the chunks summed in order.
@@ -450,8 +449,8 @@ __device__ void blk_inverse(Blk M, int s, int *perm) {
 // Per (band, shift), one block of 256 threads: step j of the forward block recurrence of (T - z) and
 // the residual estimate of the FOM solutions after j + 1 block steps.  ablk = A_j, bprev = B_j
 // (j > 0), bnext = B_{j+1} of every band; the (band, shift)'s history in hist (kb steps of D_i^-1 and
-// F_i) holds D_{j-1}^-1, F_{j-1} and takes D_j^-1, F_j, kept for the final block solve.  res[band][shift] = largest over the block's columns c of
-// ||B_{j+1} D_j^-1 F_j e_c|| / ||b_c||; once it is at most tol_int, conv[band][shift] = j + 1 and the
+// F_i) holds D_{j-1}^-1, F_{j-1} and takes D_j^-1, F_j, kept for the final block solve.
+// res[band][shift] = largest over the block's columns c of ||B_{j+1} D_j^-1 F_j e_c|| / ||b_c||; once it is at most tol_int, conv[band][shift] = j + 1 and the
 // shift's recurrence stops (its FOM solution is taken at that step).
 __global__ __launch_bounds__(kBlkThreads) void k_blk_shift(int s, int n_omega, int j,
                                                          const double2 *__restrict__ ablk,
