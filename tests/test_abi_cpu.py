@@ -74,3 +74,30 @@ def test_struct_layouts_match_the_binding(tmp_path):
     size, offs = _c_layout(tmp_path, "sgw_solve_info", list(sgw.INFO_DTYPE.names))
     assert sgw.INFO_DTYPE.itemsize == size
     assert [sgw.INFO_DTYPE.fields[n][1] for n in sgw.INFO_DTYPE.names] == offs
+
+
+def test_enum_values_match_the_binding(tmp_path):
+    """Every status, flag, solver, precision, preconditioner, guess and plane-kernel constant of the
+    binding has the value the header gives it (from the C compiler)."""
+    import subprocess
+    pairs = {"SGW_OK": sgw.SGW_OK, "SGW_NOT_CONVERGED": sgw.SGW_NOT_CONVERGED,
+             "SGW_ERR_INVALID_ARG": sgw.SGW_ERR_INVALID_ARG, "SGW_ERR_HIP": sgw.SGW_ERR_HIP,
+             "SGW_ERR_WORKSPACE": sgw.SGW_ERR_WORKSPACE, "SGW_ERR_UNSUPPORTED": sgw.SGW_ERR_UNSUPPORTED,
+             "SGW_PROJ_SPLIT_BF16": sgw.PROJ_SPLIT_BF16}
+    for names in (("FLAG", ("CONVERGED", "MAXITER", "BREAKDOWN", "NONFINITE", "ZERO_RHS", "PER_SHIFT")),
+                  ("SOLVER", ("MULTISHIFT", "PER_SHIFT", "TAIL", "BLOCK")),
+                  ("PC", ("NONE", "TETER", "LEARNED")), ("GUESS", ("ZERO", "LEARNED")),
+                  ("FFT", ("AUTO", "LINE", "PAIR", "LDS", "TRI"))):
+        for n in names[1]:
+            pairs[f"SGW_{names[0]}_{n}"] = getattr(sgw, f"{names[0]}_{n}")
+    pairs["SGW_FP64"], pairs["SGW_MIXED"] = sgw.FP64, sgw.MIXED
+    keys = sorted(pairs)
+    src = tmp_path / "enums.c"
+    lines = ['#include <stdio.h>', f'#include "{ROOT}/include/sgw.h"', 'int main(void) {']
+    lines += [f'  printf("%d\\n", (int){k});' for k in keys]
+    lines += ['  return 0;', '}']
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "enums"
+    subprocess.run(["gcc", "-std=c99", str(src), "-o", str(exe)], check=True)
+    got = [int(x) for x in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()]
+    assert dict(zip(keys, got)) == {k: pairs[k] for k in keys}
