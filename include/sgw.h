@@ -325,7 +325,8 @@ typedef struct {
   double tol_safety;        /* the recurrence stops when every shift's estimated residual
                                is below tol*tol_safety; <= 0 -> 0.5 */
   int32_t slots;            /* (v,p) pairs iterated concurrently; <= 0 -> automatic (as many as
-                               a 144 GiB workspace holds, at most all pairs) */
+                               a 144 GiB workspace holds, at most all pairs); block solver: the
+                               most bands per chunk */
   int32_t finalize_batch;   /* pairs per finalisation batch; <= 0 -> automatic */
   int32_t steps_per_sync;   /* Krylov steps between host polls; <= 0 -> 8 */
   int32_t solver;           /* SGW_SOLVER_* (default MULTISHIFT) */
@@ -379,7 +380,12 @@ typedef struct {
 } sgw_solve_info;
 
 /*
- * Device workspace needed by sternheimer_solve for these sizes and options.
+ * Device workspace needed by sternheimer_solve for these sizes and options.  Multishift: the slots
+ * that a 144 GiB budget holds (opts.slots overrides).  Block solver: one chunk of bands, as many as
+ * the 144 GiB budget holds (opts.slots caps them), each band holding its basis and its products AV
+ * for max_iter + 1 block steps (2 x 16 (max_iter + 1) min(n_pert, 32) n_pw bytes) beside the
+ * per-shift block recurrences and one run of final products; a larger workspace given to the solve
+ * is used for larger chunks.
  */
 sgw_status sternheimer_workspace_size(sgw_ctx *ctx, const sgw_ham *h_kq, int n_occ, int n_band,
                                       int n_pert, int n_omega, const sgw_opts *opts, size_t *bytes);
