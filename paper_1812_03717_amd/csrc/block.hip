@@ -553,7 +553,8 @@ __global__ __launch_bounds__(kBlkThreads) void k_blk_solve(int s, int n_omega, i
 // relres = ||b - (ax - eps x - z x)|| / ||b||, occ_leak = ||q|| / ||x||, iters = the shift's step count
 // (conv, else the band's kband; MAXITER when the residual misses tol after the step limit (maxed), no
 // flag for a band whose block lost rank, so that it is refined per shift); dpsi[g] = -x[u2i[g]].
-__global__ __launch_bounds__(256) void k_blk_final(int npw, int n_occ, int s, int n_pert, int pert0, int n_omega,
+constexpr int kFinThreads = 1024, kFinUnroll = 4;  // threads per solution of k_blk_final, elements in flight
+__global__ __launch_bounds__(kFinThreads) void k_blk_final(int npw, int n_occ, int s, int n_pert, int pert0, int n_omega,
                                                    int len, int p0, int run,
                                                    const double2 *__restrict__ xg, const double2 *__restrict__ axg,
                                                    const double2 *__restrict__ qg, const double2 *__restrict__ rhs,
@@ -563,7 +564,7 @@ __global__ __launch_bounds__(256) void k_blk_final(int npw, int n_occ, int s, in
                                                    double tol,
                                                    const int32_t *__restrict__ u2i,
                                                    double2 *__restrict__ dpsi, sgw_solve_info *info, int *bad) {
-  __shared__ double red[3][256];
+  __shared__ double red[4][kFinThreads];
   const long a = blockIdx.x;
   const int c = (int)(a % s);
   const long bl = a / s;
@@ -573,38 +574,58 @@ __global__ __launch_bounds__(256) void k_blk_final(int npw, int n_occ, int s, in
   const double2 *xa = xg + xv * npw, *ya = axg + xv * npw, *ba = rhs + ((long)b * s + c) * npw;
   const double2 z = zs[sh];
   const double e = eps[b];
-  double rr = 0.0, bb = 0.0, xx = 0.0;
-  for (int g = threadIdx.x; g < npw; g += 256) {
-    const double2 x = xa[g], y = ya[g], bv = ba[g];
-    // (A - z) x = y - eps x - z x
-    const double ax = y.x - e * x.x - (z.x * x.x - z.y * x.y);
-    const double ay = y.y - e * x.y - (z.x * x.y + z.y * x.x);
-    const double rx = bv.x - ax, ry = bv.y - ay;
-    rr += rx * rx + ry * ry;
-    bb += bv.x * bv.x + bv.y * bv.y;
-    xx += x.x * x.x + x.y * x.y;
-  }
   const long o = ((long)b * n_pert + pert0 + c) * n_omega + sh;  // caller's (band, perturbation, shift)
   double2 *out = dpsi + o * npw;
-  for (int g = threadIdx.x; g < npw; g += 256) {
-    const double2 x = xa[u2i[g]];
-    out[g] = make_double2(-x.x, -x.y);
+  // one pass: the residual terms in the internal order, the solution gathered into the caller's;
+  // kFinUnroll elements per thread in flight (the gather waits on its index load)
+  double rr = 0.0, bb = 0.0, xx = 0.0, qq = 0.0;
+  for (int g0 = threadIdx.x; g0 < npw; g0 += kFinUnroll * kFinThreads) {
+    int src[kFinUnroll];
+    double2 x[kFinUnroll], y[kFinUnroll], bv[kFinUnroll], xo[kFinUnroll];
+#pragma unroll
+    for (int u = 0; u < kFinUnroll; ++u) {
+      const int g = g0 + u * kFinThreads;
+      if (g < npw) {
+        src[u] = u2i[g];
+        x[u] = xa[g];
+        y[u] = ya[g];
+        bv[u] = ba[g];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kFinUnroll; ++u)
+      if (g0 + u * kFinThreads < npw) xo[u] = xa[src[u]];
+#pragma unroll
+    for (int u = 0; u < kFinUnroll; ++u) {
+      const int g = g0 + u * kFinThreads;
+      if (g < npw) {
+        // (A - z) x = y - eps x - z x
+        const double ax = y[u].x - e * x[u].x - (z.x * x[u].x - z.y * x[u].y);
+        const double ay = y[u].y - e * x[u].y - (z.x * x[u].y + z.y * x[u].x);
+        const double rx = bv[u].x - ax, ry = bv[u].y - ay;
+        rr += rx * rx + ry * ry;
+        bb += bv[u].x * bv[u].x + bv[u].y * bv[u].y;
+        xx += x[u].x * x[u].x + x[u].y * x[u].y;
+        out[g] = make_double2(-xo[u].x, -xo[u].y);
+      }
+    }
+  }
+  for (int i = threadIdx.x; i < n_occ; i += kFinThreads) {
+    const double2 q = qg[xv * n_occ + i];
+    qq += q.x * q.x + q.y * q.y;
   }
   red[0][threadIdx.x] = rr;
   red[1][threadIdx.x] = bb;
   red[2][threadIdx.x] = xx;
+  red[3][threadIdx.x] = qq;
   __syncthreads();
-  for (int h = 128; h > 0; h >>= 1) {
+  for (int h = kFinThreads / 2; h > 0; h >>= 1) {
     if ((int)threadIdx.x < h)
-      for (int q = 0; q < 3; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + h];
+      for (int q = 0; q < 4; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + h];
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    double occ = 0.0;
-    for (int i = 0; i < n_occ; ++i) {
-      const double2 q = qg[xv * n_occ + i];
-      occ += q.x * q.x + q.y * q.y;
-    }
+    const double occ = red[3][0];
     const int kbb = kband[b];
     const int cv = conv[(long)b * n_omega + sh] <= kbb ? conv[(long)b * n_omega + sh] : -1;
     const double nb = sqrt(red[1][0]), nx = sqrt(red[2][0]);
@@ -961,7 +982,7 @@ sgw_status block_group(sgw_ctx *ctx, const sgw_ham *h_kq, int n_occ, const sgw_c
                             (long)s * L.run * n_occ, nq, K_BLK_PRODUCT)) != SGW_OK)
               return st;
           }
-          hipLaunchKernelGGL(k_blk_final, dim3(nq * len * s), dim3(256), 0, ctx->stream, npw, n_occ, s, n_pert,
+          hipLaunchKernelGGL(k_blk_final, dim3(nq * len * s), dim3(kFinThreads), 0, ctx->stream, npw, n_occ, s, n_pert,
                              pert0, n_omega, len, p0, L.run, (const double2 *)xg, (const double2 *)axg, (const double2 *)qg,
                              (const double2 *)(rhs + (long)b_lo * s * npw), (const double *)(deps + b_lo),
                              (const double2 *)zs, dord, (const int32_t *)(conv + (long)b_lo * n_omega),
