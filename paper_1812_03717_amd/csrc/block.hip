@@ -141,15 +141,32 @@ __global__ __launch_bounds__(256) void k_blk_gram(int npw, int s, const double2 
   double2 acc[4];
   for (int r = 0; r < 4; ++r) acc[r] = make_double2(0.0, 0.0);
   const int g_end = min(npw, (chunk + 1) * kGramRows);
-  for (int g0 = chunk * kGramRows; g0 < g_end; g0 += kGramTile) {
+  // the next tile's elements (at most kGramTile kBlockMaxPert / 256 = 4 per thread) are loaded into
+  // registers while the current tile is multiplied
+  static_assert(kGramTile * kBlockMaxPert <= 4 * 256, "four staged elements per thread");
+  double2 pa[4], pb[4];
+  auto fetch = [&](int g0) {
     const int rows = min(kGramTile, g_end - g0);
-    for (int e = t; e < kGramTile * s; e += 256) {
-      const int r = e % kGramTile, c = e / kGramTile;
-      const bool in = r < rows;
-      As[r][c] = in ? a[(long)c * npw + g0 + r] : make_double2(0.0, 0.0);
-      if (!same) Bs[r][c] = in ? bb[(long)c * npw + g0 + r] : make_double2(0.0, 0.0);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = t + 256 * q, r = e % kGramTile, c = e / kGramTile;
+      const bool in = c < s && r < rows;
+      pa[q] = in ? a[(long)c * npw + g0 + r] : make_double2(0.0, 0.0);
+      if (!same) pb[q] = in ? bb[(long)c * npw + g0 + r] : make_double2(0.0, 0.0);
+    }
+  };
+  fetch(chunk * kGramRows);
+  for (int g0 = chunk * kGramRows; g0 < g_end; g0 += kGramTile) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = t + 256 * q, r = e % kGramTile, c = e / kGramTile;
+      if (c < s) {
+        As[r][c] = pa[q];
+        if (!same) Bs[r][c] = pb[q];
+      }
     }
     __syncthreads();
+    if (g0 + kGramTile < g_end) fetch(g0 + kGramTile);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int e = t + 256 * q;
