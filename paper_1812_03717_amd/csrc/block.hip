@@ -741,6 +741,7 @@ sgw_status comb(sgw_ctx *ctx, int npw, int s, int nb, int K, const double2 *src,
                      out, sout, copy, scopy)
   if (s <= 8) SGW_COMB(8);
   else if (s <= 16) SGW_COMB(16);
+  else if (s <= 20) SGW_COMB(20);
   else if (s <= 24) SGW_COMB(24);
   else SGW_COMB(32);
 #undef SGW_COMB
